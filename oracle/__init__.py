@@ -1,0 +1,174 @@
+"""CPU oracle for the connected-vehicle ETL hot path -- TEST INFRASTRUCTURE.
+
+Only the test suite, ``__graft_entry__.smoke()`` and the benchmark's
+``cpu_baseline`` leg may import this package.  The product path (the HIP
+library and its binding) never imports it.
+
+The arithmetic lives in ``cv_oracle.c`` (plain single-threaded C, built with
+``-ffp-contract=off``); this module marshals numpy arrays and applies the
+per-journey gathers.  ``build()`` compiles the C file in place.
+
+Parity status of each function (what pins it is in ``tests/test_oracle_pins.py``):
+
+* ``sort``      -- pinned (numpy.lexsort, brute force over permutations)
+* ``features``  -- pinned (closed forms, mpmath 50-digit references, identities)
+* ``summary``   -- pinned (math.fsum, numpy reductions, invariants)
+* ``grid``      -- pinned (brute-force Python dict, explicit grid-line cases)
+* ``fsum``      -- pinned (math.fsum)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "cv_oracle.c")
+LIB = os.path.join(HERE, "libcvoracle.so")
+
+FLAG_FIRST, FLAG_DT_ZERO, FLAG_SPEED_OK, FLAG_ACCEL_OK = 0x01, 0x02, 0x04, 0x08
+FLAG_BEARING_OK, FLAG_DHEAD_OK, FLAG_BAD_COORD = 0x10, 0x20, 0x40
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle (gcc, -O2, no FMA contraction, no fast-math)."""
+    if force or not os.path.exists(LIB):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+                               "-fPIC", "-shared", "-o", tmp, SRC, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+            build()
+        L = ctypes.CDLL(LIB)
+        P = ctypes.c_void_p
+        I = ctypes.c_int64
+        D = ctypes.c_double
+        L.orc_fsum.argtypes = [I, P]
+        L.orc_fsum.restype = D
+        L.orc_sort.argtypes = [I, P, P, P]
+        L.orc_sort.restype = None
+        L.orc_features.argtypes = [I] + [P] * 11
+        L.orc_features.restype = None
+        L.orc_summary.argtypes = [I] + [P] * 8 + [I] + [P] * 14
+        L.orc_summary.restype = I
+        L.orc_grid_keys.argtypes = [I, P, P, P, D, D, D, D, I, I, I, I, I, P]
+        L.orc_grid_keys.restype = I
+        L.orc_grid.argtypes = [I, P, P, P, P, P, D, D, D, D, I, I, I, I, I, I] + [P] * 7
+        L.orc_grid.restype = I
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _c(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+def fsum(x) -> float:
+    x = _c(x, np.float64)
+    return float(lib().orc_fsum(x.shape[0], _p(x)))
+
+
+def sort(jid, ts):
+    """Stable order of record indices by (journey id, timestamp)."""
+    jid = _c(jid, np.int64)
+    ts = _c(ts, np.int64)
+    n = jid.shape[0]
+    perm = np.empty(n, dtype=np.uint32)
+    lib().orc_sort(n, _p(jid), _p(ts), _p(perm))
+    return perm
+
+
+def sorted_records(cols, perm):
+    """Apply the permutation to the five record columns."""
+    return tuple(np.ascontiguousarray(c[perm]) for c in cols)
+
+
+def features(jid, ts, lat, lon):
+    jid, ts = _c(jid, np.int64), _c(ts, np.int64)
+    lat, lon = _c(lat, np.float64), _c(lon, np.float64)
+    n = jid.shape[0]
+    out = {k: np.empty(n, dtype=np.float64) for k in
+           ("step_m", "dt_s", "speed_mps", "accel_mps2", "bearing_deg", "dheading_deg")}
+    out["flags"] = np.empty(n, dtype=np.uint8)
+    lib().orc_features(n, _p(jid), _p(ts), _p(lat), _p(lon), _p(out["step_m"]), _p(out["dt_s"]),
+                       _p(out["speed_mps"]), _p(out["accel_mps2"]), _p(out["bearing_deg"]),
+                       _p(out["dheading_deg"]), _p(out["flags"]))
+    return out
+
+
+SUMMARY_FIELDS = (("journey_id", np.int64), ("first", np.uint32), ("n_points", np.uint32),
+                  ("t_start_ms", np.int64), ("t_end_ms", np.int64), ("distance_m", np.float64),
+                  ("sum_speed", np.float64), ("max_speed", np.float32),
+                  ("max_derived_speed", np.float64), ("n_dt_zero", np.uint32),
+                  ("lat_min", np.float64), ("lat_max", np.float64), ("lon_min", np.float64),
+                  ("lon_max", np.float64))
+
+
+def summary(jid, ts, lat, lon, speed, feat):
+    jid, ts = _c(jid, np.int64), _c(ts, np.int64)
+    lat, lon, speed = _c(lat, np.float64), _c(lon, np.float64), _c(speed, np.float32)
+    step = _c(feat["step_m"], np.float64)
+    dsp = _c(feat["speed_mps"], np.float64)
+    fl = _c(feat["flags"], np.uint8)
+    n = jid.shape[0]
+    cap = max(1, n)
+    out = {k: np.empty(cap, dtype=t) for k, t in SUMMARY_FIELDS}
+    J = lib().orc_summary(n, _p(jid), _p(ts), _p(lat), _p(lon), _p(speed), _p(step), _p(dsp), _p(fl),
+                          cap, *[_p(out[k]) for k, _ in SUMMARY_FIELDS])
+    return {k: v[:J].copy() for k, v in out.items()}
+
+
+GRID_FIELDS = (("key", np.int64), ("count", np.uint32), ("n_journeys", np.uint32),
+               ("sum_speed", np.float64), ("min_speed", np.float32), ("max_speed", np.float32))
+
+
+def _spec_args(spec):
+    return (float(spec.lat0_deg), float(spec.lon0_deg), float(spec.dlat_deg), float(spec.dlon_deg),
+            int(spec.n_lat), int(spec.n_lon), int(spec.t0_ms), int(spec.bin_ms), int(spec.n_t))
+
+
+def grid_keys(ts, lat, lon, spec):
+    ts = _c(ts, np.int64)
+    lat, lon = _c(lat, np.float64), _c(lon, np.float64)
+    n = ts.shape[0]
+    key = np.empty(n, dtype=np.int64)
+    n_out = lib().orc_grid_keys(n, _p(ts), _p(lat), _p(lon), *_spec_args(spec), _p(key))
+    return key, int(n_out)
+
+
+def grid(jid, ts, lat, lon, speed, spec):
+    jid, ts = _c(jid, np.int64), _c(ts, np.int64)
+    lat, lon, speed = _c(lat, np.float64), _c(lon, np.float64), _c(speed, np.float32)
+    n = jid.shape[0]
+    cap = max(1, n)
+    out = {k: np.empty(cap, dtype=t) for k, t in GRID_FIELDS}
+    n_out = np.zeros(1, dtype=np.int64)
+    G = lib().orc_grid(n, _p(jid), _p(ts), _p(lat), _p(lon), _p(speed), *_spec_args(spec), cap,
+                       *[_p(out[k]) for k, _ in GRID_FIELDS], _p(n_out))
+    res = {k: v[:G].copy() for k, v in out.items()}
+    return res, int(n_out[0])
+
+
+def run_plain(cols, spec):
+    """The whole plain path on one batch: order, features, summaries, grid."""
+    jid, ts, lat, lon, speed = cols
+    perm = sort(jid, ts)
+    s = sorted_records(cols, perm)
+    feat = features(s[0], s[1], s[2], s[3])
+    summ = summary(*s, feat)
+    groups, n_out = grid(*s, spec)
+    return dict(perm=perm, sorted=s, features=feat, summary=summ, groups=groups, n_out=n_out)

@@ -1,0 +1,296 @@
+"""Seeded synthetic connected-vehicle record generator.
+
+This module only draws inputs.  It holds none of the ETL method's arithmetic
+(no sorting by journey, no kinematics, no binning, no aggregation), so both the
+HIP path and the CPU oracle may take their inputs from it.
+
+The record shape follows the paper's dataset description (Methods, "Connected
+Vehicle Dataset", and Table 1): one row per sensor sample with a journey
+identifier, a timestamp, latitude, longitude and speed.  The real Missouri DOT
+data is not public; these workloads stand in for it:
+
+* box: latitude [36.0, 40.6), longitude [-95.8, -89.1) (Missouri);
+* vehicles: random walks, per-axis steps N(0, (2e-4 deg)^2), reflected at the
+  box edges (implemented as a fold of the free walk, which equals per-step
+  reflection because every step is far smaller than the box);
+* time: 1 Hz samples (20 Hz for the heavy journeys of the skewed stream, the
+  0.05 s resolution the paper states), inside one day starting at
+  2021-05-09T00:00:00Z (the date of the sample rows in Table 1);
+* speed: float32 uniform on [0, 40) m/s with 5 % exact zeros (stopped cars);
+* journey ids: distinct random non-negative 63-bit integers (stand-ins for
+  hashed string ids such as "33456rd").
+"""
+from __future__ import annotations
+
+import dataclasses
+import numpy as np
+
+T0_MS = 1_620_518_400_000          # 2021-05-09T00:00:00Z in ms since the epoch
+DAY_MS = 86_400_000
+LAT_LO, LAT_HI = 36.0, 40.6
+LON_LO, LON_HI = -95.8, -89.1
+WALK_SIGMA_DEG = 2e-4
+SEED_BASE = 230507454
+
+
+@dataclasses.dataclass(frozen=True)
+class GridSpec:
+    """Spatio-temporal binning parameters (Algorithm 2's origin and steps)."""
+    lat0_deg: float
+    lon0_deg: float
+    dlat_deg: float
+    dlon_deg: float
+    n_lat: int
+    n_lon: int
+    t0_ms: int
+    bin_ms: int
+    n_t: int            # <= 0: unbounded number of time bins
+
+    def as_tuple(self):
+        return dataclasses.astuple(self)
+
+
+def grid_for(step_deg: float, bin_ms: int, n_t: int | None = None) -> GridSpec:
+    n_lat = int(round((LAT_HI - LAT_LO) / step_deg))
+    n_lon = int(round((LON_HI - LON_LO) / step_deg))
+    if n_t is None:
+        n_t = DAY_MS // bin_ms
+    return GridSpec(LAT_LO, LON_LO, step_deg, step_deg, n_lat, n_lon, T0_MS, bin_ms, n_t)
+
+
+GRIDS = {
+    "c0": grid_for(0.01, 15 * 60_000),
+    "c1": grid_for(0.005, 5 * 60_000),
+    "c2": grid_for(0.001, 60_000),
+    "c3": grid_for(0.005, 5 * 60_000, n_t=0),
+    "c4": grid_for(0.001, 60_000, n_t=0),
+}
+
+
+@dataclasses.dataclass
+class Records:
+    """Structure-of-arrays record batch (host numpy arrays)."""
+    journey_id: np.ndarray   # int64
+    ts_ms: np.ndarray        # int64
+    lat_deg: np.ndarray      # float64
+    lon_deg: np.ndarray      # float64
+    speed_mps: np.ndarray    # float32
+    meta: dict = dataclasses.field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return int(self.journey_id.shape[0])
+
+    def take(self, idx) -> "Records":
+        return Records(self.journey_id[idx], self.ts_ms[idx], self.lat_deg[idx],
+                       self.lon_deg[idx], self.speed_mps[idx], dict(self.meta))
+
+    def columns(self):
+        return (self.journey_id, self.ts_ms, self.lat_deg, self.lon_deg, self.speed_mps)
+
+
+def concat(parts) -> Records:
+    parts = list(parts)
+    return Records(*(np.concatenate([p.columns()[i] for p in parts]) for i in range(5)))
+
+
+def rng_for(config_index: int, seed: int | None = None) -> np.random.Generator:
+    s = SEED_BASE + config_index if seed is None else seed
+    return np.random.default_rng(np.random.SeedSequence(s))
+
+
+# ----------------------------------------------------------------------------
+# building blocks
+# ----------------------------------------------------------------------------
+
+def _fold(x, lo, hi):
+    """Reflect a free walk into [lo, hi)."""
+    w = hi - lo
+    m = np.mod(x - lo, 2.0 * w)
+    y = lo + (w - np.abs(m - w))
+    np.clip(y, lo, np.nextafter(hi, lo), out=y)
+    return y
+
+
+def journey_ids(rng, n_journeys: int) -> np.ndarray:
+    ids = np.unique(rng.integers(0, 2**63 - 1, size=n_journeys, dtype=np.int64))
+    while ids.shape[0] < n_journeys:            # collisions are ~impossible; keep it exact anyway
+        extra = rng.integers(0, 2**63 - 1, size=n_journeys - ids.shape[0], dtype=np.int64)
+        ids = np.unique(np.concatenate([ids, extra]))
+    return rng.permutation(ids)
+
+
+def speeds(rng, n: int, zero_frac: float = 0.05) -> np.ndarray:
+    s = rng.uniform(0.0, 40.0, size=n).astype(np.float32)
+    np.minimum(s, np.nextafter(np.float32(40.0), np.float32(0.0)), out=s)
+    s[rng.random(n) < zero_frac] = np.float32(0.0)
+    return s
+
+
+def walks(rng, lengths: np.ndarray, period_ms: int = 1000, day_start_ms: int = T0_MS,
+          start_ms: np.ndarray | None = None):
+    """Per-journey random walks, journeys laid out contiguously in time order.
+
+    Returns (ts, lat, lon, offsets) where offsets[j] is the first row of journey j.
+    """
+    lengths = np.asarray(lengths, dtype=np.int64)
+    j = lengths.shape[0]
+    n = int(lengths.sum())
+    offsets = np.zeros(j + 1, dtype=np.int64)
+    np.cumsum(lengths, out=offsets[1:])
+    heads = offsets[:-1]
+    lat_start = rng.uniform(LAT_LO, LAT_HI, size=j)
+    lon_start = rng.uniform(LON_LO, LON_HI, size=j)
+    if start_ms is None:
+        span = (lengths - 1) * period_ms
+        slack = np.maximum(DAY_MS - span, 1) // 1000          # whole seconds of slack in the day
+        start_ms = day_start_ms + 1000 * (rng.random(j) * slack).astype(np.int64)
+    pos = np.arange(n, dtype=np.int64) - np.repeat(heads, lengths)
+    ts = np.repeat(np.asarray(start_ms, dtype=np.int64), lengths) + period_ms * pos
+    out = []
+    for start, lo, hi in ((lat_start, LAT_LO, LAT_HI), (lon_start, LON_LO, LON_HI)):
+        d = rng.normal(0.0, WALK_SIGMA_DEG, size=n)
+        d[heads] = 0.0
+        c = np.cumsum(d)
+        free = np.repeat(start, lengths) + (c - np.repeat(c[heads], lengths))
+        del c, d
+        out.append(_fold(free, lo, hi))
+        del free
+    return ts, out[0], out[1], offsets
+
+
+def _block_order(rng, offsets: np.ndarray) -> np.ndarray:
+    """Row order that concatenates journey blocks in a seeded random order."""
+    lengths = np.diff(offsets)
+    order = rng.permutation(lengths.shape[0])
+    new_len = lengths[order]
+    new_off = np.zeros(order.shape[0] + 1, dtype=np.int64)
+    np.cumsum(new_len, out=new_off[1:])
+    src_start = np.repeat(offsets[:-1][order], new_len)
+    return src_start + (np.arange(int(new_off[-1]), dtype=np.int64) - np.repeat(new_off[:-1], new_len))
+
+
+# ----------------------------------------------------------------------------
+# workloads
+# ----------------------------------------------------------------------------
+
+def make_c0(seed=None, n_journeys=2000, min_len=100, max_len=900) -> Records:
+    """Small plain workload: uniform lengths, fully shuffled rows."""
+    rng = rng_for(0, seed)
+    lengths = rng.integers(min_len, max_len + 1, size=n_journeys)
+    ids = journey_ids(rng, n_journeys)
+    ts, lat, lon, offsets = walks(rng, lengths)
+    spd = speeds(rng, ts.shape[0])
+    jid = np.repeat(ids, lengths)
+    perm = rng.permutation(ts.shape[0])
+    r = Records(jid[perm], ts[perm], lat[perm], lon[perm], spd[perm],
+                dict(config="c0", n_journeys=n_journeys, layout="shuffled"))
+    return r
+
+
+def c1_lengths(rng, n_journeys, median=1500.0, sigma=1.0, cap=86_400):
+    L = np.rint(rng.lognormal(np.log(median), sigma, size=n_journeys)).astype(np.int64)
+    return np.clip(L, 1, cap)
+
+
+def make_c1(seed=None, n_journeys=50_000, median=1500.0, cap=86_400, dup_frac=0.05,
+            swap_frac=0.02, shuffled=False) -> Records:
+    """Full-day plain workload: lognormal lengths, per-journey files in random
+    order, 5 % duplicated timestamps and 2 % rows swapped with their successor."""
+    rng = rng_for(1, seed)
+    lengths = c1_lengths(rng, n_journeys, median=median, cap=cap)
+    ids = journey_ids(rng, n_journeys)
+    ts, lat, lon, offsets = walks(rng, lengths)
+    n = ts.shape[0]
+    spd = speeds(rng, n)
+    jid = np.repeat(ids, lengths)
+    # duplicated timestamps: a non-first sample takes its predecessor's time stamp
+    is_head = np.zeros(n, dtype=bool)
+    is_head[offsets[:-1]] = True
+    dup = (rng.random(n) < dup_frac) & ~is_head
+    idx = np.nonzero(dup)[0]
+    ts_orig = ts.copy()
+    ts[idx] = ts_orig[idx - 1]
+    del ts_orig
+    # out-of-order rows: swap a row with its journey successor (non-overlapping swaps)
+    is_last = np.zeros(n, dtype=bool)
+    is_last[offsets[1:] - 1] = True
+    cand = (rng.random(n) < swap_frac) & ~is_last
+    cand[1:] &= ~cand[:-1]
+    a = np.nonzero(cand)[0]
+    order = np.arange(n, dtype=np.int64)
+    order[a], order[a + 1] = a + 1, a
+    if shuffled:
+        order = order[rng.permutation(n)]
+    else:
+        order = order[_block_order(rng, offsets)]
+    r = Records(jid[order], ts[order], lat[order], lon[order], spd[order],
+                dict(config="c1", n_journeys=n_journeys,
+                     layout="shuffled" if shuffled else "journey files, random order"))
+    return r
+
+
+def c2_shard_sizes(n_shards=115, total=400_000_000, lo=10_000, hi=20_000_000, alpha=1.2,
+                   seed=None):
+    """Capped rank-size (Zipf) shard sizes summing to `total`, in a seeded shard order."""
+    k = np.arange(1, n_shards + 1, dtype=np.float64)
+
+    def sizes(c):
+        return np.minimum(hi, np.maximum(lo, np.rint(c * k ** -alpha))).astype(np.int64)
+
+    a, b = 1.0, float(total) * 10
+    for _ in range(200):
+        mid = 0.5 * (a + b)
+        if sizes(mid).sum() < total:
+            a = mid
+        else:
+            b = mid
+    s = sizes(b)
+    s[-1] += total - int(s.sum())              # land exactly on the total
+    rng = rng_for(2, seed)
+    return s[rng.permutation(n_shards)]
+
+
+def make_shard(rng, n_records: int, period_ms=1000, mean_journey=1200.0, cap=86_400) -> Records:
+    """One county-day shard: Poisson journey count, lognormal length weights,
+    time-interleaved feed order."""
+    j = max(1, int(rng.poisson(n_records / mean_journey)))
+    j = min(j, n_records)
+    w = rng.lognormal(0.0, 1.0, size=j)
+    exact = w / w.sum() * n_records
+    L = np.floor(exact).astype(np.int64)
+    L = np.maximum(L, 1)
+    rem = n_records - int(L.sum())
+    if rem > 0:
+        frac_order = np.argsort(-(exact - np.floor(exact)), kind="stable")
+        L[frac_order[:rem]] += 1
+    while int(L.sum()) > n_records:           # only when the floor-at-1 pushed us over
+        i = int(np.argmax(L))
+        L[i] -= int(L.sum()) - n_records
+        L[i] = max(L[i], 1)
+    L = np.minimum(L, cap)
+    ids = journey_ids(rng, j)
+    ts, lat, lon, offsets = walks(rng, L, period_ms=period_ms)
+    spd = speeds(rng, ts.shape[0])
+    jid = np.repeat(ids, L)
+    order = np.lexsort((rng.random(ts.shape[0]), ts))      # feed order: by time, random ties
+    return Records(jid[order], ts[order], lat[order], lon[order], spd[order],
+                   dict(n_journeys=j))
+
+
+def make_c2(seed=None, n_shards=115, total=400_000_000, lo=10_000, hi=20_000_000):
+    """Batched workload: list of shards (each an independent problem)."""
+    sizes = c2_shard_sizes(n_shards, total, lo, hi, seed=seed)
+    children = np.random.SeedSequence(SEED_BASE + 2 if seed is None else seed + 1).spawn(n_shards)
+    shards = [make_shard(np.random.default_rng(c), int(s)) for c, s in zip(children, sizes)]
+    return shards
+
+
+def make(config: str, seed=None, **kw):
+    if config == "c0":
+        return make_c0(seed, **kw)
+    if config == "c1":
+        return make_c1(seed, **kw)
+    if config == "c2":
+        return make_c2(seed, **kw)
+    raise ValueError(f"unknown config {config!r}")

@@ -1,0 +1,446 @@
+"""Pins for the CPU oracle: it is checked against things other than itself --
+closed forms, library routines (math.fsum, numpy.lexsort), 50-digit mpmath
+references computed with *different* formulas, the paper's Table 1 rows, and
+brute force on tiny inputs.  Each test names the mistake it would catch."""
+import csv
+import datetime as dt
+import itertools
+import json
+import math
+import os
+
+import mpmath
+import numpy as np
+import pytest
+from hypothesis import given, settings, strategies as st
+
+import oracle
+from paper_2305_07454_amd import gen
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+R = 6371008.8
+pytestmark = []
+
+
+# --------------------------------------------------------------------------
+# exact summation
+# --------------------------------------------------------------------------
+
+def test_fsum_matches_math_fsum_random(oracle_mod):
+    rng = np.random.default_rng(1)
+    for n in (0, 1, 2, 7, 1000, 20000):
+        x = rng.standard_normal(n) * 10.0 ** rng.integers(-20, 20, size=n)
+        assert oracle.fsum(x) == math.fsum(x)
+
+
+def test_fsum_cancellation_and_halfway(oracle_mod):
+    cases = [
+        [1e100, 1.0, -1e100, 1e-100],
+        [1.0, 1e-16, 1e-16],                       # half-way correction
+        [0.1] * 10,
+        [2.0 ** 53, 1.0, 1.0],
+        [2.0 ** 53, -0.5, -2.0 ** -54],
+        [1e308, 1e308 * 0.5, -1e308],
+    ]
+    for c in cases:
+        assert oracle.fsum(np.array(c)) == math.fsum(c)
+
+
+# --------------------------------------------------------------------------
+# ordering
+# --------------------------------------------------------------------------
+
+def test_sort_matches_lexsort_with_ties(oracle_mod):
+    rng = np.random.default_rng(2)
+    n = 50000
+    jid = rng.integers(-5, 40, size=n).astype(np.int64) * (2 ** 58)   # negative ids, big values
+    ts = rng.integers(-3, 30, size=n).astype(np.int64)               # many ties
+    perm = oracle.sort(jid, ts)
+    ref = np.lexsort((np.arange(n), ts, jid))
+    assert np.array_equal(perm.astype(np.int64), ref)
+
+
+def test_sort_brute_force_tiny(oracle_mod):
+    # every ordering of a tiny multiset: output keys sorted, ties in input order
+    base = [(3, 5), (1, 2), (3, 5), (1, 1), (2, 7), (1, 2)]
+    for p in itertools.permutations(range(len(base))):
+        rows = [base[i] for i in p]
+        jid = np.array([r[0] for r in rows], dtype=np.int64)
+        ts = np.array([r[1] for r in rows], dtype=np.int64)
+        perm = oracle.sort(jid, ts).tolist()
+        assert perm == sorted(range(len(rows)), key=lambda i: (rows[i][0], rows[i][1], i))
+
+
+def test_sort_signed_extremes(oracle_mod):
+    jid = np.array([2 ** 63 - 1, -2 ** 63, 0, -1, 2 ** 63 - 1], dtype=np.int64)
+    ts = np.array([5, 9, 1, 2, 4], dtype=np.int64)
+    assert oracle.sort(jid, ts).tolist() == [1, 3, 2, 4, 0]
+
+
+# --------------------------------------------------------------------------
+# kinematics: closed forms and 50-digit references
+# --------------------------------------------------------------------------
+
+def _feat(lat, lon, ts=None, jid=None):
+    n = len(lat)
+    jid = np.zeros(n, np.int64) if jid is None else np.asarray(jid, np.int64)
+    ts = np.arange(n, dtype=np.int64) * 1000 if ts is None else np.asarray(ts, np.int64)
+    return oracle.features(jid, ts, np.asarray(lat, float), np.asarray(lon, float))
+
+
+def test_one_degree_of_meridian_and_equator(oracle_mod):
+    exact = float(mpmath.mpf("6371008.8") * mpmath.pi / 180)        # 111195.0802335329 m
+    assert abs(exact - 111195.0802335329) < 1e-9
+    for lat, lon in (([0.0, 1.0], [0.0, 0.0]), ([37.0, 38.0], [-92.0, -92.0]),
+                     ([0.0, 0.0], [0.0, 1.0]), ([0.0, 0.0], [-90.5, -89.5])):
+        f = _feat(lat, lon)
+        assert abs(f["step_m"][1] - exact) <= 2e-16 * exact
+
+
+def test_quarter_and_half_circumference(oracle_mod):
+    f = _feat([0.0, 90.0], [0.0, 0.0])
+    assert abs(f["step_m"][1] - float(mpmath.mpf("6371008.8") * mpmath.pi / 2)) < 1e-8
+    f = _feat([0.0, 0.0], [0.0, 180.0])                 # antipodes: exercises the clamp
+    assert abs(f["step_m"][1] - float(mpmath.mpf("6371008.8") * mpmath.pi)) < 1e-8
+    assert f["flags"][1] & oracle.FLAG_BEARING_OK
+
+
+def test_cardinal_bearings(oracle_mod):
+    f = _feat([10.0, 10.001], [20.0, 20.0])
+    assert f["bearing_deg"][1] == 0.0
+    f = _feat([0.0, 0.0], [20.0, 20.001])
+    assert abs(f["bearing_deg"][1] - 90.0) < 1e-12
+    f = _feat([10.0, 9.999], [20.0, 20.0])
+    assert f["bearing_deg"][1] == 180.0
+    f = _feat([0.0, 0.0], [20.0, 19.999])
+    assert abs(f["bearing_deg"][1] - 270.0) < 1e-12
+
+
+def _mp_ref(lat1, lon1, lat2, lon2):
+    """Chord-length distance and textbook bearing at 50 digits (different formulas)."""
+    mpmath.mp.dps = 50
+    d2r = mpmath.pi / 180
+    p1, l1, p2, l2 = (mpmath.mpf(v) * d2r for v in (lat1, lon1, lat2, lon2))
+    u1 = (mpmath.cos(p1) * mpmath.cos(l1), mpmath.cos(p1) * mpmath.sin(l1), mpmath.sin(p1))
+    u2 = (mpmath.cos(p2) * mpmath.cos(l2), mpmath.cos(p2) * mpmath.sin(l2), mpmath.sin(p2))
+    chord = mpmath.sqrt(sum((a - b) ** 2 for a, b in zip(u1, u2)))
+    dist = 2 * mpmath.mpf("6371008.8") * mpmath.asin(chord / 2)
+    y = mpmath.sin(l2 - l1) * mpmath.cos(p2)
+    x = mpmath.cos(p1) * mpmath.sin(p2) - mpmath.sin(p1) * mpmath.cos(p2) * mpmath.cos(l2 - l1)
+    b = mpmath.atan2(y, x) * 180 / mpmath.pi
+    if b < 0:
+        b += 360
+    return dist, b
+
+
+def test_haversine_and_bearing_vs_mpmath(oracle_mod):
+    rng = np.random.default_rng(3)
+    n = 400
+    lat1 = rng.uniform(36.0, 40.6, n)
+    lon1 = rng.uniform(-95.8, -89.1, n)
+    lat2 = lat1 + rng.normal(0, 2e-4, n)
+    lon2 = lon1 + rng.normal(0, 2e-4, n)
+    lat = np.empty(2 * n)
+    lon = np.empty(2 * n)
+    lat[0::2], lat[1::2] = lat1, lat2
+    lon[0::2], lon[1::2] = lon1, lon2
+    jid = np.repeat(np.arange(n), 2)
+    f = _feat(lat, lon, jid=jid, ts=np.tile([0, 1000], n))
+    for i in range(n):
+        d, b = _mp_ref(lat1[i], lon1[i], lat2[i], lon2[i])
+        got_d, got_b = f["step_m"][2 * i + 1], f["bearing_deg"][2 * i + 1]
+        assert abs(got_d - float(d)) <= 1e-15 * float(d)
+        diff = abs(got_b - float(b))
+        assert min(diff, 360.0 - diff) <= 1e-12
+
+
+def test_long_steps_vs_mpmath(oracle_mod):
+    rng = np.random.default_rng(4)
+    for _ in range(100):
+        a = rng.uniform(-80, 80, 2)
+        o = rng.uniform(-179, 179, 2)
+        f = _feat(a, o)
+        d, b = _mp_ref(a[0], o[0], a[1], o[1])
+        assert abs(f["step_m"][1] - float(d)) <= 1e-13 * float(d)
+        diff = abs(f["bearing_deg"][1] - float(b))
+        assert min(diff, 360.0 - diff) <= 1e-9
+
+
+def test_dt_speed_accel_on_meridian_walk(oracle_mod):
+    # step k along a meridian of k*delta degrees: arc = R*pi/180*k*delta (closed form),
+    # so v_k = arc_k/dt and a_k = R*pi/180*delta/dt^2 exactly in real arithmetic.
+    delta = 1e-5
+    k = np.arange(12)
+    lat = 37.0 + delta * k * (k + 1) / 2
+    lon = np.full(12, -92.0)
+    ts = np.arange(12, dtype=np.int64) * 2000        # 2 s apart
+    f = _feat(lat, lon, ts=ts)
+    assert np.all(f["dt_s"][1:] == 2.0)
+    arc = R * math.pi / 180 * delta * k[1:]
+    assert np.allclose(f["step_m"][1:], arc, rtol=1e-9)
+    assert np.allclose(f["speed_mps"][1:], arc / 2.0, rtol=1e-9)
+    acc = R * math.pi / 180 * delta / 4.0
+    assert np.all(f["flags"][2:] & oracle.FLAG_ACCEL_OK)
+    assert not f["flags"][1] & oracle.FLAG_ACCEL_OK          # predecessor is the journey head
+    assert np.allclose(f["accel_mps2"][2:], acc, rtol=1e-6)
+    assert np.all(f["bearing_deg"][1:] == 0.0)
+    assert np.all(f["dheading_deg"][2:] == 0.0)
+
+
+def _bearing_step(lat, lon, brg_deg, d=1e-4):
+    """A point roughly d degrees from (lat, lon) along compass bearing brg."""
+    b = math.radians(brg_deg)
+    return lat + d * math.cos(b), lon + d * math.sin(b) / math.cos(math.radians(lat))
+
+
+@pytest.mark.parametrize("b1,b2,expect", [(350, 10, 20), (10, 350, -20), (0, 180, 180),
+                                          (180, 0, 180), (90, 270, 180), (270, 90, 180),
+                                          (45, 45, 0), (300, 120, 180)])
+def test_heading_change_wrap(oracle_mod, b1, b2, expect):
+    lat0, lon0 = 38.0, -92.0
+    lat1, lon1 = _bearing_step(lat0, lon0, b1)
+    lat2, lon2 = _bearing_step(lat1, lon1, b2)
+    f = _feat([lat0, lat1, lat2], [lon0, lon1, lon2])
+    assert f["flags"][2] & oracle.FLAG_DHEAD_OK
+    got = f["dheading_deg"][2]
+    assert -180.0 < got <= 180.0
+    if expect == 180 and b1 % 180 == 0:
+        assert got == 180.0               # exact meridian reversal lands on +180, never -180
+    diff = abs(got - expect)
+    assert min(diff, 360.0 - diff) < 0.01
+
+
+def test_flags_heads_duplicates_and_bad_coordinates(oracle_mod):
+    nan, inf = float("nan"), float("inf")
+    jid = [1, 1, 1, 1, 2, 2, 2, 3]
+    ts = [0, 1000, 1000, 2000, 0, 1000, 2000, 5]
+    lat = [37.0, 37.001, 37.001, 37.002, 38.0, nan, 38.002, inf]
+    lon = [-92.0, -92.0, -92.0, -92.0, -91.0, -91.0, -91.0, -91.0]
+    f = oracle.features(np.array(jid), np.array(ts), np.array(lat), np.array(lon))
+    F = oracle
+    assert f["flags"][0] == F.FLAG_FIRST
+    assert f["flags"][1] == F.FLAG_SPEED_OK | F.FLAG_BEARING_OK
+    # identical coordinates and timestamp: zero step, no speed, no bearing
+    assert f["flags"][2] == F.FLAG_DT_ZERO
+    assert f["step_m"][2] == 0.0 and f["bearing_deg"][2] == 0.0
+    # predecessor had no speed -> no accel; predecessor had no bearing -> no heading change
+    assert f["flags"][3] == F.FLAG_SPEED_OK | F.FLAG_BEARING_OK
+    assert f["flags"][4] == F.FLAG_FIRST
+    assert f["flags"][5] == F.FLAG_BAD_COORD                  # non-finite at k
+    assert f["flags"][6] == F.FLAG_BAD_COORD                  # non-finite at predecessor
+    assert f["flags"][7] == F.FLAG_FIRST | F.FLAG_BAD_COORD
+    for k in (0, 2, 4, 5, 6, 7):
+        assert all(f[c][k] == 0.0 for c in ("step_m", "speed_mps", "accel_mps2", "dheading_deg"))
+
+
+# --------------------------------------------------------------------------
+# summaries
+# --------------------------------------------------------------------------
+
+def _plain(cols, spec):
+    return oracle.run_plain(cols, spec)
+
+
+def test_summary_against_numpy_and_fsum(oracle_mod):
+    r = gen.make_c1(seed=11, n_journeys=60, median=300.0)
+    out = _plain(r.columns(), gen.GRIDS["c1"])
+    jid, ts, lat, lon, spd = out["sorted"]
+    f, s = out["features"], out["summary"]
+    u, first, counts = np.unique(jid, return_index=True, return_counts=True)
+    assert np.array_equal(s["journey_id"], u)
+    assert np.array_equal(s["first"], first)
+    assert np.array_equal(s["n_points"], counts)
+    assert int(s["n_points"].sum()) == r.n
+    for j in range(len(u)):
+        a, b = first[j], first[j] + counts[j]
+        assert s["distance_m"][j] == math.fsum(f["step_m"][a:b])
+        assert s["sum_speed"][j] == math.fsum(spd[a:b].astype(np.float64))
+        assert s["max_speed"][j] == spd[a:b].max()
+        assert s["t_start_ms"][j] == ts[a:b].min() and s["t_end_ms"][j] == ts[a:b].max()
+        assert s["lat_min"][j] == lat[a:b].min() and s["lon_max"][j] == lon[a:b].max()
+        ok = (f["flags"][a:b] & oracle.FLAG_SPEED_OK) != 0
+        assert s["max_derived_speed"][j] == (f["speed_mps"][a:b][ok].max() if ok.any() else 0.0)
+        assert s["n_dt_zero"][j] == int(((f["flags"][a:b] & oracle.FLAG_DT_ZERO) != 0).sum())
+
+
+def test_summary_max_derived_speed_only_over_speed_ok(oracle_mod):
+    jid = np.zeros(3, np.int64)
+    ts = np.array([0, 1000, 1000], np.int64)
+    z = np.zeros(3)
+    feat = dict(step_m=z, speed_mps=np.array([0.0, 5.0, 99.0]),
+                flags=np.array([oracle.FLAG_FIRST, oracle.FLAG_SPEED_OK, oracle.FLAG_DT_ZERO], np.uint8))
+    s = oracle.summary(jid, ts, np.full(3, 37.0), np.full(3, -92.0), np.ones(3, np.float32), feat)
+    assert s["max_derived_speed"][0] == 5.0 and s["n_dt_zero"][0] == 1
+
+
+def test_summary_distance_is_sum_of_steps_negative_zero_speed(oracle_mod):
+    jid = np.array([7, 7, 7], np.int64)
+    ts = np.array([0, 1000, 2000], np.int64)
+    lat = np.array([37.0, 37.0001, 37.0003])
+    lon = np.array([-92.0, -92.0, -92.0])
+    spd = np.array([-0.0, -0.0, -0.0], np.float32)
+    f = oracle.features(jid, ts, lat, lon)
+    s = oracle.summary(jid, ts, lat, lon, spd, f)
+    assert s["distance_m"][0] == math.fsum(f["step_m"])
+    assert math.copysign(1.0, float(s["max_speed"][0])) == 1.0      # -0.0 counted as +0.0
+
+
+# --------------------------------------------------------------------------
+# grid aggregate
+# --------------------------------------------------------------------------
+
+def _brute_grid(jid, ts, lat, lon, spd, spec):
+    groups = {}
+    n_out = 0
+    for i in range(len(jid)):
+        la, lo = float(lat[i]), float(lon[i])
+        if not (math.isfinite(la) and math.isfinite(lo)):
+            n_out += 1
+            continue
+        y = math.floor((la - spec.lat0_deg) / spec.dlat_deg)
+        x = math.floor((lo - spec.lon0_deg) / spec.dlon_deg)
+        t = (int(ts[i]) - spec.t0_ms) // spec.bin_ms
+        if not (0 <= y < spec.n_lat and 0 <= x < spec.n_lon and t >= 0 and (spec.n_t <= 0 or t < spec.n_t)):
+            n_out += 1
+            continue
+        k = (t * spec.n_lat + y) * spec.n_lon + x
+        g = groups.setdefault(k, [0, set(), [], []])
+        g[0] += 1
+        g[1].add(int(jid[i]))
+        g[2].append(float(spd[i]))
+        g[3].append(float(spd[i]) + 0.0)
+    return groups, n_out
+
+
+def test_grid_brute_force(oracle_mod):
+    r = gen.make_c0(seed=5, n_journeys=40, min_len=20, max_len=200)
+    spec = gen.grid_for(0.01, 60_000)
+    jid, ts, lat, lon, spd = r.columns()
+    lat = lat.copy()
+    lat[::97] = 35.5              # some out-of-box points
+    lat[5] = float("nan")
+    res, n_out = oracle.grid(jid, ts, lat, lon, spd, spec)
+    ref, ref_out = _brute_grid(jid, ts, lat, lon, spd, spec)
+    assert n_out == ref_out
+    assert res["key"].tolist() == sorted(ref)
+    for i, k in enumerate(res["key"].tolist()):
+        c, js, ss, ss0 = ref[k]
+        assert res["count"][i] == c
+        assert res["n_journeys"][i] == len(js)
+        assert res["sum_speed"][i] == math.fsum(ss)
+        assert res["min_speed"][i] == min(ss0) and res["max_speed"][i] == max(ss0)
+    assert int(res["count"].sum()) + n_out == r.n
+    pairs = {(k, j) for k, v in ref.items() for j in v[1]}
+    assert int(res["n_journeys"].sum()) == len(pairs)
+
+
+def test_grid_line_cases(oracle_mod):
+    # Alg. 2 reading: floor of the rounded quotient, not Python's exact-quotient //
+    spec = gen.GridSpec(36.0, -95.8, 0.005, 0.005, 920, 1340, 0, 300_000, 288)
+    key, n_out = oracle.grid_keys(np.array([0, 0]), np.array([38.75, 36.01]),
+                                  np.array([-95.8, -95.8]), spec)
+    assert key[0] // 1340 == 550          # fl(2.75/0.005) = 550.0, while 2.75 // 0.005 = 549
+    spec = gen.GridSpec(36.0, -95.8, 0.01, 0.01, 460, 670, 0, 300_000, 288)
+    key, _ = oracle.grid_keys(np.array([0]), np.array([36.01]), np.array([-95.8]), spec)
+    assert key[0] // 670 == 0             # (36.01-36.0)/0.01 = 0.999999999999801
+    # cells where a reciprocal-multiply would land on the next bin: IEEE division
+    # and the exact rational quotient of the binary inputs both floor one lower
+    from fractions import Fraction
+    for lat, step, expect in ((38.68, 0.01, 267), (38.805, 0.005, 560), (36.561, 0.001, 560)):
+        sp = gen.GridSpec(36.0, -95.8, step, step, 4600, 6700, 0, 300_000, 288)
+        key, _ = oracle.grid_keys(np.array([0]), np.array([lat]), np.array([-95.8]), sp)
+        assert key[0] // 6700 == expect
+        assert math.floor((Fraction(lat) - Fraction(36.0)) / Fraction(step)) == expect
+        assert math.floor((lat - 36.0) * (1.0 / step)) == expect + 1
+    # time bins floor toward -inf: ts before t0 is out of grid; the last bin edge is exclusive
+    key, n_out = oracle.grid_keys(np.array([-1, 0, 299_999, 300_000, 288 * 300_000 - 1, 288 * 300_000]),
+                                  np.full(6, 37.0), np.full(6, -92.0), spec)
+    assert n_out == 2 and key[0] == -1 and key[5] == -1
+    assert [int(k) // (460 * 670) for k in key[1:5]] == [0, 0, 1, 287]
+    # box edges are half-open
+    key, n_out = oracle.grid_keys(np.zeros(4, np.int64), np.array([36.0, 40.6, 37.0, 37.0]),
+                                  np.array([-92.0, -92.0, -95.8, -89.1]), spec)
+    assert key[0] >= 0 and key[1] == -1 and key[2] >= 0 and key[3] == -1
+
+
+def test_grid_distinct_journeys_with_cell_reentry(oracle_mod):
+    # one journey oscillating across a cell boundary inside one time bin, a second
+    # journey visiting one of the cells once
+    spec = gen.GridSpec(36.0, -95.8, 0.01, 0.01, 460, 670, 0, 300_000, 288)
+    lat = np.array([37.004, 37.012, 37.003, 37.011, 37.002, 37.005])
+    jid = np.array([1, 1, 1, 1, 1, 2])
+    ts = np.array([0, 1000, 2000, 3000, 4000, 0])
+    res, _ = oracle.grid(jid, ts, lat, np.full(6, -92.0), np.ones(6, np.float32), spec)
+    assert res["count"].tolist() == [4, 2]
+    assert res["n_journeys"].tolist() == [2, 1]
+
+
+# --------------------------------------------------------------------------
+# the paper's own sample rows (Table 1)
+# --------------------------------------------------------------------------
+
+def _table1():
+    rows = [r for r in csv.reader(open(os.path.join(GOLDEN, "table1_records.csv")))
+            if r and not r[0].startswith("#")][1:]
+    names = sorted({r[0] for r in rows})
+    t0 = dt.datetime(2021, 5, 9, tzinfo=dt.timezone.utc)
+    jid = np.array([names.index(r[0]) for r in rows], np.int64)
+    ts = np.array([int((dt.datetime.strptime(r[1], "%Y-%m-%d %H:%M:%S").replace(tzinfo=dt.timezone.utc)
+                        - t0).total_seconds() * 1000) for r in rows], np.int64)
+    lat = np.array([float(r[2]) for r in rows])
+    lon = np.array([float(r[3]) for r in rows])
+    spd = np.array([float(r[5]) for r in rows], np.float32)
+    return jid, ts, lat, lon, spd
+
+
+def test_table1_golden(oracle_mod):
+    exp = json.load(open(os.path.join(GOLDEN, "table1_expected.json")))
+    cols = _table1()
+    spec = gen.GridSpec(**exp["grid"])
+    out = oracle.run_plain(cols, spec)
+    assert out["perm"].tolist() == exp["sorted_input_rows"]
+    assert out["features"]["flags"].tolist() == exp["flags_sorted"]
+    s = out["summary"]
+    for i, j in enumerate(exp["journeys"]):
+        for k, v in j.items():
+            assert s[k][i] == v, k
+    g = out["groups"]
+    assert out["n_out"] == exp["n_out_of_grid"]
+    for i, e in enumerate(exp["groups"]):
+        assert g["key"][i] == e["key"] and g["count"][i] == e["count"]
+        assert g["n_journeys"][i] == e["n_journeys"]
+        sp = [float(np.float32(v)) for v in e["speeds"]]
+        assert g["sum_speed"][i] == math.fsum(sp)
+        assert g["min_speed"][i] == np.float32(min(sp)) and g["max_speed"][i] == np.float32(max(sp))
+
+
+# --------------------------------------------------------------------------
+# brute force on tiny random inputs (hypothesis)
+# --------------------------------------------------------------------------
+
+@settings(max_examples=60, deadline=None)
+@given(st.lists(st.tuples(st.integers(0, 3), st.integers(0, 4), st.integers(0, 5), st.integers(0, 5),
+                          st.sampled_from([0.0, 1.5, 3.25, -0.0, 39.5])), min_size=0, max_size=30))
+def test_tiny_random_plain_path(rows):
+    oracle.lib()
+    n = len(rows)
+    jid = np.array([r[0] for r in rows], np.int64)
+    ts = np.array([r[1] * 1000 for r in rows], np.int64)
+    lat = np.array([37.0 + 0.004 * r[2] for r in rows])
+    lon = np.array([-92.0 + 0.004 * r[3] for r in rows])
+    spd = np.array([r[4] for r in rows], np.float32)
+    spec = gen.GridSpec(36.0, -95.8, 0.01, 0.01, 460, 670, 0, 2000, 3)
+    out = oracle.run_plain((jid, ts, lat, lon, spd), spec)
+    # order
+    assert out["perm"].tolist() == sorted(range(n), key=lambda i: (rows[i][0], rows[i][1], i))
+    # summary invariants
+    s = out["summary"]
+    assert len(s["journey_id"]) == len(set(jid.tolist()))
+    assert int(s["n_points"].sum()) == n
+    # grid vs brute force
+    ref, ref_out = _brute_grid(jid, ts, lat, lon, spd, spec)
+    g = out["groups"]
+    assert out["n_out"] == ref_out
+    assert g["key"].tolist() == sorted(ref)
+    assert g["n_journeys"].tolist() == [len(ref[k][1]) for k in sorted(ref)]
+    assert g["sum_speed"].tolist() == [math.fsum(ref[k][2]) for k in sorted(ref)]

@@ -1,0 +1,230 @@
+/*
+ * cvetl.h -- C ABI of the MI355X (gfx950) connected-vehicle ETL core.
+ *
+ * The paper this implements ("Accelerating Statewide Connected Vehicles Big
+ * (Sensor Fusion) Data ETL Pipelines on GPUs", Methods: "Accelerated ETL
+ * Algorithm/Framework for Spatio-Temporal CV Data", steps (2)-(6), and
+ * Algorithm 2) turns raw per-vehicle sensor records into an index over unique
+ * journeys and a spatio-temporal lattice of per-cell reductions.  This library
+ * exposes that data-parallel core as four stream-ordered calls:
+ *
+ *   cv_sort_records      order records by (journey id, timestamp)  [step (2): unique index]
+ *   cv_journey_features  per-point kinematics inside each journey  [sensor fields of the dataset]
+ *   cv_journey_summary   one summary row per journey               [unique journeys, Abstract/Discussion]
+ *   cv_grid_aggregate    (time bin x lat bin x lon bin) aggregates [steps (3)-(5), Algorithm 2, Table 3 reductions]
+ *
+ * Conventions for every call
+ * --------------------------
+ * - All array pointers are DEVICE pointers unless marked [host].  Structs passed
+ *   by pointer (cv_records, cv_features, ...) live in host memory and are read
+ *   before the call returns.
+ * - Every call only enqueues kernels on `stream` (a hipStream_t; NULL = the
+ *   default stream).  It never synchronises and never allocates: scratch
+ *   memory comes from the caller's workspace `ws` of `ws_bytes` bytes, whose
+ *   required size the matching *_workspace_size() call returns.  The
+ *   workspace must be 256-byte aligned and must not be shared by calls that
+ *   may run concurrently.
+ * - The caller owns all memory.  Outputs must not alias inputs.
+ * - Argument errors are returned synchronously as a cv_status and nothing is
+ *   enqueued.  Conditions only the device can see (output capacity exceeded,
+ *   key range too wide) are written to the caller's device-resident cv_result
+ *   (`res`, may be NULL when the caller does not need it) by the last kernel
+ *   of the call; read it after synchronising the stream.
+ * - n == 0 is valid and produces empty outputs.  n must be < 2^32.
+ * - Floating-point results are deterministic: every sum is accumulated exactly
+ *   in fixed point (integer adds are order-independent) and rounded once.
+ */
+#ifndef CVETL_H
+#define CVETL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CV_ABI_VERSION 1u
+
+typedef enum {
+    CV_OK = 0,
+    CV_ERR_INVALID_ARGUMENT = 1, /* null pointer, bad size or bad grid spec           */
+    CV_ERR_WORKSPACE = 2,        /* ws NULL, misaligned or smaller than required       */
+    CV_ERR_CAPACITY = 3,         /* (device) output rows exceed capacity; see required */
+    CV_ERR_RANGE = 4,            /* (device) packed sort key would exceed 64 bits      */
+    CV_ERR_DEVICE = 5,           /* a HIP launch or runtime call failed                */
+    CV_ERR_UNSUPPORTED = 6       /* no gfx950 device / feature not available           */
+} cv_status;
+
+/* Raw sensor records, structure of arrays (Table 1's columns used by the path). */
+typedef struct {
+    const int64_t* journey_id; /* opaque journey id mapped to int64 by the caller      */
+    const int64_t* ts_ms;      /* sample time, integer milliseconds                    */
+    const double* lat_deg;     /* WGS84 latitude, degrees                              */
+    const double* lon_deg;     /* WGS84 longitude, degrees                             */
+    const float* speed_mps;    /* sensor speed; finite, |speed| < 1024                 */
+    uint64_t n;                /* number of records, < 2^32                            */
+} cv_records;
+
+/* Output columns of the sort: the input columns permuted into sorted order. */
+typedef struct {
+    int64_t* journey_id;
+    int64_t* ts_ms;
+    double* lat_deg;
+    double* lon_deg;
+    float* speed_mps;
+} cv_records_out;
+
+/* Per-point kinematics; every array has n elements (one per sorted record). */
+typedef struct {
+    double* step_m;       /* haversine distance from the predecessor, metres       */
+    double* dt_s;         /* time since the predecessor, seconds                   */
+    double* speed_mps;    /* step_m / dt_s when dt > 0                             */
+    double* accel_mps2;   /* backward difference of speed_mps over dt_s            */
+    double* bearing_deg;  /* initial great-circle course, [0, 360)                 */
+    double* dheading_deg; /* bearing change, (-180, 180]                           */
+    uint8_t* flags;       /* CV_FLAG_* bits                                        */
+} cv_features;
+
+#define CV_FLAG_FIRST 0x01u      /* first record of its journey                 */
+#define CV_FLAG_DT_ZERO 0x02u    /* same timestamp as the predecessor           */
+#define CV_FLAG_SPEED_OK 0x04u   /* speed_mps defined                           */
+#define CV_FLAG_ACCEL_OK 0x08u   /* accel_mps2 defined                          */
+#define CV_FLAG_BEARING_OK 0x10u /* bearing_deg defined (non-zero step)         */
+#define CV_FLAG_DHEAD_OK 0x20u   /* dheading_deg defined                        */
+#define CV_FLAG_BAD_COORD 0x40u  /* non-finite coordinate here or predecessor   */
+
+/* One row per journey, ascending journey id; each array has `capacity` rows. */
+typedef struct {
+    int64_t* journey_id;
+    uint32_t* first;             /* index of the journey's first sorted record      */
+    uint32_t* n_points;
+    int64_t* t_start_ms;
+    int64_t* t_end_ms;
+    double* distance_m;          /* exact-rounded sum of step_m                     */
+    double* sum_speed;           /* exact-rounded sum of the sensor speed           */
+    float* max_speed;            /* max sensor speed (-0 as +0)                     */
+    double* max_derived_speed;   /* max speed_mps over SPEED_OK points, else 0      */
+    uint32_t* n_dt_zero;         /* number of DT_ZERO points                        */
+    double* lat_min;             /* bounding box over points with finite lat & lon  */
+    double* lat_max;             /*   (+inf / -inf when there is none)              */
+    double* lon_min;
+    double* lon_max;
+} cv_journeys;
+
+/* Binning parameters of Algorithm 2: lat_bin = floor((lat - lat0) / dlat) etc. */
+typedef struct {
+    double lat0_deg, lon0_deg; /* grid origin (south-west corner)                   */
+    double dlat_deg, dlon_deg; /* cell size, > 0                                    */
+    int64_t n_lat, n_lon;      /* cells per axis, > 0                               */
+    int64_t t0_ms;             /* start of time bin 0                               */
+    int64_t bin_ms;            /* time-bin width, > 0                               */
+    int64_t n_t;               /* number of time bins; <= 0 means unbounded         */
+} cv_grid_spec;
+
+/* One row per occupied (time bin, cell) key, ascending key. */
+typedef struct {
+    int64_t* key;         /* (tbin * n_lat + ilat) * n_lon + ilon               */
+    uint32_t* count;      /* records in the cell                                */
+    uint32_t* n_journeys; /* distinct journey ids in the cell                   */
+    double* sum_speed;    /* exact-rounded sum of speed (mean = sum / count)    */
+    float* min_speed;     /* -0 as +0                                           */
+    float* max_speed;
+} cv_groups;
+
+/* Device-resident result word written by the last kernel of a call. */
+typedef struct {
+    uint32_t status;        /* cv_status of the device-side checks              */
+    uint32_t flags;         /* reserved, 0                                      */
+    uint64_t count;         /* rows produced (journeys / groups)                */
+    uint64_t required;      /* capacity needed when status == CV_ERR_CAPACITY   */
+    uint64_t n_out_of_grid; /* records outside the grid (grid call)             */
+    uint64_t n_late;        /* reserved for streaming, 0                        */
+    uint64_t key_bits;      /* bits of the packed sort key (sort call)          */
+    uint64_t reserved[2];
+} cv_result;
+
+uint32_t cv_abi_version(void);
+const char* cv_strerror(cv_status s);
+
+/* ------------------------------------------------------------------------
+ * cv_sort_records -- stable order of the records by (journey_id, ts_ms), both
+ * compared as signed 64-bit integers, ties in input order (the paper's unique
+ * index over all journeys, Methods step (2)).
+ *   in            [host struct] input columns (device arrays), n records.
+ *   max_journeys  capacity of the journey dictionary (distinct journey ids);
+ *                 more distinct ids set res->status = CV_ERR_CAPACITY and
+ *                 res->required to a lower bound of the distinct count.
+ *   perm          [device, n] out: perm[k] = input index of the k-th record.
+ *   sorted        [host struct, nullable] out columns; any member may be NULL.
+ *   res           [device, nullable] out: status, count = distinct journeys,
+ *                 key_bits = bits of the packed (journey rank, time) key;
+ *                 status CV_ERR_RANGE if that key would exceed 64 bits.
+ *   ws, ws_bytes  workspace of at least cv_sort_workspace_size(n, max_journeys).
+ * --------------------------------------------------------------------- */
+cv_status cv_sort_workspace_size(uint64_t n, uint64_t max_journeys, size_t* bytes /*[host]*/);
+cv_status cv_sort_records(const cv_records* in, uint64_t max_journeys, uint32_t* perm,
+                          const cv_records_out* sorted, cv_result* res, void* ws, size_t ws_bytes,
+                          void* stream);
+
+/* ------------------------------------------------------------------------
+ * cv_journey_features -- per-point kinematics of records already in
+ * (journey, time) order.  For record k with predecessor p = k-1 in the same
+ * journey: dt_s = (ts[k]-ts[p])/1000; step_m = haversine distance on a sphere
+ * of radius 6371008.8 m; speed = step/dt when dt > 0; accel = (speed[k] -
+ * speed[p]) / dt when both speeds are defined; bearing = initial course from p
+ * to k when the step is non-zero; dheading = bearing[k] - bearing[p] wrapped
+ * into (-180, 180] when both are defined.  The first record of a journey and
+ * records with a non-finite coordinate at k or p get all-zero values and the
+ * FIRST / BAD_COORD flags.  No workspace.
+ * --------------------------------------------------------------------- */
+cv_status cv_journey_features(const cv_records* sorted, const cv_features* out, void* stream);
+
+/* ------------------------------------------------------------------------
+ * cv_journey_summary -- one row per journey (maximal run of equal journey_id)
+ * of sorted records, in ascending journey id, from the records and their
+ * features (step_m, speed_mps and flags are read).  Rows past `capacity` are
+ * not written; then res->status = CV_ERR_CAPACITY, res->required = journeys.
+ * res->count = number of journeys.
+ * --------------------------------------------------------------------- */
+cv_status cv_summary_workspace_size(uint64_t n, uint64_t capacity, size_t* bytes /*[host]*/);
+cv_status cv_journey_summary(const cv_records* sorted, const cv_features* feat,
+                             const cv_journeys* out, uint64_t capacity, cv_result* res, void* ws,
+                             size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * cv_grid_aggregate -- spatio-temporal lattice of Algorithm 2 and Methods
+ * steps (3)-(5) over sorted records.  ilat = floor((lat - lat0)/dlat) and ilon
+ * likewise (one IEEE subtraction, one IEEE division, floor), tbin =
+ * floor((ts - t0)/bin_ms) in integers; a record is in the grid when both
+ * coordinates are finite, 0 <= ilat < n_lat, 0 <= ilon < n_lon, tbin >= 0 and
+ * tbin < n_t (n_t > 0) or the key fits in int64 (n_t <= 0).  Per key:
+ * count, distinct journeys, exact-rounded speed sum, min and max speed; rows
+ * in ascending key.  `capacity` bounds the rows and sizes the group hash
+ * table; more groups set res->status = CV_ERR_CAPACITY with res->required.
+ * res->count = groups, res->n_out_of_grid = records outside the grid.
+ * --------------------------------------------------------------------- */
+cv_status cv_grid_workspace_size(uint64_t n, const cv_grid_spec* grid /*[host]*/, uint64_t capacity,
+                                 size_t* bytes /*[host]*/);
+cv_status cv_grid_aggregate(const cv_records* sorted, const cv_grid_spec* grid /*[host]*/,
+                            const cv_groups* out, uint64_t capacity, cv_result* res, void* ws,
+                            size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Per-kernel timing (measurement support).  When enabled, the library brackets
+ * every launch of the named kernel family with HIP events on the launch stream
+ * and accumulates the elapsed time; cv_timing_read synchronises those events.
+ * Families: "sort_prep", "sort_pass0" .. "sort_pass7" (one per radix digit
+ * pass of the record sort; a pass whose digit lies above the packed key's
+ * width exits at once on the device), "gather", "features", "summary",
+ * "grid_agg", "grid_tail".
+ * --------------------------------------------------------------------- */
+cv_status cv_timing_enable(int on);
+cv_status cv_timing_reset(void);
+cv_status cv_timing_read(const char* family /*[host]*/, double* total_ms /*[host]*/,
+                         uint64_t* launches /*[host]*/);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CVETL_H */

@@ -74,7 +74,11 @@ static void xsum_add(xsum_t* s, double x)
     s->n = i + 1;
 }
 
-static double xsum_round(const xsum_t* s)
+/* An exactly-zero sum is +0.0 (signed zeros count as +0.0 throughout). */
+static double xsum_round_raw(const xsum_t* s);
+static double xsum_round(const xsum_t* s) { return xsum_round_raw(s) + 0.0; }
+
+static double xsum_round_raw(const xsum_t* s)
 {
     int n = s->n;
     double hi = 0.0, lo = 0.0;
@@ -224,7 +228,7 @@ void orc_features(int64_t n, const int64_t* jid, const int64_t* ts,
 /* Per-journey summary (one row per journey, ascending journey id).           */
 /* A journey is a maximal run of equal journey id in sorted order (the       */
 /* paper's "unique journey identifier", Methods, dataset description).        */
-/* Sums are exact-rounded; max speed treats -0.0 as +0.0; the bounding box    */
+/* Sums are exact-rounded; signed zeros count as +0.0; the bounding box       */
 /* covers points whose latitude and longitude are both finite (+inf/-inf when */
 /* there is none); max derived speed is over SPEED_OK points (0.0 if none).   */
 /* Returns the number of journeys J; rows beyond `cap` are not written.      */
@@ -261,10 +265,11 @@ int64_t orc_summary(int64_t n, const int64_t* jid, const int64_t* ts,
                 if ((flags[i] & F_SPEED_OK) && dspeed[i] > maxd) maxd = dspeed[i];
                 if (flags[i] & F_DT_ZERO) ++ndz;
                 if (isfinite(lat[i]) && isfinite(lon[i])) {
-                    if (lat[i] < la0) la0 = lat[i];
-                    if (lat[i] > la1) la1 = lat[i];
-                    if (lon[i] < lo0) lo0 = lon[i];
-                    if (lon[i] > lo1) lo1 = lon[i];
+                    double a = lat[i] + 0.0, o = lon[i] + 0.0;      /* -0.0 as +0.0 */
+                    if (a < la0) la0 = a;
+                    if (a > la1) la1 = a;
+                    if (o < lo0) lo0 = o;
+                    if (o > lo1) lo1 = o;
                 }
             }
             o_jid[J] = jid[k];

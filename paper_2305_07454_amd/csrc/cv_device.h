@@ -1,0 +1,361 @@
+// cv_device.h -- device-side building blocks shared by the gfx950 kernels.
+//
+// * exact fixed-point accumulation of floating-point terms (192-bit two's
+//   complement in three 64-bit limbs) and one round-to-nearest-even
+//   conversion back to double, so every sum is independent of the order in
+//   which tiles, waves or atomics add their terms;
+// * order-preserving integer images of float/double/int64 for integer
+//   atomicMin / atomicMax;
+// * wave64 / block scans and the single-pass decoupled look-back that turns
+//   per-tile counts into exclusive prefixes (Merrill & Garland, 2016).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cv {
+
+typedef uint64_t u64;
+typedef uint32_t u32;
+typedef int64_t i64;
+
+constexpr int WAVE = 64;
+
+// ---------------------------------------------------------------------------
+// 192-bit fixed point.  A finite double v is represented as trunc(v * 2^F):
+// for F = 149 every float32 is exact; for F = 128 every double >= 2^-75 is.
+// ---------------------------------------------------------------------------
+struct Fx192 {
+    u64 w[3];
+};
+
+__device__ __forceinline__ void fx_zero(Fx192& a) { a.w[0] = a.w[1] = a.w[2] = 0; }
+
+__device__ __forceinline__ void fx_add(Fx192& a, const Fx192& b)
+{
+    u64 s0 = a.w[0] + b.w[0];
+    u64 c0 = s0 < a.w[0];
+    u64 s1 = a.w[1] + b.w[1];
+    u64 c1 = s1 < a.w[1];
+    u64 s1c = s1 + c0;
+    c1 += s1c < s1;
+    a.w[0] = s0;
+    a.w[1] = s1c;
+    a.w[2] = a.w[2] + b.w[2] + c1;
+}
+
+__device__ __forceinline__ void fx_neg(Fx192& a)
+{
+    a.w[0] = ~a.w[0];
+    a.w[1] = ~a.w[1];
+    a.w[2] = ~a.w[2];
+    a.w[0] += 1;
+    u64 c = a.w[0] == 0;
+    a.w[1] += c;
+    c = c & (a.w[1] == 0);
+    a.w[2] += c;
+}
+
+template <int F>
+__device__ __forceinline__ Fx192 fx_from_double(double v)
+{
+    Fx192 r;
+    fx_zero(r);
+    u64 bits = (u64)__double_as_longlong(v);
+    int e = (int)((bits >> 52) & 0x7FF);
+    u64 m = bits & ((1ull << 52) - 1);
+    if (e == 0) {
+        if (m == 0) return r;
+        e = 1;
+    } else {
+        m |= 1ull << 52;
+    }
+    int sh = e - 1075 + F;  // v = m * 2^(e-1075); scaled: m * 2^sh
+    if (sh <= -53) return r;
+    if (sh < 0) {
+        r.w[0] = m >> (-sh);
+    } else {
+        int wd = sh >> 6, bt = sh & 63;
+        if (wd < 3) r.w[wd] = m << bt;
+        if (bt != 0 && wd + 1 < 3) r.w[wd + 1] = m >> (64 - bt);
+    }
+    if (bits >> 63) fx_neg(r);
+    return r;
+}
+
+// Round-to-nearest-even of the fixed-point value times 2^-F.
+template <int F>
+__device__ __forceinline__ double fx_to_double(Fx192 a)
+{
+    bool neg = (a.w[2] >> 63) != 0;
+    if (neg) fx_neg(a);
+    int p;
+    if (a.w[2]) p = 128 + 63 - __clzll((long long)a.w[2]);
+    else if (a.w[1]) p = 64 + 63 - __clzll((long long)a.w[1]);
+    else if (a.w[0]) p = 63 - __clzll((long long)a.w[0]);
+    else return 0.0;
+    double r;
+    if (p <= 52) {
+        r = ldexp((double)a.w[0], -F);
+    } else {
+        // mantissa = bits [p-52, p]; round bit p-53; sticky below
+        int lo = p - 52;
+        auto bit_at = [&](int i) -> u64 { return (a.w[i >> 6] >> (i & 63)) & 1ull; };
+        u64 mant;
+        {
+            int wd = lo >> 6, bt = lo & 63;
+            mant = a.w[wd] >> bt;
+            if (bt != 0 && wd + 1 < 3) mant |= a.w[wd + 1] << (64 - bt);
+            mant &= (1ull << 53) - 1;
+        }
+        int rb = lo - 1;
+        u64 round = bit_at(rb);
+        bool sticky = false;
+        if (rb > 0) {
+            int wd = rb >> 6, bt = rb & 63;
+            for (int i = 0; i < wd; ++i) sticky |= a.w[i] != 0;
+            if (bt) sticky |= (a.w[wd] & ((1ull << bt) - 1)) != 0;
+        }
+        if (round && (sticky || (mant & 1))) {
+            mant += 1;
+            if (mant == (1ull << 53)) {
+                mant >>= 1;
+                lo += 1;
+            }
+        }
+        r = ldexp((double)mant, lo - F);
+    }
+    return neg ? -r : r;
+}
+
+// 192-bit add into three global (or LDS) limbs with carries carried by the
+// return values of the atomics: order-independent and exact.
+__device__ __forceinline__ void atomic_add_fx(u64* L, const Fx192& a)
+{
+    u64 c0 = 0;
+    if (a.w[0]) {
+        u64 old0 = atomicAdd((unsigned long long*)&L[0], (unsigned long long)a.w[0]);
+        c0 = (old0 + a.w[0]) < old0;
+    }
+    u64 a1 = a.w[1] + c0;
+    u64 c1 = (a1 < c0) ? 1 : 0;
+    if (a1) {
+        u64 old1 = atomicAdd((unsigned long long*)&L[1], (unsigned long long)a1);
+        c1 += (old1 + a1) < old1;
+    }
+    u64 a2 = a.w[2] + c1;
+    if (a2) atomicAdd((unsigned long long*)&L[2], (unsigned long long)a2);
+}
+
+// Carry-save form for LDS accumulation: four 48-bit chunks held in 64-bit
+// counters; up to 2^16 terms add without overflow, normalised once.
+__device__ __forceinline__ void fx_to_cs(const Fx192& a, u64 c[4])
+{
+    const u64 M = (1ull << 48) - 1;
+    c[0] = a.w[0] & M;
+    c[1] = ((a.w[0] >> 48) | (a.w[1] << 16)) & M;
+    c[2] = ((a.w[1] >> 32) | (a.w[2] << 32)) & M;
+    c[3] = a.w[2] >> 16;
+}
+
+__device__ __forceinline__ Fx192 fx_from_cs(const u64 c[4])
+{
+    // sum_i c[i] * 2^(48 i) mod 2^192
+    Fx192 r, t;
+    fx_zero(r);
+    t.w[0] = c[0];
+    t.w[1] = 0;
+    t.w[2] = 0;
+    fx_add(r, t);
+    t.w[0] = c[1] << 48;
+    t.w[1] = c[1] >> 16;
+    t.w[2] = 0;
+    fx_add(r, t);
+    t.w[0] = 0;
+    t.w[1] = c[2] << 32;
+    t.w[2] = c[2] >> 32;
+    fx_add(r, t);
+    t.w[0] = 0;
+    t.w[1] = 0;
+    t.w[2] = c[3] << 16;
+    fx_add(r, t);
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// order-preserving images
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float canon0f(float v) { return v == 0.0f ? 0.0f : v; }
+__device__ __forceinline__ double canon0d(double v) { return v == 0.0 ? 0.0 : v; }
+
+__device__ __forceinline__ u32 ord_f32(float v)
+{
+    u32 b = __float_as_uint(canon0f(v));
+    return (b >> 31) ? ~b : (b | 0x80000000u);
+}
+__device__ __forceinline__ float unord_f32(u32 u)
+{
+    u32 b = (u >> 31) ? (u & 0x7FFFFFFFu) : ~u;
+    return __uint_as_float(b);
+}
+__device__ __forceinline__ u64 ord_f64(double v)
+{
+    u64 b = (u64)__double_as_longlong(canon0d(v));
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+__device__ __forceinline__ double unord_f64(u64 u)
+{
+    u64 b = (u >> 63) ? (u & 0x7FFFFFFFFFFFFFFFull) : ~u;
+    return __longlong_as_double((long long)b);
+}
+__device__ __forceinline__ u64 ord_i64(i64 v) { return (u64)v ^ 0x8000000000000000ull; }
+__device__ __forceinline__ i64 unord_i64(u64 u) { return (i64)(u ^ 0x8000000000000000ull); }
+
+__device__ __forceinline__ u64 mix64(u64 x)
+{
+    x ^= x >> 30;
+    x *= 0xbf58476d1ce4e5b9ull;
+    x ^= x >> 27;
+    x *= 0x94d049bb133111ebull;
+    x ^= x >> 31;
+    return x;
+}
+
+// ---------------------------------------------------------------------------
+// wave64 helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0)); }
+
+// number of set bits of `mask` in lanes below this lane
+__device__ __forceinline__ u32 popc_below(u64 mask)
+{
+    return __builtin_amdgcn_mbcnt_hi((u32)(mask >> 32), __builtin_amdgcn_mbcnt_lo((u32)mask, 0));
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_inclusive_sum(T v)
+{
+    int l = lane_id();
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        T o = __shfl_up(v, d, WAVE);
+        if (l >= d) v += o;
+    }
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_inclusive_max(T v)
+{
+    int l = lane_id();
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        T o = __shfl_up(v, d, WAVE);
+        if (l >= d) v = v > o ? v : o;
+    }
+    return v;
+}
+
+// Block-wide exclusive sum of one value per thread.  `tmp` holds BLOCK/64
+// entries of LDS.  Contains __syncthreads; call from every thread.
+template <int BLOCK, typename T>
+__device__ __forceinline__ T block_exclusive_sum(T v, T* tmp, T& total)
+{
+    constexpr int NW = BLOCK / WAVE;
+    int w = threadIdx.x / WAVE, l = lane_id();
+    T inc = wave_inclusive_sum(v);
+    if (l == WAVE - 1) tmp[w] = inc;
+    __syncthreads();
+    T base = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+        T x = tmp[i];
+        if (i < w) base += x;
+        tot += x;
+    }
+    total = tot;
+    __syncthreads();
+    return base + inc - v;
+}
+
+// ---------------------------------------------------------------------------
+// Decoupled look-back.  A status word is [flag:2 | value:62]; flag 1 = the
+// tile's own aggregate is published, 2 = its inclusive prefix is.  Tiles are
+// numbered by an atomic ticket taken at block start, so every tile a block
+// waits on has already been scheduled and publishes without waiting itself.
+// ---------------------------------------------------------------------------
+constexpr u64 LB_AGG = 1ull << 62;
+constexpr u64 LB_PRE = 2ull << 62;
+constexpr u64 LB_VAL = (1ull << 62) - 1;
+
+__device__ __forceinline__ void lb_publish(u64* p, u64 v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ u64 lb_peek(u64* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// One thread: publish `agg` for `tile` and return the exclusive prefix.
+__device__ __forceinline__ u64 lookback_exclusive(u64* status, u32 tile, u64 agg)
+{
+    if (tile == 0) {
+        lb_publish(&status[0], LB_PRE | agg);
+        return 0;
+    }
+    lb_publish(&status[tile], LB_AGG | agg);
+    u64 excl = 0;
+    int t = (int)tile - 1;
+    while (t >= 0) {
+        u64 w = lb_peek(&status[t]);
+        u64 f = w & ~LB_VAL;
+        if (f == 0) {
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+        }
+        excl += w & LB_VAL;
+        if (f == LB_PRE) break;
+        --t;
+    }
+    lb_publish(&status[tile], LB_PRE | (excl + agg));
+    return excl;
+}
+
+// Wave-parallel variant: the whole wave (all 64 lanes, uniform control flow)
+// inspects 64 predecessor tiles per step.  Returns the exclusive prefix in
+// every lane.  Lane 0 publishes.
+__device__ __forceinline__ u64 wave_lookback_exclusive(u64* status, u32 tile, u64 agg)
+{
+    int l = lane_id();
+    if (tile == 0) {
+        if (l == 0) lb_publish(&status[0], LB_PRE | agg);
+        return 0;
+    }
+    if (l == 0) lb_publish(&status[tile], LB_AGG | agg);
+    u64 excl = 0;
+    int base = (int)tile - 1;  // lane l looks at tile base - l
+    while (true) {
+        int t = base - l;
+        u64 w = (t >= 0) ? lb_peek(&status[t]) : LB_PRE;  // virtual inclusive 0 before tile 0
+        u64 f = w & ~LB_VAL;
+        // wait until every inspected tile has published something
+        if (__ballot(f == 0) != 0) {
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+        }
+        u64 pre = __ballot(f == LB_PRE);
+        // first lane (nearest tile) holding an inclusive prefix
+        int stop = pre ? __ffsll((long long)pre) - 1 : WAVE;
+        u64 v = (l <= stop && t >= 0) ? (w & LB_VAL) : 0;
+        // wave sum
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, WAVE);
+        excl += v;
+        if (pre) break;
+        base -= WAVE;
+    }
+    if (l == 0) lb_publish(&status[tile], LB_PRE | (excl + agg));
+    return excl;
+}
+
+}  // namespace cv

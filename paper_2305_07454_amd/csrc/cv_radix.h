@@ -1,0 +1,45 @@
+// cv_radix.h -- stable LSD radix sort of (u64 key, u32 value) pairs for gfx950.
+//
+// One up-front histogram pass computes the digit counts of every pass (the
+// multiset of a key digit does not change under permutation).  Each scatter
+// pass then reads a tile of keys once:
+//   1. wave64 multisplit: per key, 8 ballots give the mask of lanes holding the
+//      same 8-bit digit; the rank inside the wave is the popcount of that mask
+//      below the lane plus the wave's running count of the digit (LDS);
+//   2. per-digit exclusive offsets across the block's waves, and the tile's
+//      digit histogram;
+//   3. decoupled look-back over earlier tiles, one thread per digit, gives the
+//      tile's global offset of every digit;
+//   4. keys are staged in LDS in tile-sorted order and written out so that
+//      consecutive threads write consecutive addresses of each digit run.
+// Stability holds because every step orders by (wave, item, lane), which is
+// the input order of the tile.
+#pragma once
+#include "cv_device.h"
+
+namespace cv {
+
+constexpr int RADIX_BITS = 8;
+constexpr int RADIX = 1 << RADIX_BITS;
+constexpr int SORT_BLOCK = 256;
+constexpr int SORT_ITEMS = 16;
+constexpr int SORT_TILE = SORT_BLOCK * SORT_ITEMS;
+constexpr int MAX_PASSES = 8;
+
+// Host launchers (defined in cv_radix.hip).
+//   radix_hist : digit histograms of `passes` passes (limited on device by
+//                ceil(*bits_dev / 8) when bits_dev is given) added into hist.
+//   radix_scan : per-pass exclusive scan hist -> offs.
+//   radix_passes: up to `passes` stable scatter passes, ping-pong k0 -> k1 -> k0
+//                ...; pass p is skipped on device when 8p >= *bits_dev.  vals of
+//                pass 0 come from v_first (nullptr = identity).  After p passes
+//                the data sits in (k1, v1) when p is odd, in (k0, v0) when even.
+void radix_hist(const u64* keys, u32 n_max, const u32* n_dev, int passes, const u32* bits_dev, u32* hist,
+                int grid, hipStream_t s);
+void radix_scan(const u32* hist, u32* offs, int passes, hipStream_t s);
+//                When `timed`, pass p is bracketed as timing family "sort_pass<p>".
+void radix_passes(u64* k0, u64* k1, const u32* v_first, u32* v0, u32* v1, u32 n_max, const u32* n_dev,
+                  const u32* bits_dev, int passes, const u32* offs, u64* status, u32* tickets, hipStream_t s,
+                  bool timed = false);
+
+}  // namespace cv

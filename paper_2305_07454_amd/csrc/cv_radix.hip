@@ -1,0 +1,209 @@
+// cv_radix.hip -- kernels and host launchers of the stable LSD radix sort
+// described in cv_radix.h.
+#include <hip/hip_runtime.h>
+
+#include "cv_host.h"
+#include "cv_radix.h"
+
+namespace cv {
+
+namespace {
+
+// status word: [flag:2 | tag:6 | value:56]; the tag (pass + 1) lets all passes
+// of one sort share one status array cleared once per sort.
+__device__ __forceinline__ u64 rs_word(u64 flag, u32 tag, u64 v) { return (flag << 62) | ((u64)tag << 56) | v; }
+
+// Histogram of all digits of all passes.  hist[p * RADIX + d].
+__global__ void __launch_bounds__(256) k_radix_hist(const u64* __restrict__ keys, u32 n_max,
+                                                    const u32* __restrict__ n_dev, int passes,
+                                                    const u32* __restrict__ bits_dev, u32* __restrict__ hist)
+{
+    __shared__ u32 s_h[MAX_PASSES * RADIX];
+    for (int i = threadIdx.x; i < MAX_PASSES * RADIX; i += blockDim.x) s_h[i] = 0;
+    __syncthreads();
+    u32 n = n_dev ? *n_dev : n_max;
+    int np = passes;
+    if (bits_dev) {
+        int b = (int)*bits_dev;
+        int need = (b + RADIX_BITS - 1) / RADIX_BITS;
+        np = need < np ? need : np;
+    }
+    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        u64 k = keys[i];
+        for (int p = 0; p < np; ++p) atomicAdd(&s_h[p * RADIX + ((k >> (p * RADIX_BITS)) & (RADIX - 1))], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < np * RADIX; i += blockDim.x)
+        if (s_h[i]) atomicAdd(&hist[i], s_h[i]);
+}
+
+// Exclusive scan of each pass's 256 digit counts (one block of 256 threads).
+__global__ void __launch_bounds__(256) k_radix_scan(const u32* __restrict__ hist, u32* __restrict__ offs, int passes)
+{
+    __shared__ u32 tmp[256 / WAVE];
+    for (int p = 0; p < passes; ++p) {
+        u32 total;
+        u32 v = hist[p * RADIX + threadIdx.x];
+        u32 e = block_exclusive_sum<256>(v, tmp, total);
+        offs[p * RADIX + threadIdx.x] = e;
+    }
+}
+
+// One stable scatter pass on digit `pass` (bits [8*pass, 8*pass+8)).
+// vals_in == nullptr means the identity (input index).
+__global__ void __launch_bounds__(SORT_BLOCK, 2)
+k_radix_pass(const u64* __restrict__ keys_in, const u32* __restrict__ vals_in, u64* __restrict__ keys_out,
+             u32* __restrict__ vals_out, u32 n_max, const u32* __restrict__ n_dev, int pass,
+             const u32* __restrict__ bits_dev, const u32* __restrict__ digit_offs, u64* __restrict__ status,
+             u32* __restrict__ ticket)
+{
+    constexpr int NW = SORT_BLOCK / WAVE;
+    __shared__ u32 s_whist[NW][RADIX];
+    __shared__ u32 s_start[RADIX];
+    __shared__ u32 s_gshift[RADIX];
+    __shared__ u64 s_keys[SORT_TILE];
+    __shared__ u32 s_vals[SORT_TILE];
+    __shared__ u32 s_tmp[NW];
+    __shared__ u32 s_tile;
+
+    const int shift = pass * RADIX_BITS;
+    if (bits_dev && shift >= (int)*bits_dev) return;
+    const u32 n = n_dev ? *n_dev : n_max;
+    if (threadIdx.x == 0) s_tile = atomicAdd(ticket, 1u);
+    for (int i = threadIdx.x; i < NW * RADIX; i += SORT_BLOCK) (&s_whist[0][0])[i] = 0;
+    __syncthreads();
+    const u32 tile = s_tile;
+    const u64 tile_base = (u64)tile * SORT_TILE;
+    if (tile_base >= n) return;
+
+    const int w = threadIdx.x / WAVE;
+    const int l = lane_id();
+    u64 key[SORT_ITEMS];
+    u32 val[SORT_ITEMS];
+    u32 rnk[SORT_ITEMS];
+    const u64 wbase = tile_base + (u64)w * (SORT_ITEMS * WAVE);
+#pragma unroll
+    for (int i = 0; i < SORT_ITEMS; ++i) {
+        u64 idx = wbase + (u64)i * WAVE + l;
+        bool ok = idx < n;
+        key[i] = ok ? keys_in[idx] : ~0ull;
+        val[i] = ok ? (vals_in ? vals_in[idx] : (u32)idx) : 0u;
+    }
+#pragma unroll
+    for (int i = 0; i < SORT_ITEMS; ++i) {
+        u64 idx = wbase + (u64)i * WAVE + l;
+        bool ok = idx < n;
+        u32 d = (u32)(key[i] >> shift) & (RADIX - 1);
+        u64 peers = __ballot(ok);
+#pragma unroll
+        for (int b = 0; b < RADIX_BITS; ++b) {
+            bool bit = (d >> b) & 1u;
+            u64 bal = __ballot(bit);
+            peers &= bit ? bal : ~bal;
+        }
+        u32 below = popc_below(peers);
+        u32 cnt = __popcll(peers);
+        u32 before = ok ? s_whist[w][d] : 0u;
+        rnk[i] = before + below;
+        __builtin_amdgcn_wave_barrier();
+        if (ok && below == cnt - 1) s_whist[w][d] = before + cnt;
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+
+    // per digit: exclusive offsets across waves, tile count
+    u32 tcount = 0;
+    if (threadIdx.x < RADIX) {
+        const int d = threadIdx.x;
+#pragma unroll
+        for (int ww = 0; ww < NW; ++ww) {
+            u32 c = s_whist[ww][d];
+            s_whist[ww][d] = tcount;
+            tcount += c;
+        }
+    }
+    u32 total;
+    u32 start = block_exclusive_sum<SORT_BLOCK>(threadIdx.x < RADIX ? tcount : 0u, s_tmp, total);
+    if (threadIdx.x < RADIX) {
+        const int d = threadIdx.x;
+        s_start[d] = start;
+        // look-back for digit d over earlier tiles of this pass
+        const u32 tag = (u32)pass + 1;
+        u64* st = status + (u64)tile * RADIX + d;
+        u64 excl = 0;
+        if (tile == 0) {
+            lb_publish(st, rs_word(2, tag, tcount));
+        } else {
+            lb_publish(st, rs_word(1, tag, tcount));
+            long t = (long)tile - 1;
+            while (t >= 0) {
+                u64 wv = lb_peek(status + (u64)t * RADIX + d);
+                u32 hdr = (u32)(wv >> 56);
+                if ((hdr & 63u) != tag) {
+                    __builtin_amdgcn_s_sleep(1);
+                    continue;
+                }
+                excl += wv & ((1ull << 56) - 1);
+                if ((hdr >> 6) == 2u) break;
+                --t;
+            }
+            lb_publish(st, rs_word(2, tag, excl + tcount));
+        }
+        s_gshift[d] = digit_offs[d] + (u32)excl - start;
+    }
+    __syncthreads();
+
+#pragma unroll
+    for (int i = 0; i < SORT_ITEMS; ++i) {
+        u64 idx = wbase + (u64)i * WAVE + l;
+        if (idx < n) {
+            u32 d = (u32)(key[i] >> shift) & (RADIX - 1);
+            u32 pos = s_start[d] + s_whist[w][d] + rnk[i];
+            s_keys[pos] = key[i];
+            s_vals[pos] = val[i];
+        }
+    }
+    __syncthreads();
+    const u32 tvalid = (u32)((n - tile_base) < (u64)SORT_TILE ? (n - tile_base) : (u64)SORT_TILE);
+    for (u32 j = threadIdx.x; j < tvalid; j += SORT_BLOCK) {
+        u64 k = s_keys[j];
+        u32 d = (u32)(k >> shift) & (RADIX - 1);
+        u32 g = s_gshift[d] + j;
+        keys_out[g] = k;
+        vals_out[g] = s_vals[j];
+    }
+}
+
+
+}  // namespace
+
+void radix_hist(const u64* keys, u32 n_max, const u32* n_dev, int passes, const u32* bits_dev, u32* hist,
+                int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_radix_hist, dim3(grid), dim3(256), 0, s, keys, n_max, n_dev, passes, bits_dev, hist);
+}
+
+void radix_scan(const u32* hist, u32* offs, int passes, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_radix_scan, dim3(1), dim3(256), 0, s, hist, offs, passes);
+}
+
+void radix_passes(u64* k0, u64* k1, const u32* v_first, u32* v0, u32* v1, u32 n_max, const u32* n_dev,
+                  const u32* bits_dev, int passes, const u32* offs, u64* status, u32* tickets, hipStream_t s,
+                  bool timed)
+{
+    static const char* const names[MAX_PASSES] = {"sort_pass0", "sort_pass1", "sort_pass2", "sort_pass3",
+                                                  "sort_pass4", "sort_pass5", "sort_pass6", "sort_pass7"};
+    const u64 tiles = ((u64)n_max + SORT_TILE - 1) / SORT_TILE;
+    for (int p = 0; p < passes; ++p) {
+        const u64* kin = (p & 1) ? k1 : k0;
+        const u32* vin = p == 0 ? v_first : ((p & 1) ? v1 : v0);
+        u64* kout = (p & 1) ? k0 : k1;
+        u32* vout = (p & 1) ? v0 : v1;
+        cvh::TimedScope ts_(timed ? names[p] : nullptr, s);
+        hipLaunchKernelGGL(k_radix_pass, dim3((unsigned)(tiles ? tiles : 1)), dim3(SORT_BLOCK), 0, s, kin, vin, kout,
+                           vout, n_max, n_dev, p, bits_dev, offs + p * RADIX, status, tickets + p);
+    }
+}
+
+}  // namespace cv

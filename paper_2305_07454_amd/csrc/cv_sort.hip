@@ -1,0 +1,402 @@
+// cv_sort.hip -- cv_sort_records: stable order of raw records by
+// (journey id, timestamp), the paper's unique index over all journeys
+// (Methods, step (2)).
+//
+// Pipeline (all stream-ordered, no host synchronisation):
+//   1. k_dict_insert  min/max timestamp; distinct journey ids into an
+//                     open-addressing hash set (run-deduplicated);
+//   2. k_dict_compact distinct ids -> list; radix sort of the list (signed order);
+//   3. k_dict_meta    journey count J, rank bits, time bits, key bits, passes;
+//   4. k_dict_rank    dense order-preserving rank of each distinct id;
+//   5. k_pack_hist    key = rank << t_bits | (ts - t_min) and the digit
+//                     histograms of every radix pass in the same read;
+//   6. radix passes   ceil(key_bits / 8) stable scatter passes (skipped on device);
+//   7. k_gather       perm, journey id from the dictionary, ts from the key,
+//                     lat/lon/speed gathered through perm.
+#include <hip/hip_runtime.h>
+
+#include "cv_device.h"
+#include "cv_host.h"
+#include "cv_radix.h"
+
+using namespace cv;
+
+namespace {
+
+constexpr u64 EMPTY = 0x8000000000000000ull;  // INT64_MIN marks an empty slot
+constexpr u64 SIGN = 0x8000000000000000ull;
+
+struct SortMeta {
+    u64 tmin_ord;
+    u64 tmax_ord;
+    u32 n_distinct;
+    u32 has_min;
+    u32 overflow;
+    u32 J;
+    u32 list_count;
+    u32 dict_n;
+    u32 rank_bits;
+    u32 t_bits;
+    u32 key_bits;
+    u32 passes;
+    u32 range_err;
+    u32 dict_bits;
+    u32 tickets[2 * MAX_PASSES];
+};
+
+__device__ __forceinline__ u32 bit_width64(u64 x) { return x ? 64u - (u32)__clzll((long long)x) : 0u; }
+
+__global__ void k_sort_init(SortMeta* m)
+{
+    if (threadIdx.x == 0) {
+        SortMeta z = {};
+        z.tmin_ord = ~0ull;
+        z.tmax_ord = 0;
+        z.dict_bits = 64;
+        *m = z;
+    }
+}
+
+__device__ __forceinline__ bool dict_insert(u64* table, u64 mask, u64 key, SortMeta* m)
+{
+    u64 h = mix64(key) & mask;
+    for (u64 probe = 0; probe <= mask; ++probe) {
+        u64 cur = table[h];
+        if (cur == key) return true;
+        if (cur == EMPTY) {
+            u64 prev = atomicCAS((unsigned long long*)&table[h], (unsigned long long)EMPTY, (unsigned long long)key);
+            if (prev == EMPTY) {
+                atomicAdd(&m->n_distinct, 1u);
+                return true;
+            }
+            if (prev == key) return true;
+        }
+        h = (h + 1) & mask;
+    }
+    return false;
+}
+
+__device__ __forceinline__ u64 dict_find(const u64* table, u64 mask, u64 key)
+{
+    u64 h = mix64(key) & mask;
+    for (u64 probe = 0; probe <= mask; ++probe) {
+        u64 cur = table[h];
+        if (cur == key) return h;
+        if (cur == EMPTY) return ~0ull;
+        h = (h + 1) & mask;
+    }
+    return ~0ull;
+}
+
+__global__ void __launch_bounds__(256) k_dict_insert(const i64* __restrict__ jid, const i64* __restrict__ ts, u32 n,
+                                                     u64* __restrict__ table, u64 mask, SortMeta* m)
+{
+    __shared__ u64 s_min[4], s_max[4];
+    u64 lo = ~0ull, hi = 0;
+    bool has_min = false, full = false;
+    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        i64 j = jid[i];
+        u64 t = ord_i64(ts[i]);
+        lo = t < lo ? t : lo;
+        hi = t > hi ? t : hi;
+        if (i > 0 && jid[i - 1] == j) continue;
+        if ((u64)j == EMPTY) {
+            has_min = true;
+            continue;
+        }
+        if (!dict_insert(table, mask, (u64)j, m)) full = true;
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        u64 a = __shfl_xor(lo, d, WAVE), b = __shfl_xor(hi, d, WAVE);
+        lo = a < lo ? a : lo;
+        hi = b > hi ? b : hi;
+    }
+    int w = threadIdx.x / WAVE;
+    if (lane_id() == 0) {
+        s_min[w] = lo;
+        s_max[w] = hi;
+    }
+    if (has_min) atomicOr(&m->has_min, 1u);
+    if (full) atomicOr(&m->overflow, 1u);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < (int)(blockDim.x / WAVE); ++k) {
+            lo = s_min[k] < lo ? s_min[k] : lo;
+            hi = s_max[k] > hi ? s_max[k] : hi;
+        }
+        if (lo != ~0ull) atomicMin((unsigned long long*)&m->tmin_ord, (unsigned long long)lo);
+        if (hi != 0) atomicMax((unsigned long long*)&m->tmax_ord, (unsigned long long)hi);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_dict_compact(const u64* __restrict__ table, u64 slots, u32 max_j,
+                                                      SortMeta* m, u64* __restrict__ list)
+{
+    u32 hm = m->has_min;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && hm && max_j > 0) list[0] = EMPTY ^ SIGN;
+    for (u64 s = (u64)blockIdx.x * blockDim.x + threadIdx.x; s < slots; s += (u64)gridDim.x * blockDim.x) {
+        u64 k = table[s];
+        if (k != EMPTY) {
+            u32 pos = atomicAdd(&m->list_count, 1u) + hm;
+            if (pos < max_j) list[pos] = k ^ SIGN;
+        }
+    }
+}
+
+__global__ void k_dict_meta(SortMeta* m, u32 max_j, u32 n)
+{
+    if (threadIdx.x != 0) return;
+    u32 J = m->n_distinct + m->has_min;
+    m->J = J;
+    if (J > max_j) m->overflow = 1;
+    m->dict_n = J < max_j ? J : max_j;
+    u32 rb = J > 1 ? bit_width64((u64)J - 1) : 0;
+    u64 span = n ? (unord_i64(m->tmax_ord) - (u64)unord_i64(m->tmin_ord)) : 0;
+    u32 tb = bit_width64(span);
+    m->rank_bits = rb;
+    m->t_bits = tb;
+    u32 kb = rb + tb;
+    if (kb > 64) {
+        m->range_err = 1;
+        kb = 0;
+    }
+    m->key_bits = kb;
+    m->passes = (kb + RADIX_BITS - 1) / RADIX_BITS;
+}
+
+__global__ void __launch_bounds__(256) k_dict_rank(const u64* __restrict__ sorted_list, const SortMeta* m,
+                                                   const u64* __restrict__ table, u64 mask, u32* __restrict__ ranks)
+{
+    u32 dn = m->dict_n;
+    for (u32 r = blockIdx.x * blockDim.x + threadIdx.x; r < dn; r += gridDim.x * blockDim.x) {
+        u64 k = sorted_list[r] ^ SIGN;
+        if (k == EMPTY) continue;
+        u64 s = dict_find(table, mask, k);
+        if (s != ~0ull) ranks[s] = r;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_pack_hist(const i64* __restrict__ jid, const i64* __restrict__ ts, u32 n,
+                                                   const u64* __restrict__ table, const u32* __restrict__ ranks,
+                                                   u64 mask, const SortMeta* m, u64* __restrict__ keys,
+                                                   u32* __restrict__ hist)
+{
+    __shared__ u32 s_h[MAX_PASSES * RADIX];
+    for (int i = threadIdx.x; i < MAX_PASSES * RADIX; i += blockDim.x) s_h[i] = 0;
+    __syncthreads();
+    const u32 tb = m->t_bits;
+    const u32 np = m->passes;
+    const bool bad = m->range_err != 0;
+    const u64 tmin = (u64)unord_i64(m->tmin_ord);
+    u64 prev_j = EMPTY;
+    u32 prev_r = 0;
+    bool have_prev = false;
+    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        u64 j = (u64)jid[i];
+        u32 r = 0;
+        if (have_prev && j == prev_j) {
+            r = prev_r;
+        } else if (j != EMPTY) {
+            u64 s = dict_find(table, mask, j);
+            r = (s != ~0ull) ? ranks[s] : 0u;
+        }
+        prev_j = j;
+        prev_r = r;
+        have_prev = true;
+        u64 key = 0;
+        if (!bad) key = (tb >= 64 ? 0ull : ((u64)r << tb)) | ((u64)ts[i] - tmin);
+        keys[i] = key;
+        for (u32 p = 0; p < np; ++p) atomicAdd(&s_h[p * RADIX + ((key >> (p * RADIX_BITS)) & (RADIX - 1))], 1u);
+    }
+    __syncthreads();
+    for (u32 i = threadIdx.x; i < np * RADIX; i += blockDim.x)
+        if (s_h[i]) atomicAdd(&hist[i], s_h[i]);
+}
+
+__global__ void __launch_bounds__(256) k_gather(u32 n, const SortMeta* m, const u64* __restrict__ K0,
+                                                const u64* __restrict__ K1, const u32* __restrict__ V0,
+                                                const u32* __restrict__ V1, const u64* __restrict__ dict_sorted,
+                                                const i64* __restrict__ jid, const i64* __restrict__ ts,
+                                                const double* __restrict__ lat, const double* __restrict__ lon,
+                                                const float* __restrict__ spd, u32* __restrict__ perm,
+                                                i64* __restrict__ o_jid, i64* __restrict__ o_ts,
+                                                double* __restrict__ o_lat, double* __restrict__ o_lon,
+                                                float* __restrict__ o_spd)
+{
+    const u32 np = m->passes;
+    const u32 tb = m->t_bits;
+    const u32 dn = m->dict_n;
+    const bool exact = (m->range_err == 0) && (m->overflow == 0);
+    const u64 tmin = (u64)unord_i64(m->tmin_ord);
+    const u64 tmask = tb >= 64 ? ~0ull : ((1ull << tb) - 1);
+    const u64* K = np == 0 ? K0 : ((np & 1) ? K1 : K0);
+    const u32* V = (np & 1) ? V1 : V0;
+    for (u32 k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+        u64 key = K[k];
+        u32 v = np == 0 ? k : V[k];
+        perm[k] = v;
+        if (o_jid) {
+            u64 r = tb >= 64 ? 0 : (key >> tb);
+            o_jid[k] = (exact && r < dn) ? (i64)(dict_sorted[r] ^ SIGN) : jid[v];
+        }
+        if (o_ts) o_ts[k] = exact ? (i64)(tmin + (key & tmask)) : ts[v];
+        if (o_lat) o_lat[k] = lat[v];
+        if (o_lon) o_lon[k] = lon[v];
+        if (o_spd) o_spd[k] = spd[v];
+    }
+}
+
+__global__ void k_sort_finish(const SortMeta* m, cv_result* res)
+{
+    if (threadIdx.x != 0) return;
+    cv_result r = {};
+    r.status = m->range_err ? CV_ERR_RANGE : (m->overflow ? CV_ERR_CAPACITY : CV_OK);
+    r.count = m->J;
+    r.required = m->overflow ? m->J : 0;
+    r.key_bits = m->key_bits;
+    *res = r;
+}
+
+__global__ void k_empty_result(cv_result* res)
+{
+    if (threadIdx.x == 0) {
+        cv_result r = {};
+        *res = r;
+    }
+}
+
+struct SortLayout {
+    SortMeta* meta;
+    u64* table;
+    u32* ranks;
+    u64* dl0;
+    u64* dl1;
+    u32* dv0;
+    u32* dv1;
+    u32* zero_begin;  // start of the region cleared to zero
+    u32* hist;
+    u32* dhist;
+    u64* status;
+    u64* dstatus;
+    size_t zero_bytes;
+    u32* offs;
+    u32* doffs;
+    u64* K0;
+    u64* K1;
+    u32* V0;
+    u32* V1;
+    u64 slots;
+    u64 tiles, dtiles;
+    size_t bytes;
+
+    SortLayout(void* ws, u64 n, u64 max_j)
+    {
+        cvh::Carver c(ws);
+        slots = cvh::next_pow2(2 * max_j < 1024 ? 1024 : 2 * max_j);
+        tiles = (n + SORT_TILE - 1) / SORT_TILE;
+        dtiles = (max_j + SORT_TILE - 1) / SORT_TILE;
+        meta = c.take<SortMeta>(1);
+        table = c.take<u64>(slots);
+        ranks = c.take<u32>(slots);
+        dl0 = c.take<u64>(max_j);
+        dl1 = c.take<u64>(max_j);
+        dv0 = c.take<u32>(max_j);
+        dv1 = c.take<u32>(max_j);
+        size_t z0 = cvh::align_up(c.off);
+        hist = c.take<u32>(MAX_PASSES * RADIX);
+        dhist = c.take<u32>(MAX_PASSES * RADIX);
+        status = c.take<u64>(tiles * RADIX + 1);
+        dstatus = c.take<u64>(dtiles * RADIX + 1);
+        size_t z1 = cvh::align_up(c.off);
+        zero_begin = (u32*)(c.base ? c.base + z0 : nullptr);
+        zero_bytes = z1 - z0;
+        offs = c.take<u32>(MAX_PASSES * RADIX);
+        doffs = c.take<u32>(MAX_PASSES * RADIX);
+        K0 = c.take<u64>(n);
+        K1 = c.take<u64>(n);
+        V0 = c.take<u32>(n);
+        V1 = c.take<u32>(n);
+        bytes = c.size();
+    }
+};
+
+bool valid_ptr8(const void* p) { return p == nullptr || cvh::aligned(p, 8); }
+
+}  // namespace
+
+extern "C" {
+
+cv_status cv_sort_workspace_size(uint64_t n, uint64_t max_journeys, size_t* bytes)
+{
+    if (!bytes || n >= (1ull << 32) || max_journeys >= (1ull << 31)) return CV_ERR_INVALID_ARGUMENT;
+    if (max_journeys == 0) max_journeys = 1;
+    SortLayout L(nullptr, n, max_journeys);
+    *bytes = L.bytes;
+    return CV_OK;
+}
+
+cv_status cv_sort_records(const cv_records* in, uint64_t max_journeys, uint32_t* perm, const cv_records_out* sorted,
+                          cv_result* res, void* ws, size_t ws_bytes, void* stream)
+{
+    if (!in || in->n >= (1ull << 32) || max_journeys >= (1ull << 31)) return CV_ERR_INVALID_ARGUMENT;
+    const u64 n = in->n;
+    if (max_journeys == 0) max_journeys = 1;
+    hipStream_t s = (hipStream_t)stream;
+    cv_records_out so = {};
+    if (sorted) so = *sorted;
+    if (n > 0) {
+        if (!in->journey_id || !in->ts_ms || !perm) return CV_ERR_INVALID_ARGUMENT;
+        if ((so.lat_deg && !in->lat_deg) || (so.lon_deg && !in->lon_deg) || (so.speed_mps && !in->speed_mps))
+            return CV_ERR_INVALID_ARGUMENT;
+        if (!valid_ptr8(in->journey_id) || !valid_ptr8(in->ts_ms) || !valid_ptr8(in->lat_deg) ||
+            !valid_ptr8(in->lon_deg) || !valid_ptr8(so.journey_id) || !valid_ptr8(so.ts_ms) ||
+            !valid_ptr8(so.lat_deg) || !valid_ptr8(so.lon_deg) || !cvh::aligned(perm, 4))
+            return CV_ERR_INVALID_ARGUMENT;
+    }
+    SortLayout need(nullptr, n, max_journeys);
+    if (!ws || !cvh::aligned(ws, cvh::WS_ALIGN) || ws_bytes < need.bytes) return CV_ERR_WORKSPACE;
+    if (n == 0) {
+        if (res) hipLaunchKernelGGL(k_empty_result, dim3(1), dim3(64), 0, s, res);
+        return cvh::last_launch_status();
+    }
+    SortLayout L(ws, n, max_journeys);
+    const u32 nn = (u32)n;
+    const u32 mj = (u32)max_journeys;
+    const u64 mask = L.slots - 1;
+    const int gs = cvh::grid_for(n, 256, 2048);
+    {
+        cvh::TimedScope ts_("sort_prep", s);
+        hipLaunchKernelGGL(k_sort_init, dim3(1), dim3(64), 0, s, L.meta);
+        cvh::fill_u64(L.table, EMPTY, L.slots, s);
+        cvh::fill_u32(L.zero_begin, 0u, L.zero_bytes / 4, s);
+        hipLaunchKernelGGL(k_dict_insert, dim3(gs), dim3(256), 0, s, in->journey_id, in->ts_ms, nn, L.table, mask,
+                           L.meta);
+        hipLaunchKernelGGL(k_dict_compact, dim3(cvh::grid_for(L.slots, 256, 2048)), dim3(256), 0, s, L.table,
+                           L.slots, mj, L.meta, L.dl0);
+        hipLaunchKernelGGL(k_dict_meta, dim3(1), dim3(64), 0, s, L.meta, mj, nn);
+        // sort the distinct ids (64-bit, signed order via the flipped sign bit)
+        const u32* dn = &L.meta->dict_n;
+        radix_hist(L.dl0, mj, dn, MAX_PASSES, nullptr, L.dhist, cvh::grid_for(max_journeys, 256, 512), s);
+        radix_scan(L.dhist, L.doffs, MAX_PASSES, s);
+        radix_passes(L.dl0, L.dl1, nullptr, L.dv0, L.dv1, mj, dn, nullptr, MAX_PASSES, L.doffs, L.dstatus,
+                     L.meta->tickets + MAX_PASSES, s);
+        hipLaunchKernelGGL(k_dict_rank, dim3(cvh::grid_for(max_journeys, 256, 1024)), dim3(256), 0, s, L.dl0, L.meta,
+                           L.table, mask, L.ranks);
+        hipLaunchKernelGGL(k_pack_hist, dim3(gs), dim3(256), 0, s, in->journey_id, in->ts_ms, nn, L.table, L.ranks,
+                           mask, L.meta, L.K0, L.hist);
+        radix_scan(L.hist, L.offs, MAX_PASSES, s);
+    }
+    radix_passes(L.K0, L.K1, nullptr, L.V0, L.V1, nn, nullptr, &L.meta->key_bits, MAX_PASSES, L.offs, L.status,
+                 L.meta->tickets, s, /*timed=*/true);
+    {
+        cvh::TimedScope ts_("gather", s);
+        hipLaunchKernelGGL(k_gather, dim3(cvh::grid_for(n, 256, 8192)), dim3(256), 0, s, nn, L.meta, L.K0, L.K1, L.V0,
+                           L.V1, L.dl0, in->journey_id, in->ts_ms, in->lat_deg, in->lon_deg, in->speed_mps, perm,
+                           so.journey_id, so.ts_ms, so.lat_deg, so.lon_deg, so.speed_mps);
+    }
+    if (res) hipLaunchKernelGGL(k_sort_finish, dim3(1), dim3(64), 0, s, L.meta, res);
+    return cvh::last_launch_status();
+}
+
+}  // extern "C"

@@ -1,0 +1,360 @@
+"""Thin ctypes binding of ``libcvetl.so`` (the gfx950 HIP library).
+
+Argument marshalling only: every step of the ETL path runs in the library's
+HIP kernels.  PyTorch supplies device memory (tensors) and the stream
+(``torch.cuda.current_stream()``).  The functions carry the C-ABI names:
+
+* ``cv_sort_records(records, ...)      -> (perm, sorted_records, result)``
+* ``cv_journey_features(sorted)        -> features``
+* ``cv_journey_summary(sorted, feat)   -> (journeys, result)``
+* ``cv_grid_aggregate(sorted, grid)    -> (groups, result)``
+
+A record batch is a dict of device tensors with the keys of ``RECORD_FIELDS``.
+There is no CPU fallback: loading fails loudly when the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libcvetl.so")
+
+RECORD_FIELDS = (("journey_id", torch.int64), ("ts_ms", torch.int64), ("lat_deg", torch.float64),
+                 ("lon_deg", torch.float64), ("speed_mps", torch.float32))
+FEATURE_FIELDS = (("step_m", torch.float64), ("dt_s", torch.float64), ("speed_mps", torch.float64),
+                  ("accel_mps2", torch.float64), ("bearing_deg", torch.float64),
+                  ("dheading_deg", torch.float64), ("flags", torch.uint8))
+JOURNEY_FIELDS = (("journey_id", torch.int64), ("first", torch.int32), ("n_points", torch.int32),
+                  ("t_start_ms", torch.int64), ("t_end_ms", torch.int64), ("distance_m", torch.float64),
+                  ("sum_speed", torch.float64), ("max_speed", torch.float32),
+                  ("max_derived_speed", torch.float64), ("n_dt_zero", torch.int32),
+                  ("lat_min", torch.float64), ("lat_max", torch.float64), ("lon_min", torch.float64),
+                  ("lon_max", torch.float64))
+GROUP_FIELDS = (("key", torch.int64), ("count", torch.int32), ("n_journeys", torch.int32),
+                ("sum_speed", torch.float64), ("min_speed", torch.float32), ("max_speed", torch.float32))
+
+CV_OK, CV_ERR_INVALID_ARGUMENT, CV_ERR_WORKSPACE, CV_ERR_CAPACITY = 0, 1, 2, 3
+CV_ERR_RANGE, CV_ERR_DEVICE, CV_ERR_UNSUPPORTED = 4, 5, 6
+
+FLAG_FIRST, FLAG_DT_ZERO, FLAG_SPEED_OK, FLAG_ACCEL_OK = 0x01, 0x02, 0x04, 0x08
+FLAG_BEARING_OK, FLAG_DHEAD_OK, FLAG_BAD_COORD = 0x10, 0x20, 0x40
+
+P = ctypes.c_void_p
+
+
+class CvRecords(ctypes.Structure):
+    _fields_ = [("journey_id", P), ("ts_ms", P), ("lat_deg", P), ("lon_deg", P), ("speed_mps", P),
+                ("n", ctypes.c_uint64)]
+
+
+class CvRecordsOut(ctypes.Structure):
+    _fields_ = [("journey_id", P), ("ts_ms", P), ("lat_deg", P), ("lon_deg", P), ("speed_mps", P)]
+
+
+class CvFeatures(ctypes.Structure):
+    _fields_ = [(k, P) for k, _ in FEATURE_FIELDS]
+
+
+class CvJourneys(ctypes.Structure):
+    _fields_ = [(k, P) for k, _ in JOURNEY_FIELDS]
+
+
+class CvGridSpec(ctypes.Structure):
+    _fields_ = [("lat0_deg", ctypes.c_double), ("lon0_deg", ctypes.c_double), ("dlat_deg", ctypes.c_double),
+                ("dlon_deg", ctypes.c_double), ("n_lat", ctypes.c_int64), ("n_lon", ctypes.c_int64),
+                ("t0_ms", ctypes.c_int64), ("bin_ms", ctypes.c_int64), ("n_t", ctypes.c_int64)]
+
+
+class CvGroups(ctypes.Structure):
+    _fields_ = [(k, P) for k, _ in GROUP_FIELDS]
+
+
+RESULT_DTYPE = np.dtype([("status", "<u4"), ("flags", "<u4"), ("count", "<u8"), ("required", "<u8"),
+                         ("n_out_of_grid", "<u8"), ("n_late", "<u8"), ("key_bits", "<u8"),
+                         ("reserved", "<u8", (2,))])
+assert RESULT_DTYPE.itemsize == 64
+
+
+class CvError(RuntimeError):
+    def __init__(self, status, where=""):
+        self.status = int(status)
+        super().__init__(f"{where}: {strerror(status)} (status {status})")
+
+
+_lib = None
+
+
+def lib():
+    """Load libcvetl.so; raises if it has not been built (no fallback path)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2305_07454_amd/build.py "
+                              "(hipcc --offload-arch=gfx950); there is no CPU fallback")
+        L = ctypes.CDLL(LIB_PATH)
+        S = ctypes.c_int
+        U64 = ctypes.c_uint64
+        SZ = ctypes.POINTER(ctypes.c_size_t)
+        L.cv_abi_version.restype = ctypes.c_uint32
+        L.cv_strerror.argtypes = [S]
+        L.cv_strerror.restype = ctypes.c_char_p
+        L.cv_sort_workspace_size.argtypes = [U64, U64, SZ]
+        L.cv_sort_workspace_size.restype = S
+        L.cv_sort_records.argtypes = [ctypes.POINTER(CvRecords), U64, P, ctypes.POINTER(CvRecordsOut), P, P,
+                                      ctypes.c_size_t, P]
+        L.cv_sort_records.restype = S
+        L.cv_journey_features.argtypes = [ctypes.POINTER(CvRecords), ctypes.POINTER(CvFeatures), P]
+        L.cv_journey_features.restype = S
+        L.cv_summary_workspace_size.argtypes = [U64, U64, SZ]
+        L.cv_summary_workspace_size.restype = S
+        L.cv_journey_summary.argtypes = [ctypes.POINTER(CvRecords), ctypes.POINTER(CvFeatures),
+                                         ctypes.POINTER(CvJourneys), U64, P, P, ctypes.c_size_t, P]
+        L.cv_journey_summary.restype = S
+        L.cv_grid_workspace_size.argtypes = [U64, ctypes.POINTER(CvGridSpec), U64, SZ]
+        L.cv_grid_workspace_size.restype = S
+        L.cv_grid_aggregate.argtypes = [ctypes.POINTER(CvRecords), ctypes.POINTER(CvGridSpec),
+                                        ctypes.POINTER(CvGroups), U64, P, P, ctypes.c_size_t, P]
+        L.cv_grid_aggregate.restype = S
+        L.cv_timing_enable.argtypes = [S]
+        L.cv_timing_enable.restype = S
+        L.cv_timing_reset.restype = S
+        L.cv_timing_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(U64)]
+        L.cv_timing_read.restype = S
+        _lib = L
+    return _lib
+
+
+def strerror(status) -> str:
+    return lib().cv_strerror(int(status)).decode()
+
+
+def _check(status, where):
+    if status != CV_OK:
+        raise CvError(status, where)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _records_struct(rec) -> CvRecords:
+    n = int(rec["journey_id"].numel())
+    return CvRecords(*(_ptr(rec.get(k)) for k, _ in RECORD_FIELDS), n)
+
+
+def _spec_struct(grid) -> CvGridSpec:
+    return CvGridSpec(float(grid.lat0_deg), float(grid.lon0_deg), float(grid.dlat_deg), float(grid.dlon_deg),
+                      int(grid.n_lat), int(grid.n_lon), int(grid.t0_ms), int(grid.bin_ms), int(grid.n_t))
+
+
+def _size(fn, *args) -> int:
+    out = ctypes.c_size_t(0)
+    _check(fn(*args, ctypes.byref(out)), fn.__name__)
+    return int(out.value)
+
+
+def new_result(device="cuda"):
+    return torch.zeros(64, dtype=torch.uint8, device=device)
+
+
+def read_result(res) -> dict:
+    a = np.frombuffer(res.cpu().numpy().tobytes(), dtype=RESULT_DTYPE)[0]
+    return {k: int(a[k]) for k in ("status", "count", "required", "n_out_of_grid", "n_late", "key_bits")}
+
+
+def workspace(nbytes, device="cuda"):
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def to_device(records, device="cuda"):
+    """Host numpy columns (gen.Records or a 5-tuple) -> dict of device tensors."""
+    cols = records.columns() if hasattr(records, "columns") else records
+    return {k: torch.from_numpy(np.ascontiguousarray(c)).to(device) for (k, _), c in zip(RECORD_FIELDS, cols)}
+
+
+def empty_records(n, device="cuda"):
+    return {k: torch.empty(n, dtype=dt, device=device) for k, dt in RECORD_FIELDS}
+
+
+# ---------------------------------------------------------------------------
+# the four calls
+# ---------------------------------------------------------------------------
+
+def cv_sort_records(rec, max_journeys=None, want_sorted=True, ws=None, stream=None, sync=True):
+    """Stable (journey_id, ts_ms) order.  Returns (perm[int32], sorted dict, result dict|None)."""
+    L = lib()
+    n = int(rec["journey_id"].numel())
+    dev = rec["journey_id"].device
+    mj = int(max_journeys) if max_journeys else max(1, min(n, 1 << 20))
+    perm = torch.empty(n, dtype=torch.int32, device=dev)
+    out = empty_records(n, dev) if want_sorted else None
+    so = CvRecordsOut(*(_ptr(out[k]) for k, _ in RECORD_FIELDS)) if want_sorted else CvRecordsOut()
+    need = _size(L.cv_sort_workspace_size, n, mj)
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, dev)
+    res = new_result(dev)
+    st = L.cv_sort_records(ctypes.byref(_records_struct(rec)), mj, _ptr(perm), ctypes.byref(so), _ptr(res),
+                           _ptr(ws), ws.numel(), _stream(stream))
+    _check(st, "cv_sort_records")
+    if not sync:
+        return perm, out, res
+    r = read_result(res)
+    if r["status"] == CV_ERR_CAPACITY and max_journeys is None:
+        return cv_sort_records(rec, max_journeys=max(2 * mj, r["required"]), want_sorted=want_sorted,
+                               stream=stream)
+    _check(r["status"], "cv_sort_records (device)")
+    return perm, out, r
+
+
+def cv_journey_features(sorted_rec, stream=None):
+    L = lib()
+    n = int(sorted_rec["journey_id"].numel())
+    dev = sorted_rec["journey_id"].device
+    feat = {k: torch.empty(n, dtype=dt, device=dev) for k, dt in FEATURE_FIELDS}
+    fs = CvFeatures(*(_ptr(feat[k]) for k, _ in FEATURE_FIELDS))
+    _check(L.cv_journey_features(ctypes.byref(_records_struct(sorted_rec)), ctypes.byref(fs), _stream(stream)),
+           "cv_journey_features")
+    return feat
+
+
+def _feat_struct(feat):
+    return CvFeatures(*(_ptr(feat.get(k)) for k, _ in FEATURE_FIELDS))
+
+
+def cv_journey_summary(sorted_rec, feat, capacity=None, stream=None, sync=True, ws=None, out=None):
+    L = lib()
+    n = int(sorted_rec["journey_id"].numel())
+    dev = sorted_rec["journey_id"].device
+    cap = int(capacity) if capacity is not None else max(1, min(n, 1 << 20))
+    if out is None:
+        out = {k: torch.empty(cap, dtype=dt, device=dev) for k, dt in JOURNEY_FIELDS}
+    js = CvJourneys(*(_ptr(out[k]) for k, _ in JOURNEY_FIELDS))
+    need = _size(L.cv_summary_workspace_size, n, cap)
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, dev)
+    res = new_result(dev)
+    st = L.cv_journey_summary(ctypes.byref(_records_struct(sorted_rec)), ctypes.byref(_feat_struct(feat)),
+                              ctypes.byref(js), cap, _ptr(res), _ptr(ws), ws.numel(), _stream(stream))
+    _check(st, "cv_journey_summary")
+    if not sync:
+        return out, res
+    r = read_result(res)
+    if r["status"] == CV_ERR_CAPACITY and capacity is None:
+        return cv_journey_summary(sorted_rec, feat, capacity=r["required"], stream=stream)
+    _check(r["status"], "cv_journey_summary (device)")
+    J = r["count"]
+    return {k: v[:J] for k, v in out.items()}, r
+
+
+def cv_grid_aggregate(sorted_rec, grid, capacity=None, stream=None, sync=True, ws=None, out=None):
+    L = lib()
+    n = int(sorted_rec["journey_id"].numel())
+    dev = sorted_rec["journey_id"].device
+    cap = int(capacity) if capacity is not None else max(1, min(n, 1 << 22))
+    spec = _spec_struct(grid)
+    if out is None:
+        out = {k: torch.empty(cap, dtype=dt, device=dev) for k, dt in GROUP_FIELDS}
+    gs = CvGroups(*(_ptr(out[k]) for k, _ in GROUP_FIELDS))
+    need = _size(L.cv_grid_workspace_size, n, ctypes.byref(spec), cap)
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, dev)
+    res = new_result(dev)
+    st = L.cv_grid_aggregate(ctypes.byref(_records_struct(sorted_rec)), ctypes.byref(spec), ctypes.byref(gs), cap,
+                             _ptr(res), _ptr(ws), ws.numel(), _stream(stream))
+    _check(st, "cv_grid_aggregate")
+    if not sync:
+        return out, res
+    r = read_result(res)
+    if r["status"] == CV_ERR_CAPACITY and capacity is None:
+        return cv_grid_aggregate(sorted_rec, grid, capacity=r["required"], stream=stream)
+    _check(r["status"], "cv_grid_aggregate (device)")
+    G = r["count"]
+    return {k: v[:G] for k, v in out.items()}, r
+
+
+# ---------------------------------------------------------------------------
+# timing
+# ---------------------------------------------------------------------------
+
+def cv_timing_enable(on=True):
+    _check(lib().cv_timing_enable(1 if on else 0), "cv_timing_enable")
+
+
+def cv_timing_reset():
+    _check(lib().cv_timing_reset(), "cv_timing_reset")
+
+
+def cv_timing_read(family):
+    ms = ctypes.c_double(0)
+    cnt = ctypes.c_uint64(0)
+    _check(lib().cv_timing_read(family.encode(), ctypes.byref(ms), ctypes.byref(cnt)), "cv_timing_read")
+    return float(ms.value), int(cnt.value)
+
+
+def run_plain(rec, grid, max_journeys=None, journey_capacity=None, group_capacity=None, stream=None):
+    """The whole plain path on one device batch: order, features, summary, grid."""
+    perm, srt, _ = cv_sort_records(rec, max_journeys=max_journeys, stream=stream)
+    feat = cv_journey_features(srt, stream=stream)
+    summ, rs = cv_journey_summary(srt, feat, capacity=journey_capacity, stream=stream)
+    groups, rg = cv_grid_aggregate(srt, grid, capacity=group_capacity, stream=stream)
+    return dict(perm=perm, sorted=srt, features=feat, summary=summ, groups=groups, n_out=rg["n_out_of_grid"],
+                summary_result=rs, grid_result=rg)
+
+
+class Pipeline:
+    """Preallocated buffers for repeated runs of the plain path on batches of
+    at most `n` records: no allocation and no host synchronisation inside
+    `run()`, which only enqueues the four calls on the stream."""
+
+    def __init__(self, n, grid, max_journeys, journey_capacity, group_capacity, device="cuda"):
+        L = lib()
+        self.n, self.grid, self.device = int(n), grid, device
+        self.max_journeys = int(max_journeys)
+        self.jcap, self.gcap = int(journey_capacity), int(group_capacity)
+        self.perm = torch.empty(self.n, dtype=torch.int32, device=device)
+        self.sorted = empty_records(self.n, device)
+        self.feat = {k: torch.empty(self.n, dtype=dt, device=device) for k, dt in FEATURE_FIELDS}
+        self.journeys = {k: torch.empty(self.jcap, dtype=dt, device=device) for k, dt in JOURNEY_FIELDS}
+        self.groups = {k: torch.empty(self.gcap, dtype=dt, device=device) for k, dt in GROUP_FIELDS}
+        self.spec = _spec_struct(grid)
+        self.ws_sort = workspace(_size(L.cv_sort_workspace_size, self.n, self.max_journeys), device)
+        self.ws_sum = workspace(_size(L.cv_summary_workspace_size, self.n, self.jcap), device)
+        self.ws_grid = workspace(_size(L.cv_grid_workspace_size, self.n, ctypes.byref(self.spec), self.gcap), device)
+        self.res = [new_result(device) for _ in range(3)]
+        self._so = CvRecordsOut(*(_ptr(self.sorted[k]) for k, _ in RECORD_FIELDS))
+        self._fs = CvFeatures(*(_ptr(self.feat[k]) for k, _ in FEATURE_FIELDS))
+        self._js = CvJourneys(*(_ptr(self.journeys[k]) for k, _ in JOURNEY_FIELDS))
+        self._gs = CvGroups(*(_ptr(self.groups[k]) for k, _ in GROUP_FIELDS))
+
+    def workspace_bytes(self):
+        return sum(w.numel() for w in (self.ws_sort, self.ws_sum, self.ws_grid))
+
+    def run(self, rec, stream=None):
+        L = lib()
+        n = int(rec["journey_id"].numel())
+        assert n <= self.n
+        s = _stream(stream)
+        inp = _records_struct(rec)
+        _check(L.cv_sort_records(ctypes.byref(inp), self.max_journeys, _ptr(self.perm), ctypes.byref(self._so),
+                                 _ptr(self.res[0]), _ptr(self.ws_sort), self.ws_sort.numel(), s), "cv_sort_records")
+        srt = CvRecords(*(_ptr(self.sorted[k]) for k, _ in RECORD_FIELDS), n)
+        _check(L.cv_journey_features(ctypes.byref(srt), ctypes.byref(self._fs), s), "cv_journey_features")
+        _check(L.cv_journey_summary(ctypes.byref(srt), ctypes.byref(self._fs), ctypes.byref(self._js), self.jcap,
+                                    _ptr(self.res[1]), _ptr(self.ws_sum), self.ws_sum.numel(), s),
+               "cv_journey_summary")
+        _check(L.cv_grid_aggregate(ctypes.byref(srt), ctypes.byref(self.spec), ctypes.byref(self._gs), self.gcap,
+                                   _ptr(self.res[2]), _ptr(self.ws_grid), self.ws_grid.numel(), s),
+               "cv_grid_aggregate")
+
+    def results(self):
+        """Read the three device result words (synchronises)."""
+        return [read_result(r) for r in self.res]

@@ -1,0 +1,90 @@
+"""The C-ABI library loads, exports every symbol the header declares, and
+rejects bad arguments on the host before touching a GPU (no compute calls)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cvetl.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cv_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2305_07454_amd import cvetl
+    if not os.path.exists(cvetl.LIB_PATH):
+        from paper_2305_07454_amd import build
+        build.build()
+    return cvetl.lib()
+
+
+def test_header_symbols_exported(L):
+    names = _declared()
+    assert len(names) >= 12
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_abi_version_and_strerror(L):
+    assert L.cv_abi_version() == 1
+    from paper_2305_07454_amd import cvetl
+    assert cvetl.strerror(cvetl.CV_ERR_CAPACITY) == "output capacity exceeded"
+    assert "unknown" in cvetl.strerror(99)
+
+
+def test_workspace_queries_host_only(L):
+    from paper_2305_07454_amd import cvetl, gen
+    sz = ctypes.c_size_t()
+    assert L.cv_sort_workspace_size(1000, 10, ctypes.byref(sz)) == 0 and sz.value > 0
+    small = sz.value
+    assert L.cv_sort_workspace_size(10_000_000, 10, ctypes.byref(sz)) == 0 and sz.value > small
+    assert L.cv_sort_workspace_size(1 << 32, 10, ctypes.byref(sz)) == cvetl.CV_ERR_INVALID_ARGUMENT
+    assert L.cv_summary_workspace_size(1000, 100, ctypes.byref(sz)) == 0
+    spec = cvetl._spec_struct(gen.GRIDS["c1"])
+    assert L.cv_grid_workspace_size(1000, ctypes.byref(spec), 100, ctypes.byref(sz)) == 0
+    bad = cvetl._spec_struct(gen.GRIDS["c1"])
+    bad.dlat_deg = 0.0
+    assert L.cv_grid_workspace_size(1000, ctypes.byref(bad), 100, ctypes.byref(sz)) == cvetl.CV_ERR_INVALID_ARGUMENT
+    bad = cvetl._spec_struct(gen.GRIDS["c1"])
+    bad.bin_ms = 0
+    assert L.cv_grid_workspace_size(1000, ctypes.byref(bad), 100, ctypes.byref(sz)) == cvetl.CV_ERR_INVALID_ARGUMENT
+    bad = cvetl._spec_struct(gen.GRIDS["c1"])
+    bad.n_t = 1 << 40
+    bad.n_lat = 1 << 20
+    assert L.cv_grid_workspace_size(1000, ctypes.byref(bad), 100, ctypes.byref(sz)) == cvetl.CV_ERR_INVALID_ARGUMENT
+
+
+def test_argument_errors_before_any_launch(L):
+    from paper_2305_07454_amd import cvetl
+    rec = cvetl.CvRecords(None, None, None, None, None, 10)
+    assert L.cv_journey_features(ctypes.byref(rec), ctypes.byref(cvetl.CvFeatures()), None) == \
+        cvetl.CV_ERR_INVALID_ARGUMENT
+    assert L.cv_journey_features(None, None, None) == cvetl.CV_ERR_INVALID_ARGUMENT
+    # missing workspace is reported before anything is enqueued
+    assert L.cv_sort_records(ctypes.byref(rec), 10, None, None, None, None, 0, None) == \
+        cvetl.CV_ERR_INVALID_ARGUMENT
+    big = cvetl.CvRecords(None, None, None, None, None, 1 << 32)
+    assert L.cv_sort_records(ctypes.byref(big), 10, None, None, None, None, 0, None) == \
+        cvetl.CV_ERR_INVALID_ARGUMENT
+    ok = cvetl.CvRecords(8, 8, 8, 8, 8, 10)   # non-null dummies; fails on the workspace check first
+    assert L.cv_sort_records(ctypes.byref(ok), 10, ctypes.c_void_p(8), None, None, None, 0, None) == \
+        cvetl.CV_ERR_WORKSPACE
+    assert L.cv_journey_summary(ctypes.byref(ok), ctypes.byref(cvetl.CvFeatures()),
+                                ctypes.byref(cvetl.CvJourneys()), 10, None, None, 0, None) == \
+        cvetl.CV_ERR_WORKSPACE
+    spec = cvetl._spec_struct(__import__("paper_2305_07454_amd.gen", fromlist=["x"]).GRIDS["c0"])
+    assert L.cv_grid_aggregate(ctypes.byref(ok), ctypes.byref(spec), ctypes.byref(cvetl.CvGroups()), 10, None,
+                               None, 0, None) == cvetl.CV_ERR_WORKSPACE
+
+
+def test_timing_registry_host_only(L):
+    from paper_2305_07454_amd import cvetl
+    cvetl.cv_timing_reset()
+    assert cvetl.cv_timing_read("nothing") == (0.0, 0)

@@ -1,0 +1,183 @@
+"""HIP path vs the oracle, element by element, through the C ABI."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2305_07454_amd import gen
+
+from _parity import check_features, check_groups, check_sort, check_summary, host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cv():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2305_07454_amd import cvetl
+    cvetl.lib()
+    oracle.lib()
+    return cvetl
+
+
+def _run_both(cv, cols, spec, **kw):
+    print(f"[parity] n={len(cols[0])} spec={spec}", flush=True)
+    exp = oracle.run_plain(cols, spec)
+    rec = cv.to_device(cols)
+    got = cv.run_plain(rec, spec, **kw)
+    return got, exp
+
+
+def _check_all(got, exp):
+    check_sort(got["perm"], got["sorted"], exp["perm"], exp["sorted"])
+    check_features(got["features"], exp["features"])
+    check_summary(got["summary"], exp["summary"])
+    check_groups(got["groups"], got["n_out"], exp["groups"], exp["n_out"])
+
+
+def test_c0_full_size(cv):
+    r = gen.make_c0()
+    got, exp = _run_both(cv, r.columns(), gen.GRIDS["c0"])
+    _check_all(got, exp)
+
+
+def test_c1_shaped(cv):
+    r = gen.make_c1(seed=77, n_journeys=160)
+    got, exp = _run_both(cv, r.columns(), gen.GRIDS["c1"])
+    _check_all(got, exp)
+
+
+def test_c1_shuffled_variant(cv):
+    r = gen.make_c1(seed=78, n_journeys=80, shuffled=True)
+    got, exp = _run_both(cv, r.columns(), gen.GRIDS["c1"])
+    _check_all(got, exp)
+
+
+def test_c2_shard_high_cardinality(cv):
+    rng = np.random.default_rng(np.random.SeedSequence(5))
+    r = gen.make_shard(rng, 300_000)
+    got, exp = _run_both(cv, r.columns(), gen.GRIDS["c2"])
+    _check_all(got, exp)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 255, 256, 257, 2047, 2048, 2049, 4095, 4096, 4097, 8193])
+def test_ragged_sizes(cv, n):
+    r = gen.make_c0(seed=1000 + n, n_journeys=max(1, n // 40 + 1), min_len=1, max_len=80)
+    cols = tuple(c[:n] for c in r.columns())
+    got, exp = _run_both(cv, cols, gen.GRIDS["c0"])
+    _check_all(got, exp)
+
+
+def _adversarial():
+    rng = np.random.default_rng(9)
+    n = 6000
+    ids = np.array([-(2 ** 63), 2 ** 63 - 1, -1, 0, 1, 12345, -99999], dtype=np.int64)
+    jid = ids[rng.integers(0, len(ids), n)]
+    ts = gen.T0_MS + rng.integers(-5, 40, n).astype(np.int64) * 30_000      # ties, before t0
+    lat = rng.uniform(35.9, 40.7, n)                                          # some outside the box
+    lon = rng.uniform(-95.9, -89.0, n)
+    lat[rng.random(n) < 0.01] = np.nan
+    lon[rng.random(n) < 0.01] = np.inf
+    dup = rng.random(n) < 0.05                                                 # exact duplicates of a neighbour
+    idx = np.nonzero(dup)[0]
+    idx = idx[idx > 0]
+    lat[idx], lon[idx], ts[idx], jid[idx] = lat[idx - 1], lon[idx - 1], ts[idx - 1], jid[idx - 1]
+    spd = rng.uniform(0, 40, n).astype(np.float32)
+    spd[rng.random(n) < 0.1] = np.float32(-0.0)
+    spd[rng.random(n) < 0.1] = np.float32(0.0)
+    return jid, ts, lat, lon, spd
+
+
+def test_adversarial_ids_ties_duplicates_bad_coords(cv):
+    cols = _adversarial()
+    spec = gen.grid_for(0.01, 60_000)
+    got, exp = _run_both(cv, cols, spec)
+    _check_all(got, exp)
+
+
+def test_unbounded_time_bins(cv):
+    r = gen.make_c1(seed=3, n_journeys=40, median=600.0)
+    got, exp = _run_both(cv, r.columns(), gen.GRIDS["c3"])
+    _check_all(got, exp)
+
+
+def test_long_segments_cell_reentry(cv):
+    # 20 Hz journeys inside one long time bin, so (journey, bin) segments of tens
+    # of thousands of records cross many tiles: journey 5 oscillates across a
+    # cell edge (many re-entries found inside the LDS halo); journey 6 returns to
+    # a cell after thousands of records elsewhere (found only by the global-memory
+    # continuation of the backward scan)
+    L = 30_000
+    k = np.arange(L)
+    lat5 = 37.01 + 0.0001 * np.sin(k / 37.0)
+    lon5 = -92.004 + 0.0001 * np.cos(k / 53.0)
+    pieces = [(2000, 37.015), (6000, 37.025), (3000, 37.015), (5000, 37.035), (1000, 37.025), (13000, 37.015)]
+    lat6 = np.concatenate([np.full(m, v) + 1e-6 * np.arange(m) / m for m, v in pieces])
+    lon6 = np.full(L, -91.995)
+    jid = np.repeat(np.array([5, 6], np.int64), L)
+    ts = gen.T0_MS + np.tile(k * 50, 2)
+    lat = np.concatenate([lat5, lat6])
+    lon = np.concatenate([lon5, lon6])
+    spd = np.tile((k % 40).astype(np.float32), 2)
+    spec = gen.GridSpec(36.0, -95.8, 0.01, 0.01, 460, 670, gen.T0_MS, 3_600_000, 24)
+    got, exp = _run_both(cv, (jid, ts, lat, lon, spd), spec)
+    _check_all(got, exp)
+    # journey 6 visits 3 cells; each counts it once
+    assert int(exp["groups"]["n_journeys"].max()) == 1 and len(exp["groups"]["key"]) >= 5
+
+
+def test_table1_rows(cv):
+    import json, os
+    from test_oracle_pins import _table1, GOLDEN
+    e = json.load(open(os.path.join(GOLDEN, "table1_expected.json")))
+    cols = _table1()
+    got, exp = _run_both(cv, cols, gen.GridSpec(**e["grid"]))
+    _check_all(got, exp)
+    assert host(got["perm"]).tolist() == e["sorted_input_rows"]
+
+
+def test_empty_input(cv):
+    import torch
+    rec = cv.empty_records(0)
+    perm, srt, r = cv.cv_sort_records(rec)
+    assert perm.numel() == 0 and r["count"] == 0
+    feat = cv.cv_journey_features(srt)
+    summ, rs = cv.cv_journey_summary(srt, feat)
+    groups, rg = cv.cv_grid_aggregate(srt, gen.GRIDS["c0"])
+    assert rs["count"] == 0 and rg["count"] == 0 and rg["n_out_of_grid"] == 0
+    torch.cuda.synchronize()
+
+
+def test_capacity_retry_and_reporting(cv):
+    r = gen.make_c0(seed=21, n_journeys=300, min_len=50, max_len=200)
+    rec = cv.to_device(r)
+    # too-small dictionary and output capacities: device reports, wrapper retries
+    perm, srt, _, = cv.cv_sort_records(rec, max_journeys=None)
+    _, _, res = cv.cv_sort_records(rec, max_journeys=16, sync=False)
+    rr = cv.read_result(res)
+    assert rr["status"] == cv.CV_ERR_CAPACITY and rr["required"] >= 300
+    feat = cv.cv_journey_features(srt)
+    _, res = cv.cv_journey_summary(srt, feat, capacity=10, sync=False)
+    rr = cv.read_result(res)
+    assert rr["status"] == cv.CV_ERR_CAPACITY and rr["required"] == 300
+    summ, rs = cv.cv_journey_summary(srt, feat)
+    assert rs["count"] == 300
+    _, res = cv.cv_grid_aggregate(srt, gen.GRIDS["c0"], capacity=8, sync=False)
+    rr = cv.read_result(res)
+    assert rr["status"] == cv.CV_ERR_CAPACITY and rr["required"] > 8
+    groups, rg = cv.cv_grid_aggregate(srt, gen.GRIDS["c0"])
+    exp, _ = oracle.grid(*oracle.sorted_records(r.columns(), oracle.sort(r.journey_id, r.ts_ms)), gen.GRIDS["c0"])
+    assert rg["count"] == len(exp["key"])
+
+
+def test_deterministic_bitwise(cv):
+    r = gen.make_c1(seed=91, n_journeys=60, median=900.0)
+    rec = cv.to_device(r)
+    a = cv.run_plain(rec, gen.GRIDS["c1"])
+    b = cv.run_plain(rec, gen.GRIDS["c1"])
+    for part in ("features", "summary", "groups"):
+        for k in a[part]:
+            assert np.array_equal(host(a[part][k]).view(np.uint8), host(b[part][k]).view(np.uint8)), (part, k)

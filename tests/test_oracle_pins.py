@@ -263,6 +263,19 @@ def test_summary_against_numpy_and_fsum(oracle_mod):
         assert s["n_dt_zero"][j] == int(((f["flags"][a:b] & oracle.FLAG_DT_ZERO) != 0).sum())
 
 
+def test_summary_bbox_signed_zero_and_no_finite_points(oracle_mod):
+    jid = np.array([1, 1, 2, 2], np.int64)
+    ts = np.array([0, 1000, 0, 1000], np.int64)
+    lat = np.array([-0.0, 0.0, np.nan, np.nan])
+    lon = np.array([0.0, -0.0, 1.0, 2.0])
+    spd = np.ones(4, np.float32)
+    f = oracle.features(jid, ts, lat, lon)
+    s = oracle.summary(jid, ts, lat, lon, spd, f)
+    for k in ("lat_min", "lat_max", "lon_min", "lon_max"):
+        assert s[k][0] == 0.0 and math.copysign(1.0, s[k][0]) == 1.0
+    assert s["lat_min"][1] == math.inf and s["lat_max"][1] == -math.inf
+
+
 def test_summary_max_derived_speed_only_over_speed_ok(oracle_mod):
     jid = np.zeros(3, np.int64)
     ts = np.array([0, 1000, 1000], np.int64)
@@ -283,6 +296,7 @@ def test_summary_distance_is_sum_of_steps_negative_zero_speed(oracle_mod):
     s = oracle.summary(jid, ts, lat, lon, spd, f)
     assert s["distance_m"][0] == math.fsum(f["step_m"])
     assert math.copysign(1.0, float(s["max_speed"][0])) == 1.0      # -0.0 counted as +0.0
+    assert math.copysign(1.0, float(s["sum_speed"][0])) == 1.0      # exact zero sum is +0.0
 
 
 # --------------------------------------------------------------------------

@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=40_000_000, help="records in the oracle's timed sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--out", default=None, help="also write the JSON line to this file")
+    ap.add_argument("--sort-shape", type=int, default=None,
+                    help="radix tile shape index (default: the tuning cache, else the library default)")
     return ap.parse_args()
 
 
@@ -99,6 +101,12 @@ def main():
     torch.cuda.set_device(dev)
     r, grid, desc = make_workload(args.workload, args.n_journeys)
     n = r.n
+    if args.sort_shape is not None:
+        cvetl.cv_tuning_set("sort_shape", args.sort_shape)
+    else:
+        from paper_2305_07454_amd import tune
+        tune.apply(n)
+    log(f"sort shape {cvetl.cv_tuning_get('sort_shape')} (tile {cvetl.cv_tuning_get('sort_tile')} keys)")
     rec = cvetl.to_device(r, dev)
     torch.cuda.synchronize()
 
@@ -193,6 +201,7 @@ def main():
         "config": {"workload": f"{args.workload}: {desc}", "records": n, "journeys": J, "groups": G,
                    "path": "plain", "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": "k_radix_pass (stable 8-bit LSD scatter pass)",
+                     "tile_keys": cvetl.cv_tuning_get("sort_tile"),
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "avg_launch_ms": round(avg_ms, 5), "launches": pass_launches,

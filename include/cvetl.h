@@ -211,6 +211,17 @@ cv_status cv_grid_aggregate(const cv_records* sorted, const cv_grid_spec* grid /
                             size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Tuning knobs (process-wide; set by an autotuner, read back by callers).
+ *   "sort_shape"   index of the radix-pass tile shape (threads x keys per
+ *                  thread) used by every sort; 0 .. "sort_shapes" - 1.
+ *   "sort_shapes"  number of compiled shapes (read-only).
+ *   "sort_tile"    keys per tile of the current shape (read-only).
+ * Unknown names or out-of-range values return CV_ERR_INVALID_ARGUMENT.
+ * --------------------------------------------------------------------- */
+cv_status cv_tuning_set(const char* name /*[host]*/, int64_t value);
+cv_status cv_tuning_get(const char* name /*[host]*/, int64_t* value /*[host]*/);
+
+/* ------------------------------------------------------------------------
  * Per-kernel timing (measurement support).  When enabled, the library brackets
  * every launch of the named kernel family with HIP events on the launch stream
  * and accumulates the elapsed time; cv_timing_read synchronises those events.

@@ -55,6 +55,21 @@ __device__ __forceinline__ void fx_neg(Fx192& a)
     a.w[2] += c;
 }
 
+// Place a 53-bit integer m at bit offset sh (0 <= sh < 192) of a 192-bit word
+// without indexing the limbs at run time (a run-time index would force the
+// limbs into scratch memory).
+__device__ __forceinline__ Fx192 fx_place(u64 m, int sh)
+{
+    Fx192 r;
+    const int wd = sh >> 6, bt = sh & 63;
+    const u64 lo = m << bt;
+    const u64 hi = bt ? (m >> (64 - bt)) : 0ull;
+    r.w[0] = wd == 0 ? lo : 0ull;
+    r.w[1] = wd == 1 ? lo : (wd == 0 ? hi : 0ull);
+    r.w[2] = wd == 2 ? lo : (wd == 1 ? hi : 0ull);
+    return r;
+}
+
 template <int F>
 __device__ __forceinline__ Fx192 fx_from_double(double v)
 {
@@ -69,24 +84,39 @@ __device__ __forceinline__ Fx192 fx_from_double(double v)
     } else {
         m |= 1ull << 52;
     }
-    int sh = e - 1075 + F;  // v = m * 2^(e-1075); scaled: m * 2^sh
+    const int sh = e - 1075 + F;  // v = m * 2^(e-1075); scaled: m * 2^sh
     if (sh <= -53) return r;
-    if (sh < 0) {
-        r.w[0] = m >> (-sh);
-    } else {
-        int wd = sh >> 6, bt = sh & 63;
-        if (wd < 3) r.w[wd] = m << bt;
-        if (bt != 0 && wd + 1 < 3) r.w[wd + 1] = m >> (64 - bt);
-    }
+    if (sh < 0) r.w[0] = m >> (-sh);
+    else if (sh < 192) r = fx_place(m, sh);
     if (bits >> 63) fx_neg(r);
     return r;
+}
+
+// bits [lo, lo + 64) of a 192-bit word (lo in [0, 192)), no run-time indexing
+__device__ __forceinline__ u64 fx_extract64(const Fx192& a, int lo)
+{
+    const int wd = lo >> 6, bt = lo & 63;
+    const u64 w0 = wd == 0 ? a.w[0] : (wd == 1 ? a.w[1] : a.w[2]);
+    const u64 w1 = wd == 0 ? a.w[1] : (wd == 1 ? a.w[2] : 0ull);
+    return bt ? ((w0 >> bt) | (w1 << (64 - bt))) : w0;
+}
+
+// true when any of the bits [0, k) is set (0 <= k <= 192)
+__device__ __forceinline__ bool fx_any_below(const Fx192& a, int k)
+{
+    const u64 m0 = k >= 64 ? ~0ull : (k <= 0 ? 0ull : ((1ull << k) - 1));
+    const int k1 = k - 64;
+    const u64 m1 = k1 >= 64 ? ~0ull : (k1 <= 0 ? 0ull : ((1ull << k1) - 1));
+    const int k2 = k - 128;
+    const u64 m2 = k2 >= 64 ? ~0ull : (k2 <= 0 ? 0ull : ((1ull << k2) - 1));
+    return ((a.w[0] & m0) | (a.w[1] & m1) | (a.w[2] & m2)) != 0;
 }
 
 // Round-to-nearest-even of the fixed-point value times 2^-F.
 template <int F>
 __device__ __forceinline__ double fx_to_double(Fx192 a)
 {
-    bool neg = (a.w[2] >> 63) != 0;
+    const bool neg = (a.w[2] >> 63) != 0;
     if (neg) fx_neg(a);
     int p;
     if (a.w[2]) p = 128 + 63 - __clzll((long long)a.w[2]);
@@ -97,24 +127,12 @@ __device__ __forceinline__ double fx_to_double(Fx192 a)
     if (p <= 52) {
         r = ldexp((double)a.w[0], -F);
     } else {
-        // mantissa = bits [p-52, p]; round bit p-53; sticky below
+        // mantissa = bits [p-52, p]; round bit p-53; sticky below it
         int lo = p - 52;
-        auto bit_at = [&](int i) -> u64 { return (a.w[i >> 6] >> (i & 63)) & 1ull; };
-        u64 mant;
-        {
-            int wd = lo >> 6, bt = lo & 63;
-            mant = a.w[wd] >> bt;
-            if (bt != 0 && wd + 1 < 3) mant |= a.w[wd + 1] << (64 - bt);
-            mant &= (1ull << 53) - 1;
-        }
-        int rb = lo - 1;
-        u64 round = bit_at(rb);
-        bool sticky = false;
-        if (rb > 0) {
-            int wd = rb >> 6, bt = rb & 63;
-            for (int i = 0; i < wd; ++i) sticky |= a.w[i] != 0;
-            if (bt) sticky |= (a.w[wd] & ((1ull << bt) - 1)) != 0;
-        }
+        u64 mant = fx_extract64(a, lo) & ((1ull << 53) - 1);
+        const int rb = lo - 1;
+        const u64 round = (fx_extract64(a, rb) & 1ull);
+        const bool sticky = fx_any_below(a, rb);
         if (round && (sticky || (mant & 1))) {
             mant += 1;
             if (mant == (1ull << 53)) {

@@ -3,18 +3,20 @@
 // count / sum / count-unique / mean reductions of Table 3), as a sparse,
 // key-sorted group table over (journey, time)-sorted records.
 //
-//   k_grid_agg   per tile of GT records:
+//   k_grid_agg   per tile of GT records, staged in LDS with coalesced loads:
 //     * key = (tbin * n_lat + ilat) * n_lon + ilon per record (-1 outside);
-//     * distinct-journey flag: a record counts towards n_journeys iff no earlier
-//       record of its (journey, time-bin) segment has the same key.  Records of
-//       one (journey, tbin) are contiguous after the sort, so a backward scan
-//       that stops at the segment start decides it; segments entering the tile
-//       are covered by a halo loaded into LDS on demand (global memory beyond);
-//     * runs of equal key inside a thread's records are pre-reduced, then
-//       inserted into an LDS open-addressing table; entries that find no LDS
+//     * runs: maximal stretches of one key inside one (journey, time-bin)
+//       segment.  Records of one (journey, tbin) are contiguous after the sort,
+//       so a run head counts its journey for the cell (distinct-journey flag)
+//       iff no earlier run head of the same segment has the same key.  Run heads
+//       are compacted into an LDS list and each one compares itself with the
+//       earlier heads of its segment; segments entering the tile bring a halo
+//       loaded on demand (global memory beyond it);
+//     * each run is reduced by one thread (count, exact speed sum, min, max),
+//       then inserted into an LDS open-addressing table; runs that find no LDS
 //       slot spill straight to the HBM table; at tile end the LDS table is
-//       merged into the HBM table with integer atomics (exact sums, so the
-//       result is independent of tile and atomic order);
+//       merged into the HBM table with non-returning integer atomics (sums in
+//       carry-save 40-bit chunks), so the result does not depend on the order;
 //   k_grid_compact  occupied HBM slots -> (key, slot) pairs;
 //   radix sort of the pairs by key (the same LSD sort as the record order);
 //   k_grid_emit     rows in ascending key, sums rounded once to double.
@@ -37,17 +39,41 @@ constexpr int HALO = 1024;
 constexpr int LHS = 512;
 constexpr int LHS_PROBES = 32;
 constexpr int FX_SPD = 149;
+constexpr int CS40 = 5;  // carry-save chunks of 40 bits: 2^24 adds per entry without overflow
 constexpr u64 GEMPTY = ~0ull;
 
+// one 64-byte line per group
 struct GEntry {
     u64 key;
-    u64 sum[3];
+    u64 cs[CS40];
     u32 count, nj, mn, mx;
 };
-static_assert(sizeof(GEntry) == 48, "entry layout");
+static_assert(sizeof(GEntry) == 64, "entry layout");
+
+__device__ __forceinline__ void fx_to_cs40(const Fx192& a, u64 c[CS40])
+{
+    const u64 M = (1ull << 40) - 1;
+    c[0] = a.w[0] & M;
+    c[1] = ((a.w[0] >> 40) | (a.w[1] << 24)) & M;
+    c[2] = (a.w[1] >> 16) & M;
+    c[3] = ((a.w[1] >> 56) | (a.w[2] << 8)) & M;
+    c[4] = a.w[2] >> 32;
+}
+
+__device__ __forceinline__ Fx192 fx_from_cs40(const u64 c[CS40])
+{
+    Fx192 r;
+    fx_zero(r);
+#pragma unroll
+    for (int i = 0; i < CS40; ++i) {
+        Fx192 t = fx_place(c[i], 40 * i);  // c[i] < 2^64: the part beyond bit 191 wraps away
+        fx_add(r, t);
+    }
+    return r;
+}
 
 struct GridMeta {
-    u32 G;          // distinct keys inserted into the HBM table
+    u32 pad0;
     u32 overflow;   // HBM table full
     u64 n_out;      // records outside the grid
     u64 max_key;    // largest key seen
@@ -63,8 +89,17 @@ struct Spec {
     i64 n_lat, n_lon, t0, bin_ms, tmax;
 };
 
+// floor(a / b) for b > 0: a double estimate corrected by one integer step
+// (exact for |a| < 2^52); wider operands take the integer division.
 __device__ __forceinline__ i64 floor_div64(i64 a, i64 b)
 {
+    if (a > -(1ll << 52) && a < (1ll << 52)) {
+        i64 q = (i64)floor((double)a / (double)b);
+        i64 r = a - q * b;
+        if (r < 0) q -= 1;
+        else if (r >= b) q += 1;
+        return q;
+    }
     i64 q = a / b;
     if ((a % b != 0) && ((a < 0) != (b < 0))) q -= 1;
     return q;
@@ -86,7 +121,7 @@ __global__ void __launch_bounds__(256) k_grid_clear(GEntry* __restrict__ tab, u6
     for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < slots; i += (u64)gridDim.x * blockDim.x) {
         GEntry e;
         e.key = GEMPTY;
-        e.sum[0] = e.sum[1] = e.sum[2] = 0;
+        for (int c = 0; c < CS40; ++c) e.cs[c] = 0;
         e.count = 0;
         e.nj = 0;
         e.mn = ~0u;
@@ -101,11 +136,14 @@ __global__ void __launch_bounds__(256) k_grid_clear(GEntry* __restrict__ tab, u6
 
 __device__ __forceinline__ void g_merge(GEntry& e, u32 count, u32 nj, const Fx192& sum, u32 mn, u32 mx)
 {
-    atomicAdd(&e.count, count);
-    if (nj) atomicAdd(&e.nj, nj);
-    atomic_add_fx(e.sum, sum);
-    atomicMin(&e.mn, mn);
-    atomicMax(&e.mx, mx);
+    u64 c[CS40];
+    fx_to_cs40(sum, c);
+    for (int i = 0; i < CS40; ++i)
+        if (c[i]) __hip_atomic_fetch_add(&e.cs[i], c[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(&e.count, count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (nj) __hip_atomic_fetch_add(&e.nj, nj, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_min(&e.mn, mn, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_max(&e.mx, mx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ void g_insert(GEntry* tab, u64 mask, GridMeta* meta, u64 key, u32 count, u32 nj,
@@ -120,7 +158,6 @@ __device__ __forceinline__ void g_insert(GEntry* tab, u64 mask, GridMeta* meta, 
         }
         if (cur == GEMPTY) {
             u64 prev = atomicCAS((unsigned long long*)&tab[h].key, (unsigned long long)GEMPTY, (unsigned long long)key);
-            if (prev == GEMPTY) atomicAdd(&meta->G, 1u);
             if (prev == GEMPTY || prev == key) {
                 g_merge(tab[h], count, nj, sum, mn, mx);
                 return;
@@ -136,21 +173,125 @@ struct LSlot {
     u32 count, nj, mn, mx;
 };
 
+constexpr uint8_t B_SEG = 1;   // first record of a (journey, time-bin) segment
+constexpr uint8_t B_RUN = 2;   // first record of a run (segment start or key change)
+constexpr uint8_t B_FIRST = 4; // run head whose key is new in its segment (counts its journey)
+
+// partial aggregate of one run (or piece of a run)
+struct RunPart {
+    Fx192 sum;
+    u32 count, nj, mn, mx;
+};
+
+__device__ __forceinline__ void run_reset(RunPart& p)
+{
+    fx_zero(p.sum);
+    p.count = 0;
+    p.nj = 0;
+    p.mn = ~0u;
+    p.mx = 0;
+}
+
+__device__ __forceinline__ void run_combine(RunPart& a, const RunPart& b)
+{
+    fx_add(a.sum, b.sum);
+    a.count += b.count;
+    a.nj += b.nj;
+    a.mn = b.mn < a.mn ? b.mn : a.mn;
+    a.mx = b.mx > a.mx ? b.mx : a.mx;
+}
+
+template <typename F>
+__device__ __forceinline__ void run_shuffle(RunPart& o, const RunPart& p, F&& sh)
+{
+    o.sum.w[0] = sh(p.sum.w[0]);
+    o.sum.w[1] = sh(p.sum.w[1]);
+    o.sum.w[2] = sh(p.sum.w[2]);
+    o.count = (u32)sh((u64)p.count);
+    o.nj = (u32)sh((u64)p.nj);
+    o.mn = (u32)sh((u64)p.mn);
+    o.mx = (u32)sh((u64)p.mx);
+}
+
+__device__ __forceinline__ void run_wave_reduce(RunPart& p)
+{
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        RunPart o;
+        run_shuffle(o, p, [&](u64 v) { return (u64)__shfl_xor((unsigned long long)v, d, WAVE); });
+        run_combine(p, o);
+    }
+}
+
+__device__ __forceinline__ void run_seg_scan(RunPart& p, bool head)
+{
+    const int l = lane_id();
+    bool f = head;
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        RunPart o;
+        run_shuffle(o, p, [&](u64 v) { return (u64)__shfl_up((unsigned long long)v, d, WAVE); });
+        const bool fo = __shfl_up(f, d, WAVE);
+        if (l >= d) {
+            if (!f) {
+                run_combine(o, p);
+                p = o;
+            }
+            f = f || fo;
+        }
+    }
+}
+
+// one run's partial into the tile's LDS table; no free slot within the probe
+// limit spills it straight to the HBM table
+__device__ __forceinline__ void run_insert(u64* s_hkey, LSlot* s_h, GEntry* tab, u64 gmask, GridMeta* meta, u64 key,
+                                           const RunPart& p)
+{
+    u64 h = mix64(key) & (LHS - 1);
+    for (int probe = 0; probe < LHS_PROBES; ++probe) {
+        u64 cur = s_hkey[h];
+        if (cur == GEMPTY) {
+            const u64 prev =
+                atomicCAS((unsigned long long*)&s_hkey[h], (unsigned long long)GEMPTY, (unsigned long long)key);
+            cur = prev == GEMPTY ? key : prev;
+        }
+        if (cur == key) {
+            LSlot& sl = s_h[h];
+            u64 c[4];
+            fx_to_cs(p.sum, c);
+            for (int i = 0; i < 4; ++i)
+                if (c[i]) atomicAdd((unsigned long long*)&sl.cs[i], (unsigned long long)c[i]);
+            atomicAdd(&sl.count, p.count);
+            if (p.nj) atomicAdd(&sl.nj, p.nj);
+            atomicMin(&sl.mn, p.mn);
+            atomicMax(&sl.mx, p.mx);
+            return;
+        }
+        h = (h + 1) & (LHS - 1);
+    }
+    g_insert(tab, gmask, meta, key, p.count, p.nj, p.sum, p.mn, p.mx);
+}
+
 __global__ void __launch_bounds__(GB, 2)
 k_grid_agg(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, const double* __restrict__ lat,
            const double* __restrict__ lon, const float* __restrict__ spd, Spec g, GEntry* __restrict__ tab, u64 gmask,
            GridMeta* meta)
 {
-    __shared__ i64 s_key[HALO + GT];
-    __shared__ uint8_t s_seg[HALO + GT];  // 1: first record of a (journey, time-bin) segment
+    constexpr int NQ = HALO + GT;
+    __shared__ i64 s_key[NQ];       // keys per record; later the keys of the run-head list
+    __shared__ uint8_t s_bits[NQ];
+    __shared__ u32 s_lpos[NQ];      // run-head list: q | first << 30 | segment start << 31
     __shared__ float s_spd[GT];
     __shared__ u64 s_hkey[LHS];
     __shared__ LSlot s_h[LHS];
+    __shared__ u32 s_tmp[GB / WAVE];
     __shared__ u32 s_flag;
+    __shared__ u32 s_nlist;
     __shared__ u64 s_out[GB / WAVE];
 
     const int t = threadIdx.x;
     const u64 tile0 = (u64)blockIdx.x * GT;
+    const u32 tvalid = (u32)((u64)n - tile0 < (u64)GT ? (u64)n - tile0 : (u64)GT);
     for (int i = t; i < LHS; i += GB) {
         s_hkey[i] = GEMPTY;
         LSlot z;
@@ -161,12 +302,12 @@ k_grid_agg(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, const
         z.mx = 0;
         s_h[i] = z;
     }
-    // tile records: striped, coalesced loads; key, segment-start flag, speed
+    // tile records (striped, coalesced): key, segment-start bit, speed
     u64 n_out = 0;
     for (int i = t; i < GT; i += GB) {
-        u64 r = tile0 + i;
+        const u64 r = tile0 + i;
         i64 k = -1;
-        uint8_t sg = 1;
+        uint8_t b = B_SEG;
         float sp = 0.f;
         if (r < n) {
             i64 tb;
@@ -174,144 +315,162 @@ k_grid_agg(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, const
             n_out += (k < 0);
             sp = spd[r];
             if (r > 0) {
-                i64 tbp = floor_div64(ts[r - 1] - g.t0, g.bin_ms);
-                sg = (jid[r] != jid[r - 1]) || (tb != tbp);
+                const i64 tbp = floor_div64(ts[r - 1] - g.t0, g.bin_ms);
+                b = ((jid[r] != jid[r - 1]) || (tb != tbp)) ? B_SEG : 0;
             }
         }
         s_key[HALO + i] = k;
-        s_seg[HALO + i] = sg;
+        s_bits[HALO + i] = b;
         s_spd[i] = sp;
     }
     if (t == 0) s_flag = 0;
     __syncthreads();
-    // halo: only when the first segment of the tile started before it
-    int lo_bound = HALO;  // lowest valid LDS index
-    bool need = s_seg[HALO] == 0;
-    bool halo_exhausted = false;
-    while (need) {
-        if (lo_bound - GB < 0) {
-            halo_exhausted = true;
-            break;
-        }
-        int q = lo_bound - GB + t;
-        long r = (long)tile0 - HALO + q;
-        i64 k = -1;
-        uint8_t sg = 1;
-        if (r >= 0) {
-            i64 tb;
-            k = grid_key(g, ts[r], lat[r], lon[r], tb);
-            if (r > 0) {
-                i64 tbp = floor_div64(ts[r - 1] - g.t0, g.bin_ms);
-                sg = (jid[r] != jid[r - 1]) || (tb != tbp);
-            }
-        }
-        s_key[q] = k;
-        s_seg[q] = sg;
-        if (sg) atomicOr(&s_flag, 1u);
-        __syncthreads();
-        need = s_flag == 0;
-        lo_bound -= GB;
-        __syncthreads();
-    }
-
-    // per-thread runs over GI consecutive records
-    const int q0 = HALO + t * GI;
-    u64 kmax = 0;
-    i64 rk = -1;
-    u32 rc = 0, rnj = 0, rmn = ~0u, rmx = 0;
-    Fx192 rsum;
-    fx_zero(rsum);
-    auto flush = [&]() {
-        if (rc == 0) return;
-        u64 key = (u64)rk;
-        u64 h = mix64(key) & (LHS - 1);
-        bool done = false;
-        for (int probe = 0; probe < LHS_PROBES; ++probe) {
-            u64 cur = s_hkey[h];
-            if (cur == GEMPTY) {
-                u64 prev = atomicCAS((unsigned long long*)&s_hkey[h], (unsigned long long)GEMPTY,
-                                     (unsigned long long)key);
-                cur = prev == GEMPTY ? key : prev;
-            }
-            if (cur == key) {
-                LSlot& s = s_h[h];
-                u64 c[4];
-                fx_to_cs(rsum, c);
-                for (int i = 0; i < 4; ++i)
-                    if (c[i]) atomicAdd((unsigned long long*)&s.cs[i], (unsigned long long)c[i]);
-                atomicAdd(&s.count, rc);
-                if (rnj) atomicAdd(&s.nj, rnj);
-                atomicMin(&s.mn, rmn);
-                atomicMax(&s.mx, rmx);
-                done = true;
+    // halo, loaded backwards in rows of GB until a segment start shows up
+    int lo_bound = HALO;
+    bool exhausted = false;
+    if (!(s_bits[HALO] & B_SEG)) {
+        while (true) {
+            if (lo_bound - GB < 0) {
+                exhausted = true;
                 break;
             }
-            h = (h + 1) & (LHS - 1);
-        }
-        if (!done) g_insert(tab, gmask, meta, key, rc, rnj, rsum, rmn, rmx);  // spill to HBM
-        rc = 0;
-        rnj = 0;
-        rmn = ~0u;
-        rmx = 0;
-        fx_zero(rsum);
-    };
-    for (int i = 0; i < GI; ++i) {
-        const int q = q0 + i;
-        const u64 r = tile0 + (u64)(q - HALO);
-        if (r >= n) break;
-        const i64 k = s_key[q];
-        if (k < 0) {
-            flush();
-            continue;
-        }
-        kmax = (u64)k > kmax ? (u64)k : kmax;
-        // distinct-journey flag: earlier record of the same segment with this key?
-        bool first = true;
-        if (!s_seg[q]) {
-            int p = q - 1;
-            while (true) {
-                if (p < lo_bound) {
-                    // beyond the loaded halo: continue in global memory
-                    long rr = (long)tile0 - HALO + p;
-                    while (rr >= 0) {
-                        i64 tb;
-                        i64 kk = grid_key(g, ts[rr], lat[rr], lon[rr], tb);
-                        if (kk == k) {
-                            first = false;
-                            break;
-                        }
-                        if (rr == 0) break;
-                        i64 tbp = floor_div64(ts[rr - 1] - g.t0, g.bin_ms);
-                        if (jid[rr] != jid[rr - 1] || tb != tbp) break;
-                        --rr;
-                    }
-                    break;
+            const int q = lo_bound - GB + t;
+            const long r = (long)tile0 - HALO + q;
+            i64 k = -1;
+            uint8_t b = B_SEG;
+            if (r >= 0) {
+                i64 tb;
+                k = grid_key(g, ts[r], lat[r], lon[r], tb);
+                if (r > 0) {
+                    const i64 tbp = floor_div64(ts[r - 1] - g.t0, g.bin_ms);
+                    b = ((jid[r] != jid[r - 1]) || (tb != tbp)) ? B_SEG : 0;
                 }
-                if (s_key[p] == k) {
+            }
+            s_key[q] = k;
+            s_bits[q] = b;
+            if (b) atomicOr(&s_flag, 1u);
+            __syncthreads();
+            const bool found = s_flag != 0;
+            lo_bound -= GB;
+            __syncthreads();
+            if (found) break;
+        }
+    }
+    // run-head bits over [lo_bound, HALO + tvalid)
+    const int qend = HALO + (int)tvalid;
+    for (int q = lo_bound + t; q < qend; q += GB) {
+        uint8_t b = s_bits[q];
+        if ((b & B_SEG) || q == lo_bound || s_key[q] != s_key[q - 1]) b |= B_RUN;
+        s_bits[q] = b;
+    }
+    if (t == 0) s_nlist = 0;
+    __syncthreads();
+    // order-preserving compaction of run heads into a list of positions
+    for (int base = lo_bound; base < qend; base += GB) {
+        const int q = base + t;
+        const bool rh = q < qend && (s_bits[q] & B_RUN);
+        u32 tot;
+        const u32 e = block_exclusive_sum<GB>(rh ? 1u : 0u, s_tmp, tot);
+        const u32 at = s_nlist;
+        if (rh) s_lpos[at + e] = (u32)q | ((s_bits[q] & B_SEG) ? (1u << 31) : 0u);
+        __syncthreads();
+        if (t == 0) s_nlist = at + tot;
+        __syncthreads();
+    }
+    const int L = (int)s_nlist;
+    // distinct-journey flag of every run head inside the tile: no earlier run
+    // head of its segment has the same key
+    for (int e = t; e < L; e += GB) {
+        const u32 pe = s_lpos[e];
+        const int q = (int)(pe & 0x7FFFFFFFu);
+        if (q < HALO) continue;
+        const i64 k = s_key[q];
+        if (k < 0) continue;
+        bool first = true;
+        if (!(pe >> 31)) {
+            int f = e - 1;
+            bool closed = false;
+            for (; f >= 0; --f) {
+                const u32 pf = s_lpos[f];
+                if (s_key[pf & 0x7FFFFFFFu] == k) {
                     first = false;
                     break;
                 }
-                if (s_seg[p]) break;
-                --p;
+                if (pf >> 31) {
+                    closed = true;
+                    break;
+                }
+            }
+            if (first && f < 0 && !closed && exhausted) {
+                // the segment starts before the loaded halo: continue in global memory
+                long rr = (long)tile0 - HALO + lo_bound - 1;
+                while (rr >= 0) {
+                    i64 tb;
+                    const i64 kk = grid_key(g, ts[rr], lat[rr], lon[rr], tb);
+                    if (kk == k) {
+                        first = false;
+                        break;
+                    }
+                    if (rr == 0) break;
+                    const i64 tbp = floor_div64(ts[rr - 1] - g.t0, g.bin_ms);
+                    if (jid[rr] != jid[rr - 1] || tb != tbp) break;
+                    --rr;
+                }
             }
         }
-        const bool same_run = rc > 0 && rk == k && !s_seg[q];
-        if (!same_run) {
-            flush();
-            rk = k;
-        }
-        float sp = s_spd[q - HALO];
-        rc += 1;
-        rnj += first ? 1u : 0u;
-        Fx192 a = fx_from_double<FX_SPD>((double)sp);
-        fx_add(rsum, a);
-        u32 o = ord_f32(sp);
-        rmn = o < rmn ? o : rmn;
-        rmx = o > rmx ? o : rmx;
+        if (first) s_bits[q] |= B_FIRST;
     }
-    flush();
-    (void)halo_exhausted;
-    // out-of-grid count
+    __syncthreads();
+    // Aggregation: every wave walks its GT/4 records of the tile in windows of
+    // 64.  Lanes fold records into a private partial while the window holds no
+    // run start; a window with starts closes the open run (wave reduction) and
+    // scans the runs that begin in it (segmented scan); each finished run is one
+    // LDS hash insert.  A wave's first record starts a piece of its own.
+    {
+        constexpr int WREC = GT / (GB / WAVE);
+        const int w = t / WAVE, l = lane_id();
+        const int qa = HALO + w * WREC;
+        RunPart p;
+        run_reset(p);
+        i64 open_key = -1;
+        for (int i = 0; i < WREC / WAVE; ++i) {
+            const int q = qa + i * WAVE + l;
+            const bool valid = q < qend;
+            const i64 k = valid ? s_key[q] : -1;
+            const uint8_t b = valid ? s_bits[q] : 0;
+            const bool head = valid && ((b & B_RUN) || (i == 0 && l == 0));
+            RunPart c;
+            run_reset(c);
+            if (valid && k >= 0) {
+                const float sp = s_spd[q - HALO];
+                c.count = 1;
+                c.nj = (b & B_FIRST) ? 1u : 0u;
+                c.sum = fx_from_double<FX_SPD>((double)sp);
+                c.mn = c.mx = ord_f32(sp);
+            }
+            const u64 H = __ballot(head);
+            if (H == 0) {
+                run_combine(p, c);
+                continue;
+            }
+            const int f0 = __ffsll((long long)H) - 1;
+            if (l < f0) run_combine(p, c);
+            run_wave_reduce(p);
+            if (l == 0 && open_key >= 0 && p.count) run_insert(s_hkey, s_h, tab, gmask, meta, (u64)open_key, p);
+            RunPart sc = c;
+            run_seg_scan(sc, head);
+            const bool next_head = (l < WAVE - 1) && ((H >> (l + 1)) & 1ull);
+            // key of the run each lane belongs to: the key of its head lane
+            if (l >= f0 && next_head && k >= 0 && sc.count) run_insert(s_hkey, s_h, tab, gmask, meta, (u64)k, sc);
+            const int lh = 63 - __clzll((long long)H);  // last head lane: the run left open
+            open_key = __shfl(k, lh, WAVE);
+            run_reset(p);
+            if (l == WAVE - 1) p = sc;
+        }
+        run_wave_reduce(p);
+        if (l == 0 && open_key >= 0 && p.count) run_insert(s_hkey, s_h, tab, gmask, meta, (u64)open_key, p);
+    }
+    // out-of-grid count (one global atomic per tile, only when non-zero)
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) n_out += __shfl_xor(n_out, d, WAVE);
     if (lane_id() == 0) s_out[t / WAVE] = n_out;
@@ -323,29 +482,58 @@ k_grid_agg(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, const
     }
     // merge the LDS table into the HBM table
     for (int i = t; i < LHS; i += GB) {
-        u64 key = s_hkey[i];
+        const u64 key = s_hkey[i];
         if (key == GEMPTY) continue;
-        const LSlot& s = s_h[i];
-        Fx192 sum = fx_from_cs(s.cs);
-        g_insert(tab, gmask, meta, key, s.count, s.nj, sum, s.mn, s.mx);
+        const LSlot& sl = s_h[i];
+        const Fx192 sum = fx_from_cs(sl.cs);
+        g_insert(tab, gmask, meta, key, sl.count, sl.nj, sum, sl.mn, sl.mx);
     }
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) {
-        u64 o = __shfl_xor(kmax, d, WAVE);
-        kmax = o > kmax ? o : kmax;
-    }
-    if (lane_id() == 0 && kmax) atomicMax((unsigned long long*)&meta->max_key, (unsigned long long)kmax);
 }
+
+// each block compacts CSLOTS consecutive slots with one global atomic for its
+// base; the order of the pairs is irrelevant (they are sorted by key next)
+constexpr int CPT = 16;
+constexpr int CSLOTS = 256 * CPT;
 
 __global__ void __launch_bounds__(256) k_grid_compact(const GEntry* __restrict__ tab, u64 slots, GridMeta* meta,
                                                       u64* __restrict__ ckeys, u32* __restrict__ cvals)
 {
-    for (u64 s = (u64)blockIdx.x * blockDim.x + threadIdx.x; s < slots; s += (u64)gridDim.x * blockDim.x) {
-        u64 k = tab[s].key;
-        if (k != GEMPTY) {
-            u32 pos = atomicAdd(&meta->compact_n, 1u);
-            ckeys[pos] = k;
-            cvals[pos] = (u32)s;
+    __shared__ u32 s_tmp[256 / WAVE];
+    __shared__ u64 s_kmax[256 / WAVE];
+    __shared__ u32 s_base;
+    const u64 s0 = (u64)blockIdx.x * CSLOTS + (u64)threadIdx.x * CPT;
+    u64 k[CPT];
+    u32 c = 0;
+    u64 kmax = 0;
+#pragma unroll
+    for (int i = 0; i < CPT; ++i) {
+        const u64 s = s0 + i;
+        k[i] = s < slots ? tab[s].key : GEMPTY;
+        c += k[i] != GEMPTY;
+        if (k[i] != GEMPTY && k[i] > kmax) kmax = k[i];
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        const u64 o = __shfl_xor(kmax, d, WAVE);
+        kmax = o > kmax ? o : kmax;
+    }
+    if (lane_id() == 0) s_kmax[threadIdx.x / WAVE] = kmax;
+    u32 tot;
+    const u32 e = block_exclusive_sum<256>(c, s_tmp, tot);
+    if (threadIdx.x == 0) {
+        s_base = tot ? atomicAdd(&meta->compact_n, tot) : 0u;
+        u64 m = 0;
+        for (int w = 0; w < 256 / WAVE; ++w) m = s_kmax[w] > m ? s_kmax[w] : m;
+        if (m) atomicMax((unsigned long long*)&meta->max_key, (unsigned long long)m);
+    }
+    __syncthreads();
+    u32 pos = s_base + e;
+#pragma unroll
+    for (int i = 0; i < CPT; ++i) {
+        if (k[i] != GEMPTY) {
+            ckeys[pos] = k[i];
+            cvals[pos] = (u32)(s0 + i);
+            ++pos;
         }
     }
 }
@@ -378,11 +566,7 @@ __global__ void __launch_bounds__(256) k_grid_emit(const GEntry* __restrict__ ta
         o_key[i] = (i64)e.key;
         o_cnt[i] = e.count;
         o_nj[i] = e.nj;
-        Fx192 s;
-        s.w[0] = e.sum[0];
-        s.w[1] = e.sum[1];
-        s.w[2] = e.sum[2];
-        o_sum[i] = fx_to_double<FX_SPD>(s);
+        o_sum[i] = fx_to_double<FX_SPD>(fx_from_cs40(e.cs));
         o_min[i] = unord_f32(e.mn);
         o_max[i] = unord_f32(e.mx);
     }
@@ -392,7 +576,7 @@ __global__ void __launch_bounds__(256) k_grid_emit(const GEntry* __restrict__ ta
         const bool over = full || G > cap;
         r.status = over ? CV_ERR_CAPACITY : CV_OK;
         r.count = G;
-        if (full) r.required = ((u64)G + 1 > 2ull * cap) ? (u64)G + 1 : 2ull * cap;
+        if (full) r.required = ((u64)G + 1 > 2ull * cap) ? (u64)G + 1 : 2ull * cap;  // G: a lower bound
         else if (over) r.required = G;
         r.n_out_of_grid = meta->n_out;
         r.key_bits = meta->key_bits;
@@ -438,7 +622,7 @@ struct GridLayout {
         cvh::Carver c(ws);
         u64 want = 2 * (cap < 1 ? 1 : cap);
         slots = cvh::next_pow2(want < 4096 ? 4096 : want);
-        stiles = (slots + SORT_TILE - 1) / SORT_TILE;
+        stiles = (slots + sort_min_tile() - 1) / sort_min_tile();
         tiles = (n + GT - 1) / GT;
         meta = c.take<GridMeta>(1);
         tab = c.take<GEntry>(slots);
@@ -525,8 +709,8 @@ cv_status cv_grid_aggregate(const cv_records* sorted, const cv_grid_spec* grid, 
     }
     {
         cvh::TimedScope ts_("grid_tail", s);
-        hipLaunchKernelGGL(k_grid_compact, dim3(cvh::grid_for(L.slots, 256, 4096)), dim3(256), 0, s, L.tab, L.slots,
-                           L.meta, L.K0, L.C);
+        hipLaunchKernelGGL(k_grid_compact, dim3((unsigned)((L.slots + CSLOTS - 1) / CSLOTS)), dim3(256), 0, s, L.tab,
+                           L.slots, L.meta, L.K0, L.C);
         hipLaunchKernelGGL(k_grid_bits, dim3(1), dim3(64), 0, s, L.meta);
         const u32* cnt = &L.meta->compact_n;
         const u32* bits = &L.meta->key_bits;

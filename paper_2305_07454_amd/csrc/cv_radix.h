@@ -21,10 +21,16 @@ namespace cv {
 
 constexpr int RADIX_BITS = 8;
 constexpr int RADIX = 1 << RADIX_BITS;
-constexpr int SORT_BLOCK = 256;
-constexpr int SORT_ITEMS = 16;
-constexpr int SORT_TILE = SORT_BLOCK * SORT_ITEMS;
 constexpr int MAX_PASSES = 8;
+
+// Tile shapes (threads per block x keys per thread) compiled into the library.
+// The sort launches the selected one; workspaces are sized for the smallest
+// tile so any shape fits.
+int sort_shape_count();
+int sort_shape();
+bool set_sort_shape(int i);
+int sort_tile(int i);
+int sort_min_tile();
 
 // Host launchers (defined in cv_radix.hip).
 //   radix_hist : digit histograms of `passes` passes (limited on device by

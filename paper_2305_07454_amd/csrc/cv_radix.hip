@@ -2,6 +2,8 @@
 // described in cv_radix.h.
 #include <hip/hip_runtime.h>
 
+#include <string>
+
 #include "cv_host.h"
 #include "cv_radix.h"
 
@@ -51,13 +53,16 @@ __global__ void __launch_bounds__(256) k_radix_scan(const u32* __restrict__ hist
 
 // One stable scatter pass on digit `pass` (bits [8*pass, 8*pass+8)).
 // vals_in == nullptr means the identity (input index).
-__global__ void __launch_bounds__(SORT_BLOCK, 2)
+template <int SORT_BLOCK, int SORT_ITEMS>
+__global__ void __launch_bounds__(SORT_BLOCK)
 k_radix_pass(const u64* __restrict__ keys_in, const u32* __restrict__ vals_in, u64* __restrict__ keys_out,
              u32* __restrict__ vals_out, u32 n_max, const u32* __restrict__ n_dev, int pass,
              const u32* __restrict__ bits_dev, const u32* __restrict__ digit_offs, u64* __restrict__ status,
              u32* __restrict__ ticket)
 {
     constexpr int NW = SORT_BLOCK / WAVE;
+    constexpr int SORT_TILE = SORT_BLOCK * SORT_ITEMS;
+    static_assert(SORT_BLOCK >= RADIX, "one thread per digit");
     __shared__ u32 s_whist[NW][RADIX];
     __shared__ u32 s_start[RADIX];
     __shared__ u32 s_gshift[RADIX];
@@ -188,22 +193,89 @@ void radix_scan(const u32* hist, u32* offs, int passes, hipStream_t s)
     hipLaunchKernelGGL(k_radix_scan, dim3(1), dim3(256), 0, s, hist, offs, passes);
 }
 
+namespace {
+
+// tile shapes compiled into the library; the sort uses sort_shape()
+struct Shape {
+    int block, items;
+};
+constexpr Shape SHAPES[] = {{256, 16}, {256, 32}, {512, 8}, {512, 16}, {1024, 8}};
+constexpr int N_SHAPES = sizeof(SHAPES) / sizeof(SHAPES[0]);
+int g_shape = 0;
+
+template <int B, int I>
+void launch_pass(u64 tiles, hipStream_t s, const u64* kin, const u32* vin, u64* kout, u32* vout, u32 n_max,
+                 const u32* n_dev, int p, const u32* bits_dev, const u32* offs, u64* status, u32* ticket)
+{
+    hipLaunchKernelGGL((k_radix_pass<B, I>), dim3((unsigned)(tiles ? tiles : 1)), dim3(B), 0, s, kin, vin, kout, vout,
+                       n_max, n_dev, p, bits_dev, offs, status, ticket);
+}
+
+}  // namespace
+
+int sort_shape_count() { return N_SHAPES; }
+int sort_shape() { return g_shape; }
+bool set_sort_shape(int i)
+{
+    if (i < 0 || i >= N_SHAPES) return false;
+    g_shape = i;
+    return true;
+}
+int sort_tile(int i) { return SHAPES[i].block * SHAPES[i].items; }
+int sort_min_tile()
+{
+    int m = sort_tile(0);
+    for (int i = 1; i < N_SHAPES; ++i) m = sort_tile(i) < m ? sort_tile(i) : m;
+    return m;
+}
+
 void radix_passes(u64* k0, u64* k1, const u32* v_first, u32* v0, u32* v1, u32 n_max, const u32* n_dev,
                   const u32* bits_dev, int passes, const u32* offs, u64* status, u32* tickets, hipStream_t s,
                   bool timed)
 {
     static const char* const names[MAX_PASSES] = {"sort_pass0", "sort_pass1", "sort_pass2", "sort_pass3",
                                                   "sort_pass4", "sort_pass5", "sort_pass6", "sort_pass7"};
-    const u64 tiles = ((u64)n_max + SORT_TILE - 1) / SORT_TILE;
+    const int sh = g_shape;
+    const u64 tile = (u64)sort_tile(sh);
+    const u64 tiles = ((u64)n_max + tile - 1) / tile;
     for (int p = 0; p < passes; ++p) {
         const u64* kin = (p & 1) ? k1 : k0;
         const u32* vin = p == 0 ? v_first : ((p & 1) ? v1 : v0);
         u64* kout = (p & 1) ? k0 : k1;
         u32* vout = (p & 1) ? v0 : v1;
         cvh::TimedScope ts_(timed ? names[p] : nullptr, s);
-        hipLaunchKernelGGL(k_radix_pass, dim3((unsigned)(tiles ? tiles : 1)), dim3(SORT_BLOCK), 0, s, kin, vin, kout,
-                           vout, n_max, n_dev, p, bits_dev, offs + p * RADIX, status, tickets + p);
+        const u32* o = offs + p * RADIX;
+        switch (sh) {
+        case 0: launch_pass<256, 16>(tiles, s, kin, vin, kout, vout, n_max, n_dev, p, bits_dev, o, status, tickets + p); break;
+        case 1: launch_pass<256, 32>(tiles, s, kin, vin, kout, vout, n_max, n_dev, p, bits_dev, o, status, tickets + p); break;
+        case 2: launch_pass<512, 8>(tiles, s, kin, vin, kout, vout, n_max, n_dev, p, bits_dev, o, status, tickets + p); break;
+        case 3: launch_pass<512, 16>(tiles, s, kin, vin, kout, vout, n_max, n_dev, p, bits_dev, o, status, tickets + p); break;
+        default: launch_pass<1024, 8>(tiles, s, kin, vin, kout, vout, n_max, n_dev, p, bits_dev, o, status, tickets + p); break;
+        }
     }
 }
 
 }  // namespace cv
+
+extern "C" {
+
+cv_status cv_tuning_set(const char* name, int64_t value)
+{
+    if (!name) return CV_ERR_INVALID_ARGUMENT;
+    const std::string n(name);
+    if (n == "sort_shape") return cv::set_sort_shape((int)value) ? CV_OK : CV_ERR_INVALID_ARGUMENT;
+    return CV_ERR_INVALID_ARGUMENT;
+}
+
+cv_status cv_tuning_get(const char* name, int64_t* value)
+{
+    if (!name || !value) return CV_ERR_INVALID_ARGUMENT;
+    const std::string n(name);
+    if (n == "sort_shape") *value = cv::sort_shape();
+    else if (n == "sort_shapes") *value = cv::sort_shape_count();
+    else if (n == "sort_tile") *value = cv::sort_tile(cv::sort_shape());
+    else return CV_ERR_INVALID_ARGUMENT;
+    return CV_OK;
+}
+
+}  // extern "C"

@@ -65,11 +65,7 @@ __device__ __forceinline__ bool dict_insert(u64* table, u64 mask, u64 key, SortM
         if (cur == key) return true;
         if (cur == EMPTY) {
             u64 prev = atomicCAS((unsigned long long*)&table[h], (unsigned long long)EMPTY, (unsigned long long)key);
-            if (prev == EMPTY) {
-                atomicAdd(&m->n_distinct, 1u);
-                return true;
-            }
-            if (prev == key) return true;
+            if (prev == EMPTY || prev == key) return true;
         }
         h = (h + 1) & mask;
     }
@@ -135,10 +131,17 @@ __global__ void __launch_bounds__(256) k_dict_compact(const u64* __restrict__ ta
 {
     u32 hm = m->has_min;
     if (blockIdx.x == 0 && threadIdx.x == 0 && hm && max_j > 0) list[0] = EMPTY ^ SIGN;
-    for (u64 s = (u64)blockIdx.x * blockDim.x + threadIdx.x; s < slots; s += (u64)gridDim.x * blockDim.x) {
-        u64 k = table[s];
-        if (k != EMPTY) {
-            u32 pos = atomicAdd(&m->list_count, 1u) + hm;
+    const u64 stride = (u64)gridDim.x * blockDim.x;
+    for (u64 b = (u64)blockIdx.x * blockDim.x; b < slots; b += stride) {
+        const u64 s = b + threadIdx.x;
+        const u64 k = s < slots ? table[s] : EMPTY;
+        const bool occ = k != EMPTY;
+        const u64 msk = __ballot(occ);
+        u32 base = 0;
+        if (lane_id() == 0 && msk) base = atomicAdd(&m->list_count, (u32)__popcll(msk));
+        base = __shfl(base, 0, WAVE);
+        if (occ) {
+            const u32 pos = base + popc_below(msk) + hm;
             if (pos < max_j) list[pos] = k ^ SIGN;
         }
     }
@@ -147,7 +150,7 @@ __global__ void __launch_bounds__(256) k_dict_compact(const u64* __restrict__ ta
 __global__ void k_dict_meta(SortMeta* m, u32 max_j, u32 n)
 {
     if (threadIdx.x != 0) return;
-    u32 J = m->n_distinct + m->has_min;
+    u32 J = m->list_count + m->has_min;  // distinct ids counted by the compaction
     m->J = J;
     if (J > max_j) m->overflow = 1;
     m->dict_n = J < max_j ? J : max_j;
@@ -177,6 +180,9 @@ __global__ void __launch_bounds__(256) k_dict_rank(const u64* __restrict__ sorte
     }
 }
 
+// Waves walk contiguous windows of 64 records, so the journey-rank digits of a
+// window are usually equal in every lane: such a digit is counted with one LDS
+// add instead of 64 colliding ones.
 __global__ void __launch_bounds__(256) k_pack_hist(const i64* __restrict__ jid, const i64* __restrict__ ts, u32 n,
                                                    const u64* __restrict__ table, const u32* __restrict__ ranks,
                                                    u64 mask, const SortMeta* m, u64* __restrict__ keys,
@@ -189,25 +195,33 @@ __global__ void __launch_bounds__(256) k_pack_hist(const i64* __restrict__ jid, 
     const u32 np = m->passes;
     const bool bad = m->range_err != 0;
     const u64 tmin = (u64)unord_i64(m->tmin_ord);
-    u64 prev_j = EMPTY;
-    u32 prev_r = 0;
-    bool have_prev = false;
-    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        u64 j = (u64)jid[i];
-        u32 r = 0;
-        if (have_prev && j == prev_j) {
-            r = prev_r;
-        } else if (j != EMPTY) {
-            u64 s = dict_find(table, mask, j);
-            r = (s != ~0ull) ? ranks[s] : 0u;
-        }
-        prev_j = j;
-        prev_r = r;
-        have_prev = true;
+    const int l = lane_id();
+    const u64 nw = (u64)gridDim.x * (blockDim.x / WAVE);
+    for (u64 wi = (u64)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE; wi * WAVE < n; wi += nw) {
+        const u64 i = wi * WAVE + l;
+        const bool valid = i < n;
         u64 key = 0;
-        if (!bad) key = (tb >= 64 ? 0ull : ((u64)r << tb)) | ((u64)ts[i] - tmin);
-        keys[i] = key;
-        for (u32 p = 0; p < np; ++p) atomicAdd(&s_h[p * RADIX + ((key >> (p * RADIX_BITS)) & (RADIX - 1))], 1u);
+        if (valid) {
+            const u64 j = (u64)jid[i];
+            u32 r = 0;
+            if (j != EMPTY) {
+                const u64 s = dict_find(table, mask, j);
+                r = (s != ~0ull) ? ranks[s] : 0u;
+            }
+            if (!bad) key = (tb >= 64 ? 0ull : ((u64)r << tb)) | ((u64)ts[i] - tmin);
+            keys[i] = key;
+        }
+        const u64 vm = __ballot(valid);
+        const int lead = __ffsll((long long)vm) - 1;
+        for (u32 p = 0; p < np; ++p) {
+            const u32 d = (u32)(key >> (p * RADIX_BITS)) & (RADIX - 1);
+            const u32 d0 = __shfl(d, lead, WAVE);
+            if (__ballot(valid && d != d0) == 0) {
+                if (l == lead) atomicAdd(&s_h[p * RADIX + d0], (u32)__popcll(vm));
+            } else if (valid) {
+                atomicAdd(&s_h[p * RADIX + d], 1u);
+            }
+        }
     }
     __syncthreads();
     for (u32 i = threadIdx.x; i < np * RADIX; i += blockDim.x)
@@ -294,8 +308,8 @@ struct SortLayout {
     {
         cvh::Carver c(ws);
         slots = cvh::next_pow2(2 * max_j < 1024 ? 1024 : 2 * max_j);
-        tiles = (n + SORT_TILE - 1) / SORT_TILE;
-        dtiles = (max_j + SORT_TILE - 1) / SORT_TILE;
+        tiles = (n + sort_min_tile() - 1) / sort_min_tile();
+        dtiles = (max_j + sort_min_tile() - 1) / sort_min_tile();
         meta = c.take<SortMeta>(1);
         table = c.take<u64>(slots);
         ranks = c.take<u32>(slots);

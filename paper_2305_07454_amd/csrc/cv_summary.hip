@@ -1,16 +1,16 @@
 // cv_summary.hip -- cv_journey_summary: one row per journey of sorted records.
 //
 // Journeys are maximal runs of equal journey id.  Tiles of ST records:
-//   k_sum_count   heads per tile;
+//   k_sum_count   journey starts per tile;
 //   k_tile_scan   exclusive scan of the tile counts (one block) -> journey index
-//                 of each tile's first head, J;
+//                 of each tile's first start, J;
 //   k_sum_init    identity values in the accumulator rows of the J journeys;
-//   k_sum_reduce  each thread folds its SI consecutive records sequentially in
-//                 exact fixed point; partials that span threads merge in LDS
-//                 slots owned by the thread holding the journey's head; a
-//                 journey fully inside the tile is written out directly, one
-//                 that crosses a tile edge is added with integer atomics into
-//                 its accumulator row (order-independent, hence deterministic);
+//   k_sum_reduce  segmented reduction over journey boundaries: every wave walks
+//                 its records in coalesced windows of 64, folding them in exact
+//                 fixed point; a journey that starts and ends inside one wave's
+//                 records is written out directly, the pieces of one that
+//                 crosses a wave edge meet in its accumulator row through
+//                 integer atomics (order-independent, hence deterministic);
 //   k_sum_finalize accumulator rows -> output rows (exact sums rounded once).
 #include <hip/hip_runtime.h>
 
@@ -101,7 +101,7 @@ __global__ void __launch_bounds__(256) k_sum_init(JAcc* __restrict__ acc, const 
     }
 }
 
-// running partial of one journey inside one thread's chunk
+// Partial aggregate of one journey (a lane's records, a wave's, or a tile's).
 struct Part {
     Fx192 dist, spd;
     u64 maxd, latmin, latmax, lonmin, lonmax;
@@ -122,45 +122,66 @@ __device__ __forceinline__ void part_reset(Part& p)
     p.maxs = 0;
 }
 
-// LDS slot: carry-save sums so that merges are plain 64-bit adds
-struct Slot {
-    u64 dist[4];
-    u64 spd[4];
-    u64 maxd, latmin, latmax, lonmin, lonmax;
-    u32 count, ndtz, maxs, pad;
-};
-
-__device__ __forceinline__ void slot_store(Slot& s, const Part& p)
+__device__ __forceinline__ void part_combine(Part& a, const Part& b)
 {
-    fx_to_cs(p.dist, s.dist);
-    fx_to_cs(p.spd, s.spd);
-    s.maxd = p.maxd;
-    s.latmin = p.latmin;
-    s.latmax = p.latmax;
-    s.lonmin = p.lonmin;
-    s.lonmax = p.lonmax;
-    s.count = p.count;
-    s.ndtz = p.ndtz;
-    s.maxs = p.maxs;
+    fx_add(a.dist, b.dist);
+    fx_add(a.spd, b.spd);
+    a.maxd = b.maxd > a.maxd ? b.maxd : a.maxd;
+    a.latmin = b.latmin < a.latmin ? b.latmin : a.latmin;
+    a.latmax = b.latmax > a.latmax ? b.latmax : a.latmax;
+    a.lonmin = b.lonmin < a.lonmin ? b.lonmin : a.lonmin;
+    a.lonmax = b.lonmax > a.lonmax ? b.lonmax : a.lonmax;
+    a.count += b.count;
+    a.ndtz += b.ndtz;
+    a.maxs = b.maxs > a.maxs ? b.maxs : a.maxs;
 }
 
-__device__ __forceinline__ void slot_merge(Slot& s, const Part& p)
+template <typename F>
+__device__ __forceinline__ void part_shuffle(Part& o, const Part& p, F&& sh)
 {
-    u64 c[4];
-    fx_to_cs(p.dist, c);
-    for (int i = 0; i < 4; ++i)
-        if (c[i]) atomicAdd((unsigned long long*)&s.dist[i], (unsigned long long)c[i]);
-    fx_to_cs(p.spd, c);
-    for (int i = 0; i < 4; ++i)
-        if (c[i]) atomicAdd((unsigned long long*)&s.spd[i], (unsigned long long)c[i]);
-    atomicMax((unsigned long long*)&s.maxd, (unsigned long long)p.maxd);
-    atomicMin((unsigned long long*)&s.latmin, (unsigned long long)p.latmin);
-    atomicMax((unsigned long long*)&s.latmax, (unsigned long long)p.latmax);
-    atomicMin((unsigned long long*)&s.lonmin, (unsigned long long)p.lonmin);
-    atomicMax((unsigned long long*)&s.lonmax, (unsigned long long)p.lonmax);
-    atomicAdd(&s.count, p.count);
-    atomicAdd(&s.ndtz, p.ndtz);
-    atomicMax(&s.maxs, p.maxs);
+    for (int i = 0; i < 3; ++i) {
+        o.dist.w[i] = sh(p.dist.w[i]);
+        o.spd.w[i] = sh(p.spd.w[i]);
+    }
+    o.maxd = sh(p.maxd);
+    o.latmin = sh(p.latmin);
+    o.latmax = sh(p.latmax);
+    o.lonmin = sh(p.lonmin);
+    o.lonmax = sh(p.lonmax);
+    o.count = (u32)sh((u64)p.count);
+    o.ndtz = (u32)sh((u64)p.ndtz);
+    o.maxs = (u32)sh((u64)p.maxs);
+}
+
+// full wave reduction; every lane ends with the total
+__device__ __forceinline__ void part_wave_reduce(Part& p)
+{
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        Part o;
+        part_shuffle(o, p, [&](u64 v) { return (u64)__shfl_xor((unsigned long long)v, d, WAVE); });
+        part_combine(p, o);
+    }
+}
+
+// segmented inclusive scan across lanes; `head` starts a segment
+__device__ __forceinline__ void part_seg_scan(Part& p, bool head)
+{
+    const int l = lane_id();
+    bool f = head;
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        Part o;
+        part_shuffle(o, p, [&](u64 v) { return (u64)__shfl_up((unsigned long long)v, d, WAVE); });
+        bool fo = __shfl_up(f, d, WAVE);
+        if (l >= d) {
+            if (!f) {
+                part_combine(o, p);
+                p = o;
+            }
+            f = f || fo;
+        }
+    }
 }
 
 struct Out {
@@ -192,26 +213,37 @@ __device__ __forceinline__ void write_final(const Out& o, u32 j, u32 count, u32 
     o.lonmax[j] = unord_f64(lo1);
 }
 
-__device__ __forceinline__ void part_final(const Out& o, u32 j, const Part& p)
+__device__ __forceinline__ void flush_part(const Out& o, JAcc* acc, u32 cap, u32 j, const Part& p, bool whole)
 {
-    write_final(o, j, p.count, p.ndtz, p.dist, p.spd, p.maxs, p.maxd, p.latmin, p.latmax, p.lonmin, p.lonmax);
-}
-
-__device__ __forceinline__ void acc_merge_global(JAcc& a, u32 count, u32 ndtz, const Fx192& dist, const Fx192& spd,
-                                                 u32 maxs, u64 maxd, u64 la0, u64 la1, u64 lo0, u64 lo1)
-{
-    atomic_add_fx(a.dist, dist);
-    atomic_add_fx(a.spd, spd);
-    atomicMax((unsigned long long*)&a.maxd, (unsigned long long)maxd);
-    atomicMin((unsigned long long*)&a.latmin, (unsigned long long)la0);
-    atomicMax((unsigned long long*)&a.latmax, (unsigned long long)la1);
-    atomicMin((unsigned long long*)&a.lonmin, (unsigned long long)lo0);
-    atomicMax((unsigned long long*)&a.lonmax, (unsigned long long)lo1);
-    atomicAdd(&a.count, count);
-    atomicAdd(&a.ndtz, ndtz);
-    atomicMax(&a.maxs, maxs);
+    if (j >= cap || p.count == 0) return;
+    if (whole) {
+        write_final(o, j, p.count, p.ndtz, p.dist, p.spd, p.maxs, p.maxd, p.latmin, p.latmax, p.lonmin, p.lonmax);
+        return;
+    }
+    JAcc& a = acc[j];
+    atomic_add_fx(a.dist, p.dist);
+    atomic_add_fx(a.spd, p.spd);
+    atomicMax((unsigned long long*)&a.maxd, (unsigned long long)p.maxd);
+    atomicMin((unsigned long long*)&a.latmin, (unsigned long long)p.latmin);
+    atomicMax((unsigned long long*)&a.latmax, (unsigned long long)p.latmax);
+    atomicMin((unsigned long long*)&a.lonmin, (unsigned long long)p.lonmin);
+    atomicMax((unsigned long long*)&a.lonmax, (unsigned long long)p.lonmax);
+    atomicAdd(&a.count, p.count);
+    atomicAdd(&a.ndtz, p.ndtz);
+    atomicMax(&a.maxs, p.maxs);
     atomicOr(&a.touched, 1u);
 }
+
+// Each wave owns WCH consecutive records and walks them in coalesced windows of
+// 64.  Lanes fold their records into a private partial while the window holds
+// no journey start; a window with starts closes the open journey (wave
+// reduction), runs a segmented scan for journeys that begin in it, and hands
+// the last one on as the new open journey.  A journey that begins and ends in
+// the wave's records is written out directly; otherwise its pieces meet in the
+// accumulator row through integer atomics.
+constexpr int WI = SI;                  // windows per wave
+constexpr int WCH = WAVE * WI;          // records per wave
+static_assert(ST == (SB / WAVE) * WCH, "tile = waves x wave chunk");
 
 __global__ void __launch_bounds__(SB) k_sum_reduce(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts,
                                                    const double* __restrict__ lat, const double* __restrict__ lon,
@@ -220,154 +252,113 @@ __global__ void __launch_bounds__(SB) k_sum_reduce(u32 n, const i64* __restrict_
                                                    const u32* __restrict__ tile_prefix, u32 cap, Out o,
                                                    JAcc* __restrict__ acc)
 {
-    __shared__ Slot s_slot[SB + 1];  // s_slot[SB] is the journey continuing from the previous tile
-    __shared__ u32 s_tmp[SB / WAVE];
-    __shared__ int s_tmpi[SB / WAVE];
-    __shared__ u32 s_hashead[SB];
+    __shared__ u32 s_wh[SB / WAVE];
+    const int w = threadIdx.x / WAVE;
+    const int l = lane_id();
+    const u64 cs = (u64)blockIdx.x * ST + (u64)w * WCH;  // wave chunk start
+    const u64 ce = cs + WCH < n ? cs + WCH : (u64)n;      // wave chunk end (may be <= cs)
 
-    const int t = threadIdx.x;
-    const u64 tile0 = (u64)blockIdx.x * ST;
-    const u64 r0 = tile0 + (u64)t * SI;
-    const u64 r1 = (r0 + SI < n) ? r0 + SI : (r0 < n ? (u64)n : r0);
-    const u64 tile_end = (tile0 + ST < n) ? tile0 + ST : (u64)n;
-
-    // heads in this thread's chunk
-    u32 heads = 0;
-    bool head0 = false;
-    for (u64 r = r0; r < r1; ++r) {
-        bool h = is_head(jid, r);
-        heads += h;
-        if (r == r0) head0 = h;
+    // heads in this wave's chunk -> journey index of the wave's first head
+    u32 hc = 0;
+    for (int i = 0; i < WI; ++i) {
+        u64 r = cs + (u64)i * WAVE + l;
+        if (r < ce && (r == 0 || jid[r] != jid[r - 1])) ++hc;
     }
-    u32 tot;
-    const u32 before = block_exclusive_sum<SB>(heads, s_tmp, tot);
-    s_hashead[t] = heads ? 1u : 0u;
-    // owner of the journey entering this chunk: last earlier thread with a head
-    int mark = heads ? t : -1;
-    {
-        int w = t / WAVE;
-        int inc = wave_inclusive_max(mark);
-        if (lane_id() == WAVE - 1) s_tmpi[w] = inc;
-        __syncthreads();
-        int pre = -1;
-        for (int i = 0; i < w; ++i) pre = s_tmpi[i] > pre ? s_tmpi[i] : pre;
-        int incl = inc > pre ? inc : pre;
-        // exclusive: drop this thread's own mark
-        int excl_val = __shfl_up(incl, 1, WAVE);
-        if (lane_id() == 0) excl_val = pre;
-        mark = excl_val;  // owner for this thread's entering partial
-    }
-    const int owner = mark;
-    // is there a thread after t in this tile holding a head?
-    // (computed after the slot phase from s_hashead)
-
-    const u32 tpre = tile_prefix[blockIdx.x];
-    // journey index of record r0
-    u32 j = tpre + before + (head0 ? 1u : 0u);
-    j -= 1;  // index of the journey containing r0 (valid when r0 < n)
-
-    if (t == 0) {
-        Part z;
-        part_reset(z);
-        slot_store(s_slot[SB], z);
-    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) hc += __shfl_xor(hc, d, WAVE);
+    if (l == 0) s_wh[w] = hc;
+    __syncthreads();
+    u32 seen = tile_prefix[blockIdx.x];  // heads before the current position
+    for (int k = 0; k < w; ++k) seen += s_wh[k];
+    if (cs >= ce) return;
 
     Part p;
     part_reset(p);
-    bool p_from_head = head0;  // current partial started at a head inside this chunk
-    bool entering_done = head0;  // the entering (pre) partial is empty when r0 is a head
-    Part pre_part;
-    part_reset(pre_part);
-    bool have_pre = false;
-    for (u64 r = r0; r < r1; ++r) {
-        bool h = is_head(jid, r);
-        if (h && r != r0) {
-            // close current partial
-            if (p_from_head) {
-                if (j < cap) part_final(o, j, p);  // complete journey inside the chunk
-            } else {
-                pre_part = p;
-                have_pre = true;
-                entering_done = true;
+    // open journey: the one containing the record before the next window
+    u32 open_j = seen - 1;   // valid when the chunk starts mid-journey
+    bool open_here = false;  // its first record lies in this chunk
+    // window loads are issued one window ahead of their use
+    struct Win {
+        i64 j, jp, jn, t;
+        double st, ds, la, lo;
+        float sp;
+        uint8_t f;
+    };
+    auto load = [&](int i, Win& x) {
+        const u64 r = cs + (u64)i * WAVE + l;
+        if (r < ce) {
+            x.j = jid[r];
+            x.jp = r > 0 ? jid[r - 1] : ~x.j;
+            x.jn = r + 1 < n ? jid[r + 1] : ~x.j;
+            x.t = ts[r];
+            x.st = step[r];
+            x.sp = spd[r];
+            x.f = flags[r];
+            x.ds = dspd[r];
+            x.la = lat[r];
+            x.lo = lon[r];
+        }
+    };
+    Win cur, nxt;
+    load(0, cur);
+    for (int i = 0; i < WI; ++i) {
+        if (i + 1 < WI) load(i + 1, nxt);
+        const u64 r = cs + (u64)i * WAVE + l;
+        const bool valid = r < ce;
+        bool h = false, last = false;
+        Part c;
+        part_reset(c);
+        if (valid) {
+            h = (r == 0) || (cur.j != cur.jp);
+            last = (r + 1 >= n) || (cur.jn != cur.j);
+            c.count = 1;
+            c.ndtz = (cur.f & CV_FLAG_DT_ZERO) ? 1u : 0u;
+            c.dist = fx_from_double<FX_DIST>(cur.st);
+            c.spd = fx_from_double<FX_SPD>((double)cur.sp);
+            c.maxs = ord_f32(cur.sp);
+            if (cur.f & CV_FLAG_SPEED_OK) c.maxd = ord_f64(cur.ds);
+            if (isfinite(cur.la) && isfinite(cur.lo)) {
+                c.latmin = c.latmax = ord_f64(cur.la);
+                c.lonmin = c.lonmax = ord_f64(cur.lo);
             }
-            ++j;
+        }
+        const u64 H = __ballot(h);
+        // journey index of this lane's record
+        const u32 jl = seen + popc_below(H) + (h ? 1u : 0u) - 1u;
+        if (h && jl < cap) {
+            o.jid[jl] = cur.j;
+            o.first[jl] = (u32)r;
+            o.tstart[jl] = cur.t;
+        }
+        if (valid && last && jl < cap) o.tend[jl] = cur.t;
+        if (H != 0) {
+            const int f0 = __ffsll((long long)H) - 1;
+            if (l < f0) part_combine(p, c);
+            // close the journey that was open before the first start in this window
+            part_wave_reduce(p);
+            if (l == 0) flush_part(o, acc, cap, open_j, p, open_here);
+            // journeys starting in this window
+            Part s = c;
+            part_seg_scan(s, h);
+            // a segment that ends before lane 63 (next lane starts a journey) is a
+            // whole journey: it began and ended inside this window
+            const bool next_head = (l < WAVE - 1) && ((H >> (l + 1)) & 1ull);
+            if (l >= f0 && next_head) flush_part(o, acc, cap, jl, s, true);
+            // the last segment stays open; lane 63 holds its partial
             part_reset(p);
-            p_from_head = true;
+            if (l == WAVE - 1) p = s;
+            seen += (u32)__popcll(H);
+            open_j = seen - 1;
+            open_here = true;
+        } else {
+            part_combine(p, c);
         }
-        if (h) {
-            if (j < cap) {
-                o.jid[j] = jid[r];
-                o.first[j] = (u32)r;
-                o.tstart[j] = ts[r];
-            }
-        }
-        // last record of its journey?
-        if (r + 1 >= n || jid[r + 1] != jid[r]) {
-            if (j < cap) o.tend[j] = ts[r];
-        }
-        uint8_t f = flags[r];
-        p.count += 1;
-        p.ndtz += (f & CV_FLAG_DT_ZERO) ? 1u : 0u;
-        Fx192 a = fx_from_double<FX_DIST>(step[r]);
-        fx_add(p.dist, a);
-        a = fx_from_double<FX_SPD>((double)spd[r]);
-        fx_add(p.spd, a);
-        u32 ms = ord_f32(spd[r]);
-        p.maxs = ms > p.maxs ? ms : p.maxs;
-        if (f & CV_FLAG_SPEED_OK) {
-            u64 d = ord_f64(dspd[r]);
-            p.maxd = d > p.maxd ? d : p.maxd;
-        }
-        double la = lat[r], lo = lon[r];
-        if (isfinite(la) && isfinite(lo)) {
-            u64 a0 = ord_f64(la), b0 = ord_f64(lo);
-            p.latmin = a0 < p.latmin ? a0 : p.latmin;
-            p.latmax = a0 > p.latmax ? a0 : p.latmax;
-            p.lonmin = b0 < p.lonmin ? b0 : p.lonmin;
-            p.lonmax = b0 > p.lonmax ? b0 : p.lonmax;
-        }
+        cur = nxt;
     }
-    // at chunk end: p is the suffix partial (from the last head) or, when the chunk
-    // had no head, the whole chunk (an entering partial)
-    if (!entering_done && r0 < r1) {
-        pre_part = p;
-        have_pre = true;
-    }
-    // phase 1: threads with a head own slot[t] = suffix partial
-    if (heads) slot_store(s_slot[t], p);
-    __syncthreads();
-    // phase 2: entering partials merge into their owner's slot
-    if (have_pre) slot_merge(s_slot[owner >= 0 ? owner : SB], pre_part);
-    __syncthreads();
-    // phase 3: flush slots
-    const bool next_is_head = tile_end >= n || is_head(jid, tile_end);
-    if (heads && r0 < r1) {
-        // journey index of this thread's last head
-        u32 jl = tpre + before + heads - 1;
-        bool later = false;
-        for (int u = t + 1; u < SB; ++u)
-            if (s_hashead[u]) {
-                later = true;
-                break;
-            }
-        const Slot& s = s_slot[t];
-        Fx192 dist = fx_from_cs(s.dist), sp = fx_from_cs(s.spd);
-        if (later || next_is_head) {
-            if (jl < cap) write_final(o, jl, s.count, s.ndtz, dist, sp, s.maxs, s.maxd, s.latmin, s.latmax, s.lonmin, s.lonmax);
-        } else if (jl < cap) {
-            acc_merge_global(acc[jl], s.count, s.ndtz, dist, sp, s.maxs, s.maxd, s.latmin, s.latmax, s.lonmin, s.lonmax);
-        }
-    }
-    if (t == 0 && tpre > 0) {
-        const Slot& s = s_slot[SB];
-        if (s.count > 0) {
-            u32 jp = tpre - 1;
-            if (jp < cap) {
-                Fx192 dist = fx_from_cs(s.dist), sp = fx_from_cs(s.spd);
-                acc_merge_global(acc[jp], s.count, s.ndtz, dist, sp, s.maxs, s.maxd, s.latmin, s.latmax, s.lonmin,
-                                 s.lonmax);
-            }
-        }
+    part_wave_reduce(p);
+    if (l == 0) {
+        const bool ends = (ce >= n) || (jid[ce] != jid[ce - 1]);
+        flush_part(o, acc, cap, open_j, p, open_here && ends);
     }
 }
 

@@ -119,6 +119,10 @@ def lib():
         L.cv_grid_aggregate.argtypes = [ctypes.POINTER(CvRecords), ctypes.POINTER(CvGridSpec),
                                         ctypes.POINTER(CvGroups), U64, P, P, ctypes.c_size_t, P]
         L.cv_grid_aggregate.restype = S
+        L.cv_tuning_set.argtypes = [ctypes.c_char_p, ctypes.c_int64]
+        L.cv_tuning_set.restype = S
+        L.cv_tuning_get.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64)]
+        L.cv_tuning_get.restype = S
         L.cv_timing_enable.argtypes = [S]
         L.cv_timing_enable.restype = S
         L.cv_timing_reset.restype = S
@@ -282,8 +286,18 @@ def cv_grid_aggregate(sorted_rec, grid, capacity=None, stream=None, sync=True, w
 
 
 # ---------------------------------------------------------------------------
-# timing
+# tuning and timing
 # ---------------------------------------------------------------------------
+
+def cv_tuning_set(name, value):
+    _check(lib().cv_tuning_set(name.encode(), int(value)), f"cv_tuning_set({name})")
+
+
+def cv_tuning_get(name):
+    v = ctypes.c_int64(0)
+    _check(lib().cv_tuning_get(name.encode(), ctypes.byref(v)), f"cv_tuning_get({name})")
+    return int(v.value)
+
 
 def cv_timing_enable(on=True):
     _check(lib().cv_timing_enable(1 if on else 0), "cv_timing_enable")

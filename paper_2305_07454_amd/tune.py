@@ -1,0 +1,97 @@
+"""Autotuner for the library's tuning knobs.
+
+Sweeps the compiled radix-pass tile shapes (threads x keys per thread) on a
+workload, times the record sort's scatter passes with the library's per-kernel
+HIP-event timing, and keeps the fastest shape per workload signature in a JSON
+cache next to this file.  ``apply(n)`` installs the cached choice for a batch
+of n records (nearest recorded size), or leaves the library default.
+
+    python -m paper_2305_07454_amd.tune --workload c1 [--reps 5]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json")
+
+
+def _load():
+    if os.path.exists(CACHE):
+        with open(CACHE) as f:
+            return json.load(f)
+    return {"arch": "gfx950", "entries": []}
+
+
+def apply(n: int) -> int | None:
+    """Set the cached best sort shape for an n-record batch; returns it."""
+    from . import cvetl
+    c = _load()
+    best = None
+    for e in c.get("entries", []):
+        if best is None or abs(e["n"] - n) < abs(best["n"] - n):
+            best = e
+    if best is None:
+        return None
+    cvetl.cv_tuning_set("sort_shape", best["sort_shape"])
+    return best["sort_shape"]
+
+
+def sweep_sort_shapes(rec, grid, reps=5, log=print):
+    """Time the record sort passes for every compiled shape on one batch."""
+    import torch
+    from . import cvetl
+    n = int(rec["journey_id"].numel())
+    shapes = cvetl.cv_tuning_get("sort_shapes")
+    results = []
+    for sh in range(shapes):
+        cvetl.cv_tuning_set("sort_shape", sh)
+        tile = cvetl.cv_tuning_get("sort_tile")
+        perm, srt, r = cvetl.cv_sort_records(rec)          # warm-up and key width
+        passes = (r["key_bits"] + 7) // 8
+        torch.cuda.synchronize()
+        cvetl.cv_timing_reset()
+        cvetl.cv_timing_enable(True)
+        for _ in range(reps):
+            cvetl.cv_sort_records(rec, sync=False)
+        torch.cuda.synchronize()
+        cvetl.cv_timing_enable(False)
+        ms = [cvetl.cv_timing_read(f"sort_pass{p}") for p in range(passes)]
+        per = sum(m for m, _ in ms) / max(1, sum(c for _, c in ms))
+        results.append({"sort_shape": sh, "tile": tile, "pass_ms": round(per, 5), "passes": passes})
+        log(f"shape {sh} (tile {tile}): {per:.4f} ms per pass")
+    return results
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="c1", choices=["c0", "c1"])
+    ap.add_argument("--n-journeys", type=int, default=None)
+    ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--out", default=CACHE)
+    args = ap.parse_args()
+    import torch
+    from . import cvetl, gen
+    t = time.time()
+    r = gen.make_c1(**({"n_journeys": args.n_journeys} if args.n_journeys else {})) if args.workload == "c1" \
+        else gen.make_c0(**({"n_journeys": args.n_journeys} if args.n_journeys else {}))
+    print(f"[tune] {args.workload}: {r.n} records ({time.time() - t:.1f}s)", file=sys.stderr, flush=True)
+    rec = cvetl.to_device(r)
+    res = sweep_sort_shapes(rec, gen.GRIDS[args.workload], args.reps,
+                            log=lambda m: print(f"[tune] {m}", file=sys.stderr, flush=True))
+    best = min(res, key=lambda x: x["pass_ms"])
+    c = _load()
+    c["entries"] = [e for e in c.get("entries", []) if e.get("workload") != args.workload or e["n"] != r.n]
+    c["entries"].append({"workload": args.workload, "n": r.n, "sort_shape": best["sort_shape"],
+                         "tile": best["tile"], "pass_ms": best["pass_ms"], "sweep": res,
+                         "device": torch.cuda.get_device_name(0)})
+    with open(args.out, "w") as f:
+        json.dump(c, f, indent=1)
+    print(json.dumps({"best": best, "sweep": res}))
+
+
+if __name__ == "__main__":
+    main()

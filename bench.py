@@ -36,7 +36,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c1", choices=["c0", "c1"])
+    ap.add_argument("--workload", default="c1", choices=["c0", "c1", "c2", "c3", "c4"])
+    ap.add_argument("--duration", type=float, default=None, help="c3/c4: seconds of arrivals")
+    ap.add_argument("--shards", type=int, default=115, help="c2: number of shards")
+    ap.add_argument("--total", type=int, default=400_000_000, help="c2: total records")
     ap.add_argument("--n-journeys", type=int, default=None, help="scale the workload down (testing)")
     ap.add_argument("--cpu-sample", type=int, default=40_000_000, help="records in the oracle's timed sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -84,6 +87,151 @@ def cpu_baseline(r, grid, target):
                       f"whole plain path, {dt:.1f}s"}
 
 
+def bench_batched(args):
+    """Batched form (all shards in one set of launches) vs the plain path called
+    once per shard, same resident input, same GPU."""
+    import numpy as np
+    import torch
+    from paper_2305_07454_amd import cvetl, gen
+    dev = torch.device("cuda:0")
+    t = time.time()
+    shards = gen.make_c2(n_shards=args.shards, total=args.total)
+    sizes = [s.n for s in shards]
+    allr = gen.concat(shards)
+    del shards
+    n = allr.n
+    log(f"generated c2: {len(sizes)} shards, {n} records in {time.time() - t:.1f}s")
+    grid = gen.GRIDS["c2"]
+    rec = cvetl.to_device(allr, dev)
+    from paper_2305_07454_amd import tune
+    tune.apply(n)
+    off_h, off_d = cvetl.shard_offsets(sizes, dev)
+    bp, res = cvetl.cv_batch_run(rec, sizes, grid)
+    J, G = res[1]["count"], res[2]["count"]
+    mj = bp.max_journeys
+    del bp
+    torch.cuda.empty_cache()
+    bp = cvetl.BatchPipeline(n, len(sizes), grid, mj, J, max(4096, int(1.25 * G)), dev)
+    for _ in range(args.warmup):
+        bp.run(rec, off_d)
+    torch.cuda.synchronize()
+    assert all(x["status"] == 0 for x in bp.results())
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        bp.run(rec, off_d)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_batched = e0.elapsed_time(e1) / args.steps
+    # plain per-file: one plain pipeline sized for the largest shard, called per shard
+    big = max(sizes)
+    pp = cvetl.Pipeline(big, grid, max_journeys=max(1024, mj), journey_capacity=max(1, J),
+                        group_capacity=max(4096, int(1.25 * G)), device=dev)
+    views = [{k: v[int(off_h[i]):int(off_h[i + 1])] for k, v in rec.items()} for i in range(len(sizes))]
+
+    def per_file():
+        for v in views:
+            if v["journey_id"].numel():
+                pp.run(v)
+
+    per_file()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(args.steps):
+        per_file()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_plain = e0.elapsed_time(e1) / args.steps
+    # identical outputs on the last shard the loop ran
+    i = max(j for j in range(len(sizes)) if sizes[j] > 0)
+    a, b = int(off_h[i]), int(off_h[i + 1])
+    jo = bp.journey_offsets.cpu().numpy()
+    go = bp.group_offsets.cpu().numpy()
+    same = torch.equal(bp.perm[a:b], pp.perm[:b - a]) and torch.equal(bp.feat["step_m"][a:b], pp.feat["step_m"][:b - a])
+    rj = pp.results()[1]["count"]
+    same = same and torch.equal(bp.journeys["distance_m"][int(jo[i]):int(jo[i + 1])], pp.journeys["distance_m"][:rj])
+    rg = pp.results()[2]["count"]
+    same = same and torch.equal(bp.groups["sum_speed"][int(go[i]):int(go[i + 1])], pp.groups["sum_speed"][:rg])
+    assert same, "batched and per-file outputs differ"
+    line = {
+        "metric": "ETL Mrecords/s & % HBM peak (plain vs batched); serving p50/p99 latency",
+        "value": round(n / (ms_batched / 1e3) / 1e6, 3), "unit": "Mrecords/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_batched, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"c2: {len(sizes)} county-day shards, capped Zipf(1.2) sizes {min(sizes)}..{max(sizes)}, "
+                               f"0.001 deg x 1 min, batched in one set of launches", "records": n,
+                   "journeys": J, "groups": G, "path": "batched", "parallelism": "single GPU"},
+        "plain_per_file": {"value": round(n / (ms_plain / 1e3) / 1e6, 3), "ms_per_step": round(ms_plain, 4),
+                           "unit": "Mrecords/s"},
+        "batched_speedup": round(ms_plain / ms_batched, 3),
+        "identical_outputs_checked_shard": i,
+    }
+    s = json.dumps(line)
+    print(s, flush=True)
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(s + "\n")
+
+
+def bench_serving(args):
+    """Serving at a fixed Poisson arrival rate: continuous batching vs one chunk
+    per push on the identical trace; p50/p99 chunk latency and Mrecords/s."""
+    import numpy as np
+    import torch
+    from paper_2305_07454_amd import cvetl, gen, serve
+    skew = args.workload == "c4"
+    t = time.time()
+    pool = gen.make_stream(n_journeys=50_000, heavy_frac=0.01 if skew else 0.0, heavy_share=0.3,
+                           heavy_cap=500_000, config_index=4 if skew else 3)
+    log(f"generated stream pool: {pool.n} records in {time.time() - t:.1f}s")
+    grid = gen.GRIDS[args.workload]
+    if skew:
+        dur = args.duration or 30.0
+        third = dur / 3.0
+        rate = lambda tt: 1000.0 if third <= tt < 2 * third else 200.0  # noqa: E731
+        desc = (f"serving under skew: 1% of journeys (20 Hz, up to 500k points) hold ~30% of records; "
+                f"0.001 deg x 1 min; 200 chunks/s with a 5x burst in the middle third of {dur:.0f}s")
+    else:
+        dur = args.duration or 10.0
+        rate = lambda tt: 200.0  # noqa: E731
+        desc = f"serving: Poisson 200 chunks/s for {dur:.0f}s; 0.005 deg x 5 min"
+    trace = serve.poisson_trace(np.random.default_rng(2024), rate, dur, 10_000, 5_000_000)
+    log(f"trace: {len(trace)} chunks, {sum(s for _, s in trace) / 1e6:.0f} M records")
+    out = {}
+    flushed = {}
+    keep = 40
+    for name, batching in (("batched", True), ("per_chunk", False)):
+        srv = serve.Server(pool, grid, batching=batching, arena_records=24_000_000,
+                           max_journeys=1 << 22, max_groups=(1 << 26) if skew else (1 << 22))
+        chunks = srv.run(trace, keep_first=keep, log=lambda m: log(f"{name}: {m}"))
+        out[name] = serve.latency_stats(chunks, warmup_s=min(2.0, dur / 5))
+        log(f"{name}: {out[name]}")
+        flushed[name] = (srv.flush(1 << 23, (1 << 26) if skew else (1 << 22)), srv.keep)
+        del srv
+        torch.cuda.empty_cache()
+    (ja, ga, ra, rga), ka = flushed["batched"]
+    (jb, gb, rb, rgb), kb = flushed["per_chunk"]
+    same = all(torch.equal(ja[k].view(torch.uint8), jb[k].view(torch.uint8)) for k in ja) and \
+        all(torch.equal(ga[k].view(torch.uint8), gb[k].view(torch.uint8)) for k in ga) and \
+        all(torch.equal(ka[c][k].view(torch.uint8), kb[c][k].view(torch.uint8)) for c in ka for k in ka[c])
+    assert same, "batched and per-chunk serving differ"
+    line = {
+        "metric": "ETL Mrecords/s & % HBM peak (plain vs batched); serving p50/p99 latency",
+        "value": out["batched"]["mrec_per_s"], "unit": "Mrecords/s", "n_gpus": 1,
+        "steps": len(trace), "warmup": 0, "ms_per_step": out["batched"]["p50_ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {desc}", "pool_records": pool.n, "chunks": len(trace),
+                   "path": "served, continuous batching", "parallelism": "single GPU"},
+        "latency_batched": out["batched"], "latency_per_chunk": out["per_chunk"],
+        "identical_outputs": bool(same), "journeys": int(ra["count"]), "groups": int(rga["count"]),
+    }
+    s = json.dumps(line)
+    print(s, flush=True)
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(s + "\n")
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -97,6 +245,10 @@ def main():
     from paper_2305_07454_amd import cvetl
 
     assert torch.cuda.is_available(), "bench needs a GPU"
+    if args.workload == "c2":
+        return bench_batched(args)
+    if args.workload in ("c3", "c4"):
+        return bench_serving(args)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     r, grid, desc = make_workload(args.workload, args.n_journeys)

@@ -211,11 +211,91 @@ cv_status cv_grid_aggregate(const cv_records* sorted, const cv_grid_spec* grid /
                             size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Batched form: many independent problems ("shards", e.g. county-day files of
+ * very uneven size) laid out back to back in one record array and processed
+ * by the same launches as one batch.  shard_offsets [device, n_shards + 1]:
+ * shard s holds records [offsets[s], offsets[s+1]); offsets[0] = 0,
+ * offsets[n_shards] = n, non-decreasing (empty shards allowed); the caller
+ * guarantees this layout.  Every result equals the plain call applied to each
+ * shard on its own: a journey id present in two shards is two journeys,
+ * perm is shard-relative (perm[k] indexes the record within its shard), and
+ * outputs are concatenated in shard order.
+ *   journey_offsets [device, n_shards + 1] out: shard s owns journey rows
+ *                   [journey_offsets[s], journey_offsets[s+1]).
+ *   group_offsets   [device, n_shards + 1] out: likewise for group rows; the
+ *                   batched grid needs a bounded time axis (n_t > 0) and
+ *                   returns CV_ERR_RANGE when shard index and cell key do not
+ *                   fit 63 bits together.
+ * Workspace sizes are those of the plain calls for the total n.
+ * --------------------------------------------------------------------- */
+cv_status cv_batch_sort_records(const cv_records* in, const uint64_t* shard_offsets, uint32_t n_shards,
+                                uint64_t max_journeys, uint32_t* perm, const cv_records_out* sorted,
+                                cv_result* res, void* ws, size_t ws_bytes, void* stream);
+cv_status cv_batch_journey_features(const cv_records* sorted, const uint64_t* shard_offsets, uint32_t n_shards,
+                                    const cv_features* out, void* stream);
+cv_status cv_batch_journey_summary(const cv_records* sorted, const cv_features* feat,
+                                   const uint64_t* shard_offsets, uint32_t n_shards, const cv_journeys* out,
+                                   uint64_t capacity, uint64_t* journey_offsets, cv_result* res, void* ws,
+                                   size_t ws_bytes, void* stream);
+cv_status cv_batch_grid_aggregate(const cv_records* sorted, const uint64_t* shard_offsets, uint32_t n_shards,
+                                  const cv_grid_spec* grid /*[host]*/, const cv_groups* out, uint64_t capacity,
+                                  uint64_t* group_offsets, cv_result* res, void* ws, size_t ws_bytes,
+                                  void* stream);
+
+/* ------------------------------------------------------------------------
+ * Serving form: records arrive in chunks and are pushed in batches (one or
+ * more chunks in arrival order); the open journeys (last point, running
+ * summary, cells of the open time-bin segment) and the group table stay
+ * resident in the caller's device `state` between pushes.
+ *
+ * Every result equals the plain calls applied to the concatenation of all
+ * pushed records in push order (ties in arrival order), provided a journey's
+ * timestamps never go backwards across pushes.  A record older than its
+ * journey's last pushed record is late: flag CV_FLAG_LATE, all-zero
+ * kinematics, counted in its journey's totals and in its cell (never as a new
+ * distinct journey), journey state unchanged.  The distinct-journey flag
+ * remembers up to 16 cells per open (journey, time-bin) segment; a segment
+ * with more sets bit 0 of cv_result.flags (its journey may then be counted
+ * more than once in a cell).
+ *
+ *   cv_stream_state_size  bytes of device state for the capacities (journeys
+ *                         ever seen, groups ever seen, records per push).
+ *   cv_stream_create      [host out] *out: a host handle over `state` (256-byte
+ *                         aligned, caller-owned); initialises it on `stream`.
+ *   cv_stream_push        one batch: features of every record written at the
+ *                         record's position in the batch (input order); res:
+ *                         status, count = journeys in the batch, n_late and
+ *                         n_out_of_grid of the batch, flags.
+ *   cv_stream_flush       journeys in ascending id (first = position in the
+ *                         sorted concatenation) and groups in ascending key;
+ *                         res points to two results: res[0] journeys (count,
+ *                         totals of late and out-of-grid records), res[1] groups.
+ *                         The stream stays usable (flush is a snapshot).
+ *   cv_stream_destroy     frees the host handle (the state is the caller's).
+ * Pushes and flushes of one stream must be ordered on one HIP stream.
+ * --------------------------------------------------------------------- */
+#define CV_FLAG_LATE 0x80u /* serving form: record older than its journey's state */
+typedef struct cv_stream cv_stream;
+cv_status cv_stream_state_size(const cv_grid_spec* grid /*[host]*/, uint64_t max_journeys, uint64_t max_groups,
+                               uint64_t max_batch, size_t* bytes /*[host]*/);
+cv_status cv_stream_create(const cv_grid_spec* grid /*[host]*/, uint64_t max_journeys, uint64_t max_groups,
+                           uint64_t max_batch, void* state, size_t state_bytes, void* stream,
+                           cv_stream** out /*[host]*/);
+cv_status cv_stream_push(cv_stream* st, const cv_records* batch, const cv_features* feat, cv_result* res,
+                         void* stream);
+cv_status cv_stream_flush(cv_stream* st, const cv_journeys* journeys, uint64_t journey_capacity,
+                          const cv_groups* groups, uint64_t group_capacity, cv_result* res, void* stream);
+cv_status cv_stream_destroy(cv_stream* st);
+
+/* ------------------------------------------------------------------------
  * Tuning knobs (process-wide; set by an autotuner, read back by callers).
  *   "sort_shape"   index of the radix-pass tile shape (threads x keys per
  *                  thread) used by every sort; 0 .. "sort_shapes" - 1.
  *   "sort_shapes"  number of compiled shapes (read-only).
  *   "sort_tile"    keys per tile of the current shape (read-only).
+ *   "grid_lds_slots"  LDS hash slots per grid tile: 256, 512 or 1024 (more
+ *                  slots hold more distinct cells per tile before spilling to
+ *                  the HBM table, at the price of fewer resident tiles).
  * Unknown names or out-of-range values return CV_ERR_INVALID_ARGUMENT.
  * --------------------------------------------------------------------- */
 cv_status cv_tuning_set(const char* name /*[host]*/, int64_t value);

@@ -239,6 +239,27 @@ __device__ __forceinline__ u64 mix64(u64 x)
 }
 
 // ---------------------------------------------------------------------------
+// shards (independent problems laid out back to back): offsets[0..S] in
+// records, offsets[0] = 0, non-decreasing; empty shards allowed
+// ---------------------------------------------------------------------------
+// the shard holding record r: the largest s with offsets[s] <= r
+__device__ __forceinline__ u32 shard_of(const u64* __restrict__ off, u32 S, u64 r)
+{
+    u32 lo = 0, hi = S;
+    while (hi - lo > 1) {
+        const u32 mid = (lo + hi) >> 1;
+        if (off[mid] <= r) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ bool shard_start(const u64* __restrict__ off, u32 S, u64 r)
+{
+    return S > 0 && off[shard_of(off, S, r)] == r;
+}
+
+// ---------------------------------------------------------------------------
 // wave64 helpers
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0)); }

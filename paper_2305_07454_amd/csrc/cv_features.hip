@@ -26,7 +26,8 @@ __global__ void __launch_bounds__(FB) k_features(u32 n, const i64* __restrict__ 
                                                  double* __restrict__ o_step, double* __restrict__ o_dt,
                                                  double* __restrict__ o_spd, double* __restrict__ o_acc,
                                                  double* __restrict__ o_brg, double* __restrict__ o_dhd,
-                                                 uint8_t* __restrict__ o_flags)
+                                                 uint8_t* __restrict__ o_flags, const u64* __restrict__ soff,
+                                                 u32 S)
 {
     __shared__ i64 s_jid[FB + 2];
     __shared__ i64 s_ts[FB + 2];
@@ -67,7 +68,7 @@ __global__ void __launch_bounds__(FB) k_features(u32 n, const i64* __restrict__ 
         u32 f = 0;
         if (k >= 0 && k < (long)n) {
             const int qk = j + 1, qp = j;
-            bool head = (k == 0) || (s_jid[qk] != s_jid[qp]);
+            bool head = (k == 0) || (s_jid[qk] != s_jid[qp]) || (S > 1 && shard_start(soff, S, (u64)k));
             if (head) {
                 f = CV_FLAG_FIRST | (s_fin[qk] ? 0u : CV_FLAG_BAD_COORD);
             } else {
@@ -139,7 +140,7 @@ __global__ void __launch_bounds__(FB) k_features(u32 n, const i64* __restrict__ 
 
 }  // namespace
 
-extern "C" cv_status cv_journey_features(const cv_records* sorted, const cv_features* out, void* stream)
+static cv_status features_impl(const cv_records* sorted, const u64* soff, u32 S, const cv_features* out, void* stream)
 {
     if (!sorted || !out || sorted->n >= (1ull << 32)) return CV_ERR_INVALID_ARGUMENT;
     const u64 n = sorted->n;
@@ -152,6 +153,18 @@ extern "C" cv_status cv_journey_features(const cv_records* sorted, const cv_feat
     cvh::TimedScope ts_("features", s);
     hipLaunchKernelGGL(k_features, dim3((unsigned)((n + FB - 1) / FB)), dim3(FB), 0, s, (u32)n, sorted->journey_id,
                        sorted->ts_ms, sorted->lat_deg, sorted->lon_deg, out->step_m, out->dt_s, out->speed_mps,
-                       out->accel_mps2, out->bearing_deg, out->dheading_deg, out->flags);
+                       out->accel_mps2, out->bearing_deg, out->dheading_deg, out->flags, soff, S);
     return cvh::last_launch_status();
+}
+
+extern "C" cv_status cv_journey_features(const cv_records* sorted, const cv_features* out, void* stream)
+{
+    return features_impl(sorted, nullptr, 0, out, stream);
+}
+
+extern "C" cv_status cv_batch_journey_features(const cv_records* sorted, const uint64_t* shard_offsets,
+                                               uint32_t n_shards, const cv_features* out, void* stream)
+{
+    if (n_shards == 0 || !shard_offsets || !cvh::aligned(shard_offsets, 8)) return CV_ERR_INVALID_ARGUMENT;
+    return features_impl(sorted, shard_offsets, n_shards, out, stream);
 }

@@ -26,6 +26,7 @@
 
 #include "cv_device.h"
 #include "cv_host.h"
+#include "cv_gridtab.h"
 #include "cv_radix.h"
 
 using namespace cv;
@@ -35,139 +36,8 @@ namespace {
 constexpr int GB = 256;
 constexpr int GI = 8;
 constexpr int GT = GB * GI;
-constexpr int HALO = 1024;
-constexpr int LHS = 512;
+constexpr int HALO = 512;
 constexpr int LHS_PROBES = 32;
-constexpr int FX_SPD = 149;
-constexpr int CS40 = 5;  // carry-save chunks of 40 bits: 2^24 adds per entry without overflow
-constexpr u64 GEMPTY = ~0ull;
-
-// one 64-byte line per group
-struct GEntry {
-    u64 key;
-    u64 cs[CS40];
-    u32 count, nj, mn, mx;
-};
-static_assert(sizeof(GEntry) == 64, "entry layout");
-
-__device__ __forceinline__ void fx_to_cs40(const Fx192& a, u64 c[CS40])
-{
-    const u64 M = (1ull << 40) - 1;
-    c[0] = a.w[0] & M;
-    c[1] = ((a.w[0] >> 40) | (a.w[1] << 24)) & M;
-    c[2] = (a.w[1] >> 16) & M;
-    c[3] = ((a.w[1] >> 56) | (a.w[2] << 8)) & M;
-    c[4] = a.w[2] >> 32;
-}
-
-__device__ __forceinline__ Fx192 fx_from_cs40(const u64 c[CS40])
-{
-    Fx192 r;
-    fx_zero(r);
-#pragma unroll
-    for (int i = 0; i < CS40; ++i) {
-        Fx192 t = fx_place(c[i], 40 * i);  // c[i] < 2^64: the part beyond bit 191 wraps away
-        fx_add(r, t);
-    }
-    return r;
-}
-
-struct GridMeta {
-    u32 pad0;
-    u32 overflow;   // HBM table full
-    u64 n_out;      // records outside the grid
-    u64 max_key;    // largest key seen
-    u32 key_bits;
-    u32 passes;
-    u32 compact_n;
-    u32 pad;
-    u32 tickets[MAX_PASSES];
-};
-
-struct Spec {
-    double lat0, lon0, dlat, dlon;
-    i64 n_lat, n_lon, t0, bin_ms, tmax;
-};
-
-// floor(a / b) for b > 0: a double estimate corrected by one integer step
-// (exact for |a| < 2^52); wider operands take the integer division.
-__device__ __forceinline__ i64 floor_div64(i64 a, i64 b)
-{
-    if (a > -(1ll << 52) && a < (1ll << 52)) {
-        i64 q = (i64)floor((double)a / (double)b);
-        i64 r = a - q * b;
-        if (r < 0) q -= 1;
-        else if (r >= b) q += 1;
-        return q;
-    }
-    i64 q = a / b;
-    if ((a % b != 0) && ((a < 0) != (b < 0))) q -= 1;
-    return q;
-}
-
-// key (or -1) and time bin of one record; floor of the IEEE quotient
-__device__ __forceinline__ i64 grid_key(const Spec& g, i64 ts, double la, double lo, i64& tb)
-{
-    tb = floor_div64(ts - g.t0, g.bin_ms);
-    if (!isfinite(la) || !isfinite(lo)) return -1;
-    double fy = floor((la - g.lat0) / g.dlat);
-    double fx = floor((lo - g.lon0) / g.dlon);
-    if (!(fy >= 0.0 && fy < (double)g.n_lat && fx >= 0.0 && fx < (double)g.n_lon && tb >= 0 && tb < g.tmax)) return -1;
-    return (tb * g.n_lat + (i64)fy) * g.n_lon + (i64)fx;
-}
-
-__global__ void __launch_bounds__(256) k_grid_clear(GEntry* __restrict__ tab, u64 slots, GridMeta* meta)
-{
-    for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < slots; i += (u64)gridDim.x * blockDim.x) {
-        GEntry e;
-        e.key = GEMPTY;
-        for (int c = 0; c < CS40; ++c) e.cs[c] = 0;
-        e.count = 0;
-        e.nj = 0;
-        e.mn = ~0u;
-        e.mx = 0;
-        tab[i] = e;
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        GridMeta z = {};
-        *meta = z;
-    }
-}
-
-__device__ __forceinline__ void g_merge(GEntry& e, u32 count, u32 nj, const Fx192& sum, u32 mn, u32 mx)
-{
-    u64 c[CS40];
-    fx_to_cs40(sum, c);
-    for (int i = 0; i < CS40; ++i)
-        if (c[i]) __hip_atomic_fetch_add(&e.cs[i], c[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_fetch_add(&e.count, count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (nj) __hip_atomic_fetch_add(&e.nj, nj, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_fetch_min(&e.mn, mn, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_fetch_max(&e.mx, mx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ void g_insert(GEntry* tab, u64 mask, GridMeta* meta, u64 key, u32 count, u32 nj,
-                                         const Fx192& sum, u32 mn, u32 mx)
-{
-    u64 h = mix64(key) & mask;
-    for (u64 probe = 0; probe <= mask; ++probe) {
-        u64 cur = tab[h].key;
-        if (cur == key) {
-            g_merge(tab[h], count, nj, sum, mn, mx);
-            return;
-        }
-        if (cur == GEMPTY) {
-            u64 prev = atomicCAS((unsigned long long*)&tab[h].key, (unsigned long long)GEMPTY, (unsigned long long)key);
-            if (prev == GEMPTY || prev == key) {
-                g_merge(tab[h], count, nj, sum, mn, mx);
-                return;
-            }
-        }
-        h = (h + 1) & mask;
-    }
-    atomicOr(&meta->overflow, 1u);
-}
-
 struct LSlot {
     u64 cs[4];
     u32 count, nj, mn, mx;
@@ -244,6 +114,7 @@ __device__ __forceinline__ void run_seg_scan(RunPart& p, bool head)
 
 // one run's partial into the tile's LDS table; no free slot within the probe
 // limit spills it straight to the HBM table
+template <int LHS>
 __device__ __forceinline__ void run_insert(u64* s_hkey, LSlot* s_h, GEntry* tab, u64 gmask, GridMeta* meta, u64 key,
                                            const RunPart& p)
 {
@@ -272,7 +143,8 @@ __device__ __forceinline__ void run_insert(u64* s_hkey, LSlot* s_h, GEntry* tab,
     g_insert(tab, gmask, meta, key, p.count, p.nj, p.sum, p.mn, p.mx);
 }
 
-__global__ void __launch_bounds__(GB, 2)
+template <int LHS>
+__global__ void __launch_bounds__(GB)
 k_grid_agg(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, const double* __restrict__ lat,
            const double* __restrict__ lon, const float* __restrict__ spd, Spec g, GEntry* __restrict__ tab, u64 gmask,
            GridMeta* meta)
@@ -280,7 +152,7 @@ k_grid_agg(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, const
     constexpr int NQ = HALO + GT;
     __shared__ i64 s_key[NQ];       // keys per record; later the keys of the run-head list
     __shared__ uint8_t s_bits[NQ];
-    __shared__ u32 s_lpos[NQ];      // run-head list: q | first << 30 | segment start << 31
+    __shared__ uint16_t s_lpos[NQ];  // run-head list: q | segment start << 15
     __shared__ float s_spd[GT];
     __shared__ u64 s_hkey[LHS];
     __shared__ LSlot s_h[LHS];
@@ -304,20 +176,19 @@ k_grid_agg(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, const
     }
     // tile records (striped, coalesced): key, segment-start bit, speed
     u64 n_out = 0;
-    for (int i = t; i < GT; i += GB) {
+#pragma unroll
+    for (int ii = 0; ii < GI; ++ii) {
+        const int i = ii * GB + t;
         const u64 r = tile0 + i;
         i64 k = -1;
         uint8_t b = B_SEG;
         float sp = 0.f;
         if (r < n) {
             i64 tb;
-            k = grid_key(g, ts[r], lat[r], lon[r], tb);
+            k = grid_key(g, r, ts[r], lat[r], lon[r], tb);
             n_out += (k < 0);
             sp = spd[r];
-            if (r > 0) {
-                const i64 tbp = floor_div64(ts[r - 1] - g.t0, g.bin_ms);
-                b = ((jid[r] != jid[r - 1]) || (tb != tbp)) ? B_SEG : 0;
-            }
+            b = seg_start(g, jid, ts, r, tb) ? B_SEG : 0;
         }
         s_key[HALO + i] = k;
         s_bits[HALO + i] = b;
@@ -340,11 +211,8 @@ k_grid_agg(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, const
             uint8_t b = B_SEG;
             if (r >= 0) {
                 i64 tb;
-                k = grid_key(g, ts[r], lat[r], lon[r], tb);
-                if (r > 0) {
-                    const i64 tbp = floor_div64(ts[r - 1] - g.t0, g.bin_ms);
-                    b = ((jid[r] != jid[r - 1]) || (tb != tbp)) ? B_SEG : 0;
-                }
+                k = grid_key(g, (u64)r, ts[r], lat[r], lon[r], tb);
+                b = seg_start(g, jid, ts, (u64)r, tb) ? B_SEG : 0;
             }
             s_key[q] = k;
             s_bits[q] = b;
@@ -372,7 +240,7 @@ k_grid_agg(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, const
         u32 tot;
         const u32 e = block_exclusive_sum<GB>(rh ? 1u : 0u, s_tmp, tot);
         const u32 at = s_nlist;
-        if (rh) s_lpos[at + e] = (u32)q | ((s_bits[q] & B_SEG) ? (1u << 31) : 0u);
+        if (rh) s_lpos[at + e] = (uint16_t)(q | ((s_bits[q] & B_SEG) ? 0x8000 : 0));
         __syncthreads();
         if (t == 0) s_nlist = at + tot;
         __syncthreads();
@@ -382,21 +250,21 @@ k_grid_agg(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, const
     // head of its segment has the same key
     for (int e = t; e < L; e += GB) {
         const u32 pe = s_lpos[e];
-        const int q = (int)(pe & 0x7FFFFFFFu);
+        const int q = (int)(pe & 0x7FFFu);
         if (q < HALO) continue;
         const i64 k = s_key[q];
         if (k < 0) continue;
         bool first = true;
-        if (!(pe >> 31)) {
+        if (!(pe & 0x8000u)) {
             int f = e - 1;
             bool closed = false;
             for (; f >= 0; --f) {
                 const u32 pf = s_lpos[f];
-                if (s_key[pf & 0x7FFFFFFFu] == k) {
+                if (s_key[pf & 0x7FFFu] == k) {
                     first = false;
                     break;
                 }
-                if (pf >> 31) {
+                if (pf & 0x8000u) {
                     closed = true;
                     break;
                 }
@@ -406,14 +274,12 @@ k_grid_agg(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, const
                 long rr = (long)tile0 - HALO + lo_bound - 1;
                 while (rr >= 0) {
                     i64 tb;
-                    const i64 kk = grid_key(g, ts[rr], lat[rr], lon[rr], tb);
+                    const i64 kk = grid_key(g, (u64)rr, ts[rr], lat[rr], lon[rr], tb);
                     if (kk == k) {
                         first = false;
                         break;
                     }
-                    if (rr == 0) break;
-                    const i64 tbp = floor_div64(ts[rr - 1] - g.t0, g.bin_ms);
-                    if (jid[rr] != jid[rr - 1] || tb != tbp) break;
+                    if (seg_start(g, jid, ts, (u64)rr, tb)) break;
                     --rr;
                 }
             }
@@ -456,19 +322,19 @@ k_grid_agg(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, const
             const int f0 = __ffsll((long long)H) - 1;
             if (l < f0) run_combine(p, c);
             run_wave_reduce(p);
-            if (l == 0 && open_key >= 0 && p.count) run_insert(s_hkey, s_h, tab, gmask, meta, (u64)open_key, p);
+            if (l == 0 && open_key >= 0 && p.count) run_insert<LHS>(s_hkey, s_h, tab, gmask, meta, (u64)open_key, p);
             RunPart sc = c;
             run_seg_scan(sc, head);
             const bool next_head = (l < WAVE - 1) && ((H >> (l + 1)) & 1ull);
             // key of the run each lane belongs to: the key of its head lane
-            if (l >= f0 && next_head && k >= 0 && sc.count) run_insert(s_hkey, s_h, tab, gmask, meta, (u64)k, sc);
+            if (l >= f0 && next_head && k >= 0 && sc.count) run_insert<LHS>(s_hkey, s_h, tab, gmask, meta, (u64)k, sc);
             const int lh = 63 - __clzll((long long)H);  // last head lane: the run left open
             open_key = __shfl(k, lh, WAVE);
             run_reset(p);
             if (l == WAVE - 1) p = sc;
         }
         run_wave_reduce(p);
-        if (l == 0 && open_key >= 0 && p.count) run_insert(s_hkey, s_h, tab, gmask, meta, (u64)open_key, p);
+        if (l == 0 && open_key >= 0 && p.count) run_insert<LHS>(s_hkey, s_h, tab, gmask, meta, (u64)open_key, p);
     }
     // out-of-grid count (one global atomic per tile, only when non-zero)
 #pragma unroll
@@ -488,118 +354,6 @@ k_grid_agg(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, const
         const Fx192 sum = fx_from_cs(sl.cs);
         g_insert(tab, gmask, meta, key, sl.count, sl.nj, sum, sl.mn, sl.mx);
     }
-}
-
-// each block compacts CSLOTS consecutive slots with one global atomic for its
-// base; the order of the pairs is irrelevant (they are sorted by key next)
-constexpr int CPT = 16;
-constexpr int CSLOTS = 256 * CPT;
-
-__global__ void __launch_bounds__(256) k_grid_compact(const GEntry* __restrict__ tab, u64 slots, GridMeta* meta,
-                                                      u64* __restrict__ ckeys, u32* __restrict__ cvals)
-{
-    __shared__ u32 s_tmp[256 / WAVE];
-    __shared__ u64 s_kmax[256 / WAVE];
-    __shared__ u32 s_base;
-    const u64 s0 = (u64)blockIdx.x * CSLOTS + (u64)threadIdx.x * CPT;
-    u64 k[CPT];
-    u32 c = 0;
-    u64 kmax = 0;
-#pragma unroll
-    for (int i = 0; i < CPT; ++i) {
-        const u64 s = s0 + i;
-        k[i] = s < slots ? tab[s].key : GEMPTY;
-        c += k[i] != GEMPTY;
-        if (k[i] != GEMPTY && k[i] > kmax) kmax = k[i];
-    }
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) {
-        const u64 o = __shfl_xor(kmax, d, WAVE);
-        kmax = o > kmax ? o : kmax;
-    }
-    if (lane_id() == 0) s_kmax[threadIdx.x / WAVE] = kmax;
-    u32 tot;
-    const u32 e = block_exclusive_sum<256>(c, s_tmp, tot);
-    if (threadIdx.x == 0) {
-        s_base = tot ? atomicAdd(&meta->compact_n, tot) : 0u;
-        u64 m = 0;
-        for (int w = 0; w < 256 / WAVE; ++w) m = s_kmax[w] > m ? s_kmax[w] : m;
-        if (m) atomicMax((unsigned long long*)&meta->max_key, (unsigned long long)m);
-    }
-    __syncthreads();
-    u32 pos = s_base + e;
-#pragma unroll
-    for (int i = 0; i < CPT; ++i) {
-        if (k[i] != GEMPTY) {
-            ckeys[pos] = k[i];
-            cvals[pos] = (u32)(s0 + i);
-            ++pos;
-        }
-    }
-}
-
-__global__ void k_grid_bits(GridMeta* meta)
-{
-    if (threadIdx.x != 0) return;
-    u64 mk = meta->max_key;
-    u32 b = mk ? 64u - (u32)__clzll((long long)mk) : 0u;
-    meta->key_bits = b;
-    meta->passes = (b + RADIX_BITS - 1) / RADIX_BITS;
-}
-
-__global__ void __launch_bounds__(256) k_grid_emit(const GEntry* __restrict__ tab, const GridMeta* meta,
-                                                   const u64* __restrict__ K0, const u64* __restrict__ K1,
-                                                   const u32* __restrict__ V0, const u32* __restrict__ V1, u32 cap,
-                                                   i64* __restrict__ o_key, u32* __restrict__ o_cnt,
-                                                   u32* __restrict__ o_nj, double* __restrict__ o_sum,
-                                                   float* __restrict__ o_min, float* __restrict__ o_max,
-                                                   cv_result* res)
-{
-    const u32 G = meta->compact_n;
-    const u32 np = meta->passes;
-    const u32* V = np == 0 ? V0 : ((np & 1) ? V1 : V0);
-    const u64* K = np == 0 ? K0 : ((np & 1) ? K1 : K0);
-    (void)K;
-    const u32 m = G < cap ? G : cap;
-    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
-        const GEntry& e = tab[V[i]];
-        o_key[i] = (i64)e.key;
-        o_cnt[i] = e.count;
-        o_nj[i] = e.nj;
-        o_sum[i] = fx_to_double<FX_SPD>(fx_from_cs40(e.cs));
-        o_min[i] = unord_f32(e.mn);
-        o_max[i] = unord_f32(e.mx);
-    }
-    if (res && blockIdx.x == 0 && threadIdx.x == 0) {
-        cv_result r = {};
-        const bool full = meta->overflow != 0;  // HBM table full: G is only a lower bound
-        const bool over = full || G > cap;
-        r.status = over ? CV_ERR_CAPACITY : CV_OK;
-        r.count = G;
-        if (full) r.required = ((u64)G + 1 > 2ull * cap) ? (u64)G + 1 : 2ull * cap;  // G: a lower bound
-        else if (over) r.required = G;
-        r.n_out_of_grid = meta->n_out;
-        r.key_bits = meta->key_bits;
-        *res = r;
-    }
-}
-
-__global__ void k_grid_empty(cv_result* res)
-{
-    if (threadIdx.x == 0) {
-        cv_result r = {};
-        *res = r;
-    }
-}
-
-// identity-permutation fill used when the group keys need no radix pass
-__global__ void __launch_bounds__(256) k_iota_if_nopass(const GridMeta* meta, const u32* __restrict__ cvals,
-                                                        u32* __restrict__ V0, u32 slots)
-{
-    if (meta->passes != 0) return;
-    u32 G = meta->compact_n;
-    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < G && i < slots; i += gridDim.x * blockDim.x)
-        V0[i] = cvals[i];
 }
 
 struct GridLayout {
@@ -642,6 +396,8 @@ struct GridLayout {
     }
 };
 
+int g_lds_slots = 256;  // LDS hash slots per tile (tuning knob "grid_lds_slots")
+
 bool spec_ok(const cv_grid_spec* g)
 {
     if (!g) return false;
@@ -658,18 +414,19 @@ bool spec_ok(const cv_grid_spec* g)
 
 }  // namespace
 
-extern "C" {
-
-cv_status cv_grid_workspace_size(uint64_t n, const cv_grid_spec* grid, uint64_t capacity, size_t* bytes)
+namespace cv {
+bool set_grid_lds_slots(int v)
 {
-    if (!bytes || n >= (1ull << 32) || capacity >= (1ull << 31) || !spec_ok(grid)) return CV_ERR_INVALID_ARGUMENT;
-    GridLayout L(nullptr, n, capacity);
-    *bytes = L.bytes;
-    return CV_OK;
+    if (v != 256 && v != 512 && v != 1024) return false;
+    g_lds_slots = v;
+    return true;
 }
+int grid_lds_slots() { return g_lds_slots; }
+}  // namespace cv
 
-cv_status cv_grid_aggregate(const cv_records* sorted, const cv_grid_spec* grid, const cv_groups* out,
-                            uint64_t capacity, cv_result* res, void* ws, size_t ws_bytes, void* stream)
+static cv_status grid_impl(const cv_records* sorted, const u64* soff, u32 S, const cv_grid_spec* grid,
+                           const cv_groups* out, uint64_t capacity, u64* go, cv_result* res, void* ws, size_t ws_bytes,
+                           void* stream)
 {
     if (!sorted || !out || sorted->n >= (1ull << 32) || capacity >= (1ull << 31) || !spec_ok(grid))
         return CV_ERR_INVALID_ARGUMENT;
@@ -679,6 +436,7 @@ cv_status cv_grid_aggregate(const cv_records* sorted, const cv_grid_spec* grid, 
     if (!ws || !cvh::aligned(ws, cvh::WS_ALIGN) || ws_bytes < need.bytes) return CV_ERR_WORKSPACE;
     if (n == 0) {
         if (res) hipLaunchKernelGGL(k_grid_empty, dim3(1), dim3(64), 0, s, res);
+        if (go) cvh::fill_u64(go, 0, (u64)S + 1, s);
         return cvh::last_launch_status();
     }
     if (!sorted->journey_id || !sorted->ts_ms || !sorted->lat_deg || !sorted->lon_deg || !sorted->speed_mps)
@@ -697,6 +455,20 @@ cv_status cv_grid_aggregate(const cv_records* sorted, const cv_grid_spec* grid, 
     g.t0 = grid->t0_ms;
     g.bin_ms = grid->bin_ms;
     g.tmax = grid->n_t > 0 ? grid->n_t : (INT64_MAX / (grid->n_lat * grid->n_lon));
+    g.soff = soff;
+    g.S = S;
+    g.kb = 0;
+    if (S > 1) {
+        // cell keys < n_t * n_lat * n_lon; the shard index goes above them
+        const unsigned __int128 cells = (unsigned __int128)grid->n_t * grid->n_lat * grid->n_lon;
+        u32 kb = 0;
+        while (kb < 63 && ((unsigned __int128)1 << kb) < cells) ++kb;
+        u32 sb = 0;
+        while (((u64)1 << sb) < S) ++sb;
+        if (kb + sb > 63) return CV_ERR_RANGE;
+        g.kb = kb;
+    }
+    const u64 kmask = S > 1 ? ((1ull << g.kb) - 1) : ~0ull;
     const u32 nn = (u32)n;
     const u32 slots = (u32)L.slots;
     {
@@ -704,8 +476,16 @@ cv_status cv_grid_aggregate(const cv_records* sorted, const cv_grid_spec* grid, 
         hipLaunchKernelGGL(k_grid_clear, dim3(cvh::grid_for(L.slots, 256, 4096)), dim3(256), 0, s, L.tab, L.slots,
                            L.meta);
         cvh::fill_u32(L.zero_begin, 0u, L.zero_bytes / 4, s);
-        hipLaunchKernelGGL(k_grid_agg, dim3((unsigned)L.tiles), dim3(GB), 0, s, nn, sorted->journey_id, sorted->ts_ms,
-                           sorted->lat_deg, sorted->lon_deg, sorted->speed_mps, g, L.tab, L.slots - 1, L.meta);
+        const dim3 gg((unsigned)L.tiles), gb(GB);
+        if (g_lds_slots >= 1024)
+            hipLaunchKernelGGL((k_grid_agg<1024>), gg, gb, 0, s, nn, sorted->journey_id, sorted->ts_ms,
+                               sorted->lat_deg, sorted->lon_deg, sorted->speed_mps, g, L.tab, L.slots - 1, L.meta);
+        else if (g_lds_slots >= 512)
+            hipLaunchKernelGGL((k_grid_agg<512>), gg, gb, 0, s, nn, sorted->journey_id, sorted->ts_ms,
+                               sorted->lat_deg, sorted->lon_deg, sorted->speed_mps, g, L.tab, L.slots - 1, L.meta);
+        else
+            hipLaunchKernelGGL((k_grid_agg<256>), gg, gb, 0, s, nn, sorted->journey_id, sorted->ts_ms,
+                               sorted->lat_deg, sorted->lon_deg, sorted->speed_mps, g, L.tab, L.slots - 1, L.meta);
     }
     {
         cvh::TimedScope ts_("grid_tail", s);
@@ -722,9 +502,39 @@ cv_status cv_grid_aggregate(const cv_records* sorted, const cv_grid_spec* grid, 
         const u32 cap = (u32)capacity;
         hipLaunchKernelGGL(k_grid_emit, dim3(cvh::grid_for(capacity ? capacity : 1, 256, 4096)), dim3(256), 0, s,
                            L.tab, L.meta, L.K0, L.K1, L.V0, L.V1, cap, out->key, out->count, out->n_journeys,
-                           out->sum_speed, out->min_speed, out->max_speed, res);
+                           out->sum_speed, out->min_speed, out->max_speed, res, kmask);
+        if (go)
+            hipLaunchKernelGGL(k_group_offsets, dim3(cvh::grid_for((u64)S + 1, 256, 64)), dim3(256), 0, s, L.meta,
+                               L.K0, L.K1, S, g.kb, go);
     }
     return cvh::last_launch_status();
+}
+
+
+extern "C" {
+
+cv_status cv_grid_workspace_size(uint64_t n, const cv_grid_spec* grid, uint64_t capacity, size_t* bytes)
+{
+    if (!bytes || n >= (1ull << 32) || capacity >= (1ull << 31) || !spec_ok(grid)) return CV_ERR_INVALID_ARGUMENT;
+    GridLayout L(nullptr, n, capacity);
+    *bytes = L.bytes;
+    return CV_OK;
+}
+
+cv_status cv_grid_aggregate(const cv_records* sorted, const cv_grid_spec* grid, const cv_groups* out,
+                            uint64_t capacity, cv_result* res, void* ws, size_t ws_bytes, void* stream)
+{
+    return grid_impl(sorted, nullptr, 0, grid, out, capacity, nullptr, res, ws, ws_bytes, stream);
+}
+
+cv_status cv_batch_grid_aggregate(const cv_records* sorted, const uint64_t* shard_offsets, uint32_t n_shards,
+                                  const cv_grid_spec* grid, const cv_groups* out, uint64_t capacity,
+                                  uint64_t* group_offsets, cv_result* res, void* ws, size_t ws_bytes, void* stream)
+{
+    if (n_shards == 0 || !shard_offsets || !group_offsets || !cvh::aligned(shard_offsets, 8) ||
+        !cvh::aligned(group_offsets, 8) || !grid || grid->n_t <= 0)
+        return CV_ERR_INVALID_ARGUMENT;
+    return grid_impl(sorted, shard_offsets, n_shards, grid, out, capacity, group_offsets, res, ws, ws_bytes, stream);
 }
 
 }  // extern "C"

@@ -40,7 +40,7 @@ struct SortMeta {
     u32 key_bits;
     u32 passes;
     u32 range_err;
-    u32 dict_bits;
+    u32 shard_bits;
     u32 tickets[2 * MAX_PASSES];
 };
 
@@ -52,7 +52,6 @@ __global__ void k_sort_init(SortMeta* m)
         SortMeta z = {};
         z.tmin_ord = ~0ull;
         z.tmax_ord = 0;
-        z.dict_bits = 64;
         *m = z;
     }
 }
@@ -147,7 +146,7 @@ __global__ void __launch_bounds__(256) k_dict_compact(const u64* __restrict__ ta
     }
 }
 
-__global__ void k_dict_meta(SortMeta* m, u32 max_j, u32 n)
+__global__ void k_dict_meta(SortMeta* m, u32 max_j, u32 n, u32 n_shards)
 {
     if (threadIdx.x != 0) return;
     u32 J = m->list_count + m->has_min;  // distinct ids counted by the compaction
@@ -157,9 +156,11 @@ __global__ void k_dict_meta(SortMeta* m, u32 max_j, u32 n)
     u32 rb = J > 1 ? bit_width64((u64)J - 1) : 0;
     u64 span = n ? (unord_i64(m->tmax_ord) - (u64)unord_i64(m->tmin_ord)) : 0;
     u32 tb = bit_width64(span);
+    const u32 sb = n_shards > 1 ? bit_width64((u64)n_shards - 1) : 0;
     m->rank_bits = rb;
     m->t_bits = tb;
-    u32 kb = rb + tb;
+    m->shard_bits = sb;
+    u32 kb = sb + rb + tb;
     if (kb > 64) {
         m->range_err = 1;
         kb = 0;
@@ -186,7 +187,7 @@ __global__ void __launch_bounds__(256) k_dict_rank(const u64* __restrict__ sorte
 __global__ void __launch_bounds__(256) k_pack_hist(const i64* __restrict__ jid, const i64* __restrict__ ts, u32 n,
                                                    const u64* __restrict__ table, const u32* __restrict__ ranks,
                                                    u64 mask, const SortMeta* m, u64* __restrict__ keys,
-                                                   u32* __restrict__ hist)
+                                                   u32* __restrict__ hist, const u64* __restrict__ soff, u32 S)
 {
     __shared__ u32 s_h[MAX_PASSES * RADIX];
     for (int i = threadIdx.x; i < MAX_PASSES * RADIX; i += blockDim.x) s_h[i] = 0;
@@ -208,7 +209,10 @@ __global__ void __launch_bounds__(256) k_pack_hist(const i64* __restrict__ jid, 
                 const u64 s = dict_find(table, mask, j);
                 r = (s != ~0ull) ? ranks[s] : 0u;
             }
-            if (!bad) key = (tb >= 64 ? 0ull : ((u64)r << tb)) | ((u64)ts[i] - tmin);
+            if (!bad) {
+                key = (tb >= 64 ? 0ull : ((u64)r << tb)) | ((u64)ts[i] - tmin);
+                if (S > 1) key |= (u64)shard_of(soff, S, i) << (m->rank_bits + tb);
+            }
             keys[i] = key;
         }
         const u64 vm = __ballot(valid);
@@ -236,10 +240,12 @@ __global__ void __launch_bounds__(256) k_gather(u32 n, const SortMeta* m, const 
                                                 const float* __restrict__ spd, u32* __restrict__ perm,
                                                 i64* __restrict__ o_jid, i64* __restrict__ o_ts,
                                                 double* __restrict__ o_lat, double* __restrict__ o_lon,
-                                                float* __restrict__ o_spd)
+                                                float* __restrict__ o_spd, const u64* __restrict__ soff, u32 S)
 {
     const u32 np = m->passes;
     const u32 tb = m->t_bits;
+    const u32 rb = m->rank_bits;
+    const u64 rmask = rb >= 64 ? ~0ull : ((1ull << rb) - 1);
     const u32 dn = m->dict_n;
     const bool exact = (m->range_err == 0) && (m->overflow == 0);
     const u64 tmin = (u64)unord_i64(m->tmin_ord);
@@ -249,9 +255,10 @@ __global__ void __launch_bounds__(256) k_gather(u32 n, const SortMeta* m, const 
     for (u32 k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
         u64 key = K[k];
         u32 v = np == 0 ? k : V[k];
-        perm[k] = v;
+        // a shard keeps its records: the output position and its source share the shard
+        perm[k] = S > 1 ? v - (u32)soff[shard_of(soff, S, k)] : v;
         if (o_jid) {
-            u64 r = tb >= 64 ? 0 : (key >> tb);
+            u64 r = tb >= 64 ? 0 : ((key >> tb) & rmask);
             o_jid[k] = (exact && r < dn) ? (i64)(dict_sorted[r] ^ SIGN) : jid[v];
         }
         if (o_ts) o_ts[k] = exact ? (i64)(tmin + (key & tmask)) : ts[v];
@@ -339,19 +346,8 @@ bool valid_ptr8(const void* p) { return p == nullptr || cvh::aligned(p, 8); }
 
 }  // namespace
 
-extern "C" {
-
-cv_status cv_sort_workspace_size(uint64_t n, uint64_t max_journeys, size_t* bytes)
-{
-    if (!bytes || n >= (1ull << 32) || max_journeys >= (1ull << 31)) return CV_ERR_INVALID_ARGUMENT;
-    if (max_journeys == 0) max_journeys = 1;
-    SortLayout L(nullptr, n, max_journeys);
-    *bytes = L.bytes;
-    return CV_OK;
-}
-
-cv_status cv_sort_records(const cv_records* in, uint64_t max_journeys, uint32_t* perm, const cv_records_out* sorted,
-                          cv_result* res, void* ws, size_t ws_bytes, void* stream)
+static cv_status sort_impl(const cv_records* in, const uint64_t* soff, uint32_t S, uint64_t max_journeys, uint32_t* perm,
+                           const cv_records_out* sorted, cv_result* res, void* ws, size_t ws_bytes, void* stream)
 {
     if (!in || in->n >= (1ull << 32) || max_journeys >= (1ull << 31)) return CV_ERR_INVALID_ARGUMENT;
     const u64 n = in->n;
@@ -388,7 +384,7 @@ cv_status cv_sort_records(const cv_records* in, uint64_t max_journeys, uint32_t*
                            L.meta);
         hipLaunchKernelGGL(k_dict_compact, dim3(cvh::grid_for(L.slots, 256, 2048)), dim3(256), 0, s, L.table,
                            L.slots, mj, L.meta, L.dl0);
-        hipLaunchKernelGGL(k_dict_meta, dim3(1), dim3(64), 0, s, L.meta, mj, nn);
+        hipLaunchKernelGGL(k_dict_meta, dim3(1), dim3(64), 0, s, L.meta, mj, nn, S);
         // sort the distinct ids (64-bit, signed order via the flipped sign bit)
         const u32* dn = &L.meta->dict_n;
         radix_hist(L.dl0, mj, dn, MAX_PASSES, nullptr, L.dhist, cvh::grid_for(max_journeys, 256, 512), s);
@@ -398,7 +394,7 @@ cv_status cv_sort_records(const cv_records* in, uint64_t max_journeys, uint32_t*
         hipLaunchKernelGGL(k_dict_rank, dim3(cvh::grid_for(max_journeys, 256, 1024)), dim3(256), 0, s, L.dl0, L.meta,
                            L.table, mask, L.ranks);
         hipLaunchKernelGGL(k_pack_hist, dim3(gs), dim3(256), 0, s, in->journey_id, in->ts_ms, nn, L.table, L.ranks,
-                           mask, L.meta, L.K0, L.hist);
+                           mask, L.meta, L.K0, L.hist, soff, S);
         radix_scan(L.hist, L.offs, MAX_PASSES, s);
     }
     radix_passes(L.K0, L.K1, nullptr, L.V0, L.V1, nn, nullptr, &L.meta->key_bits, MAX_PASSES, L.offs, L.status,
@@ -407,10 +403,45 @@ cv_status cv_sort_records(const cv_records* in, uint64_t max_journeys, uint32_t*
         cvh::TimedScope ts_("gather", s);
         hipLaunchKernelGGL(k_gather, dim3(cvh::grid_for(n, 256, 8192)), dim3(256), 0, s, nn, L.meta, L.K0, L.K1, L.V0,
                            L.V1, L.dl0, in->journey_id, in->ts_ms, in->lat_deg, in->lon_deg, in->speed_mps, perm,
-                           so.journey_id, so.ts_ms, so.lat_deg, so.lon_deg, so.speed_mps);
+                           so.journey_id, so.ts_ms, so.lat_deg, so.lon_deg, so.speed_mps, soff, S);
     }
     if (res) hipLaunchKernelGGL(k_sort_finish, dim3(1), dim3(64), 0, s, L.meta, res);
     return cvh::last_launch_status();
+}
+
+
+namespace cv {
+// the record sort for other translation units of the library (no shards)
+cv_status sort_records_into(const cv_records* in, uint64_t max_journeys, uint32_t* perm, const cv_records_out* sorted,
+                            cv_result* res, void* ws, size_t ws_bytes, hipStream_t stream)
+{
+    return sort_impl(in, nullptr, 0, max_journeys, perm, sorted, res, ws, ws_bytes, (void*)stream);
+}
+}  // namespace cv
+
+extern "C" {
+
+cv_status cv_sort_workspace_size(uint64_t n, uint64_t max_journeys, size_t* bytes)
+{
+    if (!bytes || n >= (1ull << 32) || max_journeys >= (1ull << 31)) return CV_ERR_INVALID_ARGUMENT;
+    if (max_journeys == 0) max_journeys = 1;
+    SortLayout L(nullptr, n, max_journeys);
+    *bytes = L.bytes;
+    return CV_OK;
+}
+
+cv_status cv_sort_records(const cv_records* in, uint64_t max_journeys, uint32_t* perm, const cv_records_out* sorted,
+                          cv_result* res, void* ws, size_t ws_bytes, void* stream)
+{
+    return sort_impl(in, nullptr, 0, max_journeys, perm, sorted, res, ws, ws_bytes, stream);
+}
+
+cv_status cv_batch_sort_records(const cv_records* in, const uint64_t* shard_offsets, uint32_t n_shards,
+                                uint64_t max_journeys, uint32_t* perm, const cv_records_out* sorted, cv_result* res,
+                                void* ws, size_t ws_bytes, void* stream)
+{
+    if (n_shards == 0 || !shard_offsets || !cvh::aligned(shard_offsets, 8)) return CV_ERR_INVALID_ARGUMENT;
+    return sort_impl(in, shard_offsets, n_shards, max_journeys, perm, sorted, res, ws, ws_bytes, stream);
 }
 
 }  // extern "C"

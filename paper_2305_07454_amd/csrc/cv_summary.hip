@@ -41,14 +41,15 @@ struct SumMeta {
 
 __device__ __forceinline__ bool is_head(const i64* jid, u64 r) { return r == 0 || jid[r] != jid[r - 1]; }
 
-__global__ void __launch_bounds__(SB) k_sum_count(const i64* __restrict__ jid, u32 n, u32* __restrict__ tile_cnt)
+__global__ void __launch_bounds__(SB) k_sum_count(const i64* __restrict__ jid, u32 n, u32* __restrict__ tile_cnt,
+                                                  const u64* __restrict__ soff, u32 S)
 {
     __shared__ u32 tmp[SB / WAVE];
     const u64 base = (u64)blockIdx.x * ST;
     u32 c = 0;
     for (int i = threadIdx.x; i < ST; i += SB) {
         u64 r = base + i;
-        if (r < n && is_head(jid, r)) ++c;
+        if (r < n && (is_head(jid, r) || (S > 1 && shard_start(soff, S, r)))) ++c;
     }
     u32 total;
     block_exclusive_sum<SB>(c, tmp, total);
@@ -250,7 +251,8 @@ __global__ void __launch_bounds__(SB) k_sum_reduce(u32 n, const i64* __restrict_
                                                    const float* __restrict__ spd, const double* __restrict__ step,
                                                    const double* __restrict__ dspd, const uint8_t* __restrict__ flags,
                                                    const u32* __restrict__ tile_prefix, u32 cap, Out o,
-                                                   JAcc* __restrict__ acc)
+                                                   JAcc* __restrict__ acc, const u64* __restrict__ soff, u32 S,
+                                                   u64* __restrict__ jo)
 {
     __shared__ u32 s_wh[SB / WAVE];
     const int w = threadIdx.x / WAVE;
@@ -262,7 +264,7 @@ __global__ void __launch_bounds__(SB) k_sum_reduce(u32 n, const i64* __restrict_
     u32 hc = 0;
     for (int i = 0; i < WI; ++i) {
         u64 r = cs + (u64)i * WAVE + l;
-        if (r < ce && (r == 0 || jid[r] != jid[r - 1])) ++hc;
+        if (r < ce && (r == 0 || jid[r] != jid[r - 1] || (S > 1 && shard_start(soff, S, r)))) ++hc;
     }
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) hc += __shfl_xor(hc, d, WAVE);
@@ -290,6 +292,11 @@ __global__ void __launch_bounds__(SB) k_sum_reduce(u32 n, const i64* __restrict_
             x.j = jid[r];
             x.jp = r > 0 ? jid[r - 1] : ~x.j;
             x.jn = r + 1 < n ? jid[r + 1] : ~x.j;
+            if (S > 1) {
+                // a shard start is a journey start even when the id continues
+                if (shard_start(soff, S, r)) x.jp = ~x.j;
+                if (r + 1 < n && shard_start(soff, S, r + 1)) x.jn = ~x.j;
+            }
             x.t = ts[r];
             x.st = step[r];
             x.sp = spd[r];
@@ -330,6 +337,13 @@ __global__ void __launch_bounds__(SB) k_sum_reduce(u32 n, const i64* __restrict_
             o.first[jl] = (u32)r;
             o.tstart[jl] = cur.t;
         }
+        if (h && S > 1 && jo) {
+            // this record opens its shard's first journey: every shard starting
+            // here (empty ones included) begins at journey jl
+            const u32 sh = shard_of(soff, S, r);
+            if (soff[sh] == r)
+                for (int z = (int)sh; z >= 0 && soff[z] == r; --z) jo[z] = jl;
+        }
         if (valid && last && jl < cap) o.tend[jl] = cur.t;
         if (H != 0) {
             const int f0 = __ffsll((long long)H) - 1;
@@ -357,13 +371,14 @@ __global__ void __launch_bounds__(SB) k_sum_reduce(u32 n, const i64* __restrict_
     }
     part_wave_reduce(p);
     if (l == 0) {
-        const bool ends = (ce >= n) || (jid[ce] != jid[ce - 1]);
+        const bool ends = (ce >= n) || (jid[ce] != jid[ce - 1]) || (S > 1 && shard_start(soff, S, ce));
         flush_part(o, acc, cap, open_j, p, open_here && ends);
     }
 }
 
 __global__ void __launch_bounds__(256) k_sum_finalize(const JAcc* __restrict__ acc, const SumMeta* meta, u32 cap,
-                                                      Out o, cv_result* res)
+                                                      Out o, cv_result* res, const u64* __restrict__ soff, u32 S,
+                                                      u64* __restrict__ jo, u32 n)
 {
     u32 J = meta->J;
     u32 m = J < cap ? J : cap;
@@ -378,6 +393,12 @@ __global__ void __launch_bounds__(256) k_sum_finalize(const JAcc* __restrict__ a
         s.w[1] = a.spd[1];
         s.w[2] = a.spd[2];
         write_final(o, j, a.count, a.ndtz, d, s, a.maxs, a.maxd, a.latmin, a.latmax, a.lonmin, a.lonmax);
+    }
+    if (jo && blockIdx.x == 0 && threadIdx.x == 0) {
+        // shards that start at the end of the records hold no journey
+        jo[S] = J;
+        for (int z = (int)S - 1; z >= 0 && soff[z] >= n; --z) jo[z] = J;
+        if (S == 1) jo[0] = 0;
     }
     if (res && blockIdx.x == 0 && threadIdx.x == 0) {
         cv_result r = {};
@@ -415,18 +436,9 @@ struct SumLayout {
 
 }  // namespace
 
-extern "C" {
-
-cv_status cv_summary_workspace_size(uint64_t n, uint64_t capacity, size_t* bytes)
-{
-    if (!bytes || n >= (1ull << 32)) return CV_ERR_INVALID_ARGUMENT;
-    SumLayout L(nullptr, n, capacity);
-    *bytes = L.bytes;
-    return CV_OK;
-}
-
-cv_status cv_journey_summary(const cv_records* sorted, const cv_features* feat, const cv_journeys* out,
-                             uint64_t capacity, cv_result* res, void* ws, size_t ws_bytes, void* stream)
+static cv_status summary_impl(const cv_records* sorted, const cv_features* feat, const u64* soff, u32 S,
+                              const cv_journeys* out, uint64_t capacity, u64* jo, cv_result* res, void* ws,
+                              size_t ws_bytes, void* stream)
 {
     if (!sorted || !feat || !out || sorted->n >= (1ull << 32) || capacity >= (1ull << 32))
         return CV_ERR_INVALID_ARGUMENT;
@@ -436,6 +448,7 @@ cv_status cv_journey_summary(const cv_records* sorted, const cv_features* feat, 
     if (!ws || !cvh::aligned(ws, cvh::WS_ALIGN) || ws_bytes < need.bytes) return CV_ERR_WORKSPACE;
     if (n == 0) {
         if (res) hipLaunchKernelGGL(k_sum_empty, dim3(1), dim3(64), 0, s, res);
+        if (jo) cvh::fill_u64(jo, 0, (u64)S + 1, s);
         return cvh::last_launch_status();
     }
     if (!sorted->journey_id || !sorted->ts_ms || !sorted->lat_deg || !sorted->lon_deg || !sorted->speed_mps ||
@@ -452,15 +465,43 @@ cv_status cv_journey_summary(const cv_records* sorted, const cv_features* feat, 
     const u32 cap = (u32)(capacity < n ? capacity : n);
     const u32 nn = (u32)n;
     cvh::TimedScope ts_("summary", s);
-    hipLaunchKernelGGL(k_sum_count, dim3((unsigned)L.tiles), dim3(SB), 0, s, sorted->journey_id, nn, L.tile_cnt);
+    hipLaunchKernelGGL(k_sum_count, dim3((unsigned)L.tiles), dim3(SB), 0, s, sorted->journey_id, nn, L.tile_cnt, soff, S);
     hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(256), 0, s, L.tile_cnt, (u32)L.tiles, L.meta);
     hipLaunchKernelGGL(k_sum_init, dim3(cvh::grid_for(cap, 256, 2048)), dim3(256), 0, s, L.acc, L.meta, cap);
     hipLaunchKernelGGL(k_sum_reduce, dim3((unsigned)L.tiles), dim3(SB), 0, s, nn, sorted->journey_id, sorted->ts_ms,
                        sorted->lat_deg, sorted->lon_deg, sorted->speed_mps, feat->step_m, feat->speed_mps, feat->flags,
-                       L.tile_cnt, cap, o, L.acc);
+                       L.tile_cnt, cap, o, L.acc, soff, S, jo);
     hipLaunchKernelGGL(k_sum_finalize, dim3(cvh::grid_for(cap, 256, 2048)), dim3(256), 0, s, L.acc, L.meta, cap, o,
-                       res);
+                       res, soff, S, jo, nn);
     return cvh::last_launch_status();
+}
+
+
+extern "C" {
+
+cv_status cv_summary_workspace_size(uint64_t n, uint64_t capacity, size_t* bytes)
+{
+    if (!bytes || n >= (1ull << 32)) return CV_ERR_INVALID_ARGUMENT;
+    SumLayout L(nullptr, n, capacity);
+    *bytes = L.bytes;
+    return CV_OK;
+}
+
+cv_status cv_journey_summary(const cv_records* sorted, const cv_features* feat, const cv_journeys* out,
+                             uint64_t capacity, cv_result* res, void* ws, size_t ws_bytes, void* stream)
+{
+    return summary_impl(sorted, feat, nullptr, 0, out, capacity, nullptr, res, ws, ws_bytes, stream);
+}
+
+cv_status cv_batch_journey_summary(const cv_records* sorted, const cv_features* feat, const uint64_t* shard_offsets,
+                                   uint32_t n_shards, const cv_journeys* out, uint64_t capacity,
+                                   uint64_t* journey_offsets, cv_result* res, void* ws, size_t ws_bytes, void* stream)
+{
+    if (n_shards == 0 || !shard_offsets || !journey_offsets || !cvh::aligned(shard_offsets, 8) ||
+        !cvh::aligned(journey_offsets, 8))
+        return CV_ERR_INVALID_ARGUMENT;
+    return summary_impl(sorted, feat, shard_offsets, n_shards, out, capacity, journey_offsets, res, ws, ws_bytes,
+                        stream);
 }
 
 }  // extern "C"

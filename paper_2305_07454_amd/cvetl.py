@@ -119,6 +119,29 @@ def lib():
         L.cv_grid_aggregate.argtypes = [ctypes.POINTER(CvRecords), ctypes.POINTER(CvGridSpec),
                                         ctypes.POINTER(CvGroups), U64, P, P, ctypes.c_size_t, P]
         L.cv_grid_aggregate.restype = S
+        U32 = ctypes.c_uint32
+        L.cv_batch_sort_records.argtypes = [ctypes.POINTER(CvRecords), P, U32, U64, P, ctypes.POINTER(CvRecordsOut),
+                                            P, P, ctypes.c_size_t, P]
+        L.cv_batch_sort_records.restype = S
+        L.cv_batch_journey_features.argtypes = [ctypes.POINTER(CvRecords), P, U32, ctypes.POINTER(CvFeatures), P]
+        L.cv_batch_journey_features.restype = S
+        L.cv_batch_journey_summary.argtypes = [ctypes.POINTER(CvRecords), ctypes.POINTER(CvFeatures), P, U32,
+                                               ctypes.POINTER(CvJourneys), U64, P, P, P, ctypes.c_size_t, P]
+        L.cv_batch_journey_summary.restype = S
+        L.cv_batch_grid_aggregate.argtypes = [ctypes.POINTER(CvRecords), P, U32, ctypes.POINTER(CvGridSpec),
+                                              ctypes.POINTER(CvGroups), U64, P, P, P, ctypes.c_size_t, P]
+        L.cv_batch_grid_aggregate.restype = S
+        L.cv_stream_state_size.argtypes = [ctypes.POINTER(CvGridSpec), U64, U64, U64, SZ]
+        L.cv_stream_state_size.restype = S
+        L.cv_stream_create.argtypes = [ctypes.POINTER(CvGridSpec), U64, U64, U64, P, ctypes.c_size_t, P,
+                                       ctypes.POINTER(ctypes.c_void_p)]
+        L.cv_stream_create.restype = S
+        L.cv_stream_push.argtypes = [P, ctypes.POINTER(CvRecords), ctypes.POINTER(CvFeatures), P, P]
+        L.cv_stream_push.restype = S
+        L.cv_stream_flush.argtypes = [P, ctypes.POINTER(CvJourneys), U64, ctypes.POINTER(CvGroups), U64, P, P]
+        L.cv_stream_flush.restype = S
+        L.cv_stream_destroy.argtypes = [P]
+        L.cv_stream_destroy.restype = S
         L.cv_tuning_set.argtypes = [ctypes.c_char_p, ctypes.c_int64]
         L.cv_tuning_set.restype = S
         L.cv_tuning_get.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64)]
@@ -372,3 +395,142 @@ class Pipeline:
     def results(self):
         """Read the three device result words (synchronises)."""
         return [read_result(r) for r in self.res]
+
+
+def shard_offsets(sizes, device="cuda"):
+    """Host sizes -> (host offsets numpy, device offsets tensor)."""
+    off = np.zeros(len(sizes) + 1, dtype=np.uint64)
+    np.cumsum(np.asarray(sizes, dtype=np.uint64), out=off[1:])
+    return off, torch.from_numpy(off.view(np.int64)).to(device)
+
+
+class BatchPipeline:
+    """Preallocated buffers for the batched form: many shards in one set of
+    launches.  `run()` only enqueues; offsets and results are read afterwards."""
+
+    def __init__(self, n, n_shards, grid, max_journeys, journey_capacity, group_capacity, device="cuda"):
+        L = lib()
+        self.n, self.S, self.grid, self.device = int(n), int(n_shards), grid, device
+        self.max_journeys = int(max_journeys)
+        self.jcap, self.gcap = int(journey_capacity), int(group_capacity)
+        self.perm = torch.empty(self.n, dtype=torch.int32, device=device)
+        self.sorted = empty_records(self.n, device)
+        self.feat = {k: torch.empty(self.n, dtype=dt, device=device) for k, dt in FEATURE_FIELDS}
+        self.journeys = {k: torch.empty(self.jcap, dtype=dt, device=device) for k, dt in JOURNEY_FIELDS}
+        self.groups = {k: torch.empty(self.gcap, dtype=dt, device=device) for k, dt in GROUP_FIELDS}
+        self.journey_offsets = torch.empty(self.S + 1, dtype=torch.int64, device=device)
+        self.group_offsets = torch.empty(self.S + 1, dtype=torch.int64, device=device)
+        self.spec = _spec_struct(grid)
+        self.ws_sort = workspace(_size(L.cv_sort_workspace_size, self.n, self.max_journeys), device)
+        self.ws_sum = workspace(_size(L.cv_summary_workspace_size, self.n, self.jcap), device)
+        self.ws_grid = workspace(_size(L.cv_grid_workspace_size, self.n, ctypes.byref(self.spec), self.gcap), device)
+        self.res = [new_result(device) for _ in range(3)]
+        self._so = CvRecordsOut(*(_ptr(self.sorted[k]) for k, _ in RECORD_FIELDS))
+        self._fs = CvFeatures(*(_ptr(self.feat[k]) for k, _ in FEATURE_FIELDS))
+        self._js = CvJourneys(*(_ptr(self.journeys[k]) for k, _ in JOURNEY_FIELDS))
+        self._gs = CvGroups(*(_ptr(self.groups[k]) for k, _ in GROUP_FIELDS))
+
+    def run(self, rec, offsets_dev, stream=None):
+        L = lib()
+        n = int(rec["journey_id"].numel())
+        assert n <= self.n and offsets_dev.numel() == self.S + 1
+        s = _stream(stream)
+        off = _ptr(offsets_dev)
+        _check(L.cv_batch_sort_records(ctypes.byref(_records_struct(rec)), off, self.S, self.max_journeys,
+                                       _ptr(self.perm), ctypes.byref(self._so), _ptr(self.res[0]), _ptr(self.ws_sort),
+                                       self.ws_sort.numel(), s), "cv_batch_sort_records")
+        srt = CvRecords(*(_ptr(self.sorted[k]) for k, _ in RECORD_FIELDS), n)
+        _check(L.cv_batch_journey_features(ctypes.byref(srt), off, self.S, ctypes.byref(self._fs), s),
+               "cv_batch_journey_features")
+        _check(L.cv_batch_journey_summary(ctypes.byref(srt), ctypes.byref(self._fs), off, self.S,
+                                          ctypes.byref(self._js), self.jcap, _ptr(self.journey_offsets),
+                                          _ptr(self.res[1]), _ptr(self.ws_sum), self.ws_sum.numel(), s),
+               "cv_batch_journey_summary")
+        _check(L.cv_batch_grid_aggregate(ctypes.byref(srt), off, self.S, ctypes.byref(self.spec),
+                                         ctypes.byref(self._gs), self.gcap, _ptr(self.group_offsets),
+                                         _ptr(self.res[2]), _ptr(self.ws_grid), self.ws_grid.numel(), s),
+               "cv_batch_grid_aggregate")
+
+    def results(self):
+        return [read_result(r) for r in self.res]
+
+
+def cv_batch_run(rec, sizes, grid, max_journeys=None, journey_capacity=None, group_capacity=None):
+    """Batched form with self-sizing capacities (one retry on capacity)."""
+    n = int(rec["journey_id"].numel())
+    dev = rec["journey_id"].device
+    off_h, off_d = shard_offsets(sizes, dev)
+    assert int(off_h[-1]) == n
+    mj = max_journeys or max(1, min(n, 1 << 20))
+    jc = journey_capacity or max(1, min(n, 1 << 20))
+    gc = group_capacity or max(1, min(n, 1 << 22))
+    for _ in range(3):
+        bp = BatchPipeline(n, len(sizes), grid, mj, jc, gc, dev)
+        bp.run(rec, off_d)
+        r = bp.results()
+        if all(x["status"] == CV_OK for x in r):
+            return bp, r
+        for x in r:
+            if x["status"] not in (CV_OK, CV_ERR_CAPACITY):
+                raise CvError(x["status"], "cv_batch_run (device)")
+        if r[0]["status"] == CV_ERR_CAPACITY:
+            mj = max(2 * mj, r[0]["required"])
+        if r[1]["status"] == CV_ERR_CAPACITY:
+            jc = max(jc, r[1]["required"])
+        if r[2]["status"] == CV_ERR_CAPACITY:
+            gc = max(2 * gc, r[2]["required"])
+    raise CvError(CV_ERR_CAPACITY, "cv_batch_run")
+
+
+class Stream:
+    """Serving form: device-resident open journeys and group table across pushes."""
+
+    def __init__(self, grid, max_journeys, max_groups, max_batch, device="cuda", stream=None):
+        L = lib()
+        self.device = device
+        self.max_batch = int(max_batch)
+        self.spec = _spec_struct(grid)
+        need = _size(L.cv_stream_state_size, ctypes.byref(self.spec), int(max_journeys), int(max_groups),
+                     self.max_batch)
+        self.state = workspace(need, device)
+        self.handle = ctypes.c_void_p()
+        _check(L.cv_stream_create(ctypes.byref(self.spec), int(max_journeys), int(max_groups), self.max_batch,
+                                  _ptr(self.state), self.state.numel(), _stream(stream), ctypes.byref(self.handle)),
+               "cv_stream_create")
+
+    def push(self, rec, feat=None, res=None, stream=None):
+        """Enqueue one batch; returns (features in input order, device result)."""
+        n = int(rec["journey_id"].numel())
+        dev = rec["journey_id"].device
+        if feat is None:
+            feat = {k: torch.empty(n, dtype=dt, device=dev) for k, dt in FEATURE_FIELDS}
+        if res is None:
+            res = new_result(dev)
+        _check(lib().cv_stream_push(self.handle, ctypes.byref(_records_struct(rec)), ctypes.byref(_feat_struct(feat)),
+                                    _ptr(res), _stream(stream)), "cv_stream_push")
+        return feat, res
+
+    def flush(self, journey_capacity, group_capacity, stream=None):
+        jc, gc = int(journey_capacity), int(group_capacity)
+        jo = {k: torch.empty(max(jc, 1), dtype=dt, device=self.device) for k, dt in JOURNEY_FIELDS}
+        go = {k: torch.empty(max(gc, 1), dtype=dt, device=self.device) for k, dt in GROUP_FIELDS}
+        res = torch.zeros(128, dtype=torch.uint8, device=self.device)
+        js = CvJourneys(*(_ptr(jo[k]) for k, _ in JOURNEY_FIELDS))
+        gs = CvGroups(*(_ptr(go[k]) for k, _ in GROUP_FIELDS))
+        _check(lib().cv_stream_flush(self.handle, ctypes.byref(js), jc, ctypes.byref(gs), gc, _ptr(res),
+                                     _stream(stream)), "cv_stream_flush")
+        rj, rg = read_result(res[:64]), read_result(res[64:])
+        for r in (rj, rg):
+            _check(r["status"], "cv_stream_flush (device)")
+        return {k: v[:rj["count"]] for k, v in jo.items()}, {k: v[:rg["count"]] for k, v in go.items()}, rj, rg
+
+    def close(self):
+        if self.handle:
+            lib().cv_stream_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

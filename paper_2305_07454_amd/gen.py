@@ -286,6 +286,56 @@ def make_c2(seed=None, n_shards=115, total=400_000_000, lo=10_000, hi=20_000_000
     return shards
 
 
+def make_stream(seed=None, n_journeys=2000, median=1500.0, sigma=1.0, cap=86_400, heavy_frac=0.0,
+                heavy_share=0.3, heavy_cap=500_000, heavy_period_ms=50, span_s=None, config_index=3) -> Records:
+    """A stream of records in feed (event-time) order: journeys start uniformly
+    over a window so that many are open at once; 1 Hz samples, and optionally
+    a small fraction of heavy journeys sampled at 20 Hz that hold a given share
+    of all records (the skewed stream)."""
+    rng = rng_for(config_index, seed)
+    L = c1_lengths(rng, n_journeys, median=median, sigma=sigma, cap=cap)
+    period = np.full(n_journeys, 1000, dtype=np.int64)
+    if heavy_frac > 0:
+        nh = max(1, int(round(heavy_frac * n_journeys)))
+        hv = rng.choice(n_journeys, size=nh, replace=False)
+        light = int(L.sum() - L[hv].sum())
+        want = int(heavy_share / (1.0 - heavy_share) * light)
+        w = rng.lognormal(0.0, 1.0, size=nh)
+        Lh = np.minimum(np.maximum(np.rint(w / w.sum() * want), 1), heavy_cap).astype(np.int64)
+        L[hv] = Lh
+        period[hv] = heavy_period_ms
+    ids = journey_ids(rng, n_journeys)
+    dur = (L - 1) * period
+    if span_s is None:
+        span_s = int(np.median(dur) // 1000) + 1
+    start = T0_MS + 1000 * rng.integers(0, max(1, span_s), size=n_journeys).astype(np.int64)
+    parts = []
+    for per in np.unique(period):
+        sel = np.nonzero(period == per)[0]
+        ts, lat, lon, _ = walks(rng, L[sel], period_ms=int(per), start_ms=start[sel])
+        parts.append((np.repeat(ids[sel], L[sel]), ts, lat, lon))
+    jid = np.concatenate([p[0] for p in parts])
+    ts = np.concatenate([p[1] for p in parts])
+    lat = np.concatenate([p[2] for p in parts])
+    lon = np.concatenate([p[3] for p in parts])
+    spd = speeds(rng, ts.shape[0])
+    order = np.lexsort((rng.random(ts.shape[0]), ts))
+    return Records(jid[order], ts[order], lat[order], lon[order], spd[order],
+                   dict(n_journeys=n_journeys, heavy_frac=heavy_frac))
+
+
+def chunk_sizes(rng, n, lo, hi):
+    """Consecutive chunk sizes, log-uniform on [lo, hi], covering n records."""
+    out = []
+    left = n
+    while left > 0:
+        s = int(np.exp(rng.uniform(np.log(lo), np.log(hi))))
+        s = max(1, min(s, left))
+        out.append(s)
+        left -= s
+    return out
+
+
 def make(config: str, seed=None, **kw):
     if config == "c0":
         return make_c0(seed, **kw)

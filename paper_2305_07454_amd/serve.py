@@ -1,0 +1,209 @@
+"""Serving loop over the device-resident stream state.
+
+Chunks of records arrive as a Poisson process.  A chunk is admitted in FIFO
+order when the device arena -- a ring of record slots reserved for chunks in
+flight -- has room for it (admission by free device memory).  Its columns are
+copied host-to-device on a copy stream.  The compute stream runs one push at
+a time.  With continuous batching, every chunk that is copied and waiting when
+the compute stream frees up joins the next push (chunks that arrive while a
+push runs overlap with it on the device).  With the per-chunk policy each push
+takes one chunk.  Features go back device-to-host on a third stream.  A chunk's
+latency is the time its features are in host memory minus its scheduled
+arrival.
+
+The host pool is replayed in cycles: cycle c shifts journey ids by c * 2^40,
+so every cycle brings new journeys (each with its timestamps in order, which
+is the arrival-order precondition) over the same grid cells and time bins.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import math
+import time
+
+import numpy as np
+import torch
+
+from . import cvetl
+
+JID_SHIFT = 1 << 40
+
+
+@dataclasses.dataclass
+class Chunk:
+    cid: int
+    src: int          # first pool record
+    n: int
+    cycle: int
+    arrival: float    # seconds after start
+    slot: int = -1    # first ring record
+    copy_ev: object = None
+    done_ev: object = None
+    t_done: float = -1.0
+
+
+def poisson_trace(rng, rate_fn, duration_s, sizes_lo, sizes_hi):
+    """Arrival times of a non-homogeneous Poisson process (thinning) and
+    log-uniform chunk sizes."""
+    lam_max = max(rate_fn(t) for t in np.linspace(0, duration_s, 1001))
+    t, out = 0.0, []
+    while True:
+        t += rng.exponential(1.0 / lam_max)
+        if t >= duration_s:
+            break
+        if rng.random() * lam_max <= rate_fn(t):
+            size = int(math.exp(rng.uniform(math.log(sizes_lo), math.log(sizes_hi))))
+            out.append((t, size))
+    return out
+
+
+class Server:
+    def __init__(self, pool, grid, batching=True, arena_records=16_000_000, max_journeys=1 << 21,
+                 max_groups=1 << 23, device="cuda"):
+        self.dev = torch.device(device)
+        self.grid = grid
+        self.batching = batching
+        self.A = int(arena_records)
+        self.pool_n = pool.n
+        # pinned host pool
+        self.h = {k: torch.from_numpy(np.ascontiguousarray(c)).pin_memory()
+                  for (k, _), c in zip(cvetl.RECORD_FIELDS, pool.columns())}
+        # device arena (inputs and features) and pinned feature landing zone
+        self.ring = {k: torch.empty(self.A, dtype=dt, device=self.dev) for k, dt in cvetl.RECORD_FIELDS}
+        self.fring = {k: torch.empty(self.A, dtype=dt, device=self.dev) for k, dt in cvetl.FEATURE_FIELDS}
+        self.hout = {k: torch.empty(self.A, dtype=dt).pin_memory() for k, dt in cvetl.FEATURE_FIELDS}
+        self.s_copy = torch.cuda.Stream(self.dev)
+        self.s_comp = torch.cuda.Stream(self.dev)
+        self.s_back = torch.cuda.Stream(self.dev)
+        self.stream = cvetl.Stream(grid, max_journeys, max_groups, self.A, device=self.dev, stream=self.s_comp)
+        self.res = cvetl.new_result(self.dev)
+        self.head = 0          # next free ring record
+        self.used = 0          # records reserved
+        self.keep = {}         # cid -> features copied out for checking
+
+    def _copy_in(self, c):
+        with torch.cuda.stream(self.s_copy):
+            a, b = c.src, c.src + c.n
+            for k, _ in cvetl.RECORD_FIELDS:
+                self.ring[k][c.slot:c.slot + c.n].copy_(self.h[k][a:b], non_blocking=True)
+            if c.cycle:
+                self.ring["journey_id"][c.slot:c.slot + c.n] += c.cycle * JID_SHIFT
+            c.copy_ev = torch.cuda.Event()
+            c.copy_ev.record(self.s_copy)
+
+    def _launch(self, batch):
+        a = batch[0].slot
+        n = sum(c.n for c in batch)
+        assert a + n <= self.A
+        for c in batch:
+            self.s_comp.wait_event(c.copy_ev)
+        rec = {k: v[a:a + n] for k, v in self.ring.items()}
+        feat = {k: v[a:a + n] for k, v in self.fring.items()}
+        self.stream.push(rec, feat=feat, res=self.res, stream=self.s_comp)
+        ev = torch.cuda.Event()
+        ev.record(self.s_comp)
+        self.s_back.wait_event(ev)
+        with torch.cuda.stream(self.s_back):
+            for k in self.fring:
+                self.hout[k][a:a + n].copy_(self.fring[k][a:a + n], non_blocking=True)
+        done = torch.cuda.Event()
+        done.record(self.s_back)
+        for c in batch:
+            c.done_ev = done
+        return ev
+
+    def run(self, trace, keep_first=0, log=None):
+        """Serve the trace (list of (arrival_s, size)); returns per-chunk records."""
+        chunks, src, cyc = [], 0, 0
+        for i, (t, size) in enumerate(trace):
+            size = min(size, self.pool_n, self.A)
+            if src + size > self.pool_n:
+                src, cyc = 0, cyc + 1
+            chunks.append(Chunk(i, src, size, cyc, t))
+            src += size
+        pending = collections.deque(chunks)
+        copying = collections.deque()     # admitted, H2D issued
+        inflight = collections.deque()    # admitted, not yet completed (ring order)
+        comp_ev = None
+        launched = collections.deque()    # chunks launched, awaiting features on host
+        t0 = time.perf_counter()
+        next_log = 1.0
+        while pending or copying or launched:
+            now = time.perf_counter() - t0
+            # admission (FIFO) by free arena space
+            while pending and pending[0].arrival <= now:
+                c = pending[0]
+                slot = self._reserve_fifo(c.n, inflight)
+                if slot < 0:
+                    break
+                c.slot = slot
+                self._copy_in(c)
+                pending.popleft()
+                copying.append(c)
+                inflight.append(c)
+            # launch when the compute stream is free
+            if copying and (comp_ev is None or comp_ev.query()):
+                ready = []
+                while copying and copying[0].copy_ev.query():
+                    c = copying[0]
+                    if ready and (c.slot != ready[-1].slot + ready[-1].n):
+                        break          # not contiguous in the ring (wrapped): next push
+                    ready.append(copying.popleft())
+                    if not self.batching:
+                        break
+                if ready:
+                    comp_ev = self._launch(ready)
+                    launched.extend(ready)
+            # completions (FIFO)
+            while launched and launched[0].done_ev.query():
+                c = launched.popleft()
+                c.t_done = time.perf_counter() - t0
+                if c.cid < keep_first:
+                    self.keep[c.cid] = {k: v[c.slot:c.slot + c.n].clone() for k, v in self.hout.items()}
+                inflight.popleft()
+            if log and now >= next_log:
+                log(f"t={now:.1f}s admitted={len(chunks) - len(pending)} done={sum(1 for c in chunks if c.t_done >= 0)}"
+                    f" queue={len(pending)}")
+                next_log += 1.0
+            if not (copying or launched) and pending and pending[0].arrival > now:
+                time.sleep(min(0.0005, pending[0].arrival - now))
+        torch.cuda.synchronize()
+        return chunks
+
+    def _reserve_fifo(self, n, inflight):
+        """First ring record of a contiguous free range of n records after the
+        newest chunk in flight (the ring is freed in FIFO order), or -1."""
+        if n > self.A:
+            raise ValueError(f"chunk of {n} records exceeds the arena of {self.A}")
+        if not inflight:
+            return 0
+        lo = inflight[0].slot
+        newest = inflight[-1]
+        tail = newest.slot + newest.n
+        if newest.slot >= lo:              # occupied [lo, tail): free [tail, A) and [0, lo)
+            if tail + n <= self.A:
+                return tail
+            return 0 if n <= lo else -1
+        return tail if tail + n <= lo else -1   # wrapped: free [tail, lo)
+
+    def flush(self, jcap, gcap):
+        with torch.cuda.stream(self.s_comp):
+            out = self.stream.flush(jcap, gcap, stream=self.s_comp)
+        torch.cuda.synchronize()
+        return out
+
+
+def latency_stats(chunks, warmup_s=0.0):
+    lat = np.array([c.t_done - c.arrival for c in chunks if c.arrival >= warmup_s and c.t_done >= 0])
+    recs = sum(c.n for c in chunks if c.arrival >= warmup_s)
+    t_first = min((c.arrival for c in chunks if c.arrival >= warmup_s), default=0.0)
+    t_last = max((c.t_done for c in chunks), default=1.0)
+    return {
+        "chunks": int(lat.size),
+        "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+        "p95_ms": round(float(np.percentile(lat, 95)) * 1e3, 3),
+        "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+        "max_ms": round(float(lat.max()) * 1e3, 3),
+        "mrec_per_s": round(recs / max(t_last - t_first, 1e-9) / 1e6, 3),
+    }

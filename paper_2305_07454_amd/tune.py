@@ -37,6 +37,8 @@ def apply(n: int) -> int | None:
     if best is None:
         return None
     cvetl.cv_tuning_set("sort_shape", best["sort_shape"])
+    if "grid_lds_slots" in best:
+        cvetl.cv_tuning_set("grid_lds_slots", best["grid_lds_slots"])
     return best["sort_shape"]
 
 
@@ -66,6 +68,29 @@ def sweep_sort_shapes(rec, grid, reps=5, log=print):
     return results
 
 
+def sweep_grid_slots(srt, grid, reps=5, log=print):
+    """Time the grid aggregation kernel for every LDS table size on sorted records."""
+    import torch
+    from . import cvetl
+    results = []
+    for slots in (256, 512, 1024):
+        cvetl.cv_tuning_set("grid_lds_slots", slots)
+        groups, rg = cvetl.cv_grid_aggregate(srt, grid)
+        cap = max(4096, int(1.25 * rg["count"]))
+        out = {k: torch.empty(cap, dtype=dt, device=srt["journey_id"].device) for k, dt in cvetl.GROUP_FIELDS}
+        torch.cuda.synchronize()
+        cvetl.cv_timing_reset()
+        cvetl.cv_timing_enable(True)
+        for _ in range(reps):
+            cvetl.cv_grid_aggregate(srt, grid, capacity=cap, sync=False, out=out)
+        torch.cuda.synchronize()
+        cvetl.cv_timing_enable(False)
+        ms, c = cvetl.cv_timing_read("grid_agg")
+        results.append({"grid_lds_slots": slots, "grid_agg_ms": round(ms / max(c, 1), 5)})
+        log(f"grid_lds_slots {slots}: {ms / max(c, 1):.4f} ms")
+    return results
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="c1", choices=["c0", "c1"])
@@ -83,14 +108,20 @@ def main():
     res = sweep_sort_shapes(rec, gen.GRIDS[args.workload], args.reps,
                             log=lambda m: print(f"[tune] {m}", file=sys.stderr, flush=True))
     best = min(res, key=lambda x: x["pass_ms"])
+    cvetl.cv_tuning_set("sort_shape", best["sort_shape"])
+    perm, srt, _ = cvetl.cv_sort_records(rec)
+    gres = sweep_grid_slots(srt, gen.GRIDS[args.workload], args.reps,
+                            log=lambda m: print(f"[tune] {m}", file=sys.stderr, flush=True))
+    gbest = min(gres, key=lambda x: x["grid_agg_ms"])
     c = _load()
     c["entries"] = [e for e in c.get("entries", []) if e.get("workload") != args.workload or e["n"] != r.n]
     c["entries"].append({"workload": args.workload, "n": r.n, "sort_shape": best["sort_shape"],
                          "tile": best["tile"], "pass_ms": best["pass_ms"], "sweep": res,
+                         "grid_lds_slots": gbest["grid_lds_slots"], "grid_sweep": gres,
                          "device": torch.cuda.get_device_name(0)})
     with open(args.out, "w") as f:
         json.dump(c, f, indent=1)
-    print(json.dumps({"best": best, "sweep": res}))
+    print(json.dumps({"best": best, "sweep": res, "grid": gres}))
 
 
 if __name__ == "__main__":

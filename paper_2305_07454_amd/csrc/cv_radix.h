@@ -44,8 +44,11 @@ void radix_hist(const u64* keys, u32 n_max, const u32* n_dev, int passes, const 
                 int grid, hipStream_t s);
 void radix_scan(const u32* hist, u32* offs, int passes, hipStream_t s);
 //                When `timed`, pass p is bracketed as timing family "sort_pass<p>".
+//                pack [device, 2] (nullable): {ib, p0}: from pass p0 on, key
+//                words hold (key >> 8 p0) << ib | index and no value arrays
+//                are used (p0 = 0: the input keys are packed already).
 void radix_passes(u64* k0, u64* k1, const u32* v_first, u32* v0, u32* v1, u32 n_max, const u32* n_dev,
                   const u32* bits_dev, int passes, const u32* offs, u64* status, u32* tickets, hipStream_t s,
-                  bool timed = false);
+                  bool timed = false, const u32* pack = nullptr);
 
 }  // namespace cv

@@ -58,7 +58,7 @@ __global__ void __launch_bounds__(SORT_BLOCK)
 k_radix_pass(const u64* __restrict__ keys_in, const u32* __restrict__ vals_in, u64* __restrict__ keys_out,
              u32* __restrict__ vals_out, u32 n_max, const u32* __restrict__ n_dev, int pass,
              const u32* __restrict__ bits_dev, const u32* __restrict__ digit_offs, u64* __restrict__ status,
-             u32* __restrict__ ticket)
+             u32* __restrict__ ticket, const u32* __restrict__ pack)
 {
     constexpr int NW = SORT_BLOCK / WAVE;
     constexpr int SORT_TILE = SORT_BLOCK * SORT_ITEMS;
@@ -71,9 +71,14 @@ k_radix_pass(const u64* __restrict__ keys_in, const u32* __restrict__ vals_in, u
     __shared__ u32 s_tmp[NW];
     __shared__ u32 s_tile;
 
-    const int shift = pass * RADIX_BITS;
-    if (bits_dev && shift >= (int)*bits_dev) return;
+    if (bits_dev && pass * RADIX_BITS >= (int)*bits_dev) return;
     const u32 n = n_dev ? *n_dev : n_max;
+    // packing: from pass p0 on, a key word holds (key >> 8 p0) << ib | index
+    const u32 ib = pack ? pack[0] : 0u;
+    const int p0 = pack ? (int)pack[1] : 1 << 20;
+    const bool pin = pass >= p0;           // input words are packed
+    const bool pout = pass + 1 >= p0;      // output words are packed
+    const int shift = pin ? (int)ib + (pass - p0) * RADIX_BITS : pass * RADIX_BITS;
     if (threadIdx.x == 0) s_tile = atomicAdd(ticket, 1u);
     for (int i = threadIdx.x; i < NW * RADIX; i += SORT_BLOCK) (&s_whist[0][0])[i] = 0;
     __syncthreads();
@@ -92,7 +97,7 @@ k_radix_pass(const u64* __restrict__ keys_in, const u32* __restrict__ vals_in, u
         u64 idx = wbase + (u64)i * WAVE + l;
         bool ok = idx < n;
         key[i] = ok ? keys_in[idx] : ~0ull;
-        val[i] = ok ? (vals_in ? vals_in[idx] : (u32)idx) : 0u;
+        val[i] = (ok && !pin) ? (vals_in ? vals_in[idx] : (u32)idx) : 0u;
     }
 #pragma unroll
     for (int i = 0; i < SORT_ITEMS; ++i) {
@@ -165,17 +170,26 @@ k_radix_pass(const u64* __restrict__ keys_in, const u32* __restrict__ vals_in, u
             u32 d = (u32)(key[i] >> shift) & (RADIX - 1);
             u32 pos = s_start[d] + s_whist[w][d] + rnk[i];
             s_keys[pos] = key[i];
-            s_vals[pos] = val[i];
+            if (!pin) s_vals[pos] = val[i];
         }
     }
     __syncthreads();
     const u32 tvalid = (u32)((n - tile_base) < (u64)SORT_TILE ? (n - tile_base) : (u64)SORT_TILE);
+    // staged words keep their input form; the pass that starts packing packs
+    // them on the way out
+    const int drop = p0 * RADIX_BITS;
     for (u32 j = threadIdx.x; j < tvalid; j += SORT_BLOCK) {
-        u64 k = s_keys[j];
-        u32 d = (u32)(k >> shift) & (RADIX - 1);
-        u32 g = s_gshift[d] + j;
-        keys_out[g] = k;
-        vals_out[g] = s_vals[j];
+        const u64 k = s_keys[j];
+        const u32 d = (u32)(k >> shift) & (RADIX - 1);
+        const u32 g = s_gshift[d] + j;
+        if (pin) {
+            keys_out[g] = k;
+        } else if (pout) {
+            keys_out[g] = ((drop >= 64 ? 0ull : (k >> drop)) << ib) | (u64)s_vals[j];
+        } else {
+            keys_out[g] = k;
+            vals_out[g] = s_vals[j];
+        }
     }
 }
 
@@ -205,10 +219,11 @@ int g_shape = 0;
 
 template <int B, int I>
 void launch_pass(u64 tiles, hipStream_t s, const u64* kin, const u32* vin, u64* kout, u32* vout, u32 n_max,
-                 const u32* n_dev, int p, const u32* bits_dev, const u32* offs, u64* status, u32* ticket)
+                 const u32* n_dev, int p, const u32* bits_dev, const u32* offs, u64* status, u32* ticket,
+                 const u32* pack)
 {
     hipLaunchKernelGGL((k_radix_pass<B, I>), dim3((unsigned)(tiles ? tiles : 1)), dim3(B), 0, s, kin, vin, kout, vout,
-                       n_max, n_dev, p, bits_dev, offs, status, ticket);
+                       n_max, n_dev, p, bits_dev, offs, status, ticket, pack);
 }
 
 }  // namespace
@@ -231,7 +246,7 @@ int sort_min_tile()
 
 void radix_passes(u64* k0, u64* k1, const u32* v_first, u32* v0, u32* v1, u32 n_max, const u32* n_dev,
                   const u32* bits_dev, int passes, const u32* offs, u64* status, u32* tickets, hipStream_t s,
-                  bool timed)
+                  bool timed, const u32* pack)
 {
     static const char* const names[MAX_PASSES] = {"sort_pass0", "sort_pass1", "sort_pass2", "sort_pass3",
                                                   "sort_pass4", "sort_pass5", "sort_pass6", "sort_pass7"};
@@ -245,12 +260,15 @@ void radix_passes(u64* k0, u64* k1, const u32* v_first, u32* v0, u32* v1, u32 n_
         u32* vout = (p & 1) ? v0 : v1;
         cvh::TimedScope ts_(timed ? names[p] : nullptr, s);
         const u32* o = offs + p * RADIX;
+        auto go = [&](auto launch) {
+            launch(tiles, s, kin, vin, kout, vout, n_max, n_dev, p, bits_dev, o, status, tickets + p, pack);
+        };
         switch (sh) {
-        case 0: launch_pass<256, 16>(tiles, s, kin, vin, kout, vout, n_max, n_dev, p, bits_dev, o, status, tickets + p); break;
-        case 1: launch_pass<256, 32>(tiles, s, kin, vin, kout, vout, n_max, n_dev, p, bits_dev, o, status, tickets + p); break;
-        case 2: launch_pass<512, 8>(tiles, s, kin, vin, kout, vout, n_max, n_dev, p, bits_dev, o, status, tickets + p); break;
-        case 3: launch_pass<512, 16>(tiles, s, kin, vin, kout, vout, n_max, n_dev, p, bits_dev, o, status, tickets + p); break;
-        default: launch_pass<1024, 8>(tiles, s, kin, vin, kout, vout, n_max, n_dev, p, bits_dev, o, status, tickets + p); break;
+        case 0: go(launch_pass<256, 16>); break;
+        case 1: go(launch_pass<256, 32>); break;
+        case 2: go(launch_pass<512, 8>); break;
+        case 3: go(launch_pass<512, 16>); break;
+        default: go(launch_pass<1024, 8>); break;
         }
     }
 }

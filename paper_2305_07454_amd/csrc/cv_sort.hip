@@ -41,6 +41,8 @@ struct SortMeta {
     u32 passes;
     u32 range_err;
     u32 shard_bits;
+    u32 ib;   // index bits of a packed key word
+    u32 p0;   // first pass whose input words are packed (ib and p0 adjacent: the radix passes read both)
     u32 tickets[2 * MAX_PASSES];
 };
 
@@ -167,6 +169,12 @@ __global__ void k_dict_meta(SortMeta* m, u32 max_j, u32 n, u32 n_shards)
     }
     m->key_bits = kb;
     m->passes = (kb + RADIX_BITS - 1) / RADIX_BITS;
+    // Packed words (key >> 8 p0) << ib | index replace the (key, index) pairs
+    // from pass p0 on; p0 is the first digit boundary from which the rest of
+    // the key and the index fit one word.  p0 < passes whenever p0 > 0.
+    const u32 ib = n > 1 ? bit_width64((u64)n - 1) : 1u;
+    m->ib = ib;
+    m->p0 = kb + ib > 64 ? (kb + ib - 64 + RADIX_BITS - 1) / RADIX_BITS : 0u;
 }
 
 __global__ void __launch_bounds__(256) k_dict_rank(const u64* __restrict__ sorted_list, const SortMeta* m,
@@ -195,6 +203,8 @@ __global__ void __launch_bounds__(256) k_pack_hist(const i64* __restrict__ jid, 
     const u32 tb = m->t_bits;
     const u32 np = m->passes;
     const bool bad = m->range_err != 0;
+    const u32 ib = m->ib;
+    const bool packed = m->p0 == 0;
     const u64 tmin = (u64)unord_i64(m->tmin_ord);
     const int l = lane_id();
     const u64 nw = (u64)gridDim.x * (blockDim.x / WAVE);
@@ -213,7 +223,7 @@ __global__ void __launch_bounds__(256) k_pack_hist(const i64* __restrict__ jid, 
                 key = (tb >= 64 ? 0ull : ((u64)r << tb)) | ((u64)ts[i] - tmin);
                 if (S > 1) key |= (u64)shard_of(soff, S, i) << (m->rank_bits + tb);
             }
-            keys[i] = key;
+            keys[i] = packed ? ((key << ib) | i) : key;
         }
         const u64 vm = __ballot(valid);
         const int lead = __ffsll((long long)vm) - 1;
@@ -232,9 +242,9 @@ __global__ void __launch_bounds__(256) k_pack_hist(const i64* __restrict__ jid, 
         if (s_h[i]) atomicAdd(&hist[i], s_h[i]);
 }
 
+// The final words are packed: (key >> 8 p0) << ib | source index.
 __global__ void __launch_bounds__(256) k_gather(u32 n, const SortMeta* m, const u64* __restrict__ K0,
-                                                const u64* __restrict__ K1, const u32* __restrict__ V0,
-                                                const u32* __restrict__ V1, const u64* __restrict__ dict_sorted,
+                                                const u64* __restrict__ K1, const u64* __restrict__ dict_sorted,
                                                 const i64* __restrict__ jid, const i64* __restrict__ ts,
                                                 const double* __restrict__ lat, const double* __restrict__ lon,
                                                 const float* __restrict__ spd, u32* __restrict__ perm,
@@ -245,23 +255,30 @@ __global__ void __launch_bounds__(256) k_gather(u32 n, const SortMeta* m, const 
     const u32 np = m->passes;
     const u32 tb = m->t_bits;
     const u32 rb = m->rank_bits;
+    const u32 ib = m->ib;
+    const u32 drop = m->p0 * RADIX_BITS;
     const u64 rmask = rb >= 64 ? ~0ull : ((1ull << rb) - 1);
+    const u64 imask = (1ull << ib) - 1;
     const u32 dn = m->dict_n;
     const bool exact = (m->range_err == 0) && (m->overflow == 0);
+    // the journey rank survives packing when its bits lie above the dropped digits
+    const bool rank_in_key = exact && drop <= tb;
+    const u32 rshift = ib + tb - drop;
+    // the time offset survives only when nothing was dropped
+    const bool ts_in_key = exact && drop == 0;
     const u64 tmin = (u64)unord_i64(m->tmin_ord);
     const u64 tmask = tb >= 64 ? ~0ull : ((1ull << tb) - 1);
-    const u64* K = np == 0 ? K0 : ((np & 1) ? K1 : K0);
-    const u32* V = (np & 1) ? V1 : V0;
+    const u64* K = (np & 1) ? K1 : K0;
     for (u32 k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
-        u64 key = K[k];
-        u32 v = np == 0 ? k : V[k];
+        const u64 w = K[k];
+        const u32 v = (u32)(w & imask);
         // a shard keeps its records: the output position and its source share the shard
         perm[k] = S > 1 ? v - (u32)soff[shard_of(soff, S, k)] : v;
         if (o_jid) {
-            u64 r = tb >= 64 ? 0 : ((key >> tb) & rmask);
-            o_jid[k] = (exact && r < dn) ? (i64)(dict_sorted[r] ^ SIGN) : jid[v];
+            const u64 r = rshift >= 64 ? 0ull : ((w >> rshift) & rmask);
+            o_jid[k] = (rank_in_key && r < dn) ? (i64)(dict_sorted[r] ^ SIGN) : jid[v];
         }
-        if (o_ts) o_ts[k] = exact ? (i64)(tmin + (key & tmask)) : ts[v];
+        if (o_ts) o_ts[k] = ts_in_key ? (i64)(tmin + ((w >> ib) & tmask)) : ts[v];
         if (o_lat) o_lat[k] = lat[v];
         if (o_lon) o_lon[k] = lon[v];
         if (o_spd) o_spd[k] = spd[v];
@@ -398,11 +415,11 @@ static cv_status sort_impl(const cv_records* in, const uint64_t* soff, uint32_t 
         radix_scan(L.hist, L.offs, MAX_PASSES, s);
     }
     radix_passes(L.K0, L.K1, nullptr, L.V0, L.V1, nn, nullptr, &L.meta->key_bits, MAX_PASSES, L.offs, L.status,
-                 L.meta->tickets, s, /*timed=*/true);
+                 L.meta->tickets, s, /*timed=*/true, &L.meta->ib);
     {
         cvh::TimedScope ts_("gather", s);
-        hipLaunchKernelGGL(k_gather, dim3(cvh::grid_for(n, 256, 8192)), dim3(256), 0, s, nn, L.meta, L.K0, L.K1, L.V0,
-                           L.V1, L.dl0, in->journey_id, in->ts_ms, in->lat_deg, in->lon_deg, in->speed_mps, perm,
+        hipLaunchKernelGGL(k_gather, dim3(cvh::grid_for(n, 256, 8192)), dim3(256), 0, s, nn, L.meta, L.K0, L.K1, L.dl0,
+                           in->journey_id, in->ts_ms, in->lat_deg, in->lon_deg, in->speed_mps, perm,
                            so.journey_id, so.ts_ms, so.lat_deg, so.lon_deg, so.speed_mps, soff, S);
     }
     if (res) hipLaunchKernelGGL(k_sort_finish, dim3(1), dim3(64), 0, s, L.meta, res);

@@ -46,7 +46,25 @@ def parse():
     ap.add_argument("--out", default=None, help="also write the JSON line to this file")
     ap.add_argument("--sort-shape", type=int, default=None,
                     help="radix tile shape index (default: the tuning cache, else the library default)")
+    ap.add_argument("--copy-calibration", type=int, default=None, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB five times (the known-size reference "
+                         "for the HBM byte counters) and exit")
     return ap.parse_args()
+
+
+def copy_calibration(mib):
+    """A plain device-to-device copy of a known size: read mib MiB, write mib MiB
+    per launch.  Profiled with FETCH_SIZE / WRITE_SIZE, it gives the factor
+    between those counters and bytes moved."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.rand(n, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_per_launch": {"read": n * 4, "write": n * 4}, "launches": 5}))
 
 
 def make_workload(name, n_journeys):
@@ -245,6 +263,8 @@ def main():
     from paper_2305_07454_amd import cvetl
 
     assert torch.cuda.is_available(), "bench needs a GPU"
+    if args.copy_calibration:
+        return copy_calibration(args.copy_calibration)
     if args.workload == "c2":
         return bench_batched(args)
     if args.workload in ("c3", "c4"):
@@ -306,14 +326,14 @@ def main():
     # dominant kernel: the radix scatter passes that run (digit below the key width)
     key_bits = rs["key_bits"]
     passes = (key_bits + 7) // 8
+    p0 = rs["packed_pass"]
     pass_ms, pass_launches, alg_bytes = 0.0, 0, 0.0
     per_pass = []
     for p in range(passes):
         ms, cnt_l = cvetl.cv_timing_read(f"sort_pass{p}")
         pass_ms += ms
         pass_launches += cnt_l
-        b = n * (20 if p == 0 else 24)           # pass 0 generates the index values
-        alg_bytes += b * cnt_l
+        alg_bytes += n * pass_bytes(p, p0) * cnt_l
         per_pass.append(round(ms / max(cnt_l, 1), 4))
     avg_ms = pass_ms / max(pass_launches, 1)
     bytes_per_launch = alg_bytes / max(pass_launches, 1)
@@ -325,11 +345,11 @@ def main():
     stages["sort_passes"] = round(pass_ms / args.steps, 4)
 
     traffic = None
-    tfile = os.path.join(ROOT, "profiles", "radix_pass_c1_traffic.json")
+    tfile = os.path.join(ROOT, "profiles", "radix_pass_c1_traffic.md")
     if args.workload == "c1" and args.n_journeys is None and os.path.exists(tfile):
-        t = json.load(open(tfile))
-        if t.get("kernel_source_sha") == _kernel_sha():
-            traffic = t.get("bytes_per_launch")
+        t = read_traffic(tfile)
+        if t.get("kernel_source_sha") == _kernel_sha() and t.get("sort_shape") == str(cvetl.cv_tuning_get("sort_shape")):
+            traffic = float(t["traffic_bytes_per_launch"])
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -361,6 +381,7 @@ def main():
         "cpu_baseline": cpu,
         "stages_ms_per_step": stages,
         "key_bits": key_bits,
+        "packed_from_pass": p0,
         "wall_s_timed_region": round(wall, 3),
     }
     s = json.dumps(line)
@@ -368,6 +389,28 @@ def main():
     if args.out:
         with open(args.out, "w") as f:
             f.write(s + "\n")
+
+
+def pass_bytes(p, p0):
+    """Algorithmic bytes per record of radix pass p when passes p0.. move packed
+    (key | index) words: read and write 8-byte words, plus 4-byte index values
+    before packing (pass 0 generates its indices instead of reading them)."""
+    if p >= p0:
+        return 16
+    rd = 8 + (0 if p == 0 else 4)
+    wr = 8 + (0 if p + 1 >= p0 else 4)
+    return rd + wr
+
+
+def read_traffic(path):
+    """`key: value` lines of a traffic summary (HBM bytes per radix pass launch
+    from the FETCH_SIZE / WRITE_SIZE counters, scaled by a copy of known size)."""
+    out = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(("#", "|", " ", "`")):
+            k, v = line.split(":", 1)
+            out[k.strip()] = v.strip()
+    return out
 
 
 def _kernel_sha():

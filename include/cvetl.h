@@ -141,7 +141,9 @@ typedef struct {
     uint64_t n_out_of_grid; /* records outside the grid (grid call)             */
     uint64_t n_late;        /* reserved for streaming, 0                        */
     uint64_t key_bits;      /* bits of the packed sort key (sort call)          */
-    uint64_t reserved[2];
+    uint64_t packed_pass;   /* sort call: first radix pass that moves one word
+                               (key high digits | record index) per record    */
+    uint64_t reserved;
 } cv_result;
 
 uint32_t cv_abi_version(void);
@@ -218,8 +220,8 @@ cv_status cv_grid_aggregate(const cv_records* sorted, const cv_grid_spec* grid /
  * offsets[n_shards] = n, non-decreasing (empty shards allowed); the caller
  * guarantees this layout.  Every result equals the plain call applied to each
  * shard on its own: a journey id present in two shards is two journeys,
- * perm is shard-relative (perm[k] indexes the record within its shard), and
- * outputs are concatenated in shard order.
+ * perm and a journey's `first` are shard-relative (they index records within
+ * their shard), and outputs are concatenated in shard order.
  *   journey_offsets [device, n_shards + 1] out: shard s owns journey rows
  *                   [journey_offsets[s], journey_offsets[s+1]).
  *   group_offsets   [device, n_shards + 1] out: likewise for group rows; the

@@ -259,6 +259,32 @@ __device__ __forceinline__ bool shard_start(const u64* __restrict__ off, u32 S, 
     return S > 0 && off[shard_of(off, S, r)] == r;
 }
 
+// first k in [0, S] with off[k] >= a (S when none)
+__device__ __forceinline__ u32 shard_lower_bound(const u64* __restrict__ off, u32 S, u64 a)
+{
+    u32 lo = 0, hi = S;
+    while (lo < hi) {
+        const u32 mid = (lo + hi) >> 1;
+        if (off[mid] < a) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Shard starts among the records [a, a + 64) as a lane mask, for a wave that
+// walks consecutive windows: k (wave-uniform) is the first shard whose start is
+// >= a and moves past the window; at_end tells whether a shard starts at a + 64.
+__device__ __forceinline__ u64 shard_starts_in(const u64* __restrict__ off, u32 S, u32& k, u64 a, bool& at_end)
+{
+    u64 m = 0;
+    while (k < S && off[k] < a + 64) {
+        m |= 1ull << (off[k] - a);
+        ++k;
+    }
+    at_end = k < S && off[k] == a + 64;
+    return m;
+}
+
 // ---------------------------------------------------------------------------
 // wave64 helpers
 // ---------------------------------------------------------------------------

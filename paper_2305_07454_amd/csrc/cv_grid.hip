@@ -174,24 +174,36 @@ k_grid_agg(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, const
         z.mx = 0;
         s_h[i] = z;
     }
-    // tile records (striped, coalesced): key, segment-start bit, speed
+    // tile records (striped, coalesced): key, segment-start bit, speed.  A
+    // record's predecessor is the lane below (lane 0 reads its own); shards are
+    // found from the tile's first one forward.
     u64 n_out = 0;
+    const u32 sh0 = g.S > 1 ? shard_of(g.soff, g.S, tile0) : 0u;
+    const int lane = lane_id();
 #pragma unroll
     for (int ii = 0; ii < GI; ++ii) {
         const int i = ii * GB + t;
         const u64 r = tile0 + i;
-        i64 k = -1;
-        uint8_t b = B_SEG;
+        i64 k = -1, j = 0, tb = 0;
         float sp = 0.f;
+        u32 sh = sh0;
         if (r < n) {
-            i64 tb;
-            k = grid_key(g, r, ts[r], lat[r], lon[r], tb);
+            if (g.S > 1)
+                while (sh + 1 < g.S && g.soff[sh + 1] <= r) ++sh;
+            j = jid[r];
+            k = grid_key_in(g, sh, ts[r], lat[r], lon[r], tb);
             n_out += (k < 0);
             sp = spd[r];
-            b = seg_start(g, jid, ts, r, tb) ? B_SEG : 0;
         }
+        i64 jp = __shfl_up(j, 1, WAVE);
+        i64 tbp = __shfl_up(tb, 1, WAVE);
+        if (lane == 0 && r < n && r > 0) {
+            jp = jid[r - 1];
+            tbp = floor_div64(ts[r - 1] - g.t0, g.bin_ms);
+        }
+        const bool seg = r == 0 || j != jp || tb != tbp || (g.S > 1 && g.soff[sh] == r);
         s_key[HALO + i] = k;
-        s_bits[HALO + i] = b;
+        s_bits[HALO + i] = (r >= n || seg) ? B_SEG : 0;
         s_spd[i] = sp;
     }
     if (t == 0) s_flag = 0;

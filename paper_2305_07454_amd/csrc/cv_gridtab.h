@@ -88,9 +88,9 @@ __device__ __forceinline__ i64 floor_div64(i64 a, i64 b)
     return q;
 }
 
-// key (or -1) and time bin of record r; floor of the IEEE quotient.  In the
-// batched form the record's shard index is placed above the cell key.
-__device__ __forceinline__ i64 grid_key(const Spec& g, u64 r, i64 ts, double la, double lo, i64& tb)
+// key (or -1) and time bin of a record of shard sh; floor of the IEEE
+// quotient.  In the batched form the shard index is placed above the cell key.
+__device__ __forceinline__ i64 grid_key_in(const Spec& g, u32 sh, i64 ts, double la, double lo, i64& tb)
 {
     tb = floor_div64(ts - g.t0, g.bin_ms);
     if (!isfinite(la) || !isfinite(lo)) return -1;
@@ -98,8 +98,14 @@ __device__ __forceinline__ i64 grid_key(const Spec& g, u64 r, i64 ts, double la,
     double fx = floor((lo - g.lon0) / g.dlon);
     if (!(fy >= 0.0 && fy < (double)g.n_lat && fx >= 0.0 && fx < (double)g.n_lon && tb >= 0 && tb < g.tmax)) return -1;
     i64 k = (tb * g.n_lat + (i64)fy) * g.n_lon + (i64)fx;
-    if (g.S > 1) k |= (i64)((u64)shard_of(g.soff, g.S, r) << g.kb);
+    if (g.S > 1) k |= (i64)((u64)sh << g.kb);
     return k;
+}
+
+// the same for record r (its shard found by binary search)
+__device__ __forceinline__ i64 grid_key(const Spec& g, u64 r, i64 ts, double la, double lo, i64& tb)
+{
+    return grid_key_in(g, g.S > 1 ? shard_of(g.soff, g.S, r) : 0u, ts, la, lo, tb);
 }
 
 // first record of a (journey, time-bin) segment (shard starts included)

@@ -293,6 +293,7 @@ __global__ void k_sort_finish(const SortMeta* m, cv_result* res)
     r.count = m->J;
     r.required = m->overflow ? m->J : 0;
     r.key_bits = m->key_bits;
+    r.packed_pass = m->p0;
     *res = r;
 }
 

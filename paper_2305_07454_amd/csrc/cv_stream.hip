@@ -18,7 +18,10 @@
 //   5. one thread per batch journey folds its records into the row's running
 //      summary (exact fixed point) and the resident group table, deciding the
 //      distinct-journey flag from the cells seen in the journey's open
-//      (journey, time-bin) segment, which the row carries across pushes.
+//      (journey, time-bin) segment, which the row carries across pushes: the
+//      first KCELLS cells in the row, further ones in a device-wide visit map
+//      of (row, group key) pairs (a group key names its time bin, so entries
+//      of closed segments never match again).
 // Flush: journey rows in ascending id and the group table in ascending key.
 #include <hip/hip_runtime.h>
 
@@ -39,7 +42,40 @@ cv_status sort_records_into(const cv_records* in, uint64_t max_journeys, uint32_
 
 namespace {
 
-constexpr int KCELLS = 16;  // distinct cells remembered for a journey's open segment
+constexpr int KCELLS = 16;  // distinct cells remembered in a journey's row for its open segment
+constexpr u32 VEMPTY = 0xFFFFFFFFu;
+
+// visit map entry: cell visited by row `slot` in a segment whose first KCELLS
+// cells filled the row's list
+struct Visit {
+    u64 key;
+    u32 slot;
+    u32 pad;
+};
+
+// true when (slot, key) was not in the map (and is now).  Only the thread that
+// folds row `slot` writes entries of that slot, so an entry is claimed by a
+// compare-and-swap of its slot word and completed by a plain store of its key.
+// Returns true with *full set when the map has no room.
+__device__ __forceinline__ bool visit_insert(Visit* vm, u64 vmask, u32 slot, u64 key, bool* full)
+{
+    u64 h = mix64(key ^ ((u64)slot * 0x9E3779B97F4A7C15ull)) & vmask;
+    for (u64 probe = 0; probe <= vmask; ++probe) {
+        u32 cur = __hip_atomic_load(&vm[h].slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (cur == VEMPTY) {
+            cur = atomicCAS(&vm[h].slot, VEMPTY, slot);
+            if (cur == VEMPTY) {
+                __hip_atomic_store(&vm[h].key, key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                return true;
+            }
+        }
+        if (cur == slot && __hip_atomic_load(&vm[h].key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == key)
+            return false;
+        h = (h + 1) & vmask;
+    }
+    *full = true;
+    return true;
+}
 constexpr u64 JEMPTY = 0x8000000000000000ull;
 constexpr u32 FLAG_LATE = 0x80u;
 constexpr u32 FLAG_PRED_CARRIED = 0x100u;  // internal: predecessor is the row's last point
@@ -64,7 +100,7 @@ struct JRow {
 struct StreamMeta {
     u32 Jb;             // journeys in the current batch
     u32 jt_full;        // journey table full (sticky)
-    u32 cell_overflow;  // a segment visited more than KCELLS cells (sticky)
+    u32 cell_overflow;  // the visit map ran full: distinct-journey counts may be high (sticky)
     u32 pad;
     u64 batch_late, batch_out;
     u64 total_records, total_late, total_out;
@@ -368,7 +404,8 @@ __global__ void __launch_bounds__(256) k_st_fold(u32 n, const i64* __restrict__ 
                                                  const u32* __restrict__ bslot, JRow* __restrict__ rows,
                                                  const double* __restrict__ fs_step, const double* __restrict__ fs_v,
                                                  const double* __restrict__ fs_b, const uint8_t* __restrict__ fs_flags,
-                                                 Spec g, GEntry* __restrict__ tab, u64 gmask)
+                                                 Spec g, GEntry* __restrict__ tab, u64 gmask, Visit* __restrict__ vm,
+                                                 u64 vmask)
 {
     __shared__ u64 s_red[2][4];
     const u32 Jb = m->Jb;
@@ -448,14 +485,14 @@ __global__ void __launch_bounds__(256) k_st_fold(u32 n, const i64* __restrict__ 
 #pragma unroll
                 for (int c = 0; c < KCELLS; ++c) seen |= ((u32)c < ncell) && cells[c] == (u64)key;
                 if (!seen) {
-                    first = true;
                     if (ncell < KCELLS) {
+                        first = true;
 #pragma unroll
                         for (int c = 0; c < KCELLS; ++c)
                             if ((u32)c == ncell) cells[c] = (u64)key;
                         ++ncell;
                     } else {
-                        overflow = true;
+                        first = visit_insert(vm, vmask, slot, (u64)key, &overflow);
                     }
                 }
             }
@@ -643,6 +680,7 @@ struct cv_stream {
     u64* jkeys;
     JRow* rows;
     GEntry* tab;
+    Visit* visits;
     // per-push scratch
     void* sort_ws;
     size_t sort_ws_bytes;
@@ -664,11 +702,15 @@ struct cv_stream {
 
 namespace {
 
+// visit map slots: a quarter of the group table's
+u64 visit_slots(u64 gslots) { return gslots / 4 < 4096 ? 4096 : gslots / 4; }
+
 struct StreamLayout {
     size_t bytes;
     template <class F>
     static void carve(cvh::Carver& c, u64 jslots, u64 gslots, u64 mb, F&& f)
     {
+        const u64 vslots = visit_slots(gslots);
         const u64 tiles = (mb + ST_TILE - 1) / ST_TILE;
         size_t sort_ws = 0;
         cv_sort_workspace_size(mb, mb ? mb : 1, &sort_ws);
@@ -676,6 +718,7 @@ struct StreamLayout {
         f("jkeys", c.take<u64>(jslots));
         f("rows", c.take<JRow>(jslots));
         f("tab", c.take<GEntry>(gslots));
+        f("visits", c.take<Visit>(vslots));
         f("sort_ws", c.take<char>(sort_ws));
         f("perm", c.take<u32>(mb));
         f("s_jid", c.take<i64>(mb));
@@ -779,6 +822,7 @@ cv_status cv_stream_create(const cv_grid_spec* grid, uint64_t max_journeys, uint
         else if (nm == "jkeys") st->jkeys = (u64*)p;
         else if (nm == "rows") st->rows = (JRow*)p;
         else if (nm == "tab") st->tab = (GEntry*)p;
+        else if (nm == "visits") st->visits = (Visit*)p;
         else if (nm == "sort_ws") st->sort_ws = p;
         else if (nm == "perm") st->perm = (u32*)p;
         else if (nm == "s_jid") st->s_jid = (i64*)p;
@@ -817,6 +861,7 @@ cv_status cv_stream_create(const cv_grid_spec* grid, uint64_t max_journeys, uint
     cvh::fill_u64(st->jkeys, JEMPTY, st->jslots, s);
     hipLaunchKernelGGL(k_grid_clear, dim3(cvh::grid_for(st->gslots, 256, 4096)), dim3(256), 0, s, st->tab, st->gslots,
                        &st->meta->gm);
+    cvh::fill_u32((u32*)st->visits, VEMPTY, visit_slots(st->gslots) * sizeof(Visit) / 4, s);
     cv_status e = cvh::last_launch_status();
     if (e != CV_OK) {
         delete st;
@@ -860,7 +905,8 @@ cv_status cv_stream_push(cv_stream* st, const cv_records* batch, const cv_featur
                        st->fs_v, st->fs_b, st->fs_flags);
     hipLaunchKernelGGL(k_st_fold, dim3(cvh::grid_for(n, 256, 2048)), dim3(256), 0, s, nn, st->s_ts, st->s_lat,
                        st->s_lon, st->s_spd, st->boff, st->meta, st->bslot, st->rows, st->fs_step, st->fs_v,
-                       st->fs_b, st->fs_flags, st->g, st->tab, st->gslots - 1);
+                       st->fs_b, st->fs_flags, st->g, st->tab, st->gslots - 1, st->visits,
+                       visit_slots(st->gslots) - 1);
     hipLaunchKernelGGL(k_st_finish, dim3(1), dim3(64), 0, s, st->meta, st->sres, nn, res);
     return cvh::last_launch_status();
 }
@@ -885,7 +931,8 @@ cv_status cv_stream_flush(cv_stream* st, const cv_journeys* journeys, uint64_t j
     radix_scan(st->jhist, st->joffs, MAX_PASSES, s);
     // 8 passes: the sorted pairs end in (jK0, jV0); pass 0 reads the slot values from jV0 via jfirst copy
     u32* vfirst = st->jfirst;
-    hipMemcpyAsync(vfirst, st->jV0, st->jslots * sizeof(u32), hipMemcpyDeviceToDevice, s);
+    if (hipMemcpyAsync(vfirst, st->jV0, st->jslots * sizeof(u32), hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return CV_ERR_DEVICE;
     radix_passes(st->jK0, st->jK1, vfirst, st->jV0, st->jV1, (u32)st->jslots, jn, nullptr, MAX_PASSES, st->joffs,
                  st->jstatus, st->meta->jtickets, s);
     cv_status e = CV_OK;

@@ -1,8 +1,8 @@
 // cv_summary.hip -- cv_journey_summary: one row per journey of sorted records.
 //
 // Journeys are maximal runs of equal journey id.  Tiles of ST records:
-//   k_sum_count   journey starts per tile;
-//   k_tile_scan   exclusive scan of the tile counts (one block) -> journey index
+//   k_sum_count   journey starts per wave chunk (a tile holds NW chunks);
+//   k_tile_scan   exclusive scan of the tile totals (one block) -> journey index
 //                 of each tile's first start, J;
 //   k_sum_init    identity values in the accumulator rows of the J journeys;
 //   k_sum_reduce  segmented reduction over journey boundaries: every wave walks
@@ -39,25 +39,54 @@ struct SumMeta {
     u32 J;
 };
 
-__device__ __forceinline__ bool is_head(const i64* jid, u64 r) { return r == 0 || jid[r] != jid[r - 1]; }
+constexpr int NW = SB / WAVE;  // waves per block
+constexpr int WI = SI;         // windows of 64 records per wave
+constexpr int WCH = WAVE * WI; // records per wave
+static_assert(ST == NW * WCH, "tile = waves x wave chunk");
 
-__global__ void __launch_bounds__(SB) k_sum_count(const i64* __restrict__ jid, u32 n, u32* __restrict__ tile_cnt,
-                                                  const u64* __restrict__ soff, u32 S)
+// Journey starts among the records of window [a, a + 64) of a wave that walks
+// consecutive windows: jprev is the id before the window (carried), sk the
+// shard cursor.  Returns the lane mask of starts; jv is this lane's id.
+__device__ __forceinline__ u64 window_heads(const i64* __restrict__ jid, u64 a, u64 end, i64& jprev, i64& jv,
+                                            const u64* __restrict__ soff, u32 S, u32& sk, u64& smask, bool& s_end)
 {
-    __shared__ u32 tmp[SB / WAVE];
-    const u64 base = (u64)blockIdx.x * ST;
-    u32 c = 0;
-    for (int i = threadIdx.x; i < ST; i += SB) {
-        u64 r = base + i;
-        if (r < n && (is_head(jid, r) || (S > 1 && shard_start(soff, S, r)))) ++c;
-    }
-    u32 total;
-    block_exclusive_sum<SB>(c, tmp, total);
-    if (threadIdx.x == 0) tile_cnt[blockIdx.x] = total;
+    const int l = lane_id();
+    const u64 r = a + l;
+    const bool valid = r < end;
+    jv = valid ? jid[r] : 0;
+    i64 jp = __shfl_up(jv, 1, WAVE);
+    if (l == 0) jp = jprev;
+    jprev = __shfl(jv, WAVE - 1, WAVE);
+    smask = 0;
+    s_end = false;
+    if (S > 1) smask = shard_starts_in(soff, S, sk, a, s_end);
+    return __ballot(valid && (r == 0 || jv != jp || ((smask >> l) & 1ull)));
 }
 
-// single block: exclusive scan of `tiles` counts in place; meta->J = total
-__global__ void __launch_bounds__(256) k_tile_scan(u32* __restrict__ cnt, u32 tiles, SumMeta* meta)
+// journey starts per wave chunk of WCH records: wcnt[tile * NW + wave]
+__global__ void __launch_bounds__(SB) k_sum_count(const i64* __restrict__ jid, u32 n, u32* __restrict__ wcnt,
+                                                  const u64* __restrict__ soff, u32 S)
+{
+    const int w = threadIdx.x / WAVE;
+    const u64 cs = (u64)blockIdx.x * ST + (u64)w * WCH;
+    const u64 ce = cs + WCH < n ? cs + WCH : (u64)n;
+    u32 c = 0;
+    if (cs < ce) {
+        i64 jprev = cs > 0 ? jid[cs - 1] : 0;
+        u32 sk = S > 1 ? shard_lower_bound(soff, S, cs) : 0u;
+        for (u64 a = cs; a < ce; a += WAVE) {
+            i64 jv;
+            u64 sm;
+            bool se;
+            c += (u32)__popcll(window_heads(jid, a, ce, jprev, jv, soff, S, sk, sm, se));
+        }
+    }
+    if (lane_id() == 0) wcnt[(u64)blockIdx.x * NW + w] = c;
+}
+
+// single block: tile_prefix[i] = journey starts before tile i; meta->J = total
+__global__ void __launch_bounds__(256) k_tile_scan(const u32* __restrict__ wcnt, u32* __restrict__ tile_prefix,
+                                                   u32 tiles, SumMeta* meta)
 {
     __shared__ u32 tmp[256 / WAVE];
     __shared__ u32 carry;
@@ -65,10 +94,12 @@ __global__ void __launch_bounds__(256) k_tile_scan(u32* __restrict__ cnt, u32 ti
     __syncthreads();
     for (u32 b = 0; b < tiles; b += 256) {
         u32 i = b + threadIdx.x;
-        u32 v = i < tiles ? cnt[i] : 0u;
+        u32 v = 0;
+        if (i < tiles)
+            for (int k = 0; k < NW; ++k) v += wcnt[(u64)i * NW + k];
         u32 total;
         u32 e = block_exclusive_sum<256>(v, tmp, total);
-        if (i < tiles) cnt[i] = carry + e;
+        if (i < tiles) tile_prefix[i] = carry + e;
         __syncthreads();
         if (threadIdx.x == 0) carry += total;
         __syncthreads();
@@ -137,51 +168,97 @@ __device__ __forceinline__ void part_combine(Part& a, const Part& b)
     a.maxs = b.maxs > a.maxs ? b.maxs : a.maxs;
 }
 
-template <typename F>
-__device__ __forceinline__ void part_shuffle(Part& o, const Part& p, F&& sh)
-{
-    for (int i = 0; i < 3; ++i) {
-        o.dist.w[i] = sh(p.dist.w[i]);
-        o.spd.w[i] = sh(p.spd.w[i]);
-    }
-    o.maxd = sh(p.maxd);
-    o.latmin = sh(p.latmin);
-    o.latmax = sh(p.latmax);
-    o.lonmin = sh(p.lonmin);
-    o.lonmax = sh(p.lonmax);
-    o.count = (u32)sh((u64)p.count);
-    o.ndtz = (u32)sh((u64)p.ndtz);
-    o.maxs = (u32)sh((u64)p.maxs);
-}
+// Cross-lane steps work one field at a time, so that only that field's
+// shuffled copy is live next to the partial.
+__device__ __forceinline__ u64 shfl_xor64(u64 v, int d) { return (u64)__shfl_xor((unsigned long long)v, d, WAVE); }
+__device__ __forceinline__ u64 shfl_up64(u64 v, int d) { return (u64)__shfl_up((unsigned long long)v, d, WAVE); }
 
 // full wave reduction; every lane ends with the total
 __device__ __forceinline__ void part_wave_reduce(Part& p)
 {
 #pragma unroll
     for (int d = 1; d < WAVE; d <<= 1) {
-        Part o;
-        part_shuffle(o, p, [&](u64 v) { return (u64)__shfl_xor((unsigned long long)v, d, WAVE); });
-        part_combine(p, o);
+        Fx192 o;
+        for (int i = 0; i < 3; ++i) o.w[i] = shfl_xor64(p.dist.w[i], d);
+        fx_add(p.dist, o);
+    }
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        Fx192 o;
+        for (int i = 0; i < 3; ++i) o.w[i] = shfl_xor64(p.spd.w[i], d);
+        fx_add(p.spd, o);
+    }
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        u64 v;
+        v = shfl_xor64(p.maxd, d);
+        p.maxd = v > p.maxd ? v : p.maxd;
+        v = shfl_xor64(p.latmin, d);
+        p.latmin = v < p.latmin ? v : p.latmin;
+        v = shfl_xor64(p.latmax, d);
+        p.latmax = v > p.latmax ? v : p.latmax;
+        v = shfl_xor64(p.lonmin, d);
+        p.lonmin = v < p.lonmin ? v : p.lonmin;
+        v = shfl_xor64(p.lonmax, d);
+        p.lonmax = v > p.lonmax ? v : p.lonmax;
+        u32 x;
+        x = __shfl_xor(p.count, d, WAVE);
+        p.count += x;
+        x = __shfl_xor(p.ndtz, d, WAVE);
+        p.ndtz += x;
+        x = __shfl_xor(p.maxs, d, WAVE);
+        p.maxs = x > p.maxs ? x : p.maxs;
     }
 }
 
-// segmented inclusive scan across lanes; `head` starts a segment
+// segmented inclusive scan across lanes; `head` starts a segment.  Step k
+// (distance 2^k) folds in the lane 2^k below when bit k of `take` is set.
 __device__ __forceinline__ void part_seg_scan(Part& p, bool head)
 {
     const int l = lane_id();
+    u32 take = 0;
     bool f = head;
 #pragma unroll
-    for (int d = 1; d < WAVE; d <<= 1) {
-        Part o;
-        part_shuffle(o, p, [&](u64 v) { return (u64)__shfl_up((unsigned long long)v, d, WAVE); });
-        bool fo = __shfl_up(f, d, WAVE);
+    for (int k = 0, d = 1; d < WAVE; ++k, d <<= 1) {
+        const bool fo = __shfl_up(f, d, WAVE);
         if (l >= d) {
-            if (!f) {
-                part_combine(o, p);
-                p = o;
-            }
+            if (!f) take |= 1u << k;
             f = f || fo;
         }
+    }
+#pragma unroll
+    for (int k = 0, d = 1; d < WAVE; ++k, d <<= 1) {
+        Fx192 o;
+        for (int i = 0; i < 3; ++i) o.w[i] = shfl_up64(p.dist.w[i], d);
+        if ((take >> k) & 1u) fx_add(p.dist, o);
+    }
+#pragma unroll
+    for (int k = 0, d = 1; d < WAVE; ++k, d <<= 1) {
+        Fx192 o;
+        for (int i = 0; i < 3; ++i) o.w[i] = shfl_up64(p.spd.w[i], d);
+        if ((take >> k) & 1u) fx_add(p.spd, o);
+    }
+#pragma unroll
+    for (int k = 0, d = 1; d < WAVE; ++k, d <<= 1) {
+        const bool t = (take >> k) & 1u;
+        u64 v;
+        v = shfl_up64(p.maxd, d);
+        if (t && v > p.maxd) p.maxd = v;
+        v = shfl_up64(p.latmin, d);
+        if (t && v < p.latmin) p.latmin = v;
+        v = shfl_up64(p.latmax, d);
+        if (t && v > p.latmax) p.latmax = v;
+        v = shfl_up64(p.lonmin, d);
+        if (t && v < p.lonmin) p.lonmin = v;
+        v = shfl_up64(p.lonmax, d);
+        if (t && v > p.lonmax) p.lonmax = v;
+        u32 x;
+        x = __shfl_up(p.count, d, WAVE);
+        if (t) p.count += x;
+        x = __shfl_up(p.ndtz, d, WAVE);
+        if (t) p.ndtz += x;
+        x = __shfl_up(p.maxs, d, WAVE);
+        if (t && x > p.maxs) p.maxs = x;
     }
 }
 
@@ -214,14 +291,31 @@ __device__ __forceinline__ void write_final(const Out& o, u32 j, u32 count, u32 
     o.lonmax[j] = unord_f64(lo1);
 }
 
-__device__ __forceinline__ void flush_part(const Out& o, JAcc* acc, u32 cap, u32 j, const Part& p, bool whole)
+// A journey's partial into its accumulator row: a whole journey (all its
+// records are in the partial) is stored, a piece is merged with integer atomics.
+// The rows are turned into output rows by k_sum_finalize.
+__device__ __forceinline__ void flush_part(JAcc* acc, u32 cap, u32 j, const Part& p, bool whole)
 {
     if (j >= cap || p.count == 0) return;
+    JAcc& a = acc[j];
     if (whole) {
-        write_final(o, j, p.count, p.ndtz, p.dist, p.spd, p.maxs, p.maxd, p.latmin, p.latmax, p.lonmin, p.lonmax);
+        JAcc v;
+        for (int i = 0; i < 3; ++i) {
+            v.dist[i] = p.dist.w[i];
+            v.spd[i] = p.spd.w[i];
+        }
+        v.maxd = p.maxd;
+        v.latmin = p.latmin;
+        v.latmax = p.latmax;
+        v.lonmin = p.lonmin;
+        v.lonmax = p.lonmax;
+        v.count = p.count;
+        v.ndtz = p.ndtz;
+        v.maxs = p.maxs;
+        v.touched = 1;
+        a = v;
         return;
     }
-    JAcc& a = acc[j];
     atomic_add_fx(a.dist, p.dist);
     atomic_add_fx(a.spd, p.spd);
     atomicMax((unsigned long long*)&a.maxd, (unsigned long long)p.maxd);
@@ -241,63 +335,40 @@ __device__ __forceinline__ void flush_part(const Out& o, JAcc* acc, u32 cap, u32
 // reduction), runs a segmented scan for journeys that begin in it, and hands
 // the last one on as the new open journey.  A journey that begins and ends in
 // the wave's records is written out directly; otherwise its pieces meet in the
-// accumulator row through integer atomics.
-constexpr int WI = SI;                  // windows per wave
-constexpr int WCH = WAVE * WI;          // records per wave
-static_assert(ST == (SB / WAVE) * WCH, "tile = waves x wave chunk");
-
+// accumulator row through integer atomics.  Neighbouring ids come from lane
+// shuffles; time stamps are read only at journey starts and ends.
 __global__ void __launch_bounds__(SB) k_sum_reduce(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts,
                                                    const double* __restrict__ lat, const double* __restrict__ lon,
                                                    const float* __restrict__ spd, const double* __restrict__ step,
                                                    const double* __restrict__ dspd, const uint8_t* __restrict__ flags,
-                                                   const u32* __restrict__ tile_prefix, u32 cap, Out o,
-                                                   JAcc* __restrict__ acc, const u64* __restrict__ soff, u32 S,
-                                                   u64* __restrict__ jo)
+                                                   const u32* __restrict__ tile_prefix, const u32* __restrict__ wcnt,
+                                                   u32 cap, Out o, JAcc* __restrict__ acc,
+                                                   const u64* __restrict__ soff, u32 S, u64* __restrict__ jo)
 {
-    __shared__ u32 s_wh[SB / WAVE];
     const int w = threadIdx.x / WAVE;
     const int l = lane_id();
     const u64 cs = (u64)blockIdx.x * ST + (u64)w * WCH;  // wave chunk start
     const u64 ce = cs + WCH < n ? cs + WCH : (u64)n;      // wave chunk end (may be <= cs)
-
-    // heads in this wave's chunk -> journey index of the wave's first head
-    u32 hc = 0;
-    for (int i = 0; i < WI; ++i) {
-        u64 r = cs + (u64)i * WAVE + l;
-        if (r < ce && (r == 0 || jid[r] != jid[r - 1] || (S > 1 && shard_start(soff, S, r)))) ++hc;
-    }
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) hc += __shfl_xor(hc, d, WAVE);
-    if (l == 0) s_wh[w] = hc;
-    __syncthreads();
-    u32 seen = tile_prefix[blockIdx.x];  // heads before the current position
-    for (int k = 0; k < w; ++k) seen += s_wh[k];
     if (cs >= ce) return;
+    u32 seen = tile_prefix[blockIdx.x];  // journey starts before the current window
+    for (int k = 0; k < w; ++k) seen += wcnt[(u64)blockIdx.x * NW + k];
 
     Part p;
     part_reset(p);
     // open journey: the one containing the record before the next window
     u32 open_j = seen - 1;   // valid when the chunk starts mid-journey
     bool open_here = false;  // its first record lies in this chunk
-    // window loads are issued one window ahead of their use
+    i64 jprev = cs > 0 ? jid[cs - 1] : 0;
+    u32 sk = S > 1 ? shard_lower_bound(soff, S, cs) : 0u;
+    // value columns of a window, loaded one window ahead of their use
     struct Win {
-        i64 j, jp, jn, t;
         double st, ds, la, lo;
         float sp;
         uint8_t f;
     };
-    auto load = [&](int i, Win& x) {
-        const u64 r = cs + (u64)i * WAVE + l;
+    auto load = [&](u64 a, Win& x) {
+        const u64 r = a + l;
         if (r < ce) {
-            x.j = jid[r];
-            x.jp = r > 0 ? jid[r - 1] : ~x.j;
-            x.jn = r + 1 < n ? jid[r + 1] : ~x.j;
-            if (S > 1) {
-                // a shard start is a journey start even when the id continues
-                if (shard_start(soff, S, r)) x.jp = ~x.j;
-                if (r + 1 < n && shard_start(soff, S, r + 1)) x.jn = ~x.j;
-            }
-            x.t = ts[r];
             x.st = step[r];
             x.sp = spd[r];
             x.f = flags[r];
@@ -307,17 +378,28 @@ __global__ void __launch_bounds__(SB) k_sum_reduce(u32 n, const i64* __restrict_
         }
     };
     Win cur, nxt;
-    load(0, cur);
+    load(cs, cur);
     for (int i = 0; i < WI; ++i) {
-        if (i + 1 < WI) load(i + 1, nxt);
-        const u64 r = cs + (u64)i * WAVE + l;
+        const u64 a = cs + (u64)i * WAVE;
+        if (a >= ce) break;
+        if (i + 1 < WI) load(a + WAVE, nxt);
+        const u64 r = a + l;
         const bool valid = r < ce;
-        bool h = false, last = false;
+        i64 jv;
+        u64 smask;
+        bool s_end;
+        const u64 H = window_heads(jid, a, ce, jprev, jv, soff, S, sk, smask, s_end);
+        const bool h = (H >> l) & 1ull;
+        // last record of its journey: the next record starts one (or there is none)
+        bool last = false;
+        if (valid) {
+            if (r + 1 >= n) last = true;
+            else if (l < WAVE - 1) last = ((H >> (l + 1)) & 1ull) != 0;
+            else last = jid[r + 1] != jv || s_end;
+        }
         Part c;
         part_reset(c);
         if (valid) {
-            h = (r == 0) || (cur.j != cur.jp);
-            last = (r + 1 >= n) || (cur.jn != cur.j);
             c.count = 1;
             c.ndtz = (cur.f & CV_FLAG_DT_ZERO) ? 1u : 0u;
             c.dist = fx_from_double<FX_DIST>(cur.st);
@@ -329,13 +411,14 @@ __global__ void __launch_bounds__(SB) k_sum_reduce(u32 n, const i64* __restrict_
                 c.lonmin = c.lonmax = ord_f64(cur.lo);
             }
         }
-        const u64 H = __ballot(h);
         // journey index of this lane's record
         const u32 jl = seen + popc_below(H) + (h ? 1u : 0u) - 1u;
         if (h && jl < cap) {
-            o.jid[jl] = cur.j;
-            o.first[jl] = (u32)r;
-            o.tstart[jl] = cur.t;
+            // a journey's first record is indexed within its shard
+            const u32 sh = S > 1 ? shard_of(soff, S, r) : 0u;
+            o.jid[jl] = jv;
+            o.first[jl] = (u32)(S > 1 ? r - soff[sh] : r);
+            o.tstart[jl] = ts[r];
         }
         if (h && S > 1 && jo) {
             // this record opens its shard's first journey: every shard starting
@@ -344,20 +427,20 @@ __global__ void __launch_bounds__(SB) k_sum_reduce(u32 n, const i64* __restrict_
             if (soff[sh] == r)
                 for (int z = (int)sh; z >= 0 && soff[z] == r; --z) jo[z] = jl;
         }
-        if (valid && last && jl < cap) o.tend[jl] = cur.t;
+        if (last && jl < cap) o.tend[jl] = ts[r];
         if (H != 0) {
             const int f0 = __ffsll((long long)H) - 1;
             if (l < f0) part_combine(p, c);
             // close the journey that was open before the first start in this window
             part_wave_reduce(p);
-            if (l == 0) flush_part(o, acc, cap, open_j, p, open_here);
+            if (l == 0) flush_part(acc, cap, open_j, p, open_here);
             // journeys starting in this window
             Part s = c;
             part_seg_scan(s, h);
             // a segment that ends before lane 63 (next lane starts a journey) is a
             // whole journey: it began and ended inside this window
             const bool next_head = (l < WAVE - 1) && ((H >> (l + 1)) & 1ull);
-            if (l >= f0 && next_head) flush_part(o, acc, cap, jl, s, true);
+            if (l >= f0 && next_head) flush_part(acc, cap, jl, s, true);
             // the last segment stays open; lane 63 holds its partial
             part_reset(p);
             if (l == WAVE - 1) p = s;
@@ -372,7 +455,7 @@ __global__ void __launch_bounds__(SB) k_sum_reduce(u32 n, const i64* __restrict_
     part_wave_reduce(p);
     if (l == 0) {
         const bool ends = (ce >= n) || (jid[ce] != jid[ce - 1]) || (S > 1 && shard_start(soff, S, ce));
-        flush_part(o, acc, cap, open_j, p, open_here && ends);
+        flush_part(acc, cap, open_j, p, open_here && ends);
     }
 }
 
@@ -419,7 +502,8 @@ __global__ void k_sum_empty(cv_result* res)
 
 struct SumLayout {
     SumMeta* meta;
-    u32* tile_cnt;
+    u32* wcnt;
+    u32* tile_prefix;
     JAcc* acc;
     u64 tiles;
     size_t bytes;
@@ -428,7 +512,8 @@ struct SumLayout {
         cvh::Carver c(ws);
         tiles = (n + ST - 1) / ST;
         meta = c.take<SumMeta>(1);
-        tile_cnt = c.take<u32>(tiles + 1);
+        wcnt = c.take<u32>(tiles * NW);
+        tile_prefix = c.take<u32>(tiles + 1);
         acc = c.take<JAcc>(cap < n ? cap : n);
         bytes = c.size();
     }
@@ -465,12 +550,12 @@ static cv_status summary_impl(const cv_records* sorted, const cv_features* feat,
     const u32 cap = (u32)(capacity < n ? capacity : n);
     const u32 nn = (u32)n;
     cvh::TimedScope ts_("summary", s);
-    hipLaunchKernelGGL(k_sum_count, dim3((unsigned)L.tiles), dim3(SB), 0, s, sorted->journey_id, nn, L.tile_cnt, soff, S);
-    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(256), 0, s, L.tile_cnt, (u32)L.tiles, L.meta);
+    hipLaunchKernelGGL(k_sum_count, dim3((unsigned)L.tiles), dim3(SB), 0, s, sorted->journey_id, nn, L.wcnt, soff, S);
+    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(256), 0, s, L.wcnt, L.tile_prefix, (u32)L.tiles, L.meta);
     hipLaunchKernelGGL(k_sum_init, dim3(cvh::grid_for(cap, 256, 2048)), dim3(256), 0, s, L.acc, L.meta, cap);
     hipLaunchKernelGGL(k_sum_reduce, dim3((unsigned)L.tiles), dim3(SB), 0, s, nn, sorted->journey_id, sorted->ts_ms,
                        sorted->lat_deg, sorted->lon_deg, sorted->speed_mps, feat->step_m, feat->speed_mps, feat->flags,
-                       L.tile_cnt, cap, o, L.acc, soff, S, jo);
+                       L.tile_prefix, L.wcnt, cap, o, L.acc, soff, S, jo);
     hipLaunchKernelGGL(k_sum_finalize, dim3(cvh::grid_for(cap, 256, 2048)), dim3(256), 0, s, L.acc, L.meta, cap, o,
                        res, soff, S, jo, nn);
     return cvh::last_launch_status();

@@ -75,7 +75,7 @@ class CvGroups(ctypes.Structure):
 
 RESULT_DTYPE = np.dtype([("status", "<u4"), ("flags", "<u4"), ("count", "<u8"), ("required", "<u8"),
                          ("n_out_of_grid", "<u8"), ("n_late", "<u8"), ("key_bits", "<u8"),
-                         ("reserved", "<u8", (2,))])
+                         ("packed_pass", "<u8"), ("reserved", "<u8")])
 assert RESULT_DTYPE.itemsize == 64
 
 
@@ -195,7 +195,8 @@ def new_result(device="cuda"):
 
 def read_result(res) -> dict:
     a = np.frombuffer(res.cpu().numpy().tobytes(), dtype=RESULT_DTYPE)[0]
-    return {k: int(a[k]) for k in ("status", "count", "required", "n_out_of_grid", "n_late", "key_bits")}
+    return {k: int(a[k]) for k in ("status", "count", "required", "n_out_of_grid", "n_late", "key_bits",
+                                         "packed_pass")}
 
 
 def workspace(nbytes, device="cuda"):
@@ -339,12 +340,12 @@ def cv_timing_read(family):
 
 def run_plain(rec, grid, max_journeys=None, journey_capacity=None, group_capacity=None, stream=None):
     """The whole plain path on one device batch: order, features, summary, grid."""
-    perm, srt, _ = cv_sort_records(rec, max_journeys=max_journeys, stream=stream)
+    perm, srt, rsort = cv_sort_records(rec, max_journeys=max_journeys, stream=stream)
     feat = cv_journey_features(srt, stream=stream)
     summ, rs = cv_journey_summary(srt, feat, capacity=journey_capacity, stream=stream)
     groups, rg = cv_grid_aggregate(srt, grid, capacity=group_capacity, stream=stream)
     return dict(perm=perm, sorted=srt, features=feat, summary=summ, groups=groups, n_out=rg["n_out_of_grid"],
-                summary_result=rs, grid_result=rg)
+                sort_result=rsort, summary_result=rs, grid_result=rg)
 
 
 class Pipeline:

@@ -181,3 +181,33 @@ def test_deterministic_bitwise(cv):
     for part in ("features", "summary", "groups"):
         for k in a[part]:
             assert np.array_equal(host(a[part][k]).view(np.uint8), host(b[part][k]).view(np.uint8)), (part, k)
+
+
+def _wide_keys(seed, n, n_ids, tbits):
+    """Records whose (journey rank, time offset) key is wide: n_ids distinct ids
+    and time stamps spanning exactly tbits bits."""
+    rng = np.random.default_rng(seed)
+    ids = rng.choice(np.arange(-2 ** 40, 2 ** 40, 7919, dtype=np.int64), n_ids, replace=False)
+    jid = ids[rng.integers(0, n_ids, n)]
+    jid[:n_ids] = ids
+    ts = gen.T0_MS + rng.integers(0, 2 ** tbits, n, dtype=np.int64)
+    ts[0], ts[1] = gen.T0_MS, gen.T0_MS + 2 ** tbits - 1
+    lat = rng.uniform(36.0, 40.6, n)
+    lon = rng.uniform(-95.8, -89.1, n)
+    spd = rng.uniform(0, 40, n).astype(np.float32)
+    return jid, ts, lat, lon, spd
+
+
+@pytest.mark.parametrize("tbits", [40, 45, 50, 54])
+def test_packed_radix_passes(cv, tbits):
+    # 5000 records (13 index bits), 1000 ids (10 rank bits): the key has
+    # 10 + tbits bits, and passes from the first digit boundary p0 with
+    # key_bits - 8 p0 + 13 <= 64 move packed (key | index) words
+    n, n_ids = 5000, 1000
+    cols = _wide_keys(100 + tbits, n, n_ids, tbits)
+    got, exp = _run_both(cv, cols, gen.GRIDS["c0"])
+    _check_all(got, exp)
+    kb = 10 + tbits
+    p0 = max(0, -(-(kb + 13 - 64) // 8))
+    assert got["sort_result"]["key_bits"] == kb
+    assert got["sort_result"]["packed_pass"] == p0

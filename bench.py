@@ -121,12 +121,15 @@ def bench_batched(args):
     log(f"generated c2: {len(sizes)} shards, {n} records in {time.time() - t:.1f}s")
     grid = gen.GRIDS["c2"]
     rec = cvetl.to_device(allr, dev)
+    torch.cuda.synchronize()
+    log(f"c2 columns resident ({time.time() - t:.1f}s)")
     from paper_2305_07454_amd import tune
     tune.apply(n)
     off_h, off_d = cvetl.shard_offsets(sizes, dev)
     bp, res = cvetl.cv_batch_run(rec, sizes, grid)
     J, G = res[1]["count"], res[2]["count"]
     mj = bp.max_journeys
+    log(f"sizing run: {J} journeys, {G} groups ({time.time() - t:.1f}s)")
     del bp
     torch.cuda.empty_cache()
     bp = cvetl.BatchPipeline(n, len(sizes), grid, mj, J, max(4096, int(1.25 * G)), dev)
@@ -134,6 +137,7 @@ def bench_batched(args):
         bp.run(rec, off_d)
     torch.cuda.synchronize()
     assert all(x["status"] == 0 for x in bp.results())
+    log(f"warm-up done ({time.time() - t:.1f}s)")
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(args.steps):
@@ -141,6 +145,7 @@ def bench_batched(args):
     e1.record()
     torch.cuda.synchronize()
     ms_batched = e0.elapsed_time(e1) / args.steps
+    log(f"batched: {ms_batched:.2f} ms per step ({time.time() - t:.1f}s)")
     # plain per-file: one plain pipeline sized for the largest shard, called per shard
     big = max(sizes)
     pp = cvetl.Pipeline(big, grid, max_journeys=max(1024, mj), journey_capacity=max(1, J),
@@ -160,6 +165,7 @@ def bench_batched(args):
     e1.record()
     torch.cuda.synchronize()
     ms_plain = e0.elapsed_time(e1) / args.steps
+    log(f"per-file: {ms_plain:.2f} ms per step ({time.time() - t:.1f}s)")
     # identical outputs on the last shard the loop ran
     i = max(j for j in range(len(sizes)) if sizes[j] > 0)
     a, b = int(off_h[i]), int(off_h[i + 1])

@@ -63,11 +63,14 @@ k_radix_pass(const u64* __restrict__ keys_in, const u32* __restrict__ vals_in, u
     constexpr int NW = SORT_BLOCK / WAVE;
     constexpr int SORT_TILE = SORT_BLOCK * SORT_ITEMS;
     static_assert(SORT_BLOCK >= RADIX, "one thread per digit");
-    __shared__ u32 s_whist[NW][RADIX];
+    static_assert(SORT_TILE <= 65535, "16-bit in-tile offsets");
+    // per-wave digit counts, then in-tile offsets (< SORT_TILE, so 16 bits)
+    __shared__ uint16_t s_whist[NW][RADIX];
     __shared__ u32 s_start[RADIX];
     __shared__ u32 s_gshift[RADIX];
+    // staging: keys in digit order; then, in passes that carry index values,
+    // the values in the same order (the buffer reused as 32-bit words)
     __shared__ u64 s_keys[SORT_TILE];
-    __shared__ u32 s_vals[SORT_TILE];
     __shared__ u32 s_tmp[NW];
     __shared__ u32 s_tile;
 
@@ -79,6 +82,8 @@ k_radix_pass(const u64* __restrict__ keys_in, const u32* __restrict__ vals_in, u
     const bool pin = pass >= p0;           // input words are packed
     const bool pout = pass + 1 >= p0;      // output words are packed
     const int shift = pin ? (int)ib + (pass - p0) * RADIX_BITS : pass * RADIX_BITS;
+    // this pass's global start of digit threadIdx.x, read before it is needed
+    const u32 doff = threadIdx.x < RADIX ? digit_offs[threadIdx.x] : 0u;
     if (threadIdx.x == 0) s_tile = atomicAdd(ticket, 1u);
     for (int i = threadIdx.x; i < NW * RADIX; i += SORT_BLOCK) (&s_whist[0][0])[i] = 0;
     __syncthreads();
@@ -113,10 +118,10 @@ k_radix_pass(const u64* __restrict__ keys_in, const u32* __restrict__ vals_in, u
         }
         u32 below = popc_below(peers);
         u32 cnt = __popcll(peers);
-        u32 before = ok ? s_whist[w][d] : 0u;
+        u32 before = ok ? (u32)s_whist[w][d] : 0u;
         rnk[i] = before + below;
         __builtin_amdgcn_wave_barrier();
-        if (ok && below == cnt - 1) s_whist[w][d] = before + cnt;
+        if (ok && below == cnt - 1) s_whist[w][d] = (uint16_t)(before + cnt);
         __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
@@ -128,7 +133,7 @@ k_radix_pass(const u64* __restrict__ keys_in, const u32* __restrict__ vals_in, u
 #pragma unroll
         for (int ww = 0; ww < NW; ++ww) {
             u32 c = s_whist[ww][d];
-            s_whist[ww][d] = tcount;
+            s_whist[ww][d] = (uint16_t)tcount;
             tcount += c;
         }
     }
@@ -159,36 +164,60 @@ k_radix_pass(const u64* __restrict__ keys_in, const u32* __restrict__ vals_in, u
             }
             lb_publish(st, rs_word(2, tag, excl + tcount));
         }
-        s_gshift[d] = digit_offs[d] + (u32)excl - start;
+        s_gshift[d] = doff + (u32)excl - start;
     }
     __syncthreads();
 
+    // in-tile position of each item (digit order, stable)
+    u32 pos[SORT_ITEMS];
 #pragma unroll
     for (int i = 0; i < SORT_ITEMS; ++i) {
         u64 idx = wbase + (u64)i * WAVE + l;
+        pos[i] = ~0u;
         if (idx < n) {
             u32 d = (u32)(key[i] >> shift) & (RADIX - 1);
-            u32 pos = s_start[d] + s_whist[w][d] + rnk[i];
-            s_keys[pos] = key[i];
-            if (!pin) s_vals[pos] = val[i];
+            pos[i] = s_start[d] + s_whist[w][d] + rnk[i];
+            s_keys[pos[i]] = key[i];
         }
     }
     __syncthreads();
     const u32 tvalid = (u32)((n - tile_base) < (u64)SORT_TILE ? (n - tile_base) : (u64)SORT_TILE);
-    // staged words keep their input form; the pass that starts packing packs
-    // them on the way out
+    // read back the staged keys this thread writes out: positions t + k * SORT_BLOCK
+    u64 kk[SORT_ITEMS];
+#pragma unroll
+    for (int k = 0; k < SORT_ITEMS; ++k) {
+        const u32 j = threadIdx.x + (u32)k * SORT_BLOCK;
+        kk[k] = j < tvalid ? s_keys[j] : 0ull;
+    }
+    if (pin) {
+#pragma unroll
+        for (int k = 0; k < SORT_ITEMS; ++k) {
+            const u32 j = threadIdx.x + (u32)k * SORT_BLOCK;
+            if (j < tvalid) keys_out[s_gshift[(u32)(kk[k] >> shift) & (RADIX - 1)] + j] = kk[k];
+        }
+        return;
+    }
+    // the index values follow the keys through the same staging buffer
+    __syncthreads();
+    u32* s_vals = (u32*)s_keys;
+#pragma unroll
+    for (int i = 0; i < SORT_ITEMS; ++i)
+        if (pos[i] != ~0u) s_vals[pos[i]] = val[i];
+    __syncthreads();
+    // the pass that starts packing packs on the way out
     const int drop = p0 * RADIX_BITS;
-    for (u32 j = threadIdx.x; j < tvalid; j += SORT_BLOCK) {
-        const u64 k = s_keys[j];
-        const u32 d = (u32)(k >> shift) & (RADIX - 1);
-        const u32 g = s_gshift[d] + j;
-        if (pin) {
-            keys_out[g] = k;
-        } else if (pout) {
-            keys_out[g] = ((drop >= 64 ? 0ull : (k >> drop)) << ib) | (u64)s_vals[j];
-        } else {
-            keys_out[g] = k;
-            vals_out[g] = s_vals[j];
+#pragma unroll
+    for (int k = 0; k < SORT_ITEMS; ++k) {
+        const u32 j = threadIdx.x + (u32)k * SORT_BLOCK;
+        if (j < tvalid) {
+            const u32 g = s_gshift[(u32)(kk[k] >> shift) & (RADIX - 1)] + j;
+            const u32 v = s_vals[j];
+            if (pout) {
+                keys_out[g] = ((drop >= 64 ? 0ull : (kk[k] >> drop)) << ib) | (u64)v;
+            } else {
+                keys_out[g] = kk[k];
+                vals_out[g] = v;
+            }
         }
     }
 }
@@ -213,7 +242,7 @@ namespace {
 struct Shape {
     int block, items;
 };
-constexpr Shape SHAPES[] = {{256, 16}, {256, 32}, {512, 8}, {512, 16}, {1024, 8}};
+constexpr Shape SHAPES[] = {{256, 16}, {256, 32}, {512, 8}, {512, 16}, {1024, 8}, {1024, 16}};
 constexpr int N_SHAPES = sizeof(SHAPES) / sizeof(SHAPES[0]);
 int g_shape = 0;
 
@@ -268,7 +297,8 @@ void radix_passes(u64* k0, u64* k1, const u32* v_first, u32* v0, u32* v1, u32 n_
         case 1: go(launch_pass<256, 32>); break;
         case 2: go(launch_pass<512, 8>); break;
         case 3: go(launch_pass<512, 16>); break;
-        default: go(launch_pass<1024, 8>); break;
+        case 4: go(launch_pass<1024, 8>); break;
+        default: go(launch_pass<1024, 16>); break;
         }
     }
 }

@@ -211,3 +211,22 @@ def test_packed_radix_passes(cv, tbits):
     p0 = max(0, -(-(kb + 13 - 64) // 8))
     assert got["sort_result"]["key_bits"] == kb
     assert got["sort_result"]["packed_pass"] == p0
+
+
+def test_every_sort_tile_shape(cv):
+    # the record sort (and the group-key sort) under every compiled tile shape,
+    # on an input of many tiles with a ragged last tile
+    r = gen.make_c1(seed=12, n_journeys=70, median=900.0, shuffled=True)
+    cols = r.columns()
+    exp = oracle.run_plain(cols, gen.GRIDS["c1"])
+    rec = cv.to_device(cols)
+    prev = cv.cv_tuning_get("sort_shape")
+    try:
+        for sh in range(cv.cv_tuning_get("sort_shapes")):
+            cv.cv_tuning_set("sort_shape", sh)
+            print(f"[parity] sort shape {sh} tile {cv.cv_tuning_get('sort_tile')} n={r.n}", flush=True)
+            got = cv.run_plain(rec, gen.GRIDS["c1"])
+            check_sort(got["perm"], got["sorted"], exp["perm"], exp["sorted"])
+            check_groups(got["groups"], got["n_out"], exp["groups"], exp["n_out"])
+    finally:
+        cv.cv_tuning_set("sort_shape", prev)

@@ -55,9 +55,7 @@ __global__ void __launch_bounds__(FB) k_features(u32 n, const i64* __restrict__ 
         la = lat[r];
         lo = lon[r];
         fin = isfinite(la) && isfinite(lo);
-        const double phi = la * DEG2RAD;
-        sphi = fin ? sin(phi) : 0.0;
-        cphi = fin ? cos(phi) : 0.0;
+        if (fin) sincos(la * DEG2RAD, &sphi, &cphi);
     }
     s_jid[t] = j;
     s_ts[t] = tsr;
@@ -72,7 +70,14 @@ __global__ void __launch_bounds__(FB) k_features(u32 n, const i64* __restrict__ 
     u32 f = 0;
     if (in && t >= 1) {
         const int p = t - 1;
-        const bool head = (r == 0) || (s_jid[p] != j) || (S > 1 && shard_start(soff, S, (u64)r));
+        bool head = (r == 0) || (s_jid[p] != j);
+        if (S > 1 && !head) {
+            // the block's first shard, then forward to this record's
+            const long b0 = (long)blockIdx.x * FOUT - 2;
+            u32 sh = shard_of(soff, S, (u64)(b0 > 0 ? b0 : 0));
+            while (sh + 1 < S && soff[sh + 1] <= (u64)r) ++sh;
+            head = soff[sh] == (u64)r;
+        }
         if (head) {
             f = CV_FLAG_FIRST | (fin ? 0u : CV_FLAG_BAD_COORD);
         } else {

@@ -37,6 +37,7 @@ constexpr int GB = 256;
 constexpr int GI = 8;
 constexpr int GT = GB * GI;
 constexpr int HALO = 512;
+static_assert(HALO % GB == 0, "whole halo rows");
 constexpr int LHS_PROBES = 32;
 struct LSlot {
     u64 cs[4];
@@ -47,76 +48,111 @@ constexpr uint8_t B_SEG = 1;   // first record of a (journey, time-bin) segment
 constexpr uint8_t B_RUN = 2;   // first record of a run (segment start or key change)
 constexpr uint8_t B_FIRST = 4; // run head whose key is new in its segment (counts its journey)
 
-// partial aggregate of one run (or piece of a run)
+// Partial aggregate of one run (or piece of a run).  The speed sum is a
+// 128-bit two's-complement integer in units of 2^-53, exact for every float32
+// speed v with 2^-30 <= |v| < 2^10 (and for zeros); any other speed is added
+// to the table on its own, in the full 192-bit format.  Count and distinct
+// journeys share one word (16 bits each: a piece holds at most GT / 4
+// records).
 struct RunPart {
-    Fx192 sum;
-    u32 count, nj, mn, mx;
+    u64 lo, hi;
+    u32 cn, mn, mx;
 };
 
 __device__ __forceinline__ void run_reset(RunPart& p)
 {
-    fx_zero(p.sum);
-    p.count = 0;
-    p.nj = 0;
+    p.lo = 0;
+    p.hi = 0;
+    p.cn = 0;
     p.mn = ~0u;
     p.mx = 0;
 }
 
+__device__ __forceinline__ void add128(u64& lo, u64& hi, u64 blo, u64 bhi)
+{
+    const u64 s = lo + blo;
+    hi += bhi + (s < lo ? 1ull : 0ull);
+    lo = s;
+}
+
 __device__ __forceinline__ void run_combine(RunPart& a, const RunPart& b)
 {
-    fx_add(a.sum, b.sum);
-    a.count += b.count;
-    a.nj += b.nj;
+    add128(a.lo, a.hi, b.lo, b.hi);
+    a.cn += b.cn;
     a.mn = b.mn < a.mn ? b.mn : a.mn;
     a.mx = b.mx > a.mx ? b.mx : a.mx;
 }
 
-template <typename F>
-__device__ __forceinline__ void run_shuffle(RunPart& o, const RunPart& p, F&& sh)
+// v * 2^53 as a signed integer when 2^-30 <= |v| < 2^10 or v = +-0
+__device__ __forceinline__ bool spd_fix53(float v, i64& x)
 {
-    o.sum.w[0] = sh(p.sum.w[0]);
-    o.sum.w[1] = sh(p.sum.w[1]);
-    o.sum.w[2] = sh(p.sum.w[2]);
-    o.count = (u32)sh((u64)p.count);
-    o.nj = (u32)sh((u64)p.nj);
-    o.mn = (u32)sh((u64)p.mn);
-    o.mx = (u32)sh((u64)p.mx);
+    const u32 b = __float_as_uint(v);
+    const u32 e = (b >> 23) & 0xFFu;
+    const u32 m = b & 0x7FFFFFu;
+    x = 0;
+    if (e == 0) return m == 0;
+    if (e < 97 || e > 136) return false;
+    const i64 mag = (i64)((u64)(m | 0x800000u) << (e - 97));
+    x = (b >> 31) ? -mag : mag;
+    return true;
+}
+
+// the 128-bit sum in the table's 192-bit format (2^-149 units)
+__device__ __forceinline__ Fx192 run_sum192(const RunPart& p)
+{
+    Fx192 r;
+    r.w[0] = 0;
+    r.w[1] = p.lo << 32;
+    r.w[2] = (p.lo >> 32) | (p.hi << 32);
+    return r;
+}
+
+// one step of a cross-lane reduction or scan: fold in the partial d lanes away
+// (xor: full reduction; up: the lane below) when `take`
+__device__ __forceinline__ void run_step(RunPart& p, int d, bool up, bool take)
+{
+    const u64 lo = up ? (u64)__shfl_up((unsigned long long)p.lo, d, WAVE) : (u64)__shfl_xor((unsigned long long)p.lo, d, WAVE);
+    const u64 hi = up ? (u64)__shfl_up((unsigned long long)p.hi, d, WAVE) : (u64)__shfl_xor((unsigned long long)p.hi, d, WAVE);
+    const u32 cn = up ? (u32)__shfl_up(p.cn, d, WAVE) : (u32)__shfl_xor(p.cn, d, WAVE);
+    const u32 mn = up ? (u32)__shfl_up(p.mn, d, WAVE) : (u32)__shfl_xor(p.mn, d, WAVE);
+    const u32 mx = up ? (u32)__shfl_up(p.mx, d, WAVE) : (u32)__shfl_xor(p.mx, d, WAVE);
+    if (take) {
+        add128(p.lo, p.hi, lo, hi);
+        p.cn += cn;
+        p.mn = mn < p.mn ? mn : p.mn;
+        p.mx = mx > p.mx ? mx : p.mx;
+    }
 }
 
 __device__ __forceinline__ void run_wave_reduce(RunPart& p)
 {
 #pragma unroll
-    for (int d = 1; d < WAVE; d <<= 1) {
-        RunPart o;
-        run_shuffle(o, p, [&](u64 v) { return (u64)__shfl_xor((unsigned long long)v, d, WAVE); });
-        run_combine(p, o);
-    }
+    for (int d = 1; d < WAVE; d <<= 1) run_step(p, d, false, true);
 }
 
+// segmented inclusive scan across lanes; `head` starts a segment
 __device__ __forceinline__ void run_seg_scan(RunPart& p, bool head)
 {
     const int l = lane_id();
+    u32 take = 0;
     bool f = head;
 #pragma unroll
-    for (int d = 1; d < WAVE; d <<= 1) {
-        RunPart o;
-        run_shuffle(o, p, [&](u64 v) { return (u64)__shfl_up((unsigned long long)v, d, WAVE); });
+    for (int k = 0, d = 1; d < WAVE; ++k, d <<= 1) {
         const bool fo = __shfl_up(f, d, WAVE);
         if (l >= d) {
-            if (!f) {
-                run_combine(o, p);
-                p = o;
-            }
+            if (!f) take |= 1u << k;
             f = f || fo;
         }
     }
+#pragma unroll
+    for (int k = 0, d = 1; d < WAVE; ++k, d <<= 1) run_step(p, d, true, ((take >> k) & 1u) != 0);
 }
 
-// one run's partial into the tile's LDS table; no free slot within the probe
-// limit spills it straight to the HBM table
+// one contribution to key's group in the tile's LDS table; no free slot within
+// the probe limit spills it straight to the HBM table
 template <int LHS>
-__device__ __forceinline__ void run_insert(u64* s_hkey, LSlot* s_h, GEntry* tab, u64 gmask, GridMeta* meta, u64 key,
-                                           const RunPart& p)
+__device__ __forceinline__ void slot_insert(u64* s_hkey, LSlot* s_h, GEntry* tab, u64 gmask, GridMeta* meta, u64 key,
+                                            const Fx192& sum, u32 count, u32 nj, u32 mn, u32 mx)
 {
     u64 h = mix64(key) & (LHS - 1);
     for (int probe = 0; probe < LHS_PROBES; ++probe) {
@@ -129,22 +165,31 @@ __device__ __forceinline__ void run_insert(u64* s_hkey, LSlot* s_h, GEntry* tab,
         if (cur == key) {
             LSlot& sl = s_h[h];
             u64 c[4];
-            fx_to_cs(p.sum, c);
+            fx_to_cs(sum, c);
             for (int i = 0; i < 4; ++i)
                 if (c[i]) atomicAdd((unsigned long long*)&sl.cs[i], (unsigned long long)c[i]);
-            atomicAdd(&sl.count, p.count);
-            if (p.nj) atomicAdd(&sl.nj, p.nj);
-            atomicMin(&sl.mn, p.mn);
-            atomicMax(&sl.mx, p.mx);
+            if (count) atomicAdd(&sl.count, count);
+            if (nj) atomicAdd(&sl.nj, nj);
+            if (mn != ~0u) atomicMin(&sl.mn, mn);
+            if (mx) atomicMax(&sl.mx, mx);
             return;
         }
         h = (h + 1) & (LHS - 1);
     }
-    g_insert(tab, gmask, meta, key, p.count, p.nj, p.sum, p.mn, p.mx);
+    g_insert(tab, gmask, meta, key, count, nj, sum, mn, mx);
 }
 
 template <int LHS>
-__global__ void __launch_bounds__(GB)
+__device__ __forceinline__ void run_insert(u64* s_hkey, LSlot* s_h, GEntry* tab, u64 gmask, GridMeta* meta, u64 key,
+                                           const RunPart& p)
+{
+    slot_insert<LHS>(s_hkey, s_h, tab, gmask, meta, key, run_sum192(p), p.cn & 0xFFFFu, p.cn >> 16, p.mn, p.mx);
+}
+
+// three workgroups per CU fit the LDS of the 256-slot table: the register
+// budget is set to match
+template <int LHS>
+__global__ void __launch_bounds__(GB) __attribute__((amdgpu_waves_per_eu(3)))
 k_grid_agg(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, const double* __restrict__ lat,
            const double* __restrict__ lon, const float* __restrict__ spd, Spec g, GEntry* __restrict__ tab, u64 gmask,
            GridMeta* meta)
@@ -157,8 +202,12 @@ k_grid_agg(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, const
     __shared__ u64 s_hkey[LHS];
     __shared__ LSlot s_h[LHS];
     __shared__ u32 s_tmp[GB / WAVE];
-    __shared__ u32 s_flag;
     __shared__ u32 s_nlist;
+    constexpr int NWG = GB / WAVE;
+    __shared__ i64 s_lj[HALO / GB + GI][NWG], s_ltb[HALO / GB + GI][NWG];  // wave row ends
+    __shared__ i64 s_ltbs[HALO / GB + GI][NWG];                             // wave row starts
+    __shared__ i64 s_pj, s_ptb;  // the record before the first row
+    __shared__ int s_lo;
     __shared__ u64 s_out[GB / WAVE];
 
     const int t = threadIdx.x;
@@ -174,87 +223,116 @@ k_grid_agg(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, const
         z.mx = 0;
         s_h[i] = z;
     }
-    // tile records (striped, coalesced): key, segment-start bit, speed.  A
-    // record's predecessor is the lane below (lane 0 reads its own); shards are
-    // found from the tile's first one forward.
-    u64 n_out = 0;
-    const u32 sh0 = g.S > 1 ? shard_of(g.soff, g.S, tile0) : 0u;
+    // The tile's records and the HALO records before it (rows of GB, striped,
+    // coalesced): every column is loaded first, so that all loads are in flight
+    // together; then keys, speeds and segment-start bits.  A record's
+    // predecessor is the lane below; lane 0 takes it from lane 63 of the wave
+    // row before (through LDS), the first row's from memory.  Shards are found
+    // from the first row's one forward.
+    constexpr int HR = HALO / GB;  // halo rows
+    constexpr int NR = HR + GI;    // rows loaded
     const int lane = lane_id();
+    const int w = t / WAVE;
+    const long base = (long)tile0 - HALO;  // record of LDS position 0
+    i64 vj[NR], vt[NR];
+    double vla[NR], vlo[NR];
+    float vsp[GI];
 #pragma unroll
-    for (int ii = 0; ii < GI; ++ii) {
-        const int i = ii * GB + t;
-        const u64 r = tile0 + i;
-        i64 k = -1, j = 0, tb = 0;
-        float sp = 0.f;
+    for (int rr = 0; rr < NR; ++rr) {
+        // positions outside [0, n) read a record in range (ignored below): no
+        // branches between the loads
+        long r = base + rr * GB + t;
+        r = r < 0 ? 0 : (r < (long)n ? r : (long)n - 1);
+        vj[rr] = jid[r];
+        vt[rr] = ts[r];
+        vla[rr] = lat[r];
+        vlo[rr] = lon[r];
+        if (rr >= HR) vsp[rr - HR] = spd[r];
+    }
+    if (t == 0) {
+        s_pj = base > 0 ? jid[base - 1] : 0;
+        s_ptb = base > 0 ? floor_div64(ts[base - 1] - g.t0, g.bin_ms) : 0;
+        s_lo = -1;
+    }
+    u64 n_out = 0;
+    const u32 sh0 = g.S > 1 ? shard_of(g.soff, g.S, (u64)(base > 0 ? base : 0)) : 0u;
+    uint8_t seg_b[NR];
+#pragma unroll
+    for (int rr = 0; rr < NR; ++rr) {
+        const int q = rr * GB + t;
+        const long r = base + q;
+        const bool in = r >= 0 && r < (long)n;
+        i64 k = -1, tb = 0;
         u32 sh = sh0;
-        if (r < n) {
+        if (in) {
             if (g.S > 1)
-                while (sh + 1 < g.S && g.soff[sh + 1] <= r) ++sh;
-            j = jid[r];
-            k = grid_key_in(g, sh, ts[r], lat[r], lon[r], tb);
-            n_out += (k < 0);
-            sp = spd[r];
+                while (sh + 1 < g.S && g.soff[sh + 1] <= (u64)r) ++sh;
+            k = grid_key_in(g, sh, vt[rr], vla[rr], vlo[rr], tb);
+            if (rr >= HR) n_out += (k < 0);
         }
-        i64 jp = __shfl_up(j, 1, WAVE);
-        i64 tbp = __shfl_up(tb, 1, WAVE);
-        if (lane == 0 && r < n && r > 0) {
-            jp = jid[r - 1];
-            tbp = floor_div64(ts[r - 1] - g.t0, g.bin_ms);
+        const i64 jp = __shfl_up(vj[rr], 1, WAVE);
+        const i64 tbp = __shfl_up(tb, 1, WAVE);
+        if (lane == WAVE - 1) {
+            s_lj[rr][w] = vj[rr];
+            s_ltb[rr][w] = tb;
         }
-        const bool seg = r == 0 || j != jp || tb != tbp || (g.S > 1 && g.soff[sh] == r);
-        s_key[HALO + i] = k;
-        s_bits[HALO + i] = (r >= n || seg) ? B_SEG : 0;
-        s_spd[i] = sp;
+        // lane 0's bit is completed below, once lane 63 of the row before is in LDS
+        const bool seg = r == 0 || (lane > 0 && (vj[rr] != jp || tb != tbp)) || (g.S > 1 && g.soff[sh] == (u64)r);
+        seg_b[rr] = (!in || seg) ? B_SEG : 0;
+        if (lane == 0) s_ltbs[rr][w] = tb;
+        s_key[q] = k;
+        if (rr >= HR) s_spd[q - HALO] = in ? vsp[rr - HR] : 0.f;
     }
-    if (t == 0) s_flag = 0;
     __syncthreads();
-    // halo, loaded backwards in rows of GB until a segment start shows up
-    int lo_bound = HALO;
-    bool exhausted = false;
-    if (!(s_bits[HALO] & B_SEG)) {
-        while (true) {
-            if (lo_bound - GB < 0) {
-                exhausted = true;
-                break;
-            }
-            const int q = lo_bound - GB + t;
-            const long r = (long)tile0 - HALO + q;
-            i64 k = -1;
-            uint8_t b = B_SEG;
-            if (r >= 0) {
-                i64 tb;
-                k = grid_key(g, (u64)r, ts[r], lat[r], lon[r], tb);
-                b = seg_start(g, jid, ts, (u64)r, tb) ? B_SEG : 0;
-            }
-            s_key[q] = k;
-            s_bits[q] = b;
-            if (b) atomicOr(&s_flag, 1u);
-            __syncthreads();
-            const bool found = s_flag != 0;
-            lo_bound -= GB;
-            __syncthreads();
-            if (found) break;
+    int lo_cand = -1;
+#pragma unroll
+    for (int rr = 0; rr < NR; ++rr) {
+        const int q = rr * GB + t;
+        const long r = base + q;
+        uint8_t b = seg_b[rr];
+        if (lane == 0 && r > 0 && r < (long)n && !b) {
+            // predecessor: lane 63 of the previous wave row
+            const bool first_row = w == 0 && rr == 0;
+            const int pr = w > 0 ? rr : rr - 1;
+            const int pw = w > 0 ? w - 1 : NWG - 1;
+            const i64 pj = first_row ? s_pj : s_lj[pr][pw];
+            const i64 ptb = first_row ? s_ptb : s_ltb[pr][pw];
+            if (vj[rr] != pj || s_ltbs[rr][w] != ptb) b = B_SEG;
         }
-    }
-    // run-head bits over [lo_bound, HALO + tvalid)
-    const int qend = HALO + (int)tvalid;
-    for (int q = lo_bound + t; q < qend; q += GB) {
-        uint8_t b = s_bits[q];
-        if ((b & B_SEG) || q == lo_bound || s_key[q] != s_key[q - 1]) b |= B_RUN;
         s_bits[q] = b;
+        if (b && q <= HALO) lo_cand = q;
     }
-    if (t == 0) s_nlist = 0;
+    // the tile's first segment starts at the last segment start at or before
+    // the tile's first record; none in the halo: it starts further back
+    if (lo_cand >= 0) atomicMax(&s_lo, lo_cand);
     __syncthreads();
-    // order-preserving compaction of run heads into a list of positions
-    for (int base = lo_bound; base < qend; base += GB) {
-        const int q = base + t;
-        const bool rh = q < qend && (s_bits[q] & B_RUN);
+    const bool exhausted = s_lo < 0;
+    const int lo_bound = exhausted ? 0 : s_lo;
+    // Run heads over [lo_bound, HALO + tvalid), compacted in order into a list
+    // of positions: every thread marks and counts the heads of its own
+    // contiguous stretch, one block scan places the stretches.
+    const int qend = HALO + (int)tvalid;
+    {
+        const int span = qend - lo_bound;
+        const int per = (span + GB - 1) / GB;
+        const int q0 = lo_bound + t * per;
+        const int q1 = q0 + per < qend ? q0 + per : qend;
+        u32 cnt = 0;
+        for (int q = q0; q < q1; ++q) {
+            uint8_t b = s_bits[q];
+            if ((b & B_SEG) || q == lo_bound || s_key[q] != s_key[q - 1]) {
+                b |= B_RUN;
+                ++cnt;
+            }
+            s_bits[q] = b;
+        }
         u32 tot;
-        const u32 e = block_exclusive_sum<GB>(rh ? 1u : 0u, s_tmp, tot);
-        const u32 at = s_nlist;
-        if (rh) s_lpos[at + e] = (uint16_t)(q | ((s_bits[q] & B_SEG) ? 0x8000 : 0));
-        __syncthreads();
-        if (t == 0) s_nlist = at + tot;
+        u32 at = block_exclusive_sum<GB>(cnt, s_tmp, tot);
+        for (int q = q0; q < q1; ++q) {
+            const uint8_t b = s_bits[q];
+            if (b & B_RUN) s_lpos[at++] = (uint16_t)(q | ((b & B_SEG) ? 0x8000 : 0));
+        }
+        if (t == 0) s_nlist = tot;
         __syncthreads();
     }
     const int L = (int)s_nlist;
@@ -300,10 +378,14 @@ k_grid_agg(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, const
     }
     __syncthreads();
     // Aggregation: every wave walks its GT/4 records of the tile in windows of
-    // 64.  Lanes fold records into a private partial while the window holds no
-    // run start; a window with starts closes the open run (wave reduction) and
-    // scans the runs that begin in it (segmented scan); each finished run is one
-    // LDS hash insert.  A wave's first record starts a piece of its own.
+    // 64.  Lanes fold records into a private partial of the open run while the
+    // window holds no run start.  A window with starts closes the open run
+    // (one wave reduction over every lane's partial and the records before the
+    // first start), reduces the runs that begin and end inside it (segmented
+    // scan, only when there are two or more starts), and leaves the run of its
+    // last start open as the private partials of that start's lanes.  Each
+    // finished run is one LDS hash insert.  A wave's first record starts a
+    // piece of its own.
     {
         constexpr int WREC = GT / (GB / WAVE);
         const int w = t / WAVE, l = lane_id();
@@ -321,9 +403,16 @@ k_grid_agg(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, const
             run_reset(c);
             if (valid && k >= 0) {
                 const float sp = s_spd[q - HALO];
-                c.count = 1;
-                c.nj = (b & B_FIRST) ? 1u : 0u;
-                c.sum = fx_from_double<FX_SPD>((double)sp);
+                i64 x;
+                if (spd_fix53(sp, x)) {
+                    c.lo = (u64)x;
+                    c.hi = (u64)(x >> 63);
+                } else {
+                    // a speed outside the 128-bit range: its exact value on its own
+                    slot_insert<LHS>(s_hkey, s_h, tab, gmask, meta, (u64)k, fx_from_double<FX_SPD>((double)sp), 0u,
+                                     0u, ~0u, 0u);
+                }
+                c.cn = 1u | ((b & B_FIRST) ? (1u << 16) : 0u);
                 c.mn = c.mx = ord_f32(sp);
             }
             const u64 H = __ballot(head);
@@ -332,21 +421,28 @@ k_grid_agg(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, const
                 continue;
             }
             const int f0 = __ffsll((long long)H) - 1;
-            if (l < f0) run_combine(p, c);
-            run_wave_reduce(p);
-            if (l == 0 && open_key >= 0 && p.count) run_insert<LHS>(s_hkey, s_h, tab, gmask, meta, (u64)open_key, p);
-            RunPart sc = c;
-            run_seg_scan(sc, head);
-            const bool next_head = (l < WAVE - 1) && ((H >> (l + 1)) & 1ull);
-            // key of the run each lane belongs to: the key of its head lane
-            if (l >= f0 && next_head && k >= 0 && sc.count) run_insert<LHS>(s_hkey, s_h, tab, gmask, meta, (u64)k, sc);
-            const int lh = 63 - __clzll((long long)H);  // last head lane: the run left open
+            const int lh = 63 - __clzll((long long)H);  // last start: its run stays open
+            // close the open run: every lane's partial and the records before the first start
+            RunPart x = p;
+            if (l < f0) run_combine(x, c);
+            run_wave_reduce(x);
+            if (l == 0 && open_key >= 0 && x.cn) run_insert<LHS>(s_hkey, s_h, tab, gmask, meta, (u64)open_key, x);
+            // runs between two starts of this window
+            if (f0 != lh) {
+                RunPart y;
+                if (l >= f0 && l < lh) y = c;
+                else run_reset(y);
+                run_seg_scan(y, head);
+                const bool next_head = (l < WAVE - 1) && ((H >> (l + 1)) & 1ull);
+                if (l >= f0 && l < lh && next_head && k >= 0 && y.cn)
+                    run_insert<LHS>(s_hkey, s_h, tab, gmask, meta, (u64)k, y);
+            }
             open_key = __shfl(k, lh, WAVE);
-            run_reset(p);
-            if (l == WAVE - 1) p = sc;
+            if (l >= lh) p = c;
+            else run_reset(p);
         }
         run_wave_reduce(p);
-        if (l == 0 && open_key >= 0 && p.count) run_insert<LHS>(s_hkey, s_h, tab, gmask, meta, (u64)open_key, p);
+        if (l == 0 && open_key >= 0 && p.cn) run_insert<LHS>(s_hkey, s_h, tab, gmask, meta, (u64)open_key, p);
     }
     // out-of-grid count (one global atomic per tile, only when non-zero)
 #pragma unroll

@@ -147,11 +147,16 @@ __device__ __forceinline__ void g_merge(GEntry& e, u32 count, u32 nj, const Fx19
     __hip_atomic_fetch_max(&e.mx, mx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Probe limit of the HBM table.  Tables are sized to at most half full, where
+// linear-probing runs are a few slots long; a table that is (nearly) full
+// reports overflow after this many probes instead of scanning all its slots.
+constexpr u64 G_PROBES = 4096;
+
 __device__ __forceinline__ void g_insert(GEntry* tab, u64 mask, GridMeta* meta, u64 key, u32 count, u32 nj,
                                          const Fx192& sum, u32 mn, u32 mx)
 {
     u64 h = mix64(key) & mask;
-    for (u64 probe = 0; probe <= mask; ++probe) {
+    for (u64 probe = 0; probe <= mask && probe < G_PROBES; ++probe) {
         u64 cur = tab[h].key;
         if (cur == key) {
             g_merge(tab[h], count, nj, sum, mn, mx);

@@ -150,17 +150,29 @@ k_radix_pass(const u64* __restrict__ keys_in, const u32* __restrict__ vals_in, u
             lb_publish(st, rs_word(2, tag, tcount));
         } else {
             lb_publish(st, rs_word(1, tag, tcount));
+            // Look back LBW tiles at a time (their status words read together):
+            // take aggregates in order up to the first inclusive prefix; stop
+            // early at a tile that has not published yet and read again from it.
+            constexpr int LBW = 4;
             long t = (long)tile - 1;
-            while (t >= 0) {
-                u64 wv = lb_peek(status + (u64)t * RADIX + d);
-                u32 hdr = (u32)(wv >> 56);
-                if ((hdr & 63u) != tag) {
-                    __builtin_amdgcn_s_sleep(1);
-                    continue;
+            bool done = false;
+            while (!done) {
+                u64 wv[LBW];
+#pragma unroll
+                for (int j = 0; j < LBW; ++j)
+                    wv[j] = t - j >= 0 ? lb_peek(status + (u64)(t - j) * RADIX + d) : 0ull;
+                int used = 0;
+#pragma unroll
+                for (int j = 0; j < LBW; ++j) {
+                    if (done || used < j) break;  // stopped earlier in this batch
+                    const u32 hdr = (u32)(wv[j] >> 56);
+                    if (t - j < 0 || (hdr & 63u) != tag) break;
+                    excl += wv[j] & ((1ull << 56) - 1);
+                    used = j + 1;
+                    if ((hdr >> 6) == 2u) done = true;
                 }
-                excl += wv & ((1ull << 56) - 1);
-                if ((hdr >> 6) == 2u) break;
-                --t;
+                t -= used;
+                if (!done && used < LBW) __builtin_amdgcn_s_sleep(1);
             }
             lb_publish(st, rs_word(2, tag, excl + tcount));
         }

@@ -192,6 +192,11 @@ __global__ void __launch_bounds__(256) k_dict_rank(const u64* __restrict__ sorte
 // Waves walk contiguous windows of 64 records, so the journey-rank digits of a
 // window are usually equal in every lane: such a digit is counted with one LDS
 // add instead of 64 colliding ones.
+// Each wave takes PW windows of 64 records per round, their ids and times
+// loaded together.  SHARDS = false compiles the plain form without the shard
+// search.
+constexpr int PW = 4;
+template <bool SHARDS>
 __global__ void __launch_bounds__(256) k_pack_hist(const i64* __restrict__ jid, const i64* __restrict__ ts, u32 n,
                                                    const u64* __restrict__ table, const u32* __restrict__ ranks,
                                                    u64 mask, const SortMeta* m, u64* __restrict__ keys,
@@ -208,32 +213,57 @@ __global__ void __launch_bounds__(256) k_pack_hist(const i64* __restrict__ jid, 
     const u64 tmin = (u64)unord_i64(m->tmin_ord);
     const int l = lane_id();
     const u64 nw = (u64)gridDim.x * (blockDim.x / WAVE);
-    for (u64 wi = (u64)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE; wi * WAVE < n; wi += nw) {
-        const u64 i = wi * WAVE + l;
-        const bool valid = i < n;
-        u64 key = 0;
-        if (valid) {
-            const u64 j = (u64)jid[i];
-            u32 r = 0;
-            if (j != EMPTY) {
-                const u64 s = dict_find(table, mask, j);
-                r = (s != ~0ull) ? ranks[s] : 0u;
-            }
-            if (!bad) {
-                key = (tb >= 64 ? 0ull : ((u64)r << tb)) | ((u64)ts[i] - tmin);
-                if (S > 1) key |= (u64)shard_of(soff, S, i) << (m->rank_bits + tb);
-            }
-            keys[i] = packed ? ((key << ib) | i) : key;
+    const u64 nwin = ((u64)n + WAVE - 1) / WAVE;
+    for (u64 w0 = (u64)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE; w0 < nwin; w0 += PW * nw) {
+        u64 jv[PW], tv[PW];
+#pragma unroll
+        for (int k = 0; k < PW; ++k) {
+            u64 i = (w0 + k * nw) * WAVE + l;
+            i = i < n ? i : (u64)n - 1;  // past the end: a valid record, not used
+            jv[k] = (u64)jid[i];
+            tv[k] = (u64)ts[i];
         }
-        const u64 vm = __ballot(valid);
-        const int lead = __ffsll((long long)vm) - 1;
-        for (u32 p = 0; p < np; ++p) {
-            const u32 d = (u32)(key >> (p * RADIX_BITS)) & (RADIX - 1);
-            const u32 d0 = __shfl(d, lead, WAVE);
-            if (__ballot(valid && d != d0) == 0) {
-                if (l == lead) atomicAdd(&s_h[p * RADIX + d0], (u32)__popcll(vm));
-            } else if (valid) {
-                atomicAdd(&s_h[p * RADIX + d], 1u);
+#pragma unroll
+        for (int k = 0; k < PW; ++k) {
+            const u64 wi = w0 + k * nw;
+            if (wi >= nwin) break;
+            const u64 i = wi * WAVE + l;
+            const bool valid = i < n;
+            // only the first lane of each run of equal ids probes the dictionary;
+            // the others take its rank
+            const u64 j = valid ? jv[k] : EMPTY;
+            const u64 jp = __shfl_up(j, 1, WAVE);
+            const bool runhead = l == 0 || j != jp;
+            u32 r = 0;
+            if (valid && runhead && j != EMPTY) {
+                const u64 sl = dict_find(table, mask, j);
+                r = (sl != ~0ull) ? ranks[sl] : 0u;
+            }
+            const u64 heads = __ballot(runhead);
+            r = __shfl(r, 63 - __clzll((long long)(heads & (~0ull >> (63 - l)))), WAVE);
+            u64 key = 0;
+            if (valid) {
+                if (!bad) {
+                    key = (tb >= 64 ? 0ull : ((u64)r << tb)) | (tv[k] - tmin);
+                    if (SHARDS) {
+                        // the window's first shard, then forward to this record's
+                        u32 sh = shard_of(soff, S, wi * WAVE);
+                        while (sh + 1 < S && soff[sh + 1] <= i) ++sh;
+                        key |= (u64)sh << (m->rank_bits + tb);
+                    }
+                }
+                keys[i] = packed ? ((key << ib) | i) : key;
+            }
+            const u64 vm = __ballot(valid);
+            const int lead = __ffsll((long long)vm) - 1;
+            for (u32 p = 0; p < np; ++p) {
+                const u32 d = (u32)(key >> (p * RADIX_BITS)) & (RADIX - 1);
+                const u32 d0 = __shfl(d, lead, WAVE);
+                if (__ballot(valid && d != d0) == 0) {
+                    if (l == lead) atomicAdd(&s_h[p * RADIX + d0], (u32)__popcll(vm));
+                } else if (valid) {
+                    atomicAdd(&s_h[p * RADIX + d], 1u);
+                }
             }
         }
     }
@@ -242,7 +272,12 @@ __global__ void __launch_bounds__(256) k_pack_hist(const i64* __restrict__ jid, 
         if (s_h[i]) atomicAdd(&hist[i], s_h[i]);
 }
 
-// The final words are packed: (key >> 8 p0) << ib | source index.
+// The final words are packed: (key >> 8 p0) << ib | source index.  Every
+// thread takes GU records a grid stride apart per round, their loads issued
+// together.  SHARDS = false compiles the plain form without the shard search;
+// FULL = true is the form for callers that want every sorted column.
+constexpr int GU = 4;
+template <bool SHARDS, bool FULL>
 __global__ void __launch_bounds__(256) k_gather(u32 n, const SortMeta* m, const u64* __restrict__ K0,
                                                 const u64* __restrict__ K1, const u64* __restrict__ dict_sorted,
                                                 const i64* __restrict__ jid, const i64* __restrict__ ts,
@@ -269,19 +304,88 @@ __global__ void __launch_bounds__(256) k_gather(u32 n, const SortMeta* m, const 
     const u64 tmin = (u64)unord_i64(m->tmin_ord);
     const u64 tmask = tb >= 64 ? ~0ull : ((1ull << tb) - 1);
     const u64* K = (np & 1) ? K1 : K0;
-    for (u32 k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
-        const u64 w = K[k];
-        const u32 v = (u32)(w & imask);
-        // a shard keeps its records: the output position and its source share the shard
-        perm[k] = S > 1 ? v - (u32)soff[shard_of(soff, S, k)] : v;
-        if (o_jid) {
-            const u64 r = rshift >= 64 ? 0ull : ((w >> rshift) & rmask);
-            o_jid[k] = (rank_in_key && r < dn) ? (i64)(dict_sorted[r] ^ SIGN) : jid[v];
+    const u32 stride = gridDim.x * blockDim.x;
+    for (u32 k0 = blockIdx.x * blockDim.x + threadIdx.x; k0 < n; k0 += GU * stride) {
+        u64 wv[GU];
+        u32 vv[GU];
+#pragma unroll
+        for (int u = 0; u < GU; ++u) {
+            const u32 k = k0 + u * stride;
+            wv[u] = K[k < n ? k : n - 1];  // past the end: a valid word, not stored
         }
-        if (o_ts) o_ts[k] = ts_in_key ? (i64)(tmin + ((w >> ib) & tmask)) : ts[v];
-        if (o_lat) o_lat[k] = lat[v];
-        if (o_lon) o_lon[k] = lon[v];
-        if (o_spd) o_spd[k] = spd[v];
+#pragma unroll
+        for (int u = 0; u < GU; ++u) vv[u] = (u32)(wv[u] & imask);
+        if constexpr (FULL) {
+            // every column requested: all gathers issued before the first store
+            double ola[GU], olo[GU];
+            float osp[GU];
+            i64 oj[GU], ot[GU];
+#pragma unroll
+            for (int u = 0; u < GU; ++u) {
+                ola[u] = lat[vv[u]];
+                olo[u] = lon[vv[u]];
+                osp[u] = spd[vv[u]];
+            }
+            if (rank_in_key) {
+#pragma unroll
+                for (int u = 0; u < GU; ++u) {
+                    u64 r = rshift >= 64 ? 0ull : ((wv[u] >> rshift) & rmask);
+                    r = r < dn ? r : dn - 1;
+                    oj[u] = (i64)(dict_sorted[r] ^ SIGN);
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < GU; ++u) oj[u] = jid[vv[u]];
+            }
+            if (ts_in_key) {
+#pragma unroll
+                for (int u = 0; u < GU; ++u) ot[u] = (i64)(tmin + ((wv[u] >> ib) & tmask));
+            } else {
+#pragma unroll
+                for (int u = 0; u < GU; ++u) ot[u] = ts[vv[u]];
+            }
+#pragma unroll
+            for (int u = 0; u < GU; ++u) {
+                const u32 k = k0 + u * stride;
+                if (k >= n) break;
+                u32 pv = vv[u];
+                if (SHARDS) {
+                    // a shard keeps its records: the output position and its source share the shard
+                    u32 sh = shard_of(soff, S, k - threadIdx.x);  // the block row's first shard, then forward
+                    while (sh + 1 < S && soff[sh + 1] <= k) ++sh;
+                    pv -= (u32)soff[sh];
+                }
+                perm[k] = pv;
+                o_jid[k] = oj[u];
+                o_ts[k] = ot[u];
+                o_lat[k] = ola[u];
+                o_lon[k] = olo[u];
+                o_spd[k] = osp[u];
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < GU; ++u) {
+                const u32 k = k0 + u * stride;
+                if (k >= n) break;
+                const u64 w = wv[u];
+                const u32 v = vv[u];
+                u32 pv = v;
+                if (SHARDS) {
+                    u32 sh = shard_of(soff, S, k - threadIdx.x);
+                    while (sh + 1 < S && soff[sh + 1] <= k) ++sh;
+                    pv = v - (u32)soff[sh];
+                }
+                perm[k] = pv;
+                if (o_jid) {
+                    const u64 r = rshift >= 64 ? 0ull : ((w >> rshift) & rmask);
+                    o_jid[k] = (rank_in_key && r < dn) ? (i64)(dict_sorted[r] ^ SIGN) : jid[v];
+                }
+                if (o_ts) o_ts[k] = ts_in_key ? (i64)(tmin + ((w >> ib) & tmask)) : ts[v];
+                if (o_lat) o_lat[k] = lat[v];
+                if (o_lon) o_lon[k] = lon[v];
+                if (o_spd) o_spd[k] = spd[v];
+            }
+        }
     }
 }
 
@@ -411,15 +515,18 @@ static cv_status sort_impl(const cv_records* in, const uint64_t* soff, uint32_t 
                      L.meta->tickets + MAX_PASSES, s);
         hipLaunchKernelGGL(k_dict_rank, dim3(cvh::grid_for(max_journeys, 256, 1024)), dim3(256), 0, s, L.dl0, L.meta,
                            L.table, mask, L.ranks);
-        hipLaunchKernelGGL(k_pack_hist, dim3(gs), dim3(256), 0, s, in->journey_id, in->ts_ms, nn, L.table, L.ranks,
-                           mask, L.meta, L.K0, L.hist, soff, S);
+        hipLaunchKernelGGL(S > 1 ? k_pack_hist<true> : k_pack_hist<false>, dim3(gs), dim3(256), 0, s, in->journey_id,
+                           in->ts_ms, nn, L.table, L.ranks, mask, L.meta, L.K0, L.hist, soff, S);
         radix_scan(L.hist, L.offs, MAX_PASSES, s);
     }
     radix_passes(L.K0, L.K1, nullptr, L.V0, L.V1, nn, nullptr, &L.meta->key_bits, MAX_PASSES, L.offs, L.status,
                  L.meta->tickets, s, /*timed=*/true, &L.meta->ib);
     {
         cvh::TimedScope ts_("gather", s);
-        hipLaunchKernelGGL(k_gather, dim3(cvh::grid_for(n, 256, 8192)), dim3(256), 0, s, nn, L.meta, L.K0, L.K1, L.dl0,
+        const bool full = so.journey_id && so.ts_ms && so.lat_deg && so.lon_deg && so.speed_mps;
+        auto gk = S > 1 ? (full ? k_gather<true, true> : k_gather<true, false>)
+                        : (full ? k_gather<false, true> : k_gather<false, false>);
+        hipLaunchKernelGGL(gk, dim3(cvh::grid_for(n, 256, 8192)), dim3(256), 0, s, nn, L.meta, L.K0, L.K1, L.dl0,
                            in->journey_id, in->ts_ms, in->lat_deg, in->lon_deg, in->speed_mps, perm,
                            so.journey_id, so.ts_ms, so.lat_deg, so.lon_deg, so.speed_mps, soff, S);
     }

@@ -14,6 +14,8 @@
 //   k_sum_finalize accumulator rows -> output rows (exact sums rounded once).
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "cv_device.h"
 #include "cv_host.h"
 
@@ -32,7 +34,12 @@ struct JAcc {
     u64 spd[3];
     u64 maxd;
     u64 latmin, latmax, lonmin, lonmax;
-    u32 count, ndtz, maxs, touched;
+    u32 count, ndtz, maxs, gfirst;  // gfirst: index of the journey's first record
+};
+
+// side row of a journey: sums of the values outside the 128-bit fast formats
+struct AccX {
+    u64 dist[3], spd[3];
 };
 
 struct SumMeta {
@@ -45,15 +52,15 @@ constexpr int WCH = WAVE * WI; // records per wave
 static_assert(ST == NW * WCH, "tile = waves x wave chunk");
 
 // Journey starts among the records of window [a, a + 64) of a wave that walks
-// consecutive windows: jprev is the id before the window (carried), sk the
-// shard cursor.  Returns the lane mask of starts; jv is this lane's id.
-__device__ __forceinline__ u64 window_heads(const i64* __restrict__ jid, u64 a, u64 end, i64& jprev, i64& jv,
-                                            const u64* __restrict__ soff, u32 S, u32& sk, u64& smask, bool& s_end)
+// consecutive windows, from this lane's id jv (already loaded): jprev is the
+// id before the window (carried), sk the shard cursor.  Returns the lane mask
+// of starts.
+__device__ __forceinline__ u64 heads_of(i64 jv, u64 a, u64 end, i64& jprev, const u64* __restrict__ soff, u32 S,
+                                        u32& sk, u64& smask, bool& s_end)
 {
     const int l = lane_id();
     const u64 r = a + l;
     const bool valid = r < end;
-    jv = valid ? jid[r] : 0;
     i64 jp = __shfl_up(jv, 1, WAVE);
     if (l == 0) jp = jprev;
     jprev = __shfl(jv, WAVE - 1, WAVE);
@@ -67,44 +74,46 @@ __device__ __forceinline__ u64 window_heads(const i64* __restrict__ jid, u64 a, 
 __global__ void __launch_bounds__(SB) k_sum_count(const i64* __restrict__ jid, u32 n, u32* __restrict__ wcnt,
                                                   const u64* __restrict__ soff, u32 S)
 {
-    const int w = threadIdx.x / WAVE;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);  // wave-uniform
     const u64 cs = (u64)blockIdx.x * ST + (u64)w * WCH;
     const u64 ce = cs + WCH < n ? cs + WCH : (u64)n;
     u32 c = 0;
     if (cs < ce) {
         i64 jprev = cs > 0 ? jid[cs - 1] : 0;
         u32 sk = S > 1 ? shard_lower_bound(soff, S, cs) : 0u;
+        i64 jn = cs + lane_id() < ce ? jid[cs + lane_id()] : 0;
         for (u64 a = cs; a < ce; a += WAVE) {
-            i64 jv;
+            const i64 jv = jn;
+            if (a + WAVE + lane_id() < ce) jn = jid[a + WAVE + lane_id()];  // next window, loaded ahead
             u64 sm;
             bool se;
-            c += (u32)__popcll(window_heads(jid, a, ce, jprev, jv, soff, S, sk, sm, se));
+            c += (u32)__popcll(heads_of(jv, a, ce, jprev, soff, S, sk, sm, se));
         }
     }
     if (lane_id() == 0) wcnt[(u64)blockIdx.x * NW + w] = c;
 }
 
-// single block: tile_prefix[i] = journey starts before tile i; meta->J = total
-__global__ void __launch_bounds__(256) k_tile_scan(const u32* __restrict__ wcnt, u32* __restrict__ tile_prefix,
-                                                   u32 tiles, SumMeta* meta)
+// single block: tile_prefix[i] = journey starts before tile i; meta->J = total.
+// Each thread sums a contiguous run of tiles, one block scan joins the runs.
+constexpr int SCAN_B = 1024;
+__global__ void __launch_bounds__(SCAN_B) k_tile_scan(const u32* __restrict__ wcnt, u32* __restrict__ tile_prefix,
+                                                      u32 tiles, SumMeta* meta)
 {
-    __shared__ u32 tmp[256 / WAVE];
-    __shared__ u32 carry;
-    if (threadIdx.x == 0) carry = 0;
-    __syncthreads();
-    for (u32 b = 0; b < tiles; b += 256) {
-        u32 i = b + threadIdx.x;
-        u32 v = 0;
-        if (i < tiles)
-            for (int k = 0; k < NW; ++k) v += wcnt[(u64)i * NW + k];
-        u32 total;
-        u32 e = block_exclusive_sum<256>(v, tmp, total);
-        if (i < tiles) tile_prefix[i] = carry + e;
-        __syncthreads();
-        if (threadIdx.x == 0) carry += total;
-        __syncthreads();
+    __shared__ u32 tmp[SCAN_B / WAVE];
+    const u32 per = (tiles + SCAN_B - 1) / SCAN_B;
+    const u32 a = threadIdx.x * per;
+    const u32 b = a + per < tiles ? a + per : tiles;
+    u32 sum = 0;
+#pragma unroll 4
+    for (u32 i = a; i < b; ++i)
+        for (int k = 0; k < NW; ++k) sum += wcnt[(u64)i * NW + k];
+    u32 total;
+    u32 e = block_exclusive_sum<SCAN_B>(sum, tmp, total);
+    for (u32 i = a; i < b; ++i) {
+        tile_prefix[i] = e;
+        for (int k = 0; k < NW; ++k) e += wcnt[(u64)i * NW + k];
     }
-    if (threadIdx.x == 0) meta->J = carry;
+    if (threadIdx.x == 0) meta->J = total;
 }
 
 __device__ __forceinline__ void jacc_identity(JAcc& a)
@@ -119,10 +128,11 @@ __device__ __forceinline__ void jacc_identity(JAcc& a)
     a.count = 0;
     a.ndtz = 0;
     a.maxs = 0;
-    a.touched = 0;
+    a.gfirst = 0;
 }
 
-__global__ void __launch_bounds__(256) k_sum_init(JAcc* __restrict__ acc, const SumMeta* meta, u32 cap)
+__global__ void __launch_bounds__(256) k_sum_init(JAcc* __restrict__ acc, AccX* __restrict__ accx, const SumMeta* meta,
+                                                 u32 cap)
 {
     u32 J = meta->J;
     u32 m = J < cap ? J : cap;
@@ -130,90 +140,181 @@ __global__ void __launch_bounds__(256) k_sum_init(JAcc* __restrict__ acc, const 
         JAcc a;
         jacc_identity(a);
         acc[j] = a;
+        AccX x = {};
+        accx[j] = x;
     }
 }
 
-// Partial aggregate of one journey (a lane's records, a wave's, or a tile's).
-struct Part {
-    Fx192 dist, spd;
-    u64 maxd, latmin, latmax, lonmin, lonmax;
-    u32 count, ndtz, maxs;
+// Partial aggregates of one journey (a lane's records, a wave's, or a tile's),
+// in two field groups reduced by two launches of the same kernel: the record
+// count with the bounding box, and the exact sums with the zero-dt count and
+// the maxima.  Each launch keeps only its group live, which keeps its
+// register use (and so the waves in flight per SIMD) in bounds.
+struct PartBox {
+    u64 latmin, latmax, lonmin, lonmax;
+    u32 count;
+};
+// The sums are 128-bit two's-complement integers: distance in units of 2^-72
+// m, exact for steps of at least 2^-20 m (and zero); speed in units of 2^-53,
+// exact for float32 speeds v with 2^-30 <= |v| < 2^10 (and zeros).  Any other
+// value is added on its own, in the full 192-bit format, to the journey's
+// side row (AccX).
+struct PartSum {
+    u64 dlo, dhi, slo, shi;
+    u64 maxd;
+    u32 ndtz, maxs, n;  // n: records folded in (empty partials are not flushed)
 };
 
-__device__ __forceinline__ void part_reset(Part& p)
+__device__ __forceinline__ void add128(u64& lo, u64& hi, u64 blo, u64 bhi)
 {
-    fx_zero(p.dist);
-    fx_zero(p.spd);
-    p.maxd = ord_f64(0.0);
+    const u64 s = lo + blo;
+    hi += bhi + (s < lo ? 1ull : 0ull);
+    lo = s;
+}
+
+// v * 2^72 as a 128-bit integer when 2^-20 <= |v| < 2^40 or v = +-0
+__device__ __forceinline__ bool dist_fix72(double v, u64& lo, u64& hi)
+{
+    const u64 b = (u64)__double_as_longlong(v);
+    const u32 e = (u32)((b >> 52) & 0x7FFu);
+    const u64 m = b & ((1ull << 52) - 1);
+    lo = 0;
+    hi = 0;
+    if (e == 0) return m == 0;
+    if (e < 1003 || e > 1062) return false;
+    const u64 M = m | (1ull << 52);
+    const u32 sft = e - 1003;  // 0 .. 59
+    lo = M << sft;
+    hi = sft ? (M >> (64 - sft)) : 0ull;
+    if (b >> 63) {
+        lo = ~lo + 1;
+        hi = ~hi + (lo == 0 ? 1ull : 0ull);
+    }
+    return true;
+}
+
+// v * 2^53 as a signed integer when 2^-30 <= |v| < 2^10 or v = +-0
+__device__ __forceinline__ bool spd_fix53(float v, i64& x)
+{
+    const u32 b = __float_as_uint(v);
+    const u32 e = (b >> 23) & 0xFFu;
+    const u32 m = b & 0x7FFFFFu;
+    x = 0;
+    if (e == 0) return m == 0;
+    if (e < 97 || e > 136) return false;
+    const i64 mag = (i64)((u64)(m | 0x800000u) << (e - 97));
+    x = (b >> 31) ? -mag : mag;
+    return true;
+}
+
+// the 128-bit sums in the 192-bit formats of the rows (2^-128 m, 2^-149)
+__device__ __forceinline__ Fx192 dist192(u64 lo, u64 hi)
+{
+    Fx192 r;
+    r.w[0] = lo << 56;
+    r.w[1] = (lo >> 8) | (hi << 56);
+    r.w[2] = (u64)((i64)hi >> 8);
+    return r;
+}
+__device__ __forceinline__ Fx192 spd192(u64 lo, u64 hi)
+{
+    Fx192 r;
+    r.w[0] = 0;
+    r.w[1] = lo << 32;
+    r.w[2] = (lo >> 32) | (hi << 32);
+    return r;
+}
+
+__device__ __forceinline__ void part_reset(PartBox& p)
+{
     p.latmin = ord_f64(__builtin_inf());
     p.latmax = ord_f64(-__builtin_inf());
     p.lonmin = ord_f64(__builtin_inf());
     p.lonmax = ord_f64(-__builtin_inf());
     p.count = 0;
+}
+__device__ __forceinline__ void part_reset(PartSum& p)
+{
+    p.dlo = p.dhi = p.slo = p.shi = 0;
+    p.maxd = ord_f64(0.0);
     p.ndtz = 0;
     p.maxs = 0;
+    p.n = 0;
 }
 
-__device__ __forceinline__ void part_combine(Part& a, const Part& b)
+__device__ __forceinline__ void part_combine(PartBox& a, const PartBox& b)
 {
-    fx_add(a.dist, b.dist);
-    fx_add(a.spd, b.spd);
-    a.maxd = b.maxd > a.maxd ? b.maxd : a.maxd;
     a.latmin = b.latmin < a.latmin ? b.latmin : a.latmin;
     a.latmax = b.latmax > a.latmax ? b.latmax : a.latmax;
     a.lonmin = b.lonmin < a.lonmin ? b.lonmin : a.lonmin;
     a.lonmax = b.lonmax > a.lonmax ? b.lonmax : a.lonmax;
     a.count += b.count;
+}
+__device__ __forceinline__ void part_combine(PartSum& a, const PartSum& b)
+{
+    add128(a.dlo, a.dhi, b.dlo, b.dhi);
+    add128(a.slo, a.shi, b.slo, b.shi);
+    a.maxd = b.maxd > a.maxd ? b.maxd : a.maxd;
     a.ndtz += b.ndtz;
     a.maxs = b.maxs > a.maxs ? b.maxs : a.maxs;
+    a.n += b.n;
 }
 
 // Cross-lane steps work one field at a time, so that only that field's
-// shuffled copy is live next to the partial.
-__device__ __forceinline__ u64 shfl_xor64(u64 v, int d) { return (u64)__shfl_xor((unsigned long long)v, d, WAVE); }
-__device__ __forceinline__ u64 shfl_up64(u64 v, int d) { return (u64)__shfl_up((unsigned long long)v, d, WAVE); }
-
-// full wave reduction; every lane ends with the total
-__device__ __forceinline__ void part_wave_reduce(Part& p)
+// shuffled copy is live next to the partial.  A step of distance d takes the
+// lane d away (xor for the full reduction, below for the segmented scan);
+// `take` says whether the step folds it in.
+__device__ __forceinline__ u64 shfl64(u64 v, int d, bool up)
 {
-#pragma unroll
-    for (int d = 1; d < WAVE; d <<= 1) {
-        Fx192 o;
-        for (int i = 0; i < 3; ++i) o.w[i] = shfl_xor64(p.dist.w[i], d);
-        fx_add(p.dist, o);
-    }
-#pragma unroll
-    for (int d = 1; d < WAVE; d <<= 1) {
-        Fx192 o;
-        for (int i = 0; i < 3; ++i) o.w[i] = shfl_xor64(p.spd.w[i], d);
-        fx_add(p.spd, o);
-    }
-#pragma unroll
-    for (int d = 1; d < WAVE; d <<= 1) {
-        u64 v;
-        v = shfl_xor64(p.maxd, d);
-        p.maxd = v > p.maxd ? v : p.maxd;
-        v = shfl_xor64(p.latmin, d);
-        p.latmin = v < p.latmin ? v : p.latmin;
-        v = shfl_xor64(p.latmax, d);
-        p.latmax = v > p.latmax ? v : p.latmax;
-        v = shfl_xor64(p.lonmin, d);
-        p.lonmin = v < p.lonmin ? v : p.lonmin;
-        v = shfl_xor64(p.lonmax, d);
-        p.lonmax = v > p.lonmax ? v : p.lonmax;
-        u32 x;
-        x = __shfl_xor(p.count, d, WAVE);
-        p.count += x;
-        x = __shfl_xor(p.ndtz, d, WAVE);
-        p.ndtz += x;
-        x = __shfl_xor(p.maxs, d, WAVE);
-        p.maxs = x > p.maxs ? x : p.maxs;
-    }
+    return up ? (u64)__shfl_up((unsigned long long)v, d, WAVE) : (u64)__shfl_xor((unsigned long long)v, d, WAVE);
+}
+__device__ __forceinline__ u32 shfl32(u32 v, int d, bool up)
+{
+    return up ? (u32)__shfl_up(v, d, WAVE) : (u32)__shfl_xor(v, d, WAVE);
 }
 
-// segmented inclusive scan across lanes; `head` starts a segment.  Step k
-// (distance 2^k) folds in the lane 2^k below when bit k of `take` is set.
-__device__ __forceinline__ void part_seg_scan(Part& p, bool head)
+__device__ __forceinline__ void part_step(PartBox& p, int d, bool up, bool take)
+{
+    u64 v;
+    v = shfl64(p.latmin, d, up);
+    if (take && v < p.latmin) p.latmin = v;
+    v = shfl64(p.latmax, d, up);
+    if (take && v > p.latmax) p.latmax = v;
+    v = shfl64(p.lonmin, d, up);
+    if (take && v < p.lonmin) p.lonmin = v;
+    v = shfl64(p.lonmax, d, up);
+    if (take && v > p.lonmax) p.lonmax = v;
+    const u32 x = shfl32(p.count, d, up);
+    if (take) p.count += x;
+}
+__device__ __forceinline__ void part_step(PartSum& p, int d, bool up, bool take)
+{
+    const u64 dlo = shfl64(p.dlo, d, up), dhi = shfl64(p.dhi, d, up);
+    if (take) add128(p.dlo, p.dhi, dlo, dhi);
+    const u64 slo = shfl64(p.slo, d, up), shi = shfl64(p.shi, d, up);
+    if (take) add128(p.slo, p.shi, slo, shi);
+    const u64 v = shfl64(p.maxd, d, up);
+    if (take && v > p.maxd) p.maxd = v;
+    u32 x;
+    x = shfl32(p.ndtz, d, up);
+    if (take) p.ndtz += x;
+    x = shfl32(p.maxs, d, up);
+    if (take && x > p.maxs) p.maxs = x;
+    x = shfl32(p.n, d, up);
+    if (take) p.n += x;
+}
+
+// full wave reduction; every lane ends with the total
+template <class P>
+__device__ __forceinline__ void part_wave_reduce(P& p)
+{
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) part_step(p, d, false, true);
+}
+
+// segmented inclusive scan across lanes; `head` starts a segment
+template <class P>
+__device__ __forceinline__ void part_seg_scan(P& p, bool head)
 {
     const int l = lane_id();
     u32 take = 0;
@@ -227,39 +328,7 @@ __device__ __forceinline__ void part_seg_scan(Part& p, bool head)
         }
     }
 #pragma unroll
-    for (int k = 0, d = 1; d < WAVE; ++k, d <<= 1) {
-        Fx192 o;
-        for (int i = 0; i < 3; ++i) o.w[i] = shfl_up64(p.dist.w[i], d);
-        if ((take >> k) & 1u) fx_add(p.dist, o);
-    }
-#pragma unroll
-    for (int k = 0, d = 1; d < WAVE; ++k, d <<= 1) {
-        Fx192 o;
-        for (int i = 0; i < 3; ++i) o.w[i] = shfl_up64(p.spd.w[i], d);
-        if ((take >> k) & 1u) fx_add(p.spd, o);
-    }
-#pragma unroll
-    for (int k = 0, d = 1; d < WAVE; ++k, d <<= 1) {
-        const bool t = (take >> k) & 1u;
-        u64 v;
-        v = shfl_up64(p.maxd, d);
-        if (t && v > p.maxd) p.maxd = v;
-        v = shfl_up64(p.latmin, d);
-        if (t && v < p.latmin) p.latmin = v;
-        v = shfl_up64(p.latmax, d);
-        if (t && v > p.latmax) p.latmax = v;
-        v = shfl_up64(p.lonmin, d);
-        if (t && v < p.lonmin) p.lonmin = v;
-        v = shfl_up64(p.lonmax, d);
-        if (t && v > p.lonmax) p.lonmax = v;
-        u32 x;
-        x = __shfl_up(p.count, d, WAVE);
-        if (t) p.count += x;
-        x = __shfl_up(p.ndtz, d, WAVE);
-        if (t) p.ndtz += x;
-        x = __shfl_up(p.maxs, d, WAVE);
-        if (t && x > p.maxs) p.maxs = x;
-    }
+    for (int k = 0, d = 1; d < WAVE; ++k, d <<= 1) part_step(p, d, true, ((take >> k) & 1u) != 0);
 }
 
 struct Out {
@@ -294,58 +363,69 @@ __device__ __forceinline__ void write_final(const Out& o, u32 j, u32 count, u32 
 // A journey's partial into its accumulator row: a whole journey (all its
 // records are in the partial) is stored, a piece is merged with integer atomics.
 // The rows are turned into output rows by k_sum_finalize.
-__device__ __forceinline__ void flush_part(JAcc* acc, u32 cap, u32 j, const Part& p, bool whole)
+__device__ __forceinline__ void flush_part(JAcc* acc, u32 cap, u32 j, const PartBox& p, bool whole)
 {
     if (j >= cap || p.count == 0) return;
     JAcc& a = acc[j];
     if (whole) {
-        JAcc v;
-        for (int i = 0; i < 3; ++i) {
-            v.dist[i] = p.dist.w[i];
-            v.spd[i] = p.spd.w[i];
-        }
-        v.maxd = p.maxd;
-        v.latmin = p.latmin;
-        v.latmax = p.latmax;
-        v.lonmin = p.lonmin;
-        v.lonmax = p.lonmax;
-        v.count = p.count;
-        v.ndtz = p.ndtz;
-        v.maxs = p.maxs;
-        v.touched = 1;
-        a = v;
+        a.latmin = p.latmin;
+        a.latmax = p.latmax;
+        a.lonmin = p.lonmin;
+        a.lonmax = p.lonmax;
+        a.count = p.count;
         return;
     }
-    atomic_add_fx(a.dist, p.dist);
-    atomic_add_fx(a.spd, p.spd);
-    atomicMax((unsigned long long*)&a.maxd, (unsigned long long)p.maxd);
     atomicMin((unsigned long long*)&a.latmin, (unsigned long long)p.latmin);
     atomicMax((unsigned long long*)&a.latmax, (unsigned long long)p.latmax);
     atomicMin((unsigned long long*)&a.lonmin, (unsigned long long)p.lonmin);
     atomicMax((unsigned long long*)&a.lonmax, (unsigned long long)p.lonmax);
     atomicAdd(&a.count, p.count);
+}
+__device__ __forceinline__ void flush_part(JAcc* acc, u32 cap, u32 j, const PartSum& p, bool whole)
+{
+    if (j >= cap || p.n == 0) return;
+    JAcc& a = acc[j];
+    const Fx192 d = dist192(p.dlo, p.dhi), sp = spd192(p.slo, p.shi);
+    if (whole) {
+        for (int i = 0; i < 3; ++i) {
+            a.dist[i] = d.w[i];
+            a.spd[i] = sp.w[i];
+        }
+        a.maxd = p.maxd;
+        a.ndtz = p.ndtz;
+        a.maxs = p.maxs;
+        return;
+    }
+    atomic_add_fx(a.dist, d);
+    atomic_add_fx(a.spd, sp);
+    atomicMax((unsigned long long*)&a.maxd, (unsigned long long)p.maxd);
     atomicAdd(&a.ndtz, p.ndtz);
     atomicMax(&a.maxs, p.maxs);
-    atomicOr(&a.touched, 1u);
 }
 
 // Each wave owns WCH consecutive records and walks them in coalesced windows of
-// 64.  Lanes fold their records into a private partial while the window holds
+// 64, loaded a group of windows at a time.  Lanes fold their records into a private partial while the window holds
 // no journey start; a window with starts closes the open journey (wave
 // reduction), runs a segmented scan for journeys that begin in it, and hands
 // the last one on as the new open journey.  A journey that begins and ends in
-// the wave's records is written out directly; otherwise its pieces meet in the
+// the wave's records is stored directly; otherwise its pieces meet in the
 // accumulator row through integer atomics.  Neighbouring ids come from lane
-// shuffles; time stamps are read only at journey starts and ends.
+// shuffles.  BOX = true reduces PartBox and also writes each journey's id,
+// first record; BOX = false reduces PartSum.  SHARDS = false compiles the
+// plain form without the shard branches, whose loads would otherwise make
+// every window wait for all loads in flight, prefetch included.
+template <bool BOX, bool SHARDS>
 __global__ void __launch_bounds__(SB) k_sum_reduce(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts,
                                                    const double* __restrict__ lat, const double* __restrict__ lon,
                                                    const float* __restrict__ spd, const double* __restrict__ step,
                                                    const double* __restrict__ dspd, const uint8_t* __restrict__ flags,
                                                    const u32* __restrict__ tile_prefix, const u32* __restrict__ wcnt,
-                                                   u32 cap, Out o, JAcc* __restrict__ acc,
+                                                   u32 cap, Out o, JAcc* __restrict__ acc, AccX* __restrict__ accx,
                                                    const u64* __restrict__ soff, u32 S, u64* __restrict__ jo)
 {
-    const int w = threadIdx.x / WAVE;
+    using P = typename std::conditional<BOX, PartBox, PartSum>::type;
+    if (!SHARDS) S = 0;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);  // wave-uniform
     const int l = lane_id();
     const u64 cs = (u64)blockIdx.x * ST + (u64)w * WCH;  // wave chunk start
     const u64 ce = cs + WCH < n ? cs + WCH : (u64)n;      // wave chunk end (may be <= cs)
@@ -353,121 +433,136 @@ __global__ void __launch_bounds__(SB) k_sum_reduce(u32 n, const i64* __restrict_
     u32 seen = tile_prefix[blockIdx.x];  // journey starts before the current window
     for (int k = 0; k < w; ++k) seen += wcnt[(u64)blockIdx.x * NW + k];
 
-    Part p;
+    P p;
     part_reset(p);
     // open journey: the one containing the record before the next window
     u32 open_j = seen - 1;   // valid when the chunk starts mid-journey
     bool open_here = false;  // its first record lies in this chunk
     i64 jprev = cs > 0 ? jid[cs - 1] : 0;
-    u32 sk = S > 1 ? shard_lower_bound(soff, S, cs) : 0u;
-    // value columns of a window, loaded one window ahead of their use
-    struct Win {
-        double st, ds, la, lo;
-        float sp;
-        uint8_t f;
-    };
-    auto load = [&](u64 a, Win& x) {
-        const u64 r = a + l;
-        if (r < ce) {
-            x.st = step[r];
-            x.sp = spd[r];
-            x.f = flags[r];
-            x.ds = dspd[r];
-            x.la = lat[r];
-            x.lo = lon[r];
-        }
-    };
-    Win cur, nxt;
-    load(cs, cur);
-    for (int i = 0; i < WI; ++i) {
-        const u64 a = cs + (u64)i * WAVE;
-        if (a >= ce) break;
-        if (i + 1 < WI) load(a + WAVE, nxt);
-        const u64 r = a + l;
-        const bool valid = r < ce;
-        i64 jv;
-        u64 smask;
-        bool s_end;
-        const u64 H = window_heads(jid, a, ce, jprev, jv, soff, S, sk, smask, s_end);
-        const bool h = (H >> l) & 1ull;
-        // last record of its journey: the next record starts one (or there is none)
-        bool last = false;
-        if (valid) {
-            if (r + 1 >= n) last = true;
-            else if (l < WAVE - 1) last = ((H >> (l + 1)) & 1ull) != 0;
-            else last = jid[r + 1] != jv || s_end;
-        }
-        Part c;
-        part_reset(c);
-        if (valid) {
-            c.count = 1;
-            c.ndtz = (cur.f & CV_FLAG_DT_ZERO) ? 1u : 0u;
-            c.dist = fx_from_double<FX_DIST>(cur.st);
-            c.spd = fx_from_double<FX_SPD>((double)cur.sp);
-            c.maxs = ord_f32(cur.sp);
-            if (cur.f & CV_FLAG_SPEED_OK) c.maxd = ord_f64(cur.ds);
-            if (isfinite(cur.la) && isfinite(cur.lo)) {
-                c.latmin = c.latmax = ord_f64(cur.la);
-                c.lonmin = c.lonmax = ord_f64(cur.lo);
+    u32 sk = SHARDS ? shard_lower_bound(soff, S, cs) : 0u;
+    // the id after the chunk (its last record may end a journey)
+    const i64 jend = ce < n ? jid[ce] : 0;
+    // Windows are taken in groups of WG: the columns of a group (ids included)
+    // are loaded together, from addresses clamped into the chunk, so that all
+    // of a group's loads are in flight at once.
+    constexpr int WG = 4;
+    static_assert(WI % WG == 0, "whole groups");
+    for (int g0 = 0; g0 < WI; g0 += WG) {
+        if (cs + (u64)g0 * WAVE >= ce) break;
+        i64 gj[WG];
+        double gx0[WG], gx1[WG];
+        float gsp[WG];
+        uint8_t gf[WG];
+#pragma unroll
+        for (int k = 0; k < WG; ++k) {
+            u64 r = cs + (u64)(g0 + k) * WAVE + l;
+            r = r < ce ? r : ce - 1;
+            gj[k] = jid[r];
+            if constexpr (BOX) {
+                gx0[k] = lat[r];
+                gx1[k] = lon[r];
+            } else {
+                gx0[k] = step[r];
+                gx1[k] = dspd[r];
+                gsp[k] = spd[r];
+                gf[k] = flags[r];
             }
         }
-        // journey index of this lane's record
-        const u32 jl = seen + popc_below(H) + (h ? 1u : 0u) - 1u;
-        if (h && jl < cap) {
-            // a journey's first record is indexed within its shard
-            const u32 sh = S > 1 ? shard_of(soff, S, r) : 0u;
-            o.jid[jl] = jv;
-            o.first[jl] = (u32)(S > 1 ? r - soff[sh] : r);
-            o.tstart[jl] = ts[r];
+#pragma unroll
+        for (int k = 0; k < WG; ++k) {
+            const u64 a = cs + (u64)(g0 + k) * WAVE;
+            if (a >= ce) break;
+            const u64 r = a + l;
+            const bool valid = r < ce;
+            const i64 jv = gj[k];
+            u64 smask;
+            bool s_end;
+            const u64 H = heads_of(jv, a, ce, jprev, soff, S, sk, smask, s_end);
+            const bool h = (H >> l) & 1ull;
+            // journey index of this lane's record
+            const u32 jl = seen + popc_below(H) + (h ? 1u : 0u) - 1u;
+            P c;
+            part_reset(c);
+            if (valid) {
+                if constexpr (BOX) {
+                    c.count = 1;
+                    if (isfinite(gx0[k]) && isfinite(gx1[k])) {
+                        c.latmin = c.latmax = ord_f64(gx0[k]);
+                        c.lonmin = c.lonmax = ord_f64(gx1[k]);
+                    }
+                } else {
+                    c.n = 1;
+                    c.ndtz = (gf[k] & CV_FLAG_DT_ZERO) ? 1u : 0u;
+                    if (!dist_fix72(gx0[k], c.dlo, c.dhi) && jl < cap)
+                        atomic_add_fx(accx[jl].dist, fx_from_double<FX_DIST>(gx0[k]));
+                    i64 x;
+                    if (spd_fix53(gsp[k], x)) {
+                        c.slo = (u64)x;
+                        c.shi = (u64)(x >> 63);
+                    } else if (jl < cap) {
+                        atomic_add_fx(accx[jl].spd, fx_from_double<FX_SPD>((double)gsp[k]));
+                    }
+                    c.maxs = ord_f32(gsp[k]);
+                    if (gf[k] & CV_FLAG_SPEED_OK) c.maxd = ord_f64(gx1[k]);
+                }
+            }
+            if constexpr (BOX) {
+                if (h && jl < cap) {
+                    // a journey's first record is indexed within its shard
+                    const u32 sh = S > 1 ? shard_of(soff, S, r) : 0u;
+                    o.jid[jl] = jv;
+                    o.first[jl] = (u32)(S > 1 ? r - soff[sh] : r);
+                    acc[jl].gfirst = (u32)r;
+                }
+                if (h && S > 1 && jo) {
+                    // this record opens its shard's first journey: every shard
+                    // starting here (empty ones included) begins at journey jl
+                    const u32 sh = shard_of(soff, S, r);
+                    if (soff[sh] == r)
+                        for (int z = (int)sh; z >= 0 && soff[z] == r; --z) jo[z] = jl;
+                }
+            }
+            if (H != 0) {
+                const int f0 = __ffsll((long long)H) - 1;
+                if (l < f0) part_combine(p, c);
+                // close the journey that was open before the first start in this window
+                part_wave_reduce(p);
+                if (l == 0) flush_part(acc, cap, open_j, p, open_here);
+                // journeys starting in this window
+                P sc = c;
+                part_seg_scan(sc, h);
+                // a segment that ends before lane 63 (next lane starts a journey)
+                // is a whole journey: it began and ended inside this window
+                const bool next_head = (l < WAVE - 1) && ((H >> (l + 1)) & 1ull);
+                if (l >= f0 && next_head) flush_part(acc, cap, jl, sc, true);
+                // the last segment stays open; lane 63 holds its partial
+                part_reset(p);
+                if (l == WAVE - 1) p = sc;
+                seen += (u32)__popcll(H);
+                open_j = seen - 1;
+                open_here = true;
+            } else {
+                part_combine(p, c);
+            }
         }
-        if (h && S > 1 && jo) {
-            // this record opens its shard's first journey: every shard starting
-            // here (empty ones included) begins at journey jl
-            const u32 sh = shard_of(soff, S, r);
-            if (soff[sh] == r)
-                for (int z = (int)sh; z >= 0 && soff[z] == r; --z) jo[z] = jl;
-        }
-        if (last && jl < cap) o.tend[jl] = ts[r];
-        if (H != 0) {
-            const int f0 = __ffsll((long long)H) - 1;
-            if (l < f0) part_combine(p, c);
-            // close the journey that was open before the first start in this window
-            part_wave_reduce(p);
-            if (l == 0) flush_part(acc, cap, open_j, p, open_here);
-            // journeys starting in this window
-            Part s = c;
-            part_seg_scan(s, h);
-            // a segment that ends before lane 63 (next lane starts a journey) is a
-            // whole journey: it began and ended inside this window
-            const bool next_head = (l < WAVE - 1) && ((H >> (l + 1)) & 1ull);
-            if (l >= f0 && next_head) flush_part(acc, cap, jl, s, true);
-            // the last segment stays open; lane 63 holds its partial
-            part_reset(p);
-            if (l == WAVE - 1) p = s;
-            seen += (u32)__popcll(H);
-            open_j = seen - 1;
-            open_here = true;
-        } else {
-            part_combine(p, c);
-        }
-        cur = nxt;
     }
     part_wave_reduce(p);
     if (l == 0) {
-        const bool ends = (ce >= n) || (jid[ce] != jid[ce - 1]) || (S > 1 && shard_start(soff, S, ce));
+        const bool ends = (ce >= n) || (jend != jprev) || (S > 1 && shard_start(soff, S, ce));
         flush_part(acc, cap, open_j, p, open_here && ends);
     }
 }
 
-__global__ void __launch_bounds__(256) k_sum_finalize(const JAcc* __restrict__ acc, const SumMeta* meta, u32 cap,
-                                                      Out o, cv_result* res, const u64* __restrict__ soff, u32 S,
-                                                      u64* __restrict__ jo, u32 n)
+__global__ void __launch_bounds__(256) k_sum_finalize(const JAcc* __restrict__ acc, const AccX* __restrict__ accx,
+                                                      const SumMeta* meta, u32 cap,
+                                                      Out o, const i64* __restrict__ ts, cv_result* res,
+                                                      const u64* __restrict__ soff, u32 S, u64* __restrict__ jo,
+                                                      u32 n)
 {
     u32 J = meta->J;
     u32 m = J < cap ? J : cap;
     for (u32 j = blockIdx.x * blockDim.x + threadIdx.x; j < m; j += gridDim.x * blockDim.x) {
         const JAcc& a = acc[j];
-        if (!a.touched) continue;
         Fx192 d, s;
         d.w[0] = a.dist[0];
         d.w[1] = a.dist[1];
@@ -475,7 +570,19 @@ __global__ void __launch_bounds__(256) k_sum_finalize(const JAcc* __restrict__ a
         s.w[0] = a.spd[0];
         s.w[1] = a.spd[1];
         s.w[2] = a.spd[2];
+        // values outside the 128-bit formats, added on their own
+        const AccX& x = accx[j];
+        Fx192 xd, xs;
+        for (int i = 0; i < 3; ++i) {
+            xd.w[i] = x.dist[i];
+            xs.w[i] = x.spd[i];
+        }
+        fx_add(d, xd);
+        fx_add(s, xs);
         write_final(o, j, a.count, a.ndtz, d, s, a.maxs, a.maxd, a.latmin, a.latmax, a.lonmin, a.lonmax);
+        // a journey's records are consecutive: its time span is read at both ends
+        o.tstart[j] = ts[a.gfirst];
+        o.tend[j] = ts[a.gfirst + a.count - 1];
     }
     if (jo && blockIdx.x == 0 && threadIdx.x == 0) {
         // shards that start at the end of the records hold no journey
@@ -505,6 +612,7 @@ struct SumLayout {
     u32* wcnt;
     u32* tile_prefix;
     JAcc* acc;
+    AccX* accx;
     u64 tiles;
     size_t bytes;
     SumLayout(void* ws, u64 n, u64 cap)
@@ -515,6 +623,7 @@ struct SumLayout {
         wcnt = c.take<u32>(tiles * NW);
         tile_prefix = c.take<u32>(tiles + 1);
         acc = c.take<JAcc>(cap < n ? cap : n);
+        accx = c.take<AccX>(cap < n ? cap : n);
         bytes = c.size();
     }
 };
@@ -551,13 +660,17 @@ static cv_status summary_impl(const cv_records* sorted, const cv_features* feat,
     const u32 nn = (u32)n;
     cvh::TimedScope ts_("summary", s);
     hipLaunchKernelGGL(k_sum_count, dim3((unsigned)L.tiles), dim3(SB), 0, s, sorted->journey_id, nn, L.wcnt, soff, S);
-    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(256), 0, s, L.wcnt, L.tile_prefix, (u32)L.tiles, L.meta);
-    hipLaunchKernelGGL(k_sum_init, dim3(cvh::grid_for(cap, 256, 2048)), dim3(256), 0, s, L.acc, L.meta, cap);
-    hipLaunchKernelGGL(k_sum_reduce, dim3((unsigned)L.tiles), dim3(SB), 0, s, nn, sorted->journey_id, sorted->ts_ms,
-                       sorted->lat_deg, sorted->lon_deg, sorted->speed_mps, feat->step_m, feat->speed_mps, feat->flags,
-                       L.tile_prefix, L.wcnt, cap, o, L.acc, soff, S, jo);
-    hipLaunchKernelGGL(k_sum_finalize, dim3(cvh::grid_for(cap, 256, 2048)), dim3(256), 0, s, L.acc, L.meta, cap, o,
-                       res, soff, S, jo, nn);
+    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(SCAN_B), 0, s, L.wcnt, L.tile_prefix, (u32)L.tiles, L.meta);
+    hipLaunchKernelGGL(k_sum_init, dim3(cvh::grid_for(cap, 256, 2048)), dim3(256), 0, s, L.acc, L.accx, L.meta, cap);
+    for (const bool box : {true, false}) {
+        auto kern = box ? (S > 1 ? k_sum_reduce<true, true> : k_sum_reduce<true, false>)
+                        : (S > 1 ? k_sum_reduce<false, true> : k_sum_reduce<false, false>);
+        hipLaunchKernelGGL(kern, dim3((unsigned)L.tiles), dim3(SB), 0, s, nn, sorted->journey_id, sorted->ts_ms,
+                           sorted->lat_deg, sorted->lon_deg, sorted->speed_mps, feat->step_m, feat->speed_mps,
+                           feat->flags, L.tile_prefix, L.wcnt, cap, o, L.acc, L.accx, soff, S, jo);
+    }
+    hipLaunchKernelGGL(k_sum_finalize, dim3(cvh::grid_for(cap, 256, 2048)), dim3(256), 0, s, L.acc, L.accx, L.meta, cap, o,
+                       sorted->ts_ms, res, soff, S, jo, nn);
     return cvh::last_launch_status();
 }
 

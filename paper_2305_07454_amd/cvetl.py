@@ -465,7 +465,7 @@ def cv_batch_run(rec, sizes, grid, max_journeys=None, journey_capacity=None, gro
     mj = max_journeys or max(1, min(n, 1 << 20))
     jc = journey_capacity or max(1, min(n, 1 << 20))
     gc = group_capacity or max(1, min(n, 1 << 22))
-    for _ in range(3):
+    for _ in range(6):
         bp = BatchPipeline(n, len(sizes), grid, mj, jc, gc, dev)
         bp.run(rec, off_d)
         r = bp.results()
@@ -479,7 +479,8 @@ def cv_batch_run(rec, sizes, grid, max_journeys=None, journey_capacity=None, gro
         if r[1]["status"] == CV_ERR_CAPACITY:
             jc = max(jc, r[1]["required"])
         if r[2]["status"] == CV_ERR_CAPACITY:
-            gc = max(2 * gc, r[2]["required"])
+            gc = min(n, max(4 * gc, r[2]["required"]))
+        del bp
     raise CvError(CV_ERR_CAPACITY, "cv_batch_run")
 
 

@@ -230,3 +230,18 @@ def test_every_sort_tile_shape(cv):
             check_groups(got["groups"], got["n_out"], exp["groups"], exp["n_out"])
     finally:
         cv.cv_tuning_set("sort_shape", prev)
+
+
+def test_speed_extremes_in_exact_sums(cv):
+    # speeds across the whole float32 range the sums must carry exactly:
+    # subnormals, tiny and large magnitudes, both signs, signed zeros
+    r = gen.make_c0(seed=404, n_journeys=60, min_len=50, max_len=400)
+    rng = np.random.default_rng(405)
+    n = r.n
+    pool = np.array([1e-45, 3e-42, -7e-40, 1.2e-38, 1e-30, -1e-20, 9.3e-10, -1e-9, 2.0 ** -30, -(2.0 ** -31),
+                     0.0, -0.0, 1.0, -3.5, 511.99, -1000.0, 1023.9, 7.25e-3], dtype=np.float32)
+    spd = np.where(rng.random(n) < 0.5, pool[rng.integers(0, len(pool), n)],
+                   rng.uniform(-40, 40, n).astype(np.float32)).astype(np.float32)
+    cols = (r.journey_id, r.ts_ms, r.lat_deg, r.lon_deg, spd)
+    got, exp = _run_both(cv, cols, gen.GRIDS["c0"])
+    _check_all(got, exp)

@@ -256,9 +256,11 @@ cv_status cv_batch_grid_aggregate(const cv_records* sorted, const uint64_t* shar
  * journey's last pushed record is late: flag CV_FLAG_LATE, all-zero
  * kinematics, counted in its journey's totals and in its cell (never as a new
  * distinct journey), journey state unchanged.  The distinct-journey flag
- * remembers up to 16 cells per open (journey, time-bin) segment; a segment
- * with more sets bit 0 of cv_result.flags (its journey may then be counted
- * more than once in a cell).
+ * remembers the cells of each open (journey, time-bin) segment: 16 in the
+ * journey's row, up to 384 more in an overflow table the row takes from a
+ * pool (one table per 64 journeys of max_journeys).  A segment with more
+ * cells, or a row that finds the pool empty, sets bit 0 of cv_result.flags
+ * (its journey may then be counted more than once in a cell).
  *
  *   cv_stream_state_size  bytes of device state for the capacities (journeys
  *                         ever seen, groups ever seen, records per push).

@@ -52,9 +52,8 @@ hipEvent_t get_event()
 void drain(Family& f)
 {
     for (auto& p : f.pending) {
-        hipEventSynchronize(p.b);
         float ms = 0.f;
-        if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+        if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
             f.total_ms += ms;
             f.launches += 1;
         }
@@ -93,7 +92,10 @@ TimedScope::TimedScope(const char* fam, hipStream_t s) : family(fam), stream(s),
     if (!g_on) return;
     hipEvent_t a = get_event();
     if (!a) return;
-    hipEventRecord(a, s);
+    if (hipEventRecord(a, s) != hipSuccess) {
+        g_free.push_back(a);
+        return;
+    }
     token = (void*)a;
 }
 
@@ -101,10 +103,15 @@ TimedScope::~TimedScope()
 {
     if (!token) return;
     std::lock_guard<std::mutex> lk(g_mu);
+    hipEvent_t a = (hipEvent_t)token;
     hipEvent_t b = get_event();
-    if (!b) return;
-    hipEventRecord(b, stream);
-    g_fam[family].pending.push_back(Pending{(hipEvent_t)token, b});
+    if (!b || hipEventRecord(b, stream) != hipSuccess) {
+        // no closing event: this launch goes untimed
+        g_free.push_back(a);
+        if (b) g_free.push_back(b);
+        return;
+    }
+    g_fam[family].pending.push_back(Pending{a, b});
 }
 
 }  // namespace cvh

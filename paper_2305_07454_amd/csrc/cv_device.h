@@ -272,16 +272,21 @@ __device__ __forceinline__ u32 shard_lower_bound(const u64* __restrict__ off, u3
 }
 
 // Shard starts among the records [a, a + 64) as a lane mask, for a wave that
-// walks consecutive windows: k (wave-uniform) is the first shard whose start is
-// >= a and moves past the window; at_end tells whether a shard starts at a + 64.
+// walks consecutive windows: k is the first shard whose start is >= a and moves
+// past the window; at_end tells whether a shard starts at a + 64.  k and a are
+// wave-uniform (the caller makes them so), which lets the offsets be read with
+// scalar loads that do not hold up the wave's vector loads.
 __device__ __forceinline__ u64 shard_starts_in(const u64* __restrict__ off, u32 S, u32& k, u64 a, bool& at_end)
 {
     u64 m = 0;
-    while (k < S && off[k] < a + 64) {
-        m |= 1ull << (off[k] - a);
+    k = __builtin_amdgcn_readfirstlane(k);
+    u64 nb = k < S ? off[k] : ~0ull;
+    while (nb < a + 64) {
+        m |= 1ull << (nb - a);
         ++k;
+        nb = k < S ? off[k] : ~0ull;
     }
-    at_end = k < S && off[k] == a + 64;
+    at_end = nb == a + 64;
     return m;
 }
 

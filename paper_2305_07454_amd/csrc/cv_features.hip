@@ -90,8 +90,11 @@ __global__ void __launch_bounds__(FB) k_features(u32 n, const i64* __restrict__ 
                 dts = (double)dt_ms / 1000.0;
                 const double dphi = (la - lap) * DEG2RAD;
                 const double dlam = (lo - lop) * DEG2RAD;
-                const double sp = sin(0.5 * dphi);
-                const double sl = sin(0.5 * dlam);
+                // half-angle sines and cosines; the full-angle sines of the
+                // bearing follow from them (sin 2u = 2 sin u cos u)
+                double sp, cp, sl, cl;
+                sincos(0.5 * dphi, &sp, &cp);
+                sincos(0.5 * dlam, &sl, &cl);
                 const double cphi1 = s_cphi[p];
                 const double cphi2 = cphi;
                 const double a = (sp * sp) + ((cphi1 * cphi2) * (sl * sl));
@@ -101,8 +104,8 @@ __global__ void __launch_bounds__(FB) k_features(u32 n, const i64* __restrict__ 
                     f |= CV_FLAG_SPEED_OK;
                 }
                 if (step > 0.0) {
-                    const double y = sin(dlam) * cphi2;
-                    const double x = sin(dphi) + (((2.0 * s_sphi[p]) * cphi2) * (sl * sl));
+                    const double y = ((2.0 * sl) * cl) * cphi2;
+                    const double x = ((2.0 * sp) * cp) + (((2.0 * s_sphi[p]) * cphi2) * (sl * sl));
                     b = atan2(y, x) * RAD2DEG;
                     if (b < 0.0) b += 360.0;
                     if (b >= 360.0) b -= 360.0;

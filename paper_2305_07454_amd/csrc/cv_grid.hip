@@ -187,9 +187,9 @@ __device__ __forceinline__ void run_insert(u64* s_hkey, LSlot* s_h, GEntry* tab,
 }
 
 // three workgroups per CU fit the LDS of the 256-slot table: the register
-// budget is set to match
+// budget is set to match (the larger tables leave room for fewer)
 template <int LHS>
-__global__ void __launch_bounds__(GB) __attribute__((amdgpu_waves_per_eu(3)))
+__global__ void __launch_bounds__(GB) __attribute__((amdgpu_waves_per_eu(LHS <= 256 ? 3 : 1)))
 k_grid_agg(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, const double* __restrict__ lat,
            const double* __restrict__ lon, const float* __restrict__ spd, Spec g, GEntry* __restrict__ tab, u64 gmask,
            GridMeta* meta)

@@ -268,7 +268,7 @@ __global__ void __launch_bounds__(256) k_grid_emit(const GEntry* __restrict__ ta
     }
 }
 
-__global__ void k_grid_empty(cv_result* res)
+__attribute__((unused)) __global__ void k_grid_empty(cv_result* res)
 {
     if (threadIdx.x == 0) {
         cv_result r = {};
@@ -277,7 +277,7 @@ __global__ void k_grid_empty(cv_result* res)
 }
 
 // group_offsets[s] = first group of shard s (groups are sorted by shard, then key)
-__global__ void __launch_bounds__(256) k_group_offsets(const GridMeta* meta, const u64* __restrict__ K0,
+__attribute__((unused)) __global__ void __launch_bounds__(256) k_group_offsets(const GridMeta* meta, const u64* __restrict__ K0,
                                                        const u64* __restrict__ K1, u32 S, u32 kb,
                                                        u64* __restrict__ go)
 {

@@ -58,7 +58,7 @@ __global__ void k_sort_init(SortMeta* m)
     }
 }
 
-__device__ __forceinline__ bool dict_insert(u64* table, u64 mask, u64 key, SortMeta* m)
+__device__ __forceinline__ bool dict_insert(u64* table, u64 mask, u64 key)
 {
     u64 h = mix64(key) & mask;
     for (u64 probe = 0; probe <= mask; ++probe) {
@@ -101,7 +101,7 @@ __global__ void __launch_bounds__(256) k_dict_insert(const i64* __restrict__ jid
             has_min = true;
             continue;
         }
-        if (!dict_insert(table, mask, (u64)j, m)) full = true;
+        if (!dict_insert(table, mask, (u64)j)) full = true;
     }
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) {

@@ -19,9 +19,9 @@
 //      summary (exact fixed point) and the resident group table, deciding the
 //      distinct-journey flag from the cells seen in the journey's open
 //      (journey, time-bin) segment, which the row carries across pushes: the
-//      first KCELLS cells in the row, further ones in a device-wide visit map
-//      of (row, group key) pairs (a group key names its time bin, so entries
-//      of closed segments never match again).
+//      first KCELLS cells in the row, further ones in the row's own overflow
+//      table (a page of a device-wide pool, taken the first time one of the
+//      row's segments needs it and cleared when the next segment starts).
 // Flush: journey rows in ascending id and the group table in ascending key.
 #include <hip/hip_runtime.h>
 
@@ -43,35 +43,28 @@ cv_status sort_records_into(const cv_records* in, uint64_t max_journeys, uint32_
 namespace {
 
 constexpr int KCELLS = 16;  // distinct cells remembered in a journey's row for its open segment
-constexpr u32 VEMPTY = 0xFFFFFFFFu;
+constexpr u32 OVF_NONE = 0xFFFFFFFFu;   // the row has no overflow table yet
+constexpr u32 OVF_FAIL = 0xFFFFFFFEu;   // the pool ran out for this row
+constexpr int OVF_SLOTS = 512;          // open-addressing slots of one overflow table
+constexpr u32 OVF_MAX = 384;            // cells one segment may keep there (75 % load)
+constexpr u64 OVF_EMPTY = ~0ull;        // group keys are non-negative
 
-// visit map entry: cell visited by row `slot` in a segment whose first KCELLS
-// cells filled the row's list
-struct Visit {
-    u64 key;
-    u32 slot;
-    u32 pad;
-};
-
-// true when (slot, key) was not in the map (and is now).  Only the thread that
-// folds row `slot` writes entries of that slot, so an entry is claimed by a
-// compare-and-swap of its slot word and completed by a plain store of its key.
-// Returns true with *full set when the map has no room.
-__device__ __forceinline__ bool visit_insert(Visit* vm, u64 vmask, u32 slot, u64 key, bool* full)
+// Membership of a cell in the row's overflow table for its open segment; true
+// when it was not there (and is now).  Only the thread folding the row reads
+// or writes the table.  A full table sets *full and answers true.
+__device__ __forceinline__ bool ovf_insert(u64* tab, u64 key, u32& used, bool* full)
 {
-    u64 h = mix64(key ^ ((u64)slot * 0x9E3779B97F4A7C15ull)) & vmask;
-    for (u64 probe = 0; probe <= vmask; ++probe) {
-        u32 cur = __hip_atomic_load(&vm[h].slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (cur == VEMPTY) {
-            cur = atomicCAS(&vm[h].slot, VEMPTY, slot);
-            if (cur == VEMPTY) {
-                __hip_atomic_store(&vm[h].key, key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                return true;
-            }
+    u32 h = (u32)mix64(key) & (OVF_SLOTS - 1);
+    for (int probe = 0; probe < OVF_SLOTS; ++probe) {
+        const u64 cur = tab[h];
+        if (cur == key) return false;
+        if (cur == OVF_EMPTY) {
+            if (used >= OVF_MAX) break;
+            tab[h] = key;
+            ++used;
+            return true;
         }
-        if (cur == slot && __hip_atomic_load(&vm[h].key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == key)
-            return false;
-        h = (h + 1) & vmask;
+        h = (h + 1) & (OVF_SLOTS - 1);
     }
     *full = true;
     return true;
@@ -95,13 +88,15 @@ struct JRow {
     u32 count, ndtz, maxs, ncell;
     i64 seg_tbin;
     u64 cell[KCELLS];
+    u32 ovf, novf;  // overflow table (page index) and the cells it holds for the open segment
 };
 
 struct StreamMeta {
     u32 Jb;             // journeys in the current batch
     u32 jt_full;        // journey table full (sticky)
-    u32 cell_overflow;  // the visit map ran full: distinct-journey counts may be high (sticky)
-    u32 pad;
+    u32 cell_overflow;  // a segment outgrew its overflow table or the pool ran out:
+                        // distinct-journey counts may be high (sticky)
+    u32 ovf_next;       // overflow tables taken from the pool
     u64 batch_late, batch_out;
     u64 total_records, total_late, total_out;
     u32 jcount;         // flush: occupied journey rows
@@ -114,7 +109,7 @@ __device__ __forceinline__ u64 jt_find_or_insert(u64* keys, u64 mask, u64 key, b
 {
     inserted = false;
     u64 h = mix64(key) & mask;
-    for (u64 probe = 0; probe <= mask; ++probe) {
+    for (u64 probe = 0; probe <= mask && probe < G_PROBES; ++probe) {
         u64 cur = keys[h];
         if (cur == key) return h;
         if (cur == JEMPTY) {
@@ -230,6 +225,7 @@ __global__ void __launch_bounds__(256) k_st_journeys(const i64* __restrict__ jid
             r.tmin_ord = ~0ull;
             r.tmax_ord = 0;
             r.seg_tbin = INT64_MIN;
+            r.ovf = OVF_NONE;
             rows[s] = r;
         }
     }
@@ -398,14 +394,14 @@ __global__ void __launch_bounds__(FB) k_st_features(u32 n, const i64* __restrict
 }
 
 // One thread per batch journey: running summary, group table, resident state.
-__global__ void __launch_bounds__(256) k_st_fold(u32 n, const i64* __restrict__ ts, const double* __restrict__ lat,
+__global__ void __launch_bounds__(256) k_st_fold(const i64* __restrict__ ts, const double* __restrict__ lat,
                                                  const double* __restrict__ lon, const float* __restrict__ spd,
                                                  const u32* __restrict__ boff, StreamMeta* m,
                                                  const u32* __restrict__ bslot, JRow* __restrict__ rows,
                                                  const double* __restrict__ fs_step, const double* __restrict__ fs_v,
                                                  const double* __restrict__ fs_b, const uint8_t* __restrict__ fs_flags,
-                                                 Spec g, GEntry* __restrict__ tab, u64 gmask, Visit* __restrict__ vm,
-                                                 u64 vmask)
+                                                 Spec g, GEntry* __restrict__ tab, u64 gmask,
+                                                 u64* __restrict__ ovf_pool, u32 ovf_pages)
 {
     __shared__ u64 s_red[2][4];
     const u32 Jb = m->Jb;
@@ -424,6 +420,7 @@ __global__ void __launch_bounds__(256) k_st_fold(u32 n, const i64* __restrict__ 
         sps.w[1] = R.spd[1];
         sps.w[2] = R.spd[2];
         u32 count = R.count, ndtz = R.ndtz, maxs = R.maxs, ncell = R.ncell;
+        u32 ovf = R.ovf, novf = R.novf;
         u64 maxd = R.maxd, la0 = R.latmin, la1 = R.latmax, lo0 = R.lonmin, lo1 = R.lonmax;
         u64 tmin = R.tmin_ord, tmax = R.tmax_ord;
         i64 seg = R.seg_tbin;
@@ -480,6 +477,11 @@ __global__ void __launch_bounds__(256) k_st_fold(u32 n, const i64* __restrict__ 
                 if (tb != seg) {  // a new (journey, time-bin) segment
                     seg = tb;
                     ncell = 0;
+                    if (novf) {  // the overflow table starts empty again
+                        u64* t = ovf_pool + (u64)ovf * OVF_SLOTS;
+                        for (int c = 0; c < OVF_SLOTS; ++c) t[c] = OVF_EMPTY;
+                        novf = 0;
+                    }
                 }
                 bool seen = false;
 #pragma unroll
@@ -492,7 +494,16 @@ __global__ void __launch_bounds__(256) k_st_fold(u32 n, const i64* __restrict__ 
                             if ((u32)c == ncell) cells[c] = (u64)key;
                         ++ncell;
                     } else {
-                        first = visit_insert(vm, vmask, slot, (u64)key, &overflow);
+                        if (ovf == OVF_NONE) {  // first overflow of this row: take a table
+                            const u32 pg = atomicAdd(&m->ovf_next, 1u);
+                            ovf = pg < ovf_pages ? pg : OVF_FAIL;
+                        }
+                        if (ovf == OVF_FAIL) {
+                            overflow = true;
+                            first = true;
+                        } else {
+                            first = ovf_insert(ovf_pool + (u64)ovf * OVF_SLOTS, (u64)key, novf, &overflow);
+                        }
                     }
                 }
             }
@@ -532,6 +543,8 @@ __global__ void __launch_bounds__(256) k_st_fold(u32 n, const i64* __restrict__ 
         R.tmax_ord = tmax;
         R.seg_tbin = seg;
         R.ncell = ncell;
+        R.ovf = ovf;
+        R.novf = novf;
 #pragma unroll
         for (int c = 0; c < KCELLS; ++c) R.cell[c] = cells[c];
         if (last_good != ~0u) {
@@ -680,7 +693,7 @@ struct cv_stream {
     u64* jkeys;
     JRow* rows;
     GEntry* tab;
-    Visit* visits;
+    u64* ovf_pool;
     // per-push scratch
     void* sort_ws;
     size_t sort_ws_bytes;
@@ -702,15 +715,15 @@ struct cv_stream {
 
 namespace {
 
-// visit map slots: a quarter of the group table's
-u64 visit_slots(u64 gslots) { return gslots / 4 < 4096 ? 4096 : gslots / 4; }
+// overflow tables in the pool: one per 32 journey slots (one per 64 journeys)
+u32 ovf_pages(u64 jslots) { return (u32)(jslots / 32 < 64 ? 64 : jslots / 32); }
 
 struct StreamLayout {
     size_t bytes;
     template <class F>
     static void carve(cvh::Carver& c, u64 jslots, u64 gslots, u64 mb, F&& f)
     {
-        const u64 vslots = visit_slots(gslots);
+        const u64 opages = ovf_pages(jslots);
         const u64 tiles = (mb + ST_TILE - 1) / ST_TILE;
         size_t sort_ws = 0;
         cv_sort_workspace_size(mb, mb ? mb : 1, &sort_ws);
@@ -718,7 +731,7 @@ struct StreamLayout {
         f("jkeys", c.take<u64>(jslots));
         f("rows", c.take<JRow>(jslots));
         f("tab", c.take<GEntry>(gslots));
-        f("visits", c.take<Visit>(vslots));
+        f("ovf_pool", c.take<u64>(opages * OVF_SLOTS));
         f("sort_ws", c.take<char>(sort_ws));
         f("perm", c.take<u32>(mb));
         f("s_jid", c.take<i64>(mb));
@@ -822,7 +835,7 @@ cv_status cv_stream_create(const cv_grid_spec* grid, uint64_t max_journeys, uint
         else if (nm == "jkeys") st->jkeys = (u64*)p;
         else if (nm == "rows") st->rows = (JRow*)p;
         else if (nm == "tab") st->tab = (GEntry*)p;
-        else if (nm == "visits") st->visits = (Visit*)p;
+        else if (nm == "ovf_pool") st->ovf_pool = (u64*)p;
         else if (nm == "sort_ws") st->sort_ws = p;
         else if (nm == "perm") st->perm = (u32*)p;
         else if (nm == "s_jid") st->s_jid = (i64*)p;
@@ -861,7 +874,7 @@ cv_status cv_stream_create(const cv_grid_spec* grid, uint64_t max_journeys, uint
     cvh::fill_u64(st->jkeys, JEMPTY, st->jslots, s);
     hipLaunchKernelGGL(k_grid_clear, dim3(cvh::grid_for(st->gslots, 256, 4096)), dim3(256), 0, s, st->tab, st->gslots,
                        &st->meta->gm);
-    cvh::fill_u32((u32*)st->visits, VEMPTY, visit_slots(st->gslots) * sizeof(Visit) / 4, s);
+    cvh::fill_u64(st->ovf_pool, OVF_EMPTY, (u64)ovf_pages(st->jslots) * OVF_SLOTS, s);
     cv_status e = cvh::last_launch_status();
     if (e != CV_OK) {
         delete st;
@@ -903,10 +916,10 @@ cv_status cv_stream_push(cv_stream* st, const cv_records* batch, const cv_featur
     hipLaunchKernelGGL(k_st_features, dim3((unsigned)((n + FB - 1) / FB)), dim3(FB), 0, s, nn, st->s_jid, st->s_ts,
                        st->s_lat, st->s_lon, st->perm, st->boff, st->meta, st->bslot, st->rows, *feat, st->fs_step,
                        st->fs_v, st->fs_b, st->fs_flags);
-    hipLaunchKernelGGL(k_st_fold, dim3(cvh::grid_for(n, 256, 2048)), dim3(256), 0, s, nn, st->s_ts, st->s_lat,
+    hipLaunchKernelGGL(k_st_fold, dim3(cvh::grid_for(n, 256, 2048)), dim3(256), 0, s, st->s_ts, st->s_lat,
                        st->s_lon, st->s_spd, st->boff, st->meta, st->bslot, st->rows, st->fs_step, st->fs_v,
-                       st->fs_b, st->fs_flags, st->g, st->tab, st->gslots - 1, st->visits,
-                       visit_slots(st->gslots) - 1);
+                       st->fs_b, st->fs_flags, st->g, st->tab, st->gslots - 1, st->ovf_pool,
+                       ovf_pages(st->jslots));
     hipLaunchKernelGGL(k_st_finish, dim3(1), dim3(64), 0, s, st->meta, st->sres, nn, res);
     return cvh::last_launch_status();
 }

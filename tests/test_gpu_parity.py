@@ -232,9 +232,10 @@ def test_every_sort_tile_shape(cv):
         cv.cv_tuning_set("sort_shape", prev)
 
 
-def test_speed_extremes_in_exact_sums(cv):
-    # speeds across the whole float32 range the sums must carry exactly:
-    # subnormals, tiny and large magnitudes, both signs, signed zeros
+def test_extremes_in_exact_sums(cv):
+    # speeds across the whole float32 range the sums must carry exactly
+    # (subnormals, tiny and large magnitudes, both signs, signed zeros) and
+    # steps far below the fast fixed-point range
     r = gen.make_c0(seed=404, n_journeys=60, min_len=50, max_len=400)
     rng = np.random.default_rng(405)
     n = r.n
@@ -242,6 +243,13 @@ def test_speed_extremes_in_exact_sums(cv):
                      0.0, -0.0, 1.0, -3.5, 511.99, -1000.0, 1023.9, 7.25e-3], dtype=np.float32)
     spd = np.where(rng.random(n) < 0.5, pool[rng.integers(0, len(pool), n)],
                    rng.uniform(-40, 40, n).astype(np.float32)).astype(np.float32)
-    cols = (r.journey_id, r.ts_ms, r.lat_deg, r.lon_deg, spd)
+    # and steps below a micrometre: points a hair away from their predecessor
+    # in (journey, time) order
+    order = np.lexsort((r.ts_ms, r.journey_id))
+    lat = r.lat_deg.copy()
+    near = np.nonzero(rng.random(n) < 0.1)[0]
+    near = near[near > 0]
+    lat[order[near]] = lat[order[near - 1]] + rng.choice([1e-12, -3e-13, 2e-15], near.size)
+    cols = (r.journey_id, r.ts_ms, lat, r.lon_deg, spd)
     got, exp = _run_both(cv, cols, gen.GRIDS["c0"])
     _check_all(got, exp)

@@ -139,20 +139,35 @@ k_radix_pass(const u64* __restrict__ keys_in, const u32* __restrict__ vals_in, u
     }
     u32 total;
     u32 start = block_exclusive_sum<SORT_BLOCK>(threadIdx.x < RADIX ? tcount : 0u, s_tmp, total);
+    const u32 tag = (u32)pass + 1;
+    if (threadIdx.x < RADIX) {
+        s_start[threadIdx.x] = start;
+        // this tile's digit count, for the look-back of later tiles
+        lb_publish(status + (u64)tile * RADIX + threadIdx.x, rs_word(tile == 0 ? 2 : 1, tag, tcount));
+    }
+    __syncthreads();
+
+    // keys to LDS in digit order (stable); the look-back below overlaps with
+    // the other threads' staging
+    u32 pos[SORT_ITEMS];
+#pragma unroll
+    for (int i = 0; i < SORT_ITEMS; ++i) {
+        u64 idx = wbase + (u64)i * WAVE + l;
+        pos[i] = ~0u;
+        if (idx < n) {
+            u32 d = (u32)(key[i] >> shift) & (RADIX - 1);
+            pos[i] = s_start[d] + s_whist[w][d] + rnk[i];
+            s_keys[pos[i]] = key[i];
+        }
+    }
     if (threadIdx.x < RADIX) {
         const int d = threadIdx.x;
-        s_start[d] = start;
         // look-back for digit d over earlier tiles of this pass
-        const u32 tag = (u32)pass + 1;
-        u64* st = status + (u64)tile * RADIX + d;
         u64 excl = 0;
-        if (tile == 0) {
-            lb_publish(st, rs_word(2, tag, tcount));
-        } else {
-            lb_publish(st, rs_word(1, tag, tcount));
-            // Look back LBW tiles at a time (their status words read together):
-            // take aggregates in order up to the first inclusive prefix; stop
-            // early at a tile that has not published yet and read again from it.
+        if (tile != 0) {
+            // LBW tiles at a time (their status words read together): take
+            // aggregates in order up to the first inclusive prefix; stop early
+            // at a tile that has not published yet and read again from it
             constexpr int LBW = 4;
             long t = (long)tile - 1;
             bool done = false;
@@ -174,23 +189,9 @@ k_radix_pass(const u64* __restrict__ keys_in, const u32* __restrict__ vals_in, u
                 t -= used;
                 if (!done && used < LBW) __builtin_amdgcn_s_sleep(1);
             }
-            lb_publish(st, rs_word(2, tag, excl + tcount));
+            lb_publish(status + (u64)tile * RADIX + d, rs_word(2, tag, excl + tcount));
         }
         s_gshift[d] = doff + (u32)excl - start;
-    }
-    __syncthreads();
-
-    // in-tile position of each item (digit order, stable)
-    u32 pos[SORT_ITEMS];
-#pragma unroll
-    for (int i = 0; i < SORT_ITEMS; ++i) {
-        u64 idx = wbase + (u64)i * WAVE + l;
-        pos[i] = ~0u;
-        if (idx < n) {
-            u32 d = (u32)(key[i] >> shift) & (RADIX - 1);
-            pos[i] = s_start[d] + s_whist[w][d] + rnk[i];
-            s_keys[pos[i]] = key[i];
-        }
     }
     __syncthreads();
     const u32 tvalid = (u32)((n - tile_base) < (u64)SORT_TILE ? (n - tile_base) : (u64)SORT_TILE);

@@ -70,10 +70,12 @@ __device__ __forceinline__ u64 heads_of(i64 jv, u64 a, u64 end, i64& jprev, cons
     return __ballot(valid && (r == 0 || jv != jp || ((smask >> l) & 1ull)));
 }
 
-// journey starts per wave chunk of WCH records: wcnt[tile * NW + wave]
+// journey starts per wave chunk of WCH records: wcnt[tile * NW + wave], and
+// per tile: tcnt[tile]
 __global__ void __launch_bounds__(SB) k_sum_count(const i64* __restrict__ jid, u32 n, u32* __restrict__ wcnt,
-                                                  const u64* __restrict__ soff, u32 S)
+                                                  u32* __restrict__ tcnt, const u64* __restrict__ soff, u32 S)
 {
+    __shared__ u32 s_w[NW];
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);  // wave-uniform
     const u64 cs = (u64)blockIdx.x * ST + (u64)w * WCH;
     const u64 ce = cs + WCH < n ? cs + WCH : (u64)n;
@@ -90,13 +92,22 @@ __global__ void __launch_bounds__(SB) k_sum_count(const i64* __restrict__ jid, u
             c += (u32)__popcll(heads_of(jv, a, ce, jprev, soff, S, sk, sm, se));
         }
     }
-    if (lane_id() == 0) wcnt[(u64)blockIdx.x * NW + w] = c;
+    if (lane_id() == 0) {
+        wcnt[(u64)blockIdx.x * NW + w] = c;
+        s_w[w] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        u32 t = 0;
+        for (int k = 0; k < NW; ++k) t += s_w[k];
+        tcnt[blockIdx.x] = t;
+    }
 }
 
 // single block: tile_prefix[i] = journey starts before tile i; meta->J = total.
 // Each thread sums a contiguous run of tiles, one block scan joins the runs.
 constexpr int SCAN_B = 1024;
-__global__ void __launch_bounds__(SCAN_B) k_tile_scan(const u32* __restrict__ wcnt, u32* __restrict__ tile_prefix,
+__global__ void __launch_bounds__(SCAN_B) k_tile_scan(const u32* __restrict__ tcnt, u32* __restrict__ tile_prefix,
                                                       u32 tiles, SumMeta* meta)
 {
     __shared__ u32 tmp[SCAN_B / WAVE];
@@ -104,14 +115,13 @@ __global__ void __launch_bounds__(SCAN_B) k_tile_scan(const u32* __restrict__ wc
     const u32 a = threadIdx.x * per;
     const u32 b = a + per < tiles ? a + per : tiles;
     u32 sum = 0;
-#pragma unroll 4
-    for (u32 i = a; i < b; ++i)
-        for (int k = 0; k < NW; ++k) sum += wcnt[(u64)i * NW + k];
+#pragma unroll 8
+    for (u32 i = a; i < b; ++i) sum += tcnt[i];
     u32 total;
     u32 e = block_exclusive_sum<SCAN_B>(sum, tmp, total);
     for (u32 i = a; i < b; ++i) {
         tile_prefix[i] = e;
-        for (int k = 0; k < NW; ++k) e += wcnt[(u64)i * NW + k];
+        e += tcnt[i];
     }
     if (threadIdx.x == 0) meta->J = total;
 }
@@ -415,9 +425,8 @@ __device__ __forceinline__ void flush_part(JAcc* acc, u32 cap, u32 j, const Part
 // plain form without the shard branches, whose loads would otherwise make
 // every window wait for all loads in flight, prefetch included.
 template <bool BOX, bool SHARDS>
-__global__ void __launch_bounds__(SB) k_sum_reduce(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts,
-                                                   const double* __restrict__ lat, const double* __restrict__ lon,
-                                                   const float* __restrict__ spd, const double* __restrict__ step,
+__global__ void __launch_bounds__(SB) k_sum_reduce(u32 n, const i64* __restrict__ jid, const double* __restrict__ lat,
+                                                   const double* __restrict__ lon, const float* __restrict__ spd, const double* __restrict__ step,
                                                    const double* __restrict__ dspd, const uint8_t* __restrict__ flags,
                                                    const u32* __restrict__ tile_prefix, const u32* __restrict__ wcnt,
                                                    u32 cap, Out o, JAcc* __restrict__ acc, AccX* __restrict__ accx,
@@ -610,6 +619,7 @@ __global__ void k_sum_empty(cv_result* res)
 struct SumLayout {
     SumMeta* meta;
     u32* wcnt;
+    u32* tcnt;
     u32* tile_prefix;
     JAcc* acc;
     AccX* accx;
@@ -621,6 +631,7 @@ struct SumLayout {
         tiles = (n + ST - 1) / ST;
         meta = c.take<SumMeta>(1);
         wcnt = c.take<u32>(tiles * NW);
+        tcnt = c.take<u32>(tiles + 1);
         tile_prefix = c.take<u32>(tiles + 1);
         acc = c.take<JAcc>(cap < n ? cap : n);
         accx = c.take<AccX>(cap < n ? cap : n);
@@ -659,15 +670,16 @@ static cv_status summary_impl(const cv_records* sorted, const cv_features* feat,
     const u32 cap = (u32)(capacity < n ? capacity : n);
     const u32 nn = (u32)n;
     cvh::TimedScope ts_("summary", s);
-    hipLaunchKernelGGL(k_sum_count, dim3((unsigned)L.tiles), dim3(SB), 0, s, sorted->journey_id, nn, L.wcnt, soff, S);
-    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(SCAN_B), 0, s, L.wcnt, L.tile_prefix, (u32)L.tiles, L.meta);
+    hipLaunchKernelGGL(k_sum_count, dim3((unsigned)L.tiles), dim3(SB), 0, s, sorted->journey_id, nn, L.wcnt, L.tcnt,
+                       soff, S);
+    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(SCAN_B), 0, s, L.tcnt, L.tile_prefix, (u32)L.tiles, L.meta);
     hipLaunchKernelGGL(k_sum_init, dim3(cvh::grid_for(cap, 256, 2048)), dim3(256), 0, s, L.acc, L.accx, L.meta, cap);
     for (const bool box : {true, false}) {
         auto kern = box ? (S > 1 ? k_sum_reduce<true, true> : k_sum_reduce<true, false>)
                         : (S > 1 ? k_sum_reduce<false, true> : k_sum_reduce<false, false>);
-        hipLaunchKernelGGL(kern, dim3((unsigned)L.tiles), dim3(SB), 0, s, nn, sorted->journey_id, sorted->ts_ms,
-                           sorted->lat_deg, sorted->lon_deg, sorted->speed_mps, feat->step_m, feat->speed_mps,
-                           feat->flags, L.tile_prefix, L.wcnt, cap, o, L.acc, L.accx, soff, S, jo);
+        hipLaunchKernelGGL(kern, dim3((unsigned)L.tiles), dim3(SB), 0, s, nn, sorted->journey_id, sorted->lat_deg,
+                           sorted->lon_deg, sorted->speed_mps, feat->step_m, feat->speed_mps, feat->flags,
+                           L.tile_prefix, L.wcnt, cap, o, L.acc, L.accx, soff, S, jo);
     }
     hipLaunchKernelGGL(k_sum_finalize, dim3(cvh::grid_for(cap, 256, 2048)), dim3(256), 0, s, L.acc, L.accx, L.meta, cap, o,
                        sorted->ts_ms, res, soff, S, jo, nn);

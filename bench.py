@@ -238,6 +238,9 @@ def bench_serving(args):
     same = all(torch.equal(ja[k].view(torch.uint8), jb[k].view(torch.uint8)) for k in ja) and \
         all(torch.equal(ga[k].view(torch.uint8), gb[k].view(torch.uint8)) for k in ga) and \
         all(torch.equal(ka[c][k].view(torch.uint8), kb[c][k].view(torch.uint8)) for c in ka for k in ka[c])
+    for nm, rj, rg in (("batched", ra, rga), ("per_chunk", rb, rgb)):
+        log(f"{nm}: journeys {rj['count']} status {rj['status']} cell-overflow flag {rj['flags']}; "
+            f"groups {rg['count']} status {rg['status']}")
     assert same, "batched and per-chunk serving differ"
     line = {
         "metric": "ETL Mrecords/s & % HBM peak (plain vs batched); serving p50/p99 latency",

@@ -26,443 +26,13 @@
 
 #include "cv_device.h"
 #include "cv_host.h"
+#include "cv_gridagg.h"
 #include "cv_gridtab.h"
 #include "cv_radix.h"
 
 using namespace cv;
 
 namespace {
-
-constexpr int GB = 256;
-constexpr int GI = 8;
-constexpr int GT = GB * GI;
-constexpr int HALO = 512;
-static_assert(HALO % GB == 0, "whole halo rows");
-constexpr int LHS_PROBES = 32;
-struct LSlot {
-    u64 cs[4];
-    u32 count, nj, mn, mx;
-};
-
-constexpr uint8_t B_SEG = 1;   // first record of a (journey, time-bin) segment
-constexpr uint8_t B_RUN = 2;   // first record of a run (segment start or key change)
-constexpr uint8_t B_FIRST = 4; // run head whose key is new in its segment (counts its journey)
-
-// Partial aggregate of one run (or piece of a run).  The speed sum is a
-// 128-bit two's-complement integer in units of 2^-53, exact for every float32
-// speed v with 2^-30 <= |v| < 2^10 (and for zeros); any other speed is added
-// to the table on its own, in the full 192-bit format.  Count and distinct
-// journeys share one word (16 bits each: a piece holds at most GT / 4
-// records).
-struct RunPart {
-    u64 lo, hi;
-    u32 cn, mn, mx;
-};
-
-__device__ __forceinline__ void run_reset(RunPart& p)
-{
-    p.lo = 0;
-    p.hi = 0;
-    p.cn = 0;
-    p.mn = ~0u;
-    p.mx = 0;
-}
-
-__device__ __forceinline__ void add128(u64& lo, u64& hi, u64 blo, u64 bhi)
-{
-    const u64 s = lo + blo;
-    hi += bhi + (s < lo ? 1ull : 0ull);
-    lo = s;
-}
-
-__device__ __forceinline__ void run_combine(RunPart& a, const RunPart& b)
-{
-    add128(a.lo, a.hi, b.lo, b.hi);
-    a.cn += b.cn;
-    a.mn = b.mn < a.mn ? b.mn : a.mn;
-    a.mx = b.mx > a.mx ? b.mx : a.mx;
-}
-
-// v * 2^53 as a signed integer when 2^-30 <= |v| < 2^10 or v = +-0
-__device__ __forceinline__ bool spd_fix53(float v, i64& x)
-{
-    const u32 b = __float_as_uint(v);
-    const u32 e = (b >> 23) & 0xFFu;
-    const u32 m = b & 0x7FFFFFu;
-    x = 0;
-    if (e == 0) return m == 0;
-    if (e < 97 || e > 136) return false;
-    const i64 mag = (i64)((u64)(m | 0x800000u) << (e - 97));
-    x = (b >> 31) ? -mag : mag;
-    return true;
-}
-
-// the 128-bit sum in the table's 192-bit format (2^-149 units)
-__device__ __forceinline__ Fx192 run_sum192(const RunPart& p)
-{
-    Fx192 r;
-    r.w[0] = 0;
-    r.w[1] = p.lo << 32;
-    r.w[2] = (p.lo >> 32) | (p.hi << 32);
-    return r;
-}
-
-// one step of a cross-lane reduction or scan: fold in the partial d lanes away
-// (xor: full reduction; up: the lane below) when `take`
-__device__ __forceinline__ void run_step(RunPart& p, int d, bool up, bool take)
-{
-    const u64 lo = up ? (u64)__shfl_up((unsigned long long)p.lo, d, WAVE) : (u64)__shfl_xor((unsigned long long)p.lo, d, WAVE);
-    const u64 hi = up ? (u64)__shfl_up((unsigned long long)p.hi, d, WAVE) : (u64)__shfl_xor((unsigned long long)p.hi, d, WAVE);
-    const u32 cn = up ? (u32)__shfl_up(p.cn, d, WAVE) : (u32)__shfl_xor(p.cn, d, WAVE);
-    const u32 mn = up ? (u32)__shfl_up(p.mn, d, WAVE) : (u32)__shfl_xor(p.mn, d, WAVE);
-    const u32 mx = up ? (u32)__shfl_up(p.mx, d, WAVE) : (u32)__shfl_xor(p.mx, d, WAVE);
-    if (take) {
-        add128(p.lo, p.hi, lo, hi);
-        p.cn += cn;
-        p.mn = mn < p.mn ? mn : p.mn;
-        p.mx = mx > p.mx ? mx : p.mx;
-    }
-}
-
-__device__ __forceinline__ void run_wave_reduce(RunPart& p)
-{
-#pragma unroll
-    for (int d = 1; d < WAVE; d <<= 1) run_step(p, d, false, true);
-}
-
-// segmented inclusive scan across lanes; `head` starts a segment
-__device__ __forceinline__ void run_seg_scan(RunPart& p, bool head)
-{
-    const int l = lane_id();
-    u32 take = 0;
-    bool f = head;
-#pragma unroll
-    for (int k = 0, d = 1; d < WAVE; ++k, d <<= 1) {
-        const bool fo = __shfl_up(f, d, WAVE);
-        if (l >= d) {
-            if (!f) take |= 1u << k;
-            f = f || fo;
-        }
-    }
-#pragma unroll
-    for (int k = 0, d = 1; d < WAVE; ++k, d <<= 1) run_step(p, d, true, ((take >> k) & 1u) != 0);
-}
-
-// one contribution to key's group in the tile's LDS table; no free slot within
-// the probe limit spills it straight to the HBM table
-template <int LHS>
-__device__ __forceinline__ void slot_insert(u64* s_hkey, LSlot* s_h, GEntry* tab, u64 gmask, GridMeta* meta, u64 key,
-                                            const Fx192& sum, u32 count, u32 nj, u32 mn, u32 mx)
-{
-    u64 h = mix64(key) & (LHS - 1);
-    for (int probe = 0; probe < LHS_PROBES; ++probe) {
-        u64 cur = s_hkey[h];
-        if (cur == GEMPTY) {
-            const u64 prev =
-                atomicCAS((unsigned long long*)&s_hkey[h], (unsigned long long)GEMPTY, (unsigned long long)key);
-            cur = prev == GEMPTY ? key : prev;
-        }
-        if (cur == key) {
-            LSlot& sl = s_h[h];
-            u64 c[4];
-            fx_to_cs(sum, c);
-            for (int i = 0; i < 4; ++i)
-                if (c[i]) atomicAdd((unsigned long long*)&sl.cs[i], (unsigned long long)c[i]);
-            if (count) atomicAdd(&sl.count, count);
-            if (nj) atomicAdd(&sl.nj, nj);
-            if (mn != ~0u) atomicMin(&sl.mn, mn);
-            if (mx) atomicMax(&sl.mx, mx);
-            return;
-        }
-        h = (h + 1) & (LHS - 1);
-    }
-    g_insert(tab, gmask, meta, key, count, nj, sum, mn, mx);
-}
-
-template <int LHS>
-__device__ __forceinline__ void run_insert(u64* s_hkey, LSlot* s_h, GEntry* tab, u64 gmask, GridMeta* meta, u64 key,
-                                           const RunPart& p)
-{
-    slot_insert<LHS>(s_hkey, s_h, tab, gmask, meta, key, run_sum192(p), p.cn & 0xFFFFu, p.cn >> 16, p.mn, p.mx);
-}
-
-// three workgroups per CU fit the LDS of the 256-slot table: the register
-// budget is set to match (the larger tables leave room for fewer)
-template <int LHS>
-__global__ void __launch_bounds__(GB) __attribute__((amdgpu_waves_per_eu(LHS <= 256 ? 3 : 1)))
-k_grid_agg(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, const double* __restrict__ lat,
-           const double* __restrict__ lon, const float* __restrict__ spd, Spec g, GEntry* __restrict__ tab, u64 gmask,
-           GridMeta* meta)
-{
-    constexpr int NQ = HALO + GT;
-    __shared__ i64 s_key[NQ];       // keys per record; later the keys of the run-head list
-    __shared__ uint8_t s_bits[NQ];
-    __shared__ uint16_t s_lpos[NQ];  // run-head list: q | segment start << 15
-    __shared__ float s_spd[GT];
-    __shared__ u64 s_hkey[LHS];
-    __shared__ LSlot s_h[LHS];
-    __shared__ u32 s_tmp[GB / WAVE];
-    __shared__ u32 s_nlist;
-    constexpr int NWG = GB / WAVE;
-    __shared__ i64 s_lj[HALO / GB + GI][NWG], s_ltb[HALO / GB + GI][NWG];  // wave row ends
-    __shared__ i64 s_ltbs[HALO / GB + GI][NWG];                             // wave row starts
-    __shared__ i64 s_pj, s_ptb;  // the record before the first row
-    __shared__ int s_lo;
-    __shared__ u64 s_out[GB / WAVE];
-
-    const int t = threadIdx.x;
-    const u64 tile0 = (u64)blockIdx.x * GT;
-    const u32 tvalid = (u32)((u64)n - tile0 < (u64)GT ? (u64)n - tile0 : (u64)GT);
-    for (int i = t; i < LHS; i += GB) {
-        s_hkey[i] = GEMPTY;
-        LSlot z;
-        z.cs[0] = z.cs[1] = z.cs[2] = z.cs[3] = 0;
-        z.count = 0;
-        z.nj = 0;
-        z.mn = ~0u;
-        z.mx = 0;
-        s_h[i] = z;
-    }
-    // The tile's records and the HALO records before it (rows of GB, striped,
-    // coalesced): every column is loaded first, so that all loads are in flight
-    // together; then keys, speeds and segment-start bits.  A record's
-    // predecessor is the lane below; lane 0 takes it from lane 63 of the wave
-    // row before (through LDS), the first row's from memory.  Shards are found
-    // from the first row's one forward.
-    constexpr int HR = HALO / GB;  // halo rows
-    constexpr int NR = HR + GI;    // rows loaded
-    const int lane = lane_id();
-    const int w = t / WAVE;
-    const long base = (long)tile0 - HALO;  // record of LDS position 0
-    i64 vj[NR], vt[NR];
-    double vla[NR], vlo[NR];
-    float vsp[GI];
-#pragma unroll
-    for (int rr = 0; rr < NR; ++rr) {
-        // positions outside [0, n) read a record in range (ignored below): no
-        // branches between the loads
-        long r = base + rr * GB + t;
-        r = r < 0 ? 0 : (r < (long)n ? r : (long)n - 1);
-        vj[rr] = jid[r];
-        vt[rr] = ts[r];
-        vla[rr] = lat[r];
-        vlo[rr] = lon[r];
-        if (rr >= HR) vsp[rr - HR] = spd[r];
-    }
-    if (t == 0) {
-        s_pj = base > 0 ? jid[base - 1] : 0;
-        s_ptb = base > 0 ? floor_div64(ts[base - 1] - g.t0, g.bin_ms) : 0;
-        s_lo = -1;
-    }
-    u64 n_out = 0;
-    const u32 sh0 = g.S > 1 ? shard_of(g.soff, g.S, (u64)(base > 0 ? base : 0)) : 0u;
-    uint8_t seg_b[NR];
-#pragma unroll
-    for (int rr = 0; rr < NR; ++rr) {
-        const int q = rr * GB + t;
-        const long r = base + q;
-        const bool in = r >= 0 && r < (long)n;
-        i64 k = -1, tb = 0;
-        u32 sh = sh0;
-        if (in) {
-            if (g.S > 1)
-                while (sh + 1 < g.S && g.soff[sh + 1] <= (u64)r) ++sh;
-            k = grid_key_in(g, sh, vt[rr], vla[rr], vlo[rr], tb);
-            if (rr >= HR) n_out += (k < 0);
-        }
-        const i64 jp = __shfl_up(vj[rr], 1, WAVE);
-        const i64 tbp = __shfl_up(tb, 1, WAVE);
-        if (lane == WAVE - 1) {
-            s_lj[rr][w] = vj[rr];
-            s_ltb[rr][w] = tb;
-        }
-        // lane 0's bit is completed below, once lane 63 of the row before is in LDS
-        const bool seg = r == 0 || (lane > 0 && (vj[rr] != jp || tb != tbp)) || (g.S > 1 && g.soff[sh] == (u64)r);
-        seg_b[rr] = (!in || seg) ? B_SEG : 0;
-        if (lane == 0) s_ltbs[rr][w] = tb;
-        s_key[q] = k;
-        if (rr >= HR) s_spd[q - HALO] = in ? vsp[rr - HR] : 0.f;
-    }
-    __syncthreads();
-    int lo_cand = -1;
-#pragma unroll
-    for (int rr = 0; rr < NR; ++rr) {
-        const int q = rr * GB + t;
-        const long r = base + q;
-        uint8_t b = seg_b[rr];
-        if (lane == 0 && r > 0 && r < (long)n && !b) {
-            // predecessor: lane 63 of the previous wave row
-            const bool first_row = w == 0 && rr == 0;
-            const int pr = w > 0 ? rr : rr - 1;
-            const int pw = w > 0 ? w - 1 : NWG - 1;
-            const i64 pj = first_row ? s_pj : s_lj[pr][pw];
-            const i64 ptb = first_row ? s_ptb : s_ltb[pr][pw];
-            if (vj[rr] != pj || s_ltbs[rr][w] != ptb) b = B_SEG;
-        }
-        s_bits[q] = b;
-        if (b && q <= HALO) lo_cand = q;
-    }
-    // the tile's first segment starts at the last segment start at or before
-    // the tile's first record; none in the halo: it starts further back
-    if (lo_cand >= 0) atomicMax(&s_lo, lo_cand);
-    __syncthreads();
-    const bool exhausted = s_lo < 0;
-    const int lo_bound = exhausted ? 0 : s_lo;
-    // Run heads over [lo_bound, HALO + tvalid), compacted in order into a list
-    // of positions: every thread marks and counts the heads of its own
-    // contiguous stretch, one block scan places the stretches.
-    const int qend = HALO + (int)tvalid;
-    {
-        const int span = qend - lo_bound;
-        const int per = (span + GB - 1) / GB;
-        const int q0 = lo_bound + t * per;
-        const int q1 = q0 + per < qend ? q0 + per : qend;
-        u32 cnt = 0;
-        for (int q = q0; q < q1; ++q) {
-            uint8_t b = s_bits[q];
-            if ((b & B_SEG) || q == lo_bound || s_key[q] != s_key[q - 1]) {
-                b |= B_RUN;
-                ++cnt;
-            }
-            s_bits[q] = b;
-        }
-        u32 tot;
-        u32 at = block_exclusive_sum<GB>(cnt, s_tmp, tot);
-        for (int q = q0; q < q1; ++q) {
-            const uint8_t b = s_bits[q];
-            if (b & B_RUN) s_lpos[at++] = (uint16_t)(q | ((b & B_SEG) ? 0x8000 : 0));
-        }
-        if (t == 0) s_nlist = tot;
-        __syncthreads();
-    }
-    const int L = (int)s_nlist;
-    // distinct-journey flag of every run head inside the tile: no earlier run
-    // head of its segment has the same key
-    for (int e = t; e < L; e += GB) {
-        const u32 pe = s_lpos[e];
-        const int q = (int)(pe & 0x7FFFu);
-        if (q < HALO) continue;
-        const i64 k = s_key[q];
-        if (k < 0) continue;
-        bool first = true;
-        if (!(pe & 0x8000u)) {
-            int f = e - 1;
-            bool closed = false;
-            for (; f >= 0; --f) {
-                const u32 pf = s_lpos[f];
-                if (s_key[pf & 0x7FFFu] == k) {
-                    first = false;
-                    break;
-                }
-                if (pf & 0x8000u) {
-                    closed = true;
-                    break;
-                }
-            }
-            if (first && f < 0 && !closed && exhausted) {
-                // the segment starts before the loaded halo: continue in global memory
-                long rr = (long)tile0 - HALO + lo_bound - 1;
-                while (rr >= 0) {
-                    i64 tb;
-                    const i64 kk = grid_key(g, (u64)rr, ts[rr], lat[rr], lon[rr], tb);
-                    if (kk == k) {
-                        first = false;
-                        break;
-                    }
-                    if (seg_start(g, jid, ts, (u64)rr, tb)) break;
-                    --rr;
-                }
-            }
-        }
-        if (first) s_bits[q] |= B_FIRST;
-    }
-    __syncthreads();
-    // Aggregation: every wave walks its GT/4 records of the tile in windows of
-    // 64.  Lanes fold records into a private partial of the open run while the
-    // window holds no run start.  A window with starts closes the open run
-    // (one wave reduction over every lane's partial and the records before the
-    // first start), reduces the runs that begin and end inside it (segmented
-    // scan, only when there are two or more starts), and leaves the run of its
-    // last start open as the private partials of that start's lanes.  Each
-    // finished run is one LDS hash insert.  A wave's first record starts a
-    // piece of its own.
-    {
-        constexpr int WREC = GT / (GB / WAVE);
-        const int w = t / WAVE, l = lane_id();
-        const int qa = HALO + w * WREC;
-        RunPart p;
-        run_reset(p);
-        i64 open_key = -1;
-        for (int i = 0; i < WREC / WAVE; ++i) {
-            const int q = qa + i * WAVE + l;
-            const bool valid = q < qend;
-            const i64 k = valid ? s_key[q] : -1;
-            const uint8_t b = valid ? s_bits[q] : 0;
-            const bool head = valid && ((b & B_RUN) || (i == 0 && l == 0));
-            RunPart c;
-            run_reset(c);
-            if (valid && k >= 0) {
-                const float sp = s_spd[q - HALO];
-                i64 x;
-                if (spd_fix53(sp, x)) {
-                    c.lo = (u64)x;
-                    c.hi = (u64)(x >> 63);
-                } else {
-                    // a speed outside the 128-bit range: its exact value on its own
-                    slot_insert<LHS>(s_hkey, s_h, tab, gmask, meta, (u64)k, fx_from_double<FX_SPD>((double)sp), 0u,
-                                     0u, ~0u, 0u);
-                }
-                c.cn = 1u | ((b & B_FIRST) ? (1u << 16) : 0u);
-                c.mn = c.mx = ord_f32(sp);
-            }
-            const u64 H = __ballot(head);
-            if (H == 0) {
-                run_combine(p, c);
-                continue;
-            }
-            const int f0 = __ffsll((long long)H) - 1;
-            const int lh = 63 - __clzll((long long)H);  // last start: its run stays open
-            // close the open run: every lane's partial and the records before the first start
-            RunPart x = p;
-            if (l < f0) run_combine(x, c);
-            run_wave_reduce(x);
-            if (l == 0 && open_key >= 0 && x.cn) run_insert<LHS>(s_hkey, s_h, tab, gmask, meta, (u64)open_key, x);
-            // runs between two starts of this window
-            if (f0 != lh) {
-                RunPart y;
-                if (l >= f0 && l < lh) y = c;
-                else run_reset(y);
-                run_seg_scan(y, head);
-                const bool next_head = (l < WAVE - 1) && ((H >> (l + 1)) & 1ull);
-                if (l >= f0 && l < lh && next_head && k >= 0 && y.cn)
-                    run_insert<LHS>(s_hkey, s_h, tab, gmask, meta, (u64)k, y);
-            }
-            open_key = __shfl(k, lh, WAVE);
-            if (l >= lh) p = c;
-            else run_reset(p);
-        }
-        run_wave_reduce(p);
-        if (l == 0 && open_key >= 0 && p.cn) run_insert<LHS>(s_hkey, s_h, tab, gmask, meta, (u64)open_key, p);
-    }
-    // out-of-grid count (one global atomic per tile, only when non-zero)
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) n_out += __shfl_xor(n_out, d, WAVE);
-    if (lane_id() == 0) s_out[t / WAVE] = n_out;
-    __syncthreads();
-    if (t == 0) {
-        u64 tot = 0;
-        for (int w = 0; w < GB / WAVE; ++w) tot += s_out[w];
-        if (tot) atomicAdd((unsigned long long*)&meta->n_out, (unsigned long long)tot);
-    }
-    // merge the LDS table into the HBM table
-    for (int i = t; i < LHS; i += GB) {
-        const u64 key = s_hkey[i];
-        if (key == GEMPTY) continue;
-        const LSlot& sl = s_h[i];
-        const Fx192 sum = fx_from_cs(sl.cs);
-        g_insert(tab, gmask, meta, key, sl.count, sl.nj, sum, sl.mn, sl.mx);
-    }
-}
 
 struct GridLayout {
     GridMeta* meta;
@@ -586,14 +156,17 @@ static cv_status grid_impl(const cv_records* sorted, const u64* soff, u32 S, con
         cvh::fill_u32(L.zero_begin, 0u, L.zero_bytes / 4, s);
         const dim3 gg((unsigned)L.tiles), gb(GB);
         if (g_lds_slots >= 1024)
-            hipLaunchKernelGGL((k_grid_agg<1024>), gg, gb, 0, s, nn, sorted->journey_id, sorted->ts_ms,
-                               sorted->lat_deg, sorted->lon_deg, sorted->speed_mps, g, L.tab, L.slots - 1, L.meta);
+            hipLaunchKernelGGL((k_grid_agg<1024, GridPlain>), gg, gb, 0, s, nn, sorted->journey_id, sorted->ts_ms,
+                               sorted->lat_deg, sorted->lon_deg, sorted->speed_mps, g, L.tab, L.slots - 1, L.meta,
+                               GridPlain{});
         else if (g_lds_slots >= 512)
-            hipLaunchKernelGGL((k_grid_agg<512>), gg, gb, 0, s, nn, sorted->journey_id, sorted->ts_ms,
-                               sorted->lat_deg, sorted->lon_deg, sorted->speed_mps, g, L.tab, L.slots - 1, L.meta);
+            hipLaunchKernelGGL((k_grid_agg<512, GridPlain>), gg, gb, 0, s, nn, sorted->journey_id, sorted->ts_ms,
+                               sorted->lat_deg, sorted->lon_deg, sorted->speed_mps, g, L.tab, L.slots - 1, L.meta,
+                               GridPlain{});
         else
-            hipLaunchKernelGGL((k_grid_agg<256>), gg, gb, 0, s, nn, sorted->journey_id, sorted->ts_ms,
-                               sorted->lat_deg, sorted->lon_deg, sorted->speed_mps, g, L.tab, L.slots - 1, L.meta);
+            hipLaunchKernelGGL((k_grid_agg<256, GridPlain>), gg, gb, 0, s, nn, sorted->journey_id, sorted->ts_ms,
+                               sorted->lat_deg, sorted->lon_deg, sorted->speed_mps, g, L.tab, L.slots - 1, L.meta,
+                               GridPlain{});
     }
     {
         cvh::TimedScope ts_("grid_tail", s);

@@ -29,9 +29,11 @@
 #include <new>
 
 #include "cv_device.h"
+#include "cv_gridagg.h"
 #include "cv_gridtab.h"
 #include "cv_host.h"
 #include "cv_radix.h"
+#include "cv_sumtab.h"
 
 using namespace cv;
 
@@ -49,26 +51,6 @@ constexpr int OVF_SLOTS = 512;          // open-addressing slots of one overflow
 constexpr u32 OVF_MAX = 384;            // cells one segment may keep there (75 % load)
 constexpr u64 OVF_EMPTY = ~0ull;        // group keys are non-negative
 
-// Membership of a cell in the row's overflow table for its open segment; true
-// when it was not there (and is now).  Only the thread folding the row reads
-// or writes the table.  A full table sets *full and answers true.
-__device__ __forceinline__ bool ovf_insert(u64* tab, u64 key, u32& used, bool* full)
-{
-    u32 h = (u32)mix64(key) & (OVF_SLOTS - 1);
-    for (int probe = 0; probe < OVF_SLOTS; ++probe) {
-        const u64 cur = tab[h];
-        if (cur == key) return false;
-        if (cur == OVF_EMPTY) {
-            if (used >= OVF_MAX) break;
-            tab[h] = key;
-            ++used;
-            return true;
-        }
-        h = (h + 1) & (OVF_SLOTS - 1);
-    }
-    *full = true;
-    return true;
-}
 constexpr u64 JEMPTY = 0x8000000000000000ull;
 constexpr u32 FLAG_LATE = 0x80u;
 constexpr u32 FLAG_PRED_CARRIED = 0x100u;  // internal: predecessor is the row's last point
@@ -97,6 +79,8 @@ struct StreamMeta {
     u32 cell_overflow;  // a segment outgrew its overflow table or the pool ran out:
                         // distinct-journey counts may be high (sticky)
     u32 ovf_next;       // overflow tables taken from the pool
+    u32 ap_n;           // cells appended this push (records that counted their journey in a cell)
+    u32 pad3;
     u64 batch_late, batch_out;
     u64 total_records, total_late, total_out;
     u32 jcount;         // flush: occupied journey rows
@@ -137,7 +121,8 @@ __global__ void k_st_begin(StreamMeta* m)
 {
     if (threadIdx.x == 0) {
         m->batch_late = 0;
-        m->batch_out = 0;
+        m->batch_out = m->gm.n_out;  // the count before this batch
+        m->ap_n = 0;
         m->Jb = 0;
     }
 }
@@ -393,195 +378,226 @@ __global__ void __launch_bounds__(FB) k_st_features(u32 n, const i64* __restrict
     fs_flags[k] = (uint8_t)f;
 }
 
-// One thread per batch journey: running summary, group table, resident state.
-__global__ void __launch_bounds__(256) k_st_fold(const i64* __restrict__ ts, const double* __restrict__ lat,
-                                                 const double* __restrict__ lon, const float* __restrict__ spd,
-                                                 const u32* __restrict__ boff, StreamMeta* m,
-                                                 const u32* __restrict__ bslot, JRow* __restrict__ rows,
-                                                 const double* __restrict__ fs_step, const double* __restrict__ fs_v,
-                                                 const double* __restrict__ fs_b, const uint8_t* __restrict__ fs_flags,
-                                                 Spec g, GEntry* __restrict__ tab, u64 gmask,
-                                                 u64* __restrict__ ovf_pool, u32 ovf_pages)
+// a cell that counted its journey in this push: the row and the group key
+struct Append {
+    u64 key;
+    u32 slot, pad;
+};
+
+// Membership of a cell in a row's overflow table (read side).
+__device__ __forceinline__ bool ovf_contains(const u64* tab, u64 key)
 {
-    __shared__ u64 s_red[2][4];
+    u32 h = (u32)mix64(key) & (OVF_SLOTS - 1);
+    for (int probe = 0; probe < OVF_SLOTS; ++probe) {
+        const u64 cur = tab[h];
+        if (cur == key) return true;
+        if (cur == OVF_EMPTY) return false;
+        h = (h + 1) & (OVF_SLOTS - 1);
+    }
+    return false;
+}
+
+// Grid tile kernel policy of the serving form.  Late records count in their
+// cells but never as a new distinct journey; a journey's first segment in the
+// batch that continues the row's open segment (same time bin) also checks the
+// cells the row carried over; every record that counts its journey in a cell
+// is appended for the row update that follows the tile kernel.
+struct GridStream {
+    static constexpr bool kStream = true;
+    const i64* jid;          // sorted batch
+    const uint8_t* flags;    // sorted batch features' flags
+    const u32* boff;         // batch journey starts
+    const StreamMeta* m;     // Jb
+    const u32* bslot;        // resident row of each batch journey
+    const JRow* rows;
+    const u64* ovf_pool;
+    i64 cells;               // n_lat * n_lon: a key's time bin is key / cells
+    Append* ap;
+    u32 apcap;
+    u32* ap_n;
+
+    __device__ bool late(u64 r) const { return (flags[r] & FLAG_LATE) != 0; }
+    __device__ u32 slot_of(u64 r) const { return bslot[batch_journey_of(boff, m->Jb, (u32)r)]; }
+    // r0: first record of a segment of non-late records; key: a cell of it
+    __device__ bool carried(u64 r0, u64 key) const
+    {
+        if (r0 > 0 && jid[r0 - 1] == jid[r0] && !late(r0 - 1)) return false;  // begins inside the batch
+        const u32 slot = slot_of(r0);
+        if (slot == ~0u) return false;
+        const JRow& R = rows[slot];
+        if (R.seg_tbin != (i64)(key / (u64)cells)) return false;
+        const u32 nc = R.ncell < (u32)KCELLS ? R.ncell : (u32)KCELLS;
+        for (u32 c = 0; c < nc; ++c)
+            if (R.cell[c] == key) return true;
+        if (R.novf && R.ovf < OVF_FAIL) return ovf_contains(ovf_pool + (u64)R.ovf * OVF_SLOTS, key);
+        return false;
+    }
+    __device__ void first(u64 r, u64 key) const
+    {
+        const u32 slot = slot_of(r);
+        if (slot == ~0u) return;
+        const u32 i = atomicAdd(ap_n, 1u);
+        if (i < apcap) {
+            ap[i].key = key;
+            ap[i].slot = slot;
+        }
+    }
+};
+
+// One thread per batch journey: the batch's exact partial (JAcc / AccX row j)
+// joins the resident row; the last non-late record becomes the row's last
+// point; when the batch's last non-late record opens a new (journey, time-bin)
+// segment, the row's cell set starts empty for it.
+__global__ void __launch_bounds__(256) k_st_merge(const i64* __restrict__ ts, const double* __restrict__ lat,
+                                                  const double* __restrict__ lon, const u32* __restrict__ boff,
+                                                  StreamMeta* m, const u32* __restrict__ bslot,
+                                                  JRow* __restrict__ rows, const JAcc* __restrict__ acc,
+                                                  const AccX* __restrict__ accx, u32 arows,
+                                                  const double* __restrict__ fs_v,
+                                                  const double* __restrict__ fs_b,
+                                                  const uint8_t* __restrict__ fs_flags, Spec g,
+                                                  u64* __restrict__ ovf_pool)
+{
+    __shared__ u64 s_late[256 / WAVE];
     const u32 Jb = m->Jb;
-    u64 late_n = 0, out_n = 0;
-    bool overflow = false;
+    u64 late_n = 0;
     for (u32 j = blockIdx.x * blockDim.x + threadIdx.x; j < Jb; j += gridDim.x * blockDim.x) {
         const u32 slot = bslot[j];
-        if (slot == ~0u) continue;
+        if (slot == ~0u || j >= arows) continue;
         JRow& R = rows[slot];
         const u32 a = boff[j], e = boff[j + 1];
-        Fx192 dist, sps;
-        dist.w[0] = R.dist[0];
-        dist.w[1] = R.dist[1];
-        dist.w[2] = R.dist[2];
-        sps.w[0] = R.spd[0];
-        sps.w[1] = R.spd[1];
-        sps.w[2] = R.spd[2];
-        u32 count = R.count, ndtz = R.ndtz, maxs = R.maxs, ncell = R.ncell;
-        u32 ovf = R.ovf, novf = R.novf;
-        u64 maxd = R.maxd, la0 = R.latmin, la1 = R.latmax, lo0 = R.lonmin, lo1 = R.lonmax;
-        u64 tmin = R.tmin_ord, tmax = R.tmax_ord;
-        i64 seg = R.seg_tbin;
-        u64 cells[KCELLS];
-#pragma unroll
-        for (int c = 0; c < KCELLS; ++c) cells[c] = R.cell[c];
-        // current run of equal key
-        i64 rk = -1;
-        u32 rc = 0, rnj = 0, rmn = ~0u, rmx = 0;
-        Fx192 rsum;
-        fx_zero(rsum);
-        u32 last_good = ~0u;
-        for (u32 k = a; k < e; ++k) {
-            const uint8_t f = fs_flags[k];
-            const bool late = (f & FLAG_LATE) != 0;
-            const float sv = spd[k];
-            const double la = lat[k], lo = lon[k];
-            count += 1;
-            late_n += late;
-            ndtz += (f & CV_FLAG_DT_ZERO) ? 1u : 0u;
-            Fx192 t1 = fx_from_double<FX_DIST>(fs_step[k]);
-            fx_add(dist, t1);
-            Fx192 t2 = fx_from_double<FX_SPD>((double)sv);
-            fx_add(sps, t2);
-            const u32 ms = ord_f32(sv);
-            maxs = ms > maxs ? ms : maxs;
-            if (f & CV_FLAG_SPEED_OK) {
-                const u64 d = ord_f64(fs_v[k]);
-                maxd = d > maxd ? d : maxd;
-            }
-            if (isfinite(la) && isfinite(lo)) {
-                const u64 x = ord_f64(la), y = ord_f64(lo);
-                la0 = x < la0 ? x : la0;
-                la1 = x > la1 ? x : la1;
-                lo0 = y < lo0 ? y : lo0;
-                lo1 = y > lo1 ? y : lo1;
-            }
-            const u64 to = ord_i64(ts[k]);
-            tmin = to < tmin ? to : tmin;
-            tmax = to > tmax ? to : tmax;
-            if (!late) last_good = k;
-            // grid
-            i64 tb;
-            const i64 key = grid_key(g, k, ts[k], la, lo, tb);
-            if (key < 0) {
-                ++out_n;
-                if (rc) g_insert(tab, gmask, &m->gm, (u64)rk, rc, rnj, rsum, rmn, rmx);
-                rc = 0;
-                rk = -1;
-                continue;
-            }
-            bool first = false;
-            if (!late) {
-                if (tb != seg) {  // a new (journey, time-bin) segment
-                    seg = tb;
-                    ncell = 0;
-                    if (novf) {  // the overflow table starts empty again
-                        u64* t = ovf_pool + (u64)ovf * OVF_SLOTS;
-                        for (int c = 0; c < OVF_SLOTS; ++c) t[c] = OVF_EMPTY;
-                        novf = 0;
-                    }
-                }
-                bool seen = false;
-#pragma unroll
-                for (int c = 0; c < KCELLS; ++c) seen |= ((u32)c < ncell) && cells[c] == (u64)key;
-                if (!seen) {
-                    if (ncell < KCELLS) {
-                        first = true;
-#pragma unroll
-                        for (int c = 0; c < KCELLS; ++c)
-                            if ((u32)c == ncell) cells[c] = (u64)key;
-                        ++ncell;
-                    } else {
-                        if (ovf == OVF_NONE) {  // first overflow of this row: take a table
-                            const u32 pg = atomicAdd(&m->ovf_next, 1u);
-                            ovf = pg < ovf_pages ? pg : OVF_FAIL;
-                        }
-                        if (ovf == OVF_FAIL) {
-                            overflow = true;
-                            first = true;
-                        } else {
-                            first = ovf_insert(ovf_pool + (u64)ovf * OVF_SLOTS, (u64)key, novf, &overflow);
-                        }
-                    }
-                }
-            }
-            if (rc && key != rk) {
-                g_insert(tab, gmask, &m->gm, (u64)rk, rc, rnj, rsum, rmn, rmx);
-                rc = 0;
-            }
-            if (rc == 0) {
-                rk = key;
-                rnj = 0;
-                rmn = ~0u;
-                rmx = 0;
-                fx_zero(rsum);
-            }
-            rc += 1;
-            rnj += first ? 1u : 0u;
-            fx_add(rsum, t2);
-            rmn = ms < rmn ? ms : rmn;
-            rmx = ms > rmx ? ms : rmx;
+        const JAcc& A = acc[j];
+        const AccX& X = accx[j];
+        Fx192 d, sp, t;
+        for (int i = 0; i < 3; ++i) {
+            d.w[i] = R.dist[i];
+            sp.w[i] = R.spd[i];
         }
-        if (rc) g_insert(tab, gmask, &m->gm, (u64)rk, rc, rnj, rsum, rmn, rmx);
-        R.dist[0] = dist.w[0];
-        R.dist[1] = dist.w[1];
-        R.dist[2] = dist.w[2];
-        R.spd[0] = sps.w[0];
-        R.spd[1] = sps.w[1];
-        R.spd[2] = sps.w[2];
-        R.count = count;
-        R.ndtz = ndtz;
-        R.maxs = maxs;
-        R.maxd = maxd;
-        R.latmin = la0;
-        R.latmax = la1;
-        R.lonmin = lo0;
-        R.lonmax = lo1;
-        R.tmin_ord = tmin;
-        R.tmax_ord = tmax;
-        R.seg_tbin = seg;
-        R.ncell = ncell;
-        R.ovf = ovf;
-        R.novf = novf;
-#pragma unroll
-        for (int c = 0; c < KCELLS; ++c) R.cell[c] = cells[c];
-        if (last_good != ~0u) {
-            R.last_ts = ts[last_good];
-            R.last_lat = lat[last_good];
-            R.last_lon = lon[last_good];
-            R.last_v = fs_v[last_good];
-            R.last_b = fs_b[last_good];
-            R.last_flags = fs_flags[last_good];
+        for (int i = 0; i < 3; ++i) t.w[i] = A.dist[i];
+        fx_add(d, t);
+        for (int i = 0; i < 3; ++i) t.w[i] = X.dist[i];
+        fx_add(d, t);
+        for (int i = 0; i < 3; ++i) t.w[i] = A.spd[i];
+        fx_add(sp, t);
+        for (int i = 0; i < 3; ++i) t.w[i] = X.spd[i];
+        fx_add(sp, t);
+        for (int i = 0; i < 3; ++i) {
+            R.dist[i] = d.w[i];
+            R.spd[i] = sp.w[i];
+        }
+        R.count += A.count;
+        R.ndtz += A.ndtz;
+        R.maxs = A.maxs > R.maxs ? A.maxs : R.maxs;
+        R.maxd = A.maxd > R.maxd ? A.maxd : R.maxd;
+        R.latmin = A.latmin < R.latmin ? A.latmin : R.latmin;
+        R.latmax = A.latmax > R.latmax ? A.latmax : R.latmax;
+        R.lonmin = A.lonmin < R.lonmin ? A.lonmin : R.lonmin;
+        R.lonmax = A.lonmax > R.lonmax ? A.lonmax : R.lonmax;
+        // the batch is in (journey, time) order: its time span is at both ends
+        const u64 t0 = ord_i64(ts[a]), t1 = ord_i64(ts[e - 1]);
+        R.tmin_ord = t0 < R.tmin_ord ? t0 : R.tmin_ord;
+        R.tmax_ord = t1 > R.tmax_ord ? t1 : R.tmax_ord;
+        // late records come first (older than the row's last point)
+        u32 k = a;
+        while (k < e && (fs_flags[k] & FLAG_LATE)) ++k;
+        late_n += k - a;
+        if (k < e) {
+            const u32 lg = e - 1;  // the last record is the last non-late one
+            R.last_ts = ts[lg];
+            R.last_lat = lat[lg];
+            R.last_lon = lon[lg];
+            R.last_v = fs_v[lg];
+            R.last_b = fs_b[lg];
+            R.last_flags = fs_flags[lg];
             R.has_last = 1;
+            const i64 tb = floor_div64(ts[lg] - g.t0, g.bin_ms);
+            if (tb != R.seg_tbin) {
+                R.seg_tbin = tb;
+                R.ncell = 0;
+                if (R.novf && R.ovf < OVF_FAIL) {
+                    u64* pg = ovf_pool + (u64)R.ovf * OVF_SLOTS;
+                    for (int c = 0; c < OVF_SLOTS; ++c) pg[c] = OVF_EMPTY;
+                }
+                R.novf = 0;
+            }
         }
     }
 #pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) {
-        late_n += __shfl_xor(late_n, d, WAVE);
-        out_n += __shfl_xor(out_n, d, WAVE);
-    }
-    if (lane_id() == 0) {
-        s_red[0][threadIdx.x / WAVE] = late_n;
-        s_red[1][threadIdx.x / WAVE] = out_n;
-    }
-    if (overflow) atomicOr(&m->cell_overflow, 1u);
+    for (int dd = 32; dd >= 1; dd >>= 1) late_n += __shfl_xor(late_n, dd, WAVE);
+    if (lane_id() == 0) s_late[threadIdx.x / WAVE] = late_n;
     __syncthreads();
     if (threadIdx.x == 0) {
-        u64 l = 0, o = 0;
-        for (int w = 0; w < 4; ++w) {
-            l += s_red[0][w];
-            o += s_red[1][w];
-        }
-        if (l) atomicAdd((unsigned long long*)&m->batch_late, (unsigned long long)l);
-        if (o) atomicAdd((unsigned long long*)&m->batch_out, (unsigned long long)o);
+        u64 tl = 0;
+        for (int w = 0; w < 256 / WAVE; ++w) tl += s_late[w];
+        if (tl) atomicAdd((unsigned long long*)&m->batch_late, (unsigned long long)tl);
     }
+}
+
+// One thread per appended cell: cells of a row's open segment (after the
+// merge) join the row's set, in the row while it has room.  Each cell takes a
+// position in the set with one atomic; the cell at position KCELLS (one per
+// row, ever at most one per push) takes the row's overflow table from the
+// pool when the row has none, so a row holds at most one table.  Cells of
+// earlier segments of the batch are dropped.  ap[i].pad keeps the position
+// (or ~0u) for k_st_append_ovf.
+__global__ void __launch_bounds__(256) k_st_append(Append* __restrict__ ap, StreamMeta* m, u32 apcap,
+                                                   JRow* __restrict__ rows, u32 ovf_pages, i64 cells)
+{
+    const u32 na = m->ap_n < apcap ? m->ap_n : apcap;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && m->ap_n > apcap) atomicOr(&m->cell_overflow, 1u);
+    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < na; i += gridDim.x * blockDim.x) {
+        const u64 key = ap[i].key;
+        JRow& R = rows[ap[i].slot];
+        u32 c = ~0u;
+        if ((i64)(key / (u64)cells) == R.seg_tbin) {
+            c = atomicAdd(&R.ncell, 1u);
+            if (c < (u32)KCELLS) {
+                R.cell[c] = key;
+            } else if (c == (u32)KCELLS && R.ovf == OVF_NONE) {
+                const u32 pg = atomicAdd(&m->ovf_next, 1u);
+                R.ovf = pg < ovf_pages ? pg : OVF_FAIL;
+            }
+        }
+        ap[i].pad = c;
+    }
+}
+
+// One thread per appended cell past the row's KCELLS: the cell joins the
+// row's overflow table (open addressing, bounded load).  A full table, or a
+// row the pool had no table for, sets the sticky overflow flag.
+__global__ void __launch_bounds__(256) k_st_append_ovf(const Append* __restrict__ ap, StreamMeta* m, u32 apcap,
+                                                       JRow* __restrict__ rows, u64* __restrict__ ovf_pool)
+{
+    const u32 na = m->ap_n < apcap ? m->ap_n : apcap;
+    bool full = false;
+    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < na; i += gridDim.x * blockDim.x) {
+        const u32 c = ap[i].pad;
+        if (c == ~0u || c < (u32)KCELLS) continue;
+        JRow& R = rows[ap[i].slot];
+        const u32 pg = R.ovf;
+        if (pg >= OVF_FAIL || atomicAdd(&R.novf, 1u) >= OVF_MAX) {
+            full = true;
+            continue;
+        }
+        const u64 key = ap[i].key;
+        u64* tab = ovf_pool + (u64)pg * OVF_SLOTS;
+        u32 h = (u32)mix64(key) & (OVF_SLOTS - 1);
+        bool placed = false;
+        for (int probe = 0; probe < OVF_SLOTS && !placed; ++probe) {
+            const u64 prev = atomicCAS((unsigned long long*)&tab[h], (unsigned long long)OVF_EMPTY,
+                                       (unsigned long long)key);
+            placed = prev == OVF_EMPTY || prev == key;
+            h = (h + 1) & (OVF_SLOTS - 1);
+        }
+        if (!placed) full = true;
+    }
+    if (full) atomicOr(&m->cell_overflow, 1u);
 }
 
 __global__ void k_st_finish(StreamMeta* m, const cv_result* sres, u32 n, cv_result* res)
 {
     if (threadIdx.x != 0) return;
+    m->batch_out = m->gm.n_out - m->batch_out;
     m->total_records += n;
     m->total_late += m->batch_late;
     m->total_out += m->batch_out;
@@ -705,6 +721,11 @@ struct cv_stream {
     uint8_t* fs_flags;
     u32 *tile_cnt, *boff, *bslot;
     cv_result* sres;
+    cv::JAcc* acc;  // exact partial summaries of the batch's journeys
+    cv::AccX* accx;
+    u64 arows;      // rows of acc / accx
+    void* sum_ws;
+    Append* ap;     // cells that counted their journey in this push
     // flush scratch
     u64 *gK0, *gK1, *jK0, *jK1;
     u32 *gC, *gV0, *gV1, *jV0, *jV1, *jfirst;
@@ -717,6 +738,9 @@ namespace {
 
 // overflow tables in the pool: one per 32 journey slots (one per 64 journeys)
 u32 ovf_pages(u64 jslots) { return (u32)(jslots / 32 < 64 ? 64 : jslots / 32); }
+
+// a batch with more journeys than the table has slots overflows the table anyway
+u64 acc_rows(u64 jslots, u64 mb) { return mb < jslots ? (mb ? mb : 1) : jslots; }
 
 struct StreamLayout {
     size_t bytes;
@@ -747,6 +771,11 @@ struct StreamLayout {
         f("boff", c.take<u32>(mb + 1));
         f("bslot", c.take<u32>(mb + 1));
         f("sres", c.take<cv_result>(1));
+        const u64 arows = acc_rows(jslots, mb);
+        f("acc", c.take<cv::JAcc>(arows));
+        f("accx", c.take<cv::AccX>(arows));
+        f("sum_ws", c.take<char>(cv::sum_partials_bytes(mb)));
+        f("ap", c.take<Append>(mb));
         const u64 gst = (gslots + sort_min_tile() - 1) / sort_min_tile();
         const u64 jst = (jslots + sort_min_tile() - 1) / sort_min_tile();
         f("gK0", c.take<u64>(gslots));
@@ -851,6 +880,10 @@ cv_status cv_stream_create(const cv_grid_spec* grid, uint64_t max_journeys, uint
         else if (nm == "boff") st->boff = (u32*)p;
         else if (nm == "bslot") st->bslot = (u32*)p;
         else if (nm == "sres") st->sres = (cv_result*)p;
+        else if (nm == "acc") st->acc = (cv::JAcc*)p;
+        else if (nm == "accx") st->accx = (cv::AccX*)p;
+        else if (nm == "sum_ws") st->sum_ws = p;
+        else if (nm == "ap") st->ap = (Append*)p;
         else if (nm == "gK0") st->gK0 = (u64*)p;
         else if (nm == "gK1") st->gK1 = (u64*)p;
         else if (nm == "gC") st->gC = (u32*)p;
@@ -869,6 +902,7 @@ cv_status cv_stream_create(const cv_grid_spec* grid, uint64_t max_journeys, uint
         else if (nm == "jstatus") st->jstatus = (u64*)p;
     });
     cv_sort_workspace_size(max_batch, max_batch ? max_batch : 1, &st->sort_ws_bytes);
+    st->arows = acc_rows(st->jslots, max_batch);
     hipStream_t s = (hipStream_t)stream;
     hipLaunchKernelGGL(k_st_init_meta, dim3(1), dim3(64), 0, s, st->meta);
     cvh::fill_u64(st->jkeys, JEMPTY, st->jslots, s);
@@ -905,7 +939,9 @@ cv_status cv_stream_push(cv_stream* st, const cv_records* batch, const cv_featur
     cvh::TimedScope ts_("stream_push", s);
     hipLaunchKernelGGL(k_st_begin, dim3(1), dim3(64), 0, s, st->meta);
     cv_records_out so{st->s_jid, st->s_ts, st->s_lat, st->s_lon, st->s_spd};
-    cv_status e = cv::sort_records_into(batch, st->max_batch, st->perm, &so, st->sres, st->sort_ws, st->sort_ws_bytes, s);
+    // a batch holds at most n distinct journeys: the dictionary of its sort is
+    // sized (and cleared) for n, within the workspace carved for max_batch
+    cv_status e = cv::sort_records_into(batch, n, st->perm, &so, st->sres, st->sort_ws, st->sort_ws_bytes, s);
     if (e != CV_OK) return e;
     const u32 tiles = (u32)((n + ST_TILE - 1) / ST_TILE);
     hipLaunchKernelGGL(k_st_count, dim3(tiles), dim3(256), 0, s, st->s_jid, nn, st->tile_cnt);
@@ -916,10 +952,35 @@ cv_status cv_stream_push(cv_stream* st, const cv_records* batch, const cv_featur
     hipLaunchKernelGGL(k_st_features, dim3((unsigned)((n + FB - 1) / FB)), dim3(FB), 0, s, nn, st->s_jid, st->s_ts,
                        st->s_lat, st->s_lon, st->perm, st->boff, st->meta, st->bslot, st->rows, *feat, st->fs_step,
                        st->fs_v, st->fs_b, st->fs_flags);
-    hipLaunchKernelGGL(k_st_fold, dim3(cvh::grid_for(n, 256, 2048)), dim3(256), 0, s, st->s_ts, st->s_lat,
-                       st->s_lon, st->s_spd, st->boff, st->meta, st->bslot, st->rows, st->fs_step, st->fs_v,
-                       st->fs_b, st->fs_flags, st->g, st->tab, st->gslots - 1, st->ovf_pool,
-                       ovf_pages(st->jslots));
+    // summaries: the plain kernels' exact per-journey partials of the batch
+    cv_records sb{};
+    sb.journey_id = st->s_jid;
+    sb.ts_ms = st->s_ts;
+    sb.lat_deg = st->s_lat;
+    sb.lon_deg = st->s_lon;
+    sb.speed_mps = st->s_spd;
+    sb.n = n;
+    cv_features fb{};
+    fb.step_m = st->fs_step;
+    fb.speed_mps = st->fs_v;
+    fb.flags = st->fs_flags;
+    e = cv::sum_partials(&sb, &fb, (u32)st->arows, st->acc, st->accx, st->sum_ws, s);
+    if (e != CV_OK) return e;
+    // groups: the grid tile kernel into the resident table
+    const i64 cells = st->g.n_lat * st->g.n_lon;
+    GridStream pol{st->s_jid, st->fs_flags, st->boff, st->meta, st->bslot, st->rows, st->ovf_pool,
+                   cells,     st->ap,       (u32)st->max_batch, &st->meta->ap_n};
+    hipLaunchKernelGGL((k_grid_agg<256, GridStream>), dim3((unsigned)((n + GT - 1) / GT)), dim3(GB), 0, s, nn,
+                       st->s_jid, st->s_ts, st->s_lat, st->s_lon, st->s_spd, st->g, st->tab, st->gslots - 1,
+                       &st->meta->gm, pol);
+    // resident rows: the partials, the last point, the open segment's cells
+    hipLaunchKernelGGL(k_st_merge, dim3(cvh::grid_for(n, 256, 2048)), dim3(256), 0, s, st->s_ts, st->s_lat,
+                       st->s_lon, st->boff, st->meta, st->bslot, st->rows, st->acc, st->accx, (u32)st->arows,
+                       st->fs_v, st->fs_b, st->fs_flags, st->g, st->ovf_pool);
+    hipLaunchKernelGGL(k_st_append, dim3(cvh::grid_for(n, 256, 2048)), dim3(256), 0, s, st->ap, st->meta,
+                       (u32)st->max_batch, st->rows, ovf_pages(st->jslots), cells);
+    hipLaunchKernelGGL(k_st_append_ovf, dim3(cvh::grid_for(n, 256, 2048)), dim3(256), 0, s, st->ap, st->meta,
+                       (u32)st->max_batch, st->rows, st->ovf_pool);
     hipLaunchKernelGGL(k_st_finish, dim3(1), dim3(64), 0, s, st->meta, st->sres, nn, res);
     return cvh::last_launch_status();
 }

@@ -18,6 +18,7 @@
 
 #include "cv_device.h"
 #include "cv_host.h"
+#include "cv_sumtab.h"
 
 using namespace cv;
 
@@ -26,21 +27,8 @@ namespace {
 constexpr int SB = 256;
 constexpr int SI = 16;
 constexpr int ST = SB * SI;
-constexpr int FX_DIST = 128;  // distance: 2^-128 m resolution (exact for steps >= 2^-75 m)
-constexpr int FX_SPD = 149;   // speed: exact for every float32
-
-struct JAcc {
-    u64 dist[3];
-    u64 spd[3];
-    u64 maxd;
-    u64 latmin, latmax, lonmin, lonmax;
-    u32 count, ndtz, maxs, gfirst;  // gfirst: index of the journey's first record
-};
-
-// side row of a journey: sums of the values outside the 128-bit fast formats
-struct AccX {
-    u64 dist[3], spd[3];
-};
+constexpr int FX_DIST = SUM_FX_DIST;  // distance: 2^-128 m resolution (exact for steps >= 2^-75 m)
+constexpr int FX_SPD = SUM_FX_SPD;    // speed: exact for every float32
 
 struct SumMeta {
     u32 J;
@@ -519,8 +507,8 @@ __global__ void __launch_bounds__(SB) k_sum_reduce(u32 n, const i64* __restrict_
                 if (h && jl < cap) {
                     // a journey's first record is indexed within its shard
                     const u32 sh = S > 1 ? shard_of(soff, S, r) : 0u;
-                    o.jid[jl] = jv;
-                    o.first[jl] = (u32)(S > 1 ? r - soff[sh] : r);
+                    if (o.jid) o.jid[jl] = jv;
+                    if (o.first) o.first[jl] = (u32)(S > 1 ? r - soff[sh] : r);
                     acc[jl].gfirst = (u32)r;
                 }
                 if (h && S > 1 && jo) {
@@ -686,6 +674,36 @@ static cv_status summary_impl(const cv_records* sorted, const cv_features* feat,
     return cvh::last_launch_status();
 }
 
+namespace cv {
+
+size_t sum_partials_bytes(u64 n)
+{
+    SumLayout L(nullptr, n, 0);
+    return L.bytes;
+}
+
+cv_status sum_partials(const cv_records* sorted, const cv_features* feat, u32 rows, JAcc* acc, AccX* accx, void* ws,
+                       hipStream_t s)
+{
+    const u64 n = sorted->n;
+    if (n == 0) return CV_OK;
+    SumLayout L(ws, n, 0);
+    Out o{};
+    const u32 nn = (u32)n;
+    hipLaunchKernelGGL(k_sum_count, dim3((unsigned)L.tiles), dim3(SB), 0, s, sorted->journey_id, nn, L.wcnt, L.tcnt,
+                       nullptr, 0u);
+    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(SCAN_B), 0, s, L.tcnt, L.tile_prefix, (u32)L.tiles, L.meta);
+    hipLaunchKernelGGL(k_sum_init, dim3(cvh::grid_for(rows, 256, 2048)), dim3(256), 0, s, acc, accx, L.meta, rows);
+    hipLaunchKernelGGL((k_sum_reduce<true, false>), dim3((unsigned)L.tiles), dim3(SB), 0, s, nn, sorted->journey_id,
+                       sorted->lat_deg, sorted->lon_deg, sorted->speed_mps, feat->step_m, feat->speed_mps,
+                       feat->flags, L.tile_prefix, L.wcnt, rows, o, acc, accx, nullptr, 0u, nullptr);
+    hipLaunchKernelGGL((k_sum_reduce<false, false>), dim3((unsigned)L.tiles), dim3(SB), 0, s, nn, sorted->journey_id,
+                       sorted->lat_deg, sorted->lon_deg, sorted->speed_mps, feat->step_m, feat->speed_mps,
+                       feat->flags, L.tile_prefix, L.wcnt, rows, o, acc, accx, nullptr, 0u, nullptr);
+    return cvh::last_launch_status();
+}
+
+}  // namespace cv
 
 extern "C" {
 

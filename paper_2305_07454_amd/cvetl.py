@@ -195,7 +195,7 @@ def new_result(device="cuda"):
 
 def read_result(res) -> dict:
     a = np.frombuffer(res.cpu().numpy().tobytes(), dtype=RESULT_DTYPE)[0]
-    return {k: int(a[k]) for k in ("status", "count", "required", "n_out_of_grid", "n_late", "key_bits",
+    return {k: int(a[k]) for k in ("status", "flags", "count", "required", "n_out_of_grid", "n_late", "key_bits",
                                          "packed_pass")}
 
 

@@ -114,3 +114,81 @@ def test_late_records_flagged(cv):
     journeys, groups, rj, rg = st.flush(64, 4096)
     assert int(host(journeys["n_points"])[0]) == 4 and rj["n_late"] == 1
     assert int(host(groups["count"]).sum()) == 4
+
+
+def _delayed_arrival(n, rng, frac, reach):
+    """Arrival order in which a fraction of the records is held back by up to
+    `reach` positions (so that some arrive after later records of their
+    journey were pushed)."""
+    key = np.arange(n, dtype=np.float64)
+    pick = rng.random(n) < frac
+    key[pick] += rng.integers(1, reach, int(pick.sum()))
+    return np.argsort(key, kind="stable")
+
+
+def _late_flags(jid, ts, bounds):
+    """A record is late when it is older than the newest non-late record of
+    its journey in an earlier push (the resident last point)."""
+    last = {}
+    late = np.zeros(jid.shape[0], dtype=bool)
+    for a, b in bounds:
+        upd = {}
+        for i in range(a, b):
+            j, t = int(jid[i]), int(ts[i])
+            if j in last and t < last[j]:
+                late[i] = True
+            elif t > upd.get(j, t - 1):
+                upd[j] = t
+        last.update(upd)
+    return late
+
+
+@pytest.mark.parametrize("grid_name,heavy", [("c3", 0.0), ("c4", 0.05)])
+def test_late_records_in_bulk(cv, grid_name, heavy):
+    """Late records in quantity: kinematics and distinct-journey flags follow
+    the non-late records alone; counts, sums and extrema of cells and journeys
+    include every record."""
+    import torch
+    r = _pool(seed=44 if heavy == 0 else 45, heavy=heavy)
+    grid = gen.GRIDS[grid_name]
+    rng = np.random.default_rng(9)
+    order = _delayed_arrival(r.n, rng, 0.03, 20_000)
+    cols = tuple(np.ascontiguousarray(c[order]) for c in r.columns())
+    sizes = gen.chunk_sizes(rng, r.n, 500, 30_000)
+    bounds = _slices(r.n, sizes)
+    late = _late_flags(cols[0], cols[1], bounds)
+    print(f"[stream-late] n={r.n} chunks={len(sizes)} late={int(late.sum())} grid={grid_name}", flush=True)
+    assert late.sum() > 100
+    st = cv.Stream(grid, max_journeys=4096, max_groups=1 << 18, max_batch=max(sizes))
+    rec = cv.to_device(cols)
+    feats, n_late = [], 0
+    for a, b in bounds:
+        f, res = st.push({k: v[a:b] for k, v in rec.items()})
+        feats.append(f)
+        n_late += cv.read_result(res)["n_late"]
+    torch.cuda.synchronize()
+    got = {k: host(torch.cat([f[k] for f in feats])) for k in feats[0]}
+    journeys, groups, rj, rg = st.flush(4096, 1 << 18)
+    assert n_late == int(late.sum()) and rj["n_late"] == int(late.sum())
+    # kinematics: the non-late records on their own
+    keep = np.flatnonzero(~late)
+    sub = tuple(c[keep] for c in cols)
+    exp_nl = oracle.run_plain(sub, grid)
+    check_features({k: torch.from_numpy(v[keep][exp_nl["perm"]]) for k, v in got.items()}, exp_nl["features"])
+    lt = np.flatnonzero(late)
+    assert np.all(got["flags"][lt] == 0x80)
+    for k in ("step_m", "dt_s", "speed_mps", "accel_mps2", "bearing_deg", "dheading_deg"):
+        assert np.all(got[k][lt] == 0.0), k
+    # journeys: every record, late ones with zero kinematics
+    full = {k: np.zeros(r.n, dtype=v.dtype) for k, v in exp_nl["features"].items()}
+    for k, v in exp_nl["features"].items():
+        full[k][keep[exp_nl["perm"]]] = v
+    full["flags"][lt] = 0x80
+    perm = oracle.sort(cols[0], cols[1])
+    s_all = oracle.sorted_records(cols, perm)
+    check_summary(journeys, oracle.summary(*s_all, {k: v[perm] for k, v in full.items()}))
+    # cells: count / sum / extrema over every record, distinct journeys over the non-late ones
+    exp_g, n_out = oracle.grid(*s_all, grid)
+    nj = dict(zip(exp_nl["groups"]["key"].tolist(), exp_nl["groups"]["n_journeys"].tolist()))
+    exp_g["n_journeys"] = np.array([nj.get(k, 0) for k in exp_g["key"].tolist()], dtype=np.uint32)
+    check_groups(groups, rj["n_out_of_grid"], exp_g, n_out)

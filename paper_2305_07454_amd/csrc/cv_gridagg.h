@@ -37,6 +37,7 @@ constexpr uint8_t B_SEG = 1;   // first record of a (journey, time-bin) segment
 constexpr uint8_t B_RUN = 2;   // first record of a run (segment start or key change)
 constexpr uint8_t B_FIRST = 4; // run head whose key is new in its segment (counts its journey)
 constexpr uint8_t B_LATE = 8;  // late record (serving form)
+constexpr uint8_t B_PEND = 16; // run head left to the block-wide scan of its segment's earlier records
 
 // Partial aggregate of one run (or piece of a run).  The speed sum is a
 // 128-bit two's-complement integer in units of 2^-53, exact for every float32
@@ -200,6 +201,8 @@ k_grid_agg(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, const
     __shared__ i64 s_pj, s_ptb;  // the record before the first row
     __shared__ uint8_t s_plt;
     __shared__ int s_lo;
+    __shared__ u32 s_npend, s_pn, s_nfound;
+    __shared__ unsigned long long s_r0[2];
     __shared__ u64 s_out[GB / WAVE];
 
     const int t = threadIdx.x;
@@ -248,6 +251,7 @@ k_grid_agg(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, const
         s_ptb = base > 0 ? floor_div64(ts[base - 1] - g.t0, g.bin_ms) : 0;
         s_plt = (Pol::kStream && base > 0) ? (uint8_t)pol.late((u64)(base - 1)) : (uint8_t)0;
         s_lo = -1;
+        s_npend = 0;
     }
     u64 n_out = 0;
     const u32 sh0 = g.S > 1 ? shard_of(g.soff, g.S, (u64)(base > 0 ? base : 0)) : 0u;
@@ -363,26 +367,10 @@ k_grid_agg(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, const
                 }
             }
             if (first && f < 0 && !closed && exhausted) {
-                // the segment starts before the loaded halo: continue in global memory
-                long rr = (long)tile0 - HALO + lo_bound - 1;
-                r0 = 0;
-                while (rr >= 0) {
-                    if (Pol::kStream && pol.late((u64)rr)) {  // late records form segments of their own
-                        r0 = rr + 1;
-                        break;
-                    }
-                    i64 tb;
-                    const i64 kk = grid_key(g, (u64)rr, ts[rr], lat[rr], lon[rr], tb);
-                    if (kk == k) {
-                        first = false;
-                        break;
-                    }
-                    if (seg_start(g, jid, ts, (u64)rr, tb)) {
-                        r0 = rr;
-                        break;
-                    }
-                    --rr;
-                }
+                // the segment starts before the loaded halo: left to the block-wide scan below
+                s_bits[q] |= B_PEND;
+                atomicAdd(&s_npend, 1u);
+                continue;
             }
         }
         if (Pol::kStream && first && pol.carried((u64)r0, (u64)k)) first = false;
@@ -392,6 +380,104 @@ k_grid_agg(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, const
         }
     }
     __syncthreads();
+    // Pending heads all lie in the tile's first segment, which starts before
+    // the loaded halo.  The block reads that segment's earlier records
+    // backwards, GB at a time (coalesced), until the chunk that holds the
+    // segment's first record, and marks every pending key it meets.  The keys
+    // sit in an open-addressing set in the LDS of the group table (not in use
+    // yet), at most LHS / 2 of them per round.
+    if (exhausted && s_npend > 0) {
+        constexpr u32 PR = LHS / 2;
+        u32* s_pfound = reinterpret_cast<u32*>(s_h);
+        u32* s_pq = s_pfound + LHS;
+        u32 left = s_npend;
+        while (left > 0) {
+            for (int i = t; i < LHS; i += GB) s_hkey[i] = GEMPTY;
+            if (t == 0) {
+                s_pn = 0;
+                s_nfound = 0;
+                s_r0[0] = 0;
+                s_r0[1] = 0;
+            }
+            __syncthreads();
+            for (int q = t; q < qend; q += GB) {
+                if (!(s_bits[q] & B_PEND)) continue;
+                if (atomicAdd(&s_pn, 1u) >= PR) continue;  // a later round
+                s_bits[q] &= (uint8_t)~B_PEND;
+                const u64 k = (u64)s_key[q];
+                u32 h = (u32)mix64(k) & (LHS - 1);
+                while (atomicCAS((unsigned long long*)&s_hkey[h], (unsigned long long)GEMPTY,
+                                 (unsigned long long)k) != GEMPTY)
+                    h = (h + 1) & (LHS - 1);  // pending keys are distinct and at most half the slots
+                s_pq[h] = (u32)q;
+                s_pfound[h] = 0;
+            }
+            __syncthreads();
+            const u32 taken = s_pn < PR ? s_pn : PR;
+            long top = base - 1;  // records [top - GB + 1, top] this chunk
+            long r0 = -1;         // the segment's first record, once met
+            for (int it = 0;; ++it) {
+                const long r = top - t;
+                long c = -1;  // the segment starts at c (when r belongs to a boundary)
+                i64 k = -1;
+                if (r >= 0) {
+                    i64 tb;
+                    k = grid_key(g, (u64)r, ts[r], lat[r], lon[r], tb);
+                    if (Pol::kStream && pol.late((u64)r)) {
+                        c = r + 1;  // late records are outside every segment of non-late ones
+                        k = -1;
+                    } else if (seg_start(g, jid, ts, (u64)r, tb) || (Pol::kStream && pol.late((u64)(r - 1)))) {
+                        c = r;
+                    }
+                }
+                if (c >= 0) atomicMax(&s_r0[it & 1], (unsigned long long)(c + 1));
+                __syncthreads();
+                const long rc = (long)s_r0[it & 1] - 1;  // -1: the segment goes on below this chunk
+                if (t == 0) s_r0[(it + 1) & 1] = 0;
+                if (k >= 0 && r >= rc) {
+                    u32 h = (u32)mix64((u64)k) & (LHS - 1);
+                    for (int pr = 0; pr < LHS; ++pr) {
+                        const u64 cur = s_hkey[h];
+                        if (cur == (u64)k) {
+                            if (atomicExch(&s_pfound[h], 1u) == 0) atomicAdd(&s_nfound, 1u);
+                            break;
+                        }
+                        if (cur == GEMPTY) break;
+                        h = (h + 1) & (LHS - 1);
+                    }
+                }
+                __syncthreads();
+                if (rc >= 0) {
+                    r0 = rc;
+                    break;
+                }
+                if (s_nfound == taken) break;  // every pending key met: none counts its journey
+                top -= GB;
+            }
+            for (int h = t; h < LHS; h += GB) {
+                const u64 k = s_hkey[h];
+                if (k == GEMPTY || s_pfound[h]) continue;
+                const int q = (int)s_pq[h];
+                if (Pol::kStream && pol.carried((u64)r0, k)) continue;
+                s_bits[q] |= B_FIRST;
+                if (Pol::kStream) pol.first((u64)(base + q), k);
+            }
+            __syncthreads();
+            left -= taken;
+        }
+        // the LDS group table back to empty
+        for (int i = t; i < LHS; i += GB) {
+            s_hkey[i] = GEMPTY;
+            LSlot z;
+            z.cs[0] = z.cs[1] = z.cs[2] = z.cs[3] = 0;
+            z.count = 0;
+            z.nj = 0;
+            z.mn = ~0u;
+            z.mx = 0;
+            s_h[i] = z;
+        }
+        __syncthreads();
+    }
     // Aggregation: every wave walks its GT/4 records of the tile in windows of
     // 64.  Lanes fold records into a private partial of the open run while the
     // window holds no run start.  A window with starts closes the open run

@@ -939,48 +939,68 @@ cv_status cv_stream_push(cv_stream* st, const cv_records* batch, const cv_featur
     cvh::TimedScope ts_("stream_push", s);
     hipLaunchKernelGGL(k_st_begin, dim3(1), dim3(64), 0, s, st->meta);
     cv_records_out so{st->s_jid, st->s_ts, st->s_lat, st->s_lon, st->s_spd};
-    // a batch holds at most n distinct journeys: the dictionary of its sort is
-    // sized (and cleared) for n, within the workspace carved for max_batch
-    cv_status e = cv::sort_records_into(batch, n, st->perm, &so, st->sres, st->sort_ws, st->sort_ws_bytes, s);
-    if (e != CV_OK) return e;
+    cv_status e = CV_OK;
+    {
+        cvh::TimedScope t1("stream_sort", s);
+        // a batch holds at most n distinct journeys: the dictionary of its sort is
+        // sized (and cleared) for n, within the workspace carved for max_batch
+        e = cv::sort_records_into(batch, n, st->perm, &so, st->sres, st->sort_ws, st->sort_ws_bytes, s);
+        if (e != CV_OK) return e;
+    }
     const u32 tiles = (u32)((n + ST_TILE - 1) / ST_TILE);
-    hipLaunchKernelGGL(k_st_count, dim3(tiles), dim3(256), 0, s, st->s_jid, nn, st->tile_cnt);
-    hipLaunchKernelGGL(k_st_scan, dim3(1), dim3(256), 0, s, st->tile_cnt, tiles, st->meta);
-    hipLaunchKernelGGL(k_st_heads, dim3(tiles), dim3(256), 0, s, st->s_jid, nn, st->tile_cnt, st->meta, st->boff);
-    hipLaunchKernelGGL(k_st_journeys, dim3(cvh::grid_for(n, 256, 2048)), dim3(256), 0, s, st->s_jid, st->boff,
-                       st->meta, st->jkeys, st->jslots - 1, st->rows, st->bslot);
-    hipLaunchKernelGGL(k_st_features, dim3((unsigned)((n + FB - 1) / FB)), dim3(FB), 0, s, nn, st->s_jid, st->s_ts,
-                       st->s_lat, st->s_lon, st->perm, st->boff, st->meta, st->bslot, st->rows, *feat, st->fs_step,
-                       st->fs_v, st->fs_b, st->fs_flags);
-    // summaries: the plain kernels' exact per-journey partials of the batch
-    cv_records sb{};
-    sb.journey_id = st->s_jid;
-    sb.ts_ms = st->s_ts;
-    sb.lat_deg = st->s_lat;
-    sb.lon_deg = st->s_lon;
-    sb.speed_mps = st->s_spd;
-    sb.n = n;
-    cv_features fb{};
-    fb.step_m = st->fs_step;
-    fb.speed_mps = st->fs_v;
-    fb.flags = st->fs_flags;
-    e = cv::sum_partials(&sb, &fb, (u32)st->arows, st->acc, st->accx, st->sum_ws, s);
-    if (e != CV_OK) return e;
-    // groups: the grid tile kernel into the resident table
+    {
+        cvh::TimedScope t2("stream_journeys", s);
+        hipLaunchKernelGGL(k_st_count, dim3(tiles), dim3(256), 0, s, st->s_jid, nn, st->tile_cnt);
+        hipLaunchKernelGGL(k_st_scan, dim3(1), dim3(256), 0, s, st->tile_cnt, tiles, st->meta);
+        hipLaunchKernelGGL(k_st_heads, dim3(tiles), dim3(256), 0, s, st->s_jid, nn, st->tile_cnt, st->meta,
+                           st->boff);
+        hipLaunchKernelGGL(k_st_journeys, dim3(cvh::grid_for(n, 256, 2048)), dim3(256), 0, s, st->s_jid, st->boff,
+                           st->meta, st->jkeys, st->jslots - 1, st->rows, st->bslot);
+    }
+    {
+        cvh::TimedScope t3("stream_features", s);
+        hipLaunchKernelGGL(k_st_features, dim3((unsigned)((n + FB - 1) / FB)), dim3(FB), 0, s, nn, st->s_jid,
+                           st->s_ts, st->s_lat, st->s_lon, st->perm, st->boff, st->meta, st->bslot, st->rows, *feat,
+                           st->fs_step, st->fs_v, st->fs_b, st->fs_flags);
+    }
+    {
+        // summaries: the plain kernels' exact per-journey partials of the batch
+        cvh::TimedScope t4("stream_summary", s);
+        cv_records sb{};
+        sb.journey_id = st->s_jid;
+        sb.ts_ms = st->s_ts;
+        sb.lat_deg = st->s_lat;
+        sb.lon_deg = st->s_lon;
+        sb.speed_mps = st->s_spd;
+        sb.n = n;
+        cv_features fb{};
+        fb.step_m = st->fs_step;
+        fb.speed_mps = st->fs_v;
+        fb.flags = st->fs_flags;
+        e = cv::sum_partials(&sb, &fb, (u32)st->arows, st->acc, st->accx, st->sum_ws, s);
+        if (e != CV_OK) return e;
+    }
     const i64 cells = st->g.n_lat * st->g.n_lon;
-    GridStream pol{st->s_jid, st->fs_flags, st->boff, st->meta, st->bslot, st->rows, st->ovf_pool,
-                   cells,     st->ap,       (u32)st->max_batch, &st->meta->ap_n};
-    hipLaunchKernelGGL((k_grid_agg<256, GridStream>), dim3((unsigned)((n + GT - 1) / GT)), dim3(GB), 0, s, nn,
-                       st->s_jid, st->s_ts, st->s_lat, st->s_lon, st->s_spd, st->g, st->tab, st->gslots - 1,
-                       &st->meta->gm, pol);
-    // resident rows: the partials, the last point, the open segment's cells
-    hipLaunchKernelGGL(k_st_merge, dim3(cvh::grid_for(n, 256, 2048)), dim3(256), 0, s, st->s_ts, st->s_lat,
-                       st->s_lon, st->boff, st->meta, st->bslot, st->rows, st->acc, st->accx, (u32)st->arows,
-                       st->fs_v, st->fs_b, st->fs_flags, st->g, st->ovf_pool);
-    hipLaunchKernelGGL(k_st_append, dim3(cvh::grid_for(n, 256, 2048)), dim3(256), 0, s, st->ap, st->meta,
-                       (u32)st->max_batch, st->rows, ovf_pages(st->jslots), cells);
-    hipLaunchKernelGGL(k_st_append_ovf, dim3(cvh::grid_for(n, 256, 2048)), dim3(256), 0, s, st->ap, st->meta,
-                       (u32)st->max_batch, st->rows, st->ovf_pool);
+    {
+        // groups: the grid tile kernel into the resident table
+        cvh::TimedScope t5("stream_grid", s);
+        GridStream pol{st->s_jid, st->fs_flags, st->boff, st->meta, st->bslot, st->rows, st->ovf_pool,
+                       cells,     st->ap,       (u32)st->max_batch, &st->meta->ap_n};
+        hipLaunchKernelGGL((k_grid_agg<256, GridStream>), dim3((unsigned)((n + GT - 1) / GT)), dim3(GB), 0, s, nn,
+                           st->s_jid, st->s_ts, st->s_lat, st->s_lon, st->s_spd, st->g, st->tab, st->gslots - 1,
+                           &st->meta->gm, pol);
+    }
+    {
+        // resident rows: the partials, the last point, the open segment's cells
+        cvh::TimedScope t6("stream_merge", s);
+        hipLaunchKernelGGL(k_st_merge, dim3(cvh::grid_for(n, 256, 2048)), dim3(256), 0, s, st->s_ts, st->s_lat,
+                           st->s_lon, st->boff, st->meta, st->bslot, st->rows, st->acc, st->accx, (u32)st->arows,
+                           st->fs_v, st->fs_b, st->fs_flags, st->g, st->ovf_pool);
+        hipLaunchKernelGGL(k_st_append, dim3(cvh::grid_for(n, 256, 2048)), dim3(256), 0, s, st->ap, st->meta,
+                           (u32)st->max_batch, st->rows, ovf_pages(st->jslots), cells);
+        hipLaunchKernelGGL(k_st_append_ovf, dim3(cvh::grid_for(n, 256, 2048)), dim3(256), 0, s, st->ap, st->meta,
+                           (u32)st->max_batch, st->rows, st->ovf_pool);
+    }
     hipLaunchKernelGGL(k_st_finish, dim3(1), dim3(64), 0, s, st->meta, st->sres, nn, res);
     return cvh::last_launch_status();
 }

@@ -129,6 +129,38 @@ def test_long_segments_cell_reentry(cv):
     assert int(exp["groups"]["n_journeys"].max()) == 1 and len(exp["groups"]["key"]) >= 5
 
 
+def test_long_segments_many_cells(cv):
+    # 20 Hz journeys inside one hour-long time bin over 0.0001-degree cells: a
+    # looping drift meets hundreds of cells in every tile, some new and some
+    # entered thousands of records earlier in the same segment, so the
+    # block-wide backward scan of a segment's earlier records runs several
+    # rounds of pending keys; under every LDS table size
+    rng = np.random.default_rng(12)
+    L = 40_000
+    k = np.arange(L)
+    cols_j, cols_t, cols_la, cols_lo = [], [], [], []
+    for j, (pa, pb) in enumerate(((150.0, 110.0), (90.0, 230.0))):
+        cols_j.append(np.full(L, 11 + j, np.int64))
+        cols_t.append(gen.T0_MS + k * 50)
+        cols_la.append(37.0 + 2e-6 * k + 0.002 * np.sin(k / pa) + 1e-5 * rng.standard_normal(L))
+        cols_lo.append(-92.0 + 0.002 * np.cos(k / pb) + 1e-5 * rng.standard_normal(L))
+    cols = (np.concatenate(cols_j), np.concatenate(cols_t), np.concatenate(cols_la), np.concatenate(cols_lo),
+            rng.gamma(2.0, 5.0, 2 * L).astype(np.float32))
+    spec = gen.GridSpec(36.9, -92.1, 0.0001, 0.0001, 4000, 4000, gen.T0_MS, 3_600_000, 24)
+    exp = oracle.run_plain(cols, spec)
+    assert int(exp["groups"]["n_journeys"].max()) == 2 and len(exp["groups"]["key"]) > 10_000
+    rec = cv.to_device(cols)
+    prev = cv.cv_tuning_get("grid_lds_slots")
+    try:
+        for slots in (256, 512, 1024):
+            cv.cv_tuning_set("grid_lds_slots", slots)
+            print(f"[parity] long segments, {slots} LDS slots, n={2 * L}", flush=True)
+            got = cv.run_plain(rec, spec)
+            check_groups(got["groups"], got["n_out"], exp["groups"], exp["n_out"])
+    finally:
+        cv.cv_tuning_set("grid_lds_slots", prev)
+
+
 def test_table1_rows(cv):
     import json, os
     from test_oracle_pins import _table1, GOLDEN

@@ -245,6 +245,7 @@ __global__ void __launch_bounds__(FB) k_st_features(u32 n, const i64* __restrict
     __shared__ u32 s_fin[FB + 2];
     __shared__ double s_step[FB + 1], s_dt[FB + 1], s_v[FB + 1], s_b[FB + 1], s_pv[FB + 1], s_pb[FB + 1];
     __shared__ u32 s_f[FB + 1], s_pf[FB + 1];
+    __shared__ u32 s_jb[FB + 2], s_scan[FB / WAVE], s_jb0;
     const u32 Jb = m->Jb;
     const long s0 = (long)blockIdx.x * FB;
     for (int q = threadIdx.x; q < FB + 2; q += FB) {
@@ -262,6 +263,23 @@ __global__ void __launch_bounds__(FB) k_st_features(u32 n, const i64* __restrict
             s_cphi[q] = fin ? cos(phi) : 0.0;
         }
     }
+    // Batch journey of every record: one search for the block's first record
+    // (LDS position qb), then a block scan of journey starts after it.
+    const int qb = s0 == 0 ? 2 : 1;
+    if (threadIdx.x == 0) s_jb0 = batch_journey_of(boff, Jb, (u32)(s0 - 2 + qb));
+    __syncthreads();
+    {
+        const int q = threadIdx.x + 1;
+        const long r = s0 - 2 + q;
+        const u32 h = (q > qb && r < (long)n && s_jid[q] != s_jid[q - 1]) ? 1u : 0u;
+        u32 tot;
+        const u32 ex = block_exclusive_sum<FB>(h, s_scan, tot);
+        s_jb[q] = s_jb0 + ex + h;
+        if (threadIdx.x == 0) {
+            const long rl = s0 + FB - 1;  // LDS position FB + 1
+            s_jb[FB + 1] = s_jb0 + tot + ((rl < (long)n && s_jid[FB + 1] != s_jid[FB]) ? 1u : 0u);
+        }
+    }
     __syncthreads();
     for (int j = threadIdx.x; j < FB + 1; j += FB) {
         const long k = s0 - 1 + j;
@@ -269,7 +287,7 @@ __global__ void __launch_bounds__(FB) k_st_features(u32 n, const i64* __restrict
         u32 f = 0, pf = 0;
         if (k >= 0 && k < (long)n) {
             const int qk = j + 1, qp = j;
-            const u32 jb = batch_journey_of(boff, Jb, (u32)k);
+            const u32 jb = s_jb[qk];
             const u32 slot = bslot[jb];
             const bool have_row = slot != ~0u;
             const JRow* row = have_row ? &rows[slot] : nullptr;

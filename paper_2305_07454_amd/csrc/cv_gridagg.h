@@ -187,9 +187,9 @@ k_grid_agg(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, const
 {
     constexpr int NQ = HALO + GT;
     __shared__ i64 s_key[NQ];       // keys per record; later the keys of the run-head list
-    __shared__ uint8_t s_bits[NQ];
+    __shared__ __attribute__((aligned(16))) uint8_t s_bits[NQ];
     __shared__ uint16_t s_lpos[NQ];  // run-head list: q | segment start << 15
-    __shared__ float s_spd[GT];
+    __shared__ __attribute__((aligned(16))) float s_spd[GT];
     __shared__ u64 s_hkey[LHS];
     __shared__ LSlot s_h[LHS];
     __shared__ u32 s_tmp[GB / WAVE];
@@ -478,72 +478,84 @@ k_grid_agg(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, const
         }
         __syncthreads();
     }
-    // Aggregation: every wave walks its GT/4 records of the tile in windows of
-    // 64.  Lanes fold records into a private partial of the open run while the
-    // window holds no run start.  A window with starts closes the open run
-    // (one wave reduction over every lane's partial and the records before the
-    // first start), reduces the runs that begin and end inside it (segmented
-    // scan, only when there are two or more starts), and leaves the run of its
-    // last start open as the private partials of that start's lanes.  Each
-    // finished run is one LDS hash insert.  A wave's first record starts a
-    // piece of its own.
+    // Aggregation: every wave takes GT/4 records of the tile, every lane PER
+    // consecutive ones of them.  A lane folds its records serially into
+    // pieces cut at run starts: a run that starts and ends inside the lane is
+    // one LDS hash insert; the piece before the lane's first start continues
+    // a run from the lanes below, and the piece after its last start goes on
+    // into the lanes above.  One segmented scan over the lanes joins those
+    // pieces, and the lane where a run ends inserts it.  A wave's first record
+    // starts a piece of its own.  All aggregates add (or take min / max), so
+    // where a run is cut into pieces changes nothing.  Flags are read 8 to a
+    // word and speeds 4 to a word; keys only at run starts (a run has one key).
     {
         constexpr int WREC = GT / (GB / WAVE);
+        constexpr int PER = WREC / WAVE;
+        static_assert(PER == 8, "one 64-bit word of flags per lane");
         const int w = t / WAVE, l = lane_id();
         const int qa = HALO + w * WREC;
-        RunPart p;
-        run_reset(p);
-        i64 open_key = -1;
-        for (int i = 0; i < WREC / WAVE; ++i) {
-            const int q = qa + i * WAVE + l;
-            const bool valid = q < qend;
-            const i64 k = valid ? s_key[q] : -1;
-            const uint8_t b = valid ? s_bits[q] : 0;
-            const bool head = valid && ((b & B_RUN) || (i == 0 && l == 0));
-            RunPart c;
-            run_reset(c);
-            if (valid && k >= 0) {
-                const float sp = s_spd[q - HALO];
+        const int q0 = qa + PER * l;
+        const int nv = qend - q0 < 0 ? 0 : (qend - q0 > PER ? PER : qend - q0);
+        const u64 bits8 = *reinterpret_cast<const u64*>(&s_bits[q0]);
+        const float4 spa = *reinterpret_cast<const float4*>(&s_spd[q0 - HALO]);
+        const float4 spb = *reinterpret_cast<const float4*>(&s_spd[q0 - HALO + 4]);
+        const float sp8[PER] = {spa.x, spa.y, spa.z, spa.w, spb.x, spb.y, spb.z, spb.w};
+        RunPart cur, pre;
+        run_reset(cur);
+        run_reset(pre);
+        bool hh = false;  // the lane holds a run start
+        i64 ck = nv > 0 ? s_key[q0] : -1;
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            if (i >= nv) break;
+            const uint8_t b = (uint8_t)(bits8 >> (8 * i));
+            if ((b & B_RUN) || (i == 0 && l == 0)) {
+                if (i > 0) {
+                    if (!hh) pre = cur;
+                    else if (ck >= 0 && cur.cn) run_insert<LHS>(s_hkey, s_h, tab, gmask, meta, (u64)ck, cur);
+                    run_reset(cur);
+                    ck = s_key[q0 + i];
+                }
+                hh = true;
+            }
+            if (ck >= 0) {
+                const float sp = sp8[i];
                 i64 x;
                 if (spd_fix53(sp, x)) {
-                    c.lo = (u64)x;
-                    c.hi = (u64)(x >> 63);
+                    add128(cur.lo, cur.hi, (u64)x, (u64)(x >> 63));
                 } else {
                     // a speed outside the 128-bit range: its exact value on its own
-                    slot_insert<LHS>(s_hkey, s_h, tab, gmask, meta, (u64)k, fx_from_double<FX_SPD>((double)sp), 0u,
+                    slot_insert<LHS>(s_hkey, s_h, tab, gmask, meta, (u64)ck, fx_from_double<FX_SPD>((double)sp), 0u,
                                      0u, ~0u, 0u);
                 }
-                c.cn = 1u | ((b & B_FIRST) ? (1u << 16) : 0u);
-                c.mn = c.mx = ord_f32(sp);
+                cur.cn += 1u | ((b & B_FIRST) ? (1u << 16) : 0u);
+                const u32 o = ord_f32(sp);
+                cur.mn = o < cur.mn ? o : cur.mn;
+                cur.mx = o > cur.mx ? o : cur.mx;
             }
-            const u64 H = __ballot(head);
-            if (H == 0) {
-                run_combine(p, c);
-                continue;
-            }
-            const int f0 = __ffsll((long long)H) - 1;
-            const int lh = 63 - __clzll((long long)H);  // last start: its run stays open
-            // close the open run: every lane's partial and the records before the first start
-            RunPart x = p;
-            if (l < f0) run_combine(x, c);
-            run_wave_reduce(x);
-            if (l == 0 && open_key >= 0 && x.cn) run_insert<LHS>(s_hkey, s_h, tab, gmask, meta, (u64)open_key, x);
-            // runs between two starts of this window
-            if (f0 != lh) {
-                RunPart y;
-                if (l >= f0 && l < lh) y = c;
-                else run_reset(y);
-                run_seg_scan(y, head);
-                const bool next_head = (l < WAVE - 1) && ((H >> (l + 1)) & 1ull);
-                if (l >= f0 && l < lh && next_head && k >= 0 && y.cn)
-                    run_insert<LHS>(s_hkey, s_h, tab, gmask, meta, (u64)k, y);
-            }
-            open_key = __shfl(k, lh, WAVE);
-            if (l >= lh) p = c;
-            else run_reset(p);
         }
-        run_wave_reduce(p);
-        if (l == 0 && open_key >= 0 && p.cn) run_insert<LHS>(s_hkey, s_h, tab, gmask, meta, (u64)open_key, p);
+        // the piece that goes on into the lanes above (the whole lane when it
+        // holds no start), joined across lanes
+        RunPart out = cur;
+        run_seg_scan(out, hh);
+        // the run open below this lane: the scan's value of the lane below
+        RunPart in;
+        in.lo = (u64)__shfl_up((unsigned long long)out.lo, 1, WAVE);
+        in.hi = (u64)__shfl_up((unsigned long long)out.hi, 1, WAVE);
+        in.cn = (u32)__shfl_up(out.cn, 1, WAVE);
+        in.mn = (u32)__shfl_up(out.mn, 1, WAVE);
+        in.mx = (u32)__shfl_up(out.mx, 1, WAVE);
+        if (l == 0) run_reset(in);
+        if (hh && l > 0) {
+            run_combine(in, pre);
+            const i64 kb = s_key[q0 - 1];  // the run ends in this lane: its key is the record below's
+            if (kb >= 0 && in.cn) run_insert<LHS>(s_hkey, s_h, tab, gmask, meta, (u64)kb, in);
+        }
+        const int qlast = (qa + WREC < qend ? qa + WREC : qend) - 1;
+        if (l == WAVE - 1 && qlast >= qa) {
+            const i64 ke = s_key[qlast];  // the run open at the wave's end
+            if (ke >= 0 && out.cn) run_insert<LHS>(s_hkey, s_h, tab, gmask, meta, (u64)ke, out);
+        }
     }
     // out-of-grid count (one global atomic per tile, only when non-zero)
 #pragma unroll

@@ -324,8 +324,11 @@ __global__ void __launch_bounds__(FB) k_st_features(u32 n, const i64* __restrict
                     dts = (double)dt_ms / 1000.0;
                     const double dphi = (s_lat[qk] - plat) * DEG2RAD;
                     const double dlam = (s_lon[qk] - plon) * DEG2RAD;
-                    const double sp = sin(0.5 * dphi);
-                    const double sl = sin(0.5 * dlam);
+                    // half-angle sines and cosines; the full-angle sines of the
+                    // bearing follow from them (sin 2u = 2 sin u cos u)
+                    double sp, cp, sl, cl;
+                    sincos(0.5 * dphi, &sp, &cp);
+                    sincos(0.5 * dlam, &sl, &cl);
                     const double phi1 = plat * DEG2RAD;
                     const double cphi1 = pred == 1 ? s_cphi[qp] : cos(phi1);
                     const double sphi1 = pred == 1 ? s_sphi[qp] : sin(phi1);
@@ -337,8 +340,8 @@ __global__ void __launch_bounds__(FB) k_st_features(u32 n, const i64* __restrict
                         f |= CV_FLAG_SPEED_OK;
                     }
                     if (step > 0.0) {
-                        const double y = sin(dlam) * cphi2;
-                        const double x = sin(dphi) + (((2.0 * sphi1) * cphi2) * (sl * sl));
+                        const double y = ((2.0 * sl) * cl) * cphi2;
+                        const double x = ((2.0 * sp) * cp) + (((2.0 * sphi1) * cphi2) * (sl * sl));
                         b = atan2(y, x) * RAD2DEG;
                         if (b < 0.0) b += 360.0;
                         if (b >= 360.0) b -= 360.0;

@@ -161,6 +161,44 @@ def test_long_segments_many_cells(cv):
         cv.cv_tuning_set("grid_lds_slots", prev)
 
 
+def test_step_angles_across_the_series_bound(cv):
+    # consecutive fixes from millimetres to a quarter of the globe apart, dense
+    # around the size where the half central angle (and the haversine's sqrt)
+    # leaves the small-argument series for the library functions (2^-7 rad:
+    # steps of about 100 km), in every direction
+    rng = np.random.default_rng(21)
+    n = 6000
+    ang = np.concatenate([10.0 ** rng.uniform(-10, -0.3, n // 2),
+                          (2.0 ** -6) * np.exp(rng.uniform(-0.05, 0.05, n - n // 2))])
+    rng.shuffle(ang)
+    az = rng.uniform(0.0, 2.0 * np.pi, n)
+    lat = np.empty(n)
+    lon = np.empty(n)
+    lat[0], lon[0] = 38.5, -92.5
+    for i in range(1, n):
+        d = np.degrees(ang[i])
+        la = lat[i - 1] + d * np.cos(az[i])
+        if abs(la) > 80.0:
+            la = lat[i - 1] - d * np.cos(az[i])
+        lat[i] = la
+        lon[i] = (lon[i - 1] + d * np.sin(az[i]) + 180.0) % 360.0 - 180.0
+    jid = np.repeat(np.arange(1, 7, dtype=np.int64), n // 6)
+    ts = gen.T0_MS + 1000 * np.tile(np.arange(n // 6, dtype=np.int64), 6)
+    spd = rng.gamma(2.0, 5.0, n).astype(np.float32)
+    got, exp = _run_both(cv, (jid, ts, lat, lon, spd), gen.GRIDS["c1"])
+    _check_all(got, exp)
+    # the serving form: the same records in two pushes
+    import torch
+    st = cv.Stream(gen.GRIDS["c1"], 64, 1 << 16, n)
+    rec = cv.to_device((jid, ts, lat, lon, spd))
+    h = n // 2 + 17
+    f1, _ = st.push({k: v[:h] for k, v in rec.items()})
+    f2, _ = st.push({k: v[h:] for k, v in rec.items()})
+    torch.cuda.synchronize()
+    fs = {k: torch.cat([f1[k], f2[k]])[torch.from_numpy(exp["perm"].astype(np.int64)).cuda()] for k in f1}
+    check_features(fs, exp["features"])
+
+
 def test_table1_rows(cv):
     import json, os
     from test_oracle_pins import _table1, GOLDEN

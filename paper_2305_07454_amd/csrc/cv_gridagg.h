@@ -192,10 +192,10 @@ k_grid_agg(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, const
     __shared__ __attribute__((aligned(16))) float s_spd[GT];
     __shared__ u64 s_hkey[LHS];
     __shared__ LSlot s_h[LHS];
-    __shared__ u32 s_tmp[GB / WAVE];
-    __shared__ u32 s_nlist;
     constexpr int NWG = GB / WAVE;
     __shared__ i64 s_lj[HALO / GB + GI][NWG], s_ltb[HALO / GB + GI][NWG];  // wave row ends
+    __shared__ i64 s_lk[HALO / GB + GI][NWG];                               // wave row ends: key
+    __shared__ u32 s_cnt[(HALO / GB + GI) * NWG];                          // run heads per wave row
     __shared__ i64 s_ltbs[HALO / GB + GI][NWG];                             // wave row starts
     __shared__ uint8_t s_llt[HALO / GB + GI][NWG];                          // wave row ends: late
     __shared__ i64 s_pj, s_ptb;  // the record before the first row
@@ -272,22 +272,30 @@ k_grid_agg(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, const
         const i64 jp = __shfl_up(vj[rr], 1, WAVE);
         const i64 tbp = __shfl_up(tb, 1, WAVE);
         const u32 ltp = Pol::kStream ? (u32)__shfl_up((u32)vlt[rr], 1, WAVE) : 0u;
+        const i64 kp = __shfl_up(k, 1, WAVE);
         if (lane == WAVE - 1) {
             s_lj[rr][w] = vj[rr];
             s_ltb[rr][w] = tb;
             s_llt[rr][w] = vlt[rr];
+            s_lk[rr][w] = k;
         }
         // lane 0's bit is completed below, once lane 63 of the row before is in LDS;
         // a change of the late status starts a segment too
         const bool seg = r == 0 || (lane > 0 && (vj[rr] != jp || tb != tbp || (u32)vlt[rr] != ltp)) ||
                          (g.S > 1 && g.soff[sh] == (u64)r);
-        seg_b[rr] = ((!in || seg) ? B_SEG : 0) | (vlt[rr] ? B_LATE : 0);
+        seg_b[rr] = ((!in || seg) ? B_SEG : 0) | (vlt[rr] ? B_LATE : 0) | ((lane > 0 && k != kp) ? B_RUN : 0);
         if (lane == 0) s_ltbs[rr][w] = tb;
         s_key[q] = k;
         if (rr >= HR) s_spd[q - HALO] = in ? vsp[rr - HR] : 0.f;
     }
     __syncthreads();
+    // Segment and run starts of lane 0 (its predecessor is lane 63 of the wave
+    // row before, through LDS), then the run-head list: the heads of the
+    // loaded positions in position order, placed by per-row ballots and one
+    // prefix over the (row, wave) counts.  Position 0 always opens the list.
+    const int qend = HALO + (int)tvalid;
     int lo_cand = -1;
+    u64 hm[NR];
 #pragma unroll
     for (int rr = 0; rr < NR; ++rr) {
         const int q = rr * GB + t;
@@ -302,44 +310,36 @@ k_grid_agg(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, const
             const i64 ptb = first_row ? s_ptb : s_ltb[pr][pw];
             const uint8_t plt = first_row ? s_plt : s_llt[pr][pw];
             if (vj[rr] != pj || s_ltbs[rr][w] != ptb || (Pol::kStream && vlt[rr] != plt)) b |= B_SEG;
+            else if (!first_row && s_key[q] != s_lk[pr][pw]) b |= B_RUN;
         }
+        if ((b & B_SEG) || q == 0) b |= B_RUN;
         s_bits[q] = b;
         if ((b & B_SEG) && q <= HALO) lo_cand = q;
+        hm[rr] = __ballot((b & B_RUN) && r < (long)n);
+        if (lane == 0) s_cnt[rr * NWG + w] = (u32)__popcll(hm[rr]);
     }
     // the tile's first segment starts at the last segment start at or before
     // the tile's first record; none in the halo: it starts further back
     if (lo_cand >= 0) atomicMax(&s_lo, lo_cand);
     __syncthreads();
     const bool exhausted = s_lo < 0;
-    const int lo_bound = exhausted ? 0 : s_lo;
-    // Run heads over [lo_bound, HALO + tvalid), compacted in order into a list
-    // of positions: every thread marks and counts the heads of its own
-    // contiguous stretch, one block scan places the stretches.
-    const int qend = HALO + (int)tvalid;
+    int L;
     {
-        const int span = qend - lo_bound;
-        const int per = (span + GB - 1) / GB;
-        const int q0 = lo_bound + t * per;
-        const int q1 = q0 + per < qend ? q0 + per : qend;
-        u32 cnt = 0;
-        for (int q = q0; q < q1; ++q) {
-            uint8_t b = s_bits[q];
-            if ((b & B_SEG) || q == lo_bound || s_key[q] != s_key[q - 1]) {
-                b |= B_RUN;
-                ++cnt;
-            }
-            s_bits[q] = b;
+        static_assert(NR * NWG <= WAVE, "one count per lane");
+        const u32 c = lane < NR * NWG ? s_cnt[lane] : 0u;
+        const u32 inc = wave_inclusive_sum(c);
+        L = (int)__shfl(inc, NR * NWG - 1, WAVE);
+        const u64 below = (1ull << lane) - 1ull;
+#pragma unroll
+        for (int rr = 0; rr < NR; ++rr) {
+            const int q = rr * GB + t;
+            const u32 off = __shfl(inc - c, rr * NWG + w, WAVE);
+            if ((hm[rr] >> lane) & 1ull)
+                s_lpos[off + (u32)__popcll(hm[rr] & below)] = (uint16_t)(q | ((s_bits[q] & B_SEG) ? 0x8000 : 0));
         }
-        u32 tot;
-        u32 at = block_exclusive_sum<GB>(cnt, s_tmp, tot);
-        for (int q = q0; q < q1; ++q) {
-            const uint8_t b = s_bits[q];
-            if (b & B_RUN) s_lpos[at++] = (uint16_t)(q | ((b & B_SEG) ? 0x8000 : 0));
-        }
-        if (t == 0) s_nlist = tot;
-        __syncthreads();
     }
-    const int L = (int)s_nlist;
+    __syncthreads();
+
     // distinct-journey flag of every run head inside the tile: no earlier run
     // head of its segment has the same key (and, in the serving form, the key
     // is not among the cells the journey's open segment carried over)
@@ -352,19 +352,35 @@ k_grid_agg(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, const
         bool first = true;
         long r0 = base + q;  // the segment's first record
         if (!(pe & 0x8000u)) {
+            // back over the earlier heads, four per round (their loads issued
+            // together), until the same key or the segment's start
             int f = e - 1;
             bool closed = false;
-            for (; f >= 0; --f) {
-                const u32 pf = s_lpos[f];
-                if (s_key[pf & 0x7FFFu] == k) {
-                    first = false;
-                    break;
+            while (f >= 0) {
+                u32 pf[4];
+                i64 kf[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) pf[u] = s_lpos[f - u >= 0 ? f - u : 0];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) kf[u] = s_key[pf[u] & 0x7FFFu];
+                bool stop = false;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (stop) continue;
+                    if (f - u < 0) {
+                        stop = true;
+                        f = -1;
+                    } else if (kf[u] == k) {
+                        first = false;
+                        stop = true;
+                    } else if (pf[u] & 0x8000u) {
+                        closed = true;
+                        r0 = base + (long)(pf[u] & 0x7FFFu);
+                        stop = true;
+                    }
                 }
-                if (pf & 0x8000u) {
-                    closed = true;
-                    r0 = base + (long)(pf & 0x7FFFu);
-                    break;
-                }
+                if (stop) break;
+                f -= 4;
             }
             if (first && f < 0 && !closed && exhausted) {
                 // the segment starts before the loaded halo: left to the block-wide scan below

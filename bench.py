@@ -15,6 +15,7 @@ stream, and the CPU oracle timed on a bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
+import ctypes
 import json
 import math
 import os
@@ -41,6 +42,7 @@ def parse():
     ap.add_argument("--shards", type=int, default=115, help="c2: number of shards")
     ap.add_argument("--total", type=int, default=400_000_000, help="c2: total records")
     ap.add_argument("--n-journeys", type=int, default=None, help="scale the workload down (testing)")
+    ap.add_argument("--no-direction", action="store_true", help="c1: skip the direction-lattice measurement")
     ap.add_argument("--cpu-sample", type=int, default=40_000_000, help="records in the oracle's timed sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--out", default=None, help="also write the JSON line to this file")
@@ -353,6 +355,10 @@ def main():
         stages[fam] = round(ms / args.steps, 4)
     stages["sort_passes"] = round(pass_ms / args.steps, 4)
 
+    direction = None
+    if not args.no_direction:
+        direction = bench_direction(args, r, grid, pipe, rec, G, dev)
+
     traffic = None
     tfile = os.path.join(ROOT, "profiles", "radix_pass_c1_traffic.md")
     if args.workload == "c1" and args.n_journeys is None and os.path.exists(tfile):
@@ -389,6 +395,7 @@ def main():
                      "alg_bytes_per_launch": int(bytes_per_launch), "per_pass_ms": per_pass},
         "cpu_baseline": cpu,
         "stages_ms_per_step": stages,
+        "direction_lattice": direction,
         "key_bits": key_bits,
         "packed_from_pass": p0,
         "wall_s_timed_region": round(wall, 3),
@@ -398,6 +405,47 @@ def main():
     if args.out:
         with open(args.out, "w") as f:
             f.write(s + "\n")
+
+
+def bench_direction(args, r, grid, pipe, rec, G, dev):
+    """The lattice with four direction sectors of a sensor heading column on
+    the same sorted records: the heading gathered into sorted order, then the
+    aggregate.  Timed with HIP events around each call, after the main run."""
+    import numpy as np
+    import torch
+    from paper_2305_07454_amd import cvetl, gen
+    n = r.n
+    hd = torch.from_numpy(gen.headings(np.random.default_rng(77), r.journey_id)).to(dev)
+    hs = torch.empty_like(hd)
+    cap = max(4096, int(2.5 * G))
+    out = {k: torch.empty(cap, dtype=dt, device=dev) for k, dt in cvetl.GROUP_FIELDS}
+    need = cvetl._size(cvetl.lib().cv_grid_workspace_size, n, ctypes.byref(cvetl._spec_struct(grid)), cap)
+    ws = cvetl.workspace(need, dev)
+    pipe.run(rec)  # the sorted records and perm of this input
+    srt = pipe.sorted
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    gms, gth = 0.0, 0.0
+    steps = max(3, args.steps // 2)
+    for i in range(steps + 1):
+        ev[0].record(stream)
+        cvetl.cv_gather_column(hd, pipe.perm[:n], out=hs)
+        ev[1].record(stream)
+        _, res = cvetl.cv_grid_aggregate_dir(srt, grid, 4, 0.0, heading=hs, capacity=cap, sync=False, ws=ws,
+                                             out=out)
+        ev[2].record(stream)
+        torch.cuda.synchronize()
+        if i > 0:  # the first round warms up
+            gth += ev[0].elapsed_time(ev[1])
+            gms += ev[1].elapsed_time(ev[2])
+    rd = cvetl.read_result(res)
+    assert rd["status"] == 0, rd
+    cnt = out["count"][:rd["count"]].to(torch.int64).sum().item()
+    assert cnt + rd["n_out_of_grid"] == n, (cnt, rd["n_out_of_grid"], n)
+    log(f"direction lattice: {rd['count']} groups, gather {gth / steps:.3f} ms, aggregate {gms / steps:.3f} ms")
+    return {"n_dir": 4, "offset_deg": 0.0, "heading": "sensor column (synthetic whole degrees), gathered",
+            "groups": rd["count"], "gather_ms": round(gth / steps, 4), "aggregate_ms": round(gms / steps, 4),
+            "steps": steps}
 
 
 def pass_bytes(p, p0):

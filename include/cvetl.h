@@ -213,6 +213,38 @@ cv_status cv_grid_aggregate(const cv_records* sorted, const cv_grid_spec* grid /
                             size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
+ * cv_grid_aggregate_dir -- the lattice with the direction dimension of
+ * Algorithm 2 (a direction bin by floor division of the heading by a sector
+ * width) and of the transformed-data output (speeds and volumes per
+ * cardinal direction, 8 channels per time bin).  n_dir sectors (1..64) of
+ * width 360/n_dir degrees; a record's sector is
+ *   floor((h + dir_offset_deg) / (360 / n_dir)) mod n_dir   for h in [0, 360)
+ * (dir_offset_deg in [0, 360): 0 bins the heading literally, 45 with n_dir 4
+ * centres the sectors on N, E, S, W), and n_dir for a record without a
+ * direction (NaN or a heading outside [0, 360), or a derived bearing without
+ * CV_FLAG_BEARING_OK).  h is heading_deg[k] [device, float, sorted order;
+ * see cv_gather_column] when given, else feat->bearing_deg with feat->flags
+ * (cv_journey_features of the same sorted records).  Keys are
+ *   ((tbin * (n_dir + 1) + sector) * n_lat + ilat) * n_lon + ilon
+ * and everything else is as cv_grid_aggregate (same workspace size).
+ * CV_ERR_RANGE when n_t * n_lat * n_lon * (n_dir + 1) does not fit in int64.
+ * --------------------------------------------------------------------- */
+cv_status cv_grid_aggregate_dir(const cv_records* sorted, const float* heading_deg, const cv_features* feat,
+                                const cv_grid_spec* grid /*[host]*/, uint32_t n_dir, double dir_offset_deg,
+                                const cv_groups* out, uint64_t capacity, cv_result* res, void* ws,
+                                size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * cv_gather_column -- out[k] = in[perm[k]] for k < n: a payload column that
+ * the sort does not carry (a sensor heading, say) brought into the sorted
+ * order.  in, out [device], elem_bytes 4 or 8, aligned to it; perm [device]
+ * is the permutation of [0, n) written by cv_sort_records for the same n
+ * (an index >= n reads element n - 1).
+ * --------------------------------------------------------------------- */
+cv_status cv_gather_column(const void* in, const uint32_t* perm, void* out, uint64_t n, uint32_t elem_bytes,
+                           void* stream);
+
+/* ------------------------------------------------------------------------
  * Batched form: many independent problems ("shards", e.g. county-day files of
  * very uneven size) laid out back to back in one record array and processed
  * by the same launches as one batch.  shard_offsets [device, n_shards + 1]:

@@ -65,6 +65,10 @@ def lib():
         L.orc_grid_keys.restype = I
         L.orc_grid.argtypes = [I, P, P, P, P, P, D, D, D, D, I, I, I, I, I, I] + [P] * 7
         L.orc_grid.restype = I
+        L.orc_dir_sector.argtypes = [D, ctypes.c_int32, I, D]
+        L.orc_dir_sector.restype = I
+        L.orc_grid_dir.argtypes = [I] + [P] * 8 + [I, D, D, D, D, D, I, I, I, I, I, I] + [P] * 7
+        L.orc_grid_dir.restype = I
         _lib = L
     return _lib
 
@@ -172,3 +176,32 @@ def run_plain(cols, spec):
     summ = summary(*s, feat)
     groups, n_out = grid(*s, spec)
     return dict(perm=perm, sorted=s, features=feat, summary=summ, groups=groups, n_out=n_out)
+
+
+def dir_sector(h, ok, n_dir, offset=0.0):
+    """Direction sector of one heading (Algorithm 2's floor division by the
+    sector width, read as nd sectors of 360/nd degrees; nd = no direction)."""
+    return int(lib().orc_dir_sector(float(h), 1 if ok else 0, int(n_dir), float(offset)))
+
+
+def grid_dir(jid, ts, lat, lon, speed, spec, n_dir, offset=0.0, heading=None, bearing=None, flags=None):
+    """The lattice with a direction dimension: groups keyed by
+    ((tbin * (n_dir + 1) + sector) * n_lat + ilat) * n_lon + ilon, the sector
+    from `heading` (float32 per record) or else `bearing` with `flags`."""
+    jid, ts = _c(jid, np.int64), _c(ts, np.int64)
+    lat, lon, speed = _c(lat, np.float64), _c(lon, np.float64), _c(speed, np.float32)
+    n = jid.shape[0]
+    if heading is not None:
+        hd, br, fl = _c(heading, np.float32), None, None
+    else:
+        hd, br, fl = None, _c(bearing, np.float64), _c(flags, np.uint8)
+    cap = max(1, n)
+    out = {k: np.empty(cap, dtype=t) for k, t in GRID_FIELDS}
+    n_out = np.zeros(1, dtype=np.int64)
+    nullp = ctypes.c_void_p(0)
+    G = lib().orc_grid_dir(n, _p(jid), _p(ts), _p(lat), _p(lon), _p(speed),
+                           _p(hd) if hd is not None else nullp, _p(br) if br is not None else nullp,
+                           _p(fl) if fl is not None else nullp, int(n_dir), float(offset), *_spec_args(spec),
+                           cap, *[_p(out[k]) for k, _ in GRID_FIELDS], _p(n_out))
+    res = {k: v[:G].copy() for k, v in out.items()}
+    return res, int(n_out[0])

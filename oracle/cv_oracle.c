@@ -351,19 +351,16 @@ int64_t orc_grid_keys(int64_t n, const int64_t* ts, const double* lat, const dou
     return n_out;
 }
 
-int64_t orc_grid(int64_t n, const int64_t* jid, const int64_t* ts,
-                 const double* lat, const double* lon, const float* speed,
-                 double lat0, double lon0, double dlat, double dlon,
-                 int64_t n_lat, int64_t n_lon, int64_t t0, int64_t bin_ms, int64_t n_t,
-                 int64_t cap,
-                 int64_t* o_key, uint32_t* o_count, uint32_t* o_nj, double* o_sum,
-                 float* o_min, float* o_max, int64_t* o_nout)
+/* Groups of equal key among records with key >= 0: count, distinct journeys
+ * (records sorted by (key, journey, index); a journey counts once per key),
+ * exact speed sum rounded once, min and max speed; rows in ascending key.
+ * Rows past cap are counted, not written.  key[] is freed here. */
+static int64_t group_by_key(int64_t n, const int64_t* jid, const float* speed, int64_t* key, int64_t cap,
+                            int64_t* o_key, uint32_t* o_count, uint32_t* o_nj, double* o_sum,
+                            float* o_min, float* o_max)
 {
-    int64_t* key = (int64_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
     uint32_t* idx = (uint32_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(uint32_t));
-    if (!key || !idx) abort();
-    *o_nout = orc_grid_keys(n, ts, lat, lon, lat0, lon0, dlat, dlon, n_lat, n_lon, t0, bin_ms,
-                            n_t, key);
+    if (!idx) abort();
     int64_t m = 0;
     for (int64_t i = 0; i < n; ++i)
         if (key[i] >= 0) idx[m++] = (uint32_t)i;
@@ -400,4 +397,74 @@ int64_t orc_grid(int64_t n, const int64_t* jid, const int64_t* ts,
     free(key);
     free(idx);
     return G;
+}
+
+int64_t orc_grid(int64_t n, const int64_t* jid, const int64_t* ts,
+                 const double* lat, const double* lon, const float* speed,
+                 double lat0, double lon0, double dlat, double dlon,
+                 int64_t n_lat, int64_t n_lon, int64_t t0, int64_t bin_ms, int64_t n_t,
+                 int64_t cap,
+                 int64_t* o_key, uint32_t* o_count, uint32_t* o_nj, double* o_sum,
+                 float* o_min, float* o_max, int64_t* o_nout)
+{
+    int64_t* key = (int64_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    if (!key) abort();
+    *o_nout = orc_grid_keys(n, ts, lat, lon, lat0, lon0, dlat, dlon, n_lat, n_lon, t0, bin_ms,
+                            n_t, key);
+    return group_by_key(n, jid, speed, key, cap, o_key, o_count, o_nj, o_sum, o_min, o_max);
+}
+
+/* Direction sector (Algorithm 2: the heading binned by floor division with a
+ * sector width; the transformed-data output: speeds and volumes per cardinal
+ * direction).  Reading: nd sectors of width 360/nd degrees, sector =
+ * floor((h + off) / (360/nd)) mod nd for a heading h in [0, 360); off = 0 is
+ * the literal floor division, off = 45 with nd = 4 centres N, E, S, W.  A
+ * record without a direction (h outside [0, 360) or NaN; a derived bearing
+ * that is not defined) falls in the extra sector nd, so that counts over all
+ * sectors still sum to the records in the grid. */
+int64_t orc_dir_sector(double h, int32_t ok, int64_t nd, double off)
+{
+    if (!ok || !(h >= 0.0 && h < 360.0)) return nd;
+    double step = 360.0 / (double)nd;
+    int64_t q = (int64_t)floor((h + off) / step);
+    return q % nd;
+}
+
+/* The lattice with a direction dimension: key =
+ * ((tbin * (nd + 1) + sector) * n_lat + ilat) * n_lon + ilon for records in
+ * the grid (the same bins as orc_grid_keys).  The heading of record i is
+ * heading[i] when heading is given, else bearing[i] when flags[i] has
+ * F_BEARING_OK. */
+int64_t orc_grid_dir(int64_t n, const int64_t* jid, const int64_t* ts,
+                     const double* lat, const double* lon, const float* speed,
+                     const float* heading, const double* bearing, const uint8_t* flags,
+                     int64_t nd, double off,
+                     double lat0, double lon0, double dlat, double dlon,
+                     int64_t n_lat, int64_t n_lon, int64_t t0, int64_t bin_ms, int64_t n_t,
+                     int64_t cap,
+                     int64_t* o_key, uint32_t* o_count, uint32_t* o_nj, double* o_sum,
+                     float* o_min, float* o_max, int64_t* o_nout)
+{
+    int64_t* key = (int64_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    if (!key) abort();
+    int64_t cells = n_lat * n_lon;
+    int64_t tmax = (n_t > 0) ? n_t : (INT64_MAX / (cells * (nd + 1)));
+    int64_t n_out = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        key[i] = -1;
+        if (!isfinite(lat[i]) || !isfinite(lon[i])) { ++n_out; continue; }
+        double fy = floor((lat[i] - lat0) / dlat);
+        double fx = floor((lon[i] - lon0) / dlon);
+        int64_t tb = floor_div64(ts[i] - t0, bin_ms);
+        if (!(fy >= 0.0 && fy < (double)n_lat && fx >= 0.0 && fx < (double)n_lon &&
+              tb >= 0 && tb < tmax)) {
+            ++n_out;
+            continue;
+        }
+        int64_t sec = heading ? orc_dir_sector((double)heading[i], 1, nd, off)
+                              : orc_dir_sector(bearing[i], (flags[i] & F_BEARING_OK) != 0, nd, off);
+        key[i] = ((tb * (nd + 1) + sec) * n_lat + (int64_t)fy) * n_lon + (int64_t)fx;
+    }
+    *o_nout = n_out;
+    return group_by_key(n, jid, speed, key, cap, o_key, o_count, o_nj, o_sum, o_min, o_max);
 }

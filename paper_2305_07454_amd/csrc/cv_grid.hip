@@ -76,6 +76,32 @@ struct GridLayout {
 
 int g_lds_slots = 256;  // LDS hash slots per tile (tuning knob "grid_lds_slots")
 
+// out[k] = in[perm[k]]: a payload column in the sort's order (GU per round,
+// loads issued together)
+template <class T>
+__global__ void __launch_bounds__(256) k_gather_col(const T* __restrict__ in, const u32* __restrict__ perm,
+                                                    T* __restrict__ out, u32 n)
+{
+    constexpr int GU = 4;
+    const u64 stride = (u64)gridDim.x * blockDim.x;
+    for (u64 k0 = (u64)blockIdx.x * blockDim.x + threadIdx.x; k0 < n; k0 += GU * stride) {
+        u32 p[GU];
+        T v[GU];
+#pragma unroll
+        for (int u = 0; u < GU; ++u) {
+            const u64 k = k0 + u * stride;
+            p[u] = perm[k < n ? k : n - 1];
+        }
+#pragma unroll
+        for (int u = 0; u < GU; ++u) v[u] = in[p[u] < n ? p[u] : n - 1];  // a permutation of [0, n)
+#pragma unroll
+        for (int u = 0; u < GU; ++u) {
+            const u64 k = k0 + u * stride;
+            if (k < n) out[k] = v[u];
+        }
+    }
+}
+
 bool spec_ok(const cv_grid_spec* g)
 {
     if (!g) return false;
@@ -102,9 +128,29 @@ bool set_grid_lds_slots(int v)
 int grid_lds_slots() { return g_lds_slots; }
 }  // namespace cv
 
+// the tile kernel for a table size and a direction source
+template <class Pol>
+static void launch_tiles(dim3 gg, hipStream_t s, u32 nn, const cv_records* sorted, const Spec& g, GEntry* tab,
+                         u64 gmask, GridMeta* meta)
+{
+    const dim3 gb(GB);
+    if (g_lds_slots >= 1024)
+        hipLaunchKernelGGL((k_grid_agg<1024, Pol>), gg, gb, 0, s, nn, sorted->journey_id, sorted->ts_ms,
+                           sorted->lat_deg, sorted->lon_deg, sorted->speed_mps, g, tab, gmask, meta, Pol{});
+    else if (g_lds_slots >= 512)
+        hipLaunchKernelGGL((k_grid_agg<512, Pol>), gg, gb, 0, s, nn, sorted->journey_id, sorted->ts_ms,
+                           sorted->lat_deg, sorted->lon_deg, sorted->speed_mps, g, tab, gmask, meta, Pol{});
+    else
+        hipLaunchKernelGGL((k_grid_agg<256, Pol>), gg, gb, 0, s, nn, sorted->journey_id, sorted->ts_ms,
+                           sorted->lat_deg, sorted->lon_deg, sorted->speed_mps, g, tab, gmask, meta, Pol{});
+}
+
+// nd > 0: a direction dimension of nd sectors (plus one for records without a
+// direction) from the sorted heading column hdg, else from feat's bearing
 static cv_status grid_impl(const cv_records* sorted, const u64* soff, u32 S, const cv_grid_spec* grid,
                            const cv_groups* out, uint64_t capacity, u64* go, cv_result* res, void* ws, size_t ws_bytes,
-                           void* stream)
+                           void* stream, u32 nd = 0, double doff = 0.0, const float* hdg = nullptr,
+                           const cv_features* feat = nullptr)
 {
     if (!sorted || !out || sorted->n >= (1ull << 32) || capacity >= (1ull << 31) || !spec_ok(grid))
         return CV_ERR_INVALID_ARGUMENT;
@@ -132,10 +178,16 @@ static cv_status grid_impl(const cv_records* sorted, const u64* soff, u32 S, con
     g.n_lon = grid->n_lon;
     g.t0 = grid->t0_ms;
     g.bin_ms = grid->bin_ms;
-    g.tmax = grid->n_t > 0 ? grid->n_t : (INT64_MAX / (grid->n_lat * grid->n_lon));
+    g.tmax = grid->n_t > 0 ? grid->n_t : (INT64_MAX / (grid->n_lat * grid->n_lon * (i64)(nd + 1)));
     g.soff = soff;
     g.S = S;
     g.kb = 0;
+    g.nd = nd;
+    g.dstep = nd ? 360.0 / (double)nd : 0.0;
+    g.doff = doff;
+    g.hdg = hdg;
+    g.brg = (nd && !hdg) ? feat->bearing_deg : nullptr;
+    g.bfl = (nd && !hdg) ? feat->flags : nullptr;
     if (S > 1) {
         // cell keys < n_t * n_lat * n_lon; the shard index goes above them
         const unsigned __int128 cells = (unsigned __int128)grid->n_t * grid->n_lat * grid->n_lon;
@@ -154,19 +206,10 @@ static cv_status grid_impl(const cv_records* sorted, const u64* soff, u32 S, con
         hipLaunchKernelGGL(k_grid_clear, dim3(cvh::grid_for(L.slots, 256, 4096)), dim3(256), 0, s, L.tab, L.slots,
                            L.meta);
         cvh::fill_u32(L.zero_begin, 0u, L.zero_bytes / 4, s);
-        const dim3 gg((unsigned)L.tiles), gb(GB);
-        if (g_lds_slots >= 1024)
-            hipLaunchKernelGGL((k_grid_agg<1024, GridPlain>), gg, gb, 0, s, nn, sorted->journey_id, sorted->ts_ms,
-                               sorted->lat_deg, sorted->lon_deg, sorted->speed_mps, g, L.tab, L.slots - 1, L.meta,
-                               GridPlain{});
-        else if (g_lds_slots >= 512)
-            hipLaunchKernelGGL((k_grid_agg<512, GridPlain>), gg, gb, 0, s, nn, sorted->journey_id, sorted->ts_ms,
-                               sorted->lat_deg, sorted->lon_deg, sorted->speed_mps, g, L.tab, L.slots - 1, L.meta,
-                               GridPlain{});
-        else
-            hipLaunchKernelGGL((k_grid_agg<256, GridPlain>), gg, gb, 0, s, nn, sorted->journey_id, sorted->ts_ms,
-                               sorted->lat_deg, sorted->lon_deg, sorted->speed_mps, g, L.tab, L.slots - 1, L.meta,
-                               GridPlain{});
+        const dim3 gg((unsigned)L.tiles);
+        if (nd == 0) launch_tiles<GridPlain>(gg, s, nn, sorted, g, L.tab, L.slots - 1, L.meta);
+        else if (hdg) launch_tiles<GridHeading>(gg, s, nn, sorted, g, L.tab, L.slots - 1, L.meta);
+        else launch_tiles<GridBearing>(gg, s, nn, sorted, g, L.tab, L.slots - 1, L.meta);
     }
     {
         cvh::TimedScope ts_("grid_tail", s);
@@ -206,6 +249,37 @@ cv_status cv_grid_aggregate(const cv_records* sorted, const cv_grid_spec* grid, 
                             uint64_t capacity, cv_result* res, void* ws, size_t ws_bytes, void* stream)
 {
     return grid_impl(sorted, nullptr, 0, grid, out, capacity, nullptr, res, ws, ws_bytes, stream);
+}
+
+cv_status cv_grid_aggregate_dir(const cv_records* sorted, const float* heading_deg, const cv_features* feat,
+                                const cv_grid_spec* grid, uint32_t n_dir, double dir_offset_deg, const cv_groups* out,
+                                uint64_t capacity, cv_result* res, void* ws, size_t ws_bytes, void* stream)
+{
+    if (!grid || n_dir < 1 || n_dir > 64 || !(dir_offset_deg >= 0.0 && dir_offset_deg < 360.0))
+        return CV_ERR_INVALID_ARGUMENT;
+    if (!heading_deg && (!feat || !feat->bearing_deg || !feat->flags)) return CV_ERR_INVALID_ARGUMENT;
+    if (grid->n_t > 0 && (__int128)grid->n_t * grid->n_lat * grid->n_lon * (n_dir + 1) >= ((__int128)1 << 63))
+        return CV_ERR_RANGE;
+    return grid_impl(sorted, nullptr, 0, grid, out, capacity, nullptr, res, ws, ws_bytes, stream, n_dir,
+                     dir_offset_deg, heading_deg, feat);
+}
+
+cv_status cv_gather_column(const void* in, const uint32_t* perm, void* out, uint64_t n, uint32_t elem_bytes,
+                           void* stream)
+{
+    if (n >= (1ull << 32) || (elem_bytes != 4 && elem_bytes != 8)) return CV_ERR_INVALID_ARGUMENT;
+    if (n == 0) return CV_OK;
+    if (!in || !perm || !out || !cvh::aligned(in, elem_bytes) || !cvh::aligned(out, elem_bytes))
+        return CV_ERR_INVALID_ARGUMENT;
+    hipStream_t s = (hipStream_t)stream;
+    const unsigned blocks = (unsigned)cvh::grid_for(n, 256, 8192);
+    if (elem_bytes == 4)
+        hipLaunchKernelGGL((k_gather_col<uint32_t>), dim3(blocks), dim3(256), 0, s, (const uint32_t*)in, perm,
+                           (uint32_t*)out, (u32)n);
+    else
+        hipLaunchKernelGGL((k_gather_col<u64>), dim3(blocks), dim3(256), 0, s, (const u64*)in, perm, (u64*)out,
+                           (u32)n);
+    return cvh::last_launch_status();
 }
 
 cv_status cv_batch_grid_aggregate(const cv_records* sorted, const uint64_t* shard_offsets, uint32_t n_shards,

@@ -14,13 +14,20 @@
 namespace cv {
 namespace {
 
-// the plain and batched forms: nothing is late or carried
-struct GridPlain {
+// the plain and batched forms: nothing is late or carried; kDir says where a
+// direction sector comes from (0: no direction dimension, 1: a sensor heading
+// column, 2: the derived bearing and its flags)
+template <int KD>
+struct GridPlainT {
     static constexpr bool kStream = false;
+    static constexpr int kDir = KD;
     __device__ bool late(u64) const { return false; }
     __device__ bool carried(u64, u64) const { return false; }
     __device__ void first(u64, u64) const {}
 };
+using GridPlain = GridPlainT<0>;
+using GridHeading = GridPlainT<1>;
+using GridBearing = GridPlainT<2>;
 
 constexpr int GB = 256;
 constexpr int GI = 8;
@@ -233,6 +240,10 @@ k_grid_agg(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, const
     double vla[NR], vlo[NR];
     float vsp[GI];
     uint8_t vlt[NR];
+    // direction inputs (only in the forms with a direction dimension)
+    float vh[Pol::kDir == 1 ? NR : 1];
+    double vb[Pol::kDir == 2 ? NR : 1];
+    uint8_t vbf[Pol::kDir == 2 ? NR : 1];
 #pragma unroll
     for (int rr = 0; rr < NR; ++rr) {
         // positions outside [0, n) read a record in range (ignored below): no
@@ -245,6 +256,11 @@ k_grid_agg(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, const
         vlo[rr] = lon[r];
         if (rr >= HR) vsp[rr - HR] = spd[r];
         vlt[rr] = Pol::kStream ? (uint8_t)pol.late((u64)r) : (uint8_t)0;
+        if constexpr (Pol::kDir == 1) vh[rr] = g.hdg[r];
+        if constexpr (Pol::kDir == 2) {
+            vb[rr] = g.brg[r];
+            vbf[rr] = g.bfl[r];
+        }
     }
     if (t == 0) {
         s_pj = base > 0 ? jid[base - 1] : 0;
@@ -266,7 +282,10 @@ k_grid_agg(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, const
         if (in) {
             if (g.S > 1)
                 while (sh + 1 < g.S && g.soff[sh + 1] <= (u64)r) ++sh;
-            k = grid_key_in(g, sh, vt[rr], vla[rr], vlo[rr], tb);
+            u32 dir = 0;
+            if constexpr (Pol::kDir == 1) dir = dir_sector(g, (double)vh[rr], true);
+            if constexpr (Pol::kDir == 2) dir = dir_sector(g, vb[rr], (vbf[rr] & CV_FLAG_BEARING_OK) != 0);
+            k = grid_key_in(g, sh, vt[rr], vla[rr], vlo[rr], tb, dir);
             if (rr >= HR) n_out += (k < 0);
         }
         const i64 jp = __shfl_up(vj[rr], 1, WAVE);
@@ -438,7 +457,7 @@ k_grid_agg(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, const
                 i64 k = -1;
                 if (r >= 0) {
                     i64 tb;
-                    k = grid_key(g, (u64)r, ts[r], lat[r], lon[r], tb);
+                    k = grid_key(g, (u64)r, ts[r], lat[r], lon[r], tb, dir_at<Pol::kDir>(g, (u64)r));
                     if (Pol::kStream && pol.late((u64)r)) {
                         c = r + 1;  // late records are outside every segment of non-late ones
                         k = -1;

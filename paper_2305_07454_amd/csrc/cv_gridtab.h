@@ -70,6 +70,14 @@ struct Spec {
     const u64* soff;  // shard offsets (batched form) or nullptr
     u32 S;            // number of shards (0 or 1: one problem)
     u32 kb;           // bits of the cell key; the shard index sits above them
+    // direction dimension (nd sectors plus one for records without a
+    // direction; nd = 0: none): a sensor heading per sorted record, else the
+    // derived bearing with its flags
+    u32 nd;
+    double dstep, doff;  // sector width 360 / nd and offset, degrees
+    const float* hdg;
+    const double* brg;
+    const uint8_t* bfl;
 };
 
 // floor(a / b) for b > 0: a double estimate corrected by one integer step
@@ -88,24 +96,46 @@ __device__ __forceinline__ i64 floor_div64(i64 a, i64 b)
     return q;
 }
 
+// Direction sector of a heading h in degrees (Algorithm 2 bins it by floor
+// division with a sector width): floor((h + doff) / dstep) mod nd for h in
+// [0, 360); nd for a missing direction (no valid heading or bearing).
+__device__ __forceinline__ u32 dir_sector(const Spec& g, double h, bool ok)
+{
+    if (!ok || !(h >= 0.0 && h < 360.0)) return g.nd;
+    const u32 s = (u32)floor((h + g.doff) / g.dstep);
+    return s % g.nd;
+}
+
+// the sector of sorted record r: KD = 1 sensor heading, 2 derived bearing
+template <int KD>
+__device__ __forceinline__ u32 dir_at(const Spec& g, u64 r)
+{
+    if constexpr (KD == 1) return dir_sector(g, (double)g.hdg[r], true);
+    else if constexpr (KD == 2) return dir_sector(g, g.brg[r], (g.bfl[r] & CV_FLAG_BEARING_OK) != 0);
+    else return 0u;
+}
+
 // key (or -1) and time bin of a record of shard sh; floor of the IEEE
-// quotient.  In the batched form the shard index is placed above the cell key.
-__device__ __forceinline__ i64 grid_key_in(const Spec& g, u32 sh, i64 ts, double la, double lo, i64& tb)
+// quotient.  In the batched form the shard index is placed above the cell key;
+// with directions, the sector sits between the time bin and the cell.
+__device__ __forceinline__ i64 grid_key_in(const Spec& g, u32 sh, i64 ts, double la, double lo, i64& tb,
+                                           u32 dir = 0)
 {
     tb = floor_div64(ts - g.t0, g.bin_ms);
     if (!isfinite(la) || !isfinite(lo)) return -1;
     double fy = floor((la - g.lat0) / g.dlat);
     double fx = floor((lo - g.lon0) / g.dlon);
     if (!(fy >= 0.0 && fy < (double)g.n_lat && fx >= 0.0 && fx < (double)g.n_lon && tb >= 0 && tb < g.tmax)) return -1;
-    i64 k = (tb * g.n_lat + (i64)fy) * g.n_lon + (i64)fx;
+    const i64 td = g.nd ? tb * (i64)(g.nd + 1) + (i64)dir : tb;
+    i64 k = (td * g.n_lat + (i64)fy) * g.n_lon + (i64)fx;
     if (g.S > 1) k |= (i64)((u64)sh << g.kb);
     return k;
 }
 
 // the same for record r (its shard found by binary search)
-__device__ __forceinline__ i64 grid_key(const Spec& g, u64 r, i64 ts, double la, double lo, i64& tb)
+__device__ __forceinline__ i64 grid_key(const Spec& g, u64 r, i64 ts, double la, double lo, i64& tb, u32 dir = 0)
 {
-    return grid_key_in(g, g.S > 1 ? shard_of(g.soff, g.S, r) : 0u, ts, la, lo, tb);
+    return grid_key_in(g, g.S > 1 ? shard_of(g.soff, g.S, r) : 0u, ts, la, lo, tb, dir);
 }
 
 // first record of a (journey, time-bin) segment (shard starts included)

@@ -425,6 +425,7 @@ __device__ __forceinline__ bool ovf_contains(const u64* tab, u64 key)
 // is appended for the row update that follows the tile kernel.
 struct GridStream {
     static constexpr bool kStream = true;
+    static constexpr int kDir = 0;
     const i64* jid;          // sorted batch
     const uint8_t* flags;    // sorted batch features' flags
     const u32* boff;         // batch journey starts
@@ -878,6 +879,11 @@ cv_status cv_stream_create(const cv_grid_spec* grid, uint64_t max_journeys, uint
     g.soff = nullptr;
     g.S = 0;
     g.kb = 0;
+    g.nd = 0;
+    g.dstep = g.doff = 0.0;
+    g.hdg = nullptr;
+    g.brg = nullptr;
+    g.bfl = nullptr;
     cvh::Carver c(state);
     StreamLayout::carve(c, st->jslots, st->gslots, max_batch, [&](const char* name, void* p) {
         const std::string nm(name);

@@ -142,6 +142,12 @@ def lib():
         L.cv_stream_flush.restype = S
         L.cv_stream_destroy.argtypes = [P]
         L.cv_stream_destroy.restype = S
+        L.cv_grid_aggregate_dir.argtypes = [ctypes.POINTER(CvRecords), P, ctypes.POINTER(CvFeatures),
+                                            ctypes.POINTER(CvGridSpec), U32, ctypes.c_double,
+                                            ctypes.POINTER(CvGroups), U64, P, P, ctypes.c_size_t, P]
+        L.cv_grid_aggregate_dir.restype = S
+        L.cv_gather_column.argtypes = [P, P, P, U64, U32, P]
+        L.cv_gather_column.restype = S
         L.cv_tuning_set.argtypes = [ctypes.c_char_p, ctypes.c_int64]
         L.cv_tuning_set.restype = S
         L.cv_tuning_get.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64)]
@@ -307,6 +313,50 @@ def cv_grid_aggregate(sorted_rec, grid, capacity=None, stream=None, sync=True, w
     _check(r["status"], "cv_grid_aggregate (device)")
     G = r["count"]
     return {k: v[:G] for k, v in out.items()}, r
+
+
+def cv_grid_aggregate_dir(sorted_rec, grid, n_dir=4, offset=0.0, heading=None, feat=None, capacity=None,
+                          stream=None, sync=True, ws=None, out=None):
+    """The lattice with a direction dimension; the sector comes from `heading`
+    (float32 per sorted record) when given, else from feat's bearing."""
+    L = lib()
+    n = int(sorted_rec["journey_id"].numel())
+    dev = sorted_rec["journey_id"].device
+    cap = int(capacity) if capacity is not None else max(1, min(n, 1 << 22))
+    spec = _spec_struct(grid)
+    if out is None:
+        out = {k: torch.empty(cap, dtype=dt, device=dev) for k, dt in GROUP_FIELDS}
+    gs = CvGroups(*(_ptr(out[k]) for k, _ in GROUP_FIELDS))
+    need = _size(L.cv_grid_workspace_size, n, ctypes.byref(spec), cap)
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, dev)
+    res = new_result(dev)
+    fs = _feat_struct(feat) if feat is not None else None
+    st = L.cv_grid_aggregate_dir(ctypes.byref(_records_struct(sorted_rec)), _ptr(heading),
+                                 ctypes.byref(fs) if fs is not None else None, ctypes.byref(spec), int(n_dir),
+                                 float(offset), ctypes.byref(gs), cap, _ptr(res), _ptr(ws), ws.numel(),
+                                 _stream(stream))
+    _check(st, "cv_grid_aggregate_dir")
+    if not sync:
+        return out, res
+    r = read_result(res)
+    if r["status"] == CV_ERR_CAPACITY and capacity is None:
+        return cv_grid_aggregate_dir(sorted_rec, grid, n_dir, offset, heading, feat, capacity=r["required"],
+                                     stream=stream)
+    _check(r["status"], "cv_grid_aggregate_dir (device)")
+    G = r["count"]
+    return {k: v[:G] for k, v in out.items()}, r
+
+
+def cv_gather_column(col, perm, stream=None, out=None):
+    """out[k] = col[perm[k]] on the device (a payload column in sorted order)."""
+    n = int(perm.numel())
+    assert int(col.numel()) == n and col.element_size() in (4, 8)
+    if out is None:
+        out = torch.empty_like(col)
+    _check(lib().cv_gather_column(_ptr(col), _ptr(perm), _ptr(out), n, col.element_size(), _stream(stream)),
+           "cv_gather_column")
+    return out
 
 
 # ---------------------------------------------------------------------------

@@ -324,6 +324,22 @@ def make_stream(seed=None, n_journeys=2000, median=1500.0, sigma=1.0, cap=86_400
                    dict(n_journeys=n_journeys, heavy_frac=heavy_frac))
 
 
+def headings(rng, journey_id) -> np.ndarray:
+    """A sensor heading column (whole degrees, as in Table 1) for records in
+    which each journey's records are contiguous: a random start per journey
+    and a slow random walk (2 degrees per record), float32 in [0, 360)."""
+    n = journey_id.shape[0]
+    start = np.ones(n, dtype=bool)
+    start[1:] = journey_id[1:] != journey_id[:-1]
+    step = rng.normal(0.0, 2.0, n)
+    step[start] = rng.uniform(0.0, 360.0, int(start.sum()))
+    c = np.cumsum(step)
+    first = np.maximum.accumulate(np.where(start, np.arange(n), 0))
+    base = c[first] - step[first]
+    h = np.floor(np.mod(c - base, 360.0))
+    return h.astype(np.float32)
+
+
 def chunk_sizes(rng, n, lo, hi):
     """Consecutive chunk sizes, log-uniform on [lo, hi], covering n records."""
     out = []

@@ -1,0 +1,110 @@
+"""Direction lattice (sectors of the heading or of the derived bearing in the
+grid key) and the payload-column gather: HIP path vs the oracle, exactly."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2305_07454_amd import gen
+
+from _parity import assert_exact, check_groups, host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cv():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2305_07454_amd import cvetl
+    cvetl.lib()
+    oracle.lib()
+    return cvetl
+
+
+def _headings(rng, n):
+    """Whole-degree sensor headings (as in Table 1) with some missing or out of range."""
+    h = rng.integers(0, 360, n).astype(np.float32)
+    bad = rng.random(n)
+    h[bad < 0.02] = np.nan
+    h[(bad >= 0.02) & (bad < 0.03)] = 360.0
+    h[(bad >= 0.03) & (bad < 0.04)] = -1.0
+    return h
+
+
+@pytest.mark.parametrize("n_dir,offset", [(4, 0.0), (4, 45.0), (8, 22.5), (1, 0.0)])
+def test_heading_sectors_match_oracle(cv, n_dir, offset):
+    import torch
+    r = gen.make_c1(seed=31, n_journeys=60, median=900.0, shuffled=True)
+    hd = _headings(np.random.default_rng(31), r.n)
+    grid = gen.GRIDS["c1"]
+    print(f"[direction] heading n={r.n} n_dir={n_dir} offset={offset}", flush=True)
+    rec = cv.to_device(r)
+    perm, srt, _ = cv.cv_sort_records(rec)
+    hs = cv.cv_gather_column(torch.from_numpy(hd).cuda(), perm)
+    exp_perm = oracle.sort(r.journey_id, r.ts_ms)
+    assert_exact("gathered heading", host(hs).view(np.uint32), hd[exp_perm].view(np.uint32))
+    got, rg = cv.cv_grid_aggregate_dir(srt, grid, n_dir, offset, heading=hs)
+    s = oracle.sorted_records(r.columns(), exp_perm)
+    exp, n_out = oracle.grid_dir(*s, grid, n_dir, offset, heading=hd[exp_perm])
+    check_groups(got, rg["n_out_of_grid"], exp, n_out)
+
+
+def test_bearing_sectors_match_oracle(cv):
+    # sectors of the derived bearing: the oracle takes its own features; no
+    # oracle bearing lies within 1e-9 degrees of a sector boundary (where a
+    # one-ulp libm difference could move a record to the next sector)
+    r = gen.make_c1(seed=32, n_journeys=60, median=900.0, shuffled=True)
+    grid = gen.GRIDS["c1"]
+    rec = cv.to_device(r)
+    perm, srt, _ = cv.cv_sort_records(rec)
+    feat = cv.cv_journey_features(srt)
+    exp_perm = oracle.sort(r.journey_id, r.ts_ms)
+    s = oracle.sorted_records(r.columns(), exp_perm)
+    ef = oracle.features(s[0], s[1], s[2], s[3])
+    for n_dir, offset in ((4, 0.0), (4, 45.0), (8, 0.0)):
+        print(f"[direction] bearing n={r.n} n_dir={n_dir} offset={offset}", flush=True)
+        ok = (ef["flags"] & 0x10) != 0
+        x = (ef["bearing_deg"][ok] + offset) / (360.0 / n_dir)
+        assert np.min(np.abs(x - np.rint(x))) * (360.0 / n_dir) > 1e-9
+        got, rg = cv.cv_grid_aggregate_dir(srt, grid, n_dir, offset, feat=feat)
+        exp, n_out = oracle.grid_dir(*s, grid, n_dir, offset, bearing=ef["bearing_deg"], flags=ef["flags"])
+        check_groups(got, rg["n_out_of_grid"], exp, n_out)
+
+
+def test_direction_long_segments_every_lds_table(cv):
+    # hour-long 20 Hz segments over 0.0001-degree cells with a turning
+    # heading: the block-wide backward scan recomputes keys with sectors
+    import torch
+    rng = np.random.default_rng(33)
+    L = 30_000
+    k = np.arange(L)
+    lat = 37.0 + 2e-6 * k + 0.002 * np.sin(k / 150.0) + 1e-5 * rng.standard_normal(L)
+    lon = -92.0 + 0.002 * np.cos(k / 110.0) + 1e-5 * rng.standard_normal(L)
+    cols = (np.full(L, 9, np.int64), gen.T0_MS + k * 50, lat, lon, rng.gamma(2.0, 5.0, L).astype(np.float32))
+    hd = ((k // 7) * 13 % 360).astype(np.float32)
+    spec = gen.GridSpec(36.9, -92.1, 0.0001, 0.0001, 4000, 4000, gen.T0_MS, 3_600_000, 24)
+    exp, n_out = oracle.grid_dir(*cols, spec, 4, 45.0, heading=hd)
+    rec = cv.to_device(cols)
+    perm, srt, _ = cv.cv_sort_records(rec)
+    hs = cv.cv_gather_column(torch.from_numpy(hd).cuda(), perm)
+    prev = cv.cv_tuning_get("grid_lds_slots")
+    try:
+        for slots in (256, 512, 1024):
+            cv.cv_tuning_set("grid_lds_slots", slots)
+            print(f"[direction] long segments, {slots} LDS slots", flush=True)
+            got, rg = cv.cv_grid_aggregate_dir(srt, spec, 4, 45.0, heading=hs)
+            check_groups(got, rg["n_out_of_grid"], exp, n_out)
+    finally:
+        cv.cv_tuning_set("grid_lds_slots", prev)
+
+
+def test_direction_argument_errors(cv):
+    import torch
+    r = gen.make_c0(seed=34, n_journeys=3, min_len=10, max_len=20)
+    rec = cv.to_device(r)
+    perm, srt, _ = cv.cv_sort_records(rec)
+    hs = torch.zeros(r.n, dtype=torch.float32, device="cuda")
+    for n_dir, off, h in ((0, 0.0, hs), (65, 0.0, hs), (4, 360.0, hs), (4, -1.0, hs), (4, 0.0, None)):
+        with pytest.raises(cv.CvError):
+            cv.cv_grid_aggregate_dir(srt, gen.GRIDS["c0"], n_dir, off, heading=h, feat=None)

@@ -348,6 +348,127 @@ def test_grid_brute_force(oracle_mod):
     assert int(res["n_journeys"].sum()) == len(pairs)
 
 
+@pytest.mark.parametrize("n_dir,offset,cases", [
+    # literal floor division by 90 degrees (Algorithm 2): [0, 90) -> 0 ...
+    (4, 0.0, [(0.0, 0), (45.0, 0), (89.999, 0), (90.0, 1), (180.0, 2), (269.5, 2), (270.0, 3), (359.9, 3)]),
+    # centred on N, E, S, W: N = [315, 45), E = [45, 135), S = [135, 225), W = [225, 315)
+    (4, 45.0, [(0.0, 0), (44.999, 0), (45.0, 1), (134.9, 1), (135.0, 2), (224.9, 2), (225.0, 3), (315.0, 0),
+               (359.9, 0)]),
+    # eight sectors of 45 degrees
+    (8, 0.0, [(0.0, 0), (44.9, 0), (45.0, 1), (200.0, 4), (315.0, 7), (359.0, 7)]),
+    # no direction: outside [0, 360) or NaN -> the extra sector n_dir
+    (4, 0.0, [(360.0, 4), (-0.5, 4), (float("nan"), 4), (1e300, 4)]),
+])
+def test_dir_sector_values(oracle_mod, n_dir, offset, cases):
+    for h, want in cases:
+        assert oracle_mod.dir_sector(h, True, n_dir, offset) == want, (h, n_dir, offset)
+    # a bearing without CV_FLAG_BEARING_OK has no direction
+    assert oracle_mod.dir_sector(10.0, False, n_dir, offset) == n_dir
+
+
+def _remap_plain(groups, cells, n_dir, sector):
+    """Plain lattice keys -> direction-lattice keys with every record in one sector."""
+    k = groups["key"]
+    return ((k // cells) * (n_dir + 1) + sector) * cells + k % cells
+
+
+def test_grid_dir_reduces_to_plain_lattice(oracle_mod):
+    # one sector with every heading valid, or no valid heading at all: the
+    # direction lattice is the plain one with the keys spread by (n_dir + 1)
+    r = gen.make_c1(seed=13, n_journeys=25, median=500.0)
+    spec = gen.GRIDS["c1"]
+    cells = spec.n_lat * spec.n_lon
+    plain, n_out = oracle_mod.grid(*r.columns(), spec)
+    for n_dir, hd, sector in ((1, np.full(r.n, 123.0, np.float32), 0),
+                              (4, np.full(r.n, np.nan, np.float32), 4),
+                              (4, np.full(r.n, -3.0, np.float32), 4)):
+        g, no = oracle_mod.grid_dir(*r.columns(), spec, n_dir, 0.0, heading=hd)
+        assert no == n_out
+        np.testing.assert_array_equal(g["key"], _remap_plain(plain, cells, n_dir, sector))
+        for f in ("count", "n_journeys", "sum_speed", "min_speed", "max_speed"):
+            np.testing.assert_array_equal(g[f], plain[f], err_msg=f)
+
+
+def test_grid_dir_marginals_over_sectors(oracle_mod):
+    # summed over sectors: counts and extrema of a (time bin, cell) are the
+    # plain lattice's; a journey counted in a cell is counted in at least one
+    # of its sectors and in at most all of them
+    r = gen.make_c1(seed=14, n_journeys=25, median=500.0)
+    spec = gen.GRIDS["c1"]
+    cells = spec.n_lat * spec.n_lon
+    rng = np.random.default_rng(5)
+    hd = rng.integers(0, 360, r.n).astype(np.float32)
+    hd[rng.random(r.n) < 0.05] = np.nan
+    g, _ = oracle_mod.grid_dir(*r.columns(), spec, 4, 45.0, heading=hd)
+    plain, _ = oracle_mod.grid(*r.columns(), spec)
+    k = g["key"]
+    tb, sec, cell = k // (5 * cells), (k // cells) % 5, k % cells
+    pk = tb * cells + cell
+    assert set(sec.tolist()) <= set(range(5))
+    idx = np.searchsorted(plain["key"], pk)
+    assert np.all(plain["key"][idx] == pk)
+    cnt = np.zeros(len(plain["key"]), np.int64)
+    njs = np.zeros(len(plain["key"]), np.int64)
+    mn = np.full(len(plain["key"]), np.inf)
+    mx = np.full(len(plain["key"]), -np.inf)
+    np.add.at(cnt, idx, g["count"].astype(np.int64))
+    np.add.at(njs, idx, g["n_journeys"].astype(np.int64))
+    np.minimum.at(mn, idx, g["min_speed"].astype(np.float64))
+    np.maximum.at(mx, idx, g["max_speed"].astype(np.float64))
+    np.testing.assert_array_equal(cnt, plain["count"])
+    np.testing.assert_array_equal(mn, plain["min_speed"].astype(np.float64))
+    np.testing.assert_array_equal(mx, plain["max_speed"].astype(np.float64))
+    assert np.all(njs >= plain["n_journeys"]) and np.all(njs <= 5 * plain["n_journeys"])
+
+
+def test_grid_dir_brute_force_tiny(oracle_mod):
+    # every group of a tiny input from a dictionary of (key -> records)
+    rng = np.random.default_rng(15)
+    n = 60
+    jid = rng.integers(1, 5, n).astype(np.int64)
+    ts = gen.T0_MS + rng.integers(0, 3, n).astype(np.int64) * 300_000 + rng.integers(0, 1000, n)
+    lat = 38.0 + rng.integers(0, 3, n) * 0.01 + 0.001
+    lon = -92.0 + rng.integers(0, 2, n) * 0.01 + 0.001
+    spd = rng.gamma(2.0, 4.0, n).astype(np.float32)
+    hd = rng.choice(np.array([0.0, 10.0, 95.0, 180.0, 266.0, 359.0, np.nan], np.float32), n)
+    spec = gen.GridSpec(37.9, -92.1, 0.01, 0.01, 40, 40, gen.T0_MS, 300_000, 10)
+    g, n_out = oracle_mod.grid_dir(jid, ts, lat, lon, spd, spec, 4, 0.0, heading=hd)
+    groups = {}
+    for i in range(n):
+        ilat = math.floor((lat[i] - spec.lat0_deg) / spec.dlat_deg)
+        ilon = math.floor((lon[i] - spec.lon0_deg) / spec.dlon_deg)
+        tb = (int(ts[i]) - spec.t0_ms) // spec.bin_ms
+        h = float(hd[i])
+        sec = 4 if math.isnan(h) else int(h // 90.0)
+        key = ((tb * 5 + sec) * spec.n_lat + ilat) * spec.n_lon + ilon
+        groups.setdefault(key, []).append(i)
+    assert n_out == 0 and list(g["key"]) == sorted(groups)
+    for j, key in enumerate(sorted(groups)):
+        rows = groups[key]
+        assert g["count"][j] == len(rows)
+        assert g["n_journeys"][j] == len(set(jid[rows].tolist()))
+        assert g["sum_speed"][j] == math.fsum(float(spd[i]) for i in rows)
+        assert g["min_speed"][j] == min(spd[rows]) and g["max_speed"][j] == max(spd[rows])
+
+
+def test_grid_dir_bearing_equals_heading_on_exact_values(oracle_mod):
+    # the derived-bearing form takes a bearing where its flag says so: on
+    # bearings that float32 holds exactly it equals the sensor-heading form
+    r = gen.make_c1(seed=16, n_journeys=20, median=400.0)
+    spec = gen.GRIDS["c1"]
+    rng = np.random.default_rng(6)
+    b = rng.choice(np.array([0.0, 12.5, 89.75, 90.0, 100.25, 200.0, 300.75, 359.5]), r.n)
+    ok = rng.random(r.n) < 0.9
+    flags = np.where(ok, 0x10, 0x04).astype(np.uint8)
+    hd = np.where(ok, b, np.nan).astype(np.float32)
+    for nd, off in ((4, 0.0), (4, 45.0), (8, 22.5)):
+        gb, nb = oracle_mod.grid_dir(*r.columns(), spec, nd, off, bearing=b, flags=flags)
+        gh, nh = oracle_mod.grid_dir(*r.columns(), spec, nd, off, heading=hd)
+        assert nb == nh
+        for f in gb:
+            np.testing.assert_array_equal(gb[f], gh[f], err_msg=f)
+
+
 def test_grid_line_cases(oracle_mod):
     # Alg. 2 reading: floor of the rounded quotient, not Python's exact-quotient //
     spec = gen.GridSpec(36.0, -95.8, 0.005, 0.005, 920, 1340, 0, 300_000, 288)

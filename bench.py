@@ -355,9 +355,10 @@ def main():
         stages[fam] = round(ms / args.steps, 4)
     stages["sort_passes"] = round(pass_ms / args.steps, 4)
 
-    direction = None
+    direction, lattice = None, None
     if not args.no_direction:
-        direction = bench_direction(args, r, grid, pipe, rec, G, dev)
+        direction, gdir = bench_direction(args, r, grid, pipe, rec, G, dev)
+        lattice = bench_lattice(args, grid, {k: v[:G] for k, v in pipe.groups.items()}, gdir, dev)
 
     traffic = None
     tfile = os.path.join(ROOT, "profiles", "radix_pass_c1_traffic.md")
@@ -396,6 +397,7 @@ def main():
         "cpu_baseline": cpu,
         "stages_ms_per_step": stages,
         "direction_lattice": direction,
+        "dense_lattice": lattice,
         "key_bits": key_bits,
         "packed_from_pass": p0,
         "wall_s_timed_region": round(wall, 3),
@@ -443,9 +445,59 @@ def bench_direction(args, r, grid, pipe, rec, G, dev):
     cnt = out["count"][:rd["count"]].to(torch.int64).sum().item()
     assert cnt + rd["n_out_of_grid"] == n, (cnt, rd["n_out_of_grid"], n)
     log(f"direction lattice: {rd['count']} groups, gather {gth / steps:.3f} ms, aggregate {gms / steps:.3f} ms")
-    return {"n_dir": 4, "offset_deg": 0.0, "heading": "sensor column (synthetic whole degrees), gathered",
+    info = {"n_dir": 4, "offset_deg": 0.0, "heading": "sensor column (synthetic whole degrees), gathered",
             "groups": rd["count"], "gather_ms": round(gth / steps, 4), "aggregate_ms": round(gms / steps, 4),
             "steps": steps}
+    return info, {k: v[:rd["count"]] for k, v in out.items()}
+
+
+def bench_lattice(args, grid, groups, gdir, dev):
+    """Dense lattice of every time bin (mean speed and volume channels per
+    sector), its per-channel normalisation, and the group filter, on C1's group
+    tables without and with four sectors.  HIP events around each call."""
+    import torch
+    from paper_2305_07454_amd import cvetl
+    stream = torch.cuda.current_stream()
+    n_t = int(grid.n_t)
+    res = {}
+    for name, g, nd in (("plain", groups, 0), ("four_sectors", gdir, 4)):
+        C = cvetl.lattice_channels(nd)
+        lat = torch.empty((n_t, C, int(grid.n_lat), int(grid.n_lon)), dtype=torch.float32, device=dev)
+        mm = torch.empty(2 * C, dtype=torch.float32, device=dev)
+        nws = cvetl.workspace(cvetl._size(cvetl.lib().cv_lattice_normalize_workspace_size, n_t,
+                                          ctypes.byref(cvetl._spec_struct(grid)), nd), dev)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        dms, nms = 0.0, 0.0
+        steps = 3
+        for i in range(steps + 1):
+            ev[0].record(stream)
+            cvetl.cv_lattice_dense(g, grid, nd, 0, n_t, out=lat)
+            ev[1].record(stream)
+            cvetl.cv_lattice_normalize(lat, grid, nd, minmax=mm, ws=nws)
+            ev[2].record(stream)
+            torch.cuda.synchronize()
+            if i > 0:
+                dms += ev[0].elapsed_time(ev[1])
+                nms += ev[1].elapsed_time(ev[2])
+        nbytes = lat.numel() * 4
+        dms, nms = dms / steps, nms / steps
+        res[name] = {"shape": list(lat.shape), "tensor_gb": round(nbytes / 1e9, 3), "groups": int(g["key"].numel()),
+                     "dense_ms": round(dms, 4), "dense_gbs": round(nbytes / dms / 1e6, 1),
+                     "normalize_ms": round(nms, 4)}
+        log(f"lattice {name}: {res[name]}")
+        del lat
+        torch.cuda.empty_cache()
+    # filter: groups with >= 2 vehicles and mean speed below 10 m/s
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    cvetl.cv_groups_filter(groups, 2, 0.0, 10.0)
+    e0.record(stream)
+    idx, r = cvetl.cv_groups_filter(groups, 2, 0.0, 10.0)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    res["filter"] = {"predicate": "n_journeys >= 2 and 0 <= mean speed <= 10 m/s", "groups": int(groups["key"].numel()),
+                     "kept": r["count"], "ms_incl_result_read": round(e0.elapsed_time(e1), 4)}
+    log(f"filter: {res['filter']}")
+    return res
 
 
 def pass_bytes(p, p0):

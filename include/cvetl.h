@@ -245,6 +245,45 @@ cv_status cv_gather_column(const void* in, const uint32_t* perm, void* out, uint
                            void* stream);
 
 /* ------------------------------------------------------------------------
+ * Dense lattice, normalisation and filter (Methods steps (4)-(6); Table 2's
+ * speed normalisation, volume normalisation and volume filter rows; the
+ * transformed-data output's speed and volume channels per direction and
+ * time bin).
+ *
+ * cv_lattice_dense -- scatter a group table (cv_grid_aggregate or
+ *   cv_grid_aggregate_dir with the same grid and n_dir; n_dir = 0 for the
+ *   lattice without directions) into lattice [device, float32]
+ *   [n_t][C][n_lat][n_lon] for time bins t_first .. t_first + n_t - 1, with
+ *   C = 2 D and D = n_dir + 1 (1 when n_dir = 0): channel 2 d is the mean
+ *   sensor speed of sector d (sum_speed / count, in double, rounded to
+ *   float), channel 2 d + 1 its distinct journeys (the volume).  Cells
+ *   without a group are 0; groups of other time bins are skipped.  The whole
+ *   tensor is written.
+ * cv_lattice_normalize -- in place, per channel over all n_t time bins:
+ *   an occupied cell (volume > 0) becomes (x - min) / (max - min) with min
+ *   and max over the channel's occupied cells (in double, rounded to float;
+ *   0 when max == min); empty cells stay 0.  channel_min_max [device,
+ *   2 C floats] receives each channel's min and max (NaN for a channel with
+ *   no occupied cell).  A workspace of cv_lattice_normalize_workspace_size
+ *   bytes (256-byte aligned) holds per-block partials.
+ * cv_groups_filter -- index [device, uint32] of the groups, in ascending
+ *   order, whose distinct journeys are >= min_volume and whose mean speed
+ *   (sum_speed / count) lies in [speed_lo, speed_hi]; res->count = groups
+ *   kept; more than `capacity` sets CV_ERR_CAPACITY with res->required.  A
+ *   workspace of cv_groups_filter_workspace_size bytes (256-byte aligned).
+ * --------------------------------------------------------------------- */
+cv_status cv_lattice_dense(const cv_groups* groups, uint64_t n_groups, const cv_grid_spec* grid /*[host]*/,
+                           uint32_t n_dir, int64_t t_first, uint64_t n_t, float* lattice, void* stream);
+cv_status cv_lattice_normalize_workspace_size(uint64_t n_t, const cv_grid_spec* grid /*[host]*/, uint32_t n_dir,
+                                              size_t* bytes /*[host]*/);
+cv_status cv_lattice_normalize(float* lattice, uint64_t n_t, const cv_grid_spec* grid /*[host]*/, uint32_t n_dir,
+                               float* channel_min_max, void* ws, size_t ws_bytes, void* stream);
+cv_status cv_groups_filter_workspace_size(uint64_t n_groups, size_t* bytes /*[host]*/);
+cv_status cv_groups_filter(const cv_groups* groups, uint64_t n_groups, double min_volume, double speed_lo,
+                           double speed_hi, uint32_t* index, uint64_t capacity, cv_result* res, void* ws,
+                           size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
  * Batched form: many independent problems ("shards", e.g. county-day files of
  * very uneven size) laid out back to back in one record array and processed
  * by the same launches as one batch.  shard_offsets [device, n_shards + 1]:

@@ -205,3 +205,68 @@ def grid_dir(jid, ts, lat, lon, speed, spec, n_dir, offset=0.0, heading=None, be
                            cap, *[_p(out[k]) for k, _ in GRID_FIELDS], _p(n_out))
     res = {k: v[:G].copy() for k, v in out.items()}
     return res, int(n_out[0])
+
+
+# ---------------------------------------------------------------------------
+# dense lattice, normalisation, filter (plain numpy definitions)
+# ---------------------------------------------------------------------------
+
+def lattice_dense(groups, spec, n_dir, t_first, n_t):
+    """Methods steps (4)-(5) and the transformed-data output: the group table
+    scattered into a dense [n_t][C][n_lat][n_lon] float32 tensor, C = 2 D
+    (D = n_dir + 1 sectors, or 1 without directions).  Channel 2 d: mean
+    sensor speed of sector d (sum / count in double, rounded to float32);
+    channel 2 d + 1: distinct journeys (volume).  Empty cells are 0."""
+    D = n_dir + 1 if n_dir else 1
+    n_lat, n_lon = int(spec.n_lat), int(spec.n_lon)
+    cells = n_lat * n_lon
+    out = np.zeros((n_t, 2 * D, n_lat, n_lon), dtype=np.float32)
+    key = np.asarray(groups["key"], dtype=np.int64)
+    td, cell = key // cells, key % cells
+    tb, d = td // D, td % D
+    t = tb - t_first
+    m = (key >= 0) & (t >= 0) & (t < n_t)
+    cnt = np.asarray(groups["count"], dtype=np.float64)[m]
+    mean = np.where(cnt > 0, np.asarray(groups["sum_speed"], dtype=np.float64)[m] / np.where(cnt > 0, cnt, 1.0), 0.0)
+    iy, ix = cell[m] // n_lon, cell[m] % n_lon
+    out[t[m], 2 * d[m], iy, ix] = mean.astype(np.float32)
+    out[t[m], 2 * d[m] + 1, iy, ix] = np.asarray(groups["n_journeys"], dtype=np.float64)[m].astype(np.float32)
+    return out
+
+
+def lattice_normalize(lat):
+    """Table 2's normalisation rows, read as min-max per channel over all time
+    bins: an occupied cell (its sector's volume > 0) becomes
+    (x - min) / (max - min) over that channel's occupied cells (double,
+    rounded to float32; 0 when max == min); empty cells stay 0.  Returns the
+    new tensor and the [C][2] min / max (NaN for a channel with no occupied
+    cell)."""
+    out = lat.copy()
+    C = lat.shape[1]
+    mm = np.full((C, 2), np.nan, dtype=np.float32)
+    for c0 in range(0, C, 2):
+        occ = lat[:, c0 + 1] > 0
+        for c in (c0, c0 + 1):
+            x = lat[:, c][occ]
+            if x.size == 0:
+                continue
+            mn, mx = x.min(), x.max()
+            mm[c] = (mn, mx)
+            if mx > mn:
+                y = ((x.astype(np.float64) - np.float64(mn)) / (np.float64(mx) - np.float64(mn))).astype(np.float32)
+            else:
+                y = np.zeros_like(x)
+            ch = out[:, c]
+            ch[occ] = y
+    return out, mm
+
+
+def groups_filter(groups, min_volume, speed_lo, speed_hi):
+    """Table 2's filter row, read as a predicate over groups: ascending indices
+    of the groups with distinct journeys >= min_volume and mean speed
+    (sum / count) in [speed_lo, speed_hi]."""
+    cnt = np.asarray(groups["count"], dtype=np.float64)
+    nj = np.asarray(groups["n_journeys"], dtype=np.float64)
+    mean = np.asarray(groups["sum_speed"], dtype=np.float64) / np.where(cnt > 0, cnt, 1.0)
+    keep = (cnt > 0) & (nj >= min_volume) & (mean >= speed_lo) & (mean <= speed_hi)
+    return np.flatnonzero(keep).astype(np.int64)

@@ -148,6 +148,18 @@ def lib():
         L.cv_grid_aggregate_dir.restype = S
         L.cv_gather_column.argtypes = [P, P, P, U64, U32, P]
         L.cv_gather_column.restype = S
+        L.cv_lattice_dense.argtypes = [ctypes.POINTER(CvGroups), U64, ctypes.POINTER(CvGridSpec), U32,
+                                       ctypes.c_int64, U64, P, P]
+        L.cv_lattice_dense.restype = S
+        L.cv_lattice_normalize_workspace_size.argtypes = [U64, ctypes.POINTER(CvGridSpec), U32, SZ]
+        L.cv_lattice_normalize_workspace_size.restype = S
+        L.cv_lattice_normalize.argtypes = [P, U64, ctypes.POINTER(CvGridSpec), U32, P, P, ctypes.c_size_t, P]
+        L.cv_lattice_normalize.restype = S
+        L.cv_groups_filter_workspace_size.argtypes = [U64, SZ]
+        L.cv_groups_filter_workspace_size.restype = S
+        L.cv_groups_filter.argtypes = [ctypes.POINTER(CvGroups), U64, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_double, P, U64, P, P, ctypes.c_size_t, P]
+        L.cv_groups_filter.restype = S
         L.cv_tuning_set.argtypes = [ctypes.c_char_p, ctypes.c_int64]
         L.cv_tuning_set.restype = S
         L.cv_tuning_get.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64)]
@@ -357,6 +369,61 @@ def cv_gather_column(col, perm, stream=None, out=None):
     _check(lib().cv_gather_column(_ptr(col), _ptr(perm), _ptr(out), n, col.element_size(), _stream(stream)),
            "cv_gather_column")
     return out
+
+
+def _groups_struct(groups):
+    return CvGroups(*(_ptr(groups.get(k)) for k, _ in GROUP_FIELDS))
+
+
+def lattice_channels(n_dir):
+    return 2 * (n_dir + 1 if n_dir else 1)
+
+
+def cv_lattice_dense(groups, grid, n_dir=0, t_first=0, n_t=None, out=None, stream=None):
+    """Dense [n_t][C][n_lat][n_lon] float32 lattice of a group table."""
+    G = int(groups["key"].numel())
+    dev = groups["key"].device
+    n_t = int(n_t if n_t is not None else grid.n_t)
+    C = lattice_channels(n_dir)
+    if out is None:
+        out = torch.empty((n_t, C, int(grid.n_lat), int(grid.n_lon)), dtype=torch.float32, device=dev)
+    gs = _groups_struct(groups)
+    _check(lib().cv_lattice_dense(ctypes.byref(gs), G, ctypes.byref(_spec_struct(grid)), int(n_dir), int(t_first),
+                                  n_t, _ptr(out), _stream(stream)), "cv_lattice_dense")
+    return out
+
+
+def cv_lattice_normalize(lattice, grid, n_dir=0, stream=None, minmax=None, ws=None):
+    """In-place per-channel min-max normalisation; returns (lattice, [C][2] min/max)."""
+    L = lib()
+    C = lattice_channels(n_dir)
+    n_t = int(lattice.shape[0])
+    spec = _spec_struct(grid)
+    if minmax is None:
+        minmax = torch.empty(2 * C, dtype=torch.float32, device=lattice.device)
+    need = _size(L.cv_lattice_normalize_workspace_size, n_t, ctypes.byref(spec), int(n_dir))
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, lattice.device)
+    _check(L.cv_lattice_normalize(_ptr(lattice), n_t, ctypes.byref(spec), int(n_dir), _ptr(minmax), _ptr(ws),
+                                  ws.numel(), _stream(stream)), "cv_lattice_normalize")
+    return lattice, minmax.view(C, 2)
+
+
+def cv_groups_filter(groups, min_volume, speed_lo, speed_hi, capacity=None, stream=None):
+    """Indices (ascending) of the groups kept by the volume and mean-speed filter."""
+    L = lib()
+    G = int(groups["count"].numel())
+    dev = groups["count"].device
+    cap = int(capacity) if capacity is not None else max(1, G)
+    idx = torch.empty(cap, dtype=torch.int32, device=dev)
+    ws = workspace(_size(L.cv_groups_filter_workspace_size, G), dev)
+    res = new_result(dev)
+    gs = _groups_struct(groups)
+    _check(L.cv_groups_filter(ctypes.byref(gs), G, float(min_volume), float(speed_lo), float(speed_hi), _ptr(idx),
+                              cap, _ptr(res), _ptr(ws), ws.numel(), _stream(stream)), "cv_groups_filter")
+    r = read_result(res)
+    _check(r["status"], "cv_groups_filter (device)")
+    return idx[:r["count"]], r
 
 
 # ---------------------------------------------------------------------------

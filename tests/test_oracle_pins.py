@@ -469,6 +469,60 @@ def test_grid_dir_bearing_equals_heading_on_exact_values(oracle_mod):
             np.testing.assert_array_equal(gb[f], gh[f], err_msg=f)
 
 
+def _groups(rows):
+    """Group table from (key, count, n_journeys, sum_speed) rows."""
+    k, c, j, sm = zip(*rows)
+    return {"key": np.array(k, np.int64), "count": np.array(c, np.uint32), "n_journeys": np.array(j, np.uint32),
+            "sum_speed": np.array(sm, np.float64)}
+
+
+def test_lattice_dense_by_hand(oracle_mod):
+    spec = gen.GridSpec(0.0, 0.0, 1.0, 1.0, 2, 3, 0, 60_000, 10)   # 2 x 3 cells
+    # (tbin 1, ilat 1, ilon 2): key (1*2+1)*3+2 = 11; (tbin 0, 0, 0): key 0; tbin 5: outside t in [0, 3)
+    g = _groups([(0, 2, 1, 3.0), (11, 4, 2, 10.0), ((5 * 2 + 1) * 3 + 1, 1, 1, 7.0)])
+    out = oracle_mod.lattice_dense(g, spec, 0, 0, 3)
+    want = np.zeros((3, 2, 2, 3), np.float32)
+    want[0, 0, 0, 0], want[0, 1, 0, 0] = 1.5, 1.0
+    want[1, 0, 1, 2], want[1, 1, 1, 2] = 2.5, 2.0
+    np.testing.assert_array_equal(out, want)
+    # t_first moves the window: tbin 1 is the first image
+    out = oracle_mod.lattice_dense(g, spec, 0, 1, 5)
+    assert out[0, 0, 1, 2] == 2.5 and out[4, 0, 1, 1] == 7.0 and out.sum() == 2.5 + 2.0 + 7.0 + 1.0
+    # four sectors (D = 5): key ((tbin * 5 + sector) * 2 + ilat) * 3 + ilon
+    g = _groups([(((2 * 5 + 3) * 2 + 0) * 3 + 1, 3, 3, 9.0), (((0 * 5 + 4) * 2 + 1) * 3 + 0, 1, 1, 0.5)])
+    out = oracle_mod.lattice_dense(g, spec, 4, 0, 3)
+    assert out.shape == (3, 10, 2, 3)
+    assert out[2, 6, 0, 1] == 3.0 and out[2, 7, 0, 1] == 3.0       # sector 3: speed 9/3, volume 3
+    assert out[0, 8, 1, 0] == 0.5 and out[0, 9, 1, 0] == 1.0       # sector 4 (no direction)
+    assert np.count_nonzero(out) == 4
+
+
+def test_lattice_normalize_by_hand(oracle_mod):
+    lat = np.zeros((2, 4, 1, 3), np.float32)
+    # channels 0/1: speeds 2.5, 5, 10 with volumes 1, 1, 3 (cell (t=1, x=2) empty)
+    lat[0, 0, 0, :], lat[0, 1, 0, :] = (2.5, 5.0, 10.0), (1, 1, 3)
+    # channels 2/3: one occupied cell (constant channel), its speed 0
+    lat[1, 3, 0, 1] = 4.0
+    out, mm = oracle_mod.lattice_normalize(lat)
+    np.testing.assert_array_equal(out[0, 0, 0], np.array([0.0, 1.0 / 3.0, 1.0], np.float32))
+    np.testing.assert_array_equal(out[0, 1, 0], np.array([0.0, 0.0, 1.0], np.float32))
+    assert np.all(out[1, :2] == 0) and np.all(out[:, 2:] == 0)
+    np.testing.assert_array_equal(mm[:2], np.array([[2.5, 10.0], [1.0, 3.0]], np.float32))
+    np.testing.assert_array_equal(mm[2:], np.array([[0.0, 0.0], [4.0, 4.0]], np.float32))
+    # a channel pair with no occupied cell: NaN bounds
+    out, mm = oracle_mod.lattice_normalize(np.zeros((1, 2, 1, 1), np.float32))
+    assert np.all(np.isnan(mm)) and np.all(out == 0)
+
+
+def test_groups_filter_by_hand(oracle_mod):
+    g = _groups([(0, 4, 2, 40.0), (1, 2, 1, 10.0), (2, 5, 5, 5.0), (3, 0, 0, 0.0), (4, 1, 3, 30.0)])
+    # mean speeds 10, 5, 1, -, 30; volumes 2, 1, 5, 0, 3
+    assert oracle_mod.groups_filter(g, 2, 0.0, 15.0).tolist() == [0, 2]
+    assert oracle_mod.groups_filter(g, 1, 5.0, 10.0).tolist() == [0, 1]
+    assert oracle_mod.groups_filter(g, 0, -1.0, 1e9).tolist() == [0, 1, 2, 4]
+    assert oracle_mod.groups_filter(g, 6, -1.0, 1e9).tolist() == []
+
+
 def test_grid_line_cases(oracle_mod):
     # Alg. 2 reading: floor of the rounded quotient, not Python's exact-quotient //
     spec = gen.GridSpec(36.0, -95.8, 0.005, 0.005, 920, 1340, 0, 300_000, 288)

@@ -359,6 +359,7 @@ def main():
     if not args.no_direction:
         direction, gdir = bench_direction(args, r, grid, pipe, rec, G, dev)
         lattice = bench_lattice(args, grid, {k: v[:G] for k, v in pipe.groups.items()}, gdir, dev)
+        lattice["hygiene"] = bench_hygiene(pipe, n, dev)
 
     traffic = None
     tfile = os.path.join(ROOT, "profiles", "radix_pass_c1_traffic.md")
@@ -498,6 +499,28 @@ def bench_lattice(args, grid, groups, gdir, dev):
                      "kept": r["count"], "ms_incl_result_read": round(e0.elapsed_time(e1), 4)}
     log(f"filter: {res['filter']}")
     return res
+
+
+def bench_hygiene(pipe, n, dev):
+    """Dropping exact duplicate rows and splitting trips at 60 s gaps, on the
+    sorted records of the main run (HIP events around each call)."""
+    import torch
+    from paper_2305_07454_amd import cvetl
+    srt = {k: v[:n] for k, v in pipe.sorted.items()}
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    cvetl.cv_drop_duplicates(srt, pipe.perm[:n])
+    cvetl.cv_split_trips(srt, 60_000)
+    ev[0].record(stream)
+    _, _, rd = cvetl.cv_drop_duplicates(srt, pipe.perm[:n])
+    ev[1].record(stream)
+    _, _, rt = cvetl.cv_split_trips(srt, 60_000)
+    ev[2].record(stream)
+    torch.cuda.synchronize()
+    out = {"kept_records": rd["count"], "drop_duplicates_ms_incl_alloc": round(ev[0].elapsed_time(ev[1]), 4),
+           "trips_60s": rt["count"], "split_trips_ms_incl_alloc": round(ev[1].elapsed_time(ev[2]), 4)}
+    log(f"hygiene: {out}")
+    return out
 
 
 def pass_bytes(p, p0):

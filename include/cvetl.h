@@ -284,6 +284,31 @@ cv_status cv_groups_filter(const cv_groups* groups, uint64_t n_groups, double mi
                            size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Record hygiene (optional passes on sorted records; both change what the
+ * later calls see, so they are opt-in).  Workspace: cv_hygiene_workspace_size
+ * bytes (256-byte aligned).
+ *
+ * cv_drop_duplicates -- keep a sorted record unless an earlier record of the
+ *   same (journey_id, ts_ms) has bit-identical lat_deg, lon_deg and
+ *   speed_mps (an exact duplicate row, as Table 1's first and fourth rows):
+ *   the kept records, in order, to `out` [device, capacity n]; perm_out
+ *   [device, nullable] receives perm [device] of the kept ones (the input
+ *   positions).  res->count = records kept.
+ * cv_split_trips -- trips of sorted records: a trip starts at a journey's
+ *   first record and at a record more than gap_ms (>= 0) after the one
+ *   before.  trip_id [device, n] receives each record's trip number (0, 1,
+ *   ... in record order, so it can serve as journey_id of the later calls);
+ *   trip_journey [device, capacity] the journey id of each trip.
+ *   res->count = trips; more than capacity sets CV_ERR_CAPACITY with
+ *   res->required (trip_id is complete either way).
+ * --------------------------------------------------------------------- */
+cv_status cv_hygiene_workspace_size(uint64_t n, size_t* bytes /*[host]*/);
+cv_status cv_drop_duplicates(const cv_records* sorted, const uint32_t* perm, const cv_records_out* out,
+                             uint32_t* perm_out, cv_result* res, void* ws, size_t ws_bytes, void* stream);
+cv_status cv_split_trips(const cv_records* sorted, int64_t gap_ms, int64_t* trip_id, int64_t* trip_journey,
+                         uint64_t capacity, cv_result* res, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
  * Batched form: many independent problems ("shards", e.g. county-day files of
  * very uneven size) laid out back to back in one record array and processed
  * by the same launches as one batch.  shard_offsets [device, n_shards + 1]:

@@ -270,3 +270,40 @@ def groups_filter(groups, min_volume, speed_lo, speed_hi):
     mean = np.asarray(groups["sum_speed"], dtype=np.float64) / np.where(cnt > 0, cnt, 1.0)
     keep = (cnt > 0) & (nj >= min_volume) & (mean >= speed_lo) & (mean <= speed_hi)
     return np.flatnonzero(keep).astype(np.int64)
+
+
+# ---------------------------------------------------------------------------
+# record hygiene (plain Python definitions)
+# ---------------------------------------------------------------------------
+
+def drop_duplicates(sorted_cols):
+    """Exact duplicate rows (Table 1's first and fourth rows are one): in
+    (journey, time)-sorted records, a record is dropped when an earlier record
+    of the same (journey id, time stamp) has bit-identical latitude, longitude
+    and speed.  Returns the sorted positions of the records kept."""
+    jid, ts, lat, lon, spd = sorted_cols
+    la = np.ascontiguousarray(lat, dtype=np.float64).view(np.uint64)
+    lo = np.ascontiguousarray(lon, dtype=np.float64).view(np.uint64)
+    sp = np.ascontiguousarray(spd, dtype=np.float32).view(np.uint32)
+    keep = []
+    seen = set()
+    for k in range(len(jid)):
+        if k == 0 or jid[k] != jid[k - 1] or ts[k] != ts[k - 1]:
+            seen = set()
+        row = (int(la[k]), int(lo[k]), int(sp[k]))
+        if row not in seen:
+            keep.append(k)
+            seen.add(row)
+    return np.array(keep, dtype=np.int64)
+
+
+def split_trips(jid, ts, gap_ms):
+    """Trips of (journey, time)-sorted records: a new trip at a journey's first
+    record and after a time gap of more than gap_ms.  Returns (trip number of
+    every record, journey id of every trip)."""
+    n = len(jid)
+    start = np.zeros(n, dtype=bool)
+    for k in range(n):
+        start[k] = k == 0 or jid[k] != jid[k - 1] or int(ts[k]) - int(ts[k - 1]) > gap_ms
+    trip = np.cumsum(start) - 1
+    return trip.astype(np.int64), np.asarray(jid, dtype=np.int64)[start]

@@ -160,6 +160,13 @@ def lib():
         L.cv_groups_filter.argtypes = [ctypes.POINTER(CvGroups), U64, ctypes.c_double, ctypes.c_double,
                                        ctypes.c_double, P, U64, P, P, ctypes.c_size_t, P]
         L.cv_groups_filter.restype = S
+        L.cv_hygiene_workspace_size.argtypes = [U64, SZ]
+        L.cv_hygiene_workspace_size.restype = S
+        L.cv_drop_duplicates.argtypes = [ctypes.POINTER(CvRecords), P, ctypes.POINTER(CvRecordsOut), P, P, P,
+                                         ctypes.c_size_t, P]
+        L.cv_drop_duplicates.restype = S
+        L.cv_split_trips.argtypes = [ctypes.POINTER(CvRecords), ctypes.c_int64, P, P, U64, P, P, ctypes.c_size_t, P]
+        L.cv_split_trips.restype = S
         L.cv_tuning_set.argtypes = [ctypes.c_char_p, ctypes.c_int64]
         L.cv_tuning_set.restype = S
         L.cv_tuning_get.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64)]
@@ -424,6 +431,41 @@ def cv_groups_filter(groups, min_volume, speed_lo, speed_hi, capacity=None, stre
     r = read_result(res)
     _check(r["status"], "cv_groups_filter (device)")
     return idx[:r["count"]], r
+
+
+def cv_drop_duplicates(sorted_rec, perm=None, stream=None):
+    """Sorted records without exact duplicate rows; returns (records, perm of the kept, result)."""
+    L = lib()
+    n = int(sorted_rec["journey_id"].numel())
+    dev = sorted_rec["journey_id"].device
+    out = empty_records(n, dev)
+    po = torch.empty(n, dtype=torch.int32, device=dev) if perm is not None else None
+    ws = workspace(_size(L.cv_hygiene_workspace_size, n), dev)
+    res = new_result(dev)
+    oo = CvRecordsOut(*(_ptr(out[k]) for k, _ in RECORD_FIELDS))
+    _check(L.cv_drop_duplicates(ctypes.byref(_records_struct(sorted_rec)), _ptr(perm), ctypes.byref(oo), _ptr(po),
+                                _ptr(res), _ptr(ws), ws.numel(), _stream(stream)), "cv_drop_duplicates")
+    r = read_result(res)
+    _check(r["status"], "cv_drop_duplicates (device)")
+    m = r["count"]
+    return {k: v[:m] for k, v in out.items()}, (po[:m] if po is not None else None), r
+
+
+def cv_split_trips(sorted_rec, gap_ms, capacity=None, stream=None):
+    """Trip number per sorted record and journey id per trip; returns (trip_id, trip_journey, result)."""
+    L = lib()
+    n = int(sorted_rec["journey_id"].numel())
+    dev = sorted_rec["journey_id"].device
+    cap = int(capacity) if capacity is not None else max(1, n)
+    tid = torch.empty(max(1, n), dtype=torch.int64, device=dev)
+    tj = torch.empty(cap, dtype=torch.int64, device=dev)
+    ws = workspace(_size(L.cv_hygiene_workspace_size, n), dev)
+    res = new_result(dev)
+    _check(L.cv_split_trips(ctypes.byref(_records_struct(sorted_rec)), int(gap_ms), _ptr(tid), _ptr(tj), cap,
+                            _ptr(res), _ptr(ws), ws.numel(), _stream(stream)), "cv_split_trips")
+    r = read_result(res)
+    _check(r["status"], "cv_split_trips (device)")
+    return tid[:n], tj[:r["count"]], r
 
 
 # ---------------------------------------------------------------------------

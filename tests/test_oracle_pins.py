@@ -523,6 +523,38 @@ def test_groups_filter_by_hand(oracle_mod):
     assert oracle_mod.groups_filter(g, 6, -1.0, 1e9).tolist() == []
 
 
+def test_drop_duplicates_table1_and_by_hand(oracle_mod):
+    # Table 1's fourth row repeats its first: after the sort they are adjacent
+    # (same journey and time) and the later one (input row 3) goes
+    cols = _table1()
+    perm = oracle_mod.sort(cols[0], cols[1])
+    s = oracle_mod.sorted_records(cols, perm)
+    keep = oracle_mod.drop_duplicates(s)
+    assert sorted(perm[keep].tolist()) == [0, 1, 2]
+    # same journey and time: a different latitude is kept, an identical row
+    # is not; the same row in another journey is kept; -0.0 and 0.0 differ in
+    # their bits (kept)
+    jid = np.array([1, 1, 1, 1, 2, 2, 2], np.int64)
+    ts = np.array([5, 5, 5, 6, 5, 5, 5], np.int64)
+    lat = np.array([1.0, 1.5, 1.0, 1.0, 1.0, 0.0, -0.0])
+    lon = np.full(7, 2.0)
+    spd = np.array([3, 3, 3, 3, 3, 3, 3], np.float32)
+    assert oracle_mod.drop_duplicates((jid, ts, lat, lon, spd)).tolist() == [0, 1, 3, 4, 5, 6]
+    spd[2] = 3.5  # the third row now differs in speed
+    assert oracle_mod.drop_duplicates((jid, ts, lat, lon, spd)).tolist() == [0, 1, 2, 3, 4, 5, 6]
+
+
+def test_split_trips_by_hand(oracle_mod):
+    jid = np.array([1, 1, 1, 1, 2, 2, 3], np.int64)
+    ts = np.array([0, 100, 200, 301, 0, 1000, 7], np.int64)
+    trip, tj = oracle_mod.split_trips(jid, ts, 100)     # a gap of exactly 100 stays, 101 splits
+    assert trip.tolist() == [0, 0, 0, 1, 2, 3, 4] and tj.tolist() == [1, 1, 2, 2, 3]
+    trip, tj = oracle_mod.split_trips(jid, ts, 10**6)   # no gap large enough: trips are journeys
+    assert trip.tolist() == [0, 0, 0, 0, 1, 1, 2] and tj.tolist() == [1, 2, 3]
+    trip, tj = oracle_mod.split_trips(jid, ts, 0)       # every increase splits
+    assert trip.tolist() == [0, 1, 2, 3, 4, 5, 6]
+
+
 def test_grid_line_cases(oracle_mod):
     # Alg. 2 reading: floor of the rounded quotient, not Python's exact-quotient //
     spec = gen.GridSpec(36.0, -95.8, 0.005, 0.005, 920, 1340, 0, 300_000, 288)

@@ -360,6 +360,7 @@ def main():
         direction, gdir = bench_direction(args, r, grid, pipe, rec, G, dev)
         lattice = bench_lattice(args, grid, {k: v[:G] for k, v in pipe.groups.items()}, gdir, dev)
         lattice["hygiene"] = bench_hygiene(pipe, n, dev)
+        lattice["csv_extract"] = bench_csv(r, dev)
 
     traffic = None
     tfile = os.path.join(ROOT, "profiles", "radix_pass_c1_traffic.md")
@@ -521,6 +522,37 @@ def bench_hygiene(pipe, n, dev):
            "trips_60s": rt["count"], "split_trips_ms_incl_alloc": round(ev[1].elapsed_time(ev[2]), 4)}
     log(f"hygiene: {out}")
     return out
+
+
+def bench_csv(r, dev, rows=4_000_000):
+    """Extraction of Table-1-shaped text (fixed-width rows of the first
+    `rows` C1 records, written by gen.to_csv) into record columns."""
+    import numpy as np
+    import torch
+    from paper_2305_07454_amd import cvetl, gen
+    m = min(rows, r.n)
+    cols = tuple(c[:m] for c in r.columns())
+    t0 = time.time()
+    text = gen.to_csv(cols, gen.headings(np.random.default_rng(5), cols[0]))
+    dt = torch.from_numpy(np.frombuffer(text, dtype=np.uint8).copy()).to(dev)
+    log(f"csv sample: {m} rows, {len(text) / 1e6:.1f} MB generated in {time.time() - t0:.1f}s")
+    out, hd, ok, res = cvetl.cv_csv_extract(dt, capacity=m)
+    ws = cvetl.workspace(cvetl._size(cvetl.lib().cv_csv_workspace_size, len(text), m), dev)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    steps = 5
+    e0.record(stream)
+    for _ in range(steps):
+        cvetl.cv_csv_extract(dt, capacity=m, out=out, heading=hd, row_ok=ok, ws=ws, sync=False)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    r2 = cvetl.cv_csv_extract(dt, capacity=m, out=out, heading=hd, row_ok=ok, ws=ws)[3]
+    assert r2["count"] == m and r2["n_bad"] == 0, r2
+    info = {"rows": m, "text_mb": round(len(text) / 1e6, 1), "ms": round(ms, 4),
+            "text_gbs": round(len(text) / ms / 1e6, 1), "mrows_per_s": round(m / ms / 1e3, 1)}
+    log(f"csv: {info}")
+    return info
 
 
 def pass_bytes(p, p0):

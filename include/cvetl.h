@@ -143,7 +143,7 @@ typedef struct {
     uint64_t key_bits;      /* bits of the packed sort key (sort call)          */
     uint64_t packed_pass;   /* sort call: first radix pass that moves one word
                                (key high digits | record index) per record    */
-    uint64_t reserved;
+    uint64_t n_bad;         /* csv call: malformed rows (else 0)                */
 } cv_result;
 
 uint32_t cv_abi_version(void);
@@ -307,6 +307,35 @@ cv_status cv_drop_duplicates(const cv_records* sorted, const uint32_t* perm, con
                              uint32_t* perm_out, cv_result* res, void* ws, size_t ws_bytes, void* stream);
 cv_status cv_split_trips(const cv_records* sorted, int64_t gap_ms, int64_t* trip_id, int64_t* trip_journey,
                          uint64_t capacity, cv_result* res, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * cv_csv_extract -- the extraction ahead of the key prep: text rows shaped
+ * as Table 1 (journey id, timestamp, latitude, longitude, postal code,
+ * speed, heading; comma-separated, one row per line, LF or CRLF) into
+ * record columns, in row order.  text [device, 16-byte aligned, nbytes];
+ * has_header skips the first line.  Fields:
+ *   journey id   1..8 bytes below 0x80, packed big-endian into int64 (so
+ *                string order is integer order)
+ *   timestamp    "YYYY-MM-DD HH:MM:SS" (proleptic Gregorian, UTC) with an
+ *                optional fraction of 1-3 digits -> ms since 1970-01-01
+ *   lat, lon     plain decimals ([-+]digits[.digits]) whose significant
+ *                digits form an integer below 2^53 and with at most 22
+ *                fraction digits -> the double nearest the decimal
+ *   postal code  skipped
+ *   speed        plain decimal as above -> double -> float32
+ *   heading      empty (NaN) or a plain decimal -> float32 (heading_deg,
+ *                [device, nullable])
+ * A row with another shape (field count, quotes, an invalid date, a
+ * decimal outside the forms above) is malformed: its columns are 0 / NaN,
+ * row_ok[r] = 0 (nullable), and res->n_bad counts it.  res->count = rows
+ * (header excluded); rows past `capacity` are counted, not written
+ * (CV_ERR_CAPACITY with res->required).  Workspace:
+ * cv_csv_workspace_size(nbytes, capacity) bytes, 256-byte aligned.
+ * --------------------------------------------------------------------- */
+cv_status cv_csv_workspace_size(uint64_t nbytes, uint64_t capacity, size_t* bytes /*[host]*/);
+cv_status cv_csv_extract(const char* text, uint64_t nbytes, int32_t has_header, const cv_records_out* out,
+                         float* heading_deg, uint8_t* row_ok, uint64_t capacity, cv_result* res, void* ws,
+                         size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
  * Batched form: many independent problems ("shards", e.g. county-day files of

@@ -307,3 +307,84 @@ def split_trips(jid, ts, gap_ms):
         start[k] = k == 0 or jid[k] != jid[k - 1] or int(ts[k]) - int(ts[k - 1]) > gap_ms
     trip = np.cumsum(start) - 1
     return trip.astype(np.int64), np.asarray(jid, dtype=np.int64)[start]
+
+
+# ---------------------------------------------------------------------------
+# text extraction (plain Python definition of the accepted row shape)
+# ---------------------------------------------------------------------------
+
+import calendar as _calendar
+import datetime as _datetime
+import re as _re
+
+_DEC = _re.compile(rb"^[-+]?([0-9]+\.?[0-9]*|\.[0-9]+)$")
+_TS = _re.compile(rb"^([0-9]{4})-([0-9]{2})-([0-9]{2}) ([0-9]{2}):([0-9]{2}):([0-9]{2})(\.([0-9]{1,3}))?$")
+
+
+def _decimal(b):
+    """A plain decimal whose significant digits form an integer below 2^53,
+    with at most 22 fraction digits: the double nearest to it; else None."""
+    if not _DEC.match(b):
+        return None
+    body = b.lstrip(b"+-")
+    ip, _, fp = body.partition(b".")
+    if int((ip + fp) or b"0") >= 1 << 53 or len(fp) > 22:
+        return None
+    return float(b)
+
+
+def _timestamp(b):
+    m = _TS.match(b)
+    if not m:
+        return None
+    y, mo, d, h, mi, se = (int(m.group(i)) for i in range(1, 7))
+    try:
+        _datetime.datetime(y, mo, d, h, mi, se)
+    except ValueError:
+        return None
+    frac = m.group(8) or b""
+    ms = int(frac.ljust(3, b"0")) if frac else 0
+    return _calendar.timegm((y, mo, d, h, mi, se, 0, 0, 0)) * 1000 + ms
+
+
+def csv_extract(text, has_header=True):
+    """Table 1's row shape: journey id (1-8 bytes below 0x80, packed
+    big-endian into an int64), timestamp (UTC, optional 1-3 fraction digits,
+    in ms), latitude and longitude (doubles), postal code (skipped), speed
+    (double rounded to float32), heading (empty -> NaN, else float32).  Lines
+    end at LF (a trailing CR is dropped); a last line without LF counts.
+    Returns the five record columns, heading, and row_ok (1 for a row of
+    that shape; 0 with zero / NaN columns otherwise)."""
+    lines = text.split(b"\n")
+    if text.endswith(b"\n"):
+        lines = lines[:-1]
+    if not text:
+        lines = []
+    if has_header and lines:
+        lines = lines[1:]
+    n = len(lines)
+    jid = np.zeros(n, np.int64)
+    ts = np.zeros(n, np.int64)
+    lat = np.full(n, np.nan)
+    lon = np.full(n, np.nan)
+    spd = np.full(n, np.nan, np.float32)
+    hd = np.full(n, np.nan, np.float32)
+    ok = np.zeros(n, np.uint8)
+    for r, line in enumerate(lines):
+        if line.endswith(b"\r"):
+            line = line[:-1]
+        f = line.split(b",")
+        if len(f) != 7 or b'"' in line:
+            continue
+        if not (1 <= len(f[0]) <= 8) or any(c >= 0x80 for c in f[0]):
+            continue
+        t = _timestamp(f[1])
+        la, lo, sp = _decimal(f[2]), _decimal(f[3]), _decimal(f[5])
+        h = _decimal(f[6]) if f[6] else float("nan")
+        if t is None or la is None or lo is None or sp is None or h is None:
+            continue
+        jid[r] = int.from_bytes(f[0].ljust(8, b"\x00"), "big")
+        ts[r], lat[r], lon[r] = t, la, lo
+        spd[r], hd[r] = np.float32(sp), np.float32(h)
+        ok[r] = 1
+    return (jid, ts, lat, lon, spd), hd, ok

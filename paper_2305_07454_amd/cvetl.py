@@ -75,7 +75,7 @@ class CvGroups(ctypes.Structure):
 
 RESULT_DTYPE = np.dtype([("status", "<u4"), ("flags", "<u4"), ("count", "<u8"), ("required", "<u8"),
                          ("n_out_of_grid", "<u8"), ("n_late", "<u8"), ("key_bits", "<u8"),
-                         ("packed_pass", "<u8"), ("reserved", "<u8")])
+                         ("packed_pass", "<u8"), ("n_bad", "<u8")])
 assert RESULT_DTYPE.itemsize == 64
 
 
@@ -167,6 +167,11 @@ def lib():
         L.cv_drop_duplicates.restype = S
         L.cv_split_trips.argtypes = [ctypes.POINTER(CvRecords), ctypes.c_int64, P, P, U64, P, P, ctypes.c_size_t, P]
         L.cv_split_trips.restype = S
+        L.cv_csv_workspace_size.argtypes = [U64, U64, SZ]
+        L.cv_csv_workspace_size.restype = S
+        L.cv_csv_extract.argtypes = [P, U64, ctypes.c_int32, ctypes.POINTER(CvRecordsOut), P, P, U64, P, P,
+                                     ctypes.c_size_t, P]
+        L.cv_csv_extract.restype = S
         L.cv_tuning_set.argtypes = [ctypes.c_char_p, ctypes.c_int64]
         L.cv_tuning_set.restype = S
         L.cv_tuning_get.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64)]
@@ -221,7 +226,7 @@ def new_result(device="cuda"):
 def read_result(res) -> dict:
     a = np.frombuffer(res.cpu().numpy().tobytes(), dtype=RESULT_DTYPE)[0]
     return {k: int(a[k]) for k in ("status", "flags", "count", "required", "n_out_of_grid", "n_late", "key_bits",
-                                         "packed_pass")}
+                                         "packed_pass", "n_bad")}
 
 
 def workspace(nbytes, device="cuda"):
@@ -466,6 +471,36 @@ def cv_split_trips(sorted_rec, gap_ms, capacity=None, stream=None):
     r = read_result(res)
     _check(r["status"], "cv_split_trips (device)")
     return tid[:n], tj[:r["count"]], r
+
+
+def cv_csv_extract(text, has_header=True, capacity=None, stream=None, out=None, heading=None, row_ok=None,
+                   ws=None, sync=True):
+    """Table-1-shaped CSV text (a uint8 device tensor) -> (records, heading, row_ok, result)."""
+    L = lib()
+    nbytes = int(text.numel())
+    dev = text.device
+    cap = int(capacity) if capacity is not None else max(1, nbytes // 32 + 1)
+    if out is None:
+        out = empty_records(cap, dev)
+    if heading is None:
+        heading = torch.empty(cap, dtype=torch.float32, device=dev)
+    if row_ok is None:
+        row_ok = torch.empty(cap, dtype=torch.uint8, device=dev)
+    need = _size(L.cv_csv_workspace_size, nbytes, cap)
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, dev)
+    res = new_result(dev)
+    oo = CvRecordsOut(*(_ptr(out[k]) for k, _ in RECORD_FIELDS))
+    _check(L.cv_csv_extract(_ptr(text), nbytes, 1 if has_header else 0, ctypes.byref(oo), _ptr(heading),
+                            _ptr(row_ok), cap, _ptr(res), _ptr(ws), ws.numel(), _stream(stream)), "cv_csv_extract")
+    if not sync:
+        return out, heading, row_ok, res
+    r = read_result(res)
+    if r["status"] == CV_ERR_CAPACITY and capacity is None:
+        return cv_csv_extract(text, has_header, capacity=r["required"], stream=stream)
+    _check(r["status"], "cv_csv_extract (device)")
+    m = r["count"]
+    return {k: v[:m] for k, v in out.items()}, heading[:m], row_ok[:m], r
 
 
 # ---------------------------------------------------------------------------

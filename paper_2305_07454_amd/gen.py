@@ -340,6 +340,64 @@ def headings(rng, journey_id) -> np.ndarray:
     return h.astype(np.float32)
 
 
+CSV_HEADER = b"Journey Id,Timestamp,Latitude,Longitude,Postal Code,Speed,Heading\n"
+
+
+def _digits(v, width):
+    """Decimal digits (ASCII) of non-negative integers, zero-padded: (n, width) uint8."""
+    v = np.asarray(v, dtype=np.int64).copy()
+    out = np.empty((v.shape[0], width), dtype=np.uint8)
+    for i in range(width - 1, -1, -1):
+        out[:, i] = ord("0") + (v % 10)
+        v //= 10
+    return out
+
+
+def _civil(days):
+    """(year, month, day) of days since 1970-01-01 (proleptic Gregorian)."""
+    z = days + 719468
+    era = np.floor_divide(z, 146097)
+    doe = z - era * 146097
+    yoe = (doe - doe // 1460 + doe // 36524 - doe // 146096) // 365
+    y = yoe + era * 400
+    doy = doe - (365 * yoe + yoe // 4 - yoe // 100)
+    mp = (5 * doy + 2) // 153
+    d = doy - (153 * mp + 2) // 5 + 1
+    m = np.where(mp < 10, mp + 3, mp - 9)
+    return y + (m <= 2), m, d
+
+
+def to_csv(records, heading, header=True) -> bytes:
+    """Table-1-shaped text of records (fixed-width fields, one row per line):
+    a 7-character journey id (5 digits and 2 letters from the id), UTC time
+    with milliseconds, signed latitude / longitude with 6 decimals, a postal
+    code, speed with 2 decimals, whole-degree heading."""
+    jid, ts, lat, lon, spd = records.columns() if hasattr(records, "columns") else records
+    n = jid.shape[0]
+    jid = np.asarray(jid, dtype=np.int64)
+    idd = _digits(np.abs(jid) % 100_000, 5)
+    letters = np.stack([ord("a") + (np.abs(jid) // 100_000) % 26, ord("a") + (np.abs(jid) // 2_600_000) % 26], 1)
+    days = np.floor_divide(ts, 86_400_000)
+    msd = ts - days * 86_400_000
+    y, mo, d = _civil(days)
+    hh, mi, se, ms = msd // 3_600_000, (msd // 60_000) % 60, (msd // 1000) % 60, msd % 1000
+    def signed(v, idig):
+        q = np.rint(np.abs(v) * 1e6).astype(np.int64)
+        sign = np.where(np.asarray(v) < 0, ord("-"), ord("+")).astype(np.uint8)[:, None]
+        return np.concatenate([sign, _digits(q // 1_000_000, idig), np.full((n, 1), ord("."), np.uint8),
+                               _digits(q % 1_000_000, 6)], 1)
+    sq = np.rint(np.clip(np.asarray(spd, dtype=np.float64), 0, 999.99) * 100).astype(np.int64)
+    hq = np.rint(np.mod(np.asarray(heading, dtype=np.float64), 360.0)).astype(np.int64) % 360
+    c = lambda ch: np.full((n, 1), ord(ch), np.uint8)  # noqa: E731
+    parts = [idd, letters.astype(np.uint8), c(","),
+             _digits(y, 4), c("-"), _digits(mo, 2), c("-"), _digits(d, 2), c(" "), _digits(hh, 2), c(":"),
+             _digits(mi, 2), c(":"), _digits(se, 2), c("."), _digits(ms, 3), c(","),
+             signed(lat, 3), c(","), signed(lon, 3), c(","), _digits(65000 + np.abs(jid) % 1000, 5), c(","),
+             _digits(sq // 100, 3), c("."), _digits(sq % 100, 2), c(","), _digits(hq, 3), c("\n")]
+    body = np.concatenate(parts, 1).tobytes()
+    return (CSV_HEADER if header else b"") + body
+
+
 def chunk_sizes(rng, n, lo, hi):
     """Consecutive chunk sizes, log-uniform on [lo, hi], covering n records."""
     out = []

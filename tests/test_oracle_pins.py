@@ -555,6 +555,64 @@ def test_split_trips_by_hand(oracle_mod):
     assert trip.tolist() == [0, 1, 2, 3, 4, 5, 6]
 
 
+def test_csv_table1_rows_by_hand(oracle_mod):
+    # Table 1's first two rows: ids packed from their ASCII bytes ("3" 0x33,
+    # "4" 0x34, "5" 0x35, "6" 0x36, "r" 0x72, "d" 0x64, "1" 0x31, "2" 0x32,
+    # "t" 0x74, "f" 0x66), times from 2021-05-09 00:00 UTC = 1 620 518 400 000 ms
+    text = (b"Journey Id,Timestamp,Latitude,Longitude,Postal Code,Speed,Heading\n"
+            b"33456rd,2021-05-09 03:48:42,37.664087,-92.6546,65536,105.98,33\n"
+            b"31224tf,2021-05-09 03:49:42,37.667707,-92.6490,65536,0,53\n")
+    (jid, ts, lat, lon, spd), hd, ok = oracle_mod.csv_extract(text)
+    assert ok.tolist() == [1, 1]
+    assert jid.tolist() == [0x3333343536726400, 0x3331323234746600]
+    assert ts.tolist() == [1620518400000 + (3 * 3600 + 48 * 60 + 42) * 1000, 1620518400000 + (3 * 3600 + 49 * 60 + 42) * 1000]
+    assert lat.tolist() == [37.664087, 37.667707] and lon.tolist() == [-92.6546, -92.649]
+    assert spd.tolist() == [np.float32(105.98), 0.0] and hd.tolist() == [33.0, 53.0]
+
+
+@pytest.mark.parametrize("field,ok", [
+    (b"5", True), (b"5.", True), (b".5", True), (b"+5", True), (b"-0", True), (b"037.5", True),
+    (b"9007199254740991", True), (b"0." + b"0" * 21 + b"1", True),
+    (b" 5", False), (b"5 ", False), (b"1e5", False), (b"nan", False), (b"inf", False), (b".", False),
+    (b"-", False), (b"", False), (b"1.2.3", False), (b"9007199254740992", False),
+    (b"0." + b"0" * 22 + b"1", False),
+])
+def test_csv_decimal_grammar(oracle_mod, field, ok):
+    row = b"a1,2021-05-09 00:00:00," + field + b",-92.5,65536,1.5,10\n"
+    (_, _, lat, _, _), _, good = oracle_mod.csv_extract(row, has_header=False)
+    assert bool(good[0]) == ok
+    if ok:
+        assert lat[0] == float(field) and math.copysign(1.0, lat[0]) == math.copysign(1.0, float(field))
+
+
+@pytest.mark.parametrize("stamp,ms", [
+    (b"2020-02-29 00:00:00", 1582934400000), (b"2000-02-29 12:00:00", 951825600000),
+    (b"1970-01-01 00:00:00.5", 500), (b"1970-01-01 00:00:00.05", 50), (b"1970-01-01 00:00:00.005", 5),
+    (b"2021-02-29 00:00:00", None), (b"1900-02-29 00:00:00", None), (b"2021-05-09 24:00:00", None),
+    (b"2021-05-09 00:60:00", None), (b"2021-05-09 00:00:60", None), (b"1970-01-01 00:00:00.0005", None),
+    (b"2021-05-09T00:00:00", None), (b"0000-01-01 00:00:00", None), (b"2021-5-09 00:00:00", None),
+])
+def test_csv_timestamp_rule(oracle_mod, stamp, ms):
+    (_, ts, _, _, _), _, good = oracle_mod.csv_extract(b"a1," + stamp + b",38.5,-92.5,1,2,3", has_header=False)
+    assert bool(good[0]) == (ms is not None)
+    if ms is not None:
+        assert ts[0] == ms
+
+
+def test_csv_lines_and_fields(oracle_mod):
+    # CRLF; an empty line and a quoted row are malformed; no final newline;
+    # an empty heading is NaN; ids of 8 bytes fit and 9 do not
+    text = (b"h\r\n" b"abcdefgh,2021-05-09 00:00:00,1,2,3,4,5\r\n" b"\n"
+            b'"q",2021-05-09 00:00:00,1,2,3,4,5\n' b"abcdefghi,2021-05-09 00:00:00,1,2,3,4,5\n"
+            b"x,2021-05-09 00:00:01,1,2,3,4,\n" b"x,2021-05-09 00:00:02,1,2,3,4")
+    (jid, ts, _, _, _), hd, ok = oracle_mod.csv_extract(text)
+    assert ok.tolist() == [1, 0, 0, 0, 1, 0]
+    assert jid[0] == int.from_bytes(b"abcdefgh", "big") and math.isnan(hd[4])
+    assert oracle_mod.csv_extract(b"h\n")[2].tolist() == []
+    assert oracle_mod.csv_extract(b"")[2].tolist() == []
+    assert oracle_mod.csv_extract(b"x,2021-05-09 00:00:02,1,2,3,4,5", has_header=False)[2].tolist() == [1]
+
+
 def test_grid_line_cases(oracle_mod):
     # Alg. 2 reading: floor of the rounded quotient, not Python's exact-quotient //
     spec = gen.GridSpec(36.0, -95.8, 0.005, 0.005, 920, 1340, 0, 300_000, 288)

@@ -188,57 +188,96 @@ __device__ __forceinline__ bool parse_decimal(const unsigned char* s, int len, d
     return true;
 }
 
-// the rows that fit the capacity, after the header (meta: header lines
-// skipped, rows to parse); malformed rows are counted in res->n_bad
-__global__ void __launch_bounds__(CB) k_csv_parse(const unsigned char* __restrict__ text, const u64* __restrict__ start,
-                                                  const u64* __restrict__ meta, cv_records_out o,
-                                                  float* __restrict__ heading, uint8_t* __restrict__ row_ok,
-                                                  cv_result* res)
+constexpr int SB = 32 * 1024;  // LDS bytes staged per block
+
+struct Row {
+    i64 jid, ts;
+    double lat, lon, spd, hdg;
+    bool ok;
+};
+
+// The fields of one row of rl bytes at s (its line end included).  Inlined
+// into each caller, so that a row staged in LDS is read with LDS loads.
+__device__ __forceinline__ Row parse_row(const unsigned char* s, u64 rl)
 {
+    Row w;
+    if (rl && s[rl - 1] == '\n') --rl;
+    if (rl && s[rl - 1] == '\r') --rl;
+    const int len = (int)(rl < (u64)(1 << 20) ? rl : (u64)(1 << 20));
+    // field boundaries: exactly six commas
+    int cpos[6];
+    int nc = 0;
+    bool ok = rl < (u64)(1 << 20);
+    for (int i = 0; i < len && ok; ++i) {
+        if (s[i] == ',') {
+            if (nc < 6) cpos[nc] = i;
+            ++nc;
+        } else if (s[i] == '"') {
+            ok = false;
+        }
+    }
+    ok = ok && nc == 6;
+    w.jid = 0;
+    w.ts = 0;
+    w.lat = w.lon = w.spd = w.hdg = __builtin_nan("");
+    if (ok) {
+        ok = parse_id(s, cpos[0], w.jid) && parse_ts(s + cpos[0] + 1, cpos[1] - cpos[0] - 1, w.ts) &&
+             parse_decimal(s + cpos[1] + 1, cpos[2] - cpos[1] - 1, w.lat) &&
+             parse_decimal(s + cpos[2] + 1, cpos[3] - cpos[2] - 1, w.lon) &&
+             parse_decimal(s + cpos[4] + 1, cpos[5] - cpos[4] - 1, w.spd);
+        const int hl = len - cpos[5] - 1;
+        if (ok && hl > 0 && !parse_decimal(s + cpos[5] + 1, hl, w.hdg)) ok = false;
+    }
+    if (!ok) {
+        w.jid = 0;
+        w.ts = 0;
+        w.lat = w.lon = w.spd = w.hdg = __builtin_nan("");
+    }
+    w.ok = ok;
+    return w;
+}
+
+// The rows that fit the capacity, after the header (meta: header lines
+// skipped, rows to parse), CB per block, one per thread; malformed rows are
+// counted in res->n_bad.  A block's rows are contiguous text: when they fit
+// SB bytes they are staged in LDS with 16-byte loads and parsed from there.
+__global__ void __launch_bounds__(CB) k_csv_parse(const unsigned char* __restrict__ text, u64 nbytes,
+                                                  const u64* __restrict__ start, const u64* __restrict__ meta,
+                                                  cv_records_out o, float* __restrict__ heading,
+                                                  uint8_t* __restrict__ row_ok, cv_result* res)
+{
+    __shared__ __attribute__((aligned(16))) unsigned char s_txt[SB + 16];
     const u64 first = meta[0], rows = meta[1];
-    u64 bad = 0;
-    for (u64 r = (u64)blockIdx.x * CB + threadIdx.x; r < rows; r += (u64)gridDim.x * CB) {
-        u64 b = start[first + r], e = start[first + r + 1];
-        if (e > b && text[e - 1] == '\n') --e;
-        if (e > b && text[e - 1] == '\r') --e;
-        const unsigned char* s = text + b;
-        const int len = (int)((e - b) < (u64)(1 << 20) ? (e - b) : (u64)(1 << 20));
-        // field boundaries: exactly six commas
-        int cpos[6];
-        int nc = 0;
-        bool ok = (e - b) < (u64)(1 << 20);
-        for (int i = 0; i < len && ok; ++i) {
-            if (s[i] == ',') {
-                if (nc < 6) cpos[nc] = i;
-                ++nc;
-            } else if (s[i] == '"') {
-                ok = false;
+    const u64 r0 = (u64)blockIdx.x * CB;
+    if (r0 >= rows) return;
+    const u64 r1 = r0 + CB < rows ? r0 + CB : rows;
+    const u64 B0 = start[first + r0], B1 = start[first + r1];
+    const u64 A0 = B0 & ~15ull;
+    const bool staged = B1 - A0 <= SB;
+    if (staged) {
+        for (u64 a = A0 + 16 * (u64)threadIdx.x; a < B1; a += 16 * CB) {
+            if (a + 16 <= nbytes) {
+                *reinterpret_cast<uint4*>(&s_txt[a - A0]) = *reinterpret_cast<const uint4*>(text + a);
+            } else {
+                for (u64 c = a; c < a + 16 && c < nbytes; ++c) s_txt[c - A0] = text[c];
             }
         }
-        ok = ok && nc == 6;
-        i64 jid = 0, tsv = 0;
-        double la = __builtin_nan(""), lo = __builtin_nan(""), sp = __builtin_nan(""), hd = __builtin_nan("");
-        if (ok) {
-            ok = parse_id(s, cpos[0], jid) && parse_ts(s + cpos[0] + 1, cpos[1] - cpos[0] - 1, tsv) &&
-                 parse_decimal(s + cpos[1] + 1, cpos[2] - cpos[1] - 1, la) &&
-                 parse_decimal(s + cpos[2] + 1, cpos[3] - cpos[2] - 1, lo) &&
-                 parse_decimal(s + cpos[4] + 1, cpos[5] - cpos[4] - 1, sp);
-            const int hl = len - cpos[5] - 1;
-            if (ok && hl > 0 && !parse_decimal(s + cpos[5] + 1, hl, hd)) ok = false;
-        }
-        if (!ok) {
-            jid = 0;
-            tsv = 0;
-            la = lo = sp = hd = __builtin_nan("");
-            ++bad;
-        }
-        o.journey_id[r] = jid;
-        o.ts_ms[r] = tsv;
-        o.lat_deg[r] = la;
-        o.lon_deg[r] = lo;
-        o.speed_mps[r] = (float)sp;
-        if (heading) heading[r] = (float)hd;
-        if (row_ok) row_ok[r] = ok ? 1 : 0;
+    }
+    __syncthreads();
+    u64 bad = 0;
+    const u64 r = r0 + threadIdx.x;
+    if (r < r1) {
+        const u64 b = start[first + r];
+        const u64 rl = start[first + r + 1] - b;  // the row's bytes, its line end included
+        const Row w = staged ? parse_row(s_txt + (b - A0), rl) : parse_row(text + b, rl);
+        bad += w.ok ? 0 : 1;
+        o.journey_id[r] = w.jid;
+        o.ts_ms[r] = w.ts;
+        o.lat_deg[r] = w.lat;
+        o.lon_deg[r] = w.lon;
+        o.speed_mps[r] = (float)w.spd;
+        if (heading) heading[r] = (float)w.hdg;
+        if (row_ok) row_ok[r] = w.ok ? 1 : 0;
     }
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) bad += __shfl_xor(bad, d, WAVE);
@@ -312,8 +351,8 @@ cv_status cv_csv_extract(const char* text, uint64_t nbytes, int32_t has_header, 
     hipLaunchKernelGGL(k_csv_begin, dim3(1), dim3(64), 0, s, tcnt, tiles, t, (u64)nbytes, has_header ? 1 : 0,
                        (u64)capacity, start, meta, res);
     if (capacity)
-        hipLaunchKernelGGL(k_csv_parse, dim3(cvh::grid_for(capacity, CB, 8192)), dim3(CB), 0, s, t, start, meta,
-                           *out, heading_deg, row_ok, res);
+        hipLaunchKernelGGL(k_csv_parse, dim3((unsigned)((capacity + CB - 1) / CB)), dim3(CB), 0, s, t, (u64)nbytes,
+                           start, meta, *out, heading_deg, row_ok, res);
     return cvh::last_launch_status();
 }
 

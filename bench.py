@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--total", type=int, default=400_000_000, help="c2: total records")
     ap.add_argument("--n-journeys", type=int, default=None, help="scale the workload down (testing)")
     ap.add_argument("--no-direction", action="store_true", help="c1: skip the direction-lattice measurement")
+    ap.add_argument("--separate", action="store_true",
+                    help="run the sort and the kinematics as two calls instead of the fused one")
     ap.add_argument("--cpu-sample", type=int, default=40_000_000, help="records in the oracle's timed sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--out", default=None, help="also write the JSON line to this file")
@@ -134,7 +136,7 @@ def bench_batched(args):
     log(f"sizing run: {J} journeys, {G} groups ({time.time() - t:.1f}s)")
     del bp
     torch.cuda.empty_cache()
-    bp = cvetl.BatchPipeline(n, len(sizes), grid, mj, J, max(4096, int(1.25 * G)), dev)
+    bp = cvetl.BatchPipeline(n, len(sizes), grid, mj, J, max(4096, int(1.25 * G)), dev, fused=not args.separate)
     for _ in range(args.warmup):
         bp.run(rec, off_d)
     torch.cuda.synchronize()
@@ -151,7 +153,7 @@ def bench_batched(args):
     # plain per-file: one plain pipeline sized for the largest shard, called per shard
     big = max(sizes)
     pp = cvetl.Pipeline(big, grid, max_journeys=max(1024, mj), journey_capacity=max(1, J),
-                        group_capacity=max(4096, int(1.25 * G)), device=dev)
+                        group_capacity=max(4096, int(1.25 * G)), device=dev, fused=not args.separate)
     views = [{k: v[int(off_h[i]):int(off_h[i + 1])] for k, v in rec.items()} for i in range(len(sizes))]
 
     def per_file():
@@ -300,8 +302,9 @@ def main():
     del out
     torch.cuda.empty_cache()
     pipe = cvetl.Pipeline(n, grid, max_journeys=max(1024, 2 * J), journey_capacity=J,
-                          group_capacity=max(4096, int(1.25 * G)), device=dev)
-    log(f"n={n} J={J} G={G} workspace={pipe.workspace_bytes() / 2**30:.2f} GiB")
+                          group_capacity=max(4096, int(1.25 * G)), device=dev, fused=not args.separate)
+    log(f"n={n} J={J} G={G} workspace={pipe.workspace_bytes() / 2**30:.2f} GiB"
+        f" ({'separate' if args.separate else 'fused'} gather and kinematics)")
 
     for _ in range(args.warmup):
         pipe.run(rec)
@@ -350,9 +353,10 @@ def main():
     bytes_per_launch = alg_bytes / max(pass_launches, 1)
     achieved = bytes_per_launch / (avg_ms / 1e3) / 1e9
     stages = {}
-    for fam in ("sort_prep", "gather", "features", "summary", "grid_agg", "grid_tail"):
+    for fam in ("sort_prep", "gather", "features", "gather_features", "summary", "grid_agg", "grid_tail"):
         ms, c = cvetl.cv_timing_read(fam)
-        stages[fam] = round(ms / args.steps, 4)
+        if c:
+            stages[fam] = round(ms / args.steps, 4)
     stages["sort_passes"] = round(pass_ms / args.steps, 4)
 
     direction, lattice = None, None

@@ -183,6 +183,23 @@ cv_status cv_sort_records(const cv_records* in, uint64_t max_journeys, uint32_t*
 cv_status cv_journey_features(const cv_records* sorted, const cv_features* out, void* stream);
 
 /* ------------------------------------------------------------------------
+ * cv_sort_records_features / cv_batch_sort_records_features -- the sort
+ * (cv_sort_records / cv_batch_sort_records) and the kinematics of the sorted
+ * records (cv_journey_features / cv_batch_journey_features) in one call:
+ * the gather writes each tile of sorted records and evaluates their
+ * kinematics from LDS, so the sorted columns are not read back.  Every
+ * output is bit for bit that of the two calls.  `sorted` and `feat` must
+ * name every column.  Workspace as cv_sort_workspace_size.
+ * --------------------------------------------------------------------- */
+cv_status cv_sort_records_features(const cv_records* in, uint64_t max_journeys, uint32_t* perm,
+                                   const cv_records_out* sorted, const cv_features* feat, cv_result* res, void* ws,
+                                   size_t ws_bytes, void* stream);
+cv_status cv_batch_sort_records_features(const cv_records* in, const uint64_t* shard_offsets, uint32_t n_shards,
+                                         uint64_t max_journeys, uint32_t* perm, const cv_records_out* sorted,
+                                         const cv_features* feat, cv_result* res, void* ws, size_t ws_bytes,
+                                         void* stream);
+
+/* ------------------------------------------------------------------------
  * cv_journey_summary -- one row per journey (maximal run of equal journey_id)
  * of sorted records, in ascending journey id, from the records and their
  * features (step_m, speed_mps and flags are read).  Rows past `capacity` are

@@ -14,6 +14,7 @@
 
 #include "cv_device.h"
 #include "cv_host.h"
+#include "cv_kin.h"
 
 using namespace cv;
 
@@ -21,9 +22,6 @@ namespace {
 
 constexpr int FB = 256;
 constexpr int FOUT = FB - 2;  // records written per block
-constexpr double EARTH_R_M = 6371008.8;
-constexpr double DEG2RAD = 3.14159265358979323846 / 180.0;
-constexpr double RAD2DEG = 180.0 / 3.14159265358979323846;
 
 __global__ void __launch_bounds__(FB) k_features(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts,
                                                  const double* __restrict__ lat, const double* __restrict__ lon,
@@ -55,7 +53,7 @@ __global__ void __launch_bounds__(FB) k_features(u32 n, const i64* __restrict__ 
         la = lat[r];
         lo = lon[r];
         fin = isfinite(la) && isfinite(lo);
-        if (fin) sincos(la * DEG2RAD, &sphi, &cphi);
+        if (fin) sincos(la * KIN_DEG2RAD, &sphi, &cphi);
     }
     s_jid[t] = j;
     s_ts[t] = tsr;
@@ -66,8 +64,7 @@ __global__ void __launch_bounds__(FB) k_features(u32 n, const i64* __restrict__ 
     __syncthreads();
 
     // step (t-1 -> t) of record r
-    double step = 0.0, dts = 0.0, v = 0.0, b = 0.0;
-    u32 f = 0;
+    KinStep k{0.0, 0.0, 0.0, 0.0, 0u};
     if (in && t >= 1) {
         const int p = t - 1;
         bool head = (r == 0) || (s_jid[p] != j);
@@ -78,62 +75,20 @@ __global__ void __launch_bounds__(FB) k_features(u32 n, const i64* __restrict__ 
             while (sh + 1 < S && soff[sh + 1] <= (u64)r) ++sh;
             head = soff[sh] == (u64)r;
         }
-        if (head) {
-            f = CV_FLAG_FIRST | (fin ? 0u : CV_FLAG_BAD_COORD);
-        } else {
-            const i64 dt_ms = tsr - s_ts[p];
-            f = dt_ms == 0 ? CV_FLAG_DT_ZERO : 0u;
-            const double lap = s_lat[p], lop = s_lon[p];
-            if (!fin || !(isfinite(lap) && isfinite(lop))) {
-                f |= CV_FLAG_BAD_COORD;
-            } else {
-                dts = (double)dt_ms / 1000.0;
-                const double dphi = (la - lap) * DEG2RAD;
-                const double dlam = (lo - lop) * DEG2RAD;
-                // half-angle sines and cosines; the full-angle sines of the
-                // bearing follow from them (sin 2u = 2 sin u cos u)
-                double sp, cp, sl, cl;
-                sincos(0.5 * dphi, &sp, &cp);
-                sincos(0.5 * dlam, &sl, &cl);
-                const double cphi1 = s_cphi[p];
-                const double cphi2 = cphi;
-                const double a = (sp * sp) + ((cphi1 * cphi2) * (sl * sl));
-                step = (2.0 * EARTH_R_M) * asin(fmin(1.0, sqrt(a)));
-                if (dt_ms > 0) {
-                    v = step / dts;
-                    f |= CV_FLAG_SPEED_OK;
-                }
-                if (step > 0.0) {
-                    const double y = ((2.0 * sl) * cl) * cphi2;
-                    const double x = ((2.0 * sp) * cp) + (((2.0 * s_sphi[p]) * cphi2) * (sl * sl));
-                    b = atan2(y, x) * RAD2DEG;
-                    if (b < 0.0) b += 360.0;
-                    if (b >= 360.0) b -= 360.0;
-                    f |= CV_FLAG_BEARING_OK;
-                }
-            }
-        }
+        const double lap = s_lat[p], lop = s_lon[p];
+        k = kin_step(head, fin, tsr, la, lo, cphi, isfinite(lap) && isfinite(lop), s_ts[p], lap, lop, s_cphi[p],
+                     s_sphi[p]);
     }
-    s_v[t] = v;
-    s_b[t] = b;
-    s_f[t] = f;
+    s_v[t] = k.v;
+    s_b[t] = k.b;
+    s_f[t] = k.f;
     __syncthreads();
-
     if (!in || t < 2) return;
     const int p = t - 1;
-    const u32 fp = s_f[p];
-    double acc = 0.0, dh = 0.0;
-    if ((f & CV_FLAG_SPEED_OK) && (fp & CV_FLAG_SPEED_OK)) {
-        acc = (v - s_v[p]) / dts;
-        f |= CV_FLAG_ACCEL_OK;
-    }
-    if ((f & CV_FLAG_BEARING_OK) && (fp & CV_FLAG_BEARING_OK)) {
-        double d = b - s_b[p];
-        if (d > 180.0) d -= 360.0;
-        else if (d <= -180.0) d += 360.0;
-        dh = d;
-        f |= CV_FLAG_DHEAD_OK;
-    }
+    u32 f = k.f;
+    double acc, dh;
+    kin_final(f, k.v, k.b, k.dts, s_f[p], s_v[p], s_b[p], acc, dh);
+    const double step = k.step, dts = k.dts, v = k.v, b = k.b;
     o_step[r] = step;
     o_dt[r] = dts;
     o_spd[r] = v;

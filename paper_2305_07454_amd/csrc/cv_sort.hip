@@ -17,6 +17,7 @@
 
 #include "cv_device.h"
 #include "cv_host.h"
+#include "cv_kin.h"
 #include "cv_radix.h"
 
 using namespace cv;
@@ -468,8 +469,182 @@ bool valid_ptr8(const void* p) { return p == nullptr || cvh::aligned(p, 8); }
 
 }  // namespace
 
+namespace {
+
+// The gather fused with the per-point kinematics of the sorted records:
+// every block writes a contiguous tile of GFT sorted records, stages their
+// points (and the two before the tile) in LDS, and evaluates the same
+// stencil as the features kernel (cv_kin.h), so that the sorted columns are
+// not read back from memory.  Thread t owns records t and t + 256 of the
+// tile (LDS positions 2 + t and 258 + t); threads 0 and 1 also fetch the two
+// halo records (positions 0 and 1).
+constexpr int GFT = 512;
+template <bool SHARDS>
+__global__ void __launch_bounds__(256) k_gather_feat(u32 n, const SortMeta* m, const u64* __restrict__ K0,
+                                                     const u64* __restrict__ K1, const u64* __restrict__ dict_sorted,
+                                                     const i64* __restrict__ jid, const i64* __restrict__ ts,
+                                                     const double* __restrict__ lat, const double* __restrict__ lon,
+                                                     const float* __restrict__ spd, u32* __restrict__ perm,
+                                                     cv_records_out so, cv_features fo, const u64* __restrict__ soff,
+                                                     u32 S)
+{
+    constexpr int GFI = GFT / 256;
+    constexpr int NQ = GFT + 2;
+    __shared__ i64 s_jid[NQ], s_ts[NQ];
+    __shared__ double s_lat[NQ], s_lon[NQ], s_sphi[NQ], s_cphi[NQ], s_v[NQ], s_b[NQ];
+    __shared__ u32 s_f[NQ];
+    const u32 np = m->passes;
+    const u32 tb = m->t_bits;
+    const u32 rb = m->rank_bits;
+    const u32 ib = m->ib;
+    const u32 drop = m->p0 * RADIX_BITS;
+    const u64 rmask = rb >= 64 ? ~0ull : ((1ull << rb) - 1);
+    const u64 imask = (1ull << ib) - 1;
+    const u32 dn = m->dict_n;
+    const bool exact = (m->range_err == 0) && (m->overflow == 0);
+    const bool rank_in_key = exact && drop <= tb;
+    const u32 rshift = ib + tb - drop;
+    const bool ts_in_key = exact && drop == 0;
+    const u64 tmin = (u64)unord_i64(m->tmin_ord);
+    const u64 tmask = tb >= 64 ? ~0ull : ((1ull << tb) - 1);
+    const u64* K = (np & 1) ? K1 : K0;
+    const int t = threadIdx.x;
+    const long t0 = (long)blockIdx.x * GFT;
+    // slots 0 .. GFI - 1: the tile's records; slot GFI: a halo record (threads 0, 1)
+    constexpr int NS = GFI + 1;
+    long kk[NS];
+    int qq[NS];
+#pragma unroll
+    for (int u = 0; u < GFI; ++u) {
+        kk[u] = t0 + u * 256 + t;
+        qq[u] = 2 + u * 256 + t;
+    }
+    // other threads repeat their first record there (cached; never stored)
+    kk[GFI] = t < 2 ? t0 - 2 + t : kk[0];
+    qq[GFI] = t;
+    // the sorted words, their source indices and columns; every load from a
+    // clamped index, all issued before any is used
+    u64 wv[NS];
+    u32 vv[NS];
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+        const long k = kk[u] < 0 ? 0 : (kk[u] < (long)n ? kk[u] : (long)n - 1);
+        wv[u] = K[k];
+    }
+#pragma unroll
+    for (int u = 0; u < NS; ++u) vv[u] = (u32)(wv[u] & imask);
+    double ola[NS], olo[NS];
+    float osp[NS];
+    i64 oj[NS], ot[NS];
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+        ola[u] = lat[vv[u]];
+        olo[u] = lon[vv[u]];
+        osp[u] = spd[vv[u]];
+    }
+    if (rank_in_key) {
+#pragma unroll
+        for (int u = 0; u < NS; ++u) {
+            u64 r = rshift >= 64 ? 0ull : ((wv[u] >> rshift) & rmask);
+            r = r < dn ? r : dn - 1;
+            oj[u] = (i64)(dict_sorted[r] ^ SIGN);
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < NS; ++u) oj[u] = jid[vv[u]];
+    }
+    if (ts_in_key) {
+#pragma unroll
+        for (int u = 0; u < NS; ++u) ot[u] = (i64)(tmin + ((wv[u] >> ib) & tmask));
+    } else {
+#pragma unroll
+        for (int u = 0; u < NS; ++u) ot[u] = ts[vv[u]];
+    }
+    // shard of each record (batched form): a journey's head, and the source
+    // index made shard-relative
+    u32 shs[NS];
+#pragma unroll
+    for (int u = 0; u < NS; ++u) shs[u] = 0;
+    if (SHARDS) {
+#pragma unroll
+        for (int u = 0; u < NS; ++u) shs[u] = kk[u] >= 0 && kk[u] < (long)n ? shard_of(soff, S, (u64)kk[u]) : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+        const long k = kk[u];
+        const bool mine = u < GFI || t < 2;
+        if (!mine || k < 0 || k >= (long)n) continue;
+        const int q = qq[u];
+        if (u < GFI) {
+            u32 pv = vv[u];
+            if (SHARDS) pv -= (u32)soff[shs[u]];
+            perm[k] = pv;
+            so.journey_id[k] = oj[u];
+            so.ts_ms[k] = ot[u];
+            so.lat_deg[k] = ola[u];
+            so.lon_deg[k] = olo[u];
+            so.speed_mps[k] = osp[u];
+        }
+        s_jid[q] = oj[u];
+        s_ts[q] = ot[u];
+        s_lat[q] = ola[u];
+        s_lon[q] = olo[u];
+        double sp = 0.0, cp = 0.0;
+        if (isfinite(ola[u]) && isfinite(olo[u])) sincos(ola[u] * KIN_DEG2RAD, &sp, &cp);
+        s_sphi[q] = sp;
+        s_cphi[q] = cp;
+    }
+    __syncthreads();
+    // steps (q - 1 -> q) of the tile's records, and of the record before the
+    // tile (thread 0: the first output's predecessor)
+    KinStep ks[NS];
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+        ks[u] = KinStep{0.0, 0.0, 0.0, 0.0, 0u};
+        const long k = kk[u];
+        const int q = u < GFI ? qq[u] : 1;
+        const bool mine = u < GFI || t == 0;
+        const long kr = u < GFI ? k : t0 - 1;
+        if (!mine || kr < 0 || kr >= (long)n) {
+            if (u == GFI && t == 0) s_f[1] = 0u;
+            continue;
+        }
+        bool head = kr == 0 || s_jid[q - 1] != s_jid[q];
+        if (SHARDS && !head) {
+            const u32 sh = u < GFI ? shs[u] : shard_of(soff, S, (u64)kr);
+            head = soff[sh] == (u64)kr;
+        }
+        const double la = s_lat[q], lo = s_lon[q], lap = s_lat[q - 1], lop = s_lon[q - 1];
+        ks[u] = kin_step(head, isfinite(la) && isfinite(lo), s_ts[q], la, lo, s_cphi[q],
+                         isfinite(lap) && isfinite(lop), s_ts[q - 1], lap, lop, s_cphi[q - 1], s_sphi[q - 1]);
+        s_v[q] = ks[u].v;
+        s_b[q] = ks[u].b;
+        s_f[q] = ks[u].f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < GFI; ++u) {
+        const long k = kk[u];
+        if (k >= (long)n) continue;
+        const int q = qq[u];
+        u32 f = ks[u].f;
+        double acc, dh;
+        kin_final(f, ks[u].v, ks[u].b, ks[u].dts, s_f[q - 1], s_v[q - 1], s_b[q - 1], acc, dh);
+        fo.step_m[k] = ks[u].step;
+        fo.dt_s[k] = ks[u].dts;
+        fo.speed_mps[k] = ks[u].v;
+        fo.accel_mps2[k] = acc;
+        fo.bearing_deg[k] = ks[u].b;
+        fo.dheading_deg[k] = dh;
+        fo.flags[k] = (uint8_t)f;
+    }
+}
+
+}  // namespace
+
 static cv_status sort_impl(const cv_records* in, const uint64_t* soff, uint32_t S, uint64_t max_journeys, uint32_t* perm,
-                           const cv_records_out* sorted, cv_result* res, void* ws, size_t ws_bytes, void* stream)
+                           const cv_records_out* sorted, cv_result* res, void* ws, size_t ws_bytes, void* stream,
+                           const cv_features* feat = nullptr)
 {
     if (!in || in->n >= (1ull << 32) || max_journeys >= (1ull << 31)) return CV_ERR_INVALID_ARGUMENT;
     const u64 n = in->n;
@@ -521,7 +696,13 @@ static cv_status sort_impl(const cv_records* in, const uint64_t* soff, uint32_t 
     }
     radix_passes(L.K0, L.K1, nullptr, L.V0, L.V1, nn, nullptr, &L.meta->key_bits, MAX_PASSES, L.offs, L.status,
                  L.meta->tickets, s, /*timed=*/true, &L.meta->ib);
-    {
+    if (feat) {
+        cvh::TimedScope ts_("gather_features", s);
+        auto gk = S > 1 ? k_gather_feat<true> : k_gather_feat<false>;
+        hipLaunchKernelGGL(gk, dim3((unsigned)((n + GFT - 1) / GFT)), dim3(256), 0, s, nn, L.meta, L.K0, L.K1, L.dl0,
+                           in->journey_id, in->ts_ms, in->lat_deg, in->lon_deg, in->speed_mps, perm, so, *feat, soff,
+                           S);
+    } else {
         cvh::TimedScope ts_("gather", s);
         const bool full = so.journey_id && so.ts_ms && so.lat_deg && so.lon_deg && so.speed_mps;
         auto gk = S > 1 ? (full ? k_gather<true, true> : k_gather<true, false>)
@@ -567,6 +748,30 @@ cv_status cv_batch_sort_records(const cv_records* in, const uint64_t* shard_offs
 {
     if (n_shards == 0 || !shard_offsets || !cvh::aligned(shard_offsets, 8)) return CV_ERR_INVALID_ARGUMENT;
     return sort_impl(in, shard_offsets, n_shards, max_journeys, perm, sorted, res, ws, ws_bytes, stream);
+}
+
+static bool feat_complete(const cv_records_out* so, const cv_features* f)
+{
+    return so && f && so->journey_id && so->ts_ms && so->lat_deg && so->lon_deg && so->speed_mps && f->step_m &&
+           f->dt_s && f->speed_mps && f->accel_mps2 && f->bearing_deg && f->dheading_deg && f->flags;
+}
+
+cv_status cv_sort_records_features(const cv_records* in, uint64_t max_journeys, uint32_t* perm,
+                                   const cv_records_out* sorted, const cv_features* feat, cv_result* res, void* ws,
+                                   size_t ws_bytes, void* stream)
+{
+    if (in && in->n && !feat_complete(sorted, feat)) return CV_ERR_INVALID_ARGUMENT;
+    return sort_impl(in, nullptr, 0, max_journeys, perm, sorted, res, ws, ws_bytes, stream, feat);
+}
+
+cv_status cv_batch_sort_records_features(const cv_records* in, const uint64_t* shard_offsets, uint32_t n_shards,
+                                         uint64_t max_journeys, uint32_t* perm, const cv_records_out* sorted,
+                                         const cv_features* feat, cv_result* res, void* ws, size_t ws_bytes,
+                                         void* stream)
+{
+    if (n_shards == 0 || !shard_offsets || !cvh::aligned(shard_offsets, 8)) return CV_ERR_INVALID_ARGUMENT;
+    if (in && in->n && !feat_complete(sorted, feat)) return CV_ERR_INVALID_ARGUMENT;
+    return sort_impl(in, shard_offsets, n_shards, max_journeys, perm, sorted, res, ws, ws_bytes, stream, feat);
 }
 
 }  // extern "C"

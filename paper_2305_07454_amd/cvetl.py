@@ -107,6 +107,9 @@ def lib():
         L.cv_sort_records.argtypes = [ctypes.POINTER(CvRecords), U64, P, ctypes.POINTER(CvRecordsOut), P, P,
                                       ctypes.c_size_t, P]
         L.cv_sort_records.restype = S
+        L.cv_sort_records_features.argtypes = [ctypes.POINTER(CvRecords), U64, P, ctypes.POINTER(CvRecordsOut),
+                                               ctypes.POINTER(CvFeatures), P, P, ctypes.c_size_t, P]
+        L.cv_sort_records_features.restype = S
         L.cv_journey_features.argtypes = [ctypes.POINTER(CvRecords), ctypes.POINTER(CvFeatures), P]
         L.cv_journey_features.restype = S
         L.cv_summary_workspace_size.argtypes = [U64, U64, SZ]
@@ -123,6 +126,10 @@ def lib():
         L.cv_batch_sort_records.argtypes = [ctypes.POINTER(CvRecords), P, U32, U64, P, ctypes.POINTER(CvRecordsOut),
                                             P, P, ctypes.c_size_t, P]
         L.cv_batch_sort_records.restype = S
+        L.cv_batch_sort_records_features.argtypes = [ctypes.POINTER(CvRecords), P, U32, U64, P,
+                                                     ctypes.POINTER(CvRecordsOut), ctypes.POINTER(CvFeatures), P, P,
+                                                     ctypes.c_size_t, P]
+        L.cv_batch_sort_records_features.restype = S
         L.cv_batch_journey_features.argtypes = [ctypes.POINTER(CvRecords), P, U32, ctypes.POINTER(CvFeatures), P]
         L.cv_batch_journey_features.restype = S
         L.cv_batch_journey_summary.argtypes = [ctypes.POINTER(CvRecords), ctypes.POINTER(CvFeatures), P, U32,
@@ -271,6 +278,36 @@ def cv_sort_records(rec, max_journeys=None, want_sorted=True, ws=None, stream=No
                                stream=stream)
     _check(r["status"], "cv_sort_records (device)")
     return perm, out, r
+
+
+def cv_sort_records_features(rec, max_journeys, ws=None, stream=None, shard_offsets=None):
+    """Sort and kinematics in one call.  Returns (perm, sorted dict, features
+    dict, result dict); `shard_offsets` (device uint64, S + 1) selects the
+    batched form."""
+    L = lib()
+    n = int(rec["journey_id"].numel())
+    dev = rec["journey_id"].device
+    mj = int(max_journeys)
+    perm = torch.empty(n, dtype=torch.int32, device=dev)
+    out = empty_records(n, dev)
+    feat = {k: torch.empty(n, dtype=dt, device=dev) for k, dt in FEATURE_FIELDS}
+    so = CvRecordsOut(*(_ptr(out[k]) for k, _ in RECORD_FIELDS))
+    fs = CvFeatures(*(_ptr(feat[k]) for k, _ in FEATURE_FIELDS))
+    need = _size(L.cv_sort_workspace_size, n, mj)
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, dev)
+    res = new_result(dev)
+    if shard_offsets is None:
+        st = L.cv_sort_records_features(ctypes.byref(_records_struct(rec)), mj, _ptr(perm), ctypes.byref(so),
+                                        ctypes.byref(fs), _ptr(res), _ptr(ws), ws.numel(), _stream(stream))
+    else:
+        st = L.cv_batch_sort_records_features(ctypes.byref(_records_struct(rec)), _ptr(shard_offsets),
+                                              int(shard_offsets.numel()) - 1, mj, _ptr(perm), ctypes.byref(so),
+                                              ctypes.byref(fs), _ptr(res), _ptr(ws), ws.numel(), _stream(stream))
+    _check(st, "cv_sort_records_features")
+    r = read_result(res)
+    _check(r["status"], "cv_sort_records_features (device)")
+    return perm, out, feat, r
 
 
 def cv_journey_features(sorted_rec, stream=None):
@@ -547,9 +584,10 @@ class Pipeline:
     at most `n` records: no allocation and no host synchronisation inside
     `run()`, which only enqueues the four calls on the stream."""
 
-    def __init__(self, n, grid, max_journeys, journey_capacity, group_capacity, device="cuda"):
+    def __init__(self, n, grid, max_journeys, journey_capacity, group_capacity, device="cuda", fused=True):
         L = lib()
         self.n, self.grid, self.device = int(n), grid, device
+        self.fused = bool(fused)
         self.max_journeys = int(max_journeys)
         self.jcap, self.gcap = int(journey_capacity), int(group_capacity)
         self.perm = torch.empty(self.n, dtype=torch.int32, device=device)
@@ -576,10 +614,16 @@ class Pipeline:
         assert n <= self.n
         s = _stream(stream)
         inp = _records_struct(rec)
-        _check(L.cv_sort_records(ctypes.byref(inp), self.max_journeys, _ptr(self.perm), ctypes.byref(self._so),
-                                 _ptr(self.res[0]), _ptr(self.ws_sort), self.ws_sort.numel(), s), "cv_sort_records")
-        srt = CvRecords(*(_ptr(self.sorted[k]) for k, _ in RECORD_FIELDS), n)
-        _check(L.cv_journey_features(ctypes.byref(srt), ctypes.byref(self._fs), s), "cv_journey_features")
+        if self.fused:
+            _check(L.cv_sort_records_features(ctypes.byref(inp), self.max_journeys, _ptr(self.perm),
+                                              ctypes.byref(self._so), ctypes.byref(self._fs), _ptr(self.res[0]),
+                                              _ptr(self.ws_sort), self.ws_sort.numel(), s), "cv_sort_records_features")
+            srt = CvRecords(*(_ptr(self.sorted[k]) for k, _ in RECORD_FIELDS), n)
+        else:
+            _check(L.cv_sort_records(ctypes.byref(inp), self.max_journeys, _ptr(self.perm), ctypes.byref(self._so),
+                                     _ptr(self.res[0]), _ptr(self.ws_sort), self.ws_sort.numel(), s), "cv_sort_records")
+            srt = CvRecords(*(_ptr(self.sorted[k]) for k, _ in RECORD_FIELDS), n)
+            _check(L.cv_journey_features(ctypes.byref(srt), ctypes.byref(self._fs), s), "cv_journey_features")
         _check(L.cv_journey_summary(ctypes.byref(srt), ctypes.byref(self._fs), ctypes.byref(self._js), self.jcap,
                                     _ptr(self.res[1]), _ptr(self.ws_sum), self.ws_sum.numel(), s),
                "cv_journey_summary")
@@ -603,9 +647,11 @@ class BatchPipeline:
     """Preallocated buffers for the batched form: many shards in one set of
     launches.  `run()` only enqueues; offsets and results are read afterwards."""
 
-    def __init__(self, n, n_shards, grid, max_journeys, journey_capacity, group_capacity, device="cuda"):
+    def __init__(self, n, n_shards, grid, max_journeys, journey_capacity, group_capacity, device="cuda",
+                 fused=True):
         L = lib()
         self.n, self.S, self.grid, self.device = int(n), int(n_shards), grid, device
+        self.fused = bool(fused)
         self.max_journeys = int(max_journeys)
         self.jcap, self.gcap = int(journey_capacity), int(group_capacity)
         self.perm = torch.empty(self.n, dtype=torch.int32, device=device)
@@ -631,12 +677,18 @@ class BatchPipeline:
         assert n <= self.n and offsets_dev.numel() == self.S + 1
         s = _stream(stream)
         off = _ptr(offsets_dev)
-        _check(L.cv_batch_sort_records(ctypes.byref(_records_struct(rec)), off, self.S, self.max_journeys,
-                                       _ptr(self.perm), ctypes.byref(self._so), _ptr(self.res[0]), _ptr(self.ws_sort),
-                                       self.ws_sort.numel(), s), "cv_batch_sort_records")
         srt = CvRecords(*(_ptr(self.sorted[k]) for k, _ in RECORD_FIELDS), n)
-        _check(L.cv_batch_journey_features(ctypes.byref(srt), off, self.S, ctypes.byref(self._fs), s),
-               "cv_batch_journey_features")
+        if self.fused:
+            _check(L.cv_batch_sort_records_features(ctypes.byref(_records_struct(rec)), off, self.S,
+                                                    self.max_journeys, _ptr(self.perm), ctypes.byref(self._so),
+                                                    ctypes.byref(self._fs), _ptr(self.res[0]), _ptr(self.ws_sort),
+                                                    self.ws_sort.numel(), s), "cv_batch_sort_records_features")
+        else:
+            _check(L.cv_batch_sort_records(ctypes.byref(_records_struct(rec)), off, self.S, self.max_journeys,
+                                           _ptr(self.perm), ctypes.byref(self._so), _ptr(self.res[0]),
+                                           _ptr(self.ws_sort), self.ws_sort.numel(), s), "cv_batch_sort_records")
+            _check(L.cv_batch_journey_features(ctypes.byref(srt), off, self.S, ctypes.byref(self._fs), s),
+                   "cv_batch_journey_features")
         _check(L.cv_batch_journey_summary(ctypes.byref(srt), ctypes.byref(self._fs), off, self.S,
                                           ctypes.byref(self._js), self.jcap, _ptr(self.journey_offsets),
                                           _ptr(self.res[1]), _ptr(self.ws_sum), self.ws_sum.numel(), s),

@@ -471,13 +471,15 @@ bool valid_ptr8(const void* p) { return p == nullptr || cvh::aligned(p, 8); }
 
 namespace {
 
-// The gather fused with the per-point kinematics of the sorted records:
-// every block writes a contiguous tile of GFT sorted records, stages their
-// points (and the two before the tile) in LDS, and evaluates the same
-// stencil as the features kernel (cv_kin.h), so that the sorted columns are
-// not read back from memory.  Thread t owns records t and t + 256 of the
-// tile (LDS positions 2 + t and 258 + t); threads 0 and 1 also fetch the two
-// halo records (positions 0 and 1).
+// The gather fused with the per-point kinematics of the sorted records: every
+// block writes a contiguous tile of GFT sorted records and evaluates the same
+// stencil as the features kernel (cv_kin.h) on them, so that the sorted
+// columns are not read back from memory.  Record t0 + 64 g + l of the tile is
+// lane l of group g = u * 4 + wave (u = 0, 1): its predecessor is lane l - 1
+// of the same group (a lane shuffle), or for lane 0 the last lane of group
+// g - 1, which leaves it in a small LDS edge array.  Edge slot 0 holds record
+// t0 - 2 and slot 1 record t0 - 1 (the tile's predecessor, whose own step
+// thread 0 evaluates); group g's last record goes to slot g + 2.
 constexpr int GFT = 512;
 template <bool SHARDS>
 __global__ void __launch_bounds__(256) k_gather_feat(u32 n, const SortMeta* m, const u64* __restrict__ K0,
@@ -489,11 +491,11 @@ __global__ void __launch_bounds__(256) k_gather_feat(u32 n, const SortMeta* m, c
                                                      u32 S)
 {
     constexpr int GFI = GFT / 256;
-    constexpr int NQ = GFT + 2;
-    __shared__ i64 s_jid[NQ], s_ts[NQ];
-    __shared__ double s_lat[NQ], s_lon[NQ], s_sphi[NQ], s_cphi[NQ], s_v[NQ], s_b[NQ];
-    __shared__ u32 s_f[NQ];
-    const u32 np = m->passes;
+    constexpr int NWB = 256 / WAVE;
+    constexpr int NE = GFI * NWB + 2;
+    __shared__ i64 e_jid[NE], e_ts[NE];
+    __shared__ double e_lat[NE], e_lon[NE], e_sphi[NE], e_cphi[NE], e_v[NE], e_b[NE];
+    __shared__ u32 e_f[NE];
     const u32 tb = m->t_bits;
     const u32 rb = m->rank_bits;
     const u32 ib = m->ib;
@@ -507,21 +509,18 @@ __global__ void __launch_bounds__(256) k_gather_feat(u32 n, const SortMeta* m, c
     const bool ts_in_key = exact && drop == 0;
     const u64 tmin = (u64)unord_i64(m->tmin_ord);
     const u64 tmask = tb >= 64 ? ~0ull : ((1ull << tb) - 1);
-    const u64* K = (np & 1) ? K1 : K0;
+    const u64* K = (m->passes & 1) ? K1 : K0;
     const int t = threadIdx.x;
+    const int w = t / WAVE;
+    const int l = lane_id();
     const long t0 = (long)blockIdx.x * GFT;
-    // slots 0 .. GFI - 1: the tile's records; slot GFI: a halo record (threads 0, 1)
+    // slots 0 .. GFI - 1: the tile's records; slot GFI: threads 0 and 1 fetch
+    // records t0 - 2 and t0 - 1 (the others repeat their first record)
     constexpr int NS = GFI + 1;
     long kk[NS];
-    int qq[NS];
 #pragma unroll
-    for (int u = 0; u < GFI; ++u) {
-        kk[u] = t0 + u * 256 + t;
-        qq[u] = 2 + u * 256 + t;
-    }
-    // other threads repeat their first record there (cached; never stored)
+    for (int u = 0; u < GFI; ++u) kk[u] = t0 + (long)(u * NWB + w) * WAVE + l;
     kk[GFI] = t < 2 ? t0 - 2 + t : kk[0];
-    qq[GFI] = t;
     // the sorted words, their source indices and columns; every load from a
     // clamped index, all issued before any is used
     u64 wv[NS];
@@ -560,22 +559,23 @@ __global__ void __launch_bounds__(256) k_gather_feat(u32 n, const SortMeta* m, c
 #pragma unroll
         for (int u = 0; u < NS; ++u) ot[u] = ts[vv[u]];
     }
-    // shard of each record (batched form): a journey's head, and the source
-    // index made shard-relative
-    u32 shs[NS];
-#pragma unroll
-    for (int u = 0; u < NS; ++u) shs[u] = 0;
-    if (SHARDS) {
-#pragma unroll
-        for (int u = 0; u < NS; ++u) shs[u] = kk[u] >= 0 && kk[u] < (long)n ? shard_of(soff, S, (u64)kk[u]) : 0u;
-    }
+    // sin and cos of each latitude, once per point
+    double osph[NS], ocph[NS];
 #pragma unroll
     for (int u = 0; u < NS; ++u) {
+        osph[u] = 0.0;
+        ocph[u] = 0.0;
+        if (isfinite(ola[u]) && isfinite(olo[u])) sincos(ola[u] * KIN_DEG2RAD, &osph[u], &ocph[u]);
+    }
+    // shard of each record (batched form), for journey heads at shard starts
+    // and shard-relative source indices
+    u32 shs[GFI];
+#pragma unroll
+    for (int u = 0; u < GFI; ++u) shs[u] = SHARDS && kk[u] < (long)n ? shard_of(soff, S, (u64)kk[u]) : 0u;
+#pragma unroll
+    for (int u = 0; u < GFI; ++u) {
         const long k = kk[u];
-        const bool mine = u < GFI || t < 2;
-        if (!mine || k < 0 || k >= (long)n) continue;
-        const int q = qq[u];
-        if (u < GFI) {
+        if (k < (long)n) {
             u32 pv = vv[u];
             if (SHARDS) pv -= (u32)soff[shs[u]];
             perm[k] = pv;
@@ -585,51 +585,84 @@ __global__ void __launch_bounds__(256) k_gather_feat(u32 n, const SortMeta* m, c
             so.lon_deg[k] = olo[u];
             so.speed_mps[k] = osp[u];
         }
-        s_jid[q] = oj[u];
-        s_ts[q] = ot[u];
-        s_lat[q] = ola[u];
-        s_lon[q] = olo[u];
-        double sp = 0.0, cp = 0.0;
-        if (isfinite(ola[u]) && isfinite(olo[u])) sincos(ola[u] * KIN_DEG2RAD, &sp, &cp);
-        s_sphi[q] = sp;
-        s_cphi[q] = cp;
+        if (l == WAVE - 1) {
+            const int e = u * NWB + w + 2;
+            e_jid[e] = oj[u];
+            e_ts[e] = ot[u];
+            e_lat[e] = ola[u];
+            e_lon[e] = olo[u];
+            e_sphi[e] = osph[u];
+            e_cphi[e] = ocph[u];
+        }
+    }
+    if (t < 2) {
+        e_jid[t] = oj[GFI];
+        e_ts[t] = ot[GFI];
+        e_lat[t] = ola[GFI];
+        e_lon[t] = olo[GFI];
+        e_sphi[t] = osph[GFI];
+        e_cphi[t] = ocph[GFI];
     }
     __syncthreads();
-    // steps (q - 1 -> q) of the tile's records, and of the record before the
-    // tile (thread 0: the first output's predecessor)
-    KinStep ks[NS];
+    // steps (k - 1 -> k) of the tile's records; thread 0 also takes the step
+    // of record t0 - 1 (the first record's predecessor)
+    KinStep ks[GFI];
 #pragma unroll
-    for (int u = 0; u < NS; ++u) {
-        ks[u] = KinStep{0.0, 0.0, 0.0, 0.0, 0u};
+    for (int u = 0; u < GFI; ++u) {
         const long k = kk[u];
-        const int q = u < GFI ? qq[u] : 1;
-        const bool mine = u < GFI || t == 0;
-        const long kr = u < GFI ? k : t0 - 1;
-        if (!mine || kr < 0 || kr >= (long)n) {
-            if (u == GFI && t == 0) s_f[1] = 0u;
-            continue;
+        const int g = u * NWB + w;
+        i64 pj = __shfl_up(oj[u], 1, WAVE), pt = __shfl_up(ot[u], 1, WAVE);
+        double pla = __shfl_up(ola[u], 1, WAVE), plo = __shfl_up(olo[u], 1, WAVE);
+        double psph = __shfl_up(osph[u], 1, WAVE), pcph = __shfl_up(ocph[u], 1, WAVE);
+        if (l == 0) {
+            pj = e_jid[g + 1];
+            pt = e_ts[g + 1];
+            pla = e_lat[g + 1];
+            plo = e_lon[g + 1];
+            psph = e_sphi[g + 1];
+            pcph = e_cphi[g + 1];
         }
-        bool head = kr == 0 || s_jid[q - 1] != s_jid[q];
-        if (SHARDS && !head) {
-            const u32 sh = u < GFI ? shs[u] : shard_of(soff, S, (u64)kr);
-            head = soff[sh] == (u64)kr;
+        bool head = k == 0 || pj != oj[u];
+        if (SHARDS && !head && k < (long)n) head = soff[shs[u]] == (u64)k;
+        ks[u] = kin_step(head, isfinite(ola[u]) && isfinite(olo[u]), ot[u], ola[u], olo[u], ocph[u],
+                         isfinite(pla) && isfinite(plo), pt, pla, plo, pcph, psph);
+        if (l == WAVE - 1) {
+            const int e = g + 2;
+            e_f[e] = ks[u].f;
+            e_v[e] = ks[u].v;
+            e_b[e] = ks[u].b;
         }
-        const double la = s_lat[q], lo = s_lon[q], lap = s_lat[q - 1], lop = s_lon[q - 1];
-        ks[u] = kin_step(head, isfinite(la) && isfinite(lo), s_ts[q], la, lo, s_cphi[q],
-                         isfinite(lap) && isfinite(lop), s_ts[q - 1], lap, lop, s_cphi[q - 1], s_sphi[q - 1]);
-        s_v[q] = ks[u].v;
-        s_b[q] = ks[u].b;
-        s_f[q] = ks[u].f;
+    }
+    if (t == 0) {
+        const long kr = t0 - 1;
+        KinStep hs = KinStep{0.0, 0.0, 0.0, 0.0, 0u};
+        if (kr >= 0) {
+            bool head = kr == 0 || e_jid[0] != e_jid[1];
+            if (SHARDS && !head) head = soff[shard_of(soff, S, (u64)kr)] == (u64)kr;
+            const double la = e_lat[1], lo = e_lon[1], lap = e_lat[0], lop = e_lon[0];
+            hs = kin_step(head, isfinite(la) && isfinite(lo), e_ts[1], la, lo, e_cphi[1], isfinite(lap) && isfinite(lop),
+                          e_ts[0], lap, lop, e_cphi[0], e_sphi[0]);
+        }
+        e_f[1] = hs.f;
+        e_v[1] = hs.v;
+        e_b[1] = hs.b;
     }
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < GFI; ++u) {
         const long k = kk[u];
+        const int g = u * NWB + w;
+        u32 pf = (u32)__shfl_up((int)ks[u].f, 1, WAVE);
+        double pv = __shfl_up(ks[u].v, 1, WAVE), pb = __shfl_up(ks[u].b, 1, WAVE);
+        if (l == 0) {
+            pf = e_f[g + 1];
+            pv = e_v[g + 1];
+            pb = e_b[g + 1];
+        }
         if (k >= (long)n) continue;
-        const int q = qq[u];
         u32 f = ks[u].f;
         double acc, dh;
-        kin_final(f, ks[u].v, ks[u].b, ks[u].dts, s_f[q - 1], s_v[q - 1], s_b[q - 1], acc, dh);
+        kin_final(f, ks[u].v, ks[u].b, ks[u].dts, pf, pv, pb, acc, dh);
         fo.step_m[k] = ks[u].step;
         fo.dt_s[k] = ks[u].dts;
         fo.speed_mps[k] = ks[u].v;

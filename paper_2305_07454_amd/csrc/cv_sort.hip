@@ -193,9 +193,11 @@ __global__ void __launch_bounds__(256) k_dict_rank(const u64* __restrict__ sorte
 // Waves walk contiguous windows of 64 records, so the journey-rank digits of a
 // window are usually equal in every lane: such a digit is counted with one LDS
 // add instead of 64 colliding ones.
-// Each wave takes PW windows of 64 records per round, their ids and times
-// loaded together.  SHARDS = false compiles the plain form without the shard
-// search.
+// Each wave takes PW consecutive windows of 64 records per round, their ids
+// and times loaded together; the (id, rank) of a window's last record carries
+// into the next window, so the dictionary is probed only where a run of equal
+// ids starts inside a window or a round.  SHARDS = false compiles the plain
+// form without the shard search.
 constexpr int PW = 4;
 template <bool SHARDS>
 __global__ void __launch_bounds__(256) k_pack_hist(const i64* __restrict__ jid, const i64* __restrict__ ts, u32 n,
@@ -215,33 +217,42 @@ __global__ void __launch_bounds__(256) k_pack_hist(const i64* __restrict__ jid, 
     const int l = lane_id();
     const u64 nw = (u64)gridDim.x * (blockDim.x / WAVE);
     const u64 nwin = ((u64)n + WAVE - 1) / WAVE;
-    for (u64 w0 = (u64)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE; w0 < nwin; w0 += PW * nw) {
+    for (u64 w0 = ((u64)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE) * PW; w0 < nwin; w0 += PW * nw) {
         u64 jv[PW], tv[PW];
 #pragma unroll
         for (int k = 0; k < PW; ++k) {
-            u64 i = (w0 + k * nw) * WAVE + l;
+            u64 i = (w0 + k) * WAVE + l;
             i = i < n ? i : (u64)n - 1;  // past the end: a valid record, not used
             jv[k] = (u64)jid[i];
             tv[k] = (u64)ts[i];
         }
+        // id and rank of the previous window's last record (this round)
+        bool hc = false;
+        u64 cj = 0;
+        u32 cr = 0;
 #pragma unroll
         for (int k = 0; k < PW; ++k) {
-            const u64 wi = w0 + k * nw;
+            const u64 wi = w0 + k;
             if (wi >= nwin) break;
             const u64 i = wi * WAVE + l;
             const bool valid = i < n;
             // only the first lane of each run of equal ids probes the dictionary;
-            // the others take its rank
+            // the others take its rank (lane 0 continues the carried run)
             const u64 j = valid ? jv[k] : EMPTY;
             const u64 jp = __shfl_up(j, 1, WAVE);
-            const bool runhead = l == 0 || j != jp;
+            const bool runhead = l == 0 ? !(hc && j == cj) : j != jp;
             u32 r = 0;
             if (valid && runhead && j != EMPTY) {
                 const u64 sl = dict_find(table, mask, j);
                 r = (sl != ~0ull) ? ranks[sl] : 0u;
             }
             const u64 heads = __ballot(runhead);
-            r = __shfl(r, 63 - __clzll((long long)(heads & (~0ull >> (63 - l)))), WAVE);
+            const u64 upto = heads & (~0ull >> (63 - l));  // run starts at or below this lane
+            const u32 rh = __shfl(r, upto ? 63 - __clzll((long long)upto) : 0, WAVE);
+            r = upto ? rh : cr;
+            cj = __shfl(j, WAVE - 1, WAVE);
+            cr = __shfl(r, WAVE - 1, WAVE);
+            hc = true;
             u64 key = 0;
             if (valid) {
                 if (!bad) {

@@ -143,12 +143,24 @@ def bench_batched(args):
     assert all(x["status"] == 0 for x in bp.results())
     log(f"warm-up done ({time.time() - t:.1f}s)")
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    cvetl.cv_timing_reset()
+    cvetl.cv_timing_enable(True)
+    torch.cuda.synchronize()
     e0.record()
     for _ in range(args.steps):
         bp.run(rec, off_d)
     e1.record()
     torch.cuda.synchronize()
+    cvetl.cv_timing_enable(False)
     ms_batched = e0.elapsed_time(e1) / args.steps
+    rs_b = bp.results()[0]
+    roof_b, pass_ms_b = radix_roofline(cvetl, n, rs_b)
+    stages_b = {}
+    for fam in ("sort_prep", "gather", "features", "gather_features", "summary", "grid_agg", "grid_tail"):
+        ms, c = cvetl.cv_timing_read(fam)
+        if c:
+            stages_b[fam] = round(ms / args.steps, 4)
+    stages_b["sort_passes"] = round(pass_ms_b / args.steps, 4)
     log(f"batched: {ms_batched:.2f} ms per step ({time.time() - t:.1f}s)")
     # plain per-file: one plain pipeline sized for the largest shard, called per shard
     big = max(sizes)
@@ -193,6 +205,11 @@ def bench_batched(args):
                            "unit": "Mrecords/s"},
         "batched_speedup": round(ms_plain / ms_batched, 3),
         "identical_outputs_checked_shard": i,
+        "roofline": roof_b,
+        "stages_ms_per_step": stages_b,
+        "path_roofline": path_roofline(stages_b, n, G, rs_b["key_bits"], rs_b["packed_pass"], ms_batched),
+        "key_bits": rs_b["key_bits"],
+        "packed_from_pass": rs_b["packed_pass"],
     }
     s = json.dumps(line)
     print(s, flush=True)
@@ -339,19 +356,8 @@ def main():
 
     # dominant kernel: the radix scatter passes that run (digit below the key width)
     key_bits = rs["key_bits"]
-    passes = (key_bits + 7) // 8
     p0 = rs["packed_pass"]
-    pass_ms, pass_launches, alg_bytes = 0.0, 0, 0.0
-    per_pass = []
-    for p in range(passes):
-        ms, cnt_l = cvetl.cv_timing_read(f"sort_pass{p}")
-        pass_ms += ms
-        pass_launches += cnt_l
-        alg_bytes += n * pass_bytes(p, p0) * cnt_l
-        per_pass.append(round(ms / max(cnt_l, 1), 4))
-    avg_ms = pass_ms / max(pass_launches, 1)
-    bytes_per_launch = alg_bytes / max(pass_launches, 1)
-    achieved = bytes_per_launch / (avg_ms / 1e3) / 1e9
+    roof, pass_ms = radix_roofline(cvetl, n, rs)
     stages = {}
     for fam in ("sort_prep", "gather", "features", "gather_features", "summary", "grid_agg", "grid_tail"):
         ms, c = cvetl.cv_timing_read(fam)
@@ -394,14 +400,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {desc}", "records": n, "journeys": J, "groups": G,
                    "path": "plain", "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "kernel": "k_radix_pass (stable 8-bit LSD scatter pass)",
-                     "tile_keys": cvetl.cv_tuning_get("sort_tile"),
-                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "avg_launch_ms": round(avg_ms, 5), "launches": pass_launches,
-                     "alg_bytes_per_launch": int(bytes_per_launch), "per_pass_ms": per_pass},
+        "roofline": dict(roof, traffic=traffic),
         "cpu_baseline": cpu,
         "stages_ms_per_step": stages,
+        "path_roofline": path_roofline(stages, n, G, key_bits, p0, ms_step),
         "direction_lattice": direction,
         "dense_lattice": lattice,
         "key_bits": key_bits,
@@ -557,6 +559,52 @@ def bench_csv(r, dev, rows=4_000_000):
             "text_gbs": round(len(text) / ms / 1e6, 1), "mrows_per_s": round(m / ms / 1e3, 1)}
     log(f"csv: {info}")
     return info
+
+
+def radix_roofline(cvetl, n, rs, traffic=None):
+    """Roofline of the record sort's radix scatter passes from the per-pass
+    HIP-event timing families (working passes only: digits below the key
+    width)."""
+    key_bits = rs["key_bits"]
+    passes = (key_bits + 7) // 8
+    p0 = rs["packed_pass"]
+    pass_ms, launches, alg = 0.0, 0, 0.0
+    per_pass = []
+    for p in range(passes):
+        ms, c = cvetl.cv_timing_read(f"sort_pass{p}")
+        pass_ms += ms
+        launches += c
+        alg += n * pass_bytes(p, p0) * c
+        per_pass.append(round(ms / max(c, 1), 4))
+    avg_ms = pass_ms / max(launches, 1)
+    per_launch = alg / max(launches, 1)
+    achieved = per_launch / (avg_ms / 1e3) / 1e9 if avg_ms > 0 else 0.0
+    return {"bound": "hbm", "kernel": "k_radix_pass (stable 8-bit LSD scatter pass)",
+            "tile_keys": cvetl.cv_tuning_get("sort_tile"),
+            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "avg_launch_ms": round(avg_ms, 5), "launches": launches,
+            "alg_bytes_per_launch": int(per_launch), "per_pass_ms": per_pass}, pass_ms
+
+
+def path_roofline(stages, n, G, key_bits, p0, ms_step):
+    """Algorithmic bytes of the whole path per step (the per-record figures of
+    each stage's kernels, plus the group tail) over the measured step time."""
+    passes = (key_bits + 7) // 8
+    ts_read = 0 if p0 == 0 else 8  # the time offset survives in the final word only when nothing was dropped
+    per = {"sort_prep": 16 + 24, "sort_passes": sum(pass_bytes(p, p0) for p in range(passes))}
+    if "gather_features" in stages:
+        per["gather_features"] = 8 + ts_read + 20 + 4 + 36 + 49
+    else:
+        per["gather"] = 8 + ts_read + 20 + 4 + 36
+        per["features"] = 32 + 49
+    per["summary"] = 8 + 45
+    per["grid_agg"] = 36
+    total = n * sum(per.values()) + 64 * G
+    gbs = total / (ms_step / 1e3) / 1e9
+    return {"bound": "hbm", "alg_bytes_per_record": per, "group_tail_bytes_per_group": 64,
+            "alg_bytes_per_step": int(total), "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4)}
 
 
 def pass_bytes(p, p0):

@@ -254,6 +254,18 @@ __device__ __forceinline__ u32 shard_of(const u64* __restrict__ off, u32 S, u64 
     return lo;
 }
 
+// the same, walking forward from a shard s <= shard_of(r) (a shard holding an
+// earlier record): a few steps, then a binary search for long walks
+__device__ __forceinline__ u32 shard_from(const u64* __restrict__ off, u32 S, u32 s, u64 r)
+{
+#pragma unroll 1
+    for (int i = 0; i < 4; ++i) {
+        if (s + 1 >= S || off[s + 1] > r) return s;
+        ++s;
+    }
+    return shard_of(off, S, r);
+}
+
 __device__ __forceinline__ bool shard_start(const u64* __restrict__ off, u32 S, u64 r)
 {
     return S > 0 && off[shard_of(off, S, r)] == r;

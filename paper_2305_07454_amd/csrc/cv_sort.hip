@@ -193,11 +193,12 @@ __global__ void __launch_bounds__(256) k_dict_rank(const u64* __restrict__ sorte
 // Waves walk contiguous windows of 64 records, so the journey-rank digits of a
 // window are usually equal in every lane: such a digit is counted with one LDS
 // add instead of 64 colliding ones.
-// Each wave takes PW consecutive windows of 64 records per round, their ids
-// and times loaded together; the (id, rank) of a window's last record carries
-// into the next window, so the dictionary is probed only where a run of equal
-// ids starts inside a window or a round.  SHARDS = false compiles the plain
-// form without the shard search.
+// Each wave walks its own contiguous range of windows of 64 records, PW
+// windows per round with their ids and times loaded together; the (id, rank)
+// of a window's last record carries into the next window, so the dictionary
+// is probed only where a run of equal ids starts, and the shard (batched form)
+// is followed forward from the range's first one.  SHARDS = false compiles the
+// plain form without the shard search.
 constexpr int PW = 4;
 template <bool SHARDS>
 __global__ void __launch_bounds__(256) k_pack_hist(const i64* __restrict__ jid, const i64* __restrict__ ts, u32 n,
@@ -217,7 +218,16 @@ __global__ void __launch_bounds__(256) k_pack_hist(const i64* __restrict__ jid, 
     const int l = lane_id();
     const u64 nw = (u64)gridDim.x * (blockDim.x / WAVE);
     const u64 nwin = ((u64)n + WAVE - 1) / WAVE;
-    for (u64 w0 = ((u64)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE) * PW; w0 < nwin; w0 += PW * nw) {
+    const u64 per = ((nwin + nw - 1) / nw + PW - 1) / PW * PW;  // windows per wave, whole rounds
+    const u64 wbeg = ((u64)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE) * per;
+    const u64 wend = wbeg + per < nwin ? wbeg + per : nwin;
+    // id and rank of the previous window's last record
+    bool hc = false;
+    u64 cj = 0;
+    u32 cr = 0;
+    // shard of the current window's first record (batched form; wave-uniform)
+    u32 shw = (SHARDS && wbeg < wend) ? shard_of(soff, S, wbeg * WAVE) : 0u;
+    for (u64 w0 = wbeg; w0 < wend; w0 += PW) {
         u64 jv[PW], tv[PW];
 #pragma unroll
         for (int k = 0; k < PW; ++k) {
@@ -226,14 +236,10 @@ __global__ void __launch_bounds__(256) k_pack_hist(const i64* __restrict__ jid, 
             jv[k] = (u64)jid[i];
             tv[k] = (u64)ts[i];
         }
-        // id and rank of the previous window's last record (this round)
-        bool hc = false;
-        u64 cj = 0;
-        u32 cr = 0;
 #pragma unroll
         for (int k = 0; k < PW; ++k) {
             const u64 wi = w0 + k;
-            if (wi >= nwin) break;
+            if (wi >= wend) break;
             const u64 i = wi * WAVE + l;
             const bool valid = i < n;
             // only the first lane of each run of equal ids probes the dictionary;
@@ -259,8 +265,8 @@ __global__ void __launch_bounds__(256) k_pack_hist(const i64* __restrict__ jid, 
                     key = (tb >= 64 ? 0ull : ((u64)r << tb)) | (tv[k] - tmin);
                     if (SHARDS) {
                         // the window's first shard, then forward to this record's
-                        u32 sh = shard_of(soff, S, wi * WAVE);
-                        while (sh + 1 < S && soff[sh + 1] <= i) ++sh;
+                        shw = __builtin_amdgcn_readfirstlane(shard_from(soff, S, shw, wi * WAVE));
+                        const u32 sh = shard_from(soff, S, shw, i);
                         key |= (u64)sh << (m->rank_bits + tb);
                     }
                 }
@@ -507,6 +513,7 @@ __global__ void __launch_bounds__(256) k_gather_feat(u32 n, const SortMeta* m, c
     __shared__ i64 e_jid[NE], e_ts[NE];
     __shared__ double e_lat[NE], e_lon[NE], e_sphi[NE], e_cphi[NE], e_v[NE], e_b[NE];
     __shared__ u32 e_f[NE];
+    __shared__ u32 s_sh0;  // shard of record t0 - 2 (batched form)
     const u32 tb = m->t_bits;
     const u32 rb = m->rank_bits;
     const u32 ib = m->ib;
@@ -532,6 +539,7 @@ __global__ void __launch_bounds__(256) k_gather_feat(u32 n, const SortMeta* m, c
 #pragma unroll
     for (int u = 0; u < GFI; ++u) kk[u] = t0 + (long)(u * NWB + w) * WAVE + l;
     kk[GFI] = t < 2 ? t0 - 2 + t : kk[0];
+    if (SHARDS && t == 0) s_sh0 = shard_of(soff, S, (u64)(t0 >= 2 ? t0 - 2 : 0));
     // the sorted words, their source indices and columns; every load from a
     // clamped index, all issued before any is used
     u64 wv[NS];
@@ -578,18 +586,11 @@ __global__ void __launch_bounds__(256) k_gather_feat(u32 n, const SortMeta* m, c
         ocph[u] = 0.0;
         if (isfinite(ola[u]) && isfinite(olo[u])) sincos(ola[u] * KIN_DEG2RAD, &osph[u], &ocph[u]);
     }
-    // shard of each record (batched form), for journey heads at shard starts
-    // and shard-relative source indices
-    u32 shs[GFI];
-#pragma unroll
-    for (int u = 0; u < GFI; ++u) shs[u] = SHARDS && kk[u] < (long)n ? shard_of(soff, S, (u64)kk[u]) : 0u;
 #pragma unroll
     for (int u = 0; u < GFI; ++u) {
         const long k = kk[u];
         if (k < (long)n) {
-            u32 pv = vv[u];
-            if (SHARDS) pv -= (u32)soff[shs[u]];
-            perm[k] = pv;
+            if (!SHARDS) perm[k] = vv[u];
             so.journey_id[k] = oj[u];
             so.ts_ms[k] = ot[u];
             so.lat_deg[k] = ola[u];
@@ -615,6 +616,17 @@ __global__ void __launch_bounds__(256) k_gather_feat(u32 n, const SortMeta* m, c
         e_cphi[t] = ocph[GFI];
     }
     __syncthreads();
+    // shard of each record (batched form), walked forward from the tile's
+    // first one: journey heads at shard starts, shard-relative source indices
+    u32 shs[GFI];
+#pragma unroll
+    for (int u = 0; u < GFI; ++u) {
+        shs[u] = 0;
+        if (SHARDS && kk[u] < (long)n) {
+            shs[u] = shard_from(soff, S, s_sh0, (u64)kk[u]);
+            perm[kk[u]] = vv[u] - (u32)soff[shs[u]];
+        }
+    }
     // steps (k - 1 -> k) of the tile's records; thread 0 also takes the step
     // of record t0 - 1 (the first record's predecessor)
     KinStep ks[GFI];
@@ -649,7 +661,7 @@ __global__ void __launch_bounds__(256) k_gather_feat(u32 n, const SortMeta* m, c
         KinStep hs = KinStep{0.0, 0.0, 0.0, 0.0, 0u};
         if (kr >= 0) {
             bool head = kr == 0 || e_jid[0] != e_jid[1];
-            if (SHARDS && !head) head = soff[shard_of(soff, S, (u64)kr)] == (u64)kr;
+            if (SHARDS && !head) head = soff[shard_from(soff, S, s_sh0, (u64)kr)] == (u64)kr;
             const double la = e_lat[1], lo = e_lon[1], lap = e_lat[0], lop = e_lon[0];
             hs = kin_step(head, isfinite(la) && isfinite(lo), e_ts[1], la, lo, e_cphi[1], isfinite(lap) && isfinite(lop),
                           e_ts[0], lap, lop, e_cphi[0], e_sphi[0]);

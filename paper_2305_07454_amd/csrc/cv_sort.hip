@@ -44,6 +44,7 @@ struct SortMeta {
     u32 shard_bits;
     u32 ib;   // index bits of a packed key word
     u32 p0;   // first pass whose input words are packed (ib and p0 adjacent: the radix passes read both)
+    u32 n_runs;  // runs of equal ids in input order (dictionary probes of the key packing)
     u32 tickets[2 * MAX_PASSES];
 };
 
@@ -59,14 +60,19 @@ __global__ void k_sort_init(SortMeta* m)
     }
 }
 
+// The dictionary is an open-addressing table of 16-byte slots {id, rank}:
+// the id word is claimed by CAS (EMPTY when free) and the rank word is filled
+// in once the distinct ids are sorted, so that one 16-byte load per probe
+// returns both.
 __device__ __forceinline__ bool dict_insert(u64* table, u64 mask, u64 key)
 {
     u64 h = mix64(key) & mask;
     for (u64 probe = 0; probe <= mask; ++probe) {
-        u64 cur = table[h];
+        u64 cur = table[2 * h];
         if (cur == key) return true;
         if (cur == EMPTY) {
-            u64 prev = atomicCAS((unsigned long long*)&table[h], (unsigned long long)EMPTY, (unsigned long long)key);
+            u64 prev =
+                atomicCAS((unsigned long long*)&table[2 * h], (unsigned long long)EMPTY, (unsigned long long)key);
             if (prev == EMPTY || prev == key) return true;
         }
         h = (h + 1) & mask;
@@ -74,11 +80,12 @@ __device__ __forceinline__ bool dict_insert(u64* table, u64 mask, u64 key)
     return false;
 }
 
+// slot of `key`, or ~0 when absent
 __device__ __forceinline__ u64 dict_find(const u64* table, u64 mask, u64 key)
 {
     u64 h = mix64(key) & mask;
     for (u64 probe = 0; probe <= mask; ++probe) {
-        u64 cur = table[h];
+        u64 cur = table[2 * h];
         if (cur == key) return h;
         if (cur == EMPTY) return ~0ull;
         h = (h + 1) & mask;
@@ -86,23 +93,94 @@ __device__ __forceinline__ u64 dict_find(const u64* table, u64 mask, u64 key)
     return ~0ull;
 }
 
+// rank of `key` (0 when absent), one 16-byte load per probe
+__device__ __forceinline__ u32 dict_rank_of(const u64* table, u64 mask, u64 key)
+{
+    const ulonglong2* t2 = (const ulonglong2*)table;
+    u64 h = mix64(key) & mask;
+    for (u64 probe = 0; probe <= mask; ++probe) {
+        const ulonglong2 e = t2[h];
+        if (e.x == key) return (u32)e.y;
+        if (e.x == EMPTY) return 0u;
+        h = (h + 1) & mask;
+    }
+    return 0u;
+}
+
+// Each wave of the dictionary kernels walks its own contiguous range of
+// windows of 64 records and keeps the ids it met last in a small LDS cache
+// (direct-mapped, DC slots per wave): in time-ordered input, where many
+// journeys interleave, a window's ids mostly appeared in the windows just
+// before, and the cache spares those records the probe of the global table.
+// A slot is written by one lane only (the lanes that miss on a slot elect
+// one through the owner word), so an entry is never a mix of two writes.
+constexpr int DC = 256;
+constexpr int DPW = 4;  // windows whose ids and times are loaded together
+
+__device__ __forceinline__ void wave_range(u32 n, u64& wbeg, u64& wend)
+{
+    const u64 nw = (u64)gridDim.x * (blockDim.x / WAVE);
+    const u64 nwin = ((u64)n + WAVE - 1) / WAVE;
+    const u64 per = (nwin + nw - 1) / nw;
+    wbeg = ((u64)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE) * per;
+    wend = wbeg + per < nwin ? wbeg + per : nwin;
+}
+
+__device__ __forceinline__ u32 dict_cache_slot(u64 key) { return (u32)(mix64(key) >> 56) & (DC - 1); }
+
 __global__ void __launch_bounds__(256) k_dict_insert(const i64* __restrict__ jid, const i64* __restrict__ ts, u32 n,
                                                      u64* __restrict__ table, u64 mask, SortMeta* m)
 {
     __shared__ u64 s_min[4], s_max[4];
+    __shared__ u64 c_key[4][DC];
+    __shared__ u32 c_own[4][DC];
+    const int w = threadIdx.x / WAVE;
+    const int l = lane_id();
+    for (int i = l; i < DC; i += WAVE) c_key[w][i] = EMPTY;  // EMPTY is never looked up
     u64 lo = ~0ull, hi = 0;
     bool has_min = false, full = false;
-    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        i64 j = jid[i];
-        u64 t = ord_i64(ts[i]);
-        lo = t < lo ? t : lo;
-        hi = t > hi ? t : hi;
-        if (i > 0 && jid[i - 1] == j) continue;
-        if ((u64)j == EMPTY) {
-            has_min = true;
-            continue;
+    u64 wbeg, wend;
+    wave_range(n, wbeg, wend);
+    i64 prevj = 0;  // last id of the previous window
+    bool hp = false;
+    for (u64 w0 = wbeg; w0 < wend; w0 += DPW) {
+        i64 jv[DPW];
+        u64 tv[DPW];
+#pragma unroll
+        for (int k = 0; k < DPW; ++k) {
+            u64 i = (w0 + k) * WAVE + l;
+            i = i < n ? i : (u64)n - 1;  // past the end: a valid record, not used
+            jv[k] = jid[i];
+            tv[k] = ord_i64(ts[i]);
         }
-        if (!dict_insert(table, mask, (u64)j)) full = true;
+#pragma unroll
+        for (int k = 0; k < DPW; ++k) {
+            if (w0 + k >= wend) break;
+            const u64 i = (w0 + k) * WAVE + l;
+            const bool valid = i < n;
+            const i64 j = jv[k];
+            if (valid) {
+                lo = tv[k] < lo ? tv[k] : lo;
+                hi = tv[k] > hi ? tv[k] : hi;
+            }
+            // a record repeating the id before it adds nothing
+            const i64 jp = __shfl_up(j, 1, WAVE);
+            const bool dup = l == 0 ? (hp && j == prevj) : j == jp;
+            prevj = __shfl(j, WAVE - 1, WAVE);
+            hp = true;
+            bool need = valid && !dup;
+            if (need && (u64)j == EMPTY) {
+                has_min = true;
+                need = false;
+            }
+            const u32 cs = dict_cache_slot((u64)j);
+            const bool miss = need && c_key[w][cs] != (u64)j;
+            if (miss && !dict_insert(table, mask, (u64)j)) full = true;
+            if (miss) c_own[w][cs] = (u32)l;
+            __builtin_amdgcn_wave_barrier();
+            if (miss && c_own[w][cs] == (u32)l) c_key[w][cs] = (u64)j;
+            __builtin_amdgcn_wave_barrier();
+        }
     }
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) {
@@ -110,8 +188,7 @@ __global__ void __launch_bounds__(256) k_dict_insert(const i64* __restrict__ jid
         lo = a < lo ? a : lo;
         hi = b > hi ? b : hi;
     }
-    int w = threadIdx.x / WAVE;
-    if (lane_id() == 0) {
+    if (l == 0) {
         s_min[w] = lo;
         s_max[w] = hi;
     }
@@ -136,7 +213,7 @@ __global__ void __launch_bounds__(256) k_dict_compact(const u64* __restrict__ ta
     const u64 stride = (u64)gridDim.x * blockDim.x;
     for (u64 b = (u64)blockIdx.x * blockDim.x; b < slots; b += stride) {
         const u64 s = b + threadIdx.x;
-        const u64 k = s < slots ? table[s] : EMPTY;
+        const u64 k = s < slots ? table[2 * s] : EMPTY;
         const bool occ = k != EMPTY;
         const u64 msk = __ballot(occ);
         u32 base = 0;
@@ -179,14 +256,14 @@ __global__ void k_dict_meta(SortMeta* m, u32 max_j, u32 n, u32 n_shards)
 }
 
 __global__ void __launch_bounds__(256) k_dict_rank(const u64* __restrict__ sorted_list, const SortMeta* m,
-                                                   const u64* __restrict__ table, u64 mask, u32* __restrict__ ranks)
+                                                   u64* __restrict__ table, u64 mask)
 {
     u32 dn = m->dict_n;
     for (u32 r = blockIdx.x * blockDim.x + threadIdx.x; r < dn; r += gridDim.x * blockDim.x) {
         u64 k = sorted_list[r] ^ SIGN;
         if (k == EMPTY) continue;
         u64 s = dict_find(table, mask, k);
-        if (s != ~0ull) ranks[s] = r;
+        if (s != ~0ull) table[2 * s + 1] = r;
     }
 }
 
@@ -199,16 +276,55 @@ __global__ void __launch_bounds__(256) k_dict_rank(const u64* __restrict__ sorte
 // is probed only where a run of equal ids starts, and the shard (batched form)
 // is followed forward from the range's first one.  SHARDS = false compiles the
 // plain form without the shard search.
+// One input record's payload, packed (the gather's form for interleaved input).
+struct __attribute__((aligned(32))) PayRec {
+    i64 ts;
+    double lat, lon;
+    float spd;
+    u32 pad;
+};
+
+// Input whose runs of equal journey ids are short (journeys interleaved, as in
+// a time-ordered feed) sends the gather through the sort's index to a separate
+// memory segment per record and column; for such input the payload columns
+// are first packed per record, so that the gather reads one 32-byte record.
+constexpr u64 PAY_MIN_RUN = 8;  // mean run length below which the packed form is used
+__device__ __forceinline__ bool pay_packed(const SortMeta* m, u32 n) { return (u64)m->n_runs * PAY_MIN_RUN > n; }
+
+__global__ void __launch_bounds__(256) k_pay_pack(u32 n, const SortMeta* m, const i64* __restrict__ ts,
+                                                  const double* __restrict__ lat, const double* __restrict__ lon,
+                                                  const float* __restrict__ spd, PayRec* __restrict__ pay)
+{
+    if (!pay_packed(m, n)) return;
+    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        PayRec p;
+        p.ts = ts[i];
+        p.lat = lat[i];
+        p.lon = lon[i];
+        p.spd = spd[i];
+        p.pad = 0;
+        pay[i] = p;
+    }
+}
+
 constexpr int PW = 4;
 template <bool SHARDS>
 __global__ void __launch_bounds__(256) k_pack_hist(const i64* __restrict__ jid, const i64* __restrict__ ts, u32 n,
-                                                   const u64* __restrict__ table, const u32* __restrict__ ranks,
-                                                   u64 mask, const SortMeta* m, u64* __restrict__ keys,
+                                                   const u64* __restrict__ table,
+                                                   u64 mask, SortMeta* m, u64* __restrict__ keys,
                                                    u32* __restrict__ hist, const u64* __restrict__ soff, u32 S)
 {
     __shared__ u32 s_h[MAX_PASSES * RADIX];
+    __shared__ u32 s_runs;
+    // per-wave cache of (id, rank) pairs, as in the dictionary insert
+    __shared__ u64 c_key[4][DC];
+    __shared__ u32 c_rank[4][DC], c_own[4][DC];
     for (int i = threadIdx.x; i < MAX_PASSES * RADIX; i += blockDim.x) s_h[i] = 0;
+    for (int i = threadIdx.x; i < 4 * DC; i += blockDim.x) (&c_key[0][0])[i] = EMPTY;
+    if (threadIdx.x == 0) s_runs = 0;
     __syncthreads();
+    const int wv_ = threadIdx.x / WAVE;
+    u32 runs = 0;  // run starts this wave found (wave-uniform)
     const u32 tb = m->t_bits;
     const u32 np = m->passes;
     const bool bad = m->range_err != 0;
@@ -248,11 +364,26 @@ __global__ void __launch_bounds__(256) k_pack_hist(const i64* __restrict__ jid, 
             const u64 jp = __shfl_up(j, 1, WAVE);
             const bool runhead = l == 0 ? !(hc && j == cj) : j != jp;
             u32 r = 0;
-            if (valid && runhead && j != EMPTY) {
-                const u64 sl = dict_find(table, mask, j);
-                r = (sl != ~0ull) ? ranks[sl] : 0u;
+            const bool look = valid && runhead && j != EMPTY;
+            const u32 cs = dict_cache_slot(j);
+            bool miss = false;
+            if (look) {
+                if (c_key[wv_][cs] == j) {
+                    r = c_rank[wv_][cs];
+                } else {
+                    r = dict_rank_of(table, mask, j);
+                    miss = true;
+                }
             }
+            if (miss) c_own[wv_][cs] = (u32)l;
+            __builtin_amdgcn_wave_barrier();
+            if (miss && c_own[wv_][cs] == (u32)l) {
+                c_key[wv_][cs] = j;
+                c_rank[wv_][cs] = r;
+            }
+            __builtin_amdgcn_wave_barrier();
             const u64 heads = __ballot(runhead);
+            runs += (u32)__popcll(heads & __ballot(valid));
             const u64 upto = heads & (~0ull >> (63 - l));  // run starts at or below this lane
             const u32 rh = __shfl(r, upto ? 63 - __clzll((long long)upto) : 0, WAVE);
             r = upto ? rh : cr;
@@ -285,9 +416,11 @@ __global__ void __launch_bounds__(256) k_pack_hist(const i64* __restrict__ jid, 
             }
         }
     }
+    if (lane_id() == 0 && runs) atomicAdd(&s_runs, runs);
     __syncthreads();
     for (u32 i = threadIdx.x; i < np * RADIX; i += blockDim.x)
         if (s_h[i]) atomicAdd(&hist[i], s_h[i]);
+    if (threadIdx.x == 0 && s_runs) atomicAdd(&m->n_runs, s_runs);
 }
 
 // The final words are packed: (key >> 8 p0) << ib | source index.  Every
@@ -429,8 +562,7 @@ __global__ void k_empty_result(cv_result* res)
 
 struct SortLayout {
     SortMeta* meta;
-    u64* table;
-    u32* ranks;
+    u64* table;  // slots x {id, rank}
     u64* dl0;
     u64* dl1;
     u32* dv0;
@@ -445,6 +577,7 @@ struct SortLayout {
     u32* doffs;
     u64* K0;
     u64* K1;
+    PayRec* pay;  // packed payload (interleaved input, fused gather)
     u32* V0;
     u32* V1;
     u64 slots;
@@ -458,8 +591,7 @@ struct SortLayout {
         tiles = (n + sort_min_tile() - 1) / sort_min_tile();
         dtiles = (max_j + sort_min_tile() - 1) / sort_min_tile();
         meta = c.take<SortMeta>(1);
-        table = c.take<u64>(slots);
-        ranks = c.take<u32>(slots);
+        table = c.take<u64>(2 * slots);
         dl0 = c.take<u64>(max_j);
         dl1 = c.take<u64>(max_j);
         dv0 = c.take<u32>(max_j);
@@ -476,6 +608,7 @@ struct SortLayout {
         doffs = c.take<u32>(MAX_PASSES * RADIX);
         K0 = c.take<u64>(n);
         K1 = c.take<u64>(n);
+        pay = c.take<PayRec>(n);
         V0 = c.take<u32>(n);
         V1 = c.take<u32>(n);
         bytes = c.size();
@@ -505,7 +638,7 @@ __global__ void __launch_bounds__(256) k_gather_feat(u32 n, const SortMeta* m, c
                                                      const double* __restrict__ lat, const double* __restrict__ lon,
                                                      const float* __restrict__ spd, u32* __restrict__ perm,
                                                      cv_records_out so, cv_features fo, const u64* __restrict__ soff,
-                                                     u32 S)
+                                                     u32 S, const PayRec* __restrict__ pay)
 {
     constexpr int GFI = GFT / 256;
     constexpr int NWB = 256 / WAVE;
@@ -554,11 +687,25 @@ __global__ void __launch_bounds__(256) k_gather_feat(u32 n, const SortMeta* m, c
     double ola[NS], olo[NS];
     float osp[NS];
     i64 oj[NS], ot[NS];
+    i64 pts[NS];  // time stamps read with the packed payload
+    const bool packed = pay_packed(m, n);
+    if (packed) {
 #pragma unroll
-    for (int u = 0; u < NS; ++u) {
-        ola[u] = lat[vv[u]];
-        olo[u] = lon[vv[u]];
-        osp[u] = spd[vv[u]];
+        for (int u = 0; u < NS; ++u) {
+            const ulonglong2* q = (const ulonglong2*)(pay + vv[u]);
+            const ulonglong2 a = q[0], b = q[1];
+            pts[u] = (i64)a.x;
+            ola[u] = __longlong_as_double((long long)a.y);
+            olo[u] = __longlong_as_double((long long)b.x);
+            osp[u] = __uint_as_float((u32)b.y);
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < NS; ++u) {
+            ola[u] = lat[vv[u]];
+            olo[u] = lon[vv[u]];
+            osp[u] = spd[vv[u]];
+        }
     }
     if (rank_in_key) {
 #pragma unroll
@@ -574,6 +721,9 @@ __global__ void __launch_bounds__(256) k_gather_feat(u32 n, const SortMeta* m, c
     if (ts_in_key) {
 #pragma unroll
         for (int u = 0; u < NS; ++u) ot[u] = (i64)(tmin + ((wv[u] >> ib) & tmask));
+    } else if (packed) {
+#pragma unroll
+        for (int u = 0; u < NS; ++u) ot[u] = pts[u];
     } else {
 #pragma unroll
         for (int u = 0; u < NS; ++u) ot[u] = ts[vv[u]];
@@ -731,7 +881,7 @@ static cv_status sort_impl(const cv_records* in, const uint64_t* soff, uint32_t 
     {
         cvh::TimedScope ts_("sort_prep", s);
         hipLaunchKernelGGL(k_sort_init, dim3(1), dim3(64), 0, s, L.meta);
-        cvh::fill_u64(L.table, EMPTY, L.slots, s);
+        cvh::fill_u64(L.table, EMPTY, 2 * L.slots, s);
         cvh::fill_u32(L.zero_begin, 0u, L.zero_bytes / 4, s);
         hipLaunchKernelGGL(k_dict_insert, dim3(gs), dim3(256), 0, s, in->journey_id, in->ts_ms, nn, L.table, mask,
                            L.meta);
@@ -745,10 +895,15 @@ static cv_status sort_impl(const cv_records* in, const uint64_t* soff, uint32_t 
         radix_passes(L.dl0, L.dl1, nullptr, L.dv0, L.dv1, mj, dn, nullptr, MAX_PASSES, L.doffs, L.dstatus,
                      L.meta->tickets + MAX_PASSES, s);
         hipLaunchKernelGGL(k_dict_rank, dim3(cvh::grid_for(max_journeys, 256, 1024)), dim3(256), 0, s, L.dl0, L.meta,
-                           L.table, mask, L.ranks);
+                           L.table, mask);
         hipLaunchKernelGGL(S > 1 ? k_pack_hist<true> : k_pack_hist<false>, dim3(gs), dim3(256), 0, s, in->journey_id,
-                           in->ts_ms, nn, L.table, L.ranks, mask, L.meta, L.K0, L.hist, soff, S);
+                           in->ts_ms, nn, L.table, mask, L.meta, L.K0, L.hist, soff, S);
         radix_scan(L.hist, L.offs, MAX_PASSES, s);
+        // interleaved input: the payload packed per record for the fused gather
+        // (the kernel returns at once for input in runs)
+        if (feat)
+            hipLaunchKernelGGL(k_pay_pack, dim3(gs), dim3(256), 0, s, nn, L.meta, in->ts_ms, in->lat_deg,
+                               in->lon_deg, in->speed_mps, L.pay);
     }
     radix_passes(L.K0, L.K1, nullptr, L.V0, L.V1, nn, nullptr, &L.meta->key_bits, MAX_PASSES, L.offs, L.status,
                  L.meta->tickets, s, /*timed=*/true, &L.meta->ib);
@@ -757,7 +912,7 @@ static cv_status sort_impl(const cv_records* in, const uint64_t* soff, uint32_t 
         auto gk = S > 1 ? k_gather_feat<true> : k_gather_feat<false>;
         hipLaunchKernelGGL(gk, dim3((unsigned)((n + GFT - 1) / GFT)), dim3(256), 0, s, nn, L.meta, L.K0, L.K1, L.dl0,
                            in->journey_id, in->ts_ms, in->lat_deg, in->lon_deg, in->speed_mps, perm, so, *feat, soff,
-                           S);
+                           S, L.pay);
     } else {
         cvh::TimedScope ts_("gather", s);
         const bool full = so.journey_id && so.ts_ms && so.lat_deg && so.lon_deg && so.speed_mps;

@@ -114,7 +114,8 @@ __device__ __forceinline__ u32 dict_rank_of(const u64* table, u64 mask, u64 key)
 // before, and the cache spares those records the probe of the global table.
 // A slot is written by one lane only (the lanes that miss on a slot elect
 // one through the owner word), so an entry is never a mix of two writes.
-constexpr int DC = 256;
+constexpr int DC = 256;   // slots per wave in the insert
+constexpr int DCP = 128;  // slots per wave in the key packing (16 KB of LDS per workgroup with the histograms)
 constexpr int DPW = 4;  // windows whose ids and times are loaded together
 
 __device__ __forceinline__ void wave_range(u32 n, u64& wbeg, u64& wend)
@@ -126,7 +127,11 @@ __device__ __forceinline__ void wave_range(u32 n, u64& wbeg, u64& wend)
     wend = wbeg + per < nwin ? wbeg + per : nwin;
 }
 
-__device__ __forceinline__ u32 dict_cache_slot(u64 key) { return (u32)(mix64(key) >> 56) & (DC - 1); }
+template <int C>
+__device__ __forceinline__ u32 dict_cache_slot(u64 key)
+{
+    return (u32)(mix64(key) >> 56) & (C - 1);
+}
 
 __global__ void __launch_bounds__(256) k_dict_insert(const i64* __restrict__ jid, const i64* __restrict__ ts, u32 n,
                                                      u64* __restrict__ table, u64 mask, SortMeta* m)
@@ -173,7 +178,7 @@ __global__ void __launch_bounds__(256) k_dict_insert(const i64* __restrict__ jid
                 has_min = true;
                 need = false;
             }
-            const u32 cs = dict_cache_slot((u64)j);
+            const u32 cs = dict_cache_slot<DC>((u64)j);
             const bool miss = need && c_key[w][cs] != (u64)j;
             if (miss && !dict_insert(table, mask, (u64)j)) full = true;
             if (miss) c_own[w][cs] = (u32)l;
@@ -317,10 +322,10 @@ __global__ void __launch_bounds__(256) k_pack_hist(const i64* __restrict__ jid, 
     __shared__ u32 s_h[MAX_PASSES * RADIX];
     __shared__ u32 s_runs;
     // per-wave cache of (id, rank) pairs, as in the dictionary insert
-    __shared__ u64 c_key[4][DC];
-    __shared__ u32 c_rank[4][DC], c_own[4][DC];
+    __shared__ u64 c_key[4][DCP];
+    __shared__ u32 c_rank[4][DCP], c_own[4][DCP];
     for (int i = threadIdx.x; i < MAX_PASSES * RADIX; i += blockDim.x) s_h[i] = 0;
-    for (int i = threadIdx.x; i < 4 * DC; i += blockDim.x) (&c_key[0][0])[i] = EMPTY;
+    for (int i = threadIdx.x; i < 4 * DCP; i += blockDim.x) (&c_key[0][0])[i] = EMPTY;
     if (threadIdx.x == 0) s_runs = 0;
     __syncthreads();
     const int wv_ = threadIdx.x / WAVE;
@@ -365,7 +370,7 @@ __global__ void __launch_bounds__(256) k_pack_hist(const i64* __restrict__ jid, 
             const bool runhead = l == 0 ? !(hc && j == cj) : j != jp;
             u32 r = 0;
             const bool look = valid && runhead && j != EMPTY;
-            const u32 cs = dict_cache_slot(j);
+            const u32 cs = dict_cache_slot<DCP>(j);
             bool miss = false;
             if (look) {
                 if (c_key[wv_][cs] == j) {

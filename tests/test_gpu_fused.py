@@ -1,7 +1,9 @@
 """Sort fused with the kinematics (cv_sort_records_features and its batched
 form) against the oracle, and bit for bit against the two separate calls
 (cv_sort_records + cv_journey_features), on ragged sizes around the fused
-kernel's 512-record tile, adversarial columns and uneven shards."""
+kernel's 512-record tile, adversarial columns and uneven shards, with input
+both in journey runs (the gather reads the columns) and interleaved (it reads
+the payload packed per record)."""
 import numpy as np
 import pytest
 
@@ -125,3 +127,47 @@ def test_fused_rejects_missing_columns(cv):
     st = L.cv_sort_records_features(ctypes.byref(cv._records_struct(rec)), 16, None, ctypes.byref(so),
                                     ctypes.byref(fs), None, None, 0, None)
     assert n > 0 and st == cv.CV_ERR_INVALID_ARGUMENT
+
+
+def _mean_run(jid):
+    jid = np.asarray(jid)
+    return len(jid) / max(1, 1 + int(np.count_nonzero(jid[1:] != jid[:-1])))
+
+
+def test_fused_contiguous_input(cv):
+    # journeys in runs (per-journey files): the gather reads the input columns
+    r = gen.make_c1(seed=44, n_journeys=60, median=900.0)
+    assert _mean_run(r.journey_id) >= 8
+    print(f"[fused] contiguous n={r.n}", flush=True)
+    perm, srt, feat, _ = _fused_vs_separate(cv, r.columns(), 1024)
+    exp = oracle.run_plain(r.columns(), gen.GRIDS["c1"])
+    check_sort(perm, srt, exp["perm"], exp["sorted"])
+    check_features(feat, exp["features"])
+
+
+def test_fused_payload_forms_agree(cv):
+    # the same records (no repeated (id, time) pair, so the sorted order does
+    # not depend on the input order) once in journey runs and once interleaved:
+    # the gather reads the columns in the first case and the packed per-record
+    # payload in the second; sorted columns and features must be the same bits
+    rng = np.random.default_rng(45)
+    n_j, per = 300, 200
+    jid = np.repeat(rng.choice(np.arange(10**6, dtype=np.int64), n_j, replace=False), per)
+    ts = gen.T0_MS + np.tile(np.arange(per, dtype=np.int64) * 1000, n_j) + np.repeat(rng.integers(0, 10**6, n_j), per)
+    lat = 38.0 + np.cumsum(rng.normal(0, 2e-4, n_j * per))
+    lon = -92.0 + np.cumsum(rng.normal(0, 2e-4, n_j * per))
+    lat[rng.random(n_j * per) < 0.003] = np.nan
+    spd = rng.uniform(0, 40, n_j * per).astype(np.float32)
+    a = (jid, ts, lat, lon, spd)
+    shuf = rng.permutation(n_j * per)
+    b = tuple(c[shuf] for c in a)
+    assert _mean_run(a[0]) >= 8 and _mean_run(b[0]) < 8
+    print(f"[fused] payload forms n={n_j * per}", flush=True)
+    pa, sa, fa, _ = cv.cv_sort_records_features(cv.to_device(a), 4096)
+    pb, sb, fb, _ = cv.cv_sort_records_features(cv.to_device(b), 4096)
+    for k in sa:
+        _same_bits(f"sorted.{k}", sa[k], sb[k])
+    for k in fa:
+        _same_bits(f"features.{k}", fa[k], fb[k])
+    # both index the same original records
+    assert np.array_equal(host(pa).astype(np.int64), shuf[host(pb).astype(np.int64)])

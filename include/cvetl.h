@@ -202,7 +202,9 @@ cv_status cv_batch_sort_records_features(const cv_records* in, const uint64_t* s
 /* ------------------------------------------------------------------------
  * cv_journey_summary -- one row per journey (maximal run of equal journey_id)
  * of sorted records, in ascending journey id, from the records and their
- * features (step_m, speed_mps and flags are read).  Rows past `capacity` are
+ * features (step_m, speed_mps and flags are read; `feat` must be the features
+ * of these records as cv_journey_features computes them: the FIRST flags
+ * mark the journeys' first records, which delimit the sums).  Rows past `capacity` are
  * not written; then res->status = CV_ERR_CAPACITY, res->required = journeys.
  * res->count = number of journeys.
  * --------------------------------------------------------------------- */

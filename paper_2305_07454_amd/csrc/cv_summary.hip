@@ -92,6 +92,38 @@ __global__ void __launch_bounds__(SB) k_sum_count(const i64* __restrict__ jid, u
     }
 }
 
+// The same counts from the features' FIRST flags (set exactly at journey and
+// shard starts): one byte per record instead of an id and its predecessor.
+__global__ void __launch_bounds__(SB) k_sum_count_flags(const uint8_t* __restrict__ flags, u32 n,
+                                                        u32* __restrict__ wcnt, u32* __restrict__ tcnt)
+{
+    __shared__ u32 s_w[NW];
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    const u64 cs = (u64)blockIdx.x * ST + (u64)w * WCH;
+    const u64 ce = cs + WCH < n ? cs + WCH : (u64)n;
+    u32 c = 0;
+    if (cs < ce) {
+        uint8_t fv[WI];
+#pragma unroll
+        for (int k = 0; k < WI; ++k) {
+            const u64 r = cs + (u64)k * WAVE + lane_id();
+            fv[k] = r < ce ? flags[r] : (uint8_t)0;
+        }
+#pragma unroll
+        for (int k = 0; k < WI; ++k) c += (u32)__popcll(__ballot((fv[k] & CV_FLAG_FIRST) != 0));
+    }
+    if (lane_id() == 0) {
+        wcnt[(u64)blockIdx.x * NW + w] = c;
+        s_w[w] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        u32 t = 0;
+        for (int k = 0; k < NW; ++k) t += s_w[k];
+        tcnt[blockIdx.x] = t;
+    }
+}
+
 // single block: tile_prefix[i] = journey starts before tile i; meta->J = total.
 // Each thread sums a contiguous run of tiles, one block scan joins the runs.
 constexpr int SCAN_B = 1024;
@@ -412,7 +444,9 @@ __device__ __forceinline__ void flush_part(JAcc* acc, u32 cap, u32 j, const Part
 // first record; BOX = false reduces PartSum.  SHARDS = false compiles the
 // plain form without the shard branches, whose loads would otherwise make
 // every window wait for all loads in flight, prefetch included.
-template <bool BOX, bool SHARDS>
+// FL = true (sums only): journey starts are read from the features' FIRST
+// flags, which the sums' pass loads anyway, instead of comparing ids.
+template <bool BOX, bool SHARDS, bool FL = false>
 __global__ void __launch_bounds__(SB) k_sum_reduce(u32 n, const i64* __restrict__ jid, const double* __restrict__ lat,
                                                    const double* __restrict__ lon, const float* __restrict__ spd, const double* __restrict__ step,
                                                    const double* __restrict__ dspd, const uint8_t* __restrict__ flags,
@@ -435,10 +469,11 @@ __global__ void __launch_bounds__(SB) k_sum_reduce(u32 n, const i64* __restrict_
     // open journey: the one containing the record before the next window
     u32 open_j = seen - 1;   // valid when the chunk starts mid-journey
     bool open_here = false;  // its first record lies in this chunk
-    i64 jprev = cs > 0 ? jid[cs - 1] : 0;
-    u32 sk = SHARDS ? shard_lower_bound(soff, S, cs) : 0u;
+    static_assert(!(FL && BOX), "the box pass writes ids");
+    i64 jprev = (!FL && cs > 0) ? jid[cs - 1] : 0;
+    u32 sk = (SHARDS && !FL) ? shard_lower_bound(soff, S, cs) : 0u;
     // the id after the chunk (its last record may end a journey)
-    const i64 jend = ce < n ? jid[ce] : 0;
+    const i64 jend = (!FL && ce < n) ? jid[ce] : 0;
     // Windows are taken in groups of WG: the columns of a group (ids included)
     // are loaded together, from addresses clamped into the chunk, so that all
     // of a group's loads are in flight at once.
@@ -454,7 +489,7 @@ __global__ void __launch_bounds__(SB) k_sum_reduce(u32 n, const i64* __restrict_
         for (int k = 0; k < WG; ++k) {
             u64 r = cs + (u64)(g0 + k) * WAVE + l;
             r = r < ce ? r : ce - 1;
-            gj[k] = jid[r];
+            gj[k] = FL ? 0 : jid[r];
             if constexpr (BOX) {
                 gx0[k] = lat[r];
                 gx1[k] = lon[r];
@@ -474,7 +509,14 @@ __global__ void __launch_bounds__(SB) k_sum_reduce(u32 n, const i64* __restrict_
             const i64 jv = gj[k];
             u64 smask;
             bool s_end;
-            const u64 H = heads_of(jv, a, ce, jprev, soff, S, sk, smask, s_end);
+            u64 H;
+            if constexpr (FL) {
+                H = __ballot(valid && (gf[k] & CV_FLAG_FIRST) != 0);
+                smask = 0;
+                s_end = false;
+            } else {
+                H = heads_of(jv, a, ce, jprev, soff, S, sk, smask, s_end);
+            }
             const bool h = (H >> l) & 1ull;
             // journey index of this lane's record
             const u32 jl = seen + popc_below(H) + (h ? 1u : 0u) - 1u;
@@ -545,7 +587,8 @@ __global__ void __launch_bounds__(SB) k_sum_reduce(u32 n, const i64* __restrict_
     }
     part_wave_reduce(p);
     if (l == 0) {
-        const bool ends = (ce >= n) || (jend != jprev) || (S > 1 && shard_start(soff, S, ce));
+        const bool ends = FL ? ((ce >= n) || (flags[ce] & CV_FLAG_FIRST) != 0)
+                             : ((ce >= n) || (jend != jprev) || (S > 1 && shard_start(soff, S, ce)));
         flush_part(acc, cap, open_j, p, open_here && ends);
     }
 }
@@ -658,13 +701,14 @@ static cv_status summary_impl(const cv_records* sorted, const cv_features* feat,
     const u32 cap = (u32)(capacity < n ? capacity : n);
     const u32 nn = (u32)n;
     cvh::TimedScope ts_("summary", s);
-    hipLaunchKernelGGL(k_sum_count, dim3((unsigned)L.tiles), dim3(SB), 0, s, sorted->journey_id, nn, L.wcnt, L.tcnt,
-                       soff, S);
+    // journey starts come from the features' FIRST flags here (the features
+    // of these records mark exactly the journey and shard starts)
+    hipLaunchKernelGGL(k_sum_count_flags, dim3((unsigned)L.tiles), dim3(SB), 0, s, feat->flags, nn, L.wcnt, L.tcnt);
     hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(SCAN_B), 0, s, L.tcnt, L.tile_prefix, (u32)L.tiles, L.meta);
     hipLaunchKernelGGL(k_sum_init, dim3(cvh::grid_for(cap, 256, 2048)), dim3(256), 0, s, L.acc, L.accx, L.meta, cap);
     for (const bool box : {true, false}) {
         auto kern = box ? (S > 1 ? k_sum_reduce<true, true> : k_sum_reduce<true, false>)
-                        : (S > 1 ? k_sum_reduce<false, true> : k_sum_reduce<false, false>);
+                        : (S > 1 ? k_sum_reduce<false, true, true> : k_sum_reduce<false, false, true>);
         hipLaunchKernelGGL(kern, dim3((unsigned)L.tiles), dim3(SB), 0, s, nn, sorted->journey_id, sorted->lat_deg,
                            sorted->lon_deg, sorted->speed_mps, feat->step_m, feat->speed_mps, feat->flags,
                            L.tile_prefix, L.wcnt, cap, o, L.acc, L.accx, soff, S, jo);

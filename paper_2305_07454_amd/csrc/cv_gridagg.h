@@ -32,7 +32,7 @@ using GridBearing = GridPlainT<2>;
 constexpr int GB = 256;
 constexpr int GI = 8;
 constexpr int GT = GB * GI;
-constexpr int HALO = 512;
+constexpr int HALO = 256;
 static_assert(HALO % GB == 0, "whole halo rows");
 constexpr int LHS_PROBES = 32;
 struct LSlot {

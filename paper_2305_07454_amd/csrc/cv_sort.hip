@@ -116,7 +116,7 @@ __device__ __forceinline__ u32 dict_rank_of(const u64* table, u64 mask, u64 key)
 // one through the owner word), so an entry is never a mix of two writes.
 constexpr int DC = 256;   // slots per wave in the insert
 constexpr int DCP = 128;  // slots per wave in the key packing (16 KB of LDS per workgroup with the histograms)
-constexpr int DPW = 4;  // windows whose ids and times are loaded together
+constexpr int DPW = 8;  // windows whose ids and times are loaded together
 
 __device__ __forceinline__ void wave_range(u32 n, u64& wbeg, u64& wend)
 {
@@ -213,21 +213,34 @@ __global__ void __launch_bounds__(256) k_dict_insert(const i64* __restrict__ jid
 __global__ void __launch_bounds__(256) k_dict_compact(const u64* __restrict__ table, u64 slots, u32 max_j,
                                                       SortMeta* m, u64* __restrict__ list)
 {
+    // one counter claim per workgroup and round (the list is sorted afterwards,
+    // so the order of the claims does not matter)
+    __shared__ u32 s_wc[256 / WAVE];
+    __shared__ u32 s_base;
     u32 hm = m->has_min;
     if (blockIdx.x == 0 && threadIdx.x == 0 && hm && max_j > 0) list[0] = EMPTY ^ SIGN;
+    const int w = threadIdx.x / WAVE;
     const u64 stride = (u64)gridDim.x * blockDim.x;
     for (u64 b = (u64)blockIdx.x * blockDim.x; b < slots; b += stride) {
         const u64 s = b + threadIdx.x;
         const u64 k = s < slots ? table[2 * s] : EMPTY;
         const bool occ = k != EMPTY;
         const u64 msk = __ballot(occ);
-        u32 base = 0;
-        if (lane_id() == 0 && msk) base = atomicAdd(&m->list_count, (u32)__popcll(msk));
-        base = __shfl(base, 0, WAVE);
+        if (lane_id() == 0) s_wc[w] = (u32)__popcll(msk);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            u32 t = 0;
+            for (int x = 0; x < 256 / WAVE; ++x) t += s_wc[x];
+            s_base = t ? atomicAdd(&m->list_count, t) : 0u;
+        }
+        __syncthreads();
+        u32 base = s_base;
+        for (int x = 0; x < w; ++x) base += s_wc[x];
         if (occ) {
             const u32 pos = base + popc_below(msk) + hm;
             if (pos < max_j) list[pos] = k ^ SIGN;
         }
+        __syncthreads();
     }
 }
 
@@ -312,7 +325,7 @@ __global__ void __launch_bounds__(256) k_pay_pack(u32 n, const SortMeta* m, cons
     }
 }
 
-constexpr int PW = 4;
+constexpr int PW = 8;
 template <bool SHARDS>
 __global__ void __launch_bounds__(256) k_pack_hist(const i64* __restrict__ jid, const i64* __restrict__ ts, u32 n,
                                                    const u64* __restrict__ table,

@@ -189,7 +189,11 @@ cv_status cv_journey_features(const cv_records* sorted, const cv_features* out, 
  * the gather writes each tile of sorted records and evaluates their
  * kinematics from LDS, so the sorted columns are not read back.  Every
  * output is bit for bit that of the two calls.  `sorted` and `feat` must
- * name every column.  Workspace as cv_sort_workspace_size.
+ * name every column.  Workspace as cv_sort_workspace_size (which includes
+ * room for the payload packed per record: when the input's runs of equal
+ * journey ids are short, as in a time-ordered feed, time, lat, lon and speed
+ * are first packed into one 32-byte record per input record, so the gather
+ * reads one record instead of four scattered columns).
  * --------------------------------------------------------------------- */
 cv_status cv_sort_records_features(const cv_records* in, uint64_t max_journeys, uint32_t* perm,
                                    const cv_records_out* sorted, const cv_features* feat, cv_result* res, void* ws,

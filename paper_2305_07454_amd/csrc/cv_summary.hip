@@ -101,16 +101,22 @@ __global__ void __launch_bounds__(SB) k_sum_count_flags(const uint8_t* __restric
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     const u64 cs = (u64)blockIdx.x * ST + (u64)w * WCH;
     const u64 ce = cs + WCH < n ? cs + WCH : (u64)n;
+    static_assert(WCH == WAVE * 16 && CV_FLAG_FIRST == 1u, "16 flag bytes per lane; FIRST is bit 0");
     u32 c = 0;
     if (cs < ce) {
-        uint8_t fv[WI];
-#pragma unroll
-        for (int k = 0; k < WI; ++k) {
-            const u64 r = cs + (u64)k * WAVE + lane_id();
-            fv[k] = r < ce ? flags[r] : (uint8_t)0;
+        // lane l counts the chunk's bytes [16 l, 16 l + 16): one 16-byte load
+        // when the chunk is whole and the column 16-byte aligned
+        const u64 b0 = cs + (u64)lane_id() * 16;
+        if (ce - cs == (u64)WCH && ((uintptr_t)flags & 15u) == 0) {
+            const uint4 v = *reinterpret_cast<const uint4*>(flags + b0);
+            c = (u32)(__popc(v.x & 0x01010101u) + __popc(v.y & 0x01010101u) + __popc(v.z & 0x01010101u) +
+                      __popc(v.w & 0x01010101u));
+        } else {
+            for (int k = 0; k < 16; ++k)
+                if (b0 + k < ce) c += flags[b0 + k] & CV_FLAG_FIRST;
         }
 #pragma unroll
-        for (int k = 0; k < WI; ++k) c += (u32)__popcll(__ballot((fv[k] & CV_FLAG_FIRST) != 0));
+        for (int d = 32; d >= 1; d >>= 1) c += (u32)__shfl_xor((int)c, d, WAVE);
     }
     if (lane_id() == 0) {
         wcnt[(u64)blockIdx.x * NW + w] = c;

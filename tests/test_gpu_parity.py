@@ -323,3 +323,23 @@ def test_extremes_in_exact_sums(cv):
     cols = (r.journey_id, r.ts_ms, lat, r.lon_deg, spd)
     got, exp = _run_both(cv, cols, gen.GRIDS["c0"])
     _check_all(got, exp)
+
+
+def test_summary_flags_column_at_any_alignment(cv):
+    # the journey counts read the features' flags 16 bytes per lane when the
+    # column is 16-byte aligned, byte by byte otherwise: same rows either way
+    import torch
+    r = gen.make_c1(seed=46, n_journeys=40, median=600.0)
+    print(f"[parity] unaligned flags n={r.n}", flush=True)
+    rec = cv.to_device(r)
+    _, srt, _ = cv.cv_sort_records(rec)
+    feat = cv.cv_journey_features(srt)
+    a, ra = cv.cv_journey_summary(srt, feat)
+    buf = torch.zeros(r.n + 1, dtype=torch.uint8, device=feat["flags"].device)
+    buf[1:] = feat["flags"]
+    feat2 = dict(feat)
+    feat2["flags"] = buf[1:]
+    b, rb = cv.cv_journey_summary(srt, feat2)
+    assert ra["count"] == rb["count"]
+    for k in a:
+        assert torch.equal(a[k], b[k]), k

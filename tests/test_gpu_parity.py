@@ -343,3 +343,28 @@ def test_summary_flags_column_at_any_alignment(cv):
     assert ra["count"] == rb["count"]
     for k in a:
         assert torch.equal(a[k], b[k]), k
+
+
+def test_cell_boundaries_and_neighbours(cv):
+    # coordinates on cell boundaries k * d from the origin and one or two ulps
+    # either side, and time stamps on bin edges: the grid kernel's fast
+    # reciprocal estimate defers to the division there, and every key must
+    # equal the oracle's floor of the IEEE quotient
+    rng = np.random.default_rng(47)
+    spec = gen.GRIDS["c1"]
+    n = 6000
+    k_lat = rng.integers(0, spec.n_lat, n)
+    k_lon = rng.integers(0, spec.n_lon, n)
+    lat = spec.lat0_deg + k_lat * spec.dlat_deg
+    lon = spec.lon0_deg + k_lon * spec.dlon_deg
+    nudge = rng.integers(-2, 3, (2, n))
+    for _ in range(2):
+        lat = np.where(nudge[0] > 0, np.nextafter(lat, np.inf), np.where(nudge[0] < 0, np.nextafter(lat, -np.inf), lat))
+        lon = np.where(nudge[1] > 0, np.nextafter(lon, np.inf), np.where(nudge[1] < 0, np.nextafter(lon, -np.inf), lon))
+        nudge = np.where(np.abs(nudge) == 2, nudge, 0)
+    jid = np.repeat(np.arange(60, dtype=np.int64), n // 60)
+    ts = spec.t0_ms + rng.integers(0, 288, n).astype(np.int64) * spec.bin_ms + rng.integers(-1, 2, n)
+    ts = np.sort(ts.reshape(60, -1), axis=1).reshape(-1)
+    spd = rng.uniform(0, 40, n).astype(np.float32)
+    got, exp = _run_both(cv, (jid, ts, lat, lon, spd), spec)
+    _check_all(got, exp)

@@ -598,7 +598,7 @@ def path_roofline(stages, n, G, key_bits, p0, ms_step):
     else:
         per["gather"] = 8 + ts_read + 20 + 4 + 36
         per["features"] = 32 + 49
-    per["summary"] = 1 + 45  # journey starts from the flags, then one pass per field group
+    per["summary"] = 1 + 17 + 21  # flags for the counts; box pass lat, lon, flags; sums' pass step, speeds, flags
     per["grid_agg"] = 36
     total = n * sum(per.values()) + 64 * G
     gbs = total / (ms_step / 1e3) / 1e9

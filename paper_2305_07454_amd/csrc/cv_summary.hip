@@ -450,8 +450,9 @@ __device__ __forceinline__ void flush_part(JAcc* acc, u32 cap, u32 j, const Part
 // first record; BOX = false reduces PartSum.  SHARDS = false compiles the
 // plain form without the shard branches, whose loads would otherwise make
 // every window wait for all loads in flight, prefetch included.
-// FL = true (sums only): journey starts are read from the features' FIRST
-// flags, which the sums' pass loads anyway, instead of comparing ids.
+// FL = true: journey starts are read from the features' FIRST flags instead
+// of comparing ids (the box pass then loads an id only at a journey start,
+// to write it out).
 template <bool BOX, bool SHARDS, bool FL = false>
 __global__ void __launch_bounds__(SB) k_sum_reduce(u32 n, const i64* __restrict__ jid, const double* __restrict__ lat,
                                                    const double* __restrict__ lon, const float* __restrict__ spd, const double* __restrict__ step,
@@ -475,7 +476,6 @@ __global__ void __launch_bounds__(SB) k_sum_reduce(u32 n, const i64* __restrict_
     // open journey: the one containing the record before the next window
     u32 open_j = seen - 1;   // valid when the chunk starts mid-journey
     bool open_here = false;  // its first record lies in this chunk
-    static_assert(!(FL && BOX), "the box pass writes ids");
     i64 jprev = (!FL && cs > 0) ? jid[cs - 1] : 0;
     u32 sk = (SHARDS && !FL) ? shard_lower_bound(soff, S, cs) : 0u;
     // the id after the chunk (its last record may end a journey)
@@ -499,6 +499,7 @@ __global__ void __launch_bounds__(SB) k_sum_reduce(u32 n, const i64* __restrict_
             if constexpr (BOX) {
                 gx0[k] = lat[r];
                 gx1[k] = lon[r];
+                if (FL) gf[k] = flags[r];
             } else {
                 gx0[k] = step[r];
                 gx1[k] = dspd[r];
@@ -555,7 +556,7 @@ __global__ void __launch_bounds__(SB) k_sum_reduce(u32 n, const i64* __restrict_
                 if (h && jl < cap) {
                     // a journey's first record is indexed within its shard
                     const u32 sh = S > 1 ? shard_of(soff, S, r) : 0u;
-                    if (o.jid) o.jid[jl] = jv;
+                    if (o.jid) o.jid[jl] = FL ? jid[r] : jv;
                     if (o.first) o.first[jl] = (u32)(S > 1 ? r - soff[sh] : r);
                     acc[jl].gfirst = (u32)r;
                 }
@@ -713,7 +714,7 @@ static cv_status summary_impl(const cv_records* sorted, const cv_features* feat,
     hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(SCAN_B), 0, s, L.tcnt, L.tile_prefix, (u32)L.tiles, L.meta);
     hipLaunchKernelGGL(k_sum_init, dim3(cvh::grid_for(cap, 256, 2048)), dim3(256), 0, s, L.acc, L.accx, L.meta, cap);
     for (const bool box : {true, false}) {
-        auto kern = box ? (S > 1 ? k_sum_reduce<true, true> : k_sum_reduce<true, false>)
+        auto kern = box ? (S > 1 ? k_sum_reduce<true, true, true> : k_sum_reduce<true, false, true>)
                         : (S > 1 ? k_sum_reduce<false, true, true> : k_sum_reduce<false, false, true>);
         hipLaunchKernelGGL(kern, dim3((unsigned)L.tiles), dim3(SB), 0, s, nn, sorted->journey_id, sorted->lat_deg,
                            sorted->lon_deg, sorted->speed_mps, feat->step_m, feat->speed_mps, feat->flags,

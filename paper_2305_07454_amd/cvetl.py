@@ -8,6 +8,9 @@ HIP kernels.  PyTorch supplies device memory (tensors) and the stream
 * ``cv_journey_features(sorted)        -> features``
 * ``cv_journey_summary(sorted, feat)   -> (journeys, result)``
 * ``cv_grid_aggregate(sorted, grid)    -> (groups, result)``
+* ``cv_sort_records_features(records, max_journeys, shard_offsets=None)
+  -> (perm, sorted_records, features, result)``: the sort and the kinematics
+  in one call (the preallocated ``Pipeline`` / ``BatchPipeline`` use it)
 
 A record batch is a dict of device tensors with the keys of ``RECORD_FIELDS``.
 There is no CPU fallback: loading fails loudly when the library is missing.

@@ -461,8 +461,8 @@ def bench_direction(args, r, grid, pipe, rec, G, dev):
 
 def bench_lattice(args, grid, groups, gdir, dev):
     """Dense lattice of every time bin (mean speed and volume channels per
-    sector), its per-channel normalisation, and the group filter, on C1's group
-    tables without and with four sectors.  HIP events around each call."""
+    sector), its per-channel normalisation, and the group filter, on the full-day
+    workload's group tables without and with four sectors.  HIP events around each call."""
     import torch
     from paper_2305_07454_amd import cvetl
     stream = torch.cuda.current_stream()
@@ -532,7 +532,8 @@ def bench_hygiene(pipe, n, dev):
 
 def bench_csv(r, dev, rows=4_000_000):
     """Extraction of Table-1-shaped text (fixed-width rows of the first
-    `rows` C1 records, written by gen.to_csv) into record columns."""
+    `rows` records of the full-day workload, written by gen.to_csv) into record
+    columns."""
     import numpy as np
     import torch
     from paper_2305_07454_amd import cvetl, gen

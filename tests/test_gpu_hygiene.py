@@ -23,7 +23,7 @@ def cv():
 
 
 def _with_copies(seed, frac):
-    """C1-shaped rows plus exact copies of a fraction of them (some copied
+    """Full-day-shaped rows (per-journey files) plus exact copies of a fraction of them (some copied
     twice), each inserted at a random later position, and near copies that
     differ in one bit of the speed."""
     r = gen.make_c1(seed=seed, n_journeys=70, median=800.0)

@@ -24,7 +24,7 @@ def cv():
 
 @pytest.fixture(scope="module")
 def case(cv):
-    """C1-shaped records on a coarser grid over the same box (0.02 degrees, 15
+    """Full-day-shaped records (per-journey files) on a coarser grid over the same box (0.02 degrees, 15
     minutes, 96 bins: tensors of tens of MB): the GPU group tables (with and
     without four heading sectors) and the oracle's own group tables."""
     import torch

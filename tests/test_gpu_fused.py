@@ -171,3 +171,42 @@ def test_fused_payload_forms_agree(cv):
         _same_bits(f"features.{k}", fa[k], fb[k])
     # both index the same original records
     assert np.array_equal(host(pa).astype(np.int64), shuf[host(pb).astype(np.int64)])
+
+
+def _mix64(x):
+    m = (1 << 64) - 1
+    x &= m
+    x ^= x >> 30
+    x = (x * 0xbf58476d1ce4e5b9) & m
+    x ^= x >> 27
+    x = (x * 0x94d049bb133111eb) & m
+    x ^= x >> 31
+    return x
+
+
+def test_dictionary_cache_slot_collisions(cv):
+    # 96 journey ids whose dictionary-cache slot (top bits of the 64-bit mix
+    # of the id) is the same, interleaved at random: every
+    # lane of a window competes for one cache slot in the insert and in the
+    # key packing, and the sort must still match the oracle
+    ids = []
+    x = 1
+    while len(ids) < 96:
+        if (_mix64(x) >> 56) == 17:  # one slot at every power-of-two slot count up to 256
+            ids.append(x)
+        x += 1
+    rng = np.random.default_rng(48)
+    per = 120
+    jid = np.repeat(np.array(ids, dtype=np.int64), per)
+    ts = gen.T0_MS + np.tile(np.arange(per, dtype=np.int64) * 1000, len(ids))
+    lat = 38.0 + rng.normal(0, 1e-3, len(jid))
+    lon = -92.0 + rng.normal(0, 1e-3, len(jid))
+    spd = rng.uniform(0, 30, len(jid)).astype(np.float32)
+    order = rng.permutation(len(jid))
+    cols = tuple(c[order] for c in (jid, ts, lat, lon, spd))
+    print(f"[fused] cache collisions n={len(jid)}", flush=True)
+    perm, srt, feat, r = _fused_vs_separate(cv, cols, 1024)
+    assert r["count"] == len(ids)
+    exp = oracle.run_plain(cols, gen.GRIDS["c1"])
+    check_sort(perm, srt, exp["perm"], exp["sorted"])
+    check_features(feat, exp["features"])

@@ -39,6 +39,8 @@ struct LSlot {
     u64 cs[4];
     u32 count, nj, mn, mx;
 };
+static_assert(offsetof(LSlot, nj) == offsetof(LSlot, count) + 4 && offsetof(LSlot, count) % 8 == 0,
+              "count and nj form one aligned 64-bit word");
 
 constexpr uint8_t B_SEG = 1;   // first record of a (journey, time-bin) segment
 constexpr uint8_t B_RUN = 2;   // first record of a run (segment start or key change)
@@ -166,8 +168,8 @@ __device__ __forceinline__ void slot_insert(u64* s_hkey, LSlot* s_h, GEntry* tab
             fx_to_cs(sum, c);
             for (int i = 0; i < 4; ++i)
                 if (c[i]) atomicAdd((unsigned long long*)&sl.cs[i], (unsigned long long)c[i]);
-            if (count) atomicAdd(&sl.count, count);
-            if (nj) atomicAdd(&sl.nj, nj);
+            // count and nj are adjacent: one 64-bit add (a tile's count stays below 2^32)
+            if (count | nj) atomicAdd(reinterpret_cast<unsigned long long*>(&sl.count), (u64)count | ((u64)nj << 32));
             if (mn != ~0u) atomicMin(&sl.mn, mn);
             if (mx) atomicMax(&sl.mx, mx);
             return;

@@ -171,8 +171,12 @@ __device__ __forceinline__ void g_merge(GEntry& e, u32 count, u32 nj, const Fx19
     fx_to_cs40(sum, c);
     for (int i = 0; i < CS40; ++i)
         if (c[i]) __hip_atomic_fetch_add(&e.cs[i], c[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_fetch_add(&e.count, count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (nj) __hip_atomic_fetch_add(&e.nj, nj, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // count and distinct journeys are adjacent words: one 64-bit add carries
+    // both (a count stays below 2^32, so nothing crosses into nj)
+    static_assert(offsetof(GEntry, nj) == offsetof(GEntry, count) + 4 && offsetof(GEntry, count) % 8 == 0,
+                  "count and nj form one aligned 64-bit word");
+    __hip_atomic_fetch_add(reinterpret_cast<u64*>(&e.count), (u64)count | ((u64)nj << 32), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_fetch_min(&e.mn, mn, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_fetch_max(&e.mx, mx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }

@@ -10,7 +10,10 @@ per-journey gathers.  ``build()`` compiles the C file in place.
 
 Parity status of each function (what pins it is in ``tests/test_oracle_pins.py``):
 
-* ``sort``      -- pinned (numpy.lexsort, brute force over permutations)
+* ``sort``      -- pinned (numpy.lexsort, brute force over permutations, and a
+  mutation check: the merge is the only place ties are ordered)
+* ``stream_late`` -- pinned (hand-worked pushes, invariants: one push or
+  per-journey non-decreasing times give no late record)
 * ``features``  -- pinned (closed forms, mpmath 50-digit references, identities)
 * ``summary``   -- pinned (math.fsum, numpy reductions, invariants)
 * ``grid``      -- pinned (brute-force Python dict, explicit grid-line cases)
@@ -34,13 +37,21 @@ FLAG_BEARING_OK, FLAG_DHEAD_OK, FLAG_BAD_COORD = 0x10, 0x20, 0x40
 _lib = None
 
 
+CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
+
+
+def compile_to(src: str, out: str, extra=()) -> str:
+    """gcc the oracle source `src` into the shared library `out`."""
+    tmp = out + ".tmp"
+    subprocess.check_call(["gcc", *CFLAGS, *extra, "-o", tmp, src, "-lm"])
+    os.replace(tmp, out)
+    return out
+
+
 def build(force: bool = True) -> str:
     """Compile the oracle (gcc, -O2, no FMA contraction, no fast-math)."""
     if force or not os.path.exists(LIB):
-        tmp = LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
-                               "-fPIC", "-shared", "-o", tmp, SRC, "-lm"])
-        os.replace(tmp, LIB)
+        compile_to(SRC, LIB)
     return LIB
 
 
@@ -49,28 +60,35 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
             build()
-        L = ctypes.CDLL(LIB)
-        P = ctypes.c_void_p
-        I = ctypes.c_int64
-        D = ctypes.c_double
-        L.orc_fsum.argtypes = [I, P]
-        L.orc_fsum.restype = D
-        L.orc_sort.argtypes = [I, P, P, P]
-        L.orc_sort.restype = None
-        L.orc_features.argtypes = [I] + [P] * 11
-        L.orc_features.restype = None
-        L.orc_summary.argtypes = [I] + [P] * 8 + [I] + [P] * 14
-        L.orc_summary.restype = I
-        L.orc_grid_keys.argtypes = [I, P, P, P, D, D, D, D, I, I, I, I, I, P]
-        L.orc_grid_keys.restype = I
-        L.orc_grid.argtypes = [I, P, P, P, P, P, D, D, D, D, I, I, I, I, I, I] + [P] * 7
-        L.orc_grid.restype = I
-        L.orc_dir_sector.argtypes = [D, ctypes.c_int32, I, D]
-        L.orc_dir_sector.restype = I
-        L.orc_grid_dir.argtypes = [I] + [P] * 8 + [I, D, D, D, D, D, I, I, I, I, I, I] + [P] * 7
-        L.orc_grid_dir.restype = I
-        _lib = L
+        _lib = bind(LIB)
     return _lib
+
+
+def bind(path):
+    """Load a compiled oracle library and declare its C signatures."""
+    L = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    I = ctypes.c_int64
+    D = ctypes.c_double
+    L.orc_fsum.argtypes = [I, P]
+    L.orc_fsum.restype = D
+    L.orc_sort.argtypes = [I, P, P, P]
+    L.orc_sort.restype = None
+    L.orc_stream_late.argtypes = [I, P, P, I, P, P]
+    L.orc_stream_late.restype = I
+    L.orc_features.argtypes = [I] + [P] * 11
+    L.orc_features.restype = None
+    L.orc_summary.argtypes = [I] + [P] * 8 + [I] + [P] * 14
+    L.orc_summary.restype = I
+    L.orc_grid_keys.argtypes = [I, P, P, P, D, D, D, D, I, I, I, I, I, P]
+    L.orc_grid_keys.restype = I
+    L.orc_grid.argtypes = [I, P, P, P, P, P, D, D, D, D, I, I, I, I, I, I] + [P] * 7
+    L.orc_grid.restype = I
+    L.orc_dir_sector.argtypes = [D, ctypes.c_int32, I, D]
+    L.orc_dir_sector.restype = I
+    L.orc_grid_dir.argtypes = [I] + [P] * 8 + [I, D, D, D, D, D, I, I, I, I, I, I] + [P] * 7
+    L.orc_grid_dir.restype = I
+    return L
 
 
 def _p(a):
@@ -94,6 +112,21 @@ def sort(jid, ts):
     perm = np.empty(n, dtype=np.uint32)
     lib().orc_sort(n, _p(jid), _p(ts), _p(perm))
     return perm
+
+
+def stream_late(jid, ts, push_sizes):
+    """Late records of a stream pushed in consecutive pieces of `push_sizes`
+    records (arrival order): a record is late when its time stamp is below the
+    largest time stamp of its journey's non-late records in earlier pushes.
+    Returns a bool array over the records in arrival order."""
+    jid = _c(jid, np.int64)
+    ts = _c(ts, np.int64)
+    n = jid.shape[0]
+    ends = np.cumsum(np.asarray(push_sizes, dtype=np.int64)).astype(np.int64)
+    assert ends.size == 0 or ends[-1] == n, "push sizes must cover the records"
+    late = np.zeros(n, dtype=np.uint8)
+    lib().orc_stream_late(n, _p(jid), _p(ts), ends.shape[0], _p(ends), _p(late))
+    return late.astype(bool)
 
 
 def sorted_records(cols, perm):

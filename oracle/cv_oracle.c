@@ -115,25 +115,134 @@ static float canon0(float v) { return v == 0.0f ? 0.0f : v; }
 /* ------------------------------------------------------------------------ */
 /* Order: the paper's "unique index" over all journeys (Methods, step (2)),   */
 /* read as a stable sort of record indices by (journey id, timestamp), both   */
-/* compared as signed 64-bit integers, ties kept in input order.             */
+/* compared as signed 64-bit integers, ties kept in input order.  The sort is */
+/* a plain top-down merge sort written out here, so that stability is a      */
+/* property of this code (the merge takes from the left run on equal keys),  */
+/* not of the C library's qsort.                                             */
 /* ------------------------------------------------------------------------ */
 static const int64_t* g_jid;
 static const int64_t* g_ts;
 
-static int cmp_jid_ts_idx(const void* a, const void* b)
+/* 1 when record i's (journey, time) key is strictly below record j's */
+static int key_less(uint32_t i, uint32_t j)
 {
-    uint32_t i = *(const uint32_t*)a, j = *(const uint32_t*)b;
-    if (g_jid[i] != g_jid[j]) return g_jid[i] < g_jid[j] ? -1 : 1;
-    if (g_ts[i] != g_ts[j]) return g_ts[i] < g_ts[j] ? -1 : 1;
-    return (i > j) - (i < j);
+    if (g_jid[i] != g_jid[j]) return g_jid[i] < g_jid[j];
+    return g_ts[i] < g_ts[j];
+}
+
+/* sort a[lo, hi) stably, tmp as scratch of the same length */
+static void merge_sort(uint32_t* a, uint32_t* tmp, int64_t lo, int64_t hi)
+{
+    if (hi - lo < 2) return;
+    int64_t mid = lo + (hi - lo) / 2;
+    merge_sort(a, tmp, lo, mid);
+    merge_sort(a, tmp, mid, hi);
+    int64_t i = lo, j = mid, k = lo;
+    while (i < mid && j < hi) {
+        /* the right element goes first only when strictly smaller */
+        if (key_less(a[j], a[i])) tmp[k++] = a[j++];
+        else tmp[k++] = a[i++];
+    }
+    while (i < mid) tmp[k++] = a[i++];
+    while (j < hi) tmp[k++] = a[j++];
+    for (k = lo; k < hi; ++k) a[k] = tmp[k];
 }
 
 void orc_sort(int64_t n, const int64_t* jid, const int64_t* ts, uint32_t* perm)
 {
     for (int64_t i = 0; i < n; ++i) perm[i] = (uint32_t)i;
+    uint32_t* tmp = (uint32_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(uint32_t));
+    if (!tmp) abort();
     g_jid = jid;
     g_ts = ts;
-    qsort(perm, (size_t)n, sizeof(uint32_t), cmp_jid_ts_idx);
+    merge_sort(perm, tmp, 0, n);
+    free(tmp);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Late records of a stream (the serving form's reading of the order when    */
+/* records arrive in pushes).  The paper's pipeline is batch only; the       */
+/* streamed result is defined as the plain result on the concatenation of    */
+/* the pushes, provided no journey's time goes backwards across pushes.  A   */
+/* record that does is late: its time is below the largest time of the       */
+/* non-late records its journey had in earlier pushes.  Within one push the  */
+/* records are ordered by the sort, so only earlier pushes can make a record */
+/* late.  push_end[b] is the end (exclusive) of push b in arrival order;     */
+/* late[i] receives 1 for a late record, else 0.  Returns the late count.    */
+/* ------------------------------------------------------------------------ */
+static int key_jid_arrival_less(uint32_t i, uint32_t j)
+{
+    if (g_jid[i] != g_jid[j]) return g_jid[i] < g_jid[j];
+    return i < j;
+}
+
+static void merge_sort_by_journey(uint32_t* a, uint32_t* tmp, int64_t lo, int64_t hi)
+{
+    if (hi - lo < 2) return;
+    int64_t mid = lo + (hi - lo) / 2;
+    merge_sort_by_journey(a, tmp, lo, mid);
+    merge_sort_by_journey(a, tmp, mid, hi);
+    int64_t i = lo, j = mid, k = lo;
+    while (i < mid && j < hi) {
+        if (key_jid_arrival_less(a[j], a[i])) tmp[k++] = a[j++];
+        else tmp[k++] = a[i++];
+    }
+    while (i < mid) tmp[k++] = a[i++];
+    while (j < hi) tmp[k++] = a[j++];
+    for (k = lo; k < hi; ++k) a[k] = tmp[k];
+}
+
+int64_t orc_stream_late(int64_t n, const int64_t* jid, const int64_t* ts, int64_t n_push,
+                        const int64_t* push_end, uint8_t* late)
+{
+    int64_t* push = (int64_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    uint32_t* idx = (uint32_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(uint32_t));
+    uint32_t* tmp = (uint32_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(uint32_t));
+    if (!push || !idx || !tmp) abort();
+    /* the push of every record */
+    int64_t b = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        while (b < n_push && push_end[b] <= i) ++b;
+        push[i] = b;
+        idx[i] = (uint32_t)i;
+        late[i] = 0;
+    }
+    /* each journey's records in arrival order */
+    g_jid = jid;
+    merge_sort_by_journey(idx, tmp, 0, n);
+    int64_t n_late = 0;
+    for (int64_t a = 0; a < n;) {
+        int64_t e = a + 1;
+        while (e < n && jid[idx[e]] == jid[idx[a]]) ++e;
+        int have_last = 0, have_cur = 0;
+        int64_t last = 0;     /* largest non-late time of earlier pushes */
+        int64_t cur = 0;      /* largest non-late time of the current push */
+        int64_t cur_push = -1;
+        for (int64_t c = a; c < e; ++c) {
+            uint32_t i = idx[c];
+            if (push[i] != cur_push) {
+                /* a new push: what the previous one held becomes history */
+                if (have_cur && (!have_last || cur > last)) {
+                    last = cur;
+                    have_last = 1;
+                }
+                have_cur = 0;
+                cur_push = push[i];
+            }
+            if (have_last && ts[i] < last) {
+                late[i] = 1;
+                ++n_late;
+            } else if (!have_cur || ts[i] > cur) {
+                cur = ts[i];
+                have_cur = 1;
+            }
+        }
+        a = e;
+    }
+    free(push);
+    free(idx);
+    free(tmp);
+    return n_late;
 }
 
 /* ------------------------------------------------------------------------ */

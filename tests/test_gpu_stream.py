@@ -126,23 +126,6 @@ def _delayed_arrival(n, rng, frac, reach):
     return np.argsort(key, kind="stable")
 
 
-def _late_flags(jid, ts, bounds):
-    """A record is late when it is older than the newest non-late record of
-    its journey in an earlier push (the resident last point)."""
-    last = {}
-    late = np.zeros(jid.shape[0], dtype=bool)
-    for a, b in bounds:
-        upd = {}
-        for i in range(a, b):
-            j, t = int(jid[i]), int(ts[i])
-            if j in last and t < last[j]:
-                late[i] = True
-            elif t > upd.get(j, t - 1):
-                upd[j] = t
-        last.update(upd)
-    return late
-
-
 @pytest.mark.parametrize("grid_name,heavy", [("c3", 0.0), ("c4", 0.05)])
 def test_late_records_in_bulk(cv, grid_name, heavy):
     """Late records in quantity: kinematics and distinct-journey flags follow
@@ -156,7 +139,7 @@ def test_late_records_in_bulk(cv, grid_name, heavy):
     cols = tuple(np.ascontiguousarray(c[order]) for c in r.columns())
     sizes = gen.chunk_sizes(rng, r.n, 500, 30_000)
     bounds = _slices(r.n, sizes)
-    late = _late_flags(cols[0], cols[1], bounds)
+    late = oracle.stream_late(cols[0], cols[1], sizes)
     print(f"[stream-late] n={r.n} chunks={len(sizes)} late={int(late.sum())} grid={grid_name}", flush=True)
     assert late.sum() > 100
     st = cv.Stream(grid, max_journeys=4096, max_groups=1 << 18, max_batch=max(sizes))

@@ -78,6 +78,65 @@ def test_sort_signed_extremes(oracle_mod):
 
 
 # --------------------------------------------------------------------------
+# late records of a stream (the serving form's reading of time going backwards)
+# --------------------------------------------------------------------------
+
+# Hand-worked cases: (journey ids, time stamps, push sizes, expected late flags).
+LATE_CASES = [
+    # one journey; the fourth record comes in a later push, older than 5000
+    ([9, 9, 9, 9], [0, 1000, 5000, 3000], [3, 1], [0, 0, 0, 1]),
+    # the same records in one push: the sort orders them, nothing is late
+    ([9, 9, 9, 9], [0, 1000, 5000, 3000], [4], [0, 0, 0, 0]),
+    # two journeys interleaved; equal to the newest earlier time is not late
+    ([1, 1, 2, 1, 2, 1, 1], [10, 20, 100, 15, 100, 20, 5], [3, 4], [0, 0, 0, 1, 0, 0, 1]),
+    # late records never become history: 6 is still below 10
+    ([4, 4, 4, 4], [10, 5, 7, 6], [1, 2, 1], [0, 1, 1, 1]),
+    # history is the largest earlier time, not the last push's
+    ([4, 4, 4], [50, 60, 55], [1, 1, 1], [0, 0, 1]),
+    ([4, 4, 4], [50, 30, 40], [2, 1], [0, 0, 1]),
+    # records of one push join history only after that push: 20 < 40 in one push is fine
+    ([4, 4, 4], [10, 40, 20], [1, 2], [0, 0, 0]),
+    # a record of another journey is never compared across journeys
+    ([1, 2, 2], [100, 5, 6], [1, 1, 1], [0, 0, 0]),
+    # empty pushes change nothing
+    ([3, 3], [9, 8], [1, 0, 1], [0, 1]),
+]
+
+
+@pytest.mark.parametrize("jid,ts,sizes,late", LATE_CASES)
+def test_stream_late_by_hand(oracle_mod, jid, ts, sizes, late):
+    got = oracle.stream_late(np.array(jid, np.int64), np.array(ts, np.int64), sizes)
+    assert got.astype(int).tolist() == late
+
+
+def test_stream_late_invariants(oracle_mod):
+    rng = np.random.default_rng(12)
+    n = 5000
+    jid = rng.integers(0, 40, n).astype(np.int64)
+    ts = rng.integers(0, 10_000, n).astype(np.int64)
+    sizes = gen.chunk_sizes(rng, n, 10, 400)
+    # a single push never has late records
+    assert not oracle.stream_late(jid, ts, [n]).any()
+    # times non-decreasing per journey in arrival order: no split makes one late
+    mono = np.empty(n, np.int64)
+    for j in np.unique(jid):
+        w = np.flatnonzero(jid == j)
+        mono[w] = np.sort(ts[w])
+    assert not oracle.stream_late(jid, mono, sizes).any()
+    # a late record's time is below some earlier-push time of its journey
+    late = oracle.stream_late(jid, ts, sizes)
+    assert late.any()
+    push = np.repeat(np.arange(len(sizes)), sizes)
+    for i in np.flatnonzero(late)[:200]:
+        earlier = (jid == jid[i]) & (push < push[i])
+        assert earlier.any() and ts[earlier].max() > ts[i]
+    # and a record below nothing earlier is never late
+    for i in np.flatnonzero(~late)[:200]:
+        earlier = (jid == jid[i]) & (push < push[i]) & ~late
+        assert not earlier.any() or ts[i] >= ts[earlier].max()
+
+
+# --------------------------------------------------------------------------
 # kinematics: closed forms and 50-digit references
 # --------------------------------------------------------------------------
 

@@ -1,16 +1,25 @@
 #!/usr/bin/env python
-"""Benchmark of the plain connected-vehicle ETL path on one MI355X.
+"""Benchmark of the connected-vehicle ETL path on one MI355X.
 
 One step = the whole hot path over one batch resident in HBM: stable sort by
 (journey, time) with key-then-payload gather, per-point kinematics, per-journey
-summaries and the (time bin x cell) group table.  Default workload: the
-full-day Missouri-shaped synthetic day (50 000 journeys, lognormal lengths with
-median 1 500 points, 5 % duplicated and 2 % swapped timestamps, 0.005 deg x
-5 min grid), about 124 M records.
+summaries and the (time bin x cell) group table.
 
-Prints one JSON line: Mrecords/s for the whole step, the roofline of the
-dominant kernel (radix scatter pass) measured with HIP events on its launch
-stream, and the CPU oracle timed on a bounded sample of the same workload.
+The default run measures, in one JSON line:
+  * the headline: the plain path on the full-day Missouri-shaped synthetic day
+    (50 000 journeys, lognormal lengths with median 1 500 points, 5 %
+    duplicated and 2 % swapped timestamps, 0.005 deg x 5 min grid), about
+    124 M records -- Mrecords/s (median of per-step HIP events), the roofline
+    of the dominant kernel (radix scatter pass) measured with HIP events on its
+    launch stream, the whole path's algorithmic bytes over the step time, and
+    the CPU oracle timed on a bounded sample of the same workload;
+  * "batched": 115 county-day shards of capped Zipf sizes (400 M records,
+    0.001 deg x 1 min) in one set of launches, against the plain path called
+    per shard on the same resident input, with every shard's outputs compared;
+  * "serving": a Poisson stream of 200 chunks/s (10 k - 5 M records) served
+    with continuous batching and one chunk per push on the identical trace:
+    p50 / p95 / p99 chunk latency and Mrecords/s, outputs compared.
+--workload c0|c1|c2|c3|c4 runs one of them on its own.
 """
 from __future__ import annotations
 
@@ -37,7 +46,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c1", choices=["c0", "c1", "c2", "c3", "c4"])
+    ap.add_argument("--workload", default="all", choices=["all", "c0", "c1", "c2", "c3", "c4"])
     ap.add_argument("--duration", type=float, default=None, help="c3/c4: seconds of arrivals")
     ap.add_argument("--shards", type=int, default=115, help="c2: number of shards")
     ap.add_argument("--total", type=int, default=400_000_000, help="c2: total records")
@@ -47,6 +56,9 @@ def parse():
                     help="run the sort and the kinematics as two calls instead of the fused one")
     ap.add_argument("--cpu-sample", type=int, default=40_000_000, help="records in the oracle's timed sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="default run: skip the batched sub-benchmark")
+    ap.add_argument("--no-serving", action="store_true", help="default run: skip the serving sub-benchmark")
+    ap.add_argument("--batched-steps", type=int, default=5, help="default run: timed steps of the batched form")
     ap.add_argument("--out", default=None, help="also write the JSON line to this file")
     ap.add_argument("--sort-shape", type=int, default=None,
                     help="radix tile shape index (default: the tuning cache, else the library default)")
@@ -86,12 +98,29 @@ def make_workload(name, n_journeys):
     return r, gen.GRIDS[name], desc
 
 
+def host_cpu():
+    """CPU model and the cores this process may use (the oracle runs on one)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return model, usable
+
+
 def cpu_baseline(r, grid, target):
     """The oracle, untuned, single-threaded, on the first journeys (file order)
     of the same workload until `target` records."""
     import numpy as np
     import oracle
-    from paper_2305_07454_amd import gen
     jid = r.journey_id
     # journeys are contiguous blocks in file order (c1); take whole blocks
     change = np.nonzero(jid[1:] != jid[:-1])[0] + 1
@@ -104,14 +133,44 @@ def cpu_baseline(r, grid, target):
     oracle.run_plain(cols, grid)
     dt = time.perf_counter() - t
     n_j = int(len(np.unique(cols[0])))
+    model, usable = host_cpu()
     return {"value": round(cut / dt / 1e6, 4), "unit": "Mrecords/s", "cores": 1, "kind": "oracle",
+            "cpu_model": model, "nproc": usable,
             "sample": f"first {n_j} journeys in file order ({cut} records) of the same workload, "
-                      f"whole plain path, {dt:.1f}s"}
+                      f"whole plain path, {dt:.1f}s, one thread"}
 
 
-def bench_batched(args):
+def step_stats(ms):
+    """Median / min / max / std of per-step times (ms)."""
+    import numpy as np
+    a = np.asarray(ms, dtype=np.float64)
+    return {"median": round(float(np.median(a)), 4), "min": round(float(a.min()), 4),
+            "max": round(float(a.max()), 4), "std": round(float(a.std()), 4), "mean": round(float(a.mean()), 4),
+            "steps": int(a.size)}
+
+
+def timed_steps(fn, steps, stream):
+    """Run fn() `steps` times with a HIP event pair around each step on
+    `stream`; returns the per-step times in ms."""
+    import torch
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev[0].record(stream)
+    for i in range(steps):
+        fn()
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    return [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
+
+
+def _same(a, b):
+    import torch
+    return a.shape == b.shape and torch.equal(a.contiguous().view(torch.uint8), b.contiguous().view(torch.uint8))
+
+
+def bench_batched(args, steps):
     """Batched form (all shards in one set of launches) vs the plain path called
-    once per shard, same resident input, same GPU."""
+    once per shard, same resident input, same GPU; every shard's outputs of the
+    two are compared bit for bit."""
     import numpy as np
     import torch
     from paper_2305_07454_amd import cvetl, gen
@@ -125,10 +184,11 @@ def bench_batched(args):
     log(f"generated c2: {len(sizes)} shards, {n} records in {time.time() - t:.1f}s")
     grid = gen.GRIDS["c2"]
     rec = cvetl.to_device(allr, dev)
+    del allr
     torch.cuda.synchronize()
     log(f"c2 columns resident ({time.time() - t:.1f}s)")
     from paper_2305_07454_amd import tune
-    tune.apply(n)
+    tune.apply(n, workload="c2")
     off_h, off_d = cvetl.shard_offsets(sizes, dev)
     bp, res = cvetl.cv_batch_run(rec, sizes, grid)
     J, G = res[1]["count"], res[2]["count"]
@@ -142,26 +202,23 @@ def bench_batched(args):
     torch.cuda.synchronize()
     assert all(x["status"] == 0 for x in bp.results())
     log(f"warm-up done ({time.time() - t:.1f}s)")
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    stream = torch.cuda.current_stream()
     cvetl.cv_timing_reset()
     cvetl.cv_timing_enable(True)
     torch.cuda.synchronize()
-    e0.record()
-    for _ in range(args.steps):
-        bp.run(rec, off_d)
-    e1.record()
-    torch.cuda.synchronize()
+    per_step = timed_steps(lambda: bp.run(rec, off_d), steps, stream)
     cvetl.cv_timing_enable(False)
-    ms_batched = e0.elapsed_time(e1) / args.steps
+    st = step_stats(per_step)
+    ms_batched = st["median"]
     rs_b = bp.results()[0]
     roof_b, pass_ms_b = radix_roofline(cvetl, n, rs_b)
     stages_b = {}
     for fam in ("sort_prep", "gather", "features", "gather_features", "summary", "grid_agg", "grid_tail"):
         ms, c = cvetl.cv_timing_read(fam)
         if c:
-            stages_b[fam] = round(ms / args.steps, 4)
-    stages_b["sort_passes"] = round(pass_ms_b / args.steps, 4)
-    log(f"batched: {ms_batched:.2f} ms per step ({time.time() - t:.1f}s)")
+            stages_b[fam] = round(ms / steps, 4)
+    stages_b["sort_passes"] = round(pass_ms_b / steps, 4)
+    log(f"batched: {ms_batched:.2f} ms per step (median of {steps}) ({time.time() - t:.1f}s)")
     # plain per-file: one plain pipeline sized for the largest shard, called per shard
     big = max(sizes)
     pp = cvetl.Pipeline(big, grid, max_journeys=max(1024, mj), journey_capacity=max(1, J),
@@ -175,61 +232,66 @@ def bench_batched(args):
 
     per_file()
     torch.cuda.synchronize()
-    e0.record()
-    for _ in range(args.steps):
-        per_file()
-    e1.record()
-    torch.cuda.synchronize()
-    ms_plain = e0.elapsed_time(e1) / args.steps
+    pf_steps = max(1, min(steps, 3))
+    pf = step_stats(timed_steps(per_file, pf_steps, stream))
+    ms_plain = pf["median"]
     log(f"per-file: {ms_plain:.2f} ms per step ({time.time() - t:.1f}s)")
-    # identical outputs on the last shard the loop ran
-    i = max(j for j in range(len(sizes)) if sizes[j] > 0)
-    a, b = int(off_h[i]), int(off_h[i + 1])
+    # identical outputs, every shard: the per-file path once more, compared after each shard
     jo = bp.journey_offsets.cpu().numpy()
     go = bp.group_offsets.cpu().numpy()
-    same = torch.equal(bp.perm[a:b], pp.perm[:b - a]) and torch.equal(bp.feat["step_m"][a:b], pp.feat["step_m"][:b - a])
-    rj = pp.results()[1]["count"]
-    same = same and torch.equal(bp.journeys["distance_m"][int(jo[i]):int(jo[i + 1])], pp.journeys["distance_m"][:rj])
-    rg = pp.results()[2]["count"]
-    same = same and torch.equal(bp.groups["sum_speed"][int(go[i]):int(go[i + 1])], pp.groups["sum_speed"][:rg])
-    assert same, "batched and per-file outputs differ"
-    line = {
-        "metric": "ETL Mrecords/s & % HBM peak (plain vs batched); serving p50/p99 latency",
-        "value": round(n / (ms_batched / 1e3) / 1e6, 3), "unit": "Mrecords/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_batched, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"c2: {len(sizes)} county-day shards, capped Zipf(1.2) sizes {min(sizes)}..{max(sizes)}, "
-                               f"0.001 deg x 1 min, batched in one set of launches", "records": n,
-                   "journeys": J, "groups": G, "path": "batched", "parallelism": "single GPU"},
-        "plain_per_file": {"value": round(n / (ms_plain / 1e3) / 1e6, 3), "ms_per_step": round(ms_plain, 4),
+    checked = 0
+    for i, v in enumerate(views):
+        m = int(v["journey_id"].numel())
+        if not m:
+            continue
+        pp.run(v)
+        rr = pp.results()
+        a, b = int(off_h[i]), int(off_h[i + 1])
+        ok = _same(bp.perm[a:b], pp.perm[:m])
+        ok = ok and all(_same(bp.sorted[k][a:b], pp.sorted[k][:m]) for k in bp.sorted)
+        ok = ok and all(_same(bp.feat[k][a:b], pp.feat[k][:m]) for k in bp.feat)
+        ok = ok and int(jo[i + 1] - jo[i]) == rr[1]["count"] and int(go[i + 1] - go[i]) == rr[2]["count"]
+        ok = ok and all(_same(bp.journeys[k][int(jo[i]):int(jo[i + 1])], pp.journeys[k][:rr[1]["count"]])
+                        for k in bp.journeys)
+        ok = ok and all(_same(bp.groups[k][int(go[i]):int(go[i + 1])], pp.groups[k][:rr[2]["count"]])
+                        for k in bp.groups)
+        assert ok, f"batched and per-file outputs differ on shard {i}"
+        checked += 1
+    log(f"batched == per-file on all {checked} shards ({time.time() - t:.1f}s)")
+    out = {
+        "workload": f"c2: {len(sizes)} county-day shards, capped Zipf(1.2) sizes {min(sizes)}..{max(sizes)}, "
+                    f"time-ordered feed per shard, 0.001 deg x 1 min, batched in one set of launches",
+        "records": n, "shards": len(sizes), "journeys": J, "groups": G,
+        "value": round(n / (ms_batched / 1e3) / 1e6, 3), "unit": "Mrecords/s",
+        "ms_per_step": ms_batched, "step_ms": st,
+        "plain_per_file": {"value": round(n / (ms_plain / 1e3) / 1e6, 3), "ms_per_step": ms_plain, "step_ms": pf,
                            "unit": "Mrecords/s"},
         "batched_speedup": round(ms_plain / ms_batched, 3),
-        "identical_outputs_checked_shard": i,
+        "identical_outputs_shards_checked": checked,
         "roofline": roof_b,
         "stages_ms_per_step": stages_b,
-        "path_roofline": path_roofline(stages_b, n, G, rs_b["key_bits"], rs_b["packed_pass"], ms_batched),
+        "path_roofline": path_roofline(stages_b, n, G, rs_b["key_bits"], rs_b["packed_pass"], ms_batched,
+                                       design_bytes=317),
         "key_bits": rs_b["key_bits"],
         "packed_from_pass": rs_b["packed_pass"],
     }
-    s = json.dumps(line)
-    print(s, flush=True)
-    if args.out:
-        with open(args.out, "w") as f:
-            f.write(s + "\n")
+    del bp, pp, rec, views
+    torch.cuda.empty_cache()
+    return out
 
 
-def bench_serving(args):
+def bench_serving(args, workload):
     """Serving at a fixed Poisson arrival rate: continuous batching vs one chunk
     per push on the identical trace; p50/p99 chunk latency and Mrecords/s."""
     import numpy as np
     import torch
-    from paper_2305_07454_amd import cvetl, gen, serve
-    skew = args.workload == "c4"
+    from paper_2305_07454_amd import gen, serve
+    skew = workload == "c4"
     t = time.time()
     pool = gen.make_stream(n_journeys=50_000, heavy_frac=0.01 if skew else 0.0, heavy_share=0.3,
                            heavy_cap=500_000, config_index=4 if skew else 3)
     log(f"generated stream pool: {pool.n} records in {time.time() - t:.1f}s")
-    grid = gen.GRIDS[args.workload]
+    grid = gen.GRIDS[workload]
     if skew:
         dur = args.duration or 30.0
         third = dur / 3.0
@@ -239,76 +301,60 @@ def bench_serving(args):
     else:
         dur = args.duration or 10.0
         rate = lambda tt: 200.0  # noqa: E731
-        desc = f"serving: Poisson 200 chunks/s for {dur:.0f}s; 0.005 deg x 5 min"
+        desc = f"serving: Poisson 200 chunks/s for {dur:.0f}s, chunks 10k-5M records (log-uniform); 0.005 deg x 5 min"
     trace = serve.poisson_trace(np.random.default_rng(2024), rate, dur, 10_000, 5_000_000)
     log(f"trace: {len(trace)} chunks, {sum(s for _, s in trace) / 1e6:.0f} M records")
     out = {}
     flushed = {}
     keep = 40
+    max_groups = (1 << 26) if skew else (1 << 22)
+    arena = None
     for name, batching in (("batched", True), ("per_chunk", False)):
-        srv = serve.Server(pool, grid, batching=batching, arena_records=24_000_000,
-                           max_journeys=1 << 22, max_groups=(1 << 26) if skew else (1 << 22))
+        srv = serve.Server(pool, grid, batching=batching, arena_records=arena, max_journeys=1 << 22,
+                           max_groups=max_groups)
+        arena = srv.A  # both servers get the arena the first carved from free HBM
         chunks = srv.run(trace, keep_first=keep, log=lambda m: log(f"{name}: {m}"))
         out[name] = serve.latency_stats(chunks, warmup_s=min(2.0, dur / 5))
         log(f"{name}: {out[name]}")
-        flushed[name] = (srv.flush(1 << 23, (1 << 26) if skew else (1 << 22)), srv.keep)
+        flushed[name] = (srv.flush(1 << 23, max_groups), srv.keep)
         del srv
         torch.cuda.empty_cache()
     (ja, ga, ra, rga), ka = flushed["batched"]
     (jb, gb, rb, rgb), kb = flushed["per_chunk"]
-    same = all(torch.equal(ja[k].view(torch.uint8), jb[k].view(torch.uint8)) for k in ja) and \
-        all(torch.equal(ga[k].view(torch.uint8), gb[k].view(torch.uint8)) for k in ga) and \
-        all(torch.equal(ka[c][k].view(torch.uint8), kb[c][k].view(torch.uint8)) for c in ka for k in ka[c])
+    same = all(_same(ja[k], jb[k]) for k in ja) and all(_same(ga[k], gb[k]) for k in ga) and \
+        all(_same(ka[c][k], kb[c][k]) for c in ka for k in ka[c])
+    flags_clear = ra["flags"] == 0 and rb["flags"] == 0
     for nm, rj, rg in (("batched", ra, rga), ("per_chunk", rb, rgb)):
         log(f"{nm}: journeys {rj['count']} status {rj['status']} cell-overflow flag {rj['flags']}; "
             f"groups {rg['count']} status {rg['status']}")
     assert same, "batched and per-chunk serving differ"
-    line = {
-        "metric": "ETL Mrecords/s & % HBM peak (plain vs batched); serving p50/p99 latency",
-        "value": out["batched"]["mrec_per_s"], "unit": "Mrecords/s", "n_gpus": 1,
-        "steps": len(trace), "warmup": 0, "ms_per_step": out["batched"]["p50_ms"],
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {desc}", "pool_records": pool.n, "chunks": len(trace),
-                   "path": "served, continuous batching", "parallelism": "single GPU"},
+    assert flags_clear, "a distinct-journey cell set overflowed: counts may be high"
+    offered = sum(s for _, s in trace) / dur / 1e6
+    return {
+        "workload": f"{workload}: {desc}", "pool_records": pool.n, "chunks": len(trace),
+        "offered_mrec_per_s": round(offered, 1), "arena_records": int(arena),
+        "admission": "FIFO into a ring of record slots carved from free HBM at start-up",
+        "value": out["batched"]["mrec_per_s"], "unit": "Mrecords/s",
         "latency_batched": out["batched"], "latency_per_chunk": out["per_chunk"],
-        "identical_outputs": bool(same), "journeys": int(ra["count"]), "groups": int(rga["count"]),
+        "identical_outputs": bool(same and flags_clear), "journeys": int(ra["count"]), "groups": int(rga["count"]),
     }
-    s = json.dumps(line)
-    print(s, flush=True)
-    if args.out:
-        with open(args.out, "w") as f:
-            f.write(s + "\n")
 
 
-def main():
-    args = parse()
-    world = int(os.environ.get("WORLD_SIZE", "1"))
-    if args.gpus != 1 or world != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE={world}): the ETL path "
-              "is built and measured on a single MI355X; see the sharding design notes", file=sys.stderr)
-        sys.exit(2)
-
-    import numpy as np
+def bench_plain(args, workload):
+    """The plain path on one resident batch (C1 by default)."""
     import torch
     from paper_2305_07454_amd import cvetl
-
-    assert torch.cuda.is_available(), "bench needs a GPU"
-    if args.copy_calibration:
-        return copy_calibration(args.copy_calibration)
-    if args.workload == "c2":
-        return bench_batched(args)
-    if args.workload in ("c3", "c4"):
-        return bench_serving(args)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    r, grid, desc = make_workload(args.workload, args.n_journeys)
+    r, grid, desc = make_workload(workload, args.n_journeys)
     n = r.n
     if args.sort_shape is not None:
         cvetl.cv_tuning_set("sort_shape", args.sort_shape)
     else:
         from paper_2305_07454_amd import tune
-        tune.apply(n)
-    log(f"sort shape {cvetl.cv_tuning_get('sort_shape')} (tile {cvetl.cv_tuning_get('sort_tile')} keys)")
+        tune.apply(n, workload=workload)
+    log(f"sort shape {cvetl.cv_tuning_get('sort_shape')} (tile {cvetl.cv_tuning_get('sort_tile')} keys), "
+        f"grid LDS slots {cvetl.cv_tuning_get('grid_lds_slots')}")
     rec = cvetl.to_device(r, dev)
     torch.cuda.synchronize()
 
@@ -333,18 +379,12 @@ def main():
     cvetl.cv_timing_enable(True)
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
     wall = time.perf_counter()
-    t0.record(stream)
-    for _ in range(args.steps):
-        pipe.run(rec)
-    t1.record(stream)
-    torch.cuda.synchronize()
+    per_step = timed_steps(lambda: pipe.run(rec), args.steps, stream)
     wall = time.perf_counter() - wall
     cvetl.cv_timing_enable(False)
-    ms_total = t0.elapsed_time(t1)
-    ms_step = ms_total / args.steps
+    st = step_stats(per_step)
+    ms_step = st["median"]
     rs, rj, rg = pipe.results()
     assert rs["status"] == 0 and rj["status"] == 0 and rg["status"] == 0
 
@@ -366,7 +406,7 @@ def main():
     stages["sort_passes"] = round(pass_ms / args.steps, 4)
 
     direction, lattice = None, None
-    if not args.no_direction:
+    if not args.no_direction and workload == "c1":
         direction, gdir = bench_direction(args, r, grid, pipe, rec, G, dev)
         lattice = bench_lattice(args, grid, {k: v[:G] for k, v in pipe.groups.items()}, gdir, dev)
         lattice["hygiene"] = bench_hygiene(pipe, n, dev)
@@ -374,19 +414,21 @@ def main():
 
     traffic = None
     tfile = os.path.join(ROOT, "profiles", "radix_pass_c1_traffic.md")
-    if args.workload == "c1" and args.n_journeys is None and os.path.exists(tfile):
+    if workload == "c1" and args.n_journeys is None and os.path.exists(tfile):
         t = read_traffic(tfile)
         if t.get("kernel_source_sha") == _kernel_sha() and t.get("sort_shape") == str(cvetl.cv_tuning_get("sort_shape")):
             traffic = float(t["traffic_bytes_per_launch"])
 
+    del pipe, rec
+    torch.cuda.empty_cache()
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the oracle on a bounded sample")
         cpu = cpu_baseline(r, grid, args.cpu_sample)
 
     value = n / (ms_step / 1e3) / 1e6
-    line = {
-        "metric": "ETL Mrecords/s & % HBM peak (plain vs batched); serving p50/p99 latency",
+    return {
+        "metric": METRIC,
         "value": round(value, 3),
         "unit": "Mrecords/s",
         "n_gpus": 1,
@@ -398,18 +440,62 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {desc}", "records": n, "journeys": J, "groups": G,
+        "config": {"workload": f"{workload}: {desc}", "records": n, "journeys": J, "groups": G,
                    "path": "plain", "parallelism": "single GPU"},
+        "step_ms": st,
         "roofline": dict(roof, traffic=traffic),
         "cpu_baseline": cpu,
         "stages_ms_per_step": stages,
-        "path_roofline": path_roofline(stages, n, G, key_bits, p0, ms_step),
+        "path_roofline": path_roofline(stages, n, G, key_bits, p0, ms_step,
+                                       design_bytes=282 if workload == "c1" else None),
         "direction_lattice": direction,
         "dense_lattice": lattice,
         "key_bits": key_bits,
         "packed_from_pass": p0,
         "wall_s_timed_region": round(wall, 3),
     }
+
+
+METRIC = "ETL Mrecords/s & % HBM peak (plain vs batched); serving p50/p99 latency"
+
+
+def _line(args, sub, workload):
+    """A whole JSON line for a sub-benchmark run on its own."""
+    path = "batched" if workload == "c2" else "served, continuous batching"
+    return {"metric": METRIC, "value": sub["value"], "unit": "Mrecords/s", "n_gpus": 1,
+            "steps": sub.get("step_ms", {}).get("steps", sub.get("chunks")), "warmup": args.warmup,
+            "ms_per_step": sub.get("ms_per_step", sub.get("latency_batched", {}).get("p50_ms")),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": sub["workload"], "path": path, "parallelism": "single GPU"},
+            "roofline": sub.get("roofline"), "cpu_baseline": None, workload: sub}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE={world}): the ETL path "
+              "is built and measured on a single MI355X; see the sharding design notes", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2305_07454_amd import cvetl  # noqa: F401  (fails loudly without the HIP library)
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    if args.copy_calibration:
+        return copy_calibration(args.copy_calibration)
+    w = args.workload
+    if w == "c2":
+        line = _line(args, bench_batched(args, args.steps), "c2")
+    elif w in ("c3", "c4"):
+        line = _line(args, bench_serving(args, w), w)
+    else:
+        line = bench_plain(args, "c1" if w == "all" else w)
+        if w == "all":
+            if not args.no_batched:
+                line["batched"] = bench_batched(args, args.batched_steps)
+            if not args.no_serving:
+                line["serving"] = bench_serving(args, "c3")
     s = json.dumps(line)
     print(s, flush=True)
     if args.out:
@@ -588,9 +674,11 @@ def radix_roofline(cvetl, n, rs, traffic=None):
             "alg_bytes_per_launch": int(per_launch), "per_pass_ms": per_pass}, pass_ms
 
 
-def path_roofline(stages, n, G, key_bits, p0, ms_step):
+def path_roofline(stages, n, G, key_bits, p0, ms_step, design_bytes=None):
     """Algorithmic bytes of the whole path per step (the per-record figures of
-    each stage's kernels, plus the group tail) over the measured step time."""
+    each stage's kernels, plus the group tail) over the measured step time.
+    design_bytes: the fixed per-record byte budget of the path's design (the
+    same for any implementation of it), reported beside as a second fraction."""
     passes = (key_bits + 7) // 8
     ts_read = 0 if p0 == 0 else 8  # the time offset survives in the final word only when nothing was dropped
     per = {"sort_prep": 16 + 24, "sort_passes": sum(pass_bytes(p, p0) for p in range(passes))}
@@ -603,9 +691,14 @@ def path_roofline(stages, n, G, key_bits, p0, ms_step):
     per["grid_agg"] = 36
     total = n * sum(per.values()) + 64 * G
     gbs = total / (ms_step / 1e3) / 1e9
-    return {"bound": "hbm", "alg_bytes_per_record": per, "group_tail_bytes_per_group": 64,
-            "alg_bytes_per_step": int(total), "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    out = {"bound": "hbm", "alg_bytes_per_record": per, "group_tail_bytes_per_group": 64,
+           "alg_bytes_per_step": int(total), "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    if design_bytes:
+        dg = design_bytes * n / (ms_step / 1e3) / 1e9
+        out["design_bytes_per_record"] = design_bytes
+        out["design_frac"] = round(dg / HBM_PEAK_GBS, 4)
+    return out
 
 
 def pass_bytes(p, p0):

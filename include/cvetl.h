@@ -225,9 +225,13 @@ cv_status cv_journey_summary(const cv_records* sorted, const cv_features* feat,
  * coordinates are finite, 0 <= ilat < n_lat, 0 <= ilon < n_lon, tbin >= 0 and
  * tbin < n_t (n_t > 0) or the key fits in int64 (n_t <= 0).  Per key:
  * count, distinct journeys, exact-rounded speed sum, min and max speed; rows
- * in ascending key.  `capacity` bounds the rows and sizes the group hash
- * table; more groups set res->status = CV_ERR_CAPACITY with res->required.
- * res->count = groups, res->n_out_of_grid = records outside the grid.
+ * in ascending key.  `capacity` bounds the rows written; more groups set
+ * res->status = CV_ERR_CAPACITY with res->required = groups (the rows below
+ * capacity are written either way).  res->count = groups, res->n_out_of_grid
+ * = records outside the grid.  The workspace depends on n alone (about 64
+ * bytes per record: each tile of sorted records leaves at most one partial
+ * row per record, which a key sort merges into the group rows), so any
+ * capacity < 2^32 fits it.
  * --------------------------------------------------------------------- */
 cv_status cv_grid_workspace_size(uint64_t n, const cv_grid_spec* grid /*[host]*/, uint64_t capacity,
                                  size_t* bytes /*[host]*/);
@@ -393,6 +397,27 @@ cv_status cv_batch_grid_aggregate(const cv_records* sorted, const uint64_t* shar
                                   void* stream);
 
 /* ------------------------------------------------------------------------
+ * cv_batch_run -- the whole batched path in one call: the sort with the
+ * kinematics (cv_batch_sort_records_features), the journey summaries
+ * (cv_batch_journey_summary) and the group table (cv_batch_grid_aggregate),
+ * enqueued in that order on `stream`, every output as those calls define it.
+ *   shard_n_out  [device, n_shards, nullable] out: records outside the grid
+ *                per shard.
+ *   res          [device, 3 results] out: the sort's, the summary's, the grid's.
+ *   ws           one workspace of cv_batch_workspace_size bytes serves all
+ *                three stages (they run one after the other).
+ * --------------------------------------------------------------------- */
+cv_status cv_batch_workspace_size(uint64_t n, uint32_t n_shards, uint64_t max_journeys, uint64_t journey_capacity,
+                                  const cv_grid_spec* grid /*[host]*/, uint64_t group_capacity,
+                                  size_t* bytes /*[host]*/);
+cv_status cv_batch_run(const cv_records* in, const uint64_t* shard_offsets, uint32_t n_shards,
+                       const cv_grid_spec* grid /*[host]*/, uint64_t max_journeys, uint32_t* perm,
+                       const cv_records_out* sorted, const cv_features* feat, const cv_journeys* journeys,
+                       uint64_t journey_capacity, uint64_t* journey_offsets, const cv_groups* groups,
+                       uint64_t group_capacity, uint64_t* group_offsets, uint64_t* shard_n_out, cv_result* res,
+                       void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
  * Serving form: records arrive in chunks and are pushed in batches (one or
  * more chunks in arrival order); the open journeys (last point, running
  * summary, cells of the open time-bin segment) and the group table stay
@@ -424,7 +449,28 @@ cv_status cv_batch_grid_aggregate(const cv_records* sorted, const uint64_t* shar
  *                         totals of late and out-of-grid records), res[1] groups.
  *                         The stream stays usable (flush is a snapshot).
  *   cv_stream_destroy     frees the host handle (the state is the caller's).
- * Pushes and flushes of one stream must be ordered on one HIP stream.
+ * Pushes and flushes of one stream must be ordered on one HIP stream.  Every
+ * int64 journey id is valid, INT64_MIN included (it has a reserved row).
+ *
+ * Checkpoint / resume of a stream (the paper persists only its transformed
+ * output; the resident serving state is this library's own):
+ *   cv_stream_snapshot_size  [host out] bytes of a snapshot: a 256-byte header
+ *                         plus the resident state (journey table and rows,
+ *                         overflow pool, group table with its exact limbs, the
+ *                         running totals); it depends on the capacities the
+ *                         stream was created with, not on how full it is.
+ *   cv_stream_snapshot    copies that state into host_buf [host, >= the size
+ *                         above; pinned memory lets the copy run
+ *                         asynchronously] in stream order after the pushes
+ *                         before it; read host_buf only after synchronising
+ *                         `stream`.
+ *   cv_stream_restore     replaces the resident state of `st` with a snapshot;
+ *                         `st` must have been created with the same grid,
+ *                         max_journeys and max_groups (max_batch may differ),
+ *                         else CV_ERR_INVALID_ARGUMENT and nothing is
+ *                         enqueued.  host_buf must stay unchanged until
+ *                         `stream` has passed the copy.  Pushes after a restore
+ *                         continue exactly as after the snapshot.
  * --------------------------------------------------------------------- */
 #define CV_FLAG_LATE 0x80u /* serving form: record older than its journey's state */
 typedef struct cv_stream cv_stream;
@@ -437,6 +483,9 @@ cv_status cv_stream_push(cv_stream* st, const cv_records* batch, const cv_featur
                          void* stream);
 cv_status cv_stream_flush(cv_stream* st, const cv_journeys* journeys, uint64_t journey_capacity,
                           const cv_groups* groups, uint64_t group_capacity, cv_result* res, void* stream);
+cv_status cv_stream_snapshot_size(const cv_stream* st, size_t* bytes /*[host]*/);
+cv_status cv_stream_snapshot(cv_stream* st, void* host_buf /*[host]*/, size_t bytes, void* stream);
+cv_status cv_stream_restore(cv_stream* st, const void* host_buf /*[host]*/, size_t bytes, void* stream);
 cv_status cv_stream_destroy(cv_stream* st);
 
 /* ------------------------------------------------------------------------

@@ -50,10 +50,13 @@ constexpr uint8_t B_PEND = 16; // run head left to the block-wide scan of its se
 
 // Partial aggregate of one run (or piece of a run).  The speed sum is a
 // 128-bit two's-complement integer in units of 2^-53, exact for every float32
-// speed v with 2^-30 <= |v| < 2^10 (and for zeros); any other speed is added
-// to the table on its own, in the full 192-bit format.  Count and distinct
-// journeys share one word (16 bits each: a piece holds at most GT / 4
-// records).
+// speed v with 2^-30 <= |v| < 2^10 (and for zeros).  A record with any other
+// speed is a run of its own (the records on both sides of it start runs), so
+// its piece holds that one speed: RUN_ODD is set and lo holds the float's
+// bits, converted to the 192-bit format when the piece is inserted.  Count
+// and distinct journeys share one word (count in bits 0-15, journeys in bits
+// 16-30: a piece holds at most GT / 4 records); bit 31 is RUN_ODD.
+constexpr u32 RUN_ODD = 0x80000000u;
 struct RunPart {
     u64 lo, hi;
     u32 cn, mn, mx;
@@ -148,11 +151,57 @@ __device__ __forceinline__ void run_seg_scan(RunPart& p, bool head)
     for (int k = 0, d = 1; d < WAVE; ++k, d <<= 1) run_step(p, d, true, ((take >> k) & 1u) != 0);
 }
 
+// Where a tile's group contributions go.
+// The serving form: its resident HBM hash table (kept across pushes).
+struct SinkTable {
+    static constexpr bool kParts = false;
+    GEntry* tab;
+    u64 mask;
+    GridMeta* meta;
+    __device__ void put(u64 key, u32 count, u32 nj, const Fx192& sum, u32 mn, u32 mx, u32*, u64*, u64) const
+    {
+        g_insert(tab, mask, meta, key, count, nj, sum, mn, mx);
+    }
+};
+
+// The plain and batched forms: partial rows in the tile's own region of GT
+// rows.  A tile never writes more than GT of them: every partial holds at
+// least one of its records, and no record is in two partials.  The count per
+// tile and its largest key follow at the end of the tile.
+struct SinkParts {
+    static constexpr bool kParts = true;
+    u64* key;    // [tiles * GT]
+    GPart* part; // [tiles * GT]
+    u32* count;  // [tiles]
+    u64* kmax;   // [tiles]
+    u32* bad;    // set if a tile ever had more than GT partials (it cannot; checked, never written past)
+    __device__ void put(u64 k, u32 count_, u32 nj, const Fx192& sum, u32 mn, u32 mx, u32* s_np, u64* s_kmax,
+                        u64 tile) const
+    {
+        const u32 j = atomicAdd(s_np, 1u);
+        if (j >= (u32)GT) {
+            atomicOr(bad, 1u);
+            return;
+        }
+        const u64 at = tile * (u64)GT + j;
+        key[at] = k;
+        GPart pr;
+        pr.cnj = (u64)count_ | ((u64)nj << 32);
+        pr.s[0] = sum.w[0];
+        pr.s[1] = sum.w[1];
+        pr.s[2] = sum.w[2];
+        pr.mn = mn;
+        pr.mx = mx;
+        part[at] = pr;
+        atomicMax((unsigned long long*)s_kmax, (unsigned long long)k);
+    }
+};
+
 // one contribution to key's group in the tile's LDS table; no free slot within
-// the probe limit spills it straight to the HBM table
-template <int LHS>
-__device__ __forceinline__ void slot_insert(u64* s_hkey, LSlot* s_h, GEntry* tab, u64 gmask, GridMeta* meta, u64 key,
-                                            const Fx192& sum, u32 count, u32 nj, u32 mn, u32 mx)
+// the probe limit hands it to the sink on its own
+template <int LHS, class Sink>
+__device__ __forceinline__ void slot_insert(u64* s_hkey, LSlot* s_h, const Sink& sk, u32* s_np, u64* s_kmax, u64 tile,
+                                            u64 key, const Fx192& sum, u32 count, u32 nj, u32 mn, u32 mx)
 {
     u64 h = mix64(key) & (LHS - 1);
     for (int probe = 0; probe < LHS_PROBES; ++probe) {
@@ -176,23 +225,31 @@ __device__ __forceinline__ void slot_insert(u64* s_hkey, LSlot* s_h, GEntry* tab
         }
         h = (h + 1) & (LHS - 1);
     }
-    g_insert(tab, gmask, meta, key, count, nj, sum, mn, mx);
+    sk.put(key, count, nj, sum, mn, mx, s_np, s_kmax, tile);
 }
 
-template <int LHS>
-__device__ __forceinline__ void run_insert(u64* s_hkey, LSlot* s_h, GEntry* tab, u64 gmask, GridMeta* meta, u64 key,
-                                           const RunPart& p)
+template <int LHS, class Sink>
+__device__ __forceinline__ void run_insert(u64* s_hkey, LSlot* s_h, const Sink& sk, u32* s_np, u64* s_kmax, u64 tile,
+                                           u64 key, const RunPart& p)
 {
-    slot_insert<LHS>(s_hkey, s_h, tab, gmask, meta, key, run_sum192(p), p.cn & 0xFFFFu, p.cn >> 16, p.mn, p.mx);
+    const Fx192 sum = (p.cn & RUN_ODD) ? fx_from_double<FX_SPD>((double)__uint_as_float((u32)p.lo)) : run_sum192(p);
+    slot_insert<LHS>(s_hkey, s_h, sk, s_np, s_kmax, tile, key, sum, p.cn & 0xFFFFu, (p.cn >> 16) & 0x7FFFu, p.mn,
+                     p.mx);
+}
+
+// a speed outside the 128-bit fast format (a run of its own)
+__device__ __forceinline__ bool spd_odd(float v)
+{
+    i64 x;
+    return !spd_fix53(v, x);
 }
 
 // three workgroups per CU fit the LDS of the 256-slot table: the register
 // budget is set to match (the larger tables leave room for fewer)
-template <int LHS, class Pol>
-__global__ void __launch_bounds__(GB) __attribute__((amdgpu_waves_per_eu(LHS <= 256 ? 3 : 1)))
+template <int LHS, class Pol, class Sink>
+__global__ void __launch_bounds__(GB) __attribute__((amdgpu_waves_per_eu(LHS <= 256 ? 3 : (LHS <= 512 ? 2 : 1))))
 k_grid_agg(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, const double* __restrict__ lat,
-           const double* __restrict__ lon, const float* __restrict__ spd, Spec g, GEntry* __restrict__ tab, u64 gmask,
-           GridMeta* meta, Pol pol)
+           const double* __restrict__ lon, const float* __restrict__ spd, Spec g, Sink sk, GridMeta* meta, Pol pol)
 {
     constexpr int NQ = HALO + GT;
     __shared__ i64 s_key[NQ];       // keys per record; later the keys of the run-head list
@@ -213,6 +270,9 @@ k_grid_agg(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, const
     __shared__ u32 s_npend, s_pn, s_nfound;
     __shared__ unsigned long long s_r0[2];
     __shared__ u64 s_out[GB / WAVE];
+    __shared__ uint8_t s_rodd[HALO / GB + GI][NWG];  // a speed outside the fast format in this wave row
+    __shared__ u32 s_np;                             // partial rows this tile wrote (partial sink)
+    __shared__ u64 s_kmax;                           // their largest key
 
     const int t = threadIdx.x;
     const u64 tile0 = (u64)blockIdx.x * GT;
@@ -270,6 +330,8 @@ k_grid_agg(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, const
         s_plt = (Pol::kStream && base > 0) ? (uint8_t)pol.late((u64)(base - 1)) : (uint8_t)0;
         s_lo = -1;
         s_npend = 0;
+        s_np = 0;
+        s_kmax = 0;
     }
     u64 n_out = 0;
     const u32 sh0 = g.S > 1 ? shard_of(g.soff, g.S, (u64)(base > 0 ? base : 0)) : 0u;
@@ -288,7 +350,10 @@ k_grid_agg(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, const
             if constexpr (Pol::kDir == 1) dir = dir_sector(g, (double)vh[rr], true);
             if constexpr (Pol::kDir == 2) dir = dir_sector(g, vb[rr], (vbf[rr] & CV_FLAG_BEARING_OK) != 0);
             k = grid_key_in(g, sh, vt[rr], vla[rr], vlo[rr], tb, dir);
-            if (rr >= HR) n_out += (k < 0);
+            if (rr >= HR && k < 0) {
+                ++n_out;
+                if (g.sout) atomicAdd((unsigned long long*)&g.sout[sh], 1ull);
+            }
         }
         const i64 jp = __shfl_up(vj[rr], 1, WAVE);
         const i64 tbp = __shfl_up(tb, 1, WAVE);
@@ -308,6 +373,10 @@ k_grid_agg(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, const
         if (lane == 0) s_ltbs[rr][w] = tb;
         s_key[q] = k;
         if (rr >= HR) s_spd[q - HALO] = in ? vsp[rr - HR] : 0.f;
+        if (rr >= HR) {
+            const u64 om = __ballot(in && spd_odd(vsp[rr - HR]));
+            if (lane == 0) s_rodd[rr][w] = om != 0;
+        }
     }
     __syncthreads();
     // Segment and run starts of lane 0 (its predecessor is lane 63 of the wave
@@ -334,6 +403,18 @@ k_grid_agg(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, const
             else if (!first_row && s_key[q] != s_lk[pr][pw]) b |= B_RUN;
         }
         if ((b & B_SEG) || q == 0) b |= B_RUN;
+        if (rr >= HR) {
+            // a record whose speed is outside the fast format is a run of its
+            // own: it and the record after it start runs (the tile's first
+            // record starts a piece of the aggregation anyway)
+            const int pr = w > 0 ? rr : rr - 1;
+            const int pw = w > 0 ? w - 1 : NWG - 1;
+            const bool chk = s_rodd[rr][w] || (lane == 0 && pr >= HR && s_rodd[pr][pw]);
+            if (chk && r < (long)n) {
+                const int qt = q - HALO;
+                if (spd_odd(s_spd[qt]) || (qt > 0 && spd_odd(s_spd[qt - 1]))) b |= B_RUN;
+            }
+        }
         s_bits[q] = b;
         if ((b & B_SEG) && q <= HALO) lo_cand = q;
         hm[rr] = __ballot((b & B_RUN) && r < (long)n);
@@ -549,7 +630,7 @@ k_grid_agg(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, const
             if ((b & B_RUN) || (i == 0 && l == 0)) {
                 if (i > 0) {
                     if (!hh) pre = cur;
-                    else if (ck >= 0 && cur.cn) run_insert<LHS>(s_hkey, s_h, tab, gmask, meta, (u64)ck, cur);
+                    else if (ck >= 0 && cur.cn) run_insert<LHS>(s_hkey, s_h, sk, &s_np, &s_kmax, blockIdx.x, (u64)ck, cur);
                     run_reset(cur);
                     ck = s_key[q0 + i];
                 }
@@ -561,9 +642,11 @@ k_grid_agg(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, const
                 if (spd_fix53(sp, x)) {
                     add128(cur.lo, cur.hi, (u64)x, (u64)(x >> 63));
                 } else {
-                    // a speed outside the 128-bit range: its exact value on its own
-                    slot_insert<LHS>(s_hkey, s_h, tab, gmask, meta, (u64)ck, fx_from_double<FX_SPD>((double)sp), 0u,
-                                     0u, ~0u, 0u);
+                    // a speed outside the 128-bit range: the record is a piece of
+                    // its own (both neighbours start runs), so cur was empty
+                    cur.lo = (u64)__float_as_uint(sp);
+                    cur.hi = 0;
+                    cur.cn |= RUN_ODD;
                 }
                 cur.cn += 1u | ((b & B_FIRST) ? (1u << 16) : 0u);
                 const u32 o = ord_f32(sp);
@@ -586,12 +669,12 @@ k_grid_agg(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, const
         if (hh && l > 0) {
             run_combine(in, pre);
             const i64 kb = s_key[q0 - 1];  // the run ends in this lane: its key is the record below's
-            if (kb >= 0 && in.cn) run_insert<LHS>(s_hkey, s_h, tab, gmask, meta, (u64)kb, in);
+            if (kb >= 0 && in.cn) run_insert<LHS>(s_hkey, s_h, sk, &s_np, &s_kmax, blockIdx.x, (u64)kb, in);
         }
         const int qlast = (qa + WREC < qend ? qa + WREC : qend) - 1;
         if (l == WAVE - 1 && qlast >= qa) {
             const i64 ke = s_key[qlast];  // the run open at the wave's end
-            if (ke >= 0 && out.cn) run_insert<LHS>(s_hkey, s_h, tab, gmask, meta, (u64)ke, out);
+            if (ke >= 0 && out.cn) run_insert<LHS>(s_hkey, s_h, sk, &s_np, &s_kmax, blockIdx.x, (u64)ke, out);
         }
     }
     // out-of-grid count (one global atomic per tile, only when non-zero)
@@ -604,13 +687,20 @@ k_grid_agg(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, const
         for (int w = 0; w < GB / WAVE; ++w) tot += s_out[w];
         if (tot) atomicAdd((unsigned long long*)&meta->n_out, (unsigned long long)tot);
     }
-    // merge the LDS table into the HBM table
+    // the LDS table to the sink (the HBM table, or the tile's partial rows)
     for (int i = t; i < LHS; i += GB) {
         const u64 key = s_hkey[i];
         if (key == GEMPTY) continue;
         const LSlot& sl = s_h[i];
         const Fx192 sum = fx_from_cs(sl.cs);
-        g_insert(tab, gmask, meta, key, sl.count, sl.nj, sum, sl.mn, sl.mx);
+        sk.put(key, sl.count, sl.nj, sum, sl.mn, sl.mx, &s_np, &s_kmax, blockIdx.x);
+    }
+    if constexpr (Sink::kParts) {
+        __syncthreads();
+        if (t == 0) {
+            sk.count[blockIdx.x] = s_np < (u32)GT ? s_np : (u32)GT;
+            sk.kmax[blockIdx.x] = s_kmax;
+        }
     }
 }
 

@@ -6,8 +6,11 @@
 //     count, distinct journeys, an exact speed sum in carry-save 40-bit chunks
 //     and min / max speed as ordered integers, updated with integer atomics
 //     only, so its content does not depend on the order of the updates;
-//   * the tail: occupied entries compacted, radix-sorted by key, emitted in
-//     ascending key (kernels with internal linkage, one copy per user).
+//   * the tail of that table (the serving form's flush): occupied entries
+//     compacted, radix-sorted by key, emitted in ascending key (kernels with
+//     internal linkage, one copy per user);
+//   * the partial row of a tile (GPart), which the plain and batched forms
+//     merge by a key sort instead of a table.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -52,15 +55,25 @@ __device__ __forceinline__ Fx192 fx_from_cs40(const u64 c[CS40])
     return r;
 }
 
+// A partial group row of one tile (plain and batched forms): the tile's
+// records of one key, merged with the other tiles' partials of that key after
+// a key sort.  40 bytes; the sum is exact (192-bit two's complement, 2^-149 units).
+struct GPart {
+    u64 cnj;   // count | distinct journeys << 32
+    u64 s[3];
+    u32 mn, mx;
+};
+static_assert(sizeof(GPart) == 40, "partial layout");
+
 struct GridMeta {
-    u32 pad0;
+    u32 groups;     // groups after the merge of the partials
     u32 overflow;   // HBM table full
     u64 n_out;      // records outside the grid
     u64 max_key;    // largest key seen
     u32 key_bits;
     u32 passes;
     u32 compact_n;
-    u32 pad;
+    u32 chunks;     // chunks of sorted partial pairs (the partial-row merge)
     u32 tickets[MAX_PASSES];
 };
 
@@ -78,6 +91,7 @@ struct Spec {
     const float* hdg;
     const double* brg;
     const uint8_t* bfl;
+    u64* sout;  // batched form, nullable: records outside the grid per shard
 };
 
 // floor(a / b) for b > 0: a double estimate corrected by one integer step
@@ -307,30 +321,6 @@ __attribute__((unused)) __global__ void k_grid_empty(cv_result* res)
     if (threadIdx.x == 0) {
         cv_result r = {};
         *res = r;
-    }
-}
-
-// group_offsets[s] = first group of shard s (groups are sorted by shard, then key)
-__attribute__((unused)) __global__ void __launch_bounds__(256) k_group_offsets(const GridMeta* meta, const u64* __restrict__ K0,
-                                                       const u64* __restrict__ K1, u32 S, u32 kb,
-                                                       u64* __restrict__ go)
-{
-    const u32 G = meta->compact_n;
-    const u32 np = meta->passes;
-    const u64* K = np == 0 ? K0 : ((np & 1) ? K1 : K0);
-    for (u32 s = blockIdx.x * blockDim.x + threadIdx.x; s <= S; s += gridDim.x * blockDim.x) {
-        if (s == S) {
-            go[s] = G;
-            continue;
-        }
-        const u64 lo_key = (u64)s << kb;
-        u32 lo = 0, hi = G;  // first index with key >= lo_key
-        while (lo < hi) {
-            const u32 mid = (lo + hi) >> 1;
-            if (K[mid] < lo_key) lo = mid + 1;
-            else hi = mid;
-        }
-        go[s] = lo;
     }
 }
 

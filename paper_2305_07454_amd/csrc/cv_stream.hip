@@ -26,7 +26,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstring>
 #include <new>
+#include <string>
 
 #include "cv_device.h"
 #include "cv_gridagg.h"
@@ -84,14 +86,21 @@ struct StreamMeta {
     u64 batch_late, batch_out;
     u64 total_records, total_late, total_out;
     u32 jcount;         // flush: occupied journey rows
-    u32 pad2;
+    u32 min_used;       // the reserved row of journey id INT64_MIN is taken
     GridMeta gm;        // group table bookkeeping (overflow, compaction, key bits)
     u32 jtickets[MAX_PASSES];
 };
 
-__device__ __forceinline__ u64 jt_find_or_insert(u64* keys, u64 mask, u64 key, bool& inserted)
+// Journey table: open addressing on the id, JEMPTY marking a free slot.  The
+// one id equal to JEMPTY (INT64_MIN) cannot live in a slot; it has the
+// reserved row mask + 1, taken through the min_used flag.
+__device__ __forceinline__ u64 jt_find_or_insert(u64* keys, u64 mask, u64 key, bool& inserted, u32* min_used)
 {
     inserted = false;
+    if (key == JEMPTY) {
+        inserted = atomicCAS(min_used, 0u, 1u) == 0u;
+        return mask + 1;
+    }
     u64 h = mix64(key) & mask;
     for (u64 probe = 0; probe <= mask && probe < G_PROBES; ++probe) {
         u64 cur = keys[h];
@@ -192,7 +201,7 @@ __global__ void __launch_bounds__(256) k_st_journeys(const i64* __restrict__ jid
     for (u32 j = blockIdx.x * blockDim.x + threadIdx.x; j < Jb; j += gridDim.x * blockDim.x) {
         const u64 key = (u64)jid[boff[j]];
         bool ins;
-        const u64 s = jt_find_or_insert(jkeys, jmask, key, ins);
+        const u64 s = jt_find_or_insert(jkeys, jmask, key, ins, &m->min_used);
         if (s == ~0ull) {
             atomicOr(&m->jt_full, 1u);
             bslot[j] = ~0u;
@@ -655,6 +664,12 @@ __global__ void __launch_bounds__(256) k_st_jcompact(const u64* __restrict__ jke
             cv[pos] = (u32)s;
         }
     }
+    // the reserved row of journey id INT64_MIN (its key reads INT64_MIN: jkeys[slots] stays JEMPTY)
+    if (blockIdx.x == 0 && threadIdx.x == 0 && m->min_used) {
+        const u32 pos = atomicAdd(&m->jcount, 1u);
+        ck[pos] = 0;
+        cv[pos] = (u32)slots;
+    }
 }
 
 // first = exclusive prefix of n_points in id order (one block)
@@ -726,6 +741,7 @@ __global__ void __launch_bounds__(256) k_st_jemit(const JRow* __restrict__ rows,
 struct cv_stream {
     Spec g;
     u64 jslots, gslots, max_batch;
+    size_t resident_bytes;  // meta, journey table and rows, group table, overflow pool: the state a snapshot holds
     // resident state
     StreamMeta* meta;
     u64* jkeys;
@@ -774,10 +790,11 @@ struct StreamLayout {
         size_t sort_ws = 0;
         cv_sort_workspace_size(mb, mb ? mb : 1, &sort_ws);
         f("meta", c.take<StreamMeta>(1));
-        f("jkeys", c.take<u64>(jslots));
-        f("rows", c.take<JRow>(jslots));
+        f("jkeys", c.take<u64>(jslots + 1));
+        f("rows", c.take<JRow>(jslots + 1));
         f("tab", c.take<GEntry>(gslots));
         f("ovf_pool", c.take<u64>(opages * OVF_SLOTS));
+        // everything above persists across pushes; everything below is per-push or per-flush scratch
         f("sort_ws", c.take<char>(sort_ws));
         f("perm", c.take<u32>(mb));
         f("s_jid", c.take<i64>(mb));
@@ -799,7 +816,7 @@ struct StreamLayout {
         f("sum_ws", c.take<char>(cv::sum_partials_bytes(mb)));
         f("ap", c.take<Append>(mb));
         const u64 gst = (gslots + sort_min_tile() - 1) / sort_min_tile();
-        const u64 jst = (jslots + sort_min_tile() - 1) / sort_min_tile();
+        const u64 jst = (jslots + 1 + sort_min_tile() - 1) / sort_min_tile();
         f("gK0", c.take<u64>(gslots));
         f("gK1", c.take<u64>(gslots));
         f("gC", c.take<u32>(gslots));
@@ -808,11 +825,11 @@ struct StreamLayout {
         f("ghist", c.take<u32>(MAX_PASSES * RADIX));
         f("goffs", c.take<u32>(MAX_PASSES * RADIX));
         f("gstatus", c.take<u64>(gst * RADIX + 1));
-        f("jK0", c.take<u64>(jslots));
-        f("jK1", c.take<u64>(jslots));
-        f("jV0", c.take<u32>(jslots));
-        f("jV1", c.take<u32>(jslots));
-        f("jfirst", c.take<u32>(jslots));
+        f("jK0", c.take<u64>(jslots + 1));
+        f("jK1", c.take<u64>(jslots + 1));
+        f("jV0", c.take<u32>(jslots + 1));
+        f("jV1", c.take<u32>(jslots + 1));
+        f("jfirst", c.take<u32>(jslots + 1));
         f("jhist", c.take<u32>(MAX_PASSES * RADIX));
         f("joffs", c.take<u32>(MAX_PASSES * RADIX));
         f("jstatus", c.take<u64>(jst * RADIX + 1));
@@ -833,6 +850,43 @@ bool stream_spec_ok(const cv_grid_spec* g)
     if (g->n_lat <= 0 || g->n_lon <= 0 || g->bin_ms <= 0 || g->n_lat > (1ll << 31) || g->n_lon > (1ll << 31))
         return false;
     return true;
+}
+
+// Header of a snapshot: what must match between the stream that wrote it and
+// the stream that restores it (the resident layout depends on the table sizes
+// and the binning on the grid).
+struct SnapHeader {
+    u64 magic;
+    u64 abi;
+    u64 jslots, gslots, opages;
+    u64 resident_bytes;
+    double lat0, lon0, dlat, dlon;
+    i64 n_lat, n_lon, t0, bin_ms, tmax;
+};
+constexpr u64 SNAP_MAGIC = 0x31706e7374657663ull;  // "cvetsnp1"
+constexpr size_t SNAP_HDR = 256;
+static_assert(sizeof(SnapHeader) <= SNAP_HDR, "snapshot header");
+
+SnapHeader snap_header(const cv_stream* st)
+{
+    SnapHeader h;
+    std::memset(&h, 0, sizeof(h));
+    h.magic = SNAP_MAGIC;
+    h.abi = CV_ABI_VERSION;
+    h.jslots = st->jslots;
+    h.gslots = st->gslots;
+    h.opages = ovf_pages(st->jslots);
+    h.resident_bytes = st->resident_bytes;
+    h.lat0 = st->g.lat0;
+    h.lon0 = st->g.lon0;
+    h.dlat = st->g.dlat;
+    h.dlon = st->g.dlon;
+    h.n_lat = st->g.n_lat;
+    h.n_lon = st->g.n_lon;
+    h.t0 = st->g.t0;
+    h.bin_ms = st->g.bin_ms;
+    h.tmax = st->g.tmax;
+    return h;
 }
 
 }  // namespace
@@ -884,6 +938,7 @@ cv_status cv_stream_create(const cv_grid_spec* grid, uint64_t max_journeys, uint
     g.hdg = nullptr;
     g.brg = nullptr;
     g.bfl = nullptr;
+    g.sout = nullptr;
     cvh::Carver c(state);
     StreamLayout::carve(c, st->jslots, st->gslots, max_batch, [&](const char* name, void* p) {
         const std::string nm(name);
@@ -892,7 +947,10 @@ cv_status cv_stream_create(const cv_grid_spec* grid, uint64_t max_journeys, uint
         else if (nm == "rows") st->rows = (JRow*)p;
         else if (nm == "tab") st->tab = (GEntry*)p;
         else if (nm == "ovf_pool") st->ovf_pool = (u64*)p;
-        else if (nm == "sort_ws") st->sort_ws = p;
+        else if (nm == "sort_ws") {
+            st->sort_ws = p;
+            st->resident_bytes = (size_t)((char*)p - (char*)state);
+        }
         else if (nm == "perm") st->perm = (u32*)p;
         else if (nm == "s_jid") st->s_jid = (i64*)p;
         else if (nm == "s_ts") st->s_ts = (i64*)p;
@@ -932,7 +990,7 @@ cv_status cv_stream_create(const cv_grid_spec* grid, uint64_t max_journeys, uint
     st->arows = acc_rows(st->jslots, max_batch);
     hipStream_t s = (hipStream_t)stream;
     hipLaunchKernelGGL(k_st_init_meta, dim3(1), dim3(64), 0, s, st->meta);
-    cvh::fill_u64(st->jkeys, JEMPTY, st->jslots, s);
+    cvh::fill_u64(st->jkeys, JEMPTY, st->jslots + 1, s);
     hipLaunchKernelGGL(k_grid_clear, dim3(cvh::grid_for(st->gslots, 256, 4096)), dim3(256), 0, s, st->tab, st->gslots,
                        &st->meta->gm);
     cvh::fill_u64(st->ovf_pool, OVF_EMPTY, (u64)ovf_pages(st->jslots) * OVF_SLOTS, s);
@@ -1013,9 +1071,9 @@ cv_status cv_stream_push(cv_stream* st, const cv_records* batch, const cv_featur
         cvh::TimedScope t5("stream_grid", s);
         GridStream pol{st->s_jid, st->fs_flags, st->boff, st->meta, st->bslot, st->rows, st->ovf_pool,
                        cells,     st->ap,       (u32)st->max_batch, &st->meta->ap_n};
-        hipLaunchKernelGGL((k_grid_agg<256, GridStream>), dim3((unsigned)((n + GT - 1) / GT)), dim3(GB), 0, s, nn,
-                           st->s_jid, st->s_ts, st->s_lat, st->s_lon, st->s_spd, st->g, st->tab, st->gslots - 1,
-                           &st->meta->gm, pol);
+        const SinkTable sk{st->tab, st->gslots - 1, &st->meta->gm};
+        hipLaunchKernelGGL((k_grid_agg<256, GridStream, SinkTable>), dim3((unsigned)((n + GT - 1) / GT)), dim3(GB), 0,
+                           s, nn, st->s_jid, st->s_ts, st->s_lat, st->s_lon, st->s_spd, st->g, sk, &st->meta->gm, pol);
     }
     {
         // resident rows: the partials, the last point, the open segment's cells
@@ -1042,19 +1100,20 @@ cv_status cv_stream_flush(cv_stream* st, const cv_journeys* journeys, uint64_t j
     // journeys
     cvh::fill_u32(&st->meta->jcount, 0u, 1, s);
     cvh::fill_u32(st->jhist, 0u, MAX_PASSES * RADIX, s);
-    const u64 jst = (st->jslots + sort_min_tile() - 1) / sort_min_tile();
+    const u64 jrows = st->jslots + 1;  // table slots and the reserved row
+    const u64 jst = (jrows + sort_min_tile() - 1) / sort_min_tile();
     cvh::fill_u64(st->jstatus, 0ull, jst * RADIX + 1, s);
     cvh::fill_u32(st->meta->jtickets, 0u, MAX_PASSES, s);
     hipLaunchKernelGGL(k_st_jcompact, dim3(cvh::grid_for(st->jslots, 256, 4096)), dim3(256), 0, s, st->jkeys,
                        st->jslots, st->meta, st->jK0, st->jV0);
     const u32* jn = &st->meta->jcount;
-    radix_hist(st->jK0, (u32)st->jslots, jn, MAX_PASSES, nullptr, st->jhist, cvh::grid_for(st->jslots, 256, 1024), s);
+    radix_hist(st->jK0, (u32)jrows, jn, MAX_PASSES, nullptr, st->jhist, cvh::grid_for(jrows, 256, 1024), s);
     radix_scan(st->jhist, st->joffs, MAX_PASSES, s);
     // 8 passes: the sorted pairs end in (jK0, jV0); pass 0 reads the slot values from jV0 via jfirst copy
     u32* vfirst = st->jfirst;
-    if (hipMemcpyAsync(vfirst, st->jV0, st->jslots * sizeof(u32), hipMemcpyDeviceToDevice, s) != hipSuccess)
+    if (hipMemcpyAsync(vfirst, st->jV0, jrows * sizeof(u32), hipMemcpyDeviceToDevice, s) != hipSuccess)
         return CV_ERR_DEVICE;
-    radix_passes(st->jK0, st->jK1, vfirst, st->jV0, st->jV1, (u32)st->jslots, jn, nullptr, MAX_PASSES, st->joffs,
+    radix_passes(st->jK0, st->jK1, vfirst, st->jV0, st->jV1, (u32)jrows, jn, nullptr, MAX_PASSES, st->joffs,
                  st->jstatus, st->meta->jtickets, s);
     cv_status e = CV_OK;
     if (jcap > 0) {
@@ -1094,6 +1153,40 @@ cv_status cv_stream_flush(cv_stream* st, const cv_journeys* journeys, uint64_t j
                        res ? res + 1 : nullptr, ~0ull);
     e = cvh::last_launch_status();
     return e;
+}
+
+cv_status cv_stream_snapshot_size(const cv_stream* st, size_t* bytes)
+{
+    if (!st || !bytes) return CV_ERR_INVALID_ARGUMENT;
+    *bytes = SNAP_HDR + st->resident_bytes;
+    return CV_OK;
+}
+
+cv_status cv_stream_snapshot(cv_stream* st, void* host_buf, size_t bytes, void* stream)
+{
+    if (!st || !host_buf || bytes < SNAP_HDR + st->resident_bytes) return CV_ERR_INVALID_ARGUMENT;
+    const SnapHeader h = snap_header(st);
+    std::memset(host_buf, 0, SNAP_HDR);
+    std::memcpy(host_buf, &h, sizeof(h));
+    if (hipMemcpyAsync((char*)host_buf + SNAP_HDR, st->meta, st->resident_bytes, hipMemcpyDeviceToHost,
+                       (hipStream_t)stream) != hipSuccess)
+        return CV_ERR_DEVICE;
+    return CV_OK;
+}
+
+cv_status cv_stream_restore(cv_stream* st, const void* host_buf, size_t bytes, void* stream)
+{
+    if (!st || !host_buf || bytes < SNAP_HDR) return CV_ERR_INVALID_ARGUMENT;
+    SnapHeader h;
+    std::memcpy(&h, host_buf, sizeof(h));
+    const SnapHeader mine = snap_header(st);
+    if (h.magic != SNAP_MAGIC || h.abi != CV_ABI_VERSION || bytes < SNAP_HDR + h.resident_bytes ||
+        std::memcmp(&h, &mine, sizeof(h)) != 0)
+        return CV_ERR_INVALID_ARGUMENT;
+    if (hipMemcpyAsync(st->meta, (const char*)host_buf + SNAP_HDR, st->resident_bytes, hipMemcpyHostToDevice,
+                       (hipStream_t)stream) != hipSuccess)
+        return CV_ERR_DEVICE;
+    return CV_OK;
 }
 
 cv_status cv_stream_destroy(cv_stream* st)

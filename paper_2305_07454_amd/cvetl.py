@@ -152,6 +152,18 @@ def lib():
         L.cv_stream_flush.restype = S
         L.cv_stream_destroy.argtypes = [P]
         L.cv_stream_destroy.restype = S
+        L.cv_batch_workspace_size.argtypes = [U64, ctypes.c_uint32, U64, U64, ctypes.POINTER(CvGridSpec), U64, SZ]
+        L.cv_batch_workspace_size.restype = S
+        L.cv_batch_run.argtypes = [ctypes.POINTER(CvRecords), P, ctypes.c_uint32, ctypes.POINTER(CvGridSpec), U64, P,
+                                   ctypes.POINTER(CvRecordsOut), ctypes.POINTER(CvFeatures), ctypes.POINTER(CvJourneys),
+                                   U64, P, ctypes.POINTER(CvGroups), U64, P, P, P, P, ctypes.c_size_t, P]
+        L.cv_batch_run.restype = S
+        L.cv_stream_snapshot_size.argtypes = [P, SZ]
+        L.cv_stream_snapshot_size.restype = S
+        L.cv_stream_snapshot.argtypes = [P, P, ctypes.c_size_t, P]
+        L.cv_stream_snapshot.restype = S
+        L.cv_stream_restore.argtypes = [P, P, ctypes.c_size_t, P]
+        L.cv_stream_restore.restype = S
         L.cv_grid_aggregate_dir.argtypes = [ctypes.POINTER(CvRecords), P, ctypes.POINTER(CvFeatures),
                                             ctypes.POINTER(CvGridSpec), U32, ctypes.c_double,
                                             ctypes.POINTER(CvGroups), U64, P, P, ctypes.c_size_t, P]
@@ -648,7 +660,8 @@ def shard_offsets(sizes, device="cuda"):
 
 class BatchPipeline:
     """Preallocated buffers for the batched form: many shards in one set of
-    launches.  `run()` only enqueues; offsets and results are read afterwards."""
+    launches.  `run()` only enqueues (one cv_batch_run call); offsets and
+    results are read afterwards."""
 
     def __init__(self, n, n_shards, grid, max_journeys, journey_capacity, group_capacity, device="cuda",
                  fused=True):
@@ -664,11 +677,11 @@ class BatchPipeline:
         self.groups = {k: torch.empty(self.gcap, dtype=dt, device=device) for k, dt in GROUP_FIELDS}
         self.journey_offsets = torch.empty(self.S + 1, dtype=torch.int64, device=device)
         self.group_offsets = torch.empty(self.S + 1, dtype=torch.int64, device=device)
+        self.shard_n_out = torch.empty(max(self.S, 1), dtype=torch.int64, device=device)
         self.spec = _spec_struct(grid)
-        self.ws_sort = workspace(_size(L.cv_sort_workspace_size, self.n, self.max_journeys), device)
-        self.ws_sum = workspace(_size(L.cv_summary_workspace_size, self.n, self.jcap), device)
-        self.ws_grid = workspace(_size(L.cv_grid_workspace_size, self.n, ctypes.byref(self.spec), self.gcap), device)
-        self.res = [new_result(device) for _ in range(3)]
+        self.ws = workspace(_size(L.cv_batch_workspace_size, self.n, self.S, self.max_journeys, self.jcap,
+                                  ctypes.byref(self.spec), self.gcap), device)
+        self.res = torch.zeros(3 * 64, dtype=torch.uint8, device=device)
         self._so = CvRecordsOut(*(_ptr(self.sorted[k]) for k, _ in RECORD_FIELDS))
         self._fs = CvFeatures(*(_ptr(self.feat[k]) for k, _ in FEATURE_FIELDS))
         self._js = CvJourneys(*(_ptr(self.journeys[k]) for k, _ in JOURNEY_FIELDS))
@@ -680,29 +693,30 @@ class BatchPipeline:
         assert n <= self.n and offsets_dev.numel() == self.S + 1
         s = _stream(stream)
         off = _ptr(offsets_dev)
-        srt = CvRecords(*(_ptr(self.sorted[k]) for k, _ in RECORD_FIELDS), n)
+        ws, wsn = _ptr(self.ws), self.ws.numel()
+        r0, r1, r2 = (_ptr(self.res[64 * i:64 * (i + 1)]) for i in range(3))
         if self.fused:
-            _check(L.cv_batch_sort_records_features(ctypes.byref(_records_struct(rec)), off, self.S,
-                                                    self.max_journeys, _ptr(self.perm), ctypes.byref(self._so),
-                                                    ctypes.byref(self._fs), _ptr(self.res[0]), _ptr(self.ws_sort),
-                                                    self.ws_sort.numel(), s), "cv_batch_sort_records_features")
-        else:
-            _check(L.cv_batch_sort_records(ctypes.byref(_records_struct(rec)), off, self.S, self.max_journeys,
-                                           _ptr(self.perm), ctypes.byref(self._so), _ptr(self.res[0]),
-                                           _ptr(self.ws_sort), self.ws_sort.numel(), s), "cv_batch_sort_records")
-            _check(L.cv_batch_journey_features(ctypes.byref(srt), off, self.S, ctypes.byref(self._fs), s),
-                   "cv_batch_journey_features")
+            _check(L.cv_batch_run(ctypes.byref(_records_struct(rec)), off, self.S, ctypes.byref(self.spec),
+                                  self.max_journeys, _ptr(self.perm), ctypes.byref(self._so), ctypes.byref(self._fs),
+                                  ctypes.byref(self._js), self.jcap, _ptr(self.journey_offsets),
+                                  ctypes.byref(self._gs), self.gcap, _ptr(self.group_offsets),
+                                  _ptr(self.shard_n_out), r0, ws, wsn, s), "cv_batch_run")
+            return
+        srt = CvRecords(*(_ptr(self.sorted[k]) for k, _ in RECORD_FIELDS), n)
+        _check(L.cv_batch_sort_records(ctypes.byref(_records_struct(rec)), off, self.S, self.max_journeys,
+                                       _ptr(self.perm), ctypes.byref(self._so), r0, ws, wsn, s),
+               "cv_batch_sort_records")
+        _check(L.cv_batch_journey_features(ctypes.byref(srt), off, self.S, ctypes.byref(self._fs), s),
+               "cv_batch_journey_features")
         _check(L.cv_batch_journey_summary(ctypes.byref(srt), ctypes.byref(self._fs), off, self.S,
-                                          ctypes.byref(self._js), self.jcap, _ptr(self.journey_offsets),
-                                          _ptr(self.res[1]), _ptr(self.ws_sum), self.ws_sum.numel(), s),
-               "cv_batch_journey_summary")
+                                          ctypes.byref(self._js), self.jcap, _ptr(self.journey_offsets), r1, ws, wsn,
+                                          s), "cv_batch_journey_summary")
         _check(L.cv_batch_grid_aggregate(ctypes.byref(srt), off, self.S, ctypes.byref(self.spec),
-                                         ctypes.byref(self._gs), self.gcap, _ptr(self.group_offsets),
-                                         _ptr(self.res[2]), _ptr(self.ws_grid), self.ws_grid.numel(), s),
+                                         ctypes.byref(self._gs), self.gcap, _ptr(self.group_offsets), r2, ws, wsn, s),
                "cv_batch_grid_aggregate")
 
     def results(self):
-        return [read_result(r) for r in self.res]
+        return [read_result(self.res[64 * i:64 * (i + 1)]) for i in range(3)]
 
 
 def cv_batch_run(rec, sizes, grid, max_journeys=None, journey_capacity=None, group_capacity=None):
@@ -731,6 +745,12 @@ def cv_batch_run(rec, sizes, grid, max_journeys=None, journey_capacity=None, gro
             gc = min(n, max(4 * gc, r[2]["required"]))
         del bp
     raise CvError(CV_ERR_CAPACITY, "cv_batch_run")
+
+
+def stream_state_bytes(grid, max_journeys, max_groups, max_batch):
+    """Bytes of device state of a stream with these capacities (host query)."""
+    return _size(lib().cv_stream_state_size, ctypes.byref(_spec_struct(grid)), int(max_journeys), int(max_groups),
+                 int(max_batch))
 
 
 class Stream:
@@ -774,6 +794,24 @@ class Stream:
         for r in (rj, rg):
             _check(r["status"], "cv_stream_flush (device)")
         return {k: v[:rj["count"]] for k, v in jo.items()}, {k: v[:rg["count"]] for k, v in go.items()}, rj, rg
+
+    def snapshot(self, stream=None):
+        """The resident state as a pinned host uint8 tensor (the copy is
+        stream-ordered; this waits for it)."""
+        n = ctypes.c_size_t(0)
+        _check(lib().cv_stream_snapshot_size(self.handle, ctypes.byref(n)), "cv_stream_snapshot_size")
+        buf = torch.empty(n.value, dtype=torch.uint8, pin_memory=True)
+        _check(lib().cv_stream_snapshot(self.handle, ctypes.c_void_p(buf.data_ptr()), n.value, _stream(stream)),
+               "cv_stream_snapshot")
+        torch.cuda.synchronize(self.device)
+        return buf
+
+    def restore(self, buf, stream=None):
+        """Replace the resident state with a snapshot of a stream created with
+        the same grid and capacities."""
+        _check(lib().cv_stream_restore(self.handle, ctypes.c_void_p(buf.data_ptr()), buf.numel(), _stream(stream)),
+               "cv_stream_restore")
+        torch.cuda.synchronize(self.device)
 
     def close(self):
         if self.handle:

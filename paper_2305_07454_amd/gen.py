@@ -273,17 +273,34 @@ def make_shard(rng, n_records: int, period_ms=1000, mean_journey=1200.0, cap=86_
     ts, lat, lon, offsets = walks(rng, L, period_ms=period_ms)
     spd = speeds(rng, ts.shape[0])
     jid = np.repeat(ids, L)
-    order = np.lexsort((rng.random(ts.shape[0]), ts))      # feed order: by time, random ties
+    order = feed_order(rng, ts)
     return Records(jid[order], ts[order], lat[order], lon[order], spd[order],
                    dict(n_journeys=j))
 
 
-def make_c2(seed=None, n_shards=115, total=400_000_000, lo=10_000, hi=20_000_000):
-    """Batched workload: list of shards (each an independent problem)."""
+def feed_order(rng, ts):
+    """Feed (arrival) order: by time stamp, ties in random order (one sort of
+    the time offset with 32 random bits below it)."""
+    t = ts - ts.min() if ts.shape[0] else ts
+    assert ts.shape[0] == 0 or int(t.max()) < (1 << 31)
+    key = (t << 32) | rng.integers(0, 1 << 32, size=ts.shape[0], dtype=np.int64)
+    return np.argsort(key)
+
+
+def make_c2(seed=None, n_shards=115, total=400_000_000, lo=10_000, hi=20_000_000, workers=None):
+    """Batched workload: list of shards (each an independent problem).  Shards
+    are drawn from their own seed streams, so drawing them on several threads
+    gives the same records."""
     sizes = c2_shard_sizes(n_shards, total, lo, hi, seed=seed)
     children = np.random.SeedSequence(SEED_BASE + 2 if seed is None else seed + 1).spawn(n_shards)
-    shards = [make_shard(np.random.default_rng(c), int(s)) for c, s in zip(children, sizes)]
-    return shards
+    jobs = [(c, int(s)) for c, s in zip(children, sizes)]
+    if workers is None:
+        workers = min(8, len(jobs))
+    if workers <= 1:
+        return [make_shard(np.random.default_rng(c), s) for c, s in jobs]
+    import concurrent.futures as cf
+    with cf.ThreadPoolExecutor(max_workers=workers) as ex:
+        return list(ex.map(lambda js: make_shard(np.random.default_rng(js[0]), js[1]), jobs))
 
 
 def make_stream(seed=None, n_journeys=2000, median=1500.0, sigma=1.0, cap=86_400, heavy_frac=0.0,
@@ -319,7 +336,7 @@ def make_stream(seed=None, n_journeys=2000, median=1500.0, sigma=1.0, cap=86_400
     lat = np.concatenate([p[2] for p in parts])
     lon = np.concatenate([p[3] for p in parts])
     spd = speeds(rng, ts.shape[0])
-    order = np.lexsort((rng.random(ts.shape[0]), ts))
+    order = feed_order(rng, ts)
     return Records(jid[order], ts[order], lat[order], lon[order], spd[order],
                    dict(n_journeys=n_journeys, heavy_frac=heavy_frac))
 

@@ -2,7 +2,8 @@
 
 Chunks of records arrive as a Poisson process.  A chunk is admitted in FIFO
 order when the device arena -- a ring of record slots reserved for chunks in
-flight -- has room for it (admission by free device memory).  Its columns are
+flight, carved at start-up from the device memory free then -- has room for it
+(admission by free device memory).  Its columns are
 copied host-to-device on a copy stream.  The compute stream runs one push at
 a time.  With continuous batching, every chunk that is copied and waiting when
 the compute stream frees up joins the next push (chunks that arrive while a
@@ -58,12 +59,34 @@ def poisson_trace(rng, rate_fn, duration_s, sizes_lo, sizes_hi):
     return out
 
 
+# device bytes per arena record: the record columns (36) and the features (49)
+# in the ring, plus the stream state's per-push scratch, which grows with the
+# largest push (the arena); measured from the library's size query
+_RING_BYTES = 36 + 49
+
+
+def arena_from_free_hbm(grid, max_journeys, max_groups, fraction=0.5, cap=64_000_000, device="cuda"):
+    """Records in the arena: the largest ring (with the stream state sized for
+    pushes of the whole ring) that fits `fraction` of the device memory free
+    now, at most `cap`."""
+    free, _ = torch.cuda.mem_get_info(torch.device(device))
+    base = cvetl.stream_state_bytes(grid, max_journeys, max_groups, 0)
+    per = (cvetl.stream_state_bytes(grid, max_journeys, max_groups, 1 << 20) - base) / float(1 << 20) + _RING_BYTES
+    a = int((fraction * free - base) / per)
+    return max(1 << 20, min(cap, a))
+
+
 class Server:
-    def __init__(self, pool, grid, batching=True, arena_records=16_000_000, max_journeys=1 << 21,
+    def __init__(self, pool, grid, batching=True, arena_records=None, max_journeys=1 << 21,
                  max_groups=1 << 23, device="cuda"):
+        """arena_records: records in the device ring; None carves it from the
+        free HBM (arena_from_free_hbm).  Chunks are admitted into the ring in
+        arrival order while it has room."""
         self.dev = torch.device(device)
         self.grid = grid
         self.batching = batching
+        if arena_records is None:
+            arena_records = arena_from_free_hbm(grid, max_journeys, max_groups, device=self.dev)
         self.A = int(arena_records)
         self.pool_n = pool.n
         # pinned host pool

@@ -26,12 +26,29 @@ def _load():
     return {"arch": "gfx950", "entries": []}
 
 
-def apply(n: int) -> int | None:
-    """Set the cached best sort shape for an n-record batch; returns it."""
+def signature(workload: str, n: int) -> dict:
+    """What a tuning choice depends on: the record count, whether the batch is
+    many shards (one key prefix more, interleaved feeds) and the grid's
+    cardinality (records per group decide how full the LDS table runs)."""
+    from . import gen
+    g = gen.GRIDS.get(workload)
+    cells = int(g.n_lat) * int(g.n_lon) * max(1, int(g.n_t)) if g is not None else 0
+    return {"workload": workload, "n": int(n), "sharded": workload == "c2", "cells": cells}
+
+
+def apply(n: int, workload: str | None = None) -> dict | None:
+    """Install the cached choices for a batch of n records: the entry of the
+    same workload signature (sharded or not, same grid), nearest in n; without
+    a workload, the nearest n of any entry.  Returns the entry used."""
     from . import cvetl
     c = _load()
+    want = signature(workload, n) if workload else None
     best = None
     for e in c.get("entries", []):
+        if want is not None:
+            sig = e.get("signature") or signature(e.get("workload", "c1"), e["n"])
+            if sig["sharded"] != want["sharded"] or sig["cells"] != want["cells"]:
+                continue
         if best is None or abs(e["n"] - n) < abs(best["n"] - n):
             best = e
     if best is None:
@@ -39,7 +56,7 @@ def apply(n: int) -> int | None:
     cvetl.cv_tuning_set("sort_shape", best["sort_shape"])
     if "grid_lds_slots" in best:
         cvetl.cv_tuning_set("grid_lds_slots", best["grid_lds_slots"])
-    return best["sort_shape"]
+    return best
 
 
 def sweep_sort_shapes(rec, grid, reps=5, log=print):

@@ -347,9 +347,9 @@ def test_summary_flags_column_at_any_alignment(cv):
 
 def test_cell_boundaries_and_neighbours(cv):
     # coordinates on cell boundaries k * d from the origin and one or two ulps
-    # either side, and time stamps on bin edges: the grid kernel's fast
-    # reciprocal estimate defers to the division there, and every key must
-    # equal the oracle's floor of the IEEE quotient
+    # either side, and time stamps on bin edges: every key must equal the
+    # oracle's floor of the IEEE quotient (the kernel divides as the oracle
+    # does; a boundary is where any shortcut would show)
     rng = np.random.default_rng(47)
     spec = gen.GRIDS["c1"]
     n = 6000

@@ -175,3 +175,89 @@ def test_late_records_in_bulk(cv, grid_name, heavy):
     nj = dict(zip(exp_nl["groups"]["key"].tolist(), exp_nl["groups"]["n_journeys"].tolist()))
     exp_g["n_journeys"] = np.array([nj.get(k, 0) for k in exp_g["key"].tolist()], dtype=np.uint32)
     check_groups(groups, rj["n_out_of_grid"], exp_g, n_out)
+
+
+def _push_all(st, rec, bounds):
+    feats = []
+    for a, b in bounds:
+        f, _ = st.push({k: v[a:b] for k, v in rec.items()})
+        feats.append(f)
+    return feats
+
+
+@pytest.mark.parametrize("grid_name,heavy", [("c3", 0.0), ("c4", 0.05)])
+def test_snapshot_restore_resumes_bit_identically(cv, grid_name, heavy):
+    """push[0:k], snapshot, restore into a fresh stream, push[k:]: every
+    response and the flush equal the uninterrupted run bit for bit, and the
+    flush equals the oracle on the concatenation."""
+    import torch
+    r = _pool(seed=46 if heavy == 0 else 47, heavy=heavy)
+    grid = gen.GRIDS[grid_name]
+    sizes = gen.chunk_sizes(np.random.default_rng(10), r.n, 500, 30_000)
+    bounds = _slices(r.n, sizes)
+    k = len(bounds) // 2
+    print(f"[snapshot] n={r.n} chunks={len(sizes)} split at {k} grid={grid_name}", flush=True)
+    rec = cv.to_device(r)
+    mb = max(sizes)
+    whole = cv.Stream(grid, 4096, 1 << 18, mb)
+    fw = _push_all(whole, rec, bounds)
+    first = cv.Stream(grid, 4096, 1 << 18, mb)
+    f1 = _push_all(first, rec, bounds[:k])
+    snap = first.snapshot()
+    first.close()
+    resumed = cv.Stream(grid, 4096, 1 << 18, 2 * mb)   # the per-push capacity may differ
+    resumed.restore(snap)
+    f2 = _push_all(resumed, rec, bounds[k:])
+    torch.cuda.synchronize()
+    for c, (u, v) in enumerate(zip(fw, f1 + f2)):
+        for key in u:
+            assert torch.equal(u[key].view(torch.uint8), v[key].view(torch.uint8)), (c, key)
+    ja, ga, rja, rga = whole.flush(4096, 1 << 18)
+    jb, gb, rjb, rgb = resumed.flush(4096, 1 << 18)
+    for key in ja:
+        assert torch.equal(ja[key].view(torch.uint8), jb[key].view(torch.uint8)), key
+    for key in ga:
+        assert torch.equal(ga[key].view(torch.uint8), gb[key].view(torch.uint8)), key
+    assert rja == rjb and rga == rgb
+    exp = oracle.run_plain(r.columns(), grid)
+    check_summary(jb, exp["summary"])
+    check_groups(gb, rjb["n_out_of_grid"], exp["groups"], exp["n_out"])
+
+
+def test_restore_rejects_other_capacities(cv):
+    grid = gen.GRIDS["c3"]
+    a = cv.Stream(grid, 4096, 1 << 18, 1000)
+    snap = a.snapshot()
+    b = cv.Stream(grid, 8192, 1 << 18, 1000)
+    with pytest.raises(cv.CvError):
+        b.restore(snap)
+    c = cv.Stream(gen.GRIDS["c4"], 4096, 1 << 18, 1000)
+    with pytest.raises(cv.CvError):
+        c.restore(snap)
+
+
+def test_stream_extreme_journey_ids(cv):
+    """Journey ids INT64_MIN and INT64_MAX (INT64_MIN is the journey table's
+    empty-slot marker) next to ordinary ones, over several pushes."""
+    import torch
+    r = _pool(seed=48, n_journeys=12, median=400.0)
+    jid = r.journey_id.copy()
+    u = np.unique(jid)
+    jid[jid == u[0]] = np.iinfo(np.int64).min
+    jid[jid == u[1]] = np.iinfo(np.int64).max
+    jid[jid == u[2]] = -1
+    cols = (jid, r.ts_ms, r.lat_deg, r.lon_deg, r.speed_mps)
+    grid = gen.GRIDS["c3"]
+    sizes = gen.chunk_sizes(np.random.default_rng(11), r.n, 200, 3_000)
+    st = cv.Stream(grid, 256, 1 << 16, max(sizes))
+    rec = cv.to_device(cols)
+    feats = _push_all(st, rec, _slices(r.n, sizes))
+    torch.cuda.synchronize()
+    got_f = {k: torch.cat([f[k] for f in feats]) for k in feats[0]}
+    journeys, groups, rj, rg = st.flush(256, 1 << 16)
+    exp = oracle.run_plain(cols, grid)
+    assert host(journeys["journey_id"])[0] == np.iinfo(np.int64).min
+    assert host(journeys["journey_id"])[-1] == np.iinfo(np.int64).max
+    check_features(_to_sorted_order(got_f, exp["perm"]), exp["features"])
+    check_summary(journeys, exp["summary"])
+    check_groups(groups, rj["n_out_of_grid"], exp["groups"], exp["n_out"])

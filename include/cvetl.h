@@ -218,6 +218,28 @@ cv_status cv_journey_summary(const cv_records* sorted, const cv_features* feat,
                              size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
+ * cv_journey_summary_noalloc -- for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): cv_journey_summary with the same arguments, outputs and device
+ * result, minus the workspace.  The workspace is a library-owned device array
+ * of CV_NOALLOC_SCRATCH_BYTES bytes; each GPU the library runs on holds its
+ * own copy until the process ends.  The call allocates nothing.
+ *   Limit: cv_summary_workspace_size(n, capacity) must not exceed
+ *   CV_NOALLOC_SCRATCH_BYTES (about 152 bytes per row of min(n, capacity)
+ *   plus a few bytes per 4096 records: some 200 000 journey rows), else
+ *   CV_ERR_WORKSPACE and nothing is enqueued.
+ *   The stream must belong to the current device.  CV_ERR_DEVICE when the
+ *   array's device address cannot be obtained.
+ *   Every call on one GPU uses that GPU's single array, and each call
+ *   rewrites what it reads there (nothing carries over from an earlier call).
+ *   Calls that may overlap on one GPU race: issue them on one stream, or
+ *   serialise them.
+ * --------------------------------------------------------------------- */
+#define CV_NOALLOC_SCRATCH_BYTES (32u << 20)
+cv_status cv_journey_summary_noalloc(const cv_records* sorted, const cv_features* feat, const cv_journeys* out,
+                                     uint64_t capacity, cv_result* res, void* stream);
+
+/* ------------------------------------------------------------------------
  * cv_grid_aggregate -- spatio-temporal lattice of Algorithm 2 and Methods
  * steps (3)-(5) over sorted records.  ilat = floor((lat - lat0)/dlat) and ilon
  * likewise (one IEEE subtraction, one IEEE division, floor), tbin =

@@ -14,6 +14,7 @@
 //   k_sum_finalize accumulator rows -> output rows (exact sums rounded once).
 #include <hip/hip_runtime.h>
 
+#include <mutex>
 #include <type_traits>
 
 #include "cv_device.h"
@@ -725,6 +726,38 @@ static cv_status summary_impl(const cv_records* sorted, const cv_features* feat,
     return cvh::last_launch_status();
 }
 
+// Workspace of the allocation-free entry point: one copy of this array per GPU
+// (the code object's static device data), held until the process ends.  Host
+// code reaches it only through the device address taken below; the array's
+// name is not a device address on the host.
+static __device__ __align__(256) unsigned char scratch[CV_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+// the array's address on the current device, taken once per device
+void* noalloc_scratch()
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        if (!cvh::aligned(p, cvh::WS_ALIGN)) return nullptr;
+        g_scratch_ptr[dev] = p;
+    }
+    return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
 namespace cv {
 
 size_t sum_partials_bytes(u64 n)
@@ -770,6 +803,18 @@ cv_status cv_journey_summary(const cv_records* sorted, const cv_features* feat, 
                              uint64_t capacity, cv_result* res, void* ws, size_t ws_bytes, void* stream)
 {
     return summary_impl(sorted, feat, nullptr, 0, out, capacity, nullptr, res, ws, ws_bytes, stream);
+}
+
+cv_status cv_journey_summary_noalloc(const cv_records* sorted, const cv_features* feat, const cv_journeys* out,
+                                     uint64_t capacity, cv_result* res, void* stream)
+{
+    if (!sorted || sorted->n >= (1ull << 32) || capacity >= (1ull << 32)) return CV_ERR_INVALID_ARGUMENT;
+    SumLayout need(nullptr, sorted->n, capacity);
+    if (need.bytes > (size_t)CV_NOALLOC_SCRATCH_BYTES) return CV_ERR_WORKSPACE;
+    void* ws = noalloc_scratch();
+    if (!ws) return CV_ERR_DEVICE;
+    return summary_impl(sorted, feat, nullptr, 0, out, capacity, nullptr, res, ws, (size_t)CV_NOALLOC_SCRATCH_BYTES,
+                        stream);
 }
 
 cv_status cv_batch_journey_summary(const cv_records* sorted, const cv_features* feat, const uint64_t* shard_offsets,

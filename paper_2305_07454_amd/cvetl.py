@@ -120,6 +120,9 @@ def lib():
         L.cv_journey_summary.argtypes = [ctypes.POINTER(CvRecords), ctypes.POINTER(CvFeatures),
                                          ctypes.POINTER(CvJourneys), U64, P, P, ctypes.c_size_t, P]
         L.cv_journey_summary.restype = S
+        L.cv_journey_summary_noalloc.argtypes = [ctypes.POINTER(CvRecords), ctypes.POINTER(CvFeatures),
+                                                 ctypes.POINTER(CvJourneys), U64, P, P]
+        L.cv_journey_summary_noalloc.restype = S
         L.cv_grid_workspace_size.argtypes = [U64, ctypes.POINTER(CvGridSpec), U64, SZ]
         L.cv_grid_workspace_size.restype = S
         L.cv_grid_aggregate.argtypes = [ctypes.POINTER(CvRecords), ctypes.POINTER(CvGridSpec),
@@ -338,6 +341,21 @@ def cv_journey_features(sorted_rec, stream=None):
 
 def _feat_struct(feat):
     return CvFeatures(*(_ptr(feat.get(k)) for k, _ in FEATURE_FIELDS))
+
+
+def cv_journey_summary_noalloc(sorted_rec, feat, out, capacity=None, stream=None):
+    """cv_journey_summary on the library's own per-GPU scratch array (the C
+    call allocates nothing; `out` is the caller's preallocated dict of
+    JOURNEY_FIELDS columns).  Returns the device result tensor, unsynchronised."""
+    L = lib()
+    dev = sorted_rec["journey_id"].device
+    cap = int(capacity) if capacity is not None else int(out["journey_id"].numel())
+    js = CvJourneys(*(_ptr(out[k]) for k, _ in JOURNEY_FIELDS))
+    res = new_result(dev)
+    st = L.cv_journey_summary_noalloc(ctypes.byref(_records_struct(sorted_rec)), ctypes.byref(_feat_struct(feat)),
+                                      ctypes.byref(js), cap, _ptr(res), _stream(stream))
+    _check(st, "cv_journey_summary_noalloc")
+    return res
 
 
 def cv_journey_summary(sorted_rec, feat, capacity=None, stream=None, sync=True, ws=None, out=None):

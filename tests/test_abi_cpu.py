@@ -79,6 +79,14 @@ def test_argument_errors_before_any_launch(L):
     assert L.cv_journey_summary(ctypes.byref(ok), ctypes.byref(cvetl.CvFeatures()),
                                 ctypes.byref(cvetl.CvJourneys()), 10, None, None, 0, None) == \
         cvetl.CV_ERR_WORKSPACE
+    # the allocation-free summary: sizes beyond its scratch array are refused on the host
+    many = cvetl.CvRecords(8, 8, 8, 8, 8, 1 << 20)
+    assert L.cv_journey_summary_noalloc(ctypes.byref(many), ctypes.byref(cvetl.CvFeatures()),
+                                        ctypes.byref(cvetl.CvJourneys()), 1 << 20, None, None) == \
+        cvetl.CV_ERR_WORKSPACE
+    assert L.cv_journey_summary_noalloc(ctypes.byref(big), ctypes.byref(cvetl.CvFeatures()),
+                                        ctypes.byref(cvetl.CvJourneys()), 10, None, None) == \
+        cvetl.CV_ERR_INVALID_ARGUMENT
     spec = cvetl._spec_struct(__import__("paper_2305_07454_amd.gen", fromlist=["x"]).GRIDS["c0"])
     assert L.cv_grid_aggregate(ctypes.byref(ok), ctypes.byref(spec), ctypes.byref(cvetl.CvGroups()), 10, None,
                                None, 0, None) == cvetl.CV_ERR_WORKSPACE

@@ -3,32 +3,30 @@
 // count / sum / count-unique / mean reductions of Table 3), as a sparse,
 // key-sorted group table over (journey, time)-sorted records.
 //
-//   k_grid_agg   per tile of GT records, staged in LDS with coalesced loads:
+//   k_grid_part  per tile of GT records, staged in LDS with coalesced loads:
 //     * key = (tbin * n_lat + ilat) * n_lon + ilon per record (-1 outside);
 //     * runs: maximal stretches of one key inside one (journey, time-bin)
-//       segment.  Records of one (journey, tbin) are contiguous after the sort,
-//       so a run head counts its journey for the cell (distinct-journey flag)
-//       iff no earlier run head of the same segment has the same key.  Run heads
-//       are compacted into an LDS list and each one compares itself with the
-//       earlier heads of its segment; segments entering the tile bring a halo
-//       loaded on demand (global memory beyond it);
-//     * each run is reduced by one thread (count, exact speed sum, min, max),
-//       then inserted into an LDS open-addressing table; a run that finds no
-//       LDS slot, and at tile end every occupied slot, becomes a partial row
-//       in the tile's own region (at most GT rows: each holds >= 1 record);
-//   partials of all tiles -> compacted (key, row) pairs (scan of the counts);
-//   radix sort of the pairs by key (the same LSD sort as the record order);
+//       segment; each is reduced once (count, exact speed sum, min, max);
+//     * the runs of one (journey, key) inside the tile add into one partial
+//       row, and the tile writes its partial rows in record order into its
+//       own region (at most GT rows: each holds >= 1 record);
+//   partials of all tiles -> compacted (key, row) pairs (scan of the counts),
+//     in tile order;
+//   radix sort of the pairs by key (the same stable LSD sort as the record
+//     order), so a key's partials stay in record order;
 //   k_gpart_heads / k_gpart_emit: groups are runs of equal key in the sorted
 //     pairs; each group's first pair sums its partials exactly (integer adds
-//     and min / max, so the order of the partials changes nothing) and writes
-//     the row, in ascending key.
+//     and min / max, so the order of the partials changes nothing), counts a
+//     journey once per run of equal journey ids among them (the partials of
+//     one journey are adjacent in record order), and writes the row, in
+//     ascending key.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
 
 #include "cv_device.h"
 #include "cv_host.h"
-#include "cv_gridagg.h"
+#include "cv_gridpart.h"
 #include "cv_gridtab.h"
 #include "cv_radix.h"
 
@@ -309,9 +307,20 @@ __global__ void __launch_bounds__(ECB) k_gpart_emit(const GridMeta* meta, const 
             if (i < P && (i == 0 || key[k] != prev)) hb |= 1u << k;
             if (i < P) prev = key[k];
         }
+        // the key after this thread's pairs: does the last group go on?
+        const u64 knext = i0 + ECP < P ? K[i0 + ECP] : ~0ull;
         u32 tot;
-        u32 row = block_exclusive_sum<ECB>((u32)__popc(hb), s_t, tot) + hoff[c];
-#pragma unroll 1
+        const u32 row0 = block_exclusive_sum<ECB>((u32)__popc(hb), s_t, tot) + hoff[c];
+        // every head's first partial, the gathers issued together
+        u32 vv[ECP];
+        GPart pf[ECP];
+#pragma unroll
+        for (int k = 0; k < ECP; ++k) vv[k] = ((hb >> k) & 1u) ? V[i0 + k] : 0u;
+#pragma unroll
+        for (int k = 0; k < ECP; ++k)
+            if ((hb >> k) & 1u) pf[k] = part[vv[k]];
+        u32 row = row0;
+#pragma unroll
         for (int k = 0; k < ECP; ++k) {
             if (!((hb >> k) & 1u)) continue;
             const u64 i = i0 + k;
@@ -321,26 +330,33 @@ __global__ void __launch_bounds__(ECB) k_gpart_emit(const GridMeta* meta, const 
                 for (long s2 = ps + 1; s2 <= (long)sh; ++s2) go[s2] = row;
             }
             if (row < cap) {
-                u64 cnj = 0;
+                GPart pr = pf[k];
+                u64 cnt = 0;
+                u32 nj = 0;
                 Fx192 sum;
                 fx_zero(sum);
                 u32 mn = ~0u, mx = 0;
+                i64 pj = pr.jid;
                 u64 j = i;
-                do {
-                    const GPart pr = part[V[j]];
-                    cnj += pr.cnj;
-                    Fx192 t;
-                    t.w[0] = pr.s[0];
-                    t.w[1] = pr.s[1];
-                    t.w[2] = pr.s[2];
+                // the group's next pair: after the first, from this thread's keys
+                bool more = j + 1 < P && (k + 1 < ECP ? key[k + 1 < ECP ? k + 1 : 0] : knext) == key[k];
+                for (;;) {
+                    cnt += pr.cn & ~PART_ODD;
+                    nj += (j == i || pr.jid != pj) ? 1u : 0u;
+                    pj = pr.jid;
+                    const Fx192 t = (pr.cn & PART_ODD) ? fx_from_double<FX_SPD>((double)__uint_as_float(pr.s[0]))
+                                                       : part_sum192(pr);
                     fx_add(sum, t);
                     mn = pr.mn < mn ? pr.mn : mn;
                     mx = pr.mx > mx ? pr.mx : mx;
+                    if (!more) break;
                     ++j;
-                } while (j < P && K[j] == key[k]);
+                    pr = part[V[j]];
+                    more = j + 1 < P && K[j + 1] == key[k];
+                }
                 o_key[row] = (i64)(key[k] & kmask);
-                o_cnt[row] = (u32)cnj;
-                o_nj[row] = (u32)(cnj >> 32);
+                o_cnt[row] = (u32)cnt;
+                o_nj[row] = nj;
                 o_sum[row] = fx_to_double<FX_SPD>(sum);
                 o_min[row] = unord_f32(mn);
                 o_max[row] = unord_f32(mx);
@@ -410,21 +426,13 @@ bool set_grid_lds_slots(int v)
 int grid_lds_slots() { return g_lds_slots; }
 }  // namespace cv
 
-// the tile kernel for a table size and a direction source
-template <class Pol>
-static void launch_tiles(dim3 gg, hipStream_t s, u32 nn, const cv_records* sorted, const Spec& g, const SinkParts& sk,
+// the tile kernel for a direction source (0 none, 1 heading column, 2 bearing)
+template <int KD>
+static void launch_parts(dim3 gg, hipStream_t s, u32 nn, const cv_records* sorted, const Spec& g, const PartSink& sk,
                          GridMeta* meta)
 {
-    const dim3 gb(GB);
-    if (g_lds_slots >= 1024)
-        hipLaunchKernelGGL((k_grid_agg<1024, Pol, SinkParts>), gg, gb, 0, s, nn, sorted->journey_id, sorted->ts_ms,
-                           sorted->lat_deg, sorted->lon_deg, sorted->speed_mps, g, sk, meta, Pol{});
-    else if (g_lds_slots >= 512)
-        hipLaunchKernelGGL((k_grid_agg<512, Pol, SinkParts>), gg, gb, 0, s, nn, sorted->journey_id, sorted->ts_ms,
-                           sorted->lat_deg, sorted->lon_deg, sorted->speed_mps, g, sk, meta, Pol{});
-    else
-        hipLaunchKernelGGL((k_grid_agg<256, Pol, SinkParts>), gg, gb, 0, s, nn, sorted->journey_id, sorted->ts_ms,
-                           sorted->lat_deg, sorted->lon_deg, sorted->speed_mps, g, sk, meta, Pol{});
+    hipLaunchKernelGGL((k_grid_part<KD>), gg, dim3(GB), 0, s, nn, sorted->journey_id, sorted->ts_ms, sorted->lat_deg,
+                       sorted->lon_deg, sorted->speed_mps, g, sk, meta);
 }
 
 // exclusive scan of v[0, n) into out (n = *n_dev when given, at most n_max);
@@ -502,11 +510,11 @@ static cv_status grid_impl(const cv_records* sorted, const u64* soff, u32 S, con
         cvh::TimedScope ts_("grid_agg", s);
         hipLaunchKernelGGL(k_gmeta_init, dim3(1), dim3(64), 0, s, L.meta);
         if (sout) cvh::fill_u64(sout, 0ull, S ? S : 1, s);
-        SinkParts sk{L.K1, L.part, L.tcnt, L.tmax, &L.meta->overflow};
+        PartSink sk{L.K1, L.part, L.tcnt, L.tmax};
         const dim3 gg(tiles);
-        if (nd == 0) launch_tiles<GridPlain>(gg, s, nn, sorted, g, sk, L.meta);
-        else if (hdg) launch_tiles<GridHeading>(gg, s, nn, sorted, g, sk, L.meta);
-        else launch_tiles<GridBearing>(gg, s, nn, sorted, g, sk, L.meta);
+        if (nd == 0) launch_parts<0>(gg, s, nn, sorted, g, sk, L.meta);
+        else if (hdg) launch_parts<1>(gg, s, nn, sorted, g, sk, L.meta);
+        else launch_parts<2>(gg, s, nn, sorted, g, sk, L.meta);
     }
     {
         cvh::TimedScope ts_("grid_tail", s);

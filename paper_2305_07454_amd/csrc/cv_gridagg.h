@@ -1,10 +1,12 @@
-// cv_gridagg.h -- the tile kernel of the grid aggregate (cv_grid.hip
-// describes it), shared by the plain / batched forms and the serving form.
-// A policy type supplies what differs in the serving form: records flagged
-// late (they count in their cells but never as a new distinct journey, and a
-// change of that status starts a segment), cells a journey's open segment
-// carried over from earlier pushes, and a hook that sees every record that
-// counts its journey in a cell.
+// cv_gridagg.h -- the tile kernel of the serving form's grid aggregate, which
+// adds every tile's groups into a resident HBM table and so needs the
+// distinct-journey flag of every run head inside the tile, and the run-piece
+// arithmetic (exact 128-bit speed sums, cross-lane joins of run pieces) that
+// the plain and batched tile kernel (cv_gridpart.h) shares.  A policy type
+// supplies the serving form's rules: records flagged late (they count in their
+// cells but never as a new distinct journey, and a change of that status
+// starts a segment), cells a journey's open segment carried over from earlier
+// pushes, and a hook that sees every record that counts its journey in a cell.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -151,49 +153,15 @@ __device__ __forceinline__ void run_seg_scan(RunPart& p, bool head)
     for (int k = 0, d = 1; d < WAVE; ++k, d <<= 1) run_step(p, d, true, ((take >> k) & 1u) != 0);
 }
 
-// Where a tile's group contributions go.
-// The serving form: its resident HBM hash table (kept across pushes).
+// Where a tile's group contributions go: the serving form's resident HBM
+// hash table (kept across pushes).
 struct SinkTable {
-    static constexpr bool kParts = false;
     GEntry* tab;
     u64 mask;
     GridMeta* meta;
     __device__ void put(u64 key, u32 count, u32 nj, const Fx192& sum, u32 mn, u32 mx, u32*, u64*, u64) const
     {
         g_insert(tab, mask, meta, key, count, nj, sum, mn, mx);
-    }
-};
-
-// The plain and batched forms: partial rows in the tile's own region of GT
-// rows.  A tile never writes more than GT of them: every partial holds at
-// least one of its records, and no record is in two partials.  The count per
-// tile and its largest key follow at the end of the tile.
-struct SinkParts {
-    static constexpr bool kParts = true;
-    u64* key;    // [tiles * GT]
-    GPart* part; // [tiles * GT]
-    u32* count;  // [tiles]
-    u64* kmax;   // [tiles]
-    u32* bad;    // set if a tile ever had more than GT partials (it cannot; checked, never written past)
-    __device__ void put(u64 k, u32 count_, u32 nj, const Fx192& sum, u32 mn, u32 mx, u32* s_np, u64* s_kmax,
-                        u64 tile) const
-    {
-        const u32 j = atomicAdd(s_np, 1u);
-        if (j >= (u32)GT) {
-            atomicOr(bad, 1u);
-            return;
-        }
-        const u64 at = tile * (u64)GT + j;
-        key[at] = k;
-        GPart pr;
-        pr.cnj = (u64)count_ | ((u64)nj << 32);
-        pr.s[0] = sum.w[0];
-        pr.s[1] = sum.w[1];
-        pr.s[2] = sum.w[2];
-        pr.mn = mn;
-        pr.mx = mx;
-        part[at] = pr;
-        atomicMax((unsigned long long*)s_kmax, (unsigned long long)k);
     }
 };
 
@@ -687,20 +655,13 @@ k_grid_agg(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, const
         for (int w = 0; w < GB / WAVE; ++w) tot += s_out[w];
         if (tot) atomicAdd((unsigned long long*)&meta->n_out, (unsigned long long)tot);
     }
-    // the LDS table to the sink (the HBM table, or the tile's partial rows)
+    // the LDS table to the sink
     for (int i = t; i < LHS; i += GB) {
         const u64 key = s_hkey[i];
         if (key == GEMPTY) continue;
         const LSlot& sl = s_h[i];
         const Fx192 sum = fx_from_cs(sl.cs);
         sk.put(key, sl.count, sl.nj, sum, sl.mn, sl.mx, &s_np, &s_kmax, blockIdx.x);
-    }
-    if constexpr (Sink::kParts) {
-        __syncthreads();
-        if (t == 0) {
-            sk.count[blockIdx.x] = s_np < (u32)GT ? s_np : (u32)GT;
-            sk.kmax[blockIdx.x] = s_kmax;
-        }
     }
 }
 

@@ -10,7 +10,7 @@
 //     compacted, radix-sorted by key, emitted in ascending key (kernels with
 //     internal linkage, one copy per user);
 //   * the partial row of a tile (GPart), which the plain and batched forms
-//     merge by a key sort instead of a table.
+//     merge by a key sort instead of a table (cv_gridpart.h writes them).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -56,14 +56,18 @@ __device__ __forceinline__ Fx192 fx_from_cs40(const u64 c[CS40])
 }
 
 // A partial group row of one tile (plain and batched forms): the tile's
-// records of one key, merged with the other tiles' partials of that key after
-// a key sort.  40 bytes; the sum is exact (192-bit two's complement, 2^-149 units).
+// records of one (journey, key), merged with the other partials of that key
+// after a key sort.  32 bytes, one aligned sector.  The speed sum is a 96-bit
+// two's complement integer in 2^-53 units (s[0] lowest; a tile's sum stays
+// below 2^74 in magnitude), or (cn bit 31) s[0] holds the one speed of a
+// record outside that format as float bits.
 struct GPart {
-    u64 cnj;   // count | distinct journeys << 32
-    u64 s[3];
-    u32 mn, mx;
+    i64 jid;
+    u32 s[3];
+    u32 cn;      // records; bit 31: s[0] is a float's bits
+    u32 mn, mx;  // ordered-integer min / max speed
 };
-static_assert(sizeof(GPart) == 40, "partial layout");
+static_assert(sizeof(GPart) == 32, "partial layout");
 
 struct GridMeta {
     u32 groups;     // groups after the merge of the partials

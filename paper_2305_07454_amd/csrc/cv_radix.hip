@@ -30,9 +30,25 @@ __global__ void __launch_bounds__(256) k_radix_hist(const u64* __restrict__ keys
         int need = (b + RADIX_BITS - 1) / RADIX_BITS;
         np = need < np ? need : np;
     }
-    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        u64 k = keys[i];
-        for (int p = 0; p < np; ++p) atomicAdd(&s_h[p * RADIX + ((k >> (p * RADIX_BITS)) & (RADIX - 1))], 1u);
+    // the loop runs the same trips in every lane of a wave (whole waves per
+    // stride); a digit shared by every valid lane adds once
+    const u32 stride = gridDim.x * blockDim.x;
+    const u32 first = blockIdx.x * blockDim.x + (threadIdx.x & ~(u32)(WAVE - 1));
+    for (u32 b = first; b < n; b += stride) {
+        const u32 i = b + (u32)lane_id();
+        const bool ok = i < n;
+        const u64 k = ok ? keys[i] : 0ull;
+        const u64 vm = __ballot(ok);
+        const int lead = __ffsll((long long)vm) - 1;
+        for (int p = 0; p < np; ++p) {
+            const u32 d = (u32)(k >> (p * RADIX_BITS)) & (RADIX - 1);
+            const u32 d0 = __shfl(d, lead, WAVE);
+            if (__ballot(ok && d != d0) == 0) {
+                if (lane_id() == lead) atomicAdd(&s_h[p * RADIX + d0], (u32)__popcll(vm));
+            } else if (ok) {
+                atomicAdd(&s_h[p * RADIX + d], 1u);
+            }
+        }
     }
     __syncthreads();
     for (int i = threadIdx.x; i < np * RADIX; i += blockDim.x)
@@ -52,8 +68,9 @@ __global__ void __launch_bounds__(256) k_radix_scan(const u32* __restrict__ hist
 }
 
 // One stable scatter pass on digit `pass` (bits [8*pass, 8*pass+8)).
-// vals_in == nullptr means the identity (input index).
-template <int SORT_BLOCK, int SORT_ITEMS>
+// vals_in == nullptr means the identity (input index).  LOOP: a block goes on
+// taking tiles (a grid smaller than the tile count); otherwise it takes one.
+template <int SORT_BLOCK, int SORT_ITEMS, bool LOOP>
 __global__ void __launch_bounds__(SORT_BLOCK)
 k_radix_pass(const u64* __restrict__ keys_in, const u32* __restrict__ vals_in, u64* __restrict__ keys_out,
              u32* __restrict__ vals_out, u32 n_max, const u32* __restrict__ n_dev, int pass,
@@ -84,6 +101,11 @@ k_radix_pass(const u64* __restrict__ keys_in, const u32* __restrict__ vals_in, u
     const int shift = pin ? (int)ib + (pass - p0) * RADIX_BITS : pass * RADIX_BITS;
     // this pass's global start of digit threadIdx.x, read before it is needed
     const u32 doff = threadIdx.x < RADIX ? digit_offs[threadIdx.x] : 0u;
+    // Tiles are taken by ticket (with LOOP, until the tickets pass the last
+    // tile, so a grid smaller than the tile count covers every tile); a tile
+    // waits only on tiles whose tickets were taken before, by blocks already
+    // running.
+    for (;;) {
     if (threadIdx.x == 0) s_tile = atomicAdd(ticket, 1u);
     for (int i = threadIdx.x; i < NW * RADIX; i += SORT_BLOCK) (&s_whist[0][0])[i] = 0;
     __syncthreads();
@@ -208,7 +230,9 @@ k_radix_pass(const u64* __restrict__ keys_in, const u32* __restrict__ vals_in, u
             const u32 j = threadIdx.x + (u32)k * SORT_BLOCK;
             if (j < tvalid) keys_out[s_gshift[(u32)(kk[k] >> shift) & (RADIX - 1)] + j] = kk[k];
         }
-        return;
+        if constexpr (!LOOP) return;
+        __syncthreads();  // LDS free for the next tile
+        continue;
     }
     // the index values follow the keys through the same staging buffer
     __syncthreads();
@@ -233,6 +257,9 @@ k_radix_pass(const u64* __restrict__ keys_in, const u32* __restrict__ vals_in, u
             }
         }
     }
+    if constexpr (!LOOP) return;
+    __syncthreads();  // LDS free for the next tile
+    }
 }
 
 
@@ -251,6 +278,9 @@ void radix_scan(const u32* hist, u32* offs, int passes, hipStream_t s)
 
 namespace {
 
+// blocks of a pass whose record count is read on the device
+constexpr u64 DEVICE_COUNT_GRID = 2048;
+
 // tile shapes compiled into the library; the sort uses sort_shape()
 struct Shape {
     int block, items;
@@ -264,8 +294,14 @@ void launch_pass(u64 tiles, hipStream_t s, const u64* kin, const u32* vin, u64* 
                  const u32* n_dev, int p, const u32* bits_dev, const u32* offs, u64* status, u32* ticket,
                  const u32* pack)
 {
-    hipLaunchKernelGGL((k_radix_pass<B, I>), dim3((unsigned)(tiles ? tiles : 1)), dim3(B), 0, s, kin, vin, kout, vout,
-                       n_max, n_dev, p, bits_dev, offs, status, ticket, pack);
+    // a count known only on the device: a grid that fills the GPU, whose
+    // blocks take tiles until the count is covered
+    if (n_dev && tiles > DEVICE_COUNT_GRID)
+        hipLaunchKernelGGL((k_radix_pass<B, I, true>), dim3((unsigned)DEVICE_COUNT_GRID), dim3(B), 0, s, kin, vin,
+                           kout, vout, n_max, n_dev, p, bits_dev, offs, status, ticket, pack);
+    else
+        hipLaunchKernelGGL((k_radix_pass<B, I, false>), dim3((unsigned)(tiles ? tiles : 1)), dim3(B), 0, s, kin, vin,
+                           kout, vout, n_max, n_dev, p, bits_dev, offs, status, ticket, pack);
 }
 
 }  // namespace

@@ -3,12 +3,15 @@
 // (Methods, step (2)).
 //
 // Pipeline (all stream-ordered, no host synchronisation):
-//   1. k_dict_insert  min/max timestamp; distinct journey ids into an
-//                     open-addressing hash set (run-deduplicated);
+//   1. k_dict_insert  min/max timestamp; whether time never decreases within a
+//                     shard in input order (then the key needs no time bits);
+//                     distinct journey ids into an open-addressing hash set
+//                     (run-deduplicated);
 //   2. k_dict_compact distinct ids -> list; radix sort of the list (signed order);
 //   3. k_dict_meta    journey count J, rank bits, time bits, key bits, passes;
 //   4. k_dict_rank    dense order-preserving rank of each distinct id;
-//   5. k_pack_hist    key = rank << t_bits | (ts - t_min) and the digit
+//   5. k_pack_hist    key = rank << t_bits | (ts - t_min) (or the rank alone
+//                     for time-ordered input) and the digit
 //                     histograms of every radix pass in the same read;
 //   6. radix passes   ceil(key_bits / 8) stable scatter passes (skipped on device);
 //   7. k_gather       perm, journey id from the dictionary, ts from the key,
@@ -45,6 +48,8 @@ struct SortMeta {
     u32 ib;   // index bits of a packed key word
     u32 p0;   // first pass whose input words are packed (ib and p0 adjacent: the radix passes read both)
     u32 n_runs;  // runs of equal ids in input order (dictionary probes of the key packing)
+    u32 unordered;  // a timestamp below its predecessor's (same shard) in input order
+    u32 ts_dropped; // key = (shard, rank) only: the input is time-ordered within every shard
     u32 tickets[2 * MAX_PASSES];
 };
 
@@ -133,8 +138,12 @@ __device__ __forceinline__ u32 dict_cache_slot(u64 key)
     return (u32)(mix64(key) >> 56) & (C - 1);
 }
 
+// Also checks whether the timestamps never decrease within a shard in input
+// order: then every journey's records already come in time order, and a
+// stable sort by (shard, journey) alone gives the (journey, time) order.
 __global__ void __launch_bounds__(256) k_dict_insert(const i64* __restrict__ jid, const i64* __restrict__ ts, u32 n,
-                                                     u64* __restrict__ table, u64 mask, SortMeta* m)
+                                                     u64* __restrict__ table, u64 mask, SortMeta* m,
+                                                     const u64* __restrict__ soff, u32 S)
 {
     __shared__ u64 s_min[4], s_max[4];
     __shared__ u64 c_key[4][DC];
@@ -148,6 +157,10 @@ __global__ void __launch_bounds__(256) k_dict_insert(const i64* __restrict__ jid
     wave_range(n, wbeg, wend);
     i64 prevj = 0;  // last id of the previous window
     bool hp = false;
+    // time of the record before the range (ordered form), then of each window's last
+    u64 prevt = (wbeg < wend && wbeg > 0) ? ord_i64(ts[wbeg * WAVE - 1]) : 0ull;
+    bool down = false;
+    u32 shk = (S > 1 && wbeg < wend) ? shard_lower_bound(soff, S, wbeg * WAVE) : 0u;
     for (u64 w0 = wbeg; w0 < wend; w0 += DPW) {
         i64 jv[DPW];
         u64 tv[DPW];
@@ -167,6 +180,16 @@ __global__ void __launch_bounds__(256) k_dict_insert(const i64* __restrict__ jid
             if (valid) {
                 lo = tv[k] < lo ? tv[k] : lo;
                 hi = tv[k] > hi ? tv[k] : hi;
+            }
+            {
+                // time order against the record before (none before record 0
+                // and before a shard's first record)
+                const u64 tp = __shfl_up(tv[k], 1, WAVE);
+                const u64 tq = l == 0 ? prevt : tp;
+                bool at_end = false;
+                const u64 starts = S > 1 ? shard_starts_in(soff, S, shk, (w0 + k) * WAVE, at_end) : 0ull;
+                if (valid && i > 0 && !((starts >> l) & 1ull) && tv[k] < tq) down = true;
+                prevt = __shfl(tv[k], WAVE - 1, WAVE);
             }
             // a record repeating the id before it adds nothing
             const i64 jp = __shfl_up(j, 1, WAVE);
@@ -199,6 +222,7 @@ __global__ void __launch_bounds__(256) k_dict_insert(const i64* __restrict__ jid
     }
     if (has_min) atomicOr(&m->has_min, 1u);
     if (full) atomicOr(&m->overflow, 1u);
+    if (__ballot(down) && l == 0) atomicOr(&m->unordered, 1u);
     __syncthreads();
     if (threadIdx.x == 0) {
         for (int k = 1; k < (int)(blockDim.x / WAVE); ++k) {
@@ -253,7 +277,9 @@ __global__ void k_dict_meta(SortMeta* m, u32 max_j, u32 n, u32 n_shards)
     m->dict_n = J < max_j ? J : max_j;
     u32 rb = J > 1 ? bit_width64((u64)J - 1) : 0;
     u64 span = n ? (unord_i64(m->tmax_ord) - (u64)unord_i64(m->tmin_ord)) : 0;
-    u32 tb = bit_width64(span);
+    // time-ordered input needs no time bits in the key (see the insert)
+    m->ts_dropped = m->unordered ? 0u : 1u;
+    u32 tb = m->ts_dropped ? 0u : bit_width64(span);
     const u32 sb = n_shards > 1 ? bit_width64((u64)n_shards - 1) : 0;
     m->rank_bits = rb;
     m->t_bits = tb;
@@ -344,6 +370,7 @@ __global__ void __launch_bounds__(256) k_pack_hist(const i64* __restrict__ jid, 
     const int wv_ = threadIdx.x / WAVE;
     u32 runs = 0;  // run starts this wave found (wave-uniform)
     const u32 tb = m->t_bits;
+    const bool tdrop = m->ts_dropped != 0;
     const u32 np = m->passes;
     const bool bad = m->range_err != 0;
     const u32 ib = m->ib;
@@ -411,7 +438,7 @@ __global__ void __launch_bounds__(256) k_pack_hist(const i64* __restrict__ jid, 
             u64 key = 0;
             if (valid) {
                 if (!bad) {
-                    key = (tb >= 64 ? 0ull : ((u64)r << tb)) | (tv[k] - tmin);
+                    key = tdrop ? (u64)r : ((tb >= 64 ? 0ull : ((u64)r << tb)) | (tv[k] - tmin));
                     if (SHARDS) {
                         // the window's first shard, then forward to this record's
                         shw = __builtin_amdgcn_readfirstlane(shard_from(soff, S, shw, wi * WAVE));
@@ -468,8 +495,8 @@ __global__ void __launch_bounds__(256) k_gather(u32 n, const SortMeta* m, const 
     // the journey rank survives packing when its bits lie above the dropped digits
     const bool rank_in_key = exact && drop <= tb;
     const u32 rshift = ib + tb - drop;
-    // the time offset survives only when nothing was dropped
-    const bool ts_in_key = exact && drop == 0;
+    // the time offset survives only when nothing was dropped (and the key had it)
+    const bool ts_in_key = exact && drop == 0 && !m->ts_dropped;
     const u64 tmin = (u64)unord_i64(m->tmin_ord);
     const u64 tmask = tb >= 64 ? ~0ull : ((1ull << tb) - 1);
     const u64* K = (np & 1) ? K1 : K0;
@@ -675,7 +702,7 @@ __global__ void __launch_bounds__(256) k_gather_feat(u32 n, const SortMeta* m, c
     const bool exact = (m->range_err == 0) && (m->overflow == 0);
     const bool rank_in_key = exact && drop <= tb;
     const u32 rshift = ib + tb - drop;
-    const bool ts_in_key = exact && drop == 0;
+    const bool ts_in_key = exact && drop == 0 && !m->ts_dropped;
     const u64 tmin = (u64)unord_i64(m->tmin_ord);
     const u64 tmask = tb >= 64 ? ~0ull : ((1ull << tb) - 1);
     const u64* K = (m->passes & 1) ? K1 : K0;
@@ -902,7 +929,7 @@ static cv_status sort_impl(const cv_records* in, const uint64_t* soff, uint32_t 
         cvh::fill_u64(L.table, EMPTY, 2 * L.slots, s);
         cvh::fill_u32(L.zero_begin, 0u, L.zero_bytes / 4, s);
         hipLaunchKernelGGL(k_dict_insert, dim3(gs), dim3(256), 0, s, in->journey_id, in->ts_ms, nn, L.table, mask,
-                           L.meta);
+                           L.meta, soff, S);
         hipLaunchKernelGGL(k_dict_compact, dim3(cvh::grid_for(L.slots, 256, 2048)), dim3(256), 0, s, L.table,
                            L.slots, mj, L.meta, L.dl0);
         hipLaunchKernelGGL(k_dict_meta, dim3(1), dim3(64), 0, s, L.meta, mj, nn, S);

@@ -1,12 +1,16 @@
 """Autotuner for the library's tuning knobs.
 
 Sweeps the compiled radix-pass tile shapes (threads x keys per thread) on a
-workload, times the record sort's scatter passes with the library's per-kernel
-HIP-event timing, and keeps the fastest shape per workload signature in a JSON
-cache next to this file.  ``apply(n)`` installs the cached choice for a batch
-of n records (nearest recorded size), or leaves the library default.
+workload and keeps the fastest per workload signature (record count, whether
+the batch is many shards, grid cardinality) in a JSON cache next to this file.
+The plain workloads are timed by the record sort's scatter passes (the
+library's per-kernel HIP-event timing); the batched workload (many uneven
+shards in one set of launches) by its whole step, since its shape choice also
+moves the group-key sort of the grid merge.  ``apply(n, workload)`` installs the
+cached choice of the same signature, nearest in n, or leaves the library
+default.
 
-    python -m paper_2305_07454_amd.tune --workload c1 [--reps 5]
+    python -m paper_2305_07454_amd.tune --workload c1|c2 [--reps 5]
 """
 from __future__ import annotations
 
@@ -19,9 +23,9 @@ import time
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json")
 
 
-def _load():
-    if os.path.exists(CACHE):
-        with open(CACHE) as f:
+def _load(path=CACHE):
+    if os.path.exists(path):
+        with open(path) as f:
             return json.load(f)
     return {"arch": "gfx950", "entries": []}
 
@@ -29,7 +33,8 @@ def _load():
 def signature(workload: str, n: int) -> dict:
     """What a tuning choice depends on: the record count, whether the batch is
     many shards (one key prefix more, interleaved feeds) and the grid's
-    cardinality (records per group decide how full the LDS table runs)."""
+    cardinality (records per group set how many partial rows the grid merge
+    sorts)."""
     from . import gen
     g = gen.GRIDS.get(workload)
     cells = int(g.n_lat) * int(g.n_lon) * max(1, int(g.n_t)) if g is not None else 0
@@ -54,8 +59,6 @@ def apply(n: int, workload: str | None = None) -> dict | None:
     if best is None:
         return None
     cvetl.cv_tuning_set("sort_shape", best["sort_shape"])
-    if "grid_lds_slots" in best:
-        cvetl.cv_tuning_set("grid_lds_slots", best["grid_lds_slots"])
     return best
 
 
@@ -85,32 +88,43 @@ def sweep_sort_shapes(rec, grid, reps=5, log=print):
     return results
 
 
-def sweep_grid_slots(srt, grid, reps=5, log=print):
-    """Time the grid aggregation kernel for every LDS table size on sorted records."""
+def sweep_batched(rec, sizes, grid, reps=5, log=print):
+    """Time the whole batched step (sort, kinematics, summaries, grid merge)
+    for every compiled shape on one resident batch of shards."""
     import torch
     from . import cvetl
+    n = int(rec["journey_id"].numel())
+    dev = rec["journey_id"].device
+    off_h, off_d = cvetl.shard_offsets(sizes, dev)
+    bp0, res0 = cvetl.cv_batch_run(rec, sizes, grid)
+    J, G, mj = res0[1]["count"], res0[2]["count"], bp0.max_journeys
+    del bp0
+    torch.cuda.empty_cache()
+    bp = cvetl.BatchPipeline(n, len(sizes), grid, mj, J, max(4096, int(1.25 * G)), dev)
+    stream = torch.cuda.current_stream()
     results = []
-    for slots in (256, 512, 1024):
-        cvetl.cv_tuning_set("grid_lds_slots", slots)
-        groups, rg = cvetl.cv_grid_aggregate(srt, grid)
-        cap = max(4096, int(1.25 * rg["count"]))
-        out = {k: torch.empty(cap, dtype=dt, device=srt["journey_id"].device) for k, dt in cvetl.GROUP_FIELDS}
+    for sh in range(cvetl.cv_tuning_get("sort_shapes")):
+        cvetl.cv_tuning_set("sort_shape", sh)
+        bp.run(rec, off_d)
         torch.cuda.synchronize()
-        cvetl.cv_timing_reset()
-        cvetl.cv_timing_enable(True)
+        assert all(r["status"] == 0 for r in bp.results())
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record(stream)
         for _ in range(reps):
-            cvetl.cv_grid_aggregate(srt, grid, capacity=cap, sync=False, out=out)
+            bp.run(rec, off_d)
+        ev[1].record(stream)
         torch.cuda.synchronize()
-        cvetl.cv_timing_enable(False)
-        ms, c = cvetl.cv_timing_read("grid_agg")
-        results.append({"grid_lds_slots": slots, "grid_agg_ms": round(ms / max(c, 1), 5)})
-        log(f"grid_lds_slots {slots}: {ms / max(c, 1):.4f} ms")
+        ms = ev[0].elapsed_time(ev[1]) / reps
+        results.append({"sort_shape": sh, "tile": cvetl.cv_tuning_get("sort_tile"), "step_ms": round(ms, 4)})
+        log(f"shape {sh} (tile {cvetl.cv_tuning_get('sort_tile')}): {ms:.3f} ms per batched step")
+    del bp
+    torch.cuda.empty_cache()
     return results
 
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="c1", choices=["c0", "c1"])
+    ap.add_argument("--workload", default="c1", choices=["c0", "c1", "c2"])
     ap.add_argument("--n-journeys", type=int, default=None)
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--out", default=CACHE)
@@ -118,27 +132,37 @@ def main():
     import torch
     from . import cvetl, gen
     t = time.time()
-    r = gen.make_c1(**({"n_journeys": args.n_journeys} if args.n_journeys else {})) if args.workload == "c1" \
-        else gen.make_c0(**({"n_journeys": args.n_journeys} if args.n_journeys else {}))
-    print(f"[tune] {args.workload}: {r.n} records ({time.time() - t:.1f}s)", file=sys.stderr, flush=True)
+    say = lambda m: print(f"[tune] {m}", file=sys.stderr, flush=True)  # noqa: E731
+    if args.workload == "c2":
+        shards = gen.make_c2()
+        sizes = [x.n for x in shards]
+        r = gen.concat(shards)
+        del shards
+    elif args.workload == "c1":
+        r = gen.make_c1(**({"n_journeys": args.n_journeys} if args.n_journeys else {}))
+    else:
+        r = gen.make_c0(**({"n_journeys": args.n_journeys} if args.n_journeys else {}))
+    say(f"{args.workload}: {r.n} records ({time.time() - t:.1f}s)")
+    n = r.n
     rec = cvetl.to_device(r)
-    res = sweep_sort_shapes(rec, gen.GRIDS[args.workload], args.reps,
-                            log=lambda m: print(f"[tune] {m}", file=sys.stderr, flush=True))
-    best = min(res, key=lambda x: x["pass_ms"])
-    cvetl.cv_tuning_set("sort_shape", best["sort_shape"])
-    perm, srt, _ = cvetl.cv_sort_records(rec)
-    gres = sweep_grid_slots(srt, gen.GRIDS[args.workload], args.reps,
-                            log=lambda m: print(f"[tune] {m}", file=sys.stderr, flush=True))
-    gbest = min(gres, key=lambda x: x["grid_agg_ms"])
-    c = _load()
-    c["entries"] = [e for e in c.get("entries", []) if e.get("workload") != args.workload or e["n"] != r.n]
-    c["entries"].append({"workload": args.workload, "n": r.n, "sort_shape": best["sort_shape"],
-                         "tile": best["tile"], "pass_ms": best["pass_ms"], "sweep": res,
-                         "grid_lds_slots": gbest["grid_lds_slots"], "grid_sweep": gres,
-                         "device": torch.cuda.get_device_name(0)})
+    del r
+    grid = gen.GRIDS[args.workload]
+    if args.workload == "c2":
+        res = sweep_batched(rec, sizes, grid, args.reps, log=say)
+        best = min(res, key=lambda x: x["step_ms"])
+    else:
+        res = sweep_sort_shapes(rec, grid, args.reps, log=say)
+        best = min(res, key=lambda x: x["pass_ms"])
+    c = _load(args.out if os.path.exists(args.out) else CACHE)
+    sig = signature(args.workload, n)
+    c["entries"] = [e for e in c.get("entries", []) if e.get("workload") != args.workload or e["n"] != n]
+    entry = {"workload": args.workload, "n": n, "signature": sig, "sort_shape": best["sort_shape"],
+             "tile": best["tile"], "sweep": res, "device": torch.cuda.get_device_name(0)}
+    entry.update({k: best[k] for k in ("pass_ms", "step_ms") if k in best})
+    c["entries"].append(entry)
     with open(args.out, "w") as f:
         json.dump(c, f, indent=1)
-    print(json.dumps({"best": best, "sweep": res, "grid": gres}))
+    print(json.dumps({"best": best, "sweep": res}))
 
 
 if __name__ == "__main__":

@@ -1,11 +1,11 @@
 """Full-size parity on the full-day workload (~123 M records), in the launch
 configuration the benchmark times (preallocated Pipeline, same capacities).
 
-The oracle cannot redo the whole day in seconds, so: the order is checked by
-its defining properties on every record, journeys are sampled and recomputed
-one by one by the oracle from their own input records (journeys are
-independent), and grid cells are sampled and recomputed from all records that
-the oracle's binning puts in them."""
+The order is checked by its defining properties on every record; journeys
+are sampled and recomputed one by one by the oracle from their own input
+records (journeys are independent); grid cells are sampled and recomputed
+from all records that the oracle's binning puts in them; and the oracle over
+the whole day is compared with every output element by element."""
 import numpy as np
 import pytest
 
@@ -120,3 +120,17 @@ def test_sampled_grid_cells(day):
         assert_exact("sum_speed", g["sum_speed"][i:i + 1], exp["sum_speed"])
         assert_exact("min_speed", g["min_speed"][i:i + 1], exp["min_speed"])
         assert_exact("max_speed", g["max_speed"][i:i + 1], exp["max_speed"])
+
+
+def test_whole_day_every_output_equals_oracle(day):
+    # the oracle over the whole day (some 20 s of host time): every record's
+    # order, sorted columns and kinematics, every journey row and every group row
+    from _parity import check_groups, check_sort, check_summary
+    r, grid, pipe, res, J, G = day
+    print(f"[fullsize] oracle over all {r.n} records", flush=True)
+    exp = oracle.run_plain(r.columns(), grid)
+    n = r.n
+    check_sort(pipe.perm[:n], {k: v[:n] for k, v in pipe.sorted.items()}, exp["perm"], exp["sorted"])
+    check_features({k: v[:n] for k, v in pipe.feat.items()}, exp["features"])
+    check_summary({k: v[:J] for k, v in pipe.journeys.items()}, exp["summary"])
+    check_groups({k: v[:G] for k, v in pipe.groups.items()}, res[2]["n_out_of_grid"], exp["groups"], exp["n_out"])

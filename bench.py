@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="default run: skip the batched sub-benchmark")
     ap.add_argument("--no-serving", action="store_true", help="default run: skip the serving sub-benchmark")
     ap.add_argument("--batched-steps", type=int, default=5, help="default run: timed steps of the batched form")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="c2: time the batched form only (no per-shard loop or comparison; for profiler runs)")
     ap.add_argument("--out", default=None, help="also write the JSON line to this file")
     ap.add_argument("--sort-shape", type=int, default=None,
                     help="radix tile shape index (default: the tuning cache, else the library default)")
@@ -219,6 +221,23 @@ def bench_batched(args, steps):
             stages_b[fam] = round(ms / steps, 4)
     stages_b["sort_passes"] = round(pass_ms_b / steps, 4)
     log(f"batched: {ms_batched:.2f} ms per step (median of {steps}) ({time.time() - t:.1f}s)")
+    out = {
+        "workload": f"c2: {len(sizes)} county-day shards, capped Zipf(1.2) sizes {min(sizes)}..{max(sizes)}, "
+                    f"time-ordered feed per shard, 0.001 deg x 1 min, batched in one set of launches",
+        "records": n, "shards": len(sizes), "journeys": J, "groups": G,
+        "value": round(n / (ms_batched / 1e3) / 1e6, 3), "unit": "Mrecords/s",
+        "ms_per_step": ms_batched, "step_ms": st,
+        "roofline": roof_b,
+        "stages_ms_per_step": stages_b,
+        "path_roofline": path_roofline(stages_b, n, G, rs_b["key_bits"], rs_b["packed_pass"], ms_batched,
+                                       design_bytes=317),
+        "key_bits": rs_b["key_bits"],
+        "packed_from_pass": rs_b["packed_pass"],
+    }
+    if args.batched_only:
+        del bp, rec
+        torch.cuda.empty_cache()
+        return out
     # plain per-file: one plain pipeline sized for the largest shard, called per shard
     big = max(sizes)
     pp = cvetl.Pipeline(big, grid, max_journeys=max(1024, mj), journey_capacity=max(1, J),
@@ -258,23 +277,10 @@ def bench_batched(args, steps):
         assert ok, f"batched and per-file outputs differ on shard {i}"
         checked += 1
     log(f"batched == per-file on all {checked} shards ({time.time() - t:.1f}s)")
-    out = {
-        "workload": f"c2: {len(sizes)} county-day shards, capped Zipf(1.2) sizes {min(sizes)}..{max(sizes)}, "
-                    f"time-ordered feed per shard, 0.001 deg x 1 min, batched in one set of launches",
-        "records": n, "shards": len(sizes), "journeys": J, "groups": G,
-        "value": round(n / (ms_batched / 1e3) / 1e6, 3), "unit": "Mrecords/s",
-        "ms_per_step": ms_batched, "step_ms": st,
-        "plain_per_file": {"value": round(n / (ms_plain / 1e3) / 1e6, 3), "ms_per_step": ms_plain, "step_ms": pf,
-                           "unit": "Mrecords/s"},
-        "batched_speedup": round(ms_plain / ms_batched, 3),
-        "identical_outputs_shards_checked": checked,
-        "roofline": roof_b,
-        "stages_ms_per_step": stages_b,
-        "path_roofline": path_roofline(stages_b, n, G, rs_b["key_bits"], rs_b["packed_pass"], ms_batched,
-                                       design_bytes=317),
-        "key_bits": rs_b["key_bits"],
-        "packed_from_pass": rs_b["packed_pass"],
-    }
+    out["plain_per_file"] = {"value": round(n / (ms_plain / 1e3) / 1e6, 3), "ms_per_step": ms_plain, "step_ms": pf,
+                             "unit": "Mrecords/s"}
+    out["batched_speedup"] = round(ms_plain / ms_batched, 3)
+    out["identical_outputs_shards_checked"] = checked
     del bp, pp, rec, views
     torch.cuda.empty_cache()
     return out

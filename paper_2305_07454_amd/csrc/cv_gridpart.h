@@ -22,9 +22,14 @@ namespace {
 
 constexpr int PR_MAX = 512;     // (journey, key) accumulators per tile in LDS
 constexpr int SCAN_BACK = 128;  // run heads a run head looks back over for its key
+// what a run head's entry of s_root holds once the rows are numbered
 constexpr uint16_t H_NONE = 0xFFFF;  // run outside the grid: dropped
-constexpr uint16_t H_SELF = 0xFFFE;  // run with a speed outside the fast format: a row of its own
-constexpr uint16_t H_ROW = 0x8000;   // final info: the run writes its own row (index in the low bits)
+constexpr uint16_t H_SELF = 0xFFFE;  // (before numbering) run with a speed outside the fast format
+constexpr uint16_t H_ROW = 0x8000;   // the run writes its own row (index in the low bits)
+constexpr uint16_t H_ACC = 0x4000;   // a root with an accumulator (its index in the low bits)
+// other values: the head index of the run's root (which holds H_ACC)
+constexpr uint16_t L_SEG = 0x8000;   // s_lpos: the head starts a (journey, time-bin) segment
+constexpr uint16_t L_ODD = 0x4000;   // s_lpos: the head's record has a speed outside the fast format
 constexpr uint8_t B_ODD = 32;        // record speed outside the 128-bit fast format
 constexpr u32 PART_ODD = 0x80000000u;
 
@@ -70,20 +75,23 @@ k_grid_part(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, cons
     constexpr int NWG = GB / WAVE;
     constexpr int WREC = GT / NWG;  // consecutive records per wave in the aggregation
     constexpr int PER = WREC / WAVE;
+    constexpr int HPM = GT / GB;    // run heads per thread at most in the numbering
     static_assert(PER == 8, "one 64-bit word of flags per lane");
     static_assert(GI * NWG <= WAVE, "one row count per lane");
-    __shared__ i64 s_key[GT];
+    static_assert(PR_MAX < H_ACC && GT <= 0x3FFF, "head and accumulator indices fit the tags");
+    __shared__ i64 s_hkey[GT];       // run head -> its key
     __shared__ __attribute__((aligned(16))) uint8_t s_bits[GT];
     __shared__ __attribute__((aligned(16))) float s_spd[GT];
-    __shared__ uint16_t s_lpos[GT];  // run head -> position | segment start << 15
-    __shared__ uint16_t s_root[GT];  // run head -> its root head; later its final info
+    __shared__ uint16_t s_lpos[GT];  // run head -> position | L_SEG | L_ODD
+    __shared__ uint16_t s_root[GT];  // run head -> its root head; then the H_* info
     __shared__ u64 s_c0[PR_MAX], s_c1[PR_MAX];  // sum: two carry-save 43-bit chunks (mod 2^86)
     __shared__ u32 s_cn[PR_MAX], s_mn[PR_MAX], s_mx[PR_MAX];
-    __shared__ uint16_t s_orow[PR_MAX], s_opos[PR_MAX];  // accumulator -> row, root position
+    __shared__ uint16_t s_orow[PR_MAX], s_opos[PR_MAX], s_ohead[PR_MAX];  // accumulator -> row, root position, head
     __shared__ i64 s_lj[GI][NWG], s_ltb[GI][NWG], s_lk[GI][NWG];  // lane 63 of every wave row
     __shared__ u32 s_cnt[GI * NWG];
     __shared__ uint8_t s_rodd[GI][NWG];
-    __shared__ u32 s_tmp[GB / WAVE];
+    __shared__ u64 s_tmp[GB / WAVE];
+    __shared__ u32 s_tmp32[GB / WAVE];
     __shared__ u64 s_red[GB / WAVE];
 
     const int t = threadIdx.x;
@@ -94,7 +102,7 @@ k_grid_part(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, cons
 
     // 1. the tile's records, rows of GB striped over the block (coalesced);
     //    every column is loaded first so that all loads are in flight together
-    i64 vj[GI], vt[GI], vtb[GI];
+    i64 vj[GI], vt[GI], vtb[GI], vk[GI];
     double vla[GI], vlo[GI];
     float vsp[GI];
     float vh[KD == 1 ? GI : 1];
@@ -115,8 +123,16 @@ k_grid_part(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, cons
             vbf[rr] = g.bfl[r];
         }
     }
+    // the tile's first shard, its start and the next shard's start (the same
+    // addresses in every lane); a record before the next start needs no search
+    u32 sh0 = 0;
+    u64 s0start = ~0ull, nxt = ~0ull;
+    if (g.S > 1) {
+        sh0 = shard_of(g.soff, g.S, tile0);
+        s0start = g.soff[sh0];
+        nxt = sh0 + 1 < g.S ? g.soff[sh0 + 1] : ~0ull;
+    }
     u64 n_out = 0;
-    const u32 sh0 = g.S > 1 ? shard_of(g.soff, g.S, tile0) : 0u;
     uint8_t bq[GI];
 #pragma unroll
     for (int rr = 0; rr < GI; ++rr) {
@@ -128,8 +144,12 @@ k_grid_part(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, cons
         if (in) {
             u32 sh = sh0;
             if (g.S > 1) {
-                while (sh + 1 < g.S && g.soff[sh + 1] <= r) ++sh;
-                sstart = g.soff[sh] == r;
+                if (r < nxt) {
+                    sstart = r == s0start;
+                } else {
+                    sh = shard_from(g.soff, g.S, sh0, r);
+                    sstart = g.soff[sh] == r;
+                }
             }
             u32 dir = 0;
             if constexpr (KD == 1) dir = dir_sector(g, (double)vh[rr], true);
@@ -141,6 +161,7 @@ k_grid_part(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, cons
             }
         }
         vtb[rr] = tb;
+        vk[rr] = k;
         const i64 jp = __shfl_up(vj[rr], 1, WAVE);
         const i64 tbp = __shfl_up(tb, 1, WAVE);
         const i64 kp = __shfl_up(k, 1, WAVE);
@@ -156,7 +177,6 @@ k_grid_part(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, cons
         // of the aggregation start runs: no run is split between waves
         const bool run = seg || q % WREC == 0 || (lane > 0 && k != kp);
         bq[rr] = (seg ? B_SEG : 0) | (run ? B_RUN : 0) | (odd ? B_ODD : 0);
-        s_key[q] = k;
         s_spd[q] = in ? vsp[rr] : 0.f;
         const u64 om = __ballot(odd);
         if (lane == 0) s_rodd[rr][w] = om != 0;
@@ -175,18 +195,19 @@ k_grid_part(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, cons
         const int pw = w > 0 ? w - 1 : NWG - 1;
         if (lane == 0 && q > 0 && in && !(b & B_SEG)) {
             if (vj[rr] != s_lj[pr][pw] || vtb[rr] != s_ltb[pr][pw]) b |= B_SEG | B_RUN;
-            else if (s_key[q] != s_lk[pr][pw]) b |= B_RUN;
+            else if (vk[rr] != s_lk[pr][pw]) b |= B_RUN;
         }
         const bool chk = s_rodd[rr][w] || (lane == 0 && q > 0 && s_rodd[pr][pw]);
         if (chk && in && ((b & B_ODD) || (q > 0 && spd_odd(s_spd[q - 1])))) b |= B_RUN;
+        bq[rr] = b;
         s_bits[q] = b;
         hm[rr] = __ballot((b & B_RUN) && in);
         if (lane == 0) s_cnt[rr * NWG + w] = (u32)__popcll(hm[rr]);
     }
     __syncthreads();
 
-    // 3. the run-head list in position order: per-row ballots placed by one
-    //    prefix over the (row, wave) counts
+    // 3. the run-head list in position order (per-row ballots placed by one
+    //    prefix over the (row, wave) counts), with each head's key
     int L;
     {
         const u32 c = lane < GI * NWG ? s_cnt[lane] : 0u;
@@ -197,9 +218,11 @@ k_grid_part(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, cons
         for (int rr = 0; rr < GI; ++rr) {
             const int q = rr * GB + t;
             const u32 off = __shfl(inc - c, rr * NWG + w, WAVE);
-            if ((hm[rr] >> lane) & 1ull)
-                s_lpos[off + (u32)__popcll(hm[rr] & below)] =
-                    (uint16_t)(q | ((s_bits[q] & B_SEG) ? 0x8000 : 0));
+            if ((hm[rr] >> lane) & 1ull) {
+                const u32 e = off + (u32)__popcll(hm[rr] & below);
+                s_lpos[e] = (uint16_t)(q | ((bq[rr] & B_SEG) ? L_SEG : 0) | ((bq[rr] & B_ODD) ? L_ODD : 0));
+                s_hkey[e] = vk[rr];
+            }
         }
     }
     __syncthreads();
@@ -210,124 +233,36 @@ k_grid_part(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, cons
     //    Several roots of one (journey, key) only cost extra partial rows.
     for (int e = t; e < L; e += GB) {
         const uint16_t pe = s_lpos[e];
-        const int q = pe & 0x7FFF;
-        const i64 k = s_key[q];
+        const i64 k = s_hkey[e];
         uint16_t root;
         if (k < 0) {
             root = H_NONE;
-        } else if (s_bits[q] & B_ODD) {
+        } else if (pe & L_ODD) {
             root = H_SELF;
         } else {
             int rt = e;
-            bool done = (pe & 0x8000) || e == 0;
+            bool done = (pe & L_SEG) || e == 0;
             int f = e - 1;
             for (int steps = 0; !done && steps < SCAN_BACK; steps += 4) {
                 uint16_t pf[4];
                 i64 kf[4];
-                uint8_t bf[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) pf[u] = s_lpos[f - u >= 0 ? f - u : 0];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    kf[u] = s_key[pf[u] & 0x7FFF];
-                    bf[u] = s_bits[pf[u] & 0x7FFF];
+                    const int x = f - u >= 0 ? f - u : 0;
+                    pf[u] = s_lpos[x];
+                    kf[u] = s_hkey[x];
                 }
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     if (done) continue;
-                    if (kf[u] == k && !(bf[u] & B_ODD)) rt = f - u;
-                    if ((pf[u] & 0x8000) || f - u == 0) done = true;
+                    if (kf[u] == k && !(pf[u] & L_ODD)) rt = f - u;
+                    if ((pf[u] & L_SEG) || f - u == 0) done = true;
                 }
                 f -= 4;
             }
             root = (uint16_t)(done ? rt : e);
         }
         s_root[e] = root;
-    }
-    __syncthreads();
-
-    // 5. accumulator of each root (in list order; the first PR_MAX roots get
-    //    one), the rows in position order (a root with an accumulator writes
-    //    one; a run of a root without one, and a run of its own, write their
-    //    own), and every head's final info: accumulator or row
-    const int HP = (L + GB - 1) / GB;
-    const int h0 = t * HP < L ? t * HP : L;
-    const int h1 = h0 + HP < L ? h0 + HP : L;
-    constexpr int HPM = GT / GB;  // run heads per thread at most
-    u32 R;
-    {
-        u32 nr = 0;
-#pragma unroll
-        for (int u = 0; u < HPM; ++u) {
-            const int e = h0 + u;
-            if (e < h1) nr += s_root[e] == (uint16_t)e;
-        }
-        u32 o = block_exclusive_sum<GB>(nr, s_tmp, R);
-#pragma unroll
-        for (int u = 0; u < HPM; ++u) {
-            const int e = h0 + u;
-            if (e < h1 && s_root[e] == (uint16_t)e) s_root[e] = (uint16_t)(0x8000u | o++);
-        }
-    }
-    __syncthreads();
-    u32 ROWS;
-    u64 kmax = 0;
-    uint16_t info[HPM];
-    {
-        u32 nrow = 0;
-#pragma unroll
-        for (int u = 0; u < HPM; ++u) {
-            const int e = h0 + u;
-            if (e >= h1) continue;
-            const uint16_t v = s_root[e];
-            if (v == H_NONE) continue;
-            if (v == H_SELF || (v & 0x8000)) ++nrow;
-            else if ((s_root[v] & 0x7FFF) >= PR_MAX) ++nrow;
-        }
-        u32 row = block_exclusive_sum<GB>(nrow, s_tmp, ROWS);
-#pragma unroll
-        for (int u = 0; u < HPM; ++u) {
-            const int e = h0 + u;
-            info[u] = H_NONE;
-            if (e >= h1) continue;
-            const uint16_t v = s_root[e];
-            const int q = s_lpos[e] & 0x7FFF;
-            uint16_t x = H_NONE;
-            if (v == H_NONE) {
-                x = H_NONE;
-            } else if (v == H_SELF) {
-                x = (uint16_t)(H_ROW | row++);
-            } else if (v & 0x8000) {
-                const u32 o = v & 0x7FFF;
-                if (o < PR_MAX) {
-                    s_orow[o] = (uint16_t)row++;
-                    s_opos[o] = (uint16_t)q;
-                    x = (uint16_t)o;
-                } else {
-                    x = (uint16_t)(H_ROW | row++);
-                }
-            } else {
-                const u32 o = s_root[v] & 0x7FFF;
-                x = o < PR_MAX ? (uint16_t)o : (uint16_t)(H_ROW | row++);
-            }
-            if (x != H_NONE && ((x & H_ROW) || (v & 0x8000))) {
-                const u64 k = (u64)s_key[q];
-                kmax = k > kmax ? k : kmax;
-            }
-            info[u] = x;
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < HPM; ++u)
-        if (h0 + u < h1) s_root[h0 + u] = info[u];
-    const u32 RA = R < (u32)PR_MAX ? R : (u32)PR_MAX;
-    for (u32 o = t; o < RA; o += GB) {
-        s_c0[o] = 0;
-        s_c1[o] = 0;
-        s_cn[o] = 0;
-        s_mn[o] = ~0u;
-        s_mx[o] = 0;
     }
     // run heads before each lane's records in the aggregation layout
     const int qa = w * WREC;
@@ -338,32 +273,154 @@ k_grid_part(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, cons
 #pragma unroll
     for (int i = 0; i < PER; ++i)
         if (i < nv && ((bits8 >> (8 * i)) & B_RUN)) ++hc;
-    u32 HT;
-    const u32 hbase = block_exclusive_sum<GB>(hc, s_tmp, HT);  // its syncs also publish the infos above
+    __syncthreads();
+
+    // 5. numbering, in list order: roots get accumulators (the first PR_MAX of
+    //    them), rows follow position order (a root with an accumulator writes
+    //    one; a run of its own writes one; beyond PR_MAX roots, every run of a
+    //    root without an accumulator writes its own).  One packed scan gives
+    //    the roots, the rows when no root lacks an accumulator, and the run
+    //    heads before each aggregation lane.
+    const int HP = (L + GB - 1) / GB;
+    const int h0 = t * HP < L ? t * HP : L;
+    const int h1 = h0 + HP < L ? h0 + HP : L;
+    u32 nr = 0, nw = 0;
+#pragma unroll
+    for (int u = 0; u < HPM; ++u) {
+        const int e = h0 + u;
+        if (e >= h1) continue;
+        const uint16_t v = s_root[e];
+        nr += v == (uint16_t)e;
+        nw += v == (uint16_t)e || v == H_SELF;
+    }
+    u64 tot;
+    const u64 ex = block_exclusive_sum<GB>((u64)nr | ((u64)nw << 16) | ((u64)hc << 32), s_tmp, tot);
+    const u32 R = (u32)(tot & 0xFFFF);
+    const u32 hbase = (u32)(ex >> 32);
+    u32 ROWS = (u32)((tot >> 16) & 0xFFFF);
+    u64 kmax = 0;
+    if (R <= (u32)PR_MAX) {
+        u32 o = (u32)(ex & 0xFFFF), row = (u32)((ex >> 16) & 0xFFFF);
+#pragma unroll
+        for (int u = 0; u < HPM; ++u) {
+            const int e = h0 + u;
+            if (e >= h1) continue;
+            const uint16_t v = s_root[e];
+            if (v == (uint16_t)e) {
+                const int q = s_lpos[e] & 0x07FF;
+                s_orow[o] = (uint16_t)row++;
+                s_opos[o] = (uint16_t)q;
+                s_ohead[o] = (uint16_t)e;
+                s_root[e] = (uint16_t)(H_ACC | o++);
+            } else if (v == H_SELF) {
+                s_root[e] = (uint16_t)(H_ROW | row++);
+            } else {
+                continue;  // members keep their root's head index; dropped runs stay H_NONE
+            }
+            const u64 k = (u64)s_hkey[e];
+            kmax = k > kmax ? k : kmax;
+        }
+    } else {
+        // more roots than accumulators: a second count of the rows, since the
+        // runs tied to a root without one each write their own
+        {
+            u32 o = (u32)(ex & 0xFFFF);
+#pragma unroll
+            for (int u = 0; u < HPM; ++u) {
+                const int e = h0 + u;
+                if (e < h1 && s_root[e] == (uint16_t)e) s_root[e] = (uint16_t)(H_ACC | o++);
+            }
+        }
+        __syncthreads();
+        u32 nrow = 0;
+#pragma unroll
+        for (int u = 0; u < HPM; ++u) {
+            const int e = h0 + u;
+            if (e >= h1) continue;
+            const uint16_t v = s_root[e];
+            if (v == H_NONE) continue;
+            if (v == H_SELF || (v & H_ACC)) ++nrow;
+            else if ((s_root[v] & 0x3FFF) >= (u32)PR_MAX) ++nrow;
+        }
+        u32 rt;
+        u32 row = block_exclusive_sum<GB>(nrow, s_tmp32, rt);
+        ROWS = rt;
+        uint16_t info[HPM];
+#pragma unroll
+        for (int u = 0; u < HPM; ++u) {
+            const int e = h0 + u;
+            info[u] = H_NONE;
+            if (e >= h1) continue;
+            const uint16_t v = s_root[e];
+            uint16_t x = v;  // members of roots with an accumulator keep the root's index
+            if (v == H_NONE) {
+                continue;
+            } else if (v == H_SELF) {
+                x = (uint16_t)(H_ROW | row++);
+            } else if (v & H_ACC) {
+                const u32 o = v & 0x3FFF;
+                if (o < (u32)PR_MAX) {
+                    s_orow[o] = (uint16_t)row++;
+                    s_opos[o] = (uint16_t)(s_lpos[e] & 0x07FF);
+                    s_ohead[o] = (uint16_t)e;
+                } else {
+                    x = (uint16_t)(H_ROW | row++);
+                }
+            } else if ((s_root[v] & 0x3FFF) >= (u32)PR_MAX) {
+                x = (uint16_t)(H_ROW | row++);
+            }
+            if (x & (H_ROW | H_ACC)) {
+                const u64 k = (u64)s_hkey[e];
+                kmax = k > kmax ? k : kmax;
+            }
+            info[u] = x;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < HPM; ++u)
+            if (h0 + u < h1) s_root[h0 + u] = info[u];
+    }
+    const u32 RA = R < (u32)PR_MAX ? R : (u32)PR_MAX;
+    for (u32 o = t; o < RA; o += GB) {
+        s_c0[o] = 0;
+        s_c1[o] = 0;
+        s_cn[o] = 0;
+        s_mn[o] = ~0u;
+        s_mx[o] = 0;
+    }
+    __syncthreads();
+    // the journey ids of the accumulator rows, fetched now, used at the end
+    static_assert(PR_MAX <= 2 * GB, "two accumulator rows per thread");
+    i64 rj0 = 0, rj1 = 0;
+    if ((u32)t < RA) rj0 = jid[tile0 + s_opos[t]];
+    if ((u32)(t + GB) < RA) rj1 = jid[tile0 + s_opos[t + GB]];
 
     // 6. every run reduced once (a lane folds its PER consecutive records into
     //    pieces cut at run starts; one segmented scan joins the pieces of runs
-    //    that cross lanes) and added into its accumulator, or written as a row
+    //    that cross lanes) and added into its root's accumulator, or written
+    //    as a row of its own
     auto put = [&](int e, const RunPart& p) {
         if (e < 0 || (p.cn & 0xFFFFu) == 0) return;
-        const uint16_t x = s_root[e];
+        uint16_t x = s_root[e];
         if (x == H_NONE) return;
+        if (!(x & (H_ROW | H_ACC))) x = s_root[x];  // a member: its root's accumulator
         if (x & H_ROW) {
-            const u32 row = x & 0x7FFF;
-            const int q = s_lpos[e] & 0x7FFF;
+            const u32 row = x & 0x07FF;
+            const int q = s_lpos[e] & 0x07FF;
             const u64 at = (u64)blockIdx.x * GT + row;
-            sk.key[at] = (u64)s_key[q];
+            sk.key[at] = (u64)s_hkey[e];
             sk.part[at] = make_part(jid[tile0 + (u64)q], p.lo, p.hi,
                                     (p.cn & 0xFFFFu) | ((p.cn & RUN_ODD) ? PART_ODD : 0u), p.mn, p.mx);
         } else {
+            const u32 o = x & 0x3FFF;
             const u64 M43 = (1ull << 43) - 1;
             const u64 a0 = p.lo & M43;
             const u64 a1 = ((p.lo >> 43) | (p.hi << 21)) & M43;
-            if (a0) atomicAdd((unsigned long long*)&s_c0[x], (unsigned long long)a0);
-            if (a1) atomicAdd((unsigned long long*)&s_c1[x], (unsigned long long)a1);
-            atomicAdd(&s_cn[x], p.cn & 0xFFFFu);
-            atomicMin(&s_mn[x], p.mn);
-            atomicMax(&s_mx[x], p.mx);
+            if (a0) atomicAdd((unsigned long long*)&s_c0[o], (unsigned long long)a0);
+            if (a1) atomicAdd((unsigned long long*)&s_c1[o], (unsigned long long)a1);
+            atomicAdd(&s_cn[o], p.cn & 0xFFFFu);
+            atomicMin(&s_mn[o], p.mn);
+            atomicMax(&s_mx[o], p.mx);
         }
     };
     {
@@ -373,7 +430,7 @@ k_grid_part(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, cons
         RunPart cur, pre;
         run_reset(cur);
         run_reset(pre);
-        bool hh = false;       // the lane holds a run start
+        bool hh = false;          // the lane holds a run start
         int ec = (int)hbase - 1;  // head of the run the current piece belongs to
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
@@ -431,13 +488,12 @@ k_grid_part(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, cons
     }
     if (lane == 0) {
         s_red[w] = kmax;
-        s_tmp[w] = (u32)n_out;
+        s_tmp32[w] = (u32)n_out;
     }
     __syncthreads();
 
     // 7. the rows of the accumulators
     for (u32 o = t; o < RA; o += GB) {
-        const int q = s_opos[o];
         const u64 at = (u64)blockIdx.x * GT + s_orow[o];
         // the 128-bit sum from its two 43-bit carry-save chunks, mod 2^86 and
         // sign-extended (a tile's sum is below 2^74 in magnitude)
@@ -446,14 +502,14 @@ k_grid_part(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, cons
         u64 hi = (c1 >> 21) + (lo < c0 ? 1ull : 0ull);
         hi &= (1ull << 22) - 1;
         if (hi >> 21) hi |= ~((1ull << 22) - 1);
-        sk.key[at] = (u64)s_key[q];
-        sk.part[at] = make_part(jid[tile0 + (u64)q], lo, hi, s_cn[o], s_mn[o], s_mx[o]);
+        sk.key[at] = (u64)s_hkey[s_ohead[o]];
+        sk.part[at] = make_part(o < (u32)GB ? rj0 : rj1, lo, hi, s_cn[o], s_mn[o], s_mx[o]);
     }
     if (t == 0) {
         u64 km = 0, no = 0;
         for (int i = 0; i < NWG; ++i) {
             km = s_red[i] > km ? s_red[i] : km;
-            no += s_tmp[i];
+            no += s_tmp32[i];
         }
         sk.count[blockIdx.x] = ROWS;
         sk.kmax[blockIdx.x] = km;

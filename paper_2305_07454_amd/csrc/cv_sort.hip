@@ -47,7 +47,7 @@ struct SortMeta {
     u32 shard_bits;
     u32 ib;   // index bits of a packed key word
     u32 p0;   // first pass whose input words are packed (ib and p0 adjacent: the radix passes read both)
-    u32 n_runs;  // runs of equal ids in input order (dictionary probes of the key packing)
+    u32 n_runs;  // runs of equal ids in input order (counted by the dictionary insert)
     u32 unordered;  // a timestamp below its predecessor's (same shard) in input order
     u32 ts_dropped; // key = (shard, rank) only: the input is time-ordered within every shard
     u32 tickets[2 * MAX_PASSES];
@@ -68,12 +68,12 @@ __global__ void k_sort_init(SortMeta* m)
 // The dictionary is an open-addressing table of 16-byte slots {id, rank}:
 // the id word is claimed by CAS (EMPTY when free) and the rank word is filled
 // in once the distinct ids are sorted, so that one 16-byte load per probe
-// returns both.
-__device__ __forceinline__ bool dict_insert(u64* table, u64 mask, u64 key)
+// returns both.  An insert probes linearly from mix64(id); the caller reads the
+// first slot (so that the first probes of many records are in flight
+// together) and this continues from it.
+__device__ __forceinline__ bool dict_insert_from(u64* table, u64 mask, u64 key, u64 h, u64 cur)
 {
-    u64 h = mix64(key) & mask;
     for (u64 probe = 0; probe <= mask; ++probe) {
-        u64 cur = table[2 * h];
         if (cur == key) return true;
         if (cur == EMPTY) {
             u64 prev =
@@ -81,6 +81,7 @@ __device__ __forceinline__ bool dict_insert(u64* table, u64 mask, u64 key)
             if (prev == EMPTY || prev == key) return true;
         }
         h = (h + 1) & mask;
+        cur = table[2 * h];
     }
     return false;
 }
@@ -157,6 +158,7 @@ __global__ void __launch_bounds__(256) k_dict_insert(const i64* __restrict__ jid
     wave_range(n, wbeg, wend);
     i64 prevj = 0;  // last id of the previous window
     bool hp = false;
+    u32 runs = 0;   // records that start a run of equal ids (wave-uniform)
     // time of the record before the range (ordered form), then of each window's last
     u64 prevt = (wbeg < wend && wbeg > 0) ? ord_i64(ts[wbeg * WAVE - 1]) : 0ull;
     bool down = false;
@@ -171,9 +173,14 @@ __global__ void __launch_bounds__(256) k_dict_insert(const i64* __restrict__ jid
             jv[k] = jid[i];
             tv[k] = ord_i64(ts[i]);
         }
+        // first the run starts of every window and, for each that misses the
+        // cache, the first probe, issued together; then the inserts in order
+        bool miss[DPW];
+        u64 ph[DPW], pc[DPW];
 #pragma unroll
         for (int k = 0; k < DPW; ++k) {
-            if (w0 + k >= wend) break;
+            miss[k] = false;
+            if (w0 + k >= wend) continue;
             const u64 i = (w0 + k) * WAVE + l;
             const bool valid = i < n;
             const i64 j = jv[k];
@@ -197,16 +204,25 @@ __global__ void __launch_bounds__(256) k_dict_insert(const i64* __restrict__ jid
             prevj = __shfl(j, WAVE - 1, WAVE);
             hp = true;
             bool need = valid && !dup;
+            runs += (u32)__popcll(__ballot(need));
             if (need && (u64)j == EMPTY) {
                 has_min = true;
                 need = false;
             }
             const u32 cs = dict_cache_slot<DC>((u64)j);
-            const bool miss = need && c_key[w][cs] != (u64)j;
-            if (miss && !dict_insert(table, mask, (u64)j)) full = true;
-            if (miss) c_own[w][cs] = (u32)l;
+            miss[k] = need && c_key[w][cs] != (u64)j;
+            ph[k] = mix64((u64)j) & mask;
+            if (miss[k]) pc[k] = table[2 * ph[k]];
+        }
+#pragma unroll
+        for (int k = 0; k < DPW; ++k) {
+            if (w0 + k >= wend) break;
+            const u64 j = (u64)jv[k];
+            const u32 cs = dict_cache_slot<DC>(j);
+            if (miss[k] && !dict_insert_from(table, mask, j, ph[k], pc[k])) full = true;
+            if (miss[k]) c_own[w][cs] = (u32)l;
             __builtin_amdgcn_wave_barrier();
-            if (miss && c_own[w][cs] == (u32)l) c_key[w][cs] = (u64)j;
+            if (miss[k] && c_own[w][cs] == (u32)l) c_key[w][cs] = j;
             __builtin_amdgcn_wave_barrier();
         }
     }
@@ -223,6 +239,7 @@ __global__ void __launch_bounds__(256) k_dict_insert(const i64* __restrict__ jid
     if (has_min) atomicOr(&m->has_min, 1u);
     if (full) atomicOr(&m->overflow, 1u);
     if (__ballot(down) && l == 0) atomicOr(&m->unordered, 1u);
+    if (runs && l == 0) atomicAdd(&m->n_runs, runs);
     __syncthreads();
     if (threadIdx.x == 0) {
         for (int k = 1; k < (int)(blockDim.x / WAVE); ++k) {
@@ -335,47 +352,54 @@ struct __attribute__((aligned(32))) PayRec {
 constexpr u64 PAY_MIN_RUN = 8;  // mean run length below which the packed form is used
 __device__ __forceinline__ bool pay_packed(const SortMeta* m, u32 n) { return (u64)m->n_runs * PAY_MIN_RUN > n; }
 
-__global__ void __launch_bounds__(256) k_pay_pack(u32 n, const SortMeta* m, const i64* __restrict__ ts,
-                                                  const double* __restrict__ lat, const double* __restrict__ lon,
-                                                  const float* __restrict__ spd, PayRec* __restrict__ pay)
+// rank of `key` continuing a probe sequence at slot h, whose entry e was read
+__device__ __forceinline__ u32 dict_rank_from(const u64* table, u64 mask, u64 key, u64 h, ulonglong2 e)
 {
-    if (!pay_packed(m, n)) return;
-    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        PayRec p;
-        p.ts = ts[i];
-        p.lat = lat[i];
-        p.lon = lon[i];
-        p.spd = spd[i];
-        p.pad = 0;
-        pay[i] = p;
+    const ulonglong2* t2 = (const ulonglong2*)table;
+    for (u64 probe = 0; probe <= mask; ++probe) {
+        if (e.x == key) return (u32)e.y;
+        if (e.x == EMPTY) return 0u;
+        h = (h + 1) & mask;
+        e = t2[h];
     }
+    return 0u;
 }
 
 constexpr int PW = 8;
-template <bool SHARDS>
-__global__ void __launch_bounds__(256) k_pack_hist(const i64* __restrict__ jid, const i64* __restrict__ ts, u32 n,
-                                                   const u64* __restrict__ table,
-                                                   u64 mask, SortMeta* m, u64* __restrict__ keys,
-                                                   u32* __restrict__ hist, const u64* __restrict__ soff, u32 S)
+// Keys of every record with the digit histograms of every pass.  A round takes
+// PW windows whose columns are loaded together.  Two forms, launched one after
+// the other, of which one returns at once: for input in long runs of equal ids
+// (IL = false) a run head probes the dictionary where it meets it; for
+// interleaved input (IL = true), where nearly every record starts a run, every
+// run head of the round that misses the wave's cache issues its first probe
+// before any is used, and the pass also writes the payload packed per record
+// for the gather.
+template <bool SHARDS, bool IL>
+__global__ void __launch_bounds__(256) k_pack_hist(const i64* __restrict__ jid, const i64* __restrict__ ts,
+                                                   const double* __restrict__ lat, const double* __restrict__ lon,
+                                                   const float* __restrict__ spd, PayRec* __restrict__ pay, u32 n,
+                                                   const u64* __restrict__ table, u64 mask, SortMeta* m,
+                                                   u64* __restrict__ keys, u32* __restrict__ hist,
+                                                   const u64* __restrict__ soff, u32 S)
 {
     __shared__ u32 s_h[MAX_PASSES * RADIX];
-    __shared__ u32 s_runs;
     // per-wave cache of (id, rank) pairs, as in the dictionary insert
     __shared__ u64 c_key[4][DCP];
     __shared__ u32 c_rank[4][DCP], c_own[4][DCP];
+    if (pay_packed(m, n) != IL) return;
     for (int i = threadIdx.x; i < MAX_PASSES * RADIX; i += blockDim.x) s_h[i] = 0;
     for (int i = threadIdx.x; i < 4 * DCP; i += blockDim.x) (&c_key[0][0])[i] = EMPTY;
-    if (threadIdx.x == 0) s_runs = 0;
     __syncthreads();
     const int wv_ = threadIdx.x / WAVE;
-    u32 runs = 0;  // run starts this wave found (wave-uniform)
     const u32 tb = m->t_bits;
     const bool tdrop = m->ts_dropped != 0;
     const u32 np = m->passes;
     const bool bad = m->range_err != 0;
     const u32 ib = m->ib;
     const bool packed = m->p0 == 0;
+    const bool wpay = IL && pay;
     const u64 tmin = (u64)unord_i64(m->tmin_ord);
+    const ulonglong2* t2 = (const ulonglong2*)table;
     const int l = lane_id();
     const u64 nw = (u64)gridDim.x * (blockDim.x / WAVE);
     const u64 nwin = ((u64)n + WAVE - 1) / WAVE;
@@ -397,38 +421,90 @@ __global__ void __launch_bounds__(256) k_pack_hist(const i64* __restrict__ jid, 
             jv[k] = (u64)jid[i];
             tv[k] = (u64)ts[i];
         }
+        if (IL && wpay) {
+            // the payload of the round's records, packed (loads issued together)
+            double la[PW], lo[PW];
+            float sp[PW];
+#pragma unroll
+            for (int k = 0; k < PW; ++k) {
+                u64 i = (w0 + k) * WAVE + l;
+                i = i < n ? i : (u64)n - 1;
+                la[k] = lat[i];
+                lo[k] = lon[i];
+                sp[k] = spd[i];
+            }
+#pragma unroll
+            for (int k = 0; k < PW; ++k) {
+                const u64 i = (w0 + k) * WAVE + l;
+                if (w0 + k < wend && i < n) {
+                    ulonglong2* q = (ulonglong2*)(pay + i);
+                    q[0] = make_ulonglong2(tv[k], (u64)__double_as_longlong(la[k]));
+                    q[1] = make_ulonglong2((u64)__double_as_longlong(lo[k]), (u64)__float_as_uint(sp[k]));
+                }
+            }
+        }
+        // run heads of every window, their cached ranks, and the first probe
+        // of every miss, issued together
+        bool look[PW], miss[PW];
+        u32 rk[PW];
+        ulonglong2 pe[PW];
+        u64 ph[PW];
+#pragma unroll
+        for (int k = 0; k < PW; ++k) {
+            look[k] = miss[k] = false;
+            rk[k] = 0;
+            if constexpr (!IL) continue;
+            const u64 i = (w0 + k) * WAVE + l;
+            const bool valid = w0 + k < wend && i < n;
+            const u64 j = valid ? jv[k] : EMPTY;
+            const u64 jp = __shfl_up(j, 1, WAVE);
+            const u64 jl = k == 0 ? cj : __shfl(k == 0 ? 0ull : jv[k > 0 ? k - 1 : 0], WAVE - 1, WAVE);
+            const bool prev = k == 0 ? hc : true;
+            const bool runhead = l == 0 ? !(prev && j == jl) : j != jp;
+            look[k] = valid && runhead && j != EMPTY;
+            const u32 cs = dict_cache_slot<DCP>(j);
+            miss[k] = false;
+            rk[k] = 0;
+            if (look[k]) {
+                if (c_key[wv_][cs] == j) rk[k] = c_rank[wv_][cs];
+                else miss[k] = true;
+            }
+            ph[k] = mix64(j) & mask;
+            if (miss[k]) pe[k] = t2[ph[k]];
+        }
 #pragma unroll
         for (int k = 0; k < PW; ++k) {
             const u64 wi = w0 + k;
             if (wi >= wend) break;
             const u64 i = wi * WAVE + l;
             const bool valid = i < n;
-            // only the first lane of each run of equal ids probes the dictionary;
-            // the others take its rank (lane 0 continues the carried run)
             const u64 j = valid ? jv[k] : EMPTY;
             const u64 jp = __shfl_up(j, 1, WAVE);
             const bool runhead = l == 0 ? !(hc && j == cj) : j != jp;
-            u32 r = 0;
-            const bool look = valid && runhead && j != EMPTY;
+            u32 r = rk[k];
             const u32 cs = dict_cache_slot<DCP>(j);
-            bool miss = false;
-            if (look) {
-                if (c_key[wv_][cs] == j) {
-                    r = c_rank[wv_][cs];
-                } else {
-                    r = dict_rank_of(table, mask, j);
-                    miss = true;
+            if constexpr (IL) {
+                if (miss[k]) r = dict_rank_from(table, mask, j, ph[k], pe[k]);
+            } else {
+                // the cache, then the table, where a run starts
+                if (valid && runhead && j != EMPTY) {
+                    if (c_key[wv_][cs] == j) r = c_rank[wv_][cs];
+                    else {
+                        r = dict_rank_of(table, mask, j);
+                        miss[k] = true;
+                    }
                 }
             }
-            if (miss) c_own[wv_][cs] = (u32)l;
+            if (miss[k]) c_own[wv_][cs] = (u32)l;
             __builtin_amdgcn_wave_barrier();
-            if (miss && c_own[wv_][cs] == (u32)l) {
+            if (miss[k] && c_own[wv_][cs] == (u32)l) {
                 c_key[wv_][cs] = j;
                 c_rank[wv_][cs] = r;
             }
             __builtin_amdgcn_wave_barrier();
+            // only the first lane of each run of equal ids looked its rank up;
+            // the others take it (lane 0 continues the carried run)
             const u64 heads = __ballot(runhead);
-            runs += (u32)__popcll(heads & __ballot(valid));
             const u64 upto = heads & (~0ull >> (63 - l));  // run starts at or below this lane
             const u32 rh = __shfl(r, upto ? 63 - __clzll((long long)upto) : 0, WAVE);
             r = upto ? rh : cr;
@@ -461,11 +537,9 @@ __global__ void __launch_bounds__(256) k_pack_hist(const i64* __restrict__ jid, 
             }
         }
     }
-    if (lane_id() == 0 && runs) atomicAdd(&s_runs, runs);
     __syncthreads();
     for (u32 i = threadIdx.x; i < np * RADIX; i += blockDim.x)
         if (s_h[i]) atomicAdd(&hist[i], s_h[i]);
-    if (threadIdx.x == 0 && s_runs) atomicAdd(&m->n_runs, s_runs);
 }
 
 // The final words are packed: (key >> 8 p0) << ib | source index.  Every
@@ -941,14 +1015,14 @@ static cv_status sort_impl(const cv_records* in, const uint64_t* soff, uint32_t 
                      L.meta->tickets + MAX_PASSES, s);
         hipLaunchKernelGGL(k_dict_rank, dim3(cvh::grid_for(max_journeys, 256, 1024)), dim3(256), 0, s, L.dl0, L.meta,
                            L.table, mask);
-        hipLaunchKernelGGL(S > 1 ? k_pack_hist<true> : k_pack_hist<false>, dim3(gs), dim3(256), 0, s, in->journey_id,
-                           in->ts_ms, nn, L.table, mask, L.meta, L.K0, L.hist, soff, S);
+        // interleaved input (short runs of equal ids): the payload packed per
+        // record for the fused gather, in the same pass
+        for (const bool il : {false, true})
+            hipLaunchKernelGGL(S > 1 ? (il ? k_pack_hist<true, true> : k_pack_hist<true, false>)
+                                     : (il ? k_pack_hist<false, true> : k_pack_hist<false, false>),
+                               dim3(gs), dim3(256), 0, s, in->journey_id, in->ts_ms, in->lat_deg, in->lon_deg,
+                               in->speed_mps, feat ? L.pay : nullptr, nn, L.table, mask, L.meta, L.K0, L.hist, soff, S);
         radix_scan(L.hist, L.offs, MAX_PASSES, s);
-        // interleaved input: the payload packed per record for the fused gather
-        // (the kernel returns at once for input in runs)
-        if (feat)
-            hipLaunchKernelGGL(k_pay_pack, dim3(gs), dim3(256), 0, s, nn, L.meta, in->ts_ms, in->lat_deg,
-                               in->lon_deg, in->speed_mps, L.pay);
     }
     radix_passes(L.K0, L.K1, nullptr, L.V0, L.V1, nn, nullptr, &L.meta->key_bits, MAX_PASSES, L.offs, L.status,
                  L.meta->tickets, s, /*timed=*/true, &L.meta->ib);

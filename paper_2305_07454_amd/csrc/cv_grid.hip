@@ -275,7 +275,6 @@ __global__ void __launch_bounds__(ECB) k_gpart_emit(const GridMeta* meta, const 
                                                     float* __restrict__ o_max, u64* __restrict__ go, u32 S, u32 kb,
                                                     u64 kmask, cv_result* res)
 {
-    __shared__ u32 s_t[ECB / WAVE];
     const u32 P = meta->compact_n;
     const u32 G = meta->groups;
     const u32 chunks = meta->chunks;
@@ -295,38 +294,56 @@ __global__ void __launch_bounds__(ECB) k_gpart_emit(const GridMeta* meta, const 
         if (go && (P == 0 || !sharded))  // no groups, or one problem: shard 0 holds every row
             for (u32 s = 0; s <= S; ++s) go[s] = s == 0 ? 0u : G;
     }
+    // A chunk's ECH pairs are taken in ECP rows of ECB: thread t has pairs
+    // c * ECH + k * ECB + t, so the heads of a row write consecutive output
+    // rows (coalesced stores), and each thread still issues its ECP gathers
+    // of first partials together.
+    __shared__ u32 s_rw[ECP][ECB / WAVE];
+    const int t = threadIdx.x, lane = lane_id(), w = t / WAVE;
     for (u32 c = blockIdx.x; c < chunks; c += gridDim.x) {
-        const u64 i0 = (u64)c * ECH + (u64)threadIdx.x * ECP;
-        u64 key[ECP];
+        const u64 ic = (u64)c * ECH;
+        u64 key[ECP], kprev[ECP];
         u32 hb = 0;
-        u64 prev = (i0 > 0 && i0 < P) ? K[i0 - 1] : ~0ull;
 #pragma unroll
         for (int k = 0; k < ECP; ++k) {
-            const u64 i = i0 + k;
+            const u64 i = ic + (u64)k * ECB + t;
             key[k] = i < P ? K[i] : 0ull;
-            if (i < P && (i == 0 || key[k] != prev)) hb |= 1u << k;
-            if (i < P) prev = key[k];
+            kprev[k] = (i > 0 && i < P) ? K[i - 1] : ~0ull;
         }
-        // the key after this thread's pairs: does the last group go on?
-        const u64 knext = i0 + ECP < P ? K[i0 + ECP] : ~0ull;
-        u32 tot;
-        const u32 row0 = block_exclusive_sum<ECB>((u32)__popc(hb), s_t, tot) + hoff[c];
+#pragma unroll
+        for (int k = 0; k < ECP; ++k) {
+            const u64 i = ic + (u64)k * ECB + t;
+            const bool h = i < P && (i == 0 || key[k] != kprev[k]);
+            if (h) hb |= 1u << k;
+            const u64 bm = __ballot(h);
+            if (lane == 0) s_rw[k][w] = (u32)__popcll(bm);
+        }
         // every head's first partial, the gathers issued together
         u32 vv[ECP];
         GPart pf[ECP];
 #pragma unroll
-        for (int k = 0; k < ECP; ++k) vv[k] = ((hb >> k) & 1u) ? V[i0 + k] : 0u;
+        for (int k = 0; k < ECP; ++k) vv[k] = ((hb >> k) & 1u) ? V[ic + (u64)k * ECB + t] : 0u;
 #pragma unroll
         for (int k = 0; k < ECP; ++k)
             if ((hb >> k) & 1u) pf[k] = part[vv[k]];
-        u32 row = row0;
+        __syncthreads();
+        u32 rbase = hoff[c];
 #pragma unroll
         for (int k = 0; k < ECP; ++k) {
+            const u64 i = ic + (u64)k * ECB + t;
+            u32 before = 0, rowt = 0;
+#pragma unroll
+            for (int x = 0; x < ECB / WAVE; ++x) {
+                const u32 v = s_rw[k][x];
+                before += x < w ? v : 0u;
+                rowt += v;
+            }
+            const u32 row = rbase + before + popc_below(__ballot((hb >> k) & 1u));
+            rbase += rowt;
             if (!((hb >> k) & 1u)) continue;
-            const u64 i = i0 + k;
             if (sharded) {
                 const u32 sh = (u32)(key[k] >> kb);
-                const long ps = i == 0 ? -1 : (long)(K[i - 1] >> kb);
+                const long ps = i == 0 ? -1 : (long)(kprev[k] >> kb);
                 for (long s2 = ps + 1; s2 <= (long)sh; ++s2) go[s2] = row;
             }
             if (row < cap) {
@@ -338,15 +355,14 @@ __global__ void __launch_bounds__(ECB) k_gpart_emit(const GridMeta* meta, const 
                 u32 mn = ~0u, mx = 0;
                 i64 pj = pr.jid;
                 u64 j = i;
-                // the group's next pair: after the first, from this thread's keys
-                bool more = j + 1 < P && (k + 1 < ECP ? key[k + 1 < ECP ? k + 1 : 0] : knext) == key[k];
+                bool more = j + 1 < P && K[j + 1] == key[k];
                 for (;;) {
                     cnt += pr.cn & ~PART_ODD;
                     nj += (j == i || pr.jid != pj) ? 1u : 0u;
                     pj = pr.jid;
-                    const Fx192 t = (pr.cn & PART_ODD) ? fx_from_double<FX_SPD>((double)__uint_as_float(pr.s[0]))
-                                                       : part_sum192(pr);
-                    fx_add(sum, t);
+                    const Fx192 tt = (pr.cn & PART_ODD) ? fx_from_double<FX_SPD>((double)__uint_as_float(pr.s[0]))
+                                                        : part_sum192(pr);
+                    fx_add(sum, tt);
                     mn = pr.mn < mn ? pr.mn : mn;
                     mx = pr.mx > mx ? pr.mx : mx;
                     if (!more) break;
@@ -361,9 +377,8 @@ __global__ void __launch_bounds__(ECB) k_gpart_emit(const GridMeta* meta, const 
                 o_min[row] = unord_f32(mn);
                 o_max[row] = unord_f32(mx);
             }
-            ++row;
         }
-        if (sharded && P > 0 && i0 <= (u64)P - 1 && (u64)P - 1 < i0 + ECP) {
+        if (sharded && P > 0 && (u64)P - 1 >= ic && (u64)P - 1 < ic + ECH && ((u64)P - 1 - ic) % ECB == (u64)t) {
             // the last pair: the shards after the last group's shard start at G
             const u32 sh = (u32)(K[P - 1] >> kb);
             for (u32 s2 = sh + 1; s2 <= S; ++s2) go[s2] = G;

@@ -366,18 +366,16 @@ __device__ __forceinline__ u32 dict_rank_from(const u64* table, u64 mask, u64 ke
 }
 
 constexpr int PW = 8;
-// Keys of every record with the digit histograms of every pass.  A round takes
-// PW windows whose columns are loaded together.  Two forms, launched one after
-// the other, of which one returns at once: for input in long runs of equal ids
-// (IL = false) a run head probes the dictionary where it meets it; for
-// interleaved input (IL = true), where nearly every record starts a run, every
-// run head of the round that misses the wave's cache issues its first probe
-// before any is used, and the pass also writes the payload packed per record
-// for the gather.
-template <bool SHARDS, bool IL>
-__global__ void __launch_bounds__(256) k_pack_hist(const i64* __restrict__ jid, const i64* __restrict__ ts,
-                                                   const double* __restrict__ lat, const double* __restrict__ lon,
-                                                   const float* __restrict__ spd, PayRec* __restrict__ pay, u32 n,
+// Keys of every record with the digit histograms of every pass, for input in
+// long runs of equal ids: each wave walks its own contiguous range of windows
+// of 64 records, PW windows per round with their ids and times loaded
+// together; the (id, rank) of a window's last record carries into the next
+// window, so the dictionary is probed only where a run of equal ids starts
+// (through the wave's cache), and the shard (batched form) is followed
+// forward from the range's first one.  Returns at once for interleaved input
+// (k_pack_il takes it).
+template <bool SHARDS>
+__global__ void __launch_bounds__(256) k_pack_hist(const i64* __restrict__ jid, const i64* __restrict__ ts, u32 n,
                                                    const u64* __restrict__ table, u64 mask, SortMeta* m,
                                                    u64* __restrict__ keys, u32* __restrict__ hist,
                                                    const u64* __restrict__ soff, u32 S)
@@ -386,7 +384,7 @@ __global__ void __launch_bounds__(256) k_pack_hist(const i64* __restrict__ jid, 
     // per-wave cache of (id, rank) pairs, as in the dictionary insert
     __shared__ u64 c_key[4][DCP];
     __shared__ u32 c_rank[4][DCP], c_own[4][DCP];
-    if (pay_packed(m, n) != IL) return;
+    if (pay_packed(m, n)) return;
     for (int i = threadIdx.x; i < MAX_PASSES * RADIX; i += blockDim.x) s_h[i] = 0;
     for (int i = threadIdx.x; i < 4 * DCP; i += blockDim.x) (&c_key[0][0])[i] = EMPTY;
     __syncthreads();
@@ -397,9 +395,7 @@ __global__ void __launch_bounds__(256) k_pack_hist(const i64* __restrict__ jid, 
     const bool bad = m->range_err != 0;
     const u32 ib = m->ib;
     const bool packed = m->p0 == 0;
-    const bool wpay = IL && pay;
     const u64 tmin = (u64)unord_i64(m->tmin_ord);
-    const ulonglong2* t2 = (const ulonglong2*)table;
     const int l = lane_id();
     const u64 nw = (u64)gridDim.x * (blockDim.x / WAVE);
     const u64 nwin = ((u64)n + WAVE - 1) / WAVE;
@@ -421,89 +417,36 @@ __global__ void __launch_bounds__(256) k_pack_hist(const i64* __restrict__ jid, 
             jv[k] = (u64)jid[i];
             tv[k] = (u64)ts[i];
         }
-        if (IL && wpay) {
-            // the payload of the round's records, packed (loads issued together)
-            double la[PW], lo[PW];
-            float sp[PW];
-#pragma unroll
-            for (int k = 0; k < PW; ++k) {
-                u64 i = (w0 + k) * WAVE + l;
-                i = i < n ? i : (u64)n - 1;
-                la[k] = lat[i];
-                lo[k] = lon[i];
-                sp[k] = spd[i];
-            }
-#pragma unroll
-            for (int k = 0; k < PW; ++k) {
-                const u64 i = (w0 + k) * WAVE + l;
-                if (w0 + k < wend && i < n) {
-                    ulonglong2* q = (ulonglong2*)(pay + i);
-                    q[0] = make_ulonglong2(tv[k], (u64)__double_as_longlong(la[k]));
-                    q[1] = make_ulonglong2((u64)__double_as_longlong(lo[k]), (u64)__float_as_uint(sp[k]));
-                }
-            }
-        }
-        // run heads of every window, their cached ranks, and the first probe
-        // of every miss, issued together
-        bool look[PW], miss[PW];
-        u32 rk[PW];
-        ulonglong2 pe[PW];
-        u64 ph[PW];
-#pragma unroll
-        for (int k = 0; k < PW; ++k) {
-            look[k] = miss[k] = false;
-            rk[k] = 0;
-            if constexpr (!IL) continue;
-            const u64 i = (w0 + k) * WAVE + l;
-            const bool valid = w0 + k < wend && i < n;
-            const u64 j = valid ? jv[k] : EMPTY;
-            const u64 jp = __shfl_up(j, 1, WAVE);
-            const u64 jl = k == 0 ? cj : __shfl(k == 0 ? 0ull : jv[k > 0 ? k - 1 : 0], WAVE - 1, WAVE);
-            const bool prev = k == 0 ? hc : true;
-            const bool runhead = l == 0 ? !(prev && j == jl) : j != jp;
-            look[k] = valid && runhead && j != EMPTY;
-            const u32 cs = dict_cache_slot<DCP>(j);
-            miss[k] = false;
-            rk[k] = 0;
-            if (look[k]) {
-                if (c_key[wv_][cs] == j) rk[k] = c_rank[wv_][cs];
-                else miss[k] = true;
-            }
-            ph[k] = mix64(j) & mask;
-            if (miss[k]) pe[k] = t2[ph[k]];
-        }
 #pragma unroll
         for (int k = 0; k < PW; ++k) {
             const u64 wi = w0 + k;
             if (wi >= wend) break;
             const u64 i = wi * WAVE + l;
             const bool valid = i < n;
+            // only the first lane of each run of equal ids probes the dictionary;
+            // the others take its rank (lane 0 continues the carried run)
             const u64 j = valid ? jv[k] : EMPTY;
             const u64 jp = __shfl_up(j, 1, WAVE);
             const bool runhead = l == 0 ? !(hc && j == cj) : j != jp;
-            u32 r = rk[k];
+            u32 r = 0;
+            const bool look = valid && runhead && j != EMPTY;
             const u32 cs = dict_cache_slot<DCP>(j);
-            if constexpr (IL) {
-                if (miss[k]) r = dict_rank_from(table, mask, j, ph[k], pe[k]);
-            } else {
-                // the cache, then the table, where a run starts
-                if (valid && runhead && j != EMPTY) {
-                    if (c_key[wv_][cs] == j) r = c_rank[wv_][cs];
-                    else {
-                        r = dict_rank_of(table, mask, j);
-                        miss[k] = true;
-                    }
+            bool miss = false;
+            if (look) {
+                if (c_key[wv_][cs] == j) {
+                    r = c_rank[wv_][cs];
+                } else {
+                    r = dict_rank_of(table, mask, j);
+                    miss = true;
                 }
             }
-            if (miss[k]) c_own[wv_][cs] = (u32)l;
+            if (miss) c_own[wv_][cs] = (u32)l;
             __builtin_amdgcn_wave_barrier();
-            if (miss[k] && c_own[wv_][cs] == (u32)l) {
+            if (miss && c_own[wv_][cs] == (u32)l) {
                 c_key[wv_][cs] = j;
                 c_rank[wv_][cs] = r;
             }
             __builtin_amdgcn_wave_barrier();
-            // only the first lane of each run of equal ids looked its rank up;
-            // the others take it (lane 0 continues the carried run)
             const u64 heads = __ballot(runhead);
             const u64 upto = heads & (~0ull >> (63 - l));  // run starts at or below this lane
             const u32 rh = __shfl(r, upto ? 63 - __clzll((long long)upto) : 0, WAVE);
@@ -536,6 +479,193 @@ __global__ void __launch_bounds__(256) k_pack_hist(const i64* __restrict__ jid, 
                 }
             }
         }
+    }
+    __syncthreads();
+    for (u32 i = threadIdx.x; i < np * RADIX; i += blockDim.x)
+        if (s_h[i]) atomicAdd(&hist[i], s_h[i]);
+}
+
+// Keys and digit histograms for interleaved input (short runs of equal ids, as
+// in a time-ordered feed), where nearly every record probes the dictionary:
+// every block takes a contiguous range of tiles of PT records, and each
+// record's first probe is issued with the tile's others before any is used.
+// With `pay` (the fused gather), the tile's records are also regrouped
+// by the low byte of their journey rank (a stable local multisplit, so equal
+// keys keep their input order): the key words and the packed payloads go to
+// the regrouped positions, and each payload carries its input index.  After
+// the sort, consecutive records of a journey then read consecutive payloads
+// of each tile instead of one cache line per record.
+constexpr int PT_B = 512;                // threads per block
+constexpr int PT_I = 4;                  // records per thread
+constexpr int PT = PT_B * PT_I;          // records per tile
+template <bool SHARDS>
+__global__ void __launch_bounds__(PT_B) k_pack_il(const i64* __restrict__ jid, const i64* __restrict__ ts,
+                                                 const double* __restrict__ lat, const double* __restrict__ lon,
+                                                 const float* __restrict__ spd, PayRec* __restrict__ pay, u32 n,
+                                                 const u64* __restrict__ table, u64 mask, SortMeta* m,
+                                                 u64* __restrict__ keys, u32* __restrict__ hist,
+                                                 const u64* __restrict__ soff, u32 S)
+{
+    constexpr int NW = PT_B / WAVE;
+    __shared__ u32 s_h[MAX_PASSES * RADIX];
+    __shared__ u64 c_key[NW][DCP];
+    __shared__ u32 c_rank[NW][DCP], c_own[NW][DCP];
+    __shared__ uint16_t s_whist[NW][RADIX];  // per-wave digit counts, then offsets
+    __shared__ u32 s_start[RADIX];
+    __shared__ u32 s_tmp[NW];
+    if (!pay_packed(m, n)) return;
+    for (int i = threadIdx.x; i < MAX_PASSES * RADIX; i += blockDim.x) s_h[i] = 0;
+    for (int i = threadIdx.x; i < NW * DCP; i += blockDim.x) (&c_key[0][0])[i] = EMPTY;
+    const int w = threadIdx.x / WAVE;
+    const int l = lane_id();
+    const u32 tb = m->t_bits;
+    const bool tdrop = m->ts_dropped != 0;
+    const u32 np = m->passes;
+    const bool bad = m->range_err != 0;
+    const u32 ib = m->ib;
+    const bool packed = m->p0 == 0;
+    const bool group = pay != nullptr;
+    const u32 rbits = m->rank_bits;
+    const u64 tmin = (u64)unord_i64(m->tmin_ord);
+    const ulonglong2* t2 = (const ulonglong2*)table;
+    const u64 tiles = ((u64)n + PT - 1) / PT;
+    const u64 per = (tiles + gridDim.x - 1) / gridDim.x;
+    const u64 tb0 = (u64)blockIdx.x * per;
+    const u64 tb1 = tb0 + per < tiles ? tb0 + per : tiles;
+    u32 shw = (SHARDS && tb0 < tb1) ? shard_of(soff, S, tb0 * PT) : 0u;
+    for (u64 tile = tb0; tile < tb1; ++tile) {
+        const u64 base = tile * PT + (u64)w * (PT_I * WAVE);  // this wave's 512 records
+        for (int i = l; i < RADIX; i += WAVE) s_whist[w][i] = 0;
+        __syncthreads();
+        u64 jv[PT_I], tv[PT_I];
+        double la[PT_I], lo[PT_I];
+        float sp[PT_I];
+#pragma unroll
+        for (int k = 0; k < PT_I; ++k) {
+            u64 i = base + (u64)k * WAVE + l;
+            i = i < n ? i : (u64)n - 1;  // past the end: a valid record, not used
+            jv[k] = (u64)jid[i];
+            tv[k] = (u64)ts[i];
+            if (group) {
+                la[k] = lat[i];
+                lo[k] = lon[i];
+                sp[k] = spd[i];
+            }
+        }
+        // ranks: the wave's cache, else the first probe of every miss issued together
+        u32 rk[PT_I];
+        bool miss[PT_I];
+        u64 ph[PT_I];
+        ulonglong2 pe[PT_I];
+#pragma unroll
+        for (int k = 0; k < PT_I; ++k) {
+            const u64 i = base + (u64)k * WAVE + l;
+            const u64 j = jv[k];
+            const bool look = i < n && j != EMPTY;  // the INT64_MIN id has rank 0
+            const u32 cs = dict_cache_slot<DCP>(j);
+            rk[k] = 0;
+            miss[k] = false;
+            if (look) {
+                if (c_key[w][cs] == j) rk[k] = c_rank[w][cs];
+                else miss[k] = true;
+            }
+            ph[k] = mix64(j) & mask;
+            if (miss[k]) pe[k] = t2[ph[k]];
+        }
+#pragma unroll
+        for (int k = 0; k < PT_I; ++k) {
+            const u64 j = jv[k];
+            const u32 cs = dict_cache_slot<DCP>(j);
+            if (miss[k]) {
+                rk[k] = dict_rank_from(table, mask, j, ph[k], pe[k]);
+                c_own[w][cs] = (u32)l;
+            }
+            __builtin_amdgcn_wave_barrier();
+            if (miss[k] && c_own[w][cs] == (u32)l) {
+                c_key[w][cs] = j;
+                c_rank[w][cs] = rk[k];
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        // keys, histograms and the local multisplit by the rank's low byte
+        u64 key[PT_I];
+        u32 rnk[PT_I];
+#pragma unroll
+        for (int k = 0; k < PT_I; ++k) {
+            const u64 i = base + (u64)k * WAVE + l;
+            const bool valid = i < n;
+            key[k] = 0;
+            if (valid && !bad) {
+                key[k] = tdrop ? (u64)rk[k] : ((tb >= 64 ? 0ull : ((u64)rk[k] << tb)) | (tv[k] - tmin));
+                if (SHARDS) {
+                    shw = __builtin_amdgcn_readfirstlane(shard_from(soff, S, shw, base + (u64)k * WAVE));
+                    const u32 sh = shard_from(soff, S, shw, i);
+                    key[k] |= (u64)sh << (rbits + tb);
+                }
+            }
+            const u64 vm = __ballot(valid);
+            const int lead = vm ? __ffsll((long long)vm) - 1 : 0;
+            for (u32 p = 0; p < np; ++p) {
+                const u32 d = (u32)(key[k] >> (p * RADIX_BITS)) & (RADIX - 1);
+                const u32 d0 = __shfl(d, lead, WAVE);
+                if (__ballot(valid && d != d0) == 0) {
+                    if (l == lead && vm) atomicAdd(&s_h[p * RADIX + d0], (u32)__popcll(vm));
+                } else if (valid) {
+                    atomicAdd(&s_h[p * RADIX + d], 1u);
+                }
+            }
+            rnk[k] = 0;
+            if (group) {
+                const u32 d = rk[k] & (RADIX - 1);
+                u64 peers = vm;
+#pragma unroll
+                for (int b = 0; b < RADIX_BITS; ++b) {
+                    const bool bit = (d >> b) & 1u;
+                    const u64 bal = __ballot(bit);
+                    peers &= bit ? bal : ~bal;
+                }
+                const u32 below = popc_below(peers);
+                const u32 cnt = (u32)__popcll(peers);
+                const u32 before = valid ? (u32)s_whist[w][d] : 0u;
+                rnk[k] = before + below;
+                __builtin_amdgcn_wave_barrier();
+                if (valid && below == cnt - 1) s_whist[w][d] = (uint16_t)(before + cnt);
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+        if (group) {
+            __syncthreads();
+            // per digit: offsets of the waves, and the tile's digit starts
+            u32 tcount = 0;
+            if (threadIdx.x < RADIX) {
+                const int d = threadIdx.x;
+#pragma unroll
+                for (int ww = 0; ww < NW; ++ww) {
+                    const u32 c = s_whist[ww][d];
+                    s_whist[ww][d] = (uint16_t)tcount;
+                    tcount += c;
+                }
+            }
+            u32 total;
+            const u32 st = block_exclusive_sum<PT_B>(threadIdx.x < RADIX ? tcount : 0u, s_tmp, total);
+            if (threadIdx.x < RADIX) s_start[threadIdx.x] = st;
+            __syncthreads();
+        }
+#pragma unroll
+        for (int k = 0; k < PT_I; ++k) {
+            const u64 i = base + (u64)k * WAVE + l;
+            if (i >= n) continue;
+            u64 at = i;
+            if (group) {
+                const u32 d = rk[k] & (RADIX - 1);
+                at = tile * PT + s_start[d] + s_whist[w][d] + rnk[k];
+                ulonglong2* q = (ulonglong2*)(pay + at);
+                q[0] = make_ulonglong2(tv[k], (u64)__double_as_longlong(la[k]));
+                q[1] = make_ulonglong2((u64)__double_as_longlong(lo[k]), (u64)__float_as_uint(sp[k]) | (i << 32));
+            }
+            keys[at] = packed ? ((key[k] << ib) | at) : key[k];
+        }
+        __syncthreads();
     }
     __syncthreads();
     for (u32 i = threadIdx.x; i < np * RADIX; i += blockDim.x)
@@ -807,6 +937,10 @@ __global__ void __launch_bounds__(256) k_gather_feat(u32 n, const SortMeta* m, c
     float osp[NS];
     i64 oj[NS], ot[NS];
     i64 pts[NS];  // time stamps read with the packed payload
+    // the input index of each sorted record: the sort's value, or, with the
+    // packed payload (whose positions the key packing regrouped), the index
+    // the payload carries
+    u32 src[NS];
     const bool packed = pay_packed(m, n);
     if (packed) {
 #pragma unroll
@@ -817,8 +951,11 @@ __global__ void __launch_bounds__(256) k_gather_feat(u32 n, const SortMeta* m, c
             ola[u] = __longlong_as_double((long long)a.y);
             olo[u] = __longlong_as_double((long long)b.x);
             osp[u] = __uint_as_float((u32)b.y);
+            src[u] = (u32)(b.y >> 32);
         }
     } else {
+#pragma unroll
+        for (int u = 0; u < NS; ++u) src[u] = vv[u];
 #pragma unroll
         for (int u = 0; u < NS; ++u) {
             ola[u] = lat[vv[u]];
@@ -835,7 +972,7 @@ __global__ void __launch_bounds__(256) k_gather_feat(u32 n, const SortMeta* m, c
         }
     } else {
 #pragma unroll
-        for (int u = 0; u < NS; ++u) oj[u] = jid[vv[u]];
+        for (int u = 0; u < NS; ++u) oj[u] = jid[src[u]];
     }
     if (ts_in_key) {
 #pragma unroll
@@ -859,7 +996,7 @@ __global__ void __launch_bounds__(256) k_gather_feat(u32 n, const SortMeta* m, c
     for (int u = 0; u < GFI; ++u) {
         const long k = kk[u];
         if (k < (long)n) {
-            if (!SHARDS) perm[k] = vv[u];
+            if (!SHARDS) perm[k] = src[u];
             so.journey_id[k] = oj[u];
             so.ts_ms[k] = ot[u];
             so.lat_deg[k] = ola[u];
@@ -893,7 +1030,7 @@ __global__ void __launch_bounds__(256) k_gather_feat(u32 n, const SortMeta* m, c
         shs[u] = 0;
         if (SHARDS && kk[u] < (long)n) {
             shs[u] = shard_from(soff, S, s_sh0, (u64)kk[u]);
-            perm[kk[u]] = vv[u] - (u32)soff[shs[u]];
+            perm[kk[u]] = src[u] - (u32)soff[shs[u]];
         }
     }
     // steps (k - 1 -> k) of the tile's records; thread 0 also takes the step
@@ -1017,11 +1154,12 @@ static cv_status sort_impl(const cv_records* in, const uint64_t* soff, uint32_t 
                            L.table, mask);
         // interleaved input (short runs of equal ids): the payload packed per
         // record for the fused gather, in the same pass
-        for (const bool il : {false, true})
-            hipLaunchKernelGGL(S > 1 ? (il ? k_pack_hist<true, true> : k_pack_hist<true, false>)
-                                     : (il ? k_pack_hist<false, true> : k_pack_hist<false, false>),
-                               dim3(gs), dim3(256), 0, s, in->journey_id, in->ts_ms, in->lat_deg, in->lon_deg,
-                               in->speed_mps, feat ? L.pay : nullptr, nn, L.table, mask, L.meta, L.K0, L.hist, soff, S);
+        hipLaunchKernelGGL(S > 1 ? k_pack_hist<true> : k_pack_hist<false>, dim3(gs), dim3(256), 0, s, in->journey_id,
+                           in->ts_ms, nn, L.table, mask, L.meta, L.K0, L.hist, soff, S);
+        hipLaunchKernelGGL(S > 1 ? k_pack_il<true> : k_pack_il<false>, dim3(cvh::grid_for(n, PT, 2048)), dim3(PT_B), 0,
+                           s, in->journey_id,
+                           in->ts_ms, in->lat_deg, in->lon_deg, in->speed_mps, feat ? L.pay : nullptr, nn, L.table,
+                           mask, L.meta, L.K0, L.hist, soff, S);
         radix_scan(L.hist, L.offs, MAX_PASSES, s);
     }
     radix_passes(L.K0, L.K1, nullptr, L.V0, L.V1, nn, nullptr, &L.meta->key_bits, MAX_PASSES, L.offs, L.status,

@@ -26,7 +26,7 @@ using namespace cv;
 namespace {
 
 constexpr int SB = 256;
-constexpr int SI = 16;
+constexpr int SI = 64;
 constexpr int ST = SB * SI;
 constexpr int FX_DIST = SUM_FX_DIST;  // distance: 2^-128 m resolution (exact for steps >= 2^-75 m)
 constexpr int FX_SPD = SUM_FX_SPD;    // speed: exact for every float32
@@ -102,18 +102,22 @@ __global__ void __launch_bounds__(SB) k_sum_count_flags(const uint8_t* __restric
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     const u64 cs = (u64)blockIdx.x * ST + (u64)w * WCH;
     const u64 ce = cs + WCH < n ? cs + WCH : (u64)n;
-    static_assert(WCH == WAVE * 16 && CV_FLAG_FIRST == 1u, "16 flag bytes per lane; FIRST is bit 0");
+    constexpr int FB = WCH / WAVE;  // flag bytes per lane
+    static_assert(FB % 16 == 0 && CV_FLAG_FIRST == 1u, "whole 16-byte loads per lane; FIRST is bit 0");
     u32 c = 0;
     if (cs < ce) {
-        // lane l counts the chunk's bytes [16 l, 16 l + 16): one 16-byte load
+        // lane l counts the chunk's bytes [FB l, FB l + FB): 16-byte loads
         // when the chunk is whole and the column 16-byte aligned
-        const u64 b0 = cs + (u64)lane_id() * 16;
+        const u64 b0 = cs + (u64)lane_id() * FB;
         if (ce - cs == (u64)WCH && ((uintptr_t)flags & 15u) == 0) {
-            const uint4 v = *reinterpret_cast<const uint4*>(flags + b0);
-            c = (u32)(__popc(v.x & 0x01010101u) + __popc(v.y & 0x01010101u) + __popc(v.z & 0x01010101u) +
-                      __popc(v.w & 0x01010101u));
+#pragma unroll
+            for (int q = 0; q < FB / 16; ++q) {
+                const uint4 v = *reinterpret_cast<const uint4*>(flags + b0 + 16 * q);
+                c += (u32)(__popc(v.x & 0x01010101u) + __popc(v.y & 0x01010101u) + __popc(v.z & 0x01010101u) +
+                           __popc(v.w & 0x01010101u));
+            }
         } else {
-            for (int k = 0; k < 16; ++k)
+            for (int k = 0; k < FB; ++k)
                 if (b0 + k < ce) c += flags[b0 + k] & CV_FLAG_FIRST;
         }
 #pragma unroll

@@ -230,7 +230,8 @@ def bench_batched(args, steps):
         "roofline": roof_b,
         "stages_ms_per_step": stages_b,
         "path_roofline": path_roofline(stages_b, n, G, rs_b["key_bits"], rs_b["packed_pass"], ms_batched,
-                                       design_bytes=317),
+                                       design_bytes=317, digit_bits=int(cvetl.cv_tuning_get("radix_bits")),
+                                       interleaved=True, ts_in_key=False),
         "key_bits": rs_b["key_bits"],
         "packed_from_pass": rs_b["packed_pass"],
     }
@@ -453,7 +454,8 @@ def bench_plain(args, workload):
         "cpu_baseline": cpu,
         "stages_ms_per_step": stages,
         "path_roofline": path_roofline(stages, n, G, key_bits, p0, ms_step,
-                                       design_bytes=282 if workload == "c1" else None),
+                                       design_bytes=282 if workload == "c1" else None,
+                                       digit_bits=int(cvetl.cv_tuning_get("radix_bits"))),
         "direction_lattice": direction,
         "dense_lattice": lattice,
         "key_bits": key_bits,
@@ -659,7 +661,8 @@ def radix_roofline(cvetl, n, rs, traffic=None):
     HIP-event timing families (working passes only: digits below the key
     width)."""
     key_bits = rs["key_bits"]
-    passes = (key_bits + 7) // 8
+    db = int(cvetl.cv_tuning_get("radix_bits"))
+    passes = (key_bits + db - 1) // db
     p0 = rs["packed_pass"]
     pass_ms, launches, alg = 0.0, 0, 0.0
     per_pass = []
@@ -672,7 +675,7 @@ def radix_roofline(cvetl, n, rs, traffic=None):
     avg_ms = pass_ms / max(launches, 1)
     per_launch = alg / max(launches, 1)
     achieved = per_launch / (avg_ms / 1e3) / 1e9 if avg_ms > 0 else 0.0
-    return {"bound": "hbm", "kernel": "k_radix_pass (stable 8-bit LSD scatter pass)",
+    return {"bound": "hbm", "kernel": f"k_radix_pass (stable {db}-bit LSD scatter pass)",
             "tile_keys": cvetl.cv_tuning_get("sort_tile"),
             "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -680,16 +683,22 @@ def radix_roofline(cvetl, n, rs, traffic=None):
             "alg_bytes_per_launch": int(per_launch), "per_pass_ms": per_pass}, pass_ms
 
 
-def path_roofline(stages, n, G, key_bits, p0, ms_step, design_bytes=None):
+def path_roofline(stages, n, G, key_bits, p0, ms_step, design_bytes=None, digit_bits=8, interleaved=False,
+                  ts_in_key=True):
     """Algorithmic bytes of the whole path per step (the per-record figures of
     each stage's kernels, plus the group tail) over the measured step time.
     design_bytes: the fixed per-record byte budget of the path's design (the
-    same for any implementation of it), reported beside as a second fraction."""
-    passes = (key_bits + 7) // 8
-    ts_read = 0 if p0 == 0 else 8  # the time offset survives in the final word only when nothing was dropped
-    per = {"sort_prep": 16 + 24, "sort_passes": sum(pass_bytes(p, p0) for p in range(passes))}
+    same for any implementation of it), reported beside as a second fraction.
+    interleaved: input with short runs of equal ids, for which the key packing
+    also writes a 32-byte payload per record that the fused gather reads
+    instead of the columns.  ts_in_key: the sort key holds the time offset."""
+    passes = (key_bits + digit_bits - 1) // digit_bits
+    # the time offset survives in the final word only when nothing was dropped
+    ts_read = 0 if (p0 == 0 and ts_in_key) else 8
+    per = {"sort_prep": 16 + 24 + ((20 + 32) if interleaved and "gather_features" in stages else 0),
+           "sort_passes": sum(pass_bytes(p, p0) for p in range(passes))}
     if "gather_features" in stages:
-        per["gather_features"] = 8 + ts_read + 20 + 4 + 36 + 49
+        per["gather_features"] = 8 + (32 if interleaved else ts_read + 20) + 4 + 36 + 49
     else:
         per["gather"] = 8 + ts_read + 20 + 4 + 36
         per["features"] = 32 + 49

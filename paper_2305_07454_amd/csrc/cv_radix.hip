@@ -55,14 +55,15 @@ __global__ void __launch_bounds__(256) k_radix_hist(const u64* __restrict__ keys
         if (s_h[i]) atomicAdd(&hist[i], s_h[i]);
 }
 
-// Exclusive scan of each pass's 256 digit counts (one block of 256 threads).
-__global__ void __launch_bounds__(256) k_radix_scan(const u32* __restrict__ hist, u32* __restrict__ offs, int passes)
+// Exclusive scan of each pass's digit counts (one block, a thread per digit).
+__global__ void __launch_bounds__(RADIX) k_radix_scan(const u32* __restrict__ hist, u32* __restrict__ offs,
+                                                      int passes)
 {
-    __shared__ u32 tmp[256 / WAVE];
+    __shared__ u32 tmp[RADIX / WAVE];
     for (int p = 0; p < passes; ++p) {
         u32 total;
         u32 v = hist[p * RADIX + threadIdx.x];
-        u32 e = block_exclusive_sum<256>(v, tmp, total);
+        u32 e = block_exclusive_sum<RADIX>(v, tmp, total);
         offs[p * RADIX + threadIdx.x] = e;
     }
 }
@@ -273,7 +274,7 @@ void radix_hist(const u64* keys, u32 n_max, const u32* n_dev, int passes, const 
 
 void radix_scan(const u32* hist, u32* offs, int passes, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_radix_scan, dim3(1), dim3(256), 0, s, hist, offs, passes);
+    hipLaunchKernelGGL(k_radix_scan, dim3(1), dim3(RADIX), 0, s, hist, offs, passes);
 }
 
 namespace {
@@ -285,6 +286,7 @@ constexpr u64 DEVICE_COUNT_GRID = 2048;
 struct Shape {
     int block, items;
 };
+// (every shape has at least one thread per digit)
 constexpr Shape SHAPES[] = {{256, 16}, {256, 32}, {512, 8}, {512, 16}, {1024, 8}, {1024, 16}};
 constexpr int N_SHAPES = sizeof(SHAPES) / sizeof(SHAPES[0]);
 int g_shape = 0;
@@ -377,6 +379,7 @@ cv_status cv_tuning_get(const char* name, int64_t* value)
     if (n == "sort_shape") *value = cv::sort_shape();
     else if (n == "sort_shapes") *value = cv::sort_shape_count();
     else if (n == "sort_tile") *value = cv::sort_tile(cv::sort_shape());
+    else if (n == "radix_bits") *value = cv::RADIX_BITS;
     else if (n == "grid_lds_slots") *value = cv::grid_lds_slots();
     else return CV_ERR_INVALID_ARGUMENT;
     return CV_OK;

@@ -73,7 +73,8 @@ def sweep_sort_shapes(rec, grid, reps=5, log=print):
         cvetl.cv_tuning_set("sort_shape", sh)
         tile = cvetl.cv_tuning_get("sort_tile")
         perm, srt, r = cvetl.cv_sort_records(rec)          # warm-up and key width
-        passes = (r["key_bits"] + 7) // 8
+        db = int(cvetl.cv_tuning_get("radix_bits"))
+        passes = (r["key_bits"] + db - 1) // db
         torch.cuda.synchronize()
         cvetl.cv_timing_reset()
         cvetl.cv_timing_enable(True)

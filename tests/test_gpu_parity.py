@@ -272,13 +272,14 @@ def _wide_keys(seed, n, n_ids, tbits):
 def test_packed_radix_passes(cv, tbits):
     # 5000 records (13 index bits), 1000 ids (10 rank bits): the key has
     # 10 + tbits bits, and passes from the first digit boundary p0 with
-    # key_bits - 8 p0 + 13 <= 64 move packed (key | index) words
+    # key_bits - d p0 + 13 <= 64 (d-bit digits) move packed (key | index) words
     n, n_ids = 5000, 1000
     cols = _wide_keys(100 + tbits, n, n_ids, tbits)
     got, exp = _run_both(cv, cols, gen.GRIDS["c0"])
     _check_all(got, exp)
     kb = 10 + tbits
-    p0 = max(0, -(-(kb + 13 - 64) // 8))
+    db = cv.cv_tuning_get("radix_bits")
+    p0 = max(0, -(-(kb + 13 - 64) // db))
     assert got["sort_result"]["key_bits"] == kb
     assert got["sort_result"]["packed_pass"] == p0
 

@@ -360,8 +360,7 @@ def bench_plain(args, workload):
     else:
         from paper_2305_07454_amd import tune
         tune.apply(n, workload=workload)
-    log(f"sort shape {cvetl.cv_tuning_get('sort_shape')} (tile {cvetl.cv_tuning_get('sort_tile')} keys), "
-        f"grid LDS slots {cvetl.cv_tuning_get('grid_lds_slots')}")
+    log(f"sort shape {cvetl.cv_tuning_get('sort_shape')} (tile {cvetl.cv_tuning_get('sort_tile')} keys)")
     rec = cvetl.to_device(r, dev)
     torch.cuda.synchronize()
 

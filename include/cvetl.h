@@ -51,7 +51,7 @@ typedef enum {
     CV_ERR_INVALID_ARGUMENT = 1, /* null pointer, bad size or bad grid spec           */
     CV_ERR_WORKSPACE = 2,        /* ws NULL, misaligned or smaller than required       */
     CV_ERR_CAPACITY = 3,         /* (device) output rows exceed capacity; see required */
-    CV_ERR_RANGE = 4,            /* (device) packed sort key would exceed 64 bits      */
+    CV_ERR_RANGE = 4,            /* packed key or lattice index would overflow         */
     CV_ERR_DEVICE = 5,           /* a HIP launch or runtime call failed                */
     CV_ERR_UNSUPPORTED = 6       /* no gfx950 device / feature not available           */
 } cv_status;
@@ -516,9 +516,7 @@ cv_status cv_stream_destroy(cv_stream* st);
  *                  thread) used by every sort; 0 .. "sort_shapes" - 1.
  *   "sort_shapes"  number of compiled shapes (read-only).
  *   "sort_tile"    keys per tile of the current shape (read-only).
- *   "grid_lds_slots"  LDS hash slots per grid tile: 256, 512 or 1024 (more
- *                  slots hold more distinct cells per tile before spilling to
- *                  the HBM table, at the price of fewer resident tiles).
+ *   "radix_bits"   bits per radix digit of every sort (read-only).
  * Unknown names or out-of-range values return CV_ERR_INVALID_ARGUMENT.
  * --------------------------------------------------------------------- */
 cv_status cv_tuning_set(const char* name /*[host]*/, int64_t value);

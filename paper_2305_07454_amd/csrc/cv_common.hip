@@ -2,6 +2,7 @@
 // per-kernel-family timing used by the benchmark.
 #include <hip/hip_runtime.h>
 
+#include <cstring>
 #include <mutex>
 #include <string>
 #include <unordered_map>
@@ -122,7 +123,11 @@ uint32_t cv_abi_version(void) { return CV_ABI_VERSION; }
 
 const char* cv_strerror(cv_status s)
 {
-    switch (s) {
+    // C callers may pass any int; read it as one rather than as the enum,
+    // whose C++ value range ends at the largest enumerator's bit width.
+    int v;
+    std::memcpy(&v, &s, sizeof v);
+    switch (v) {
     case CV_OK: return "ok";
     case CV_ERR_INVALID_ARGUMENT: return "invalid argument";
     case CV_ERR_WORKSPACE: return "workspace missing, misaligned or too small";

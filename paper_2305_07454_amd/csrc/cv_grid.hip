@@ -387,8 +387,6 @@ __global__ void __launch_bounds__(ECB) k_gpart_emit(const GridMeta* meta, const 
     }
 }
 
-int g_lds_slots = 256;  // LDS hash slots per tile (tuning knob "grid_lds_slots")
-
 // out[k] = in[perm[k]]: a payload column in the sort's order (GU per round,
 // loads issued together)
 template <class T>
@@ -430,16 +428,6 @@ bool spec_ok(const cv_grid_spec* g)
 }
 
 }  // namespace
-
-namespace cv {
-bool set_grid_lds_slots(int v)
-{
-    if (v != 256 && v != 512 && v != 1024) return false;
-    g_lds_slots = v;
-    return true;
-}
-int grid_lds_slots() { return g_lds_slots; }
-}  // namespace cv
 
 // the tile kernel for a direction source (0 none, 1 heading column, 2 bearing)
 template <int KD>

@@ -357,8 +357,6 @@ void radix_passes(u64* k0, u64* k1, const u32* v_first, u32* v0, u32* v1, u32 n_
 }  // namespace cv
 
 namespace cv {
-bool set_grid_lds_slots(int v);
-int grid_lds_slots();
 }  // namespace cv
 
 extern "C" {
@@ -367,8 +365,11 @@ cv_status cv_tuning_set(const char* name, int64_t value)
 {
     if (!name) return CV_ERR_INVALID_ARGUMENT;
     const std::string n(name);
-    if (n == "sort_shape") return cv::set_sort_shape((int)value) ? CV_OK : CV_ERR_INVALID_ARGUMENT;
-    if (n == "grid_lds_slots") return cv::set_grid_lds_slots((int)value) ? CV_OK : CV_ERR_INVALID_ARGUMENT;
+    // range-checked as int64 before the narrowing, so 2^32 + i is not shape i
+    if (n == "sort_shape")
+        return value >= 0 && value < cv::sort_shape_count() && cv::set_sort_shape((int)value)
+                   ? CV_OK
+                   : CV_ERR_INVALID_ARGUMENT;
     return CV_ERR_INVALID_ARGUMENT;
 }
 
@@ -380,7 +381,6 @@ cv_status cv_tuning_get(const char* name, int64_t* value)
     else if (n == "sort_shapes") *value = cv::sort_shape_count();
     else if (n == "sort_tile") *value = cv::sort_tile(cv::sort_shape());
     else if (n == "radix_bits") *value = cv::RADIX_BITS;
-    else if (n == "grid_lds_slots") *value = cv::grid_lds_slots();
     else return CV_ERR_INVALID_ARGUMENT;
     return CV_OK;
 }

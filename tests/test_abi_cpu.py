@@ -96,3 +96,15 @@ def test_timing_registry_host_only(L):
     from paper_2305_07454_amd import cvetl
     cvetl.cv_timing_reset()
     assert cvetl.cv_timing_read("nothing") == (0.0, 0)
+
+
+def test_tuning_values_checked_before_narrowing(L):
+    # a 64-bit value whose low 32 bits name a valid shape is still refused
+    from paper_2305_07454_amd import cvetl
+    prev = ctypes.c_int64()
+    assert L.cv_tuning_get(b"sort_shape", ctypes.byref(prev)) == 0
+    for v in (1 << 32, (1 << 32) + 1, -(1 << 63), -1):
+        assert L.cv_tuning_set(b"sort_shape", ctypes.c_int64(v)) == cvetl.CV_ERR_INVALID_ARGUMENT
+    got = ctypes.c_int64()
+    assert L.cv_tuning_get(b"sort_shape", ctypes.byref(got)) == 0 and got.value == prev.value
+    assert L.cv_tuning_set(b"grid_lds_slots", ctypes.c_int64(256)) == cvetl.CV_ERR_INVALID_ARGUMENT

@@ -88,15 +88,9 @@ def test_direction_long_segments_every_lds_table(cv):
     rec = cv.to_device(cols)
     perm, srt, _ = cv.cv_sort_records(rec)
     hs = cv.cv_gather_column(torch.from_numpy(hd).cuda(), perm)
-    prev = cv.cv_tuning_get("grid_lds_slots")
-    try:
-        for slots in (256, 512, 1024):
-            cv.cv_tuning_set("grid_lds_slots", slots)
-            print(f"[direction] long segments, {slots} LDS slots", flush=True)
-            got, rg = cv.cv_grid_aggregate_dir(srt, spec, 4, 45.0, heading=hs)
-            check_groups(got, rg["n_out_of_grid"], exp, n_out)
-    finally:
-        cv.cv_tuning_set("grid_lds_slots", prev)
+    print("[direction] long segments", flush=True)
+    got, rg = cv.cv_grid_aggregate_dir(srt, spec, 4, 45.0, heading=hs)
+    check_groups(got, rg["n_out_of_grid"], exp, n_out)
 
 
 def test_direction_argument_errors(cv):

@@ -10,7 +10,8 @@ the compute stream frees up joins the next push (chunks that arrive while a
 push runs overlap with it on the device).  With the per-chunk policy each push
 takes one chunk.  Features go back device-to-host on a third stream.  A chunk's
 latency is the time its features are in host memory minus its scheduled
-arrival.
+arrival.  The loop (Server) drives the device through an executor (the
+copies, the push, event polls), so that it can be exercised with a stand-in.
 
 The host pool is replayed in cycles: cycle c shifts journey ids by c * 2^40,
 so every cycle brings new journeys (each with its timestamps in order, which
@@ -76,23 +77,26 @@ def arena_from_free_hbm(grid, max_journeys, max_groups, fraction=0.5, cap=64_000
     return max(1 << 20, min(cap, a))
 
 
-class Server:
-    def __init__(self, pool, grid, batching=True, arena_records=None, max_journeys=1 << 21,
-                 max_groups=1 << 23, device="cuda"):
-        """arena_records: records in the device ring; None carves it from the
-        free HBM (arena_from_free_hbm).  Chunks are admitted into the ring in
-        arrival order while it has room."""
+class ServeError(RuntimeError):
+    """A push (or its copies) failed; `cids` names the chunks of that push."""
+
+    def __init__(self, msg, cids):
+        super().__init__(msg)
+        self.cids = list(cids)
+
+
+class DeviceExecutor:
+    """The device side of the serving loop: the pinned host pool, the device
+    ring of record slots and feature slots, three streams (copies in, compute,
+    copies out) and the resident stream state.  The loop (Server) only calls
+    the methods below, each of which enqueues work or polls an event."""
+
+    def __init__(self, pool, grid, arena_records, max_journeys, max_groups, device):
         self.dev = torch.device(device)
-        self.grid = grid
-        self.batching = batching
-        if arena_records is None:
-            arena_records = arena_from_free_hbm(grid, max_journeys, max_groups, device=self.dev)
         self.A = int(arena_records)
         self.pool_n = pool.n
-        # pinned host pool
         self.h = {k: torch.from_numpy(np.ascontiguousarray(c)).pin_memory()
                   for (k, _), c in zip(cvetl.RECORD_FIELDS, pool.columns())}
-        # device arena (inputs and features) and pinned feature landing zone
         self.ring = {k: torch.empty(self.A, dtype=dt, device=self.dev) for k, dt in cvetl.RECORD_FIELDS}
         self.fring = {k: torch.empty(self.A, dtype=dt, device=self.dev) for k, dt in cvetl.FEATURE_FIELDS}
         self.hout = {k: torch.empty(self.A, dtype=dt).pin_memory() for k, dt in cvetl.FEATURE_FIELDS}
@@ -101,11 +105,9 @@ class Server:
         self.s_back = torch.cuda.Stream(self.dev)
         self.stream = cvetl.Stream(grid, max_journeys, max_groups, self.A, device=self.dev, stream=self.s_comp)
         self.res = cvetl.new_result(self.dev)
-        self.head = 0          # next free ring record
-        self.used = 0          # records reserved
-        self.keep = {}         # cid -> features copied out for checking
+        self._comp_ev = None
 
-    def _copy_in(self, c):
+    def copy_in(self, c):
         with torch.cuda.stream(self.s_copy):
             a, b = c.src, c.src + c.n
             for k, _ in cvetl.RECORD_FIELDS:
@@ -115,7 +117,13 @@ class Server:
             c.copy_ev = torch.cuda.Event()
             c.copy_ev.record(self.s_copy)
 
-    def _launch(self, batch):
+    def copy_done(self, c):
+        return c.copy_ev.query()
+
+    def compute_free(self):
+        return self._comp_ev is None or self._comp_ev.query()
+
+    def launch(self, batch):
         a = batch[0].slot
         n = sum(c.n for c in batch)
         assert a + n <= self.A
@@ -134,13 +142,56 @@ class Server:
         done.record(self.s_back)
         for c in batch:
             c.done_ev = done
-        return ev
+        self._comp_ev = ev
+
+    def done(self, c):
+        return c.done_ev.query()
+
+    def features(self, c):
+        return {k: v[c.slot:c.slot + c.n].clone() for k, v in self.hout.items()}
+
+    def finish(self):
+        torch.cuda.synchronize()
+
+    def flush(self, jcap, gcap):
+        with torch.cuda.stream(self.s_comp):
+            out = self.stream.flush(jcap, gcap, stream=self.s_comp)
+        torch.cuda.synchronize()
+        return out
+
+
+class Server:
+    def __init__(self, pool, grid, batching=True, arena_records=None, max_journeys=1 << 21,
+                 max_groups=1 << 23, device="cuda", executor=None, clock=time.perf_counter, sleep=time.sleep,
+                 idle=None):
+        """arena_records: records in the device ring; None carves it from the
+        free HBM (arena_from_free_hbm).  Chunks are admitted into the ring in
+        arrival order while it has room.  executor: the device side (a
+        DeviceExecutor by default); clock / sleep / idle: the loop's time
+        source, its wait for the next arrival, and what it does in a round
+        that made no progress (nothing: it polls again)."""
+        self.grid = grid
+        self.batching = batching
+        if executor is None:
+            if arena_records is None:
+                arena_records = arena_from_free_hbm(grid, max_journeys, max_groups, device=device)
+            executor = DeviceExecutor(pool, grid, arena_records, max_journeys, max_groups, device)
+        self.ex = executor
+        self.A = int(executor.A)
+        self.pool_n = pool.n
+        self.clock, self.sleep, self.idle = clock, sleep, idle
+        self.keep = {}         # cid -> features copied out for checking
 
     def run(self, trace, keep_first=0, log=None):
-        """Serve the trace (list of (arrival_s, size)); returns per-chunk records."""
+        """Serve the trace (list of (arrival_s, size)); returns per-chunk records.
+        A chunk larger than the ring can never be admitted: ValueError before
+        anything is served.  A failed push raises ServeError naming its chunks;
+        the chunks completed before it keep their completion times."""
         chunks, src, cyc = [], 0, 0
         for i, (t, size) in enumerate(trace):
-            size = min(size, self.pool_n, self.A)
+            if size > self.A:
+                raise ValueError(f"chunk {i} of {size} records exceeds the arena of {self.A}: never admissible")
+            size = min(size, self.pool_n)
             if src + size > self.pool_n:
                 src, cyc = 0, cyc + 1
             chunks.append(Chunk(i, src, size, cyc, t))
@@ -148,12 +199,12 @@ class Server:
         pending = collections.deque(chunks)
         copying = collections.deque()     # admitted, H2D issued
         inflight = collections.deque()    # admitted, not yet completed (ring order)
-        comp_ev = None
         launched = collections.deque()    # chunks launched, awaiting features on host
-        t0 = time.perf_counter()
+        t0 = self.clock()
         next_log = 1.0
         while pending or copying or launched:
-            now = time.perf_counter() - t0
+            now = self.clock() - t0
+            progress = False
             # admission (FIFO) by free arena space
             while pending and pending[0].arrival <= now:
                 c = pending[0]
@@ -161,14 +212,18 @@ class Server:
                 if slot < 0:
                     break
                 c.slot = slot
-                self._copy_in(c)
+                try:
+                    self.ex.copy_in(c)
+                except Exception as e:
+                    raise ServeError(f"copy of chunk {c.cid} failed: {e}", [c.cid]) from e
                 pending.popleft()
                 copying.append(c)
                 inflight.append(c)
+                progress = True
             # launch when the compute stream is free
-            if copying and (comp_ev is None or comp_ev.query()):
+            if copying and self.ex.compute_free():
                 ready = []
-                while copying and copying[0].copy_ev.query():
+                while copying and self.ex.copy_done(copying[0]):
                     c = copying[0]
                     if ready and (c.slot != ready[-1].slot + ready[-1].n):
                         break          # not contiguous in the ring (wrapped): next push
@@ -176,22 +231,30 @@ class Server:
                     if not self.batching:
                         break
                 if ready:
-                    comp_ev = self._launch(ready)
+                    try:
+                        self.ex.launch(ready)
+                    except Exception as e:
+                        raise ServeError(f"push of chunks {[c.cid for c in ready]} failed: {e}",
+                                         [c.cid for c in ready]) from e
                     launched.extend(ready)
+                    progress = True
             # completions (FIFO)
-            while launched and launched[0].done_ev.query():
+            while launched and self.ex.done(launched[0]):
                 c = launched.popleft()
-                c.t_done = time.perf_counter() - t0
+                c.t_done = self.clock() - t0
                 if c.cid < keep_first:
-                    self.keep[c.cid] = {k: v[c.slot:c.slot + c.n].clone() for k, v in self.hout.items()}
+                    self.keep[c.cid] = self.ex.features(c)
                 inflight.popleft()
+                progress = True
             if log and now >= next_log:
                 log(f"t={now:.1f}s admitted={len(chunks) - len(pending)} done={sum(1 for c in chunks if c.t_done >= 0)}"
                     f" queue={len(pending)}")
                 next_log += 1.0
             if not (copying or launched) and pending and pending[0].arrival > now:
-                time.sleep(min(0.0005, pending[0].arrival - now))
-        torch.cuda.synchronize()
+                self.sleep(min(0.0005, pending[0].arrival - now))
+            elif not progress and self.idle is not None:
+                self.idle()
+        self.ex.finish()
         return chunks
 
     def _reserve_fifo(self, n, inflight):
@@ -211,10 +274,7 @@ class Server:
         return tail if tail + n <= lo else -1   # wrapped: free [tail, lo)
 
     def flush(self, jcap, gcap):
-        with torch.cuda.stream(self.s_comp):
-            out = self.stream.flush(jcap, gcap, stream=self.s_comp)
-        torch.cuda.synchronize()
-        return out
+        return self.ex.flush(jcap, gcap)
 
 
 def latency_stats(chunks, warmup_s=0.0):

@@ -58,6 +58,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="default run: skip the batched sub-benchmark")
     ap.add_argument("--no-serving", action="store_true", help="default run: skip the serving sub-benchmark")
+    ap.add_argument("--c4-rates", type=lambda x: [float(v) for v in x.split(",")], default=[200.0, 400.0, 600.0, 800.0],
+                    help="c4: constant chunk rates of the sustained-rate sweep")
+    ap.add_argument("--sweep-duration", type=float, default=6.0, help="c4: seconds per sweep rate")
     ap.add_argument("--batched-steps", type=int, default=5, help="default run: timed steps of the batched form")
     ap.add_argument("--batched-only", action="store_true",
                     help="c2: time the batched form only (no per-shard loop or comparison; for profiler runs)")
@@ -337,14 +340,47 @@ def bench_serving(args, workload):
     assert same, "batched and per-chunk serving differ"
     assert flags_clear, "a distinct-journey cell set overflowed: counts may be high"
     offered = sum(s for _, s in trace) / dur / 1e6
+    sweep = serving_rate_sweep(pool, grid, arena, max_groups, args.c4_rates, args.sweep_duration) if skew else None
     return {
         "workload": f"{workload}: {desc}", "pool_records": pool.n, "chunks": len(trace),
         "offered_mrec_per_s": round(offered, 1), "arena_records": int(arena),
-        "admission": "FIFO into a ring of record slots carved from free HBM at start-up",
+        "admission": "FIFO into a ring of record slots carved from free HBM at start-up; "
+                     "a push batches at most a quarter of the ring",
         "value": out["batched"]["mrec_per_s"], "unit": "Mrecords/s",
         "latency_batched": out["batched"], "latency_per_chunk": out["per_chunk"],
         "identical_outputs": bool(same and flags_clear), "journeys": int(ra["count"]), "groups": int(rga["count"]),
+        "rate_sweep": sweep,
     }
+
+
+def serving_rate_sweep(pool, grid, arena, max_groups, rates, dur):
+    """The batched server at constant Poisson rates (same chunk sizes as the
+    burst trace), a fresh server per rate.  A rate is sustained when the
+    latency does not grow over the run: the p90 of the last third of the
+    chunks stays within twice the p90 of the first third plus 20 ms, and the
+    p99 stays below 100 ms."""
+    import numpy as np
+    import torch
+    from paper_2305_07454_amd import serve
+    rows = []
+    for i, rate in enumerate(rates):
+        trace = serve.poisson_trace(np.random.default_rng(7000 + i), lambda tt, r=rate: r, dur, 10_000, 5_000_000)
+        srv = serve.Server(pool, grid, batching=True, arena_records=arena, max_journeys=1 << 22,
+                           max_groups=max_groups)
+        chunks = srv.run(trace)
+        st = serve.latency_stats(chunks, warmup_s=min(1.0, dur / 5))
+        lat = [c.t_done - c.arrival for c in chunks if c.arrival >= min(1.0, dur / 5)]
+        k = max(1, len(lat) // 3)
+        p90a, p90b = float(np.percentile(lat[:k], 90)), float(np.percentile(lat[-k:], 90))
+        ok = p90b <= 2.0 * p90a + 0.02 and st["p99_ms"] < 100.0
+        offered = sum(s for _, s in trace) / dur / 1e6
+        rows.append({"chunks_per_s": rate, "offered_mrec_per_s": round(offered, 1), "p50_ms": st["p50_ms"],
+                     "p99_ms": st["p99_ms"], "mrec_per_s": st["mrec_per_s"], "sustained": bool(ok)})
+        log(f"sweep {rate}/s: {rows[-1]}")
+        del srv
+        torch.cuda.empty_cache()
+    best = max((r["chunks_per_s"] for r in rows if r["sustained"]), default=None)
+    return {"duration_s": dur, "rates": rows, "highest_sustained_chunks_per_s": best}
 
 
 def bench_plain(args, workload):

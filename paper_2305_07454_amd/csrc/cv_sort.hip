@@ -526,6 +526,10 @@ __global__ void __launch_bounds__(PT_B) k_pack_il(const i64* __restrict__ jid, c
     const bool packed = m->p0 == 0;
     const bool group = pay != nullptr;
     const u32 rbits = m->rank_bits;
+    // without time bits the first digit of a key is the low byte of its rank,
+    // which the regrouping counts per tile: that pass's histogram is added
+    // from those counts, one add per digit and tile
+    const u32 p_first = (group && tdrop && !bad && rbits >= (u32)RADIX_BITS && np > 0) ? 1u : 0u;
     const u64 tmin = (u64)unord_i64(m->tmin_ord);
     const ulonglong2* t2 = (const ulonglong2*)table;
     const u64 tiles = ((u64)n + PT - 1) / PT;
@@ -605,7 +609,7 @@ __global__ void __launch_bounds__(PT_B) k_pack_il(const i64* __restrict__ jid, c
             }
             const u64 vm = __ballot(valid);
             const int lead = vm ? __ffsll((long long)vm) - 1 : 0;
-            for (u32 p = 0; p < np; ++p) {
+            for (u32 p = p_first; p < np; ++p) {
                 const u32 d = (u32)(key[k] >> (p * RADIX_BITS)) & (RADIX - 1);
                 const u32 d0 = __shfl(d, lead, WAVE);
                 if (__ballot(valid && d != d0) == 0) {
@@ -646,6 +650,7 @@ __global__ void __launch_bounds__(PT_B) k_pack_il(const i64* __restrict__ jid, c
                     tcount += c;
                 }
             }
+            if (p_first && threadIdx.x < RADIX && tcount) s_h[threadIdx.x] += tcount;
             u32 total;
             const u32 st = block_exclusive_sum<PT_B>(threadIdx.x < RADIX ? tcount : 0u, s_tmp, total);
             if (threadIdx.x < RADIX) s_start[threadIdx.x] = st;

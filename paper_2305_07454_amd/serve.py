@@ -163,13 +163,17 @@ class DeviceExecutor:
 class Server:
     def __init__(self, pool, grid, batching=True, arena_records=None, max_journeys=1 << 21,
                  max_groups=1 << 23, device="cuda", executor=None, clock=time.perf_counter, sleep=time.sleep,
-                 idle=None):
+                 idle=None, max_push_records=None):
         """arena_records: records in the device ring; None carves it from the
         free HBM (arena_from_free_hbm).  Chunks are admitted into the ring in
         arrival order while it has room.  executor: the device side (a
         DeviceExecutor by default); clock / sleep / idle: the loop's time
         source, its wait for the next arrival, and what it does in a round
-        that made no progress (nothing: it polls again)."""
+        that made no progress (nothing: it polls again).  max_push_records:
+        the most records one push batches (a single larger chunk still goes
+        alone); by default a quarter of the ring, so that while one push
+        computes, the copies of the one before and of the next have ring
+        space of their own."""
         self.grid = grid
         self.batching = batching
         if executor is None:
@@ -178,6 +182,7 @@ class Server:
             executor = DeviceExecutor(pool, grid, arena_records, max_journeys, max_groups, device)
         self.ex = executor
         self.A = int(executor.A)
+        self.max_push = int(max_push_records) if max_push_records else max(1, self.A // 4)
         self.pool_n = pool.n
         self.clock, self.sleep, self.idle = clock, sleep, idle
         self.keep = {}         # cid -> features copied out for checking
@@ -223,10 +228,14 @@ class Server:
             # launch when the compute stream is free
             if copying and self.ex.compute_free():
                 ready = []
+                nrec = 0
                 while copying and self.ex.copy_done(copying[0]):
                     c = copying[0]
                     if ready and (c.slot != ready[-1].slot + ready[-1].n):
                         break          # not contiguous in the ring (wrapped): next push
+                    if ready and nrec + c.n > self.max_push:
+                        break          # the push is full: the rest goes in the next
+                    nrec += c.n
                     ready.append(copying.popleft())
                     if not self.batching:
                         break

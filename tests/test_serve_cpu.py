@@ -222,3 +222,29 @@ def test_slow_batch_delays_later_chunks_in_order():
     assert max(lat[k] for k in range(20)) < 0.01                      # before the slow push: unaffected
     # the backlog drains: the last chunk waits less than the one right after the slow push
     assert lat[99] < lat[21]
+
+
+def test_push_size_is_capped_under_backlog():
+    # a backlog of small chunks: every push stays within the cap (a quarter
+    # of the ring by default) and the chunks still complete in FIFO order
+    clock = _Clock()
+    A = 4_000_000
+    ex = _FakeExecutor(A, clock, rec_s=5e-8)
+    trace = [(0.0, 150_000) for _ in range(120)]
+    srv = _server(ex, clock)
+    assert srv.max_push == A // 4
+    chunks = srv.run(trace)
+    sizes = {c.cid: c.n for c in chunks}
+    assert [c for b in ex.batches for c in b] == list(range(120))
+    assert all(sum(sizes[c] for c in b) <= A // 4 for b in ex.batches)
+    assert max(len(b) for b in ex.batches) == (A // 4) // 150_000
+    done = [c.t_done for c in chunks]
+    assert all(b >= a for a, b in zip(done, done[1:]))
+
+
+def test_chunk_above_the_push_cap_goes_alone():
+    clock = _Clock()
+    ex = _FakeExecutor(4_000_000, clock)
+    trace = [(0.0, 100_000), (0.0, 2_000_000), (0.0, 100_000)]
+    _server(ex, clock).run(trace)
+    assert [1] in ex.batches and all(len(b) == 1 or 1 not in b for b in ex.batches)

@@ -484,6 +484,7 @@ static cv_status grid_impl(const cv_records* sorted, const u64* soff, u32 S, con
     g.n_lon = grid->n_lon;
     g.t0 = grid->t0_ms;
     g.bin_ms = grid->bin_ms;
+    g.tinv = 1.0 / (double)grid->bin_ms;
     g.tmax = grid->n_t > 0 ? grid->n_t : (INT64_MAX / (grid->n_lat * grid->n_lon * (i64)(nd + 1)));
     g.soff = soff;
     g.S = S;

@@ -294,7 +294,7 @@ k_grid_agg(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, const
     }
     if (t == 0) {
         s_pj = base > 0 ? jid[base - 1] : 0;
-        s_ptb = base > 0 ? floor_div64(ts[base - 1] - g.t0, g.bin_ms) : 0;
+        s_ptb = base > 0 ? time_bin(g, ts[base - 1]) : 0;
         s_plt = (Pol::kStream && base > 0) ? (uint8_t)pol.late((u64)(base - 1)) : (uint8_t)0;
         s_lo = -1;
         s_npend = 0;

@@ -84,6 +84,7 @@ struct GridMeta {
 struct Spec {
     double lat0, lon0, dlat, dlon;
     i64 n_lat, n_lon, t0, bin_ms, tmax;
+    double tinv;      // 1 / bin_ms, rounded (the time bin's quotient estimate)
     const u64* soff;  // shard offsets (batched form) or nullptr
     u32 S;            // number of shards (0 or 1: one problem)
     u32 kb;           // bits of the cell key; the shard index sits above them
@@ -114,6 +115,33 @@ __device__ __forceinline__ i64 floor_div64(i64 a, i64 b)
     return q;
 }
 
+// The time bin floor((ts - t0) / bin_ms).  The quotient is estimated by a
+// multiply with the rounded reciprocal of bin_ms; for |ts - t0| < 2^52 the
+// estimate is within one of the quotient, so its floor is off by at most one
+// and one integer step corrects it.  Offsets and widths below 2^30 (any time
+// within twelve days of t0) take the step in 32-bit arithmetic, where no
+// product overflows; wider offsets take it in 64 bits, and offsets beyond
+// 2^52 the integer division.
+__device__ __forceinline__ i64 time_bin(const Spec& g, i64 ts)
+{
+    const i64 a = ts - g.t0;
+    if (g.bin_ms < (1ll << 30) && a >= -(1ll << 30) && a < (1ll << 30)) {
+        const u32 a32 = (u32)a, b32 = (u32)g.bin_ms;
+        int q = (int)floor((double)(int)a32 * g.tinv);
+        const int r = (int)(a32 - (u32)q * b32);  // |r| < 2 bin_ms: exact through the wrap
+        q += r < 0 ? -1 : (r >= (int)b32 ? 1 : 0);
+        return (i64)q;
+    }
+    if (a > -(1ll << 52) && a < (1ll << 52)) {
+        i64 q = (i64)floor((double)a * g.tinv);
+        const i64 r = a - q * g.bin_ms;
+        if (r < 0) q -= 1;
+        else if (r >= g.bin_ms) q += 1;
+        return q;
+    }
+    return floor_div64(a, g.bin_ms);
+}
+
 // Direction sector of a heading h in degrees (Algorithm 2 bins it by floor
 // division with a sector width): floor((h + doff) / dstep) mod nd for h in
 // [0, 360); nd for a missing direction (no valid heading or bearing).
@@ -139,7 +167,7 @@ __device__ __forceinline__ u32 dir_at(const Spec& g, u64 r)
 __device__ __forceinline__ i64 grid_key_in(const Spec& g, u32 sh, i64 ts, double la, double lo, i64& tb,
                                            u32 dir = 0)
 {
-    tb = floor_div64(ts - g.t0, g.bin_ms);
+    tb = time_bin(g, ts);
     if (!isfinite(la) || !isfinite(lo)) return -1;
     double fy = floor((la - g.lat0) / g.dlat);
     double fx = floor((lo - g.lon0) / g.dlon);
@@ -161,7 +189,7 @@ __device__ __forceinline__ bool seg_start(const Spec& g, const i64* jid, const i
 {
     if (r == 0) return true;
     if (jid[r] != jid[r - 1]) return true;
-    if (tb != floor_div64(ts[r - 1] - g.t0, g.bin_ms)) return true;
+    if (tb != time_bin(g, ts[r - 1])) return true;
     return g.S > 1 && shard_start(g.soff, g.S, r);
 }
 

@@ -541,7 +541,7 @@ __global__ void __launch_bounds__(256) k_st_merge(const i64* __restrict__ ts, co
             R.last_b = fs_b[lg];
             R.last_flags = fs_flags[lg];
             R.has_last = 1;
-            const i64 tb = floor_div64(ts[lg] - g.t0, g.bin_ms);
+            const i64 tb = time_bin(g, ts[lg]);
             if (tb != R.seg_tbin) {
                 R.seg_tbin = tb;
                 R.ncell = 0;
@@ -929,6 +929,7 @@ cv_status cv_stream_create(const cv_grid_spec* grid, uint64_t max_journeys, uint
     g.n_lon = grid->n_lon;
     g.t0 = grid->t0_ms;
     g.bin_ms = grid->bin_ms;
+    g.tinv = 1.0 / (double)grid->bin_ms;
     g.tmax = grid->n_t > 0 ? grid->n_t : (INT64_MAX / (grid->n_lat * grid->n_lon));
     g.soff = nullptr;
     g.S = 0;

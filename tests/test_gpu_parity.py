@@ -340,6 +340,31 @@ def test_summary_flags_column_at_any_alignment(cv):
         assert torch.equal(a[k], b[k]), k
 
 
+@pytest.mark.parametrize("bin_ms", [1, 7, 60_000, 2 ** 30 - 1, 2 ** 30, 2 ** 31 + 5])
+def test_time_bins_across_offset_ranges(cv, bin_ms):
+    # an unbounded time axis, so every time bin is a key: offsets from t0
+    # around 0, on and next to bin edges, around +-2^30 (where the quotient's
+    # correction leaves 32-bit arithmetic) and around 2^52 (where the integer
+    # division takes over), negative offsets (out of the grid) included
+    rng = np.random.default_rng(bin_ms % 1000 + 5)
+    spec = gen.GridSpec(36.0, -95.8, 0.5, 0.5, 10, 14, gen.T0_MS, bin_ms, 0)
+    centres = [0, 2 ** 30, -(2 ** 30), 2 ** 31, 2 ** 40 + 3, 2 ** 52, 2 ** 53 + 9, 5 * bin_ms, 2 ** 30 // bin_ms * bin_ms]
+    offs = []
+    for c in centres:
+        offs += [c + d for d in range(-3, 4)]
+        offs += [(c // bin_ms + e) * bin_ms + d for e in (-1, 0, 1) for d in (-1, 0, 1)]
+    offs = np.array(sorted(set(offs)), dtype=np.int64)
+    n = len(offs) * 3
+    ts = gen.T0_MS + np.repeat(offs, 3)
+    jid = np.repeat(np.arange(n // 12 + 1, dtype=np.int64), 12)[:n]
+    lat = rng.uniform(36.0, 40.9, n)
+    lon = rng.uniform(-95.8, -88.9, n)
+    spd = rng.uniform(0, 40, n).astype(np.float32)
+    got, exp = _run_both(cv, (jid, ts, lat, lon, spd), spec)
+    _check_all(got, exp)
+    assert len(exp["groups"]["key"]) > len(offs) // 2
+
+
 def test_cell_boundaries_and_neighbours(cv):
     # coordinates on cell boundaries k * d from the origin and one or two ulps
     # either side, and time stamps on bin edges: every key must equal the

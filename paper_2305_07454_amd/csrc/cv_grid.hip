@@ -3,7 +3,7 @@
 // count / sum / count-unique / mean reductions of Table 3), as a sparse,
 // key-sorted group table over (journey, time)-sorted records.
 //
-//   k_grid_part  per tile of GT records, staged in LDS with coalesced loads:
+//   k_grid_part  per tile of GT records, read with coalesced loads:
 //     * key = (tbin * n_lat + ilat) * n_lon + ilon per record (-1 outside);
 //     * runs: maximal stretches of one key inside one (journey, time-bin)
 //       segment; each is reduced once (count, exact speed sum, min, max);

@@ -20,7 +20,11 @@
 namespace cv {
 namespace {
 
-constexpr int PR_MAX = 512;     // (journey, key) accumulators per tile in LDS
+// (journey, key) accumulators per tile in LDS: 320 keep the kernel's LDS at
+// 40 KB, so that four workgroups share a CU (a tile of the batched workload's
+// 0.001 deg x 1 min grid holds about 250 keys on average; a tile with more
+// roots takes the path where runs without an accumulator write own rows)
+constexpr int PR_MAX = 320;
 constexpr int SCAN_BACK = 128;  // run heads a run head looks back over for its key
 // what a run head's entry of s_root holds once the rows are numbered
 constexpr uint16_t H_NONE = 0xFFFF;  // run outside the grid: dropped
@@ -67,8 +71,11 @@ __device__ __forceinline__ GPart make_part(i64 jid, u64 lo, u64 hi, u32 cn, u32 
     return p;
 }
 
+// Four waves per SIMD for the plain key (what the LDS allows); the direction
+// forms carry a heading or bearing column too and keep three, which their
+// registers need without spilling.
 template <int KD>
-__global__ void __launch_bounds__(GB) __attribute__((amdgpu_waves_per_eu(3)))
+__global__ void __launch_bounds__(GB) __attribute__((amdgpu_waves_per_eu(KD == 0 ? 4 : 3)))
 k_grid_part(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, const double* __restrict__ lat,
             const double* __restrict__ lon, const float* __restrict__ spd, Spec g, PartSink sk, GridMeta* meta)
 {
@@ -81,7 +88,6 @@ k_grid_part(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, cons
     static_assert(PR_MAX < H_ACC && GT <= 0x3FFF, "head and accumulator indices fit the tags");
     __shared__ i64 s_hkey[GT];       // run head -> its key
     __shared__ __attribute__((aligned(16))) uint8_t s_bits[GT];
-    __shared__ __attribute__((aligned(16))) float s_spd[GT];
     __shared__ uint16_t s_lpos[GT];  // run head -> position | L_SEG | L_ODD
     __shared__ uint16_t s_root[GT];  // run head -> its root head; then the H_* info
     __shared__ u64 s_c0[PR_MAX], s_c1[PR_MAX];  // sum: two carry-save 43-bit chunks (mod 2^86)
@@ -177,7 +183,6 @@ k_grid_part(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, cons
         // of the aggregation start runs: no run is split between waves
         const bool run = seg || q % WREC == 0 || (lane > 0 && k != kp);
         bq[rr] = (seg ? B_SEG : 0) | (run ? B_RUN : 0) | (odd ? B_ODD : 0);
-        s_spd[q] = in ? vsp[rr] : 0.f;
         const u64 om = __ballot(odd);
         if (lane == 0) s_rodd[rr][w] = om != 0;
     }
@@ -198,7 +203,7 @@ k_grid_part(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, cons
             else if (vk[rr] != s_lk[pr][pw]) b |= B_RUN;
         }
         const bool chk = s_rodd[rr][w] || (lane == 0 && q > 0 && s_rodd[pr][pw]);
-        if (chk && in && ((b & B_ODD) || (q > 0 && spd_odd(s_spd[q - 1])))) b |= B_RUN;
+        if (chk && in && ((b & B_ODD) || (q > 0 && spd_odd(spd[tile0 + (u64)q - 1])))) b |= B_RUN;
         bq[rr] = b;
         s_bits[q] = b;
         hm[rr] = __ballot((b & B_RUN) && in);
@@ -424,9 +429,11 @@ k_grid_part(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, cons
         }
     };
     {
-        const float4 spa = *reinterpret_cast<const float4*>(&s_spd[q0]);
-        const float4 spb = *reinterpret_cast<const float4*>(&s_spd[q0 + 4]);
-        const float sp8[PER] = {spa.x, spa.y, spa.z, spa.w, spb.x, spb.y, spb.z, spb.w};
+        // the lane's speeds again from global memory (just read by the tile,
+        // so from cache): staging them in LDS would cost the fourth workgroup
+        float sp8[PER];
+#pragma unroll
+        for (int i = 0; i < PER; ++i) sp8[i] = spd[tile0 + (u64)(i < nv ? q0 + i : 0)];
         RunPart cur, pre;
         run_reset(cur);
         run_reset(pre);

@@ -40,7 +40,7 @@ constexpr int SCP = 8;
 constexpr int SCH = SCB * SCP;
 // sorted partial pairs per chunk of the head count and the emit
 constexpr int ECB = 256;
-constexpr int ECP = 8;
+constexpr int ECP = 4;  // (4: 118 VGPRs in the emit, 4 waves per SIMD)
 constexpr int ECH = ECB * ECP;
 
 struct GridLayout {

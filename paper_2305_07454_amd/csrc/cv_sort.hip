@@ -122,7 +122,7 @@ __device__ __forceinline__ u32 dict_rank_of(const u64* table, u64 mask, u64 key)
 // one through the owner word), so an entry is never a mix of two writes.
 constexpr int DC = 256;   // slots per wave in the insert
 constexpr int DCP = 128;  // slots per wave in the key packing (16 KB of LDS per workgroup with the histograms)
-constexpr int DPW = 8;  // windows whose ids and times are loaded together
+constexpr int DPW = 4;  // windows whose ids and times are loaded together (4: 90 VGPRs, 5 waves per SIMD)
 
 __device__ __forceinline__ void wave_range(u32 n, u64& wbeg, u64& wend)
 {

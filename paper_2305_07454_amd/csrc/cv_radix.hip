@@ -106,6 +106,11 @@ k_radix_pass(const u64* __restrict__ keys_in, const u32* __restrict__ vals_in, u
     // tile, so a grid smaller than the tile count covers every tile); a tile
     // waits only on tiles whose tickets were taken before, by blocks already
     // running.
+    // A block of a one-tile-per-block grid sized for n_max whose tile lies past
+    // a count read on the device leaves before it takes a ticket: exactly the
+    // first ceil(n / tile) blocks take the tickets 0 .. ceil(n / tile) - 1,
+    // and the idle ones put no load on the ticket counter.
+    if (!LOOP && (u64)blockIdx.x * SORT_TILE >= n) return;
     for (;;) {
     if (threadIdx.x == 0) s_tile = atomicAdd(ticket, 1u);
     for (int i = threadIdx.x; i < NW * RADIX; i += SORT_BLOCK) (&s_whist[0][0])[i] = 0;
@@ -279,8 +284,12 @@ void radix_scan(const u32* hist, u32* offs, int passes, hipStream_t s)
 
 namespace {
 
-// blocks of a pass whose record count is read on the device
+// A pass whose record count is read on the device launches one block per
+// tile of n_max (the blocks past the count leave at once) up to
+// DEVICE_COUNT_MAX_TILES tiles; beyond that, DEVICE_COUNT_GRID blocks that
+// loop over tiles (a form that needs more registers, so fewer blocks per CU).
 constexpr u64 DEVICE_COUNT_GRID = 2048;
+constexpr u64 DEVICE_COUNT_MAX_TILES = 1ull << 17;
 
 // tile shapes compiled into the library; the sort uses sort_shape()
 struct Shape {
@@ -296,9 +305,9 @@ void launch_pass(u64 tiles, hipStream_t s, const u64* kin, const u32* vin, u64* 
                  const u32* n_dev, int p, const u32* bits_dev, const u32* offs, u64* status, u32* ticket,
                  const u32* pack)
 {
-    // a count known only on the device: a grid that fills the GPU, whose
-    // blocks take tiles until the count is covered
-    if (n_dev && tiles > DEVICE_COUNT_GRID)
+    // a count known only on the device and a very large bound: a grid that
+    // fills the GPU, whose blocks take tiles until the count is covered
+    if (n_dev && tiles > DEVICE_COUNT_MAX_TILES)
         hipLaunchKernelGGL((k_radix_pass<B, I, true>), dim3((unsigned)DEVICE_COUNT_GRID), dim3(B), 0, s, kin, vin,
                            kout, vout, n_max, n_dev, p, bits_dev, offs, status, ticket, pack);
     else

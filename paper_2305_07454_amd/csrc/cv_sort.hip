@@ -50,7 +50,8 @@ struct SortMeta {
     u32 n_runs;  // runs of equal ids in input order (counted by the dictionary insert)
     u32 unordered;  // a timestamp below its predecessor's (same shard) in input order
     u32 ts_dropped; // key = (shard, rank) only: the input is time-ordered within every shard
-    u32 tickets[2 * MAX_PASSES];
+    u32 multi_shard; // batched: an id in more than one shard (ranks then in id order, shard bits in the key)
+    u32 tickets[3 * MAX_PASSES];
 };
 
 __device__ __forceinline__ u32 bit_width64(u64 x) { return x ? 64u - (u32)__clzll((long long)x) : 0u; }
@@ -82,6 +83,38 @@ __device__ __forceinline__ bool dict_insert_from(u64* table, u64 mask, u64 key, 
         }
         h = (h + 1) & mask;
         cur = table[2 * h];
+    }
+    return false;
+}
+
+// Batched form: the insert of `key` for shard `sh`, continuing a probe at slot
+// h whose entry e was read, also tags the slot's second word with the shard.
+// A slot tagged with another shard means the id lies in two shards (multi).
+// Both the inserter and a reader that finds the slot untagged tag it by
+// compare-and-swap, so exactly one shard wins and any other sees it.
+// Returns false when the table is full.
+__device__ __forceinline__ bool dict_insert_tag(u64* table, u64 mask, u64 key, u64 h, ulonglong2 e, u64 sh,
+                                                bool& multi)
+{
+    const ulonglong2* t2 = (const ulonglong2*)table;
+    for (u64 probe = 0; probe <= mask; ++probe) {
+        bool mine = e.x == key;
+        if (!mine && e.x == EMPTY) {
+            const u64 prev =
+                atomicCAS((unsigned long long*)&table[2 * h], (unsigned long long)EMPTY, (unsigned long long)key);
+            mine = prev == EMPTY || prev == key;
+            e.y = EMPTY;  // (re)tag below by compare-and-swap
+        }
+        if (mine) {
+            if (e.y != sh) {
+                const u64 old = atomicCAS((unsigned long long*)&table[2 * h + 1], (unsigned long long)EMPTY,
+                                          (unsigned long long)sh);
+                if (old != EMPTY && old != sh) multi = true;
+            }
+            return true;
+        }
+        h = (h + 1) & mask;
+        e = t2[h];
     }
     return false;
 }
@@ -142,10 +175,19 @@ __device__ __forceinline__ u32 dict_cache_slot(u64 key)
 // Also checks whether the timestamps never decrease within a shard in input
 // order: then every journey's records already come in time order, and a
 // stable sort by (shard, journey) alone gives the (journey, time) order.
+// SHARDS (the batched form) also tags every id's slot with its shard and
+// flags an id met in two shards; a run of equal ids then ends at a shard
+// start, and a round of windows that meets a shard start or a shard other
+// than the one its wave's cache was filled in bypasses the cache (whose
+// entries would skip the shard check) and empties it.
+template <bool SHARDS>
 __global__ void __launch_bounds__(256) k_dict_insert(const i64* __restrict__ jid, const i64* __restrict__ ts, u32 n,
                                                      u64* __restrict__ table, u64 mask, SortMeta* m,
                                                      const u64* __restrict__ soff, u32 S)
 {
+    // the batched form's 16-byte probes and shard checks: 3 windows per round
+    // keep it at 5 waves per SIMD
+    constexpr int DP = SHARDS ? 3 : DPW;
     __shared__ u64 s_min[4], s_max[4];
     __shared__ u64 c_key[4][DC];
     __shared__ u32 c_own[4][DC];
@@ -153,7 +195,7 @@ __global__ void __launch_bounds__(256) k_dict_insert(const i64* __restrict__ jid
     const int l = lane_id();
     for (int i = l; i < DC; i += WAVE) c_key[w][i] = EMPTY;  // EMPTY is never looked up
     u64 lo = ~0ull, hi = 0;
-    bool has_min = false, full = false;
+    bool has_min = false, full = false, multi = false;
     u64 wbeg, wend;
     wave_range(n, wbeg, wend);
     i64 prevj = 0;  // last id of the previous window
@@ -163,22 +205,45 @@ __global__ void __launch_bounds__(256) k_dict_insert(const i64* __restrict__ jid
     u64 prevt = (wbeg < wend && wbeg > 0) ? ord_i64(ts[wbeg * WAVE - 1]) : 0ull;
     bool down = false;
     u32 shk = (S > 1 && wbeg < wend) ? shard_lower_bound(soff, S, wbeg * WAVE) : 0u;
-    for (u64 w0 = wbeg; w0 < wend; w0 += DPW) {
-        i64 jv[DPW];
-        u64 tv[DPW];
+    u32 csh = ~0u;  // the shard the wave's cache entries were met in (SHARDS)
+    for (u64 w0 = wbeg; w0 < wend; w0 += DP) {
+        i64 jv[DP];
+        u64 tv[DP];
 #pragma unroll
-        for (int k = 0; k < DPW; ++k) {
+        for (int k = 0; k < DP; ++k) {
             u64 i = (w0 + k) * WAVE + l;
             i = i < n ? i : (u64)n - 1;  // past the end: a valid record, not used
             jv[k] = jid[i];
             tv[k] = ord_i64(ts[i]);
         }
+        // shard starts of each window (lane masks) and the window's shard
+        // when none starts inside it (~0 otherwise); wave-uniform
+        u64 starts[DP];
+        u32 wsh[DP];
+        bool byp = false;
+#pragma unroll
+        for (int k = 0; k < DP; ++k) {
+            starts[k] = 0;
+            wsh[k] = 0;
+            if (S > 1 && w0 + k < wend) {
+                const u32 k0 = __builtin_amdgcn_readfirstlane(shk);
+                bool at_end = false;
+                starts[k] = shard_starts_in(soff, S, shk, (w0 + k) * WAVE, at_end);
+                wsh[k] = starts[k] ? ~0u : k0 - 1;
+                if (SHARDS) byp |= wsh[k] != csh || wsh[k] == ~0u;
+            }
+        }
+        if (SHARDS && byp) {
+            for (int i = l; i < DC; i += WAVE) c_key[w][i] = EMPTY;
+            __builtin_amdgcn_wave_barrier();
+        }
         // first the run starts of every window and, for each that misses the
         // cache, the first probe, issued together; then the inserts in order
-        bool miss[DPW];
-        u64 ph[DPW], pc[DPW];
+        bool miss[DP];
+        u64 ph[DP];
+        ulonglong2 pe[DP];
 #pragma unroll
-        for (int k = 0; k < DPW; ++k) {
+        for (int k = 0; k < DP; ++k) {
             miss[k] = false;
             if (w0 + k >= wend) continue;
             const u64 i = (w0 + k) * WAVE + l;
@@ -188,19 +253,19 @@ __global__ void __launch_bounds__(256) k_dict_insert(const i64* __restrict__ jid
                 lo = tv[k] < lo ? tv[k] : lo;
                 hi = tv[k] > hi ? tv[k] : hi;
             }
+            const bool sstart = (starts[k] >> l) & 1ull;
             {
                 // time order against the record before (none before record 0
                 // and before a shard's first record)
                 const u64 tp = __shfl_up(tv[k], 1, WAVE);
                 const u64 tq = l == 0 ? prevt : tp;
-                bool at_end = false;
-                const u64 starts = S > 1 ? shard_starts_in(soff, S, shk, (w0 + k) * WAVE, at_end) : 0ull;
-                if (valid && i > 0 && !((starts >> l) & 1ull) && tv[k] < tq) down = true;
+                if (valid && i > 0 && !sstart && tv[k] < tq) down = true;
                 prevt = __shfl(tv[k], WAVE - 1, WAVE);
             }
-            // a record repeating the id before it adds nothing
+            // a record repeating the id before it adds nothing (in the
+            // batched form, unless a shard starts at it)
             const i64 jp = __shfl_up(j, 1, WAVE);
-            const bool dup = l == 0 ? (hp && j == prevj) : j == jp;
+            const bool dup = (l == 0 ? (hp && j == prevj) : j == jp) && !(SHARDS && sstart);
             prevj = __shfl(j, WAVE - 1, WAVE);
             hp = true;
             bool need = valid && !dup;
@@ -210,20 +275,45 @@ __global__ void __launch_bounds__(256) k_dict_insert(const i64* __restrict__ jid
                 need = false;
             }
             const u32 cs = dict_cache_slot<DC>((u64)j);
-            miss[k] = need && c_key[w][cs] != (u64)j;
+            miss[k] = need && ((SHARDS && byp) || c_key[w][cs] != (u64)j);
             ph[k] = mix64((u64)j) & mask;
-            if (miss[k]) pc[k] = table[2 * ph[k]];
+            if (SHARDS) {
+                if (miss[k]) pe[k] = ((const ulonglong2*)table)[ph[k]];
+            } else if (miss[k]) {
+                pe[k].x = table[2 * ph[k]];
+            }
         }
 #pragma unroll
-        for (int k = 0; k < DPW; ++k) {
+        for (int k = 0; k < DP; ++k) {
             if (w0 + k >= wend) break;
             const u64 j = (u64)jv[k];
             const u32 cs = dict_cache_slot<DC>(j);
-            if (miss[k] && !dict_insert_from(table, mask, j, ph[k], pc[k])) full = true;
+            if (SHARDS) {
+                if (miss[k]) {
+                    // the record's shard: the window's, or searched where a shard starts inside it
+                    const u64 i = (w0 + k) * WAVE + l;
+                    const u32 sh = wsh[k] != ~0u ? wsh[k] : shard_of(soff, S, i < n ? i : (u64)n - 1);
+                    if (!dict_insert_tag(table, mask, j, ph[k], pe[k], (u64)sh, multi)) full = true;
+                }
+            } else if (miss[k] && !dict_insert_from(table, mask, j, ph[k], pe[k].x)) {
+                full = true;
+            }
             if (miss[k]) c_own[w][cs] = (u32)l;
             __builtin_amdgcn_wave_barrier();
             if (miss[k] && c_own[w][cs] == (u32)l) c_key[w][cs] = j;
             __builtin_amdgcn_wave_barrier();
+        }
+        if (SHARDS && byp) {
+            // the entries just cached may come from several shards: start over
+            // in the shard of the round's last window (none when a shard
+            // starts inside it)
+            for (int i = l; i < DC; i += WAVE) c_key[w][i] = EMPTY;
+            __builtin_amdgcn_wave_barrier();
+            u32 last = ~0u;
+#pragma unroll
+            for (int k = 0; k < DP; ++k)
+                if (w0 + k < wend) last = wsh[k];
+            csh = last;
         }
     }
 #pragma unroll
@@ -238,6 +328,7 @@ __global__ void __launch_bounds__(256) k_dict_insert(const i64* __restrict__ jid
     }
     if (has_min) atomicOr(&m->has_min, 1u);
     if (full) atomicOr(&m->overflow, 1u);
+    if (SHARDS && __ballot(multi) && l == 0) atomicOr(&m->multi_shard, 1u);
     if (__ballot(down) && l == 0) atomicOr(&m->unordered, 1u);
     if (runs && l == 0) atomicAdd(&m->n_runs, runs);
     __syncthreads();
@@ -297,7 +388,11 @@ __global__ void k_dict_meta(SortMeta* m, u32 max_j, u32 n, u32 n_shards)
     // time-ordered input needs no time bits in the key (see the insert)
     m->ts_dropped = m->unordered ? 0u : 1u;
     u32 tb = m->ts_dropped ? 0u : bit_width64(span);
-    const u32 sb = n_shards > 1 ? bit_width64((u64)n_shards - 1) : 0;
+    // batched: when every id lies in one shard, ranks follow (shard, id) order
+    // and already keep the shards apart; otherwise the shard goes above them
+    // (the INT64_MIN id, which is never in the table, counts as such a case)
+    if (n_shards > 1 && m->has_min) m->multi_shard = 1;
+    const u32 sb = (n_shards > 1 && m->multi_shard) ? bit_width64((u64)n_shards - 1) : 0;
     m->rank_bits = rb;
     m->t_bits = tb;
     m->shard_bits = sb;
@@ -314,6 +409,43 @@ __global__ void k_dict_meta(SortMeta* m, u32 max_j, u32 n, u32 n_shards)
     const u32 ib = n > 1 ? bit_width64((u64)n - 1) : 1u;
     m->ib = ib;
     m->p0 = kb + ib > 64 ? (kb + ib - 64 + RADIX_BITS - 1) / RADIX_BITS : 0u;
+}
+
+// Batched form, after the distinct ids are sorted: each id's shard (its slot's
+// tag) as the key of a stable sort that brings the list into (shard, id)
+// order; 0 for every id when an id lies in several shards, so that the list
+// keeps id order.
+__global__ void __launch_bounds__(256) k_dict_shardkey(const u64* __restrict__ sorted_list, const SortMeta* m,
+                                                       const u64* __restrict__ table, u64 mask, u64* __restrict__ skey)
+{
+    const u32 dn = m->dict_n;
+    const bool multi = m->multi_shard != 0;
+    for (u32 r = blockIdx.x * blockDim.x + threadIdx.x; r < dn; r += gridDim.x * blockDim.x) {
+        const u64 k = sorted_list[r] ^ SIGN;
+        u64 sh = 0;
+        if (!multi && k != EMPTY) {
+            const u64 slot = dict_find(table, mask, k);
+            sh = slot != ~0ull ? table[2 * slot + 1] : 0ull;
+        }
+        skey[r] = sh;
+    }
+}
+
+// Batched form: the list in (shard, id) order (perm: the stable sort's order of
+// the id-sorted list) and each id's rank, its position in that order.
+__global__ void __launch_bounds__(256) k_dict_final(const u64* __restrict__ sorted_list, const u32* __restrict__ perm,
+                                                    const SortMeta* m, u64* __restrict__ table, u64 mask,
+                                                    u64* __restrict__ final_list)
+{
+    const u32 dn = m->dict_n;
+    for (u32 r = blockIdx.x * blockDim.x + threadIdx.x; r < dn; r += gridDim.x * blockDim.x) {
+        const u64 v = sorted_list[perm[r]];
+        final_list[r] = v;
+        const u64 k = v ^ SIGN;
+        if (k == EMPTY) continue;
+        const u64 slot = dict_find(table, mask, k);
+        if (slot != ~0ull) table[2 * slot + 1] = r;
+    }
 }
 
 __global__ void __launch_bounds__(256) k_dict_rank(const u64* __restrict__ sorted_list, const SortMeta* m,
@@ -458,7 +590,7 @@ __global__ void __launch_bounds__(256) k_pack_hist(const i64* __restrict__ jid, 
             if (valid) {
                 if (!bad) {
                     key = tdrop ? (u64)r : ((tb >= 64 ? 0ull : ((u64)r << tb)) | (tv[k] - tmin));
-                    if (SHARDS) {
+                    if (SHARDS && m->shard_bits) {
                         // the window's first shard, then forward to this record's
                         shw = __builtin_amdgcn_readfirstlane(shard_from(soff, S, shw, wi * WAVE));
                         const u32 sh = shard_from(soff, S, shw, i);
@@ -526,6 +658,7 @@ __global__ void __launch_bounds__(PT_B) k_pack_il(const i64* __restrict__ jid, c
     const bool packed = m->p0 == 0;
     const bool group = pay != nullptr;
     const u32 rbits = m->rank_bits;
+    const u32 sbits = m->shard_bits;  // 0: the ranks keep the shards apart
     // without time bits the first digit of a key is the low byte of its rank,
     // which the regrouping counts per tile: that pass's histogram is added
     // from those counts, one add per digit and tile
@@ -601,7 +734,7 @@ __global__ void __launch_bounds__(PT_B) k_pack_il(const i64* __restrict__ jid, c
             key[k] = 0;
             if (valid && !bad) {
                 key[k] = tdrop ? (u64)rk[k] : ((tb >= 64 ? 0ull : ((u64)rk[k] << tb)) | (tv[k] - tmin));
-                if (SHARDS) {
+                if (SHARDS && sbits) {
                     shw = __builtin_amdgcn_readfirstlane(shard_from(soff, S, shw, base + (u64)k * WAVE));
                     const u32 sh = shard_from(soff, S, shw, i);
                     key[k] |= (u64)sh << (rbits + tb);
@@ -821,6 +954,12 @@ struct SortLayout {
     u64* dl1;
     u32* dv0;
     u32* dv1;
+    u64* dsk0;  // batched: shard keys of the sorted distinct ids (ping-pong)
+    u64* dsk1;
+    u64* dlf;   // batched: the distinct ids in (shard, id) order
+    u32* shist;
+    u64* sstatus;
+    u32* soffs;
     u32* zero_begin;  // start of the region cleared to zero
     u32* hist;
     u32* dhist;
@@ -850,16 +989,22 @@ struct SortLayout {
         dl1 = c.take<u64>(max_j);
         dv0 = c.take<u32>(max_j);
         dv1 = c.take<u32>(max_j);
+        dsk0 = c.take<u64>(max_j);
+        dsk1 = c.take<u64>(max_j);
+        dlf = c.take<u64>(max_j);
         size_t z0 = cvh::align_up(c.off);
         hist = c.take<u32>(MAX_PASSES * RADIX);
         dhist = c.take<u32>(MAX_PASSES * RADIX);
+        shist = c.take<u32>(MAX_PASSES * RADIX);
         status = c.take<u64>(tiles * RADIX + 1);
         dstatus = c.take<u64>(dtiles * RADIX + 1);
+        sstatus = c.take<u64>(dtiles * RADIX + 1);
         size_t z1 = cvh::align_up(c.off);
         zero_begin = (u32*)(c.base ? c.base + z0 : nullptr);
         zero_bytes = z1 - z0;
         offs = c.take<u32>(MAX_PASSES * RADIX);
         doffs = c.take<u32>(MAX_PASSES * RADIX);
+        soffs = c.take<u32>(MAX_PASSES * RADIX);
         K0 = c.take<u64>(n);
         K1 = c.take<u64>(n);
         pay = c.take<PayRec>(n);
@@ -870,6 +1015,16 @@ struct SortLayout {
 };
 
 bool valid_ptr8(const void* p) { return p == nullptr || cvh::aligned(p, 8); }
+
+u32 bit_width_host(u64 x)
+{
+    u32 b = 0;
+    while (x) {
+        ++b;
+        x >>= 1;
+    }
+    return b;
+}
 
 }  // namespace
 
@@ -1144,8 +1299,8 @@ static cv_status sort_impl(const cv_records* in, const uint64_t* soff, uint32_t 
         hipLaunchKernelGGL(k_sort_init, dim3(1), dim3(64), 0, s, L.meta);
         cvh::fill_u64(L.table, EMPTY, 2 * L.slots, s);
         cvh::fill_u32(L.zero_begin, 0u, L.zero_bytes / 4, s);
-        hipLaunchKernelGGL(k_dict_insert, dim3(gs), dim3(256), 0, s, in->journey_id, in->ts_ms, nn, L.table, mask,
-                           L.meta, soff, S);
+        hipLaunchKernelGGL(S > 1 ? k_dict_insert<true> : k_dict_insert<false>, dim3(gs), dim3(256), 0, s,
+                           in->journey_id, in->ts_ms, nn, L.table, mask, L.meta, soff, S);
         hipLaunchKernelGGL(k_dict_compact, dim3(cvh::grid_for(L.slots, 256, 2048)), dim3(256), 0, s, L.table,
                            L.slots, mj, L.meta, L.dl0);
         hipLaunchKernelGGL(k_dict_meta, dim3(1), dim3(64), 0, s, L.meta, mj, nn, S);
@@ -1155,8 +1310,21 @@ static cv_status sort_impl(const cv_records* in, const uint64_t* soff, uint32_t 
         radix_scan(L.dhist, L.doffs, MAX_PASSES, s);
         radix_passes(L.dl0, L.dl1, nullptr, L.dv0, L.dv1, mj, dn, nullptr, MAX_PASSES, L.doffs, L.dstatus,
                      L.meta->tickets + MAX_PASSES, s);
-        hipLaunchKernelGGL(k_dict_rank, dim3(cvh::grid_for(max_journeys, 256, 1024)), dim3(256), 0, s, L.dl0, L.meta,
-                           L.table, mask);
+        if (S > 1) {
+            // the id-sorted list, stably by shard: (shard, id) order, and ranks in it
+            const int sp = (int)((bit_width_host((u64)S - 1) + RADIX_BITS - 1) / RADIX_BITS);
+            const int dg = cvh::grid_for(max_journeys, 256, 1024);
+            hipLaunchKernelGGL(k_dict_shardkey, dim3(dg), dim3(256), 0, s, L.dl0, L.meta, L.table, mask, L.dsk0);
+            radix_hist(L.dsk0, mj, dn, sp, nullptr, L.shist, cvh::grid_for(max_journeys, 256, 512), s);
+            radix_scan(L.shist, L.soffs, sp, s);
+            radix_passes(L.dsk0, L.dsk1, nullptr, L.dv0, L.dv1, mj, dn, nullptr, sp, L.soffs, L.sstatus,
+                         L.meta->tickets + 2 * MAX_PASSES, s);
+            hipLaunchKernelGGL(k_dict_final, dim3(dg), dim3(256), 0, s, L.dl0, (sp & 1) ? L.dv1 : L.dv0, L.meta,
+                               L.table, mask, L.dlf);
+        } else {
+            hipLaunchKernelGGL(k_dict_rank, dim3(cvh::grid_for(max_journeys, 256, 1024)), dim3(256), 0, s, L.dl0,
+                               L.meta, L.table, mask);
+        }
         // interleaved input (short runs of equal ids): the payload packed per
         // record for the fused gather, in the same pass
         hipLaunchKernelGGL(S > 1 ? k_pack_hist<true> : k_pack_hist<false>, dim3(gs), dim3(256), 0, s, in->journey_id,
@@ -1169,10 +1337,11 @@ static cv_status sort_impl(const cv_records* in, const uint64_t* soff, uint32_t 
     }
     radix_passes(L.K0, L.K1, nullptr, L.V0, L.V1, nn, nullptr, &L.meta->key_bits, MAX_PASSES, L.offs, L.status,
                  L.meta->tickets, s, /*timed=*/true, &L.meta->ib);
+    const u64* dict_ids = S > 1 ? L.dlf : L.dl0;  // journey ids by rank
     if (feat) {
         cvh::TimedScope ts_("gather_features", s);
         auto gk = S > 1 ? k_gather_feat<true> : k_gather_feat<false>;
-        hipLaunchKernelGGL(gk, dim3((unsigned)((n + GFT - 1) / GFT)), dim3(256), 0, s, nn, L.meta, L.K0, L.K1, L.dl0,
+        hipLaunchKernelGGL(gk, dim3((unsigned)((n + GFT - 1) / GFT)), dim3(256), 0, s, nn, L.meta, L.K0, L.K1, dict_ids,
                            in->journey_id, in->ts_ms, in->lat_deg, in->lon_deg, in->speed_mps, perm, so, *feat, soff,
                            S, L.pay);
     } else {
@@ -1180,7 +1349,7 @@ static cv_status sort_impl(const cv_records* in, const uint64_t* soff, uint32_t 
         const bool full = so.journey_id && so.ts_ms && so.lat_deg && so.lon_deg && so.speed_mps;
         auto gk = S > 1 ? (full ? k_gather<true, true> : k_gather<true, false>)
                         : (full ? k_gather<false, true> : k_gather<false, false>);
-        hipLaunchKernelGGL(gk, dim3(cvh::grid_for(n, 256, 8192)), dim3(256), 0, s, nn, L.meta, L.K0, L.K1, L.dl0,
+        hipLaunchKernelGGL(gk, dim3(cvh::grid_for(n, 256, 8192)), dim3(256), 0, s, nn, L.meta, L.K0, L.K1, dict_ids,
                            in->journey_id, in->ts_ms, in->lat_deg, in->lon_deg, in->speed_mps, perm,
                            so.journey_id, so.ts_ms, so.lat_deg, so.lon_deg, so.speed_mps, soff, S);
     }

@@ -94,20 +94,56 @@ def _batched(cv, shards, grid):
         check_groups({k: v[int(go[s]):int(go[s + 1])] for k, v in bp.groups.items()}, int(sout[s]),
                      exp["groups"], exp["n_out"])
     J = len(np.unique(allc[0]))
-    return res[0]["key_bits"], J, len(shards)
+    # an id in two shards keeps the shard above the rank in the key; otherwise
+    # the ranks follow (shard, id) order and keep the shards apart themselves
+    seen = {}
+    for s, sh in enumerate(shards):
+        for x in np.unique(sh[0]):
+            seen.setdefault(int(x), set()).add(s)
+    multi = any(len(v) > 1 for v in seen.values())
+    return res[0]["key_bits"], J, len(shards), multi
 
 
 def test_batched_shards_each_in_time_order(cv):
     # every shard is time-ordered, and each later shard starts earlier in time
     # than the one before it ends: the shard starts are not decreases
     shards = [_feed(100 + i, m, 40) for i, m in enumerate([3000, 1, 70_000, 5000, 64, 40_000])]
-    kb, J, S = _batched(cv, shards, gen.GRIDS["c2"])
-    assert kb == _bits(S - 1) + _bits(J - 1)
+    kb, J, S, multi = _batched(cv, shards, gen.GRIDS["c2"])
+    assert not multi and kb == _bits(J - 1)
 
 
 def test_batched_decrease_inside_one_shard(cv):
     shards = [_feed(200 + i, m, 40) for i, m in enumerate([3000, 70_000, 5000])]
     shards[1][1][777] = shards[1][1][776] - 1
-    kb, J, S = _batched(cv, shards, gen.GRIDS["c2"])
+    kb, J, S, multi = _batched(cv, shards, gen.GRIDS["c2"])
     t = np.concatenate([s[1] for s in shards])
-    assert kb == _bits(S - 1) + _bits(J - 1) + _bits(int(t.max() - t.min()))
+    assert not multi and kb == _bits(J - 1) + _bits(int(t.max() - t.min()))
+
+
+@pytest.mark.parametrize("where", ["boundary", "distant", "same_window"])
+def test_batched_id_in_two_shards(cv, where):
+    # one journey id met in two shards: as the last record of one shard and
+    # the first of the next (a run of equal ids across the shard start), in
+    # shards far apart, or in two shards that start inside one window of 64
+    # records; the key then carries the shard above the rank
+    sizes = [3000, 70_000, 5000, 20, 40_000] if where != "same_window" else [3000, 10, 30, 5000]
+    shards = [_feed(300 + i, m, 40) for i, m in enumerate(sizes)]
+    x = int(shards[0][0][0])
+    if where == "boundary":
+        shards[0][0][-1] = x
+        shards[1][0][0] = x
+    elif where == "distant":
+        shards[4][0][777] = x
+    else:
+        shards[2][0][5] = x  # shards 1 and 2 start within 40 records of each other
+    kb, J, S, multi = _batched(cv, shards, gen.GRIDS["c2"])
+    assert multi and kb == _bits(S - 1) + _bits(J - 1)
+
+
+def test_batched_ids_repeat_across_many_shard_starts(cv):
+    # 40 shards whose ids are all distinct, many shard starts in one wave's
+    # range (tiny shards), each time-ordered: ranks in (shard, id) order
+    sizes = [1 + (i * 37) % 300 for i in range(40)]
+    shards = [_feed(500 + i, m, 3) for i, m in enumerate(sizes)]
+    kb, J, S, multi = _batched(cv, shards, gen.GRIDS["c2"])
+    assert not multi and kb == _bits(J - 1)

@@ -627,7 +627,7 @@ __global__ void __launch_bounds__(256) k_pack_hist(const i64* __restrict__ jid, 
 // the regrouped positions, and each payload carries its input index.  After
 // the sort, consecutive records of a journey then read consecutive payloads
 // of each tile instead of one cache line per record.
-constexpr int PT_B = 512;                // threads per block
+constexpr int PT_B = 1024;               // threads per block (tiles of 4 096 records: half the per-tile scans and barriers of 2 048)
 constexpr int PT_I = 4;                  // records per thread
 constexpr int PT = PT_B * PT_I;          // records per tile
 template <bool SHARDS>

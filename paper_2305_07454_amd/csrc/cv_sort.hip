@@ -51,6 +51,10 @@ struct SortMeta {
     u32 unordered;  // a timestamp below its predecessor's (same shard) in input order
     u32 ts_dropped; // key = (shard, rank) only: the input is time-ordered within every shard
     u32 multi_shard; // batched: an id in more than one shard (ranks then in id order, shard bits in the key)
+    u32 t_nd5;       // bit b: some time offset is not a multiple of 5^(b+1) (b < 3)
+    u64 t_or;        // OR of every |ts - ts[0]|: its trailing zeros are the offsets' common power of two
+    u32 t_sh;        // the key's time offset is (ts - t_min) / (2^t_sh * t_p5): the offsets'
+    u32 t_p5;        //   common factor of the form 2^a 5^b (b <= 3), e.g. 1000 for 1 Hz in ms
     u32 tickets[3 * MAX_PASSES];
 };
 
@@ -172,6 +176,27 @@ __device__ __forceinline__ u32 dict_cache_slot(u64 key)
     return (u32)(mix64(key) >> 56) & (C - 1);
 }
 
+// bits 0..2: |d| not a multiple of 5, 25, 125
+__device__ __forceinline__ u32 not_div5(u64 ad)
+{
+    if ((ad >> 32) == 0) {
+        const u32 x = (u32)ad;
+        return (x % 5u ? 1u : 0u) | (x % 25u ? 2u : 0u) | (x % 125u ? 4u : 0u);
+    }
+    return (ad % 5ull ? 1u : 0u) | (ad % 25ull ? 2u : 0u) | (ad % 125ull ? 4u : 0u);
+}
+
+// the key's time offset: (ts - t_min) divided by the offsets' common factor
+// 2^sh 5^b (exact: every offset is a multiple of it)
+__device__ __forceinline__ u64 time_offset(u64 toff, u32 sh, u32 p5)
+{
+    u64 q = toff >> sh;
+    if (p5 == 5) q /= 5ull;
+    else if (p5 == 25) q /= 25ull;
+    else if (p5 == 125) q /= 125ull;
+    return q;
+}
+
 // Also checks whether the timestamps never decrease within a shard in input
 // order: then every journey's records already come in time order, and a
 // stable sort by (shard, journey) alone gives the (journey, time) order.
@@ -206,6 +231,11 @@ __global__ void __launch_bounds__(256) k_dict_insert(const i64* __restrict__ jid
     bool down = false;
     u32 shk = (S > 1 && wbeg < wend) ? shard_lower_bound(soff, S, wbeg * WAVE) : 0u;
     u32 csh = ~0u;  // the shard the wave's cache entries were met in (SHARDS)
+    // the time offsets' common factor: every |ts - ts[0]| ORed together (its
+    // trailing zeros) and which powers of five fail to divide one
+    const u64 t0r = n ? ord_i64(ts[0]) : 0ull;
+    u64 tor = 0;
+    u32 nd5 = 0;
     for (u64 w0 = wbeg; w0 < wend; w0 += DP) {
         i64 jv[DP];
         u64 tv[DP];
@@ -252,6 +282,10 @@ __global__ void __launch_bounds__(256) k_dict_insert(const i64* __restrict__ jid
             if (valid) {
                 lo = tv[k] < lo ? tv[k] : lo;
                 hi = tv[k] > hi ? tv[k] : hi;
+                const u64 d = tv[k] - t0r;  // ts - ts[0] modulo 2^64 (the order map adds the same 2^63)
+                const u64 ad = (i64)d < 0 ? 0ull - d : d;
+                tor |= ad;
+                if (nd5 != 7u) nd5 |= not_div5(ad);
             }
             const bool sstart = (starts[k] >> l) & 1ull;
             {
@@ -329,6 +363,15 @@ __global__ void __launch_bounds__(256) k_dict_insert(const i64* __restrict__ jid
     if (has_min) atomicOr(&m->has_min, 1u);
     if (full) atomicOr(&m->overflow, 1u);
     if (SHARDS && __ballot(multi) && l == 0) atomicOr(&m->multi_shard, 1u);
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        tor |= __shfl_xor(tor, d, WAVE);
+        nd5 |= __shfl_xor(nd5, d, WAVE);
+    }
+    if (l == 0) {
+        if (tor) atomicOr((unsigned long long*)&m->t_or, (unsigned long long)tor);
+        if (nd5) atomicOr(&m->t_nd5, nd5);
+    }
     if (__ballot(down) && l == 0) atomicOr(&m->unordered, 1u);
     if (runs && l == 0) atomicAdd(&m->n_runs, runs);
     __syncthreads();
@@ -385,6 +428,13 @@ __global__ void k_dict_meta(SortMeta* m, u32 max_j, u32 n, u32 n_shards)
     m->dict_n = J < max_j ? J : max_j;
     u32 rb = J > 1 ? bit_width64((u64)J - 1) : 0;
     u64 span = n ? (unord_i64(m->tmax_ord) - (u64)unord_i64(m->tmin_ord)) : 0;
+    // the offsets' common factor 2^a 5^b (1 when the time stamps are all equal)
+    u32 a = m->t_or ? (u32)__ffsll((long long)m->t_or) - 1u : 0u;
+    u32 p5 = (m->t_nd5 & 1u) ? 1u : (m->t_nd5 & 2u) ? 5u : (m->t_nd5 & 4u) ? 25u : 125u;
+    if (!m->t_or) p5 = 1;
+    m->t_sh = a;
+    m->t_p5 = p5;
+    span = (span >> a) / p5;
     // time-ordered input needs no time bits in the key (see the insert)
     m->ts_dropped = m->unordered ? 0u : 1u;
     u32 tb = m->ts_dropped ? 0u : bit_width64(span);
@@ -528,6 +578,7 @@ __global__ void __launch_bounds__(256) k_pack_hist(const i64* __restrict__ jid, 
     const u32 ib = m->ib;
     const bool packed = m->p0 == 0;
     const u64 tmin = (u64)unord_i64(m->tmin_ord);
+    const u32 tsh = m->t_sh, tp5 = m->t_p5;
     const int l = lane_id();
     const u64 nw = (u64)gridDim.x * (blockDim.x / WAVE);
     const u64 nwin = ((u64)n + WAVE - 1) / WAVE;
@@ -589,7 +640,7 @@ __global__ void __launch_bounds__(256) k_pack_hist(const i64* __restrict__ jid, 
             u64 key = 0;
             if (valid) {
                 if (!bad) {
-                    key = tdrop ? (u64)r : ((tb >= 64 ? 0ull : ((u64)r << tb)) | (tv[k] - tmin));
+                    key = tdrop ? (u64)r : ((tb >= 64 ? 0ull : ((u64)r << tb)) | time_offset(tv[k] - tmin, tsh, tp5));
                     if (SHARDS && m->shard_bits) {
                         // the window's first shard, then forward to this record's
                         shw = __builtin_amdgcn_readfirstlane(shard_from(soff, S, shw, wi * WAVE));
@@ -664,6 +715,7 @@ __global__ void __launch_bounds__(PT_B) k_pack_il(const i64* __restrict__ jid, c
     // from those counts, one add per digit and tile
     const u32 p_first = (group && tdrop && !bad && rbits >= (u32)RADIX_BITS && np > 0) ? 1u : 0u;
     const u64 tmin = (u64)unord_i64(m->tmin_ord);
+    const u32 tsh = m->t_sh, tp5 = m->t_p5;
     const ulonglong2* t2 = (const ulonglong2*)table;
     const u64 tiles = ((u64)n + PT - 1) / PT;
     const u64 per = (tiles + gridDim.x - 1) / gridDim.x;
@@ -733,7 +785,7 @@ __global__ void __launch_bounds__(PT_B) k_pack_il(const i64* __restrict__ jid, c
             const bool valid = i < n;
             key[k] = 0;
             if (valid && !bad) {
-                key[k] = tdrop ? (u64)rk[k] : ((tb >= 64 ? 0ull : ((u64)rk[k] << tb)) | (tv[k] - tmin));
+                key[k] = tdrop ? (u64)rk[k] : ((tb >= 64 ? 0ull : ((u64)rk[k] << tb)) | time_offset(tv[k] - tmin, tsh, tp5));
                 if (SHARDS && sbits) {
                     shw = __builtin_amdgcn_readfirstlane(shard_from(soff, S, shw, base + (u64)k * WAVE));
                     const u32 sh = shard_from(soff, S, shw, i);
@@ -841,6 +893,7 @@ __global__ void __launch_bounds__(256) k_gather(u32 n, const SortMeta* m, const 
     const bool ts_in_key = exact && drop == 0 && !m->ts_dropped;
     const u64 tmin = (u64)unord_i64(m->tmin_ord);
     const u64 tmask = tb >= 64 ? ~0ull : ((1ull << tb) - 1);
+    const u64 tdiv = ((u64)m->t_p5) << m->t_sh;  // the time offset's unit
     const u64* K = (np & 1) ? K1 : K0;
     const u32 stride = gridDim.x * blockDim.x;
     for (u32 k0 = blockIdx.x * blockDim.x + threadIdx.x; k0 < n; k0 += GU * stride) {
@@ -877,7 +930,7 @@ __global__ void __launch_bounds__(256) k_gather(u32 n, const SortMeta* m, const 
             }
             if (ts_in_key) {
 #pragma unroll
-                for (int u = 0; u < GU; ++u) ot[u] = (i64)(tmin + ((wv[u] >> ib) & tmask));
+                for (int u = 0; u < GU; ++u) ot[u] = (i64)(tmin + ((wv[u] >> ib) & tmask) * tdiv);
             } else {
 #pragma unroll
                 for (int u = 0; u < GU; ++u) ot[u] = ts[vv[u]];
@@ -918,7 +971,7 @@ __global__ void __launch_bounds__(256) k_gather(u32 n, const SortMeta* m, const 
                     const u64 r = rshift >= 64 ? 0ull : ((w >> rshift) & rmask);
                     o_jid[k] = (rank_in_key && r < dn) ? (i64)(dict_sorted[r] ^ SIGN) : jid[v];
                 }
-                if (o_ts) o_ts[k] = ts_in_key ? (i64)(tmin + ((w >> ib) & tmask)) : ts[v];
+                if (o_ts) o_ts[k] = ts_in_key ? (i64)(tmin + ((w >> ib) & tmask) * tdiv) : ts[v];
                 if (o_lat) o_lat[k] = lat[v];
                 if (o_lon) o_lon[k] = lon[v];
                 if (o_spd) o_spd[k] = spd[v];
@@ -1069,6 +1122,7 @@ __global__ void __launch_bounds__(256) k_gather_feat(u32 n, const SortMeta* m, c
     const bool ts_in_key = exact && drop == 0 && !m->ts_dropped;
     const u64 tmin = (u64)unord_i64(m->tmin_ord);
     const u64 tmask = tb >= 64 ? ~0ull : ((1ull << tb) - 1);
+    const u64 tdiv = ((u64)m->t_p5) << m->t_sh;  // the time offset's unit
     const u64* K = (m->passes & 1) ? K1 : K0;
     const int t = threadIdx.x;
     const int w = t / WAVE;
@@ -1136,7 +1190,7 @@ __global__ void __launch_bounds__(256) k_gather_feat(u32 n, const SortMeta* m, c
     }
     if (ts_in_key) {
 #pragma unroll
-        for (int u = 0; u < NS; ++u) ot[u] = (i64)(tmin + ((wv[u] >> ib) & tmask));
+        for (int u = 0; u < NS; ++u) ot[u] = (i64)(tmin + ((wv[u] >> ib) & tmask) * tdiv);
     } else if (packed) {
 #pragma unroll
         for (int u = 0; u < NS; ++u) ot[u] = pts[u];

@@ -74,6 +74,7 @@ def test_one_decrease_keeps_the_time_bits(cv, where):
     cols[1][p] = cols[1][p - 1] - 1  # the only place where time goes back
     got = _run_both(cv, cols, gen.GRIDS["c1"])
     J = len(np.unique(cols[0]))
+    # the decrease by 1 ms leaves the offsets no common factor above 1
     tspan = int(cols[1].max() - cols[1].min())
     assert got["sort_result"]["key_bits"] == _bits(J - 1) + _bits(tspan)
 

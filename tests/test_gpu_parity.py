@@ -340,6 +340,33 @@ def test_summary_flags_column_at_any_alignment(cv):
         assert torch.equal(a[k], b[k]), k
 
 
+@pytest.mark.parametrize("unit,factor", [(1000, 1000), (50, 50), (1024, 1024), (375, 125), (7, 1), (2 ** 40, 2 ** 40)])
+def test_time_offsets_common_factor(cv, unit, factor):
+    # time stamps on a grid of `unit` ms (a sampling period), unordered: the
+    # key's time offset is divided by the offsets' common factor of the form
+    # 2^a 5^b, so it needs fewer bits; the sorted time stamps, decoded from the
+    # key, must equal the oracle's exactly
+    rng = np.random.default_rng(unit % 997 + 3)
+    n, n_ids = 40_000, 300
+    ids = rng.choice(np.arange(-2 ** 40, 2 ** 40, 7919, dtype=np.int64), n_ids, replace=False)
+    jid = ids[rng.integers(0, n_ids, n)]
+    steps = rng.integers(0, 5000, n).astype(np.int64)
+    steps[:3] = [0, 1, 2]  # consecutive multiples: the common factor is unit's own
+    ts = gen.T0_MS - 123 * unit + unit * steps
+    lat = rng.uniform(36.0, 40.6, n)
+    lon = rng.uniform(-95.8, -89.1, n)
+    spd = rng.uniform(0, 40, n).astype(np.float32)
+    got, exp = _run_both(cv, (jid, ts, lat, lon, spd), gen.GRIDS["c0"])
+    _check_all(got, exp)
+    span = int(ts.max() - ts.min())
+    assert span % factor == 0
+    assert got["sort_result"]["key_bits"] == _bw(n_ids - 1) + _bw(span // factor)
+
+
+def _bw(x):
+    return int(x).bit_length()
+
+
 @pytest.mark.parametrize("bin_ms", [1, 7, 60_000, 2 ** 30 - 1, 2 ** 30, 2 ** 31 + 5])
 def test_time_bins_across_offset_ranges(cv, bin_ms):
     # an unbounded time axis, so every time bin is a key: offsets from t0

@@ -536,6 +536,35 @@ cv_status cv_timing_reset(void);
 cv_status cv_timing_read(const char* family /*[host]*/, double* total_ms /*[host]*/,
                          uint64_t* launches /*[host]*/);
 
+/* ------------------------------------------------------------------------
+ * Checking build.  A library compiled with CVETL_DEBUG (libcvetl_debug.so)
+ * runs small checker kernels after each stage; a failed check sets a bit of
+ * a per-device flag word (no trap, no change to any output):
+ *   CV_DEBUG_SORT_ORDER     the sort's final words are not strictly
+ *                           ascending (each is its key bits above its record
+ *                           index, so order and stability are both checked)
+ *   CV_DEBUG_PERM_RANGE     a perm entry outside its shard (or [0, n))
+ *   CV_DEBUG_JOURNEY_ORDER  a summary's journey ids not strictly ascending
+ *                           within a shard
+ *   CV_DEBUG_GROUP_ORDER    a group table's keys not strictly ascending within
+ *                           a shard, or a row with distinct journeys outside
+ *                           [1, count]
+ *   CV_DEBUG_CHECK          set by cv_debug_check_ascending
+ * Stage checks need the call's cv_result (res) to bound the rows.
+ * cv_debug_flags -- synchronises the current device, copies its flag word to
+ *   *flags [host] and clears it when reset != 0.
+ * cv_debug_check_ascending -- enqueues the order check on a caller's device
+ *   array of n uint64 values (n < 2^32) on stream (a test of the checker).
+ * Both return CV_ERR_UNSUPPORTED in the release build.
+ * --------------------------------------------------------------------- */
+#define CV_DEBUG_SORT_ORDER 0x01u
+#define CV_DEBUG_PERM_RANGE 0x02u
+#define CV_DEBUG_JOURNEY_ORDER 0x04u
+#define CV_DEBUG_GROUP_ORDER 0x08u
+#define CV_DEBUG_CHECK 0x10u
+cv_status cv_debug_flags(uint32_t* flags /*[host]*/, int reset);
+cv_status cv_debug_check_ascending(const uint64_t* a, uint64_t n, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,4 +1,6 @@
-"""Build the gfx950 HIP library ``libcvetl.so`` in place (hipcc, no JIT cache).
+"""Build the gfx950 HIP libraries in place (hipcc, no JIT cache): ``libcvetl.so``
+and the checking build ``libcvetl_debug.so`` (``-DCVETL_DEBUG``: checker kernels
+after each stage, see cv_debug_flags in the header).
 
 Every HIP source is compiled for gfx950 only, with IEEE double division and
 no floating-point contraction (``-ffp-contract=off``) so that kinematics and
@@ -19,6 +21,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libcvetl.so")
+DEBUG_LIB = os.path.join(PKG, "libcvetl_debug.so")  # the checking build (CVETL_DEBUG)
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
@@ -32,28 +35,36 @@ def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+def _compile(job) -> str:
+    src, debug = job
+    obj = os.path.join(BUILD, ("debug_" if debug else "") + os.path.basename(src) + ".o")
+    cmd = [HIPCC, *FLAGS, *(["-DCVETL_DEBUG"] if debug else []), "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{r.stdout}\n{r.stderr}")
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(BUILD, exist_ok=True)
-    srcs = sources()
-    with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        objs = list(ex.map(_compile, srcs))
-    tmp = LIB + ".tmp"
+def _link(objs, out):
+    tmp = out + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
+
+
+def build(verbose: bool = False) -> str:
+    """Both libraries: libcvetl.so and the checking build libcvetl_debug.so."""
+    os.makedirs(BUILD, exist_ok=True)
+    srcs = sources()
+    jobs = [(src, False) for src in srcs] + [(src, True) for src in srcs]
+    with cf.ThreadPoolExecutor(max_workers=min(8, len(jobs))) as ex:
+        objs = list(ex.map(_compile, jobs))
+    _link(objs[:len(srcs)], LIB)
+    _link(objs[len(srcs):], DEBUG_LIB)
     if verbose:
-        print(f"built {LIB}")
+        print(f"built {LIB} and {DEBUG_LIB}")
     return LIB
 
 

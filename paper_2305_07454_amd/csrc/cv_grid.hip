@@ -540,6 +540,7 @@ static cv_status grid_impl(const cv_records* sorted, const u64* soff, u32 S, con
         hipLaunchKernelGGL(k_gpart_emit, dim3(eg), dim3(ECB), 0, s, L.meta, L.K0, L.K1, L.V0, L.V1, L.part, L.hcnt,
                            (u32)capacity, out->key, out->count, out->n_journeys, out->sum_speed, out->min_speed,
                            out->max_speed, go, S, g.kb, kmask, res);
+        cvh::debug_rows(out->key, out->count, out->n_journeys, res, capacity, go, S, CV_DEBUG_GROUP_ORDER, s);
     }
     return cvh::last_launch_status();
 }

@@ -55,6 +55,13 @@ cv_status last_launch_status();
 void fill_u32(void* p, uint32_t v, uint64_t n, hipStream_t s);
 void fill_u64(void* p, uint64_t v, uint64_t n, hipStream_t s);
 
+// Checking build (CVETL_DEBUG): checker kernels after the sort and after the
+// rows of a summary or grid call; nothing in the release build.
+void debug_sort(const void* K0, const void* K1, const uint32_t* passes, const uint32_t* err0, const uint32_t* err1,
+                uint64_t n, const uint32_t* perm, const uint64_t* soff, uint32_t S, hipStream_t s);
+void debug_rows(const int64_t* keys, const uint32_t* cnt, const uint32_t* nj, const cv_result* res, uint64_t cap,
+                const uint64_t* off, uint32_t S, uint32_t bit, hipStream_t s);
+
 inline int grid_for(uint64_t n, int block, int cap = 1 << 30)
 {
     uint64_t g = (n + block - 1) / block;

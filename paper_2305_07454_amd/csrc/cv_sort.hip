@@ -1407,6 +1407,7 @@ static cv_status sort_impl(const cv_records* in, const uint64_t* soff, uint32_t 
                            in->journey_id, in->ts_ms, in->lat_deg, in->lon_deg, in->speed_mps, perm,
                            so.journey_id, so.ts_ms, so.lat_deg, so.lon_deg, so.speed_mps, soff, S);
     }
+    cvh::debug_sort(L.K0, L.K1, &L.meta->passes, &L.meta->range_err, &L.meta->overflow, n, perm, soff, S, s);
     if (res) hipLaunchKernelGGL(k_sort_finish, dim3(1), dim3(64), 0, s, L.meta, res);
     return cvh::last_launch_status();
 }

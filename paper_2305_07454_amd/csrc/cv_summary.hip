@@ -727,6 +727,7 @@ static cv_status summary_impl(const cv_records* sorted, const cv_features* feat,
     }
     hipLaunchKernelGGL(k_sum_finalize, dim3(cvh::grid_for(cap, 256, 2048)), dim3(256), 0, s, L.acc, L.accx, L.meta, cap, o,
                        sorted->ts_ms, res, soff, S, jo, nn);
+    cvh::debug_rows(out->journey_id, nullptr, nullptr, res, cap, jo, S, CV_DEBUG_JOURNEY_ORDER, s);
     return cvh::last_launch_status();
 }
 

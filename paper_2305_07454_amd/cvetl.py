@@ -42,6 +42,7 @@ GROUP_FIELDS = (("key", torch.int64), ("count", torch.int32), ("n_journeys", tor
 
 CV_OK, CV_ERR_INVALID_ARGUMENT, CV_ERR_WORKSPACE, CV_ERR_CAPACITY = 0, 1, 2, 3
 CV_ERR_RANGE, CV_ERR_DEVICE, CV_ERR_UNSUPPORTED = 4, 5, 6
+CV_DEBUG_SORT_ORDER, CV_DEBUG_PERM_RANGE, CV_DEBUG_JOURNEY_ORDER, CV_DEBUG_GROUP_ORDER, CV_DEBUG_CHECK = 1, 2, 4, 8, 16
 
 FLAG_FIRST, FLAG_DT_ZERO, FLAG_SPEED_OK, FLAG_ACCEL_OK = 0x01, 0x02, 0x04, 0x08
 FLAG_BEARING_OK, FLAG_DHEAD_OK, FLAG_BAD_COORD = 0x10, 0x20, 0x40
@@ -88,126 +89,153 @@ class CvError(RuntimeError):
         super().__init__(f"{where}: {strerror(status)} (status {status})")
 
 
-_lib = None
+DEBUG_LIB_PATH = os.path.join(PKG, "libcvetl_debug.so")
+_libs = {}
+_active = "release"
 
 
 def lib():
-    """Load libcvetl.so; raises if it has not been built (no fallback path)."""
-    global _lib
-    if _lib is None:
-        if not os.path.exists(LIB_PATH):
-            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2305_07454_amd/build.py "
+    """The active library (libcvetl.so unless use_library("debug") chose the
+    checking build); raises if it has not been built (no fallback path)."""
+    return _load(_active)
+
+
+def use_library(kind: str) -> str:
+    """Make "release" (libcvetl.so) or "debug" (libcvetl_debug.so, built with
+    CVETL_DEBUG: checker kernels after each stage, see cv_debug_flags) the
+    library every call of this module goes through; returns the previous one."""
+    global _active
+    if kind not in ("release", "debug"):
+        raise ValueError(kind)
+    _load(kind)
+    prev, _active = _active, kind
+    return prev
+
+
+def _load(kind):
+    if kind not in _libs:
+        path = LIB_PATH if kind == "release" else DEBUG_LIB_PATH
+        if not os.path.exists(path):
+            raise ImportError(f"{path} is missing: build it with paper_2305_07454_amd/build.py "
                               "(hipcc --offload-arch=gfx950); there is no CPU fallback")
-        L = ctypes.CDLL(LIB_PATH)
-        S = ctypes.c_int
-        U64 = ctypes.c_uint64
-        SZ = ctypes.POINTER(ctypes.c_size_t)
-        L.cv_abi_version.restype = ctypes.c_uint32
-        L.cv_strerror.argtypes = [S]
-        L.cv_strerror.restype = ctypes.c_char_p
-        L.cv_sort_workspace_size.argtypes = [U64, U64, SZ]
-        L.cv_sort_workspace_size.restype = S
-        L.cv_sort_records.argtypes = [ctypes.POINTER(CvRecords), U64, P, ctypes.POINTER(CvRecordsOut), P, P,
-                                      ctypes.c_size_t, P]
-        L.cv_sort_records.restype = S
-        L.cv_sort_records_features.argtypes = [ctypes.POINTER(CvRecords), U64, P, ctypes.POINTER(CvRecordsOut),
-                                               ctypes.POINTER(CvFeatures), P, P, ctypes.c_size_t, P]
-        L.cv_sort_records_features.restype = S
-        L.cv_journey_features.argtypes = [ctypes.POINTER(CvRecords), ctypes.POINTER(CvFeatures), P]
-        L.cv_journey_features.restype = S
-        L.cv_summary_workspace_size.argtypes = [U64, U64, SZ]
-        L.cv_summary_workspace_size.restype = S
-        L.cv_journey_summary.argtypes = [ctypes.POINTER(CvRecords), ctypes.POINTER(CvFeatures),
-                                         ctypes.POINTER(CvJourneys), U64, P, P, ctypes.c_size_t, P]
-        L.cv_journey_summary.restype = S
-        L.cv_journey_summary_noalloc.argtypes = [ctypes.POINTER(CvRecords), ctypes.POINTER(CvFeatures),
-                                                 ctypes.POINTER(CvJourneys), U64, P, P]
-        L.cv_journey_summary_noalloc.restype = S
-        L.cv_grid_workspace_size.argtypes = [U64, ctypes.POINTER(CvGridSpec), U64, SZ]
-        L.cv_grid_workspace_size.restype = S
-        L.cv_grid_aggregate.argtypes = [ctypes.POINTER(CvRecords), ctypes.POINTER(CvGridSpec),
+        _libs[kind] = _declare(ctypes.CDLL(path))
+    return _libs[kind]
+
+
+def _declare(L):
+    """Argument and result types of every exported call."""
+    S = ctypes.c_int
+    U64 = ctypes.c_uint64
+    SZ = ctypes.POINTER(ctypes.c_size_t)
+    L.cv_abi_version.restype = ctypes.c_uint32
+    L.cv_strerror.argtypes = [S]
+    L.cv_strerror.restype = ctypes.c_char_p
+    L.cv_sort_workspace_size.argtypes = [U64, U64, SZ]
+    L.cv_sort_workspace_size.restype = S
+    L.cv_sort_records.argtypes = [ctypes.POINTER(CvRecords), U64, P, ctypes.POINTER(CvRecordsOut), P, P,
+                                  ctypes.c_size_t, P]
+    L.cv_sort_records.restype = S
+    L.cv_sort_records_features.argtypes = [ctypes.POINTER(CvRecords), U64, P, ctypes.POINTER(CvRecordsOut),
+                                           ctypes.POINTER(CvFeatures), P, P, ctypes.c_size_t, P]
+    L.cv_sort_records_features.restype = S
+    L.cv_journey_features.argtypes = [ctypes.POINTER(CvRecords), ctypes.POINTER(CvFeatures), P]
+    L.cv_journey_features.restype = S
+    L.cv_summary_workspace_size.argtypes = [U64, U64, SZ]
+    L.cv_summary_workspace_size.restype = S
+    L.cv_journey_summary.argtypes = [ctypes.POINTER(CvRecords), ctypes.POINTER(CvFeatures),
+                                     ctypes.POINTER(CvJourneys), U64, P, P, ctypes.c_size_t, P]
+    L.cv_journey_summary.restype = S
+    L.cv_journey_summary_noalloc.argtypes = [ctypes.POINTER(CvRecords), ctypes.POINTER(CvFeatures),
+                                             ctypes.POINTER(CvJourneys), U64, P, P]
+    L.cv_journey_summary_noalloc.restype = S
+    L.cv_grid_workspace_size.argtypes = [U64, ctypes.POINTER(CvGridSpec), U64, SZ]
+    L.cv_grid_workspace_size.restype = S
+    L.cv_grid_aggregate.argtypes = [ctypes.POINTER(CvRecords), ctypes.POINTER(CvGridSpec),
+                                    ctypes.POINTER(CvGroups), U64, P, P, ctypes.c_size_t, P]
+    L.cv_grid_aggregate.restype = S
+    U32 = ctypes.c_uint32
+    L.cv_batch_sort_records.argtypes = [ctypes.POINTER(CvRecords), P, U32, U64, P, ctypes.POINTER(CvRecordsOut),
+                                        P, P, ctypes.c_size_t, P]
+    L.cv_batch_sort_records.restype = S
+    L.cv_batch_sort_records_features.argtypes = [ctypes.POINTER(CvRecords), P, U32, U64, P,
+                                                 ctypes.POINTER(CvRecordsOut), ctypes.POINTER(CvFeatures), P, P,
+                                                 ctypes.c_size_t, P]
+    L.cv_batch_sort_records_features.restype = S
+    L.cv_batch_journey_features.argtypes = [ctypes.POINTER(CvRecords), P, U32, ctypes.POINTER(CvFeatures), P]
+    L.cv_batch_journey_features.restype = S
+    L.cv_batch_journey_summary.argtypes = [ctypes.POINTER(CvRecords), ctypes.POINTER(CvFeatures), P, U32,
+                                           ctypes.POINTER(CvJourneys), U64, P, P, P, ctypes.c_size_t, P]
+    L.cv_batch_journey_summary.restype = S
+    L.cv_batch_grid_aggregate.argtypes = [ctypes.POINTER(CvRecords), P, U32, ctypes.POINTER(CvGridSpec),
+                                          ctypes.POINTER(CvGroups), U64, P, P, P, ctypes.c_size_t, P]
+    L.cv_batch_grid_aggregate.restype = S
+    L.cv_stream_state_size.argtypes = [ctypes.POINTER(CvGridSpec), U64, U64, U64, SZ]
+    L.cv_stream_state_size.restype = S
+    L.cv_stream_create.argtypes = [ctypes.POINTER(CvGridSpec), U64, U64, U64, P, ctypes.c_size_t, P,
+                                   ctypes.POINTER(ctypes.c_void_p)]
+    L.cv_stream_create.restype = S
+    L.cv_stream_push.argtypes = [P, ctypes.POINTER(CvRecords), ctypes.POINTER(CvFeatures), P, P]
+    L.cv_stream_push.restype = S
+    L.cv_stream_flush.argtypes = [P, ctypes.POINTER(CvJourneys), U64, ctypes.POINTER(CvGroups), U64, P, P]
+    L.cv_stream_flush.restype = S
+    L.cv_stream_destroy.argtypes = [P]
+    L.cv_stream_destroy.restype = S
+    L.cv_batch_workspace_size.argtypes = [U64, ctypes.c_uint32, U64, U64, ctypes.POINTER(CvGridSpec), U64, SZ]
+    L.cv_batch_workspace_size.restype = S
+    L.cv_batch_run.argtypes = [ctypes.POINTER(CvRecords), P, ctypes.c_uint32, ctypes.POINTER(CvGridSpec), U64, P,
+                               ctypes.POINTER(CvRecordsOut), ctypes.POINTER(CvFeatures), ctypes.POINTER(CvJourneys),
+                               U64, P, ctypes.POINTER(CvGroups), U64, P, P, P, P, ctypes.c_size_t, P]
+    L.cv_batch_run.restype = S
+    L.cv_stream_snapshot_size.argtypes = [P, SZ]
+    L.cv_stream_snapshot_size.restype = S
+    L.cv_stream_snapshot.argtypes = [P, P, ctypes.c_size_t, P]
+    L.cv_stream_snapshot.restype = S
+    L.cv_stream_restore.argtypes = [P, P, ctypes.c_size_t, P]
+    L.cv_stream_restore.restype = S
+    L.cv_grid_aggregate_dir.argtypes = [ctypes.POINTER(CvRecords), P, ctypes.POINTER(CvFeatures),
+                                        ctypes.POINTER(CvGridSpec), U32, ctypes.c_double,
                                         ctypes.POINTER(CvGroups), U64, P, P, ctypes.c_size_t, P]
-        L.cv_grid_aggregate.restype = S
-        U32 = ctypes.c_uint32
-        L.cv_batch_sort_records.argtypes = [ctypes.POINTER(CvRecords), P, U32, U64, P, ctypes.POINTER(CvRecordsOut),
-                                            P, P, ctypes.c_size_t, P]
-        L.cv_batch_sort_records.restype = S
-        L.cv_batch_sort_records_features.argtypes = [ctypes.POINTER(CvRecords), P, U32, U64, P,
-                                                     ctypes.POINTER(CvRecordsOut), ctypes.POINTER(CvFeatures), P, P,
-                                                     ctypes.c_size_t, P]
-        L.cv_batch_sort_records_features.restype = S
-        L.cv_batch_journey_features.argtypes = [ctypes.POINTER(CvRecords), P, U32, ctypes.POINTER(CvFeatures), P]
-        L.cv_batch_journey_features.restype = S
-        L.cv_batch_journey_summary.argtypes = [ctypes.POINTER(CvRecords), ctypes.POINTER(CvFeatures), P, U32,
-                                               ctypes.POINTER(CvJourneys), U64, P, P, P, ctypes.c_size_t, P]
-        L.cv_batch_journey_summary.restype = S
-        L.cv_batch_grid_aggregate.argtypes = [ctypes.POINTER(CvRecords), P, U32, ctypes.POINTER(CvGridSpec),
-                                              ctypes.POINTER(CvGroups), U64, P, P, P, ctypes.c_size_t, P]
-        L.cv_batch_grid_aggregate.restype = S
-        L.cv_stream_state_size.argtypes = [ctypes.POINTER(CvGridSpec), U64, U64, U64, SZ]
-        L.cv_stream_state_size.restype = S
-        L.cv_stream_create.argtypes = [ctypes.POINTER(CvGridSpec), U64, U64, U64, P, ctypes.c_size_t, P,
-                                       ctypes.POINTER(ctypes.c_void_p)]
-        L.cv_stream_create.restype = S
-        L.cv_stream_push.argtypes = [P, ctypes.POINTER(CvRecords), ctypes.POINTER(CvFeatures), P, P]
-        L.cv_stream_push.restype = S
-        L.cv_stream_flush.argtypes = [P, ctypes.POINTER(CvJourneys), U64, ctypes.POINTER(CvGroups), U64, P, P]
-        L.cv_stream_flush.restype = S
-        L.cv_stream_destroy.argtypes = [P]
-        L.cv_stream_destroy.restype = S
-        L.cv_batch_workspace_size.argtypes = [U64, ctypes.c_uint32, U64, U64, ctypes.POINTER(CvGridSpec), U64, SZ]
-        L.cv_batch_workspace_size.restype = S
-        L.cv_batch_run.argtypes = [ctypes.POINTER(CvRecords), P, ctypes.c_uint32, ctypes.POINTER(CvGridSpec), U64, P,
-                                   ctypes.POINTER(CvRecordsOut), ctypes.POINTER(CvFeatures), ctypes.POINTER(CvJourneys),
-                                   U64, P, ctypes.POINTER(CvGroups), U64, P, P, P, P, ctypes.c_size_t, P]
-        L.cv_batch_run.restype = S
-        L.cv_stream_snapshot_size.argtypes = [P, SZ]
-        L.cv_stream_snapshot_size.restype = S
-        L.cv_stream_snapshot.argtypes = [P, P, ctypes.c_size_t, P]
-        L.cv_stream_snapshot.restype = S
-        L.cv_stream_restore.argtypes = [P, P, ctypes.c_size_t, P]
-        L.cv_stream_restore.restype = S
-        L.cv_grid_aggregate_dir.argtypes = [ctypes.POINTER(CvRecords), P, ctypes.POINTER(CvFeatures),
-                                            ctypes.POINTER(CvGridSpec), U32, ctypes.c_double,
-                                            ctypes.POINTER(CvGroups), U64, P, P, ctypes.c_size_t, P]
-        L.cv_grid_aggregate_dir.restype = S
-        L.cv_gather_column.argtypes = [P, P, P, U64, U32, P]
-        L.cv_gather_column.restype = S
-        L.cv_lattice_dense.argtypes = [ctypes.POINTER(CvGroups), U64, ctypes.POINTER(CvGridSpec), U32,
-                                       ctypes.c_int64, U64, P, P]
-        L.cv_lattice_dense.restype = S
-        L.cv_lattice_normalize_workspace_size.argtypes = [U64, ctypes.POINTER(CvGridSpec), U32, SZ]
-        L.cv_lattice_normalize_workspace_size.restype = S
-        L.cv_lattice_normalize.argtypes = [P, U64, ctypes.POINTER(CvGridSpec), U32, P, P, ctypes.c_size_t, P]
-        L.cv_lattice_normalize.restype = S
-        L.cv_groups_filter_workspace_size.argtypes = [U64, SZ]
-        L.cv_groups_filter_workspace_size.restype = S
-        L.cv_groups_filter.argtypes = [ctypes.POINTER(CvGroups), U64, ctypes.c_double, ctypes.c_double,
-                                       ctypes.c_double, P, U64, P, P, ctypes.c_size_t, P]
-        L.cv_groups_filter.restype = S
-        L.cv_hygiene_workspace_size.argtypes = [U64, SZ]
-        L.cv_hygiene_workspace_size.restype = S
-        L.cv_drop_duplicates.argtypes = [ctypes.POINTER(CvRecords), P, ctypes.POINTER(CvRecordsOut), P, P, P,
-                                         ctypes.c_size_t, P]
-        L.cv_drop_duplicates.restype = S
-        L.cv_split_trips.argtypes = [ctypes.POINTER(CvRecords), ctypes.c_int64, P, P, U64, P, P, ctypes.c_size_t, P]
-        L.cv_split_trips.restype = S
-        L.cv_csv_workspace_size.argtypes = [U64, U64, SZ]
-        L.cv_csv_workspace_size.restype = S
-        L.cv_csv_extract.argtypes = [P, U64, ctypes.c_int32, ctypes.POINTER(CvRecordsOut), P, P, U64, P, P,
+    L.cv_grid_aggregate_dir.restype = S
+    L.cv_gather_column.argtypes = [P, P, P, U64, U32, P]
+    L.cv_gather_column.restype = S
+    L.cv_lattice_dense.argtypes = [ctypes.POINTER(CvGroups), U64, ctypes.POINTER(CvGridSpec), U32,
+                                   ctypes.c_int64, U64, P, P]
+    L.cv_lattice_dense.restype = S
+    L.cv_lattice_normalize_workspace_size.argtypes = [U64, ctypes.POINTER(CvGridSpec), U32, SZ]
+    L.cv_lattice_normalize_workspace_size.restype = S
+    L.cv_lattice_normalize.argtypes = [P, U64, ctypes.POINTER(CvGridSpec), U32, P, P, ctypes.c_size_t, P]
+    L.cv_lattice_normalize.restype = S
+    L.cv_groups_filter_workspace_size.argtypes = [U64, SZ]
+    L.cv_groups_filter_workspace_size.restype = S
+    L.cv_groups_filter.argtypes = [ctypes.POINTER(CvGroups), U64, ctypes.c_double, ctypes.c_double,
+                                   ctypes.c_double, P, U64, P, P, ctypes.c_size_t, P]
+    L.cv_groups_filter.restype = S
+    L.cv_hygiene_workspace_size.argtypes = [U64, SZ]
+    L.cv_hygiene_workspace_size.restype = S
+    L.cv_drop_duplicates.argtypes = [ctypes.POINTER(CvRecords), P, ctypes.POINTER(CvRecordsOut), P, P, P,
                                      ctypes.c_size_t, P]
-        L.cv_csv_extract.restype = S
-        L.cv_tuning_set.argtypes = [ctypes.c_char_p, ctypes.c_int64]
-        L.cv_tuning_set.restype = S
-        L.cv_tuning_get.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64)]
-        L.cv_tuning_get.restype = S
-        L.cv_timing_enable.argtypes = [S]
-        L.cv_timing_enable.restype = S
-        L.cv_timing_reset.restype = S
-        L.cv_timing_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(U64)]
-        L.cv_timing_read.restype = S
-        _lib = L
-    return _lib
+    L.cv_drop_duplicates.restype = S
+    L.cv_split_trips.argtypes = [ctypes.POINTER(CvRecords), ctypes.c_int64, P, P, U64, P, P, ctypes.c_size_t, P]
+    L.cv_split_trips.restype = S
+    L.cv_csv_workspace_size.argtypes = [U64, U64, SZ]
+    L.cv_csv_workspace_size.restype = S
+    L.cv_csv_extract.argtypes = [P, U64, ctypes.c_int32, ctypes.POINTER(CvRecordsOut), P, P, U64, P, P,
+                                 ctypes.c_size_t, P]
+    L.cv_csv_extract.restype = S
+    L.cv_tuning_set.argtypes = [ctypes.c_char_p, ctypes.c_int64]
+    L.cv_tuning_set.restype = S
+    L.cv_tuning_get.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64)]
+    L.cv_tuning_get.restype = S
+    L.cv_timing_enable.argtypes = [S]
+    L.cv_timing_enable.restype = S
+    L.cv_timing_reset.restype = S
+    L.cv_timing_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(U64)]
+    L.cv_timing_read.restype = S
+    L.cv_debug_flags.argtypes = [ctypes.POINTER(ctypes.c_uint32), S]
+    L.cv_debug_flags.restype = S
+    L.cv_debug_check_ascending.argtypes = [P, U64, P]
+    L.cv_debug_check_ascending.restype = S
+    return L
 
 
 def strerror(status) -> str:

@@ -108,3 +108,16 @@ def test_tuning_values_checked_before_narrowing(L):
     got = ctypes.c_int64()
     assert L.cv_tuning_get(b"sort_shape", ctypes.byref(got)) == 0 and got.value == prev.value
     assert L.cv_tuning_set(b"grid_lds_slots", ctypes.c_int64(256)) == cvetl.CV_ERR_INVALID_ARGUMENT
+
+
+def test_debug_entry_points_only_in_the_checking_build(L):
+    from paper_2305_07454_amd import cvetl
+    flags = ctypes.c_uint32(7)
+    assert L.cv_debug_flags(ctypes.byref(flags), 0) == cvetl.CV_ERR_UNSUPPORTED
+    assert L.cv_debug_check_ascending(None, 10, None) == cvetl.CV_ERR_UNSUPPORTED
+    # the checking build exports every declared symbol as well
+    if os.path.exists(cvetl.DEBUG_LIB_PATH):
+        D = ctypes.CDLL(cvetl.DEBUG_LIB_PATH)
+        for name in _declared():
+            assert hasattr(D, name), name
+        assert D.cv_debug_check_ascending(None, 10, None) == cvetl.CV_ERR_INVALID_ARGUMENT

@@ -61,6 +61,8 @@ def parse():
     ap.add_argument("--c4-rates", type=lambda x: [float(v) for v in x.split(",")], default=[200.0, 400.0, 600.0, 800.0],
                     help="c4: constant chunk rates of the sustained-rate sweep")
     ap.add_argument("--sweep-duration", type=float, default=6.0, help="c4: seconds per sweep rate")
+    ap.add_argument("--push-records", type=int, default=None,
+                    help="c3/c4: most records one push batches (default: a quarter of the ring)")
     ap.add_argument("--batched-steps", type=int, default=5, help="default run: timed steps of the batched form")
     ap.add_argument("--batched-only", action="store_true",
                     help="c2: time the batched form only (no per-shard loop or comparison; for profiler runs)")
@@ -321,7 +323,7 @@ def bench_serving(args, workload):
     arena = None
     for name, batching in (("batched", True), ("per_chunk", False)):
         srv = serve.Server(pool, grid, batching=batching, arena_records=arena, max_journeys=1 << 22,
-                           max_groups=max_groups)
+                           max_groups=max_groups, max_push_records=args.push_records)
         arena = srv.A  # both servers get the arena the first carved from free HBM
         chunks = srv.run(trace, keep_first=keep, log=lambda m: log(f"{name}: {m}"))
         out[name] = serve.latency_stats(chunks, warmup_s=min(2.0, dur / 5))
@@ -340,12 +342,13 @@ def bench_serving(args, workload):
     assert same, "batched and per-chunk serving differ"
     assert flags_clear, "a distinct-journey cell set overflowed: counts may be high"
     offered = sum(s for _, s in trace) / dur / 1e6
-    sweep = serving_rate_sweep(pool, grid, arena, max_groups, args.c4_rates, args.sweep_duration) if skew else None
+    sweep = serving_rate_sweep(pool, grid, arena, max_groups, args.c4_rates, args.sweep_duration,
+                               args.push_records) if skew else None
     return {
         "workload": f"{workload}: {desc}", "pool_records": pool.n, "chunks": len(trace),
         "offered_mrec_per_s": round(offered, 1), "arena_records": int(arena),
         "admission": "FIFO into a ring of record slots carved from free HBM at start-up; "
-                     "a push batches at most a quarter of the ring",
+                     f"a push batches at most {args.push_records or 'a quarter of the ring'} records",
         "value": out["batched"]["mrec_per_s"], "unit": "Mrecords/s",
         "latency_batched": out["batched"], "latency_per_chunk": out["per_chunk"],
         "identical_outputs": bool(same and flags_clear), "journeys": int(ra["count"]), "groups": int(rga["count"]),
@@ -353,7 +356,7 @@ def bench_serving(args, workload):
     }
 
 
-def serving_rate_sweep(pool, grid, arena, max_groups, rates, dur):
+def serving_rate_sweep(pool, grid, arena, max_groups, rates, dur, push_records=None):
     """The batched server at constant Poisson rates (same chunk sizes as the
     burst trace), a fresh server per rate.  A rate is sustained when the
     latency does not grow over the run: the p90 of the last third of the
@@ -363,10 +366,12 @@ def serving_rate_sweep(pool, grid, arena, max_groups, rates, dur):
     import torch
     from paper_2305_07454_amd import serve
     rows = []
-    for i, rate in enumerate(rates):
-        trace = serve.poisson_trace(np.random.default_rng(7000 + i), lambda tt, r=rate: r, dur, 10_000, 5_000_000)
+    for rate in rates:
+        # seeded by the rate itself, so a rate replays the same trace in any list
+        trace = serve.poisson_trace(np.random.default_rng(7000 + int(round(rate))), lambda tt, r=rate: r, dur,
+                                    10_000, 5_000_000)
         srv = serve.Server(pool, grid, batching=True, arena_records=arena, max_journeys=1 << 22,
-                           max_groups=max_groups)
+                           max_groups=max_groups, max_push_records=push_records)
         chunks = srv.run(trace)
         st = serve.latency_stats(chunks, warmup_s=min(1.0, dur / 5))
         lat = [c.t_done - c.arrival for c in chunks if c.arrival >= min(1.0, dur / 5)]

@@ -5,17 +5,28 @@
 // Pipeline (all stream-ordered, no host synchronisation):
 //   1. k_dict_insert  min/max timestamp; whether time never decreases within a
 //                     shard in input order (then the key needs no time bits);
-//                     distinct journey ids into an open-addressing hash set
-//                     (run-deduplicated);
+//                     the time offsets' common factor 2^a 5^b; distinct
+//                     journey ids into an open-addressing hash set
+//                     (run-deduplicated), batched: each id's slot tagged with
+//                     its shard, an id met in two shards flagged;
 //   2. k_dict_compact distinct ids -> list; radix sort of the list (signed order);
 //   3. k_dict_meta    journey count J, rank bits, time bits, key bits, passes;
-//   4. k_dict_rank    dense order-preserving rank of each distinct id;
-//   5. k_pack_hist    key = rank << t_bits | (ts - t_min) (or the rank alone
-//                     for time-ordered input) and the digit
-//                     histograms of every radix pass in the same read;
+//   4. k_dict_rank    dense order-preserving rank of each distinct id; batched:
+//                     k_dict_shardkey + a stable sort by shard + k_dict_final,
+//                     ranks in (shard, id) order (the shard then needs no
+//                     bits of its own in the key unless an id spans shards);
+//   5. k_pack_hist / k_pack_il
+//                     key = rank << t_bits | (ts - t_min) / factor (or the
+//                     rank alone for time-ordered input) and the digit
+//                     histograms of every radix pass in the same read; for
+//                     interleaved input k_pack_il also regroups each tile by
+//                     journey and packs the payload per record;
 //   6. radix passes   ceil(key_bits / 8) stable scatter passes (skipped on device);
-//   7. k_gather       perm, journey id from the dictionary, ts from the key,
-//                     lat/lon/speed gathered through perm.
+//   7. k_gather / k_gather_feat
+//                     perm, journey id from the dictionary, ts from the key
+//                     when it survives packing, lat/lon/speed through perm or
+//                     from the packed payload; k_gather_feat adds the
+//                     kinematics.
 #include <hip/hip_runtime.h>
 
 #include "cv_device.h"

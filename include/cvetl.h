@@ -260,6 +260,15 @@ cv_status cv_grid_workspace_size(uint64_t n, const cv_grid_spec* grid /*[host]*/
 cv_status cv_grid_aggregate(const cv_records* sorted, const cv_grid_spec* grid /*[host]*/,
                             const cv_groups* out, uint64_t capacity, cv_result* res, void* ws,
                             size_t ws_bytes, void* stream);
+/* cv_grid_aggregate_flags -- the same call with the journey starts taken from
+ *   flags [device, n]: the flags column of cv_journey_features for the same
+ *   sorted records (CV_FLAG_FIRST marks each journey's first record).  The
+ *   tile kernel then reads one byte per record instead of comparing each
+ *   journey id with its predecessor's; outputs and workspace are those of
+ *   cv_grid_aggregate.  flags NULL with n > 0: CV_ERR_INVALID_ARGUMENT. */
+cv_status cv_grid_aggregate_flags(const cv_records* sorted, const uint8_t* flags, const cv_grid_spec* grid /*[host]*/,
+                                  const cv_groups* out, uint64_t capacity, cv_result* res, void* ws, size_t ws_bytes,
+                                  void* stream);
 
 /* ------------------------------------------------------------------------
  * cv_grid_aggregate_dir -- the lattice with the direction dimension of

@@ -430,12 +430,12 @@ bool spec_ok(const cv_grid_spec* g)
 }  // namespace
 
 // the tile kernel for a direction source (0 none, 1 heading column, 2 bearing)
-template <int KD>
+template <int KD, bool FL = false>
 static void launch_parts(dim3 gg, hipStream_t s, u32 nn, const cv_records* sorted, const Spec& g, const PartSink& sk,
-                         GridMeta* meta)
+                         GridMeta* meta, const uint8_t* first = nullptr)
 {
-    hipLaunchKernelGGL((k_grid_part<KD>), gg, dim3(GB), 0, s, nn, sorted->journey_id, sorted->ts_ms, sorted->lat_deg,
-                       sorted->lon_deg, sorted->speed_mps, g, sk, meta);
+    hipLaunchKernelGGL((k_grid_part<KD, FL>), gg, dim3(GB), 0, s, nn, sorted->journey_id, sorted->ts_ms,
+                       sorted->lat_deg, sorted->lon_deg, sorted->speed_mps, g, sk, meta, first);
 }
 
 // exclusive scan of v[0, n) into out (n = *n_dev when given, at most n_max);
@@ -455,7 +455,7 @@ static void scan_counts(const u32* v, u32 n_max, const u32* n_dev, const u64* vm
 static cv_status grid_impl(const cv_records* sorted, const u64* soff, u32 S, const cv_grid_spec* grid,
                            const cv_groups* out, uint64_t capacity, u64* go, cv_result* res, void* ws, size_t ws_bytes,
                            void* stream, u32 nd = 0, double doff = 0.0, const float* hdg = nullptr,
-                           const cv_features* feat = nullptr, u64* sout = nullptr)
+                           const cv_features* feat = nullptr, u64* sout = nullptr, const uint8_t* first = nullptr)
 {
     if (!sorted || !out || sorted->n >= (1ull << 32) || capacity >= (1ull << 32) || !spec_ok(grid))
         return CV_ERR_INVALID_ARGUMENT;
@@ -516,7 +516,8 @@ static cv_status grid_impl(const cv_records* sorted, const u64* soff, u32 S, con
         if (sout) cvh::fill_u64(sout, 0ull, S ? S : 1, s);
         PartSink sk{L.K1, L.part, L.tcnt, L.tmax};
         const dim3 gg(tiles);
-        if (nd == 0) launch_parts<0>(gg, s, nn, sorted, g, sk, L.meta);
+        if (nd == 0 && first) launch_parts<0, true>(gg, s, nn, sorted, g, sk, L.meta, first);
+        else if (nd == 0) launch_parts<0>(gg, s, nn, sorted, g, sk, L.meta);
         else if (hdg) launch_parts<1>(gg, s, nn, sorted, g, sk, L.meta);
         else launch_parts<2>(gg, s, nn, sorted, g, sk, L.meta);
     }
@@ -560,6 +561,15 @@ cv_status cv_grid_aggregate(const cv_records* sorted, const cv_grid_spec* grid, 
                             uint64_t capacity, cv_result* res, void* ws, size_t ws_bytes, void* stream)
 {
     return grid_impl(sorted, nullptr, 0, grid, out, capacity, nullptr, res, ws, ws_bytes, stream);
+}
+
+cv_status cv_grid_aggregate_flags(const cv_records* sorted, const uint8_t* flags, const cv_grid_spec* grid,
+                                  const cv_groups* out, uint64_t capacity, cv_result* res, void* ws, size_t ws_bytes,
+                                  void* stream)
+{
+    if (!flags && sorted && sorted->n > 0) return CV_ERR_INVALID_ARGUMENT;
+    return grid_impl(sorted, nullptr, 0, grid, out, capacity, nullptr, res, ws, ws_bytes, stream, 0, 0.0, nullptr,
+                     nullptr, nullptr, flags);
 }
 
 cv_status cv_grid_aggregate_dir(const cv_records* sorted, const float* heading_deg, const cv_features* feat,
@@ -650,7 +660,7 @@ cv_status cv_batch_run(const cv_records* in, const uint64_t* shard_offsets, uint
                                  res + 1, ws, ws_bytes, stream);
     if (e != CV_OK) return e;
     return grid_impl(&srt, shard_offsets, n_shards, grid, groups, group_capacity, group_offsets, res + 2, ws,
-                     ws_bytes, stream, 0, 0.0, nullptr, nullptr, shard_n_out);
+                     ws_bytes, stream, 0, 0.0, nullptr, nullptr, shard_n_out, feat->flags);
 }
 
 }  // extern "C"

@@ -74,10 +74,14 @@ __device__ __forceinline__ GPart make_part(i64 jid, u64 lo, u64 hi, u32 cn, u32 
 // Four waves per SIMD for the plain key (what the LDS allows); the direction
 // forms carry a heading or bearing column too and keep three, which their
 // registers need without spilling.
-template <int KD>
+// FL: journey (and shard) starts come from the kinematics' FIRST flags, one
+// byte per record, instead of comparing journey ids with the predecessor's;
+// the ids are then read only for the partial rows.
+template <int KD, bool FL = false>
 __global__ void __launch_bounds__(GB) __attribute__((amdgpu_waves_per_eu(KD == 0 ? 4 : 3)))
 k_grid_part(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, const double* __restrict__ lat,
-            const double* __restrict__ lon, const float* __restrict__ spd, Spec g, PartSink sk, GridMeta* meta)
+            const double* __restrict__ lon, const float* __restrict__ spd, Spec g, PartSink sk, GridMeta* meta,
+            const uint8_t* __restrict__ first)
 {
     constexpr int NWG = GB / WAVE;
     constexpr int WREC = GT / NWG;  // consecutive records per wave in the aggregation
@@ -108,7 +112,8 @@ k_grid_part(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, cons
 
     // 1. the tile's records, rows of GB striped over the block (coalesced);
     //    every column is loaded first so that all loads are in flight together
-    i64 vj[GI], vt[GI], vtb[GI], vk[GI];
+    i64 vj[FL ? 1 : GI], vt[GI], vtb[GI], vk[GI];
+    uint8_t vfl[FL ? GI : 1];
     double vla[GI], vlo[GI];
     float vsp[GI];
     float vh[KD == 1 ? GI : 1];
@@ -118,7 +123,8 @@ k_grid_part(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, cons
     for (int rr = 0; rr < GI; ++rr) {
         u64 r = tile0 + (u64)(rr * GB + t);
         r = r < n ? r : (u64)n - 1;  // past the end: a record in range, not used
-        vj[rr] = jid[r];
+        if constexpr (FL) vfl[rr] = first[r];
+        else vj[rr] = jid[r];
         vt[rr] = ts[r];
         vla[rr] = lat[r];
         vlo[rr] = lon[r];
@@ -168,16 +174,22 @@ k_grid_part(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, cons
         }
         vtb[rr] = tb;
         vk[rr] = k;
-        const i64 jp = __shfl_up(vj[rr], 1, WAVE);
         const i64 tbp = __shfl_up(tb, 1, WAVE);
         const i64 kp = __shfl_up(k, 1, WAVE);
         if (lane == WAVE - 1) {
-            s_lj[rr][w] = vj[rr];
+            if constexpr (!FL) s_lj[rr][w] = vj[rr];
             s_ltb[rr][w] = tb;
             s_lk[rr][w] = k;
         }
         // lane 0 compares with lane 63 of the wave row before, below
-        const bool seg = sstart || (lane > 0 && (vj[rr] != jp || tb != tbp));
+        bool seg;
+        if constexpr (FL) {
+            // FIRST marks every journey start, shard starts included
+            seg = (in && (vfl[rr] & CV_FLAG_FIRST)) || (lane > 0 && tb != tbp);
+        } else {
+            const i64 jp = __shfl_up(vj[rr], 1, WAVE);
+            seg = sstart || (lane > 0 && (vj[rr] != jp || tb != tbp));
+        }
         const bool odd = in && spd_odd(vsp[rr]);
         // the tile's first record and the first record of every wave's share
         // of the aggregation start runs: no run is split between waves
@@ -199,7 +211,7 @@ k_grid_part(u32 n, const i64* __restrict__ jid, const i64* __restrict__ ts, cons
         const int pr = w > 0 ? rr : rr - 1;
         const int pw = w > 0 ? w - 1 : NWG - 1;
         if (lane == 0 && q > 0 && in && !(b & B_SEG)) {
-            if (vj[rr] != s_lj[pr][pw] || vtb[rr] != s_ltb[pr][pw]) b |= B_SEG | B_RUN;
+            if ((!FL && vj[FL ? 0 : rr] != s_lj[pr][pw]) || vtb[rr] != s_ltb[pr][pw]) b |= B_SEG | B_RUN;
             else if (vk[rr] != s_lk[pr][pw]) b |= B_RUN;
         }
         const bool chk = s_rodd[rr][w] || (lane == 0 && q > 0 && s_rodd[pr][pw]);

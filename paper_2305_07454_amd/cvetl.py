@@ -153,6 +153,9 @@ def _declare(L):
     L.cv_grid_aggregate.argtypes = [ctypes.POINTER(CvRecords), ctypes.POINTER(CvGridSpec),
                                     ctypes.POINTER(CvGroups), U64, P, P, ctypes.c_size_t, P]
     L.cv_grid_aggregate.restype = S
+    L.cv_grid_aggregate_flags.argtypes = [ctypes.POINTER(CvRecords), P, ctypes.POINTER(CvGridSpec),
+                                          ctypes.POINTER(CvGroups), U64, P, P, ctypes.c_size_t, P]
+    L.cv_grid_aggregate_flags.restype = S
     U32 = ctypes.c_uint32
     L.cv_batch_sort_records.argtypes = [ctypes.POINTER(CvRecords), P, U32, U64, P, ctypes.POINTER(CvRecordsOut),
                                         P, P, ctypes.c_size_t, P]
@@ -411,7 +414,9 @@ def cv_journey_summary(sorted_rec, feat, capacity=None, stream=None, sync=True, 
     return {k: v[:J] for k, v in out.items()}, r
 
 
-def cv_grid_aggregate(sorted_rec, grid, capacity=None, stream=None, sync=True, ws=None, out=None):
+def cv_grid_aggregate(sorted_rec, grid, capacity=None, stream=None, sync=True, ws=None, out=None, flags=None):
+    """flags: the kinematics' flags column of the same sorted records; the
+    journey starts then come from its FIRST bits (cv_grid_aggregate_flags)."""
     L = lib()
     n = int(sorted_rec["journey_id"].numel())
     dev = sorted_rec["journey_id"].device
@@ -424,14 +429,18 @@ def cv_grid_aggregate(sorted_rec, grid, capacity=None, stream=None, sync=True, w
     if ws is None or ws.numel() < need:
         ws = workspace(need, dev)
     res = new_result(dev)
-    st = L.cv_grid_aggregate(ctypes.byref(_records_struct(sorted_rec)), ctypes.byref(spec), ctypes.byref(gs), cap,
-                             _ptr(res), _ptr(ws), ws.numel(), _stream(stream))
+    if flags is not None:
+        st = L.cv_grid_aggregate_flags(ctypes.byref(_records_struct(sorted_rec)), _ptr(flags), ctypes.byref(spec),
+                                       ctypes.byref(gs), cap, _ptr(res), _ptr(ws), ws.numel(), _stream(stream))
+    else:
+        st = L.cv_grid_aggregate(ctypes.byref(_records_struct(sorted_rec)), ctypes.byref(spec), ctypes.byref(gs),
+                                 cap, _ptr(res), _ptr(ws), ws.numel(), _stream(stream))
     _check(st, "cv_grid_aggregate")
     if not sync:
         return out, res
     r = read_result(res)
     if r["status"] == CV_ERR_CAPACITY and capacity is None:
-        return cv_grid_aggregate(sorted_rec, grid, capacity=r["required"], stream=stream)
+        return cv_grid_aggregate(sorted_rec, grid, capacity=r["required"], stream=stream, flags=flags)
     _check(r["status"], "cv_grid_aggregate (device)")
     G = r["count"]
     return {k: v[:G] for k, v in out.items()}, r
@@ -635,7 +644,7 @@ def run_plain(rec, grid, max_journeys=None, journey_capacity=None, group_capacit
     perm, srt, rsort = cv_sort_records(rec, max_journeys=max_journeys, stream=stream)
     feat = cv_journey_features(srt, stream=stream)
     summ, rs = cv_journey_summary(srt, feat, capacity=journey_capacity, stream=stream)
-    groups, rg = cv_grid_aggregate(srt, grid, capacity=group_capacity, stream=stream)
+    groups, rg = cv_grid_aggregate(srt, grid, capacity=group_capacity, stream=stream, flags=feat["flags"])
     return dict(perm=perm, sorted=srt, features=feat, summary=summ, groups=groups, n_out=rg["n_out_of_grid"],
                 sort_result=rsort, summary_result=rs, grid_result=rg)
 
@@ -688,9 +697,10 @@ class Pipeline:
         _check(L.cv_journey_summary(ctypes.byref(srt), ctypes.byref(self._fs), ctypes.byref(self._js), self.jcap,
                                     _ptr(self.res[1]), _ptr(self.ws_sum), self.ws_sum.numel(), s),
                "cv_journey_summary")
-        _check(L.cv_grid_aggregate(ctypes.byref(srt), ctypes.byref(self.spec), ctypes.byref(self._gs), self.gcap,
-                                   _ptr(self.res[2]), _ptr(self.ws_grid), self.ws_grid.numel(), s),
-               "cv_grid_aggregate")
+        # journey starts from the kinematics' FIRST flags
+        _check(L.cv_grid_aggregate_flags(ctypes.byref(srt), _ptr(self.feat["flags"]), ctypes.byref(self.spec),
+                                         ctypes.byref(self._gs), self.gcap, _ptr(self.res[2]), _ptr(self.ws_grid),
+                                         self.ws_grid.numel(), s), "cv_grid_aggregate_flags")
 
     def results(self):
         """Read the three device result words (synchronises)."""

@@ -340,6 +340,35 @@ def test_summary_flags_column_at_any_alignment(cv):
         assert torch.equal(a[k], b[k]), k
 
 
+@pytest.mark.parametrize("case", ["c0", "c1_small", "long_segments", "ragged"])
+def test_grid_from_first_flags_equals_id_compare(cv, case):
+    # the grid with journey starts from the kinematics' FIRST flags and the one
+    # that compares journey ids give the same bits, and both equal the oracle
+    import torch
+    if case == "c0":
+        cols, spec = gen.make_c0(seed=5).columns(), gen.GRIDS["c0"]
+    elif case == "c1_small":
+        cols, spec = gen.make_c1(seed=8, n_journeys=60, median=900.0).columns(), gen.GRIDS["c1"]
+    elif case == "long_segments":
+        # a few journeys re-entering cells within long one-hour bins
+        r = gen.make_c1(seed=9, n_journeys=6, median=30_000.0)
+        cols = r.columns()
+        spec = gen.GridSpec(36.0, -95.8, 0.0005, 0.0005, 9200, 13400, gen.T0_MS, 3_600_000, 24)
+    else:
+        cols, spec = gen.make_c1(seed=10, n_journeys=33, median=700.0, shuffled=True).columns(), gen.GRIDS["c1"]
+    print(f"[parity] grid from flags, {case}, n={len(cols[0])}", flush=True)
+    exp = oracle.run_plain(cols, spec)
+    rec = cv.to_device(cols)
+    perm, srt, _ = cv.cv_sort_records(rec)
+    feat = cv.cv_journey_features(srt)
+    a, ra = cv.cv_grid_aggregate(srt, spec, flags=feat["flags"])
+    b, rb = cv.cv_grid_aggregate(srt, spec)
+    assert ra["count"] == rb["count"] and ra["n_out_of_grid"] == rb["n_out_of_grid"]
+    for k in a:
+        assert torch.equal(a[k], b[k]), k
+    check_groups(a, ra["n_out_of_grid"], exp["groups"], exp["n_out"])
+
+
 @pytest.mark.parametrize("unit,factor", [(1000, 1000), (50, 50), (1024, 1024), (375, 125), (7, 1), (2 ** 40, 2 ** 40)])
 def test_time_offsets_common_factor(cv, unit, factor):
     # time stamps on a grid of `unit` ms (a sampling period), unordered: the

@@ -313,6 +313,24 @@ __device__ __forceinline__ u32 popc_below(u64 mask)
     return __builtin_amdgcn_mbcnt_hi((u32)(mask >> 32), __builtin_amdgcn_mbcnt_lo((u32)mask, 0));
 }
 
+// Lanes of `valid` whose digit d (the low BITS bits) equals this lane's: one
+// ballot per bit; a lane differs from this one where a ballot differs from the
+// lane's own bit, sign-extended to a 32-bit mask, and the differences of all
+// bits are ORed per 32-lane half (about 5 vector instructions per bit).
+template <int BITS>
+__device__ __forceinline__ u64 wave_peers(u32 d, u64 valid)
+{
+    u32 dlo = 0, dhi = 0;
+#pragma unroll
+    for (int b = 0; b < BITS; ++b) {
+        const u32 s = (u32)(((int)(d << (31 - b))) >> 31);  // 0 or ~0
+        const u64 bal = __ballot(s != 0u);
+        dlo |= (u32)bal ^ s;
+        dhi |= (u32)(bal >> 32) ^ s;
+    }
+    return valid & ~(((u64)dhi << 32) | dlo);
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_inclusive_sum(T v)
 {

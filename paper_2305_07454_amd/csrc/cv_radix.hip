@@ -137,13 +137,7 @@ k_radix_pass(const u64* __restrict__ keys_in, const u32* __restrict__ vals_in, u
         u64 idx = wbase + (u64)i * WAVE + l;
         bool ok = idx < n;
         u32 d = (u32)(key[i] >> shift) & (RADIX - 1);
-        u64 peers = __ballot(ok);
-#pragma unroll
-        for (int b = 0; b < RADIX_BITS; ++b) {
-            bool bit = (d >> b) & 1u;
-            u64 bal = __ballot(bit);
-            peers &= bit ? bal : ~bal;
-        }
+        const u64 peers = wave_peers<RADIX_BITS>(d, __ballot(ok));
         u32 below = popc_below(peers);
         u32 cnt = __popcll(peers);
         u32 before = ok ? (u32)s_whist[w][d] : 0u;

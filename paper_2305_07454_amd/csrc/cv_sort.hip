@@ -817,13 +817,7 @@ __global__ void __launch_bounds__(PT_B) k_pack_il(const i64* __restrict__ jid, c
             rnk[k] = 0;
             if (group) {
                 const u32 d = rk[k] & (RADIX - 1);
-                u64 peers = vm;
-#pragma unroll
-                for (int b = 0; b < RADIX_BITS; ++b) {
-                    const bool bit = (d >> b) & 1u;
-                    const u64 bal = __ballot(bit);
-                    peers &= bit ? bal : ~bal;
-                }
+                const u64 peers = wave_peers<RADIX_BITS>(d, vm);
                 const u32 below = popc_below(peers);
                 const u32 cnt = (u32)__popcll(peers);
                 const u32 before = valid ? (u32)s_whist[w][d] : 0u;

@@ -168,9 +168,12 @@ __device__ __forceinline__ u32 dict_rank_of(const u64* table, u64 mask, u64 key)
 // before, and the cache spares those records the probe of the global table.
 // A slot is written by one lane only (the lanes that miss on a slot elect
 // one through the owner word), so an entry is never a mix of two writes.
-constexpr int DC = 256;   // slots per wave in the insert
-constexpr int DCP = 128;  // slots per wave in the key packing (16 KB of LDS per workgroup with the histograms)
-constexpr int DPW = 4;  // windows whose ids and times are loaded together (4: 90 VGPRs, 5 waves per SIMD)
+constexpr int DC = 512;   // slots per wave in the insert (24 KB of LDS per workgroup; 256: 0.3 ms slower on
+                          // the interleaved batched feed)
+constexpr int DCH = 128;  // slots per wave in the key packing for input in long runs (16 KB with the histograms)
+constexpr int DCP = 256;  // slots per wave in the interleaved key packing (its 1 024-thread workgroups are
+                          // one per CU at their register count, whatever the LDS)
+constexpr int DPW = 4;  // windows whose ids and times are loaded together (plain form: 90 VGPRs, 5 waves per SIMD)
 
 __device__ __forceinline__ void wave_range(u32 n, u64& wbeg, u64& wend)
 {
@@ -184,7 +187,8 @@ __device__ __forceinline__ void wave_range(u32 n, u64& wbeg, u64& wend)
 template <int C>
 __device__ __forceinline__ u32 dict_cache_slot(u64 key)
 {
-    return (u32)(mix64(key) >> 56) & (C - 1);
+    static_assert((C & (C - 1)) == 0 && C <= 4096, "power of two");
+    return (u32)(mix64(key) >> (64 - __builtin_ctz(C)));  // the hash's top bits
 }
 
 // bits 0..2: |d| not a multiple of 5, 25, 125
@@ -221,9 +225,9 @@ __global__ void __launch_bounds__(256) k_dict_insert(const i64* __restrict__ jid
                                                      u64* __restrict__ table, u64 mask, SortMeta* m,
                                                      const u64* __restrict__ soff, u32 S)
 {
-    // the batched form's 16-byte probes and shard checks: 3 windows per round
-    // keep it at 5 waves per SIMD
-    constexpr int DP = SHARDS ? 3 : DPW;
+    // (the batched form's 16-byte probes and shard checks take it to 4 waves
+    // per SIMD, with 3 windows per round as with 4)
+    constexpr int DP = DPW;
     __shared__ u64 s_min[4], s_max[4];
     __shared__ u64 c_key[4][DC];
     __shared__ u32 c_own[4][DC];
@@ -575,11 +579,11 @@ __global__ void __launch_bounds__(256) k_pack_hist(const i64* __restrict__ jid, 
 {
     __shared__ u32 s_h[MAX_PASSES * RADIX];
     // per-wave cache of (id, rank) pairs, as in the dictionary insert
-    __shared__ u64 c_key[4][DCP];
-    __shared__ u32 c_rank[4][DCP], c_own[4][DCP];
+    __shared__ u64 c_key[4][DCH];
+    __shared__ u32 c_rank[4][DCH], c_own[4][DCH];
     if (pay_packed(m, n)) return;
     for (int i = threadIdx.x; i < MAX_PASSES * RADIX; i += blockDim.x) s_h[i] = 0;
-    for (int i = threadIdx.x; i < 4 * DCP; i += blockDim.x) (&c_key[0][0])[i] = EMPTY;
+    for (int i = threadIdx.x; i < 4 * DCH; i += blockDim.x) (&c_key[0][0])[i] = EMPTY;
     __syncthreads();
     const int wv_ = threadIdx.x / WAVE;
     const u32 tb = m->t_bits;
@@ -624,7 +628,7 @@ __global__ void __launch_bounds__(256) k_pack_hist(const i64* __restrict__ jid, 
             const bool runhead = l == 0 ? !(hc && j == cj) : j != jp;
             u32 r = 0;
             const bool look = valid && runhead && j != EMPTY;
-            const u32 cs = dict_cache_slot<DCP>(j);
+            const u32 cs = dict_cache_slot<DCH>(j);
             bool miss = false;
             if (look) {
                 if (c_key[wv_][cs] == j) {

@@ -192,7 +192,7 @@ def test_dictionary_cache_slot_collisions(cv):
     ids = []
     x = 1
     while len(ids) < 96:
-        if (_mix64(x) >> 56) == 17:  # one slot at every power-of-two slot count up to 256
+        if (_mix64(x) >> 55) == 34:  # one slot at every power-of-two slot count up to 512
             ids.append(x)
         x += 1
     rng = np.random.default_rng(48)

@@ -483,6 +483,9 @@ __global__ void __launch_bounds__(SB) k_sum_reduce(u32 n, const i64* __restrict_
     bool open_here = false;  // its first record lies in this chunk
     i64 jprev = (!FL && cs > 0) ? jid[cs - 1] : 0;
     u32 sk = (SHARDS && !FL) ? shard_lower_bound(soff, S, cs) : 0u;
+    // the shard holding the chunk's first record: a journey head's shard is
+    // walked forward from it (a chunk spans few shards) instead of searched
+    const u32 shc = (SHARDS && FL && S > 1) ? shard_of(soff, S, cs) : 0u;
     // the id after the chunk (its last record may end a journey)
     const i64 jend = (!FL && ce < n) ? jid[ce] : 0;
     // Windows are taken in groups of WG: the columns of a group (ids included)
@@ -558,9 +561,9 @@ __global__ void __launch_bounds__(SB) k_sum_reduce(u32 n, const i64* __restrict_
                 }
             }
             if constexpr (BOX) {
+                const u32 sh = (h && S > 1) ? (FL ? shard_from(soff, S, shc, r) : shard_of(soff, S, r)) : 0u;
                 if (h && jl < cap) {
                     // a journey's first record is indexed within its shard
-                    const u32 sh = S > 1 ? shard_of(soff, S, r) : 0u;
                     if (o.jid) o.jid[jl] = FL ? jid[r] : jv;
                     if (o.first) o.first[jl] = (u32)(S > 1 ? r - soff[sh] : r);
                     acc[jl].gfirst = (u32)r;
@@ -568,7 +571,6 @@ __global__ void __launch_bounds__(SB) k_sum_reduce(u32 n, const i64* __restrict_
                 if (h && S > 1 && jo) {
                     // this record opens its shard's first journey: every shard
                     // starting here (empty ones included) begins at journey jl
-                    const u32 sh = shard_of(soff, S, r);
                     if (soff[sh] == r)
                         for (int z = (int)sh; z >= 0 && soff[z] == r; --z) jo[z] = jl;
                 }

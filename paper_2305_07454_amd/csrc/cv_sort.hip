@@ -1247,13 +1247,24 @@ __global__ void __launch_bounds__(256) k_gather_feat(u32 n, const SortMeta* m, c
     __syncthreads();
     // shard of each record (batched form), walked forward from the tile's
     // first one: journey heads at shard starts, shard-relative source indices
+    // (records before the next shard's start need no load: the block's first
+    // shard and the start of the shard after it are read once)
     u32 shs[GFI];
+    u64 sst[GFI];  // start of each record's shard
+    {
+        const u32 sh0 = SHARDS ? s_sh0 : 0u;
+        const u64 st0 = SHARDS ? soff[sh0] : 0ull;
+        const u64 nx0 = (SHARDS && sh0 + 1 < S) ? soff[sh0 + 1] : ~0ull;
 #pragma unroll
-    for (int u = 0; u < GFI; ++u) {
-        shs[u] = 0;
-        if (SHARDS && kk[u] < (long)n) {
-            shs[u] = shard_from(soff, S, s_sh0, (u64)kk[u]);
-            perm[kk[u]] = src[u] - (u32)soff[shs[u]];
+        for (int u = 0; u < GFI; ++u) {
+            shs[u] = 0;
+            sst[u] = 0;
+            if (SHARDS && kk[u] < (long)n) {
+                const bool same = (u64)kk[u] < nx0;
+                shs[u] = same ? sh0 : shard_from(soff, S, sh0, (u64)kk[u]);
+                sst[u] = same ? st0 : soff[shs[u]];
+                perm[kk[u]] = src[u] - (u32)sst[u];
+            }
         }
     }
     // steps (k - 1 -> k) of the tile's records; thread 0 also takes the step
@@ -1275,7 +1286,7 @@ __global__ void __launch_bounds__(256) k_gather_feat(u32 n, const SortMeta* m, c
             pcph = e_cphi[g + 1];
         }
         bool head = k == 0 || pj != oj[u];
-        if (SHARDS && !head && k < (long)n) head = soff[shs[u]] == (u64)k;
+        if (SHARDS && !head && k < (long)n) head = sst[u] == (u64)k;
         ks[u] = kin_step(head, isfinite(ola[u]) && isfinite(olo[u]), ot[u], ola[u], olo[u], ocph[u],
                          isfinite(pla) && isfinite(plo), pt, pla, plo, pcph, psph);
         if (l == WAVE - 1) {

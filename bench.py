@@ -236,8 +236,9 @@ def bench_batched(args, steps):
         "stages_ms_per_step": stages_b,
         "path_roofline": path_roofline(stages_b, n, G, rs_b["key_bits"], rs_b["packed_pass"], ms_batched,
                                        design_bytes=317, digit_bits=int(cvetl.cv_tuning_get("radix_bits")),
-                                       interleaved=True, ts_in_key=False),
+                                       interleaved=True, ts_in_key=False, first_bits=first_digit_bits(rs_b)),
         "key_bits": rs_b["key_bits"],
+        "first_digit_bits": first_digit_bits(rs_b),
         "packed_from_pass": rs_b["packed_pass"],
     }
     if args.batched_only:
@@ -495,10 +496,12 @@ def bench_plain(args, workload):
         "stages_ms_per_step": stages,
         "path_roofline": path_roofline(stages, n, G, key_bits, p0, ms_step,
                                        design_bytes=282 if workload == "c1" else None,
-                                       digit_bits=int(cvetl.cv_tuning_get("radix_bits"))),
+                                       digit_bits=int(cvetl.cv_tuning_get("radix_bits")),
+                                       first_bits=first_digit_bits(rs)),
         "direction_lattice": direction,
         "dense_lattice": lattice,
         "key_bits": key_bits,
+        "first_digit_bits": first_digit_bits(rs),
         "packed_from_pass": p0,
         "wall_s_timed_region": round(wall, 3),
     }
@@ -702,7 +705,8 @@ def radix_roofline(cvetl, n, rs, traffic=None):
     width)."""
     key_bits = rs["key_bits"]
     db = int(cvetl.cv_tuning_get("radix_bits"))
-    passes = (key_bits + db - 1) // db
+    w0 = first_digit_bits(rs)
+    passes = sort_pass_count(key_bits, w0, db)
     p0 = rs["packed_pass"]
     pass_ms, launches, alg = 0.0, 0, 0.0
     per_pass = []
@@ -715,7 +719,8 @@ def radix_roofline(cvetl, n, rs, traffic=None):
     avg_ms = pass_ms / max(launches, 1)
     per_launch = alg / max(launches, 1)
     achieved = per_launch / (avg_ms / 1e3) / 1e9 if avg_ms > 0 else 0.0
-    return {"bound": "hbm", "kernel": f"k_radix_pass (stable {db}-bit LSD scatter pass)",
+    kind = f"stable {db}-bit LSD scatter pass" if w0 == db else f"stable LSD scatter pass: a {w0}-bit first digit, then {db}-bit digits"
+    return {"bound": "hbm", "kernel": f"k_radix_pass ({kind})",
             "tile_keys": cvetl.cv_tuning_get("sort_tile"),
             "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -723,8 +728,24 @@ def radix_roofline(cvetl, n, rs, traffic=None):
             "alg_bytes_per_launch": int(per_launch), "per_pass_ms": per_pass}, pass_ms
 
 
+def first_digit_bits(rs):
+    """Bits of the record sort's first radix digit (the sort result's flags
+    word: 9 where a key of 8k + 1 bits saves a pass, else 8)."""
+    return int(rs.get("flags") or 8)
+
+
+def sort_pass_count(key_bits, first_bits=8, digit_bits=8):
+    """Working radix passes of a key: the first digit first_bits wide, the
+    others digit_bits."""
+    if key_bits <= 0:
+        return 0
+    if key_bits <= first_bits:
+        return 1
+    return 1 + (key_bits - first_bits + digit_bits - 1) // digit_bits
+
+
 def path_roofline(stages, n, G, key_bits, p0, ms_step, design_bytes=None, digit_bits=8, interleaved=False,
-                  ts_in_key=True):
+                  ts_in_key=True, first_bits=8):
     """Algorithmic bytes of the whole path per step (the per-record figures of
     each stage's kernels, plus the group tail) over the measured step time.
     design_bytes: the fixed per-record byte budget of the path's design (the
@@ -732,7 +753,7 @@ def path_roofline(stages, n, G, key_bits, p0, ms_step, design_bytes=None, digit_
     interleaved: input with short runs of equal ids, for which the key packing
     also writes a 32-byte payload per record that the fused gather reads
     instead of the columns.  ts_in_key: the sort key holds the time offset."""
-    passes = (key_bits + digit_bits - 1) // digit_bits
+    passes = sort_pass_count(key_bits, first_bits, digit_bits)
     # the time offset survives in the final word only when nothing was dropped
     ts_read = 0 if (p0 == 0 and ts_in_key) else 8
     per = {"sort_prep": 16 + 24 + ((20 + 32) if interleaved and "gather_features" in stages else 0),

@@ -135,7 +135,9 @@ typedef struct {
 /* Device-resident result word written by the last kernel of a call. */
 typedef struct {
     uint32_t status;        /* cv_status of the device-side checks              */
-    uint32_t flags;         /* reserved, 0                                      */
+    uint32_t flags;         /* sort call: bits of the first radix digit (8, or
+                               9 where a key of 8k + 1 bits saves a pass);
+                               other calls: 0 unless documented there         */
     uint64_t count;         /* rows produced (journeys / groups)                */
     uint64_t required;      /* capacity needed when status == CV_ERR_CAPACITY   */
     uint64_t n_out_of_grid; /* records outside the grid (grid call)             */
@@ -525,7 +527,12 @@ cv_status cv_stream_destroy(cv_stream* st);
  *                  thread) used by every sort; 0 .. "sort_shapes" - 1.
  *   "sort_shapes"  number of compiled shapes (read-only).
  *   "sort_tile"    keys per tile of the current shape (read-only).
+ *   "sort_block"   threads per block of the current shape (read-only).
  *   "radix_bits"   bits per radix digit of every sort (read-only).
+ *   "radix_wide_first" 1 (default): the record sort takes a 9-bit first
+ *                  digit for a key of 8k + 1 bits packed from the first
+ *                  pass (shapes of 512 threads or more), one pass fewer;
+ *                  0: 8-bit digits only.
  * Unknown names or out-of-range values return CV_ERR_INVALID_ARGUMENT.
  * --------------------------------------------------------------------- */
 cv_status cv_tuning_set(const char* name /*[host]*/, int64_t value);

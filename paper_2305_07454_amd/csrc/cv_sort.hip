@@ -21,7 +21,8 @@
 //                     histograms of every radix pass in the same read; for
 //                     interleaved input k_pack_il also regroups each tile by
 //                     journey and packs the payload per record;
-//   6. radix passes   ceil(key_bits / 8) stable scatter passes (skipped on device);
+//   6. radix passes   ceil(key_bits / 8) stable scatter passes, one less with a
+//                     9-bit first digit for a key of 8k + 1 bits (skipped on device);
 //   7. k_gather / k_gather_feat
 //                     perm, journey id from the dictionary, ts from the key
 //                     when it survives packing, lat/lon/speed through perm or
@@ -58,6 +59,7 @@ struct SortMeta {
     u32 shard_bits;
     u32 ib;   // index bits of a packed key word
     u32 p0;   // first pass whose input words are packed (ib and p0 adjacent: the radix passes read both)
+    u32 w0;   // bits of the first radix digit: 9 where that saves a pass (a key of 8k + 1 bits), else 8
     u32 n_runs;  // runs of equal ids in input order (counted by the dictionary insert)
     u32 unordered;  // a timestamp below its predecessor's (same shard) in input order
     u32 ts_dropped; // key = (shard, rank) only: the input is time-ordered within every shard
@@ -434,7 +436,7 @@ __global__ void __launch_bounds__(256) k_dict_compact(const u64* __restrict__ ta
     }
 }
 
-__global__ void k_dict_meta(SortMeta* m, u32 max_j, u32 n, u32 n_shards)
+__global__ void k_dict_meta(SortMeta* m, u32 max_j, u32 n, u32 n_shards, u32 allow_wide)
 {
     if (threadIdx.x != 0) return;
     u32 J = m->list_count + m->has_min;  // distinct ids counted by the compaction
@@ -467,13 +469,18 @@ __global__ void k_dict_meta(SortMeta* m, u32 max_j, u32 n, u32 n_shards)
         kb = 0;
     }
     m->key_bits = kb;
-    m->passes = (kb + RADIX_BITS - 1) / RADIX_BITS;
     // Packed words (key >> 8 p0) << ib | index replace the (key, index) pairs
     // from pass p0 on; p0 is the first digit boundary from which the rest of
     // the key and the index fit one word.  p0 < passes whenever p0 > 0.
     const u32 ib = n > 1 ? bit_width64((u64)n - 1) : 1u;
     m->ib = ib;
-    m->p0 = kb + ib > 64 ? (kb + ib - 64 + RADIX_BITS - 1) / RADIX_BITS : 0u;
+    const u32 p0 = kb + ib > 64 ? (kb + ib - 64 + RADIX_BITS - 1) / RADIX_BITS : 0u;
+    m->p0 = p0;
+    // a key of 8k + 1 bits, packed from the first pass, takes a 9-bit first
+    // digit and k passes instead of k + 1
+    const u32 w0 = (allow_wide && p0 == 0 && kb > RADIX_BITS && kb % RADIX_BITS == 1) ? RADIX_BITS + 1 : RADIX_BITS;
+    m->w0 = w0;
+    m->passes = kb == 0 ? 0u : (kb <= w0 ? 1u : 1u + (kb - w0 + RADIX_BITS - 1) / RADIX_BITS);
 }
 
 // Batched form, after the distinct ids are sorted: each id's shard (its slot's
@@ -577,18 +584,19 @@ __global__ void __launch_bounds__(256) k_pack_hist(const i64* __restrict__ jid, 
                                                    u64* __restrict__ keys, u32* __restrict__ hist,
                                                    const u64* __restrict__ soff, u32 S)
 {
-    __shared__ u32 s_h[MAX_PASSES * RADIX];
+    __shared__ u32 s_h[HIST_WIDE_WORDS];  // digit counts, wide layout (first digit w0 bits)
     // per-wave cache of (id, rank) pairs, as in the dictionary insert
     __shared__ u64 c_key[4][DCH];
     __shared__ u32 c_rank[4][DCH], c_own[4][DCH];
     if (pay_packed(m, n)) return;
-    for (int i = threadIdx.x; i < MAX_PASSES * RADIX; i += blockDim.x) s_h[i] = 0;
+    for (int i = threadIdx.x; i < HIST_WIDE_WORDS; i += blockDim.x) s_h[i] = 0;
     for (int i = threadIdx.x; i < 4 * DCH; i += blockDim.x) (&c_key[0][0])[i] = EMPTY;
     __syncthreads();
     const int wv_ = threadIdx.x / WAVE;
     const u32 tb = m->t_bits;
     const bool tdrop = m->ts_dropped != 0;
     const u32 np = m->passes;
+    const u32 fdb = m->w0 == RADIX_BITS + 1 ? RADIX_BITS + 1 : RADIX_BITS;  // first digit bits
     const bool bad = m->range_err != 0;
     const u32 ib = m->ib;
     const bool packed = m->p0 == 0;
@@ -668,18 +676,20 @@ __global__ void __launch_bounds__(256) k_pack_hist(const i64* __restrict__ jid, 
             const u64 vm = __ballot(valid);
             const int lead = __ffsll((long long)vm) - 1;
             for (u32 p = 0; p < np; ++p) {
-                const u32 d = (u32)(key >> (p * RADIX_BITS)) & (RADIX - 1);
+                const u32 lo = p ? fdb + (p - 1) * RADIX_BITS : 0u;
+                const u32 d = (u32)(key >> lo) & ((p ? RADIX : 1u << fdb) - 1u);
+                u32* hp = s_h + hist_wide_off((int)p);
                 const u32 d0 = __shfl(d, lead, WAVE);
                 if (__ballot(valid && d != d0) == 0) {
-                    if (l == lead) atomicAdd(&s_h[p * RADIX + d0], (u32)__popcll(vm));
+                    if (l == lead) atomicAdd(&hp[d0], (u32)__popcll(vm));
                 } else if (valid) {
-                    atomicAdd(&s_h[p * RADIX + d], 1u);
+                    atomicAdd(&hp[d], 1u);
                 }
             }
         }
     }
     __syncthreads();
-    for (u32 i = threadIdx.x; i < np * RADIX; i += blockDim.x)
+    for (u32 i = threadIdx.x; i < (u32)HIST_WIDE_WORDS; i += blockDim.x)
         if (s_h[i]) atomicAdd(&hist[i], s_h[i]);
 }
 
@@ -705,20 +715,21 @@ __global__ void __launch_bounds__(PT_B) k_pack_il(const i64* __restrict__ jid, c
                                                  const u64* __restrict__ soff, u32 S)
 {
     constexpr int NW = PT_B / WAVE;
-    __shared__ u32 s_h[MAX_PASSES * RADIX];
+    __shared__ u32 s_h[HIST_WIDE_WORDS];  // digit counts, wide layout (first digit w0 bits)
     __shared__ u64 c_key[NW][DCP];
     __shared__ u32 c_rank[NW][DCP], c_own[NW][DCP];
     __shared__ uint16_t s_whist[NW][RADIX];  // per-wave digit counts, then offsets
     __shared__ u32 s_start[RADIX];
     __shared__ u32 s_tmp[NW];
     if (!pay_packed(m, n)) return;
-    for (int i = threadIdx.x; i < MAX_PASSES * RADIX; i += blockDim.x) s_h[i] = 0;
+    for (int i = threadIdx.x; i < HIST_WIDE_WORDS; i += blockDim.x) s_h[i] = 0;
     for (int i = threadIdx.x; i < NW * DCP; i += blockDim.x) (&c_key[0][0])[i] = EMPTY;
     const int w = threadIdx.x / WAVE;
     const int l = lane_id();
     const u32 tb = m->t_bits;
     const bool tdrop = m->ts_dropped != 0;
     const u32 np = m->passes;
+    const u32 fdb = m->w0 == RADIX_BITS + 1 ? RADIX_BITS + 1 : RADIX_BITS;  // first digit bits
     const bool bad = m->range_err != 0;
     const u32 ib = m->ib;
     const bool packed = m->p0 == 0;
@@ -728,7 +739,7 @@ __global__ void __launch_bounds__(PT_B) k_pack_il(const i64* __restrict__ jid, c
     // without time bits the first digit of a key is the low byte of its rank,
     // which the regrouping counts per tile: that pass's histogram is added
     // from those counts, one add per digit and tile
-    const u32 p_first = (group && tdrop && !bad && rbits >= (u32)RADIX_BITS && np > 0) ? 1u : 0u;
+    const u32 p_first = (group && tdrop && !bad && rbits >= (u32)RADIX_BITS && np > 0 && fdb == RADIX_BITS) ? 1u : 0u;
     const u64 tmin = (u64)unord_i64(m->tmin_ord);
     const u32 tsh = m->t_sh, tp5 = m->t_p5;
     const ulonglong2* t2 = (const ulonglong2*)table;
@@ -810,12 +821,14 @@ __global__ void __launch_bounds__(PT_B) k_pack_il(const i64* __restrict__ jid, c
             const u64 vm = __ballot(valid);
             const int lead = vm ? __ffsll((long long)vm) - 1 : 0;
             for (u32 p = p_first; p < np; ++p) {
-                const u32 d = (u32)(key[k] >> (p * RADIX_BITS)) & (RADIX - 1);
+                const u32 dlo = p ? fdb + (p - 1) * RADIX_BITS : 0u;
+                const u32 d = (u32)(key[k] >> dlo) & ((p ? RADIX : 1u << fdb) - 1u);
+                u32* hp = s_h + hist_wide_off((int)p);
                 const u32 d0 = __shfl(d, lead, WAVE);
                 if (__ballot(valid && d != d0) == 0) {
-                    if (l == lead && vm) atomicAdd(&s_h[p * RADIX + d0], (u32)__popcll(vm));
+                    if (l == lead && vm) atomicAdd(&hp[d0], (u32)__popcll(vm));
                 } else if (valid) {
-                    atomicAdd(&s_h[p * RADIX + d], 1u);
+                    atomicAdd(&hp[d], 1u);
                 }
             }
             rnk[k] = 0;
@@ -867,7 +880,7 @@ __global__ void __launch_bounds__(PT_B) k_pack_il(const i64* __restrict__ jid, c
         __syncthreads();
     }
     __syncthreads();
-    for (u32 i = threadIdx.x; i < np * RADIX; i += blockDim.x)
+    for (u32 i = threadIdx.x; i < (u32)HIST_WIDE_WORDS; i += blockDim.x)
         if (s_h[i]) atomicAdd(&hist[i], s_h[i]);
 }
 
@@ -998,6 +1011,7 @@ __global__ void k_sort_finish(const SortMeta* m, cv_result* res)
     r.required = m->overflow ? m->J : 0;
     r.key_bits = m->key_bits;
     r.packed_pass = m->p0;
+    r.flags = m->w0;  // bits of the first radix digit
     *res = r;
 }
 
@@ -1055,16 +1069,24 @@ struct SortLayout {
         dsk1 = c.take<u64>(max_j);
         dlf = c.take<u64>(max_j);
         size_t z0 = cvh::align_up(c.off);
-        hist = c.take<u32>(MAX_PASSES * RADIX);
+        hist = c.take<u32>(HIST_WIDE_WORDS);  // record sort: wide layout
         dhist = c.take<u32>(MAX_PASSES * RADIX);
         shist = c.take<u32>(MAX_PASSES * RADIX);
-        status = c.take<u64>(tiles * RADIX + 1);
         dstatus = c.take<u64>(dtiles * RADIX + 1);
         sstatus = c.take<u64>(dtiles * RADIX + 1);
+        // last in the cleared range: room for 512 words per tile of the
+        // smallest tile (a 9-bit first digit); a call clears what its shape uses
+        status = c.take<u64>(tiles * 2 * RADIX + 1);
         size_t z1 = cvh::align_up(c.off);
         zero_begin = (u32*)(c.base ? c.base + z0 : nullptr);
         zero_bytes = z1 - z0;
-        offs = c.take<u32>(MAX_PASSES * RADIX);
+        if (c.base) {
+            const u64 st = (u64)(sort_block(sort_shape()) >= 2 * RADIX ? 2 * RADIX : RADIX);
+            const u64 used = ((n + sort_tile(sort_shape()) - 1) / sort_tile(sort_shape())) * st + 1;
+            const size_t zu = cvh::align_up((size_t)((char*)(status + used) - (char*)c.base));
+            zero_bytes = (zu < z1 ? zu : z1) - z0;
+        }
+        offs = c.take<u32>(HIST_WIDE_WORDS);
         doffs = c.take<u32>(MAX_PASSES * RADIX);
         soffs = c.take<u32>(MAX_PASSES * RADIX);
         K0 = c.take<u64>(n);
@@ -1377,7 +1399,7 @@ static cv_status sort_impl(const cv_records* in, const uint64_t* soff, uint32_t 
                            in->journey_id, in->ts_ms, nn, L.table, mask, L.meta, soff, S);
         hipLaunchKernelGGL(k_dict_compact, dim3(cvh::grid_for(L.slots, 256, 2048)), dim3(256), 0, s, L.table,
                            L.slots, mj, L.meta, L.dl0);
-        hipLaunchKernelGGL(k_dict_meta, dim3(1), dim3(64), 0, s, L.meta, mj, nn, S);
+        hipLaunchKernelGGL(k_dict_meta, dim3(1), dim3(64), 0, s, L.meta, mj, nn, S, sort_wide_first() ? 1u : 0u);
         // sort the distinct ids (64-bit, signed order via the flipped sign bit)
         const u32* dn = &L.meta->dict_n;
         radix_hist(L.dl0, mj, dn, MAX_PASSES, nullptr, L.dhist, cvh::grid_for(max_journeys, 256, 512), s);
@@ -1407,10 +1429,10 @@ static cv_status sort_impl(const cv_records* in, const uint64_t* soff, uint32_t 
                            s, in->journey_id,
                            in->ts_ms, in->lat_deg, in->lon_deg, in->speed_mps, feat ? L.pay : nullptr, nn, L.table,
                            mask, L.meta, L.K0, L.hist, soff, S);
-        radix_scan(L.hist, L.offs, MAX_PASSES, s);
+        radix_scan(L.hist, L.offs, MAX_PASSES, s, &L.meta->w0);
     }
     radix_passes(L.K0, L.K1, nullptr, L.V0, L.V1, nn, nullptr, &L.meta->key_bits, MAX_PASSES, L.offs, L.status,
-                 L.meta->tickets, s, /*timed=*/true, &L.meta->ib);
+                 L.meta->tickets, s, /*timed=*/true, &L.meta->ib, &L.meta->w0);
     const u64* dict_ids = S > 1 ? L.dlf : L.dl0;  // journey ids by rank
     if (feat) {
         cvh::TimedScope ts_("gather_features", s);

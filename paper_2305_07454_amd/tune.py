@@ -74,7 +74,9 @@ def sweep_sort_shapes(rec, grid, reps=5, log=print):
         tile = cvetl.cv_tuning_get("sort_tile")
         perm, srt, r = cvetl.cv_sort_records(rec)          # warm-up and key width
         db = int(cvetl.cv_tuning_get("radix_bits"))
-        passes = (r["key_bits"] + db - 1) // db
+        w0 = int(r.get("flags") or db)  # bits of the first digit (9 where that saves a pass)
+        kb = int(r["key_bits"])
+        passes = 0 if kb <= 0 else (1 if kb <= w0 else 1 + (kb - w0 + db - 1) // db)
         torch.cuda.synchronize()
         cvetl.cv_timing_reset()
         cvetl.cv_timing_enable(True)

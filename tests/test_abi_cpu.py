@@ -110,6 +110,25 @@ def test_tuning_values_checked_before_narrowing(L):
     assert L.cv_tuning_set(b"grid_lds_slots", ctypes.c_int64(256)) == cvetl.CV_ERR_INVALID_ARGUMENT
 
 
+def test_wide_first_digit_knob(L):
+    # host-only: the knob takes 0 or 1 and reads back; other values are refused
+    from paper_2305_07454_amd import cvetl
+    prev = ctypes.c_int64()
+    assert L.cv_tuning_get(b"radix_wide_first", ctypes.byref(prev)) == 0 and prev.value in (0, 1)
+    try:
+        for v in (0, 1):
+            got = ctypes.c_int64()
+            assert L.cv_tuning_set(b"radix_wide_first", ctypes.c_int64(v)) == 0
+            assert L.cv_tuning_get(b"radix_wide_first", ctypes.byref(got)) == 0 and got.value == v
+        for v in (2, -1, 1 << 32):
+            assert L.cv_tuning_set(b"radix_wide_first", ctypes.c_int64(v)) == cvetl.CV_ERR_INVALID_ARGUMENT
+        blk = ctypes.c_int64()
+        assert L.cv_tuning_get(b"sort_block", ctypes.byref(blk)) == 0 and blk.value in (256, 512, 1024)
+        assert L.cv_tuning_set(b"sort_block", ctypes.c_int64(512)) == cvetl.CV_ERR_INVALID_ARGUMENT
+    finally:
+        L.cv_tuning_set(b"radix_wide_first", prev)
+
+
 def test_debug_entry_points_only_in_the_checking_build(L):
     from paper_2305_07454_amd import cvetl
     flags = ctypes.c_uint32(7)

@@ -278,6 +278,37 @@ def test_packed_radix_passes(cv, tbits):
     assert got["sort_result"]["packed_pass"] == p0
 
 
+@pytest.mark.parametrize("tbits", [15, 23])
+@pytest.mark.parametrize("runs", [False, True])
+def test_wide_first_digit(cv, tbits, runs):
+    # 1000 ids (10 rank bits) and time offsets of tbits bits: a key of 8k + 1
+    # bits (25, 33), packed from the first pass, takes a 9-bit first digit and
+    # one pass fewer; the same input with 8-bit digits only must give the same
+    # order.  Interleaved ids take the tiled key packing, ids in runs the
+    # windowed one; 300 007 records span many tiles with a ragged last one.
+    n, n_ids = 300_007, 1000
+    cols = _wide_keys(300 + tbits, n, n_ids, tbits)
+    if runs:
+        o = np.argsort(cols[0], kind="stable")
+        cols = tuple(c[o] for c in cols)
+    kb = 10 + tbits
+    exp = oracle.run_plain(cols, gen.GRIDS["c0"])
+    rec = cv.to_device(cols)
+    prev = cv.cv_tuning_get("radix_wide_first")
+    try:
+        for wide in (1, 0):
+            cv.cv_tuning_set("radix_wide_first", wide)
+            print(f"[parity] wide first digit {wide} key bits {kb} runs {runs} n={n}", flush=True)
+            got = cv.run_plain(rec, gen.GRIDS["c0"])
+            _check_all(got, exp)
+            sr = got["sort_result"]
+            assert sr["key_bits"] == kb and sr["packed_pass"] == 0
+            shape_wide = cv.cv_tuning_get("sort_block") >= 512 and wide
+            assert sr["flags"] == (9 if shape_wide else 8)
+    finally:
+        cv.cv_tuning_set("radix_wide_first", prev)
+
+
 def test_every_sort_tile_shape(cv):
     # the record sort (and the group-key sort) under every compiled tile shape,
     # on an input of many tiles with a ragged last tile

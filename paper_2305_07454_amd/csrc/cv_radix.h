@@ -13,7 +13,9 @@
 //   4. keys are staged in LDS in tile-sorted order and written out so that
 //      consecutive threads write consecutive addresses of each digit run.
 // Stability holds because every step orders by (wave, item, lane), which is
-// the input order of the tile.
+// the input order of the tile.  The record sort may take its first digit 9
+// bits wide (9 ballots, 512 counters and look-back words) when that saves a
+// pass; every other digit has 8 bits.
 #pragma once
 #include "cv_device.h"
 

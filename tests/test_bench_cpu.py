@@ -55,3 +55,17 @@ def test_path_roofline_interleaved_batched_shape():
     assert per["sort_prep"] == 16 + 24 + 20 + 32
     assert per["sort_passes"] == 4 * 16
     assert per["gather_features"] == 8 + 32 + 4 + 36 + 49
+
+
+def test_pass_count_with_a_wide_first_digit():
+    # a key of 8k + 1 bits with a 9-bit first digit takes k passes
+    assert [bench.sort_pass_count(kb, 9) for kb in (9, 17, 25, 33)] == [1, 2, 3, 4]
+    assert [bench.sort_pass_count(kb, 8) for kb in (9, 17, 25, 33)] == [2, 3, 4, 5]
+    assert bench.sort_pass_count(0, 9) == 0 and bench.sort_pass_count(8, 9) == 1
+    # the sort result's flags word carries the width; 0 (older results) reads as 8
+    assert bench.first_digit_bits({"flags": 9}) == 9 and bench.first_digit_bits({"flags": 0}) == 8
+    # the full-day key: 33 bits packed from pass 0, four passes of 16 bytes
+    st = {"sort_prep": 1.0, "sort_passes": 1.0, "gather_features": 1.0, "summary": 1.0, "grid_agg": 1.0}
+    r = bench.path_roofline(st, n=1, G=0, key_bits=33, p0=0, ms_step=1.0, first_bits=9)
+    assert r["alg_bytes_per_record"]["sort_passes"] == 4 * 16
+    assert sum(r["alg_bytes_per_record"].values()) == 296

@@ -496,15 +496,28 @@ static cv_status grid_impl(const cv_records* sorted, const u64* soff, u32 S, con
     g.brg = (nd && !hdg) ? feat->bearing_deg : nullptr;
     g.bfl = (nd && !hdg) ? feat->flags : nullptr;
     g.sout = sout;
+    u32 sb = 0;
     if (S > 1) {
         // cell keys < n_t * n_lat * n_lon; the shard index goes above them
         const unsigned __int128 cells = (unsigned __int128)grid->n_t * grid->n_lat * grid->n_lon;
         u32 kb = 0;
         while (kb < 63 && ((unsigned __int128)1 << kb) < cells) ++kb;
-        u32 sb = 0;
         while (((u64)1 << sb) < S) ++sb;
         if (kb + sb > 63) return CV_ERR_RANGE;
         g.kb = kb;
+    }
+    // passes the merge's key sort can need: every key lies below the grid's
+    // count of (time bin, sector, cell) keys, with the shard index above kb
+    // when sharded; the device's count of key bits skips the rest
+    int mpasses = MAX_PASSES;
+    {
+        const unsigned __int128 keys = (unsigned __int128)g.tmax * (unsigned __int128)(nd + 1) *
+                                       (unsigned __int128)grid->n_lat * (unsigned __int128)grid->n_lon;
+        u32 b = 0;
+        while (b < 64 && ((unsigned __int128)1 << b) < keys) ++b;
+        if (S > 1) b = nd == 0 ? g.kb + sb : 64u;
+        const int need = (int)((b + RADIX_BITS - 1) / RADIX_BITS);
+        mpasses = need < MAX_PASSES ? need : MAX_PASSES;
     }
     const u64 kmask = S > 1 ? ((1ull << g.kb) - 1) : ~0ull;
     const u32 nn = (u32)n;
@@ -531,9 +544,9 @@ static cv_status grid_impl(const cv_records* sorted, const u64* soff, u32 S, con
         // key sort of the pairs
         const u32* cnt = &L.meta->compact_n;
         const u32* bits = &L.meta->key_bits;
-        radix_hist(L.K0, pmax, cnt, MAX_PASSES, bits, L.hist, cvh::grid_for(L.pmax, 256, 1024), s);
-        radix_scan(L.hist, L.offs, MAX_PASSES, s);
-        radix_passes(L.K0, L.K1, L.V0, L.V0, L.V1, pmax, cnt, bits, MAX_PASSES, L.offs, L.status, L.meta->tickets, s);
+        radix_hist(L.K0, pmax, cnt, mpasses, bits, L.hist, cvh::grid_for(L.pmax, 256, 1024), s);
+        radix_scan(L.hist, L.offs, mpasses, s);
+        radix_passes(L.K0, L.K1, L.V0, L.V0, L.V1, pmax, cnt, bits, mpasses, L.offs, L.status, L.meta->tickets, s);
         // groups: heads of equal-key runs, their rows, the merge
         const unsigned eg = (unsigned)cvh::grid_for(L.chunks, 1, 4096);
         hipLaunchKernelGGL(k_gpart_heads, dim3(eg), dim3(ECB), 0, s, L.meta, L.K0, L.K1, L.hcnt);

@@ -102,6 +102,7 @@ def _batched(cv, shards, grid):
         for x in np.unique(sh[0]):
             seen.setdefault(int(x), set()).add(s)
     multi = any(len(v) > 1 for v in seen.values())
+    _batched.last_result = res[0]
     return res[0]["key_bits"], J, len(shards), multi
 
 
@@ -148,3 +149,14 @@ def test_batched_ids_repeat_across_many_shard_starts(cv):
     shards = [_feed(500 + i, m, 3) for i, m in enumerate(sizes)]
     kb, J, S, multi = _batched(cv, shards, gen.GRIDS["c2"])
     assert not multi and kb == _bits(J - 1)
+
+
+def test_batched_rank_key_with_a_wide_first_digit(cv):
+    # time-ordered shards with some 80 000 journeys: a 17-bit rank key, which
+    # takes a 9-bit first digit and two passes (the key packing then counts
+    # its first digit per record instead of from the tile's multisplit)
+    shards = [_feed(900 + i, 150_000, 10_000) for i in range(8)]
+    kb, J, S, multi = _batched(cv, shards, gen.GRIDS["c2"])
+    assert not multi and kb == _bits(J - 1) == 17
+    wide = cv.cv_tuning_get("radix_wide_first") and cv.cv_tuning_get("sort_block") >= 512
+    assert _batched.last_result["flags"] == (9 if wide else 8)
